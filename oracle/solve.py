@@ -1,0 +1,151 @@
+"""Oracle, solve phase: l1-Jacobi hybrid smoother, V-cycle, inexact PCG (FP64).
+
+Test infrastructure only (see the package docstring).
+
+Paper anchors
+-------------
+* Section 4.1, eq. (4.1): hybrid smoother -- a point smoother on A, then a point
+  smoother on the auxiliary matrix D^T A D applied to D^T times the residual,
+  with the correction mapped back through D.  The transpose smoother runs the
+  two steps in reverse order with the transposed point smoothers.
+* Section 4.1 (smoother choice) and section 5.1: two sweeps for the primary and
+  for the auxiliary smoothing.  The point smoother here is l1-Jacobi,
+  d_i = sum_j |a_ij| (the l1 scaling of the cited smoother paper with point
+  blocks); its sweeps are symmetric so M^{-T} = M^{-1}.  The auxiliary sweeps
+  start from zero.
+* Algorithm 4.1: V-cycle, pre-relax, restrict with P^T, recurse or coarse solve,
+  prolong, post-relax with the transposed smoother.
+* Section 4.2 / 5.1: the coarsest-level solver; here an exact dense Cholesky
+  solve in FP64 (the footnote of section 5.1 allows other coarse solvers).
+* Section 4 (use in PCG) and section 5.1: one V-cycle with zero initial guess
+  per PCG iteration; inexact (flexible) PCG; stop when the residual measured in
+  the preconditioner norm has dropped by the relative tolerance.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+
+def l1_diag(A):
+    """Row l1 norms d_i = sum_j |a_ij| of a sparse matrix."""
+    return np.asarray(abs(A).sum(axis=1)).ravel()
+
+
+class SolveLevel:
+    def __init__(self, A, D, P=None, nu_primary=2, nu_aux=2):
+        self.A = A.tocsr()
+        self.D = D.tocsr()
+        self.Ahat = (self.D.T @ self.A @ self.D).tocsr()
+        self.d = l1_diag(self.A)
+        self.dhat = l1_diag(self.Ahat)
+        self.P = None if P is None else P.tocsr()
+        self.nu_primary, self.nu_aux = nu_primary, nu_aux
+
+
+class Multilevel:
+    """Algorithm 4.1 over a list of levels; the last one is solved by Cholesky."""
+
+    def __init__(self, As, Ds, Ps, nu_primary=2, nu_aux=2):
+        L = len(As)
+        self.levels = [SolveLevel(As[k], Ds[k], Ps[k] if k < L - 1 else None, nu_primary, nu_aux)
+                       for k in range(L)]
+        self.chol = sla.cho_factor(As[-1].toarray(), lower=True)
+
+    @classmethod
+    def from_hierarchy(cls, H, **kw):
+        return cls(H.A, H.D, H.P, **kw)
+
+    # --- hybrid smoother, eq. (4.1) -------------------------------------------
+    @staticmethod
+    def primary(lv, b, x):
+        for _ in range(lv.nu_primary):
+            x = x + (b - lv.A @ x) / lv.d
+        return x
+
+    @staticmethod
+    def auxiliary(lv, b, x):
+        g = lv.D.T @ (b - lv.A @ x)
+        y = np.zeros_like(g)
+        for _ in range(lv.nu_aux):
+            y = y + (g - lv.Ahat @ y) / lv.dhat
+        return x + lv.D @ y
+
+    def smooth(self, lv, b, x):
+        """x + M^{-1}(b - A x) with the hybrid smoother."""
+        return self.auxiliary(lv, b, self.primary(lv, b, x))
+
+    def smooth_transpose(self, lv, b, x):
+        """x + M^{-T}(b - A x): the steps in reverse order."""
+        return self.primary(lv, b, self.auxiliary(lv, b, x))
+
+    # --- Algorithm 4.1 ----------------------------------------------------------
+    def coarse_solve(self, b):
+        return sla.cho_solve(self.chol, b)
+
+    def vcycle(self, b, l=0, x0=None):
+        if l == len(self.levels) - 1:
+            return self.coarse_solve(b)
+        lv = self.levels[l]
+        x = np.zeros_like(b) if x0 is None else x0.copy()
+        x = self.smooth(lv, b, x)
+        ec = self.vcycle(lv.P.T @ (b - lv.A @ x), l + 1)
+        x = x + lv.P @ ec
+        return self.smooth_transpose(lv, b, x)
+
+    __call__ = vcycle
+
+
+def pcg(A, b, precond, rtol=1e-8, maxit=1000, stop="bnorm", fixed_iters=None):
+    """Inexact PCG with x0 = 0.
+
+    beta = (r_{k+1}.z_{k+1} - r_{k+1}.z_k) / (r_k.z_k), the flexible form that
+    reduces to the standard one for a fixed symmetric preconditioner.
+    stop = "bnorm": stop when sqrt(r.z / r0.z0) <= rtol (preconditioner norm);
+    stop = "l2": stop when ||r|| / ||b|| <= rtol.
+    fixed_iters: run exactly that many iterations regardless of the test.
+    Returns (x, iterations, history) where iterations counts products with A.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = precond(r)
+    p = z.copy()
+    delta = float(r @ z)
+    delta0 = delta
+    bnorm = float(np.linalg.norm(b))
+    hist = [1.0]
+    if delta0 <= 0 or not np.isfinite(delta0):
+        raise FloatingPointError("preconditioner not positive on b")
+    it = 0
+    while True:
+        if fixed_iters is not None and it >= fixed_iters:
+            break
+        if fixed_iters is None and it >= maxit:
+            break
+        q = A @ p
+        pq = float(p @ q)
+        if not pq > 0:
+            raise FloatingPointError("PCG breakdown: p.q <= 0")
+        alpha = delta / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        it += 1
+        zn = precond(r)
+        dn = float(r @ zn)
+        rzo = float(r @ z)
+        rel = np.sqrt(max(dn, 0.0) / delta0) if stop == "bnorm" else float(np.linalg.norm(r)) / bnorm
+        hist.append(rel)
+        if fixed_iters is None and rel <= rtol:
+            break
+        beta = (dn - rzo) / delta
+        p = zn + beta * p
+        z = zn
+        delta = dn
+    return x, it, hist
+
+
+def cg_plain(A, b, rtol=1e-8, maxit=1000, fixed_iters=None):
+    """Unpreconditioned CG (B = I) through the same loop."""
+    return pcg(A, b, lambda r: r.copy(), rtol=rtol, maxit=maxit, stop="l2", fixed_iters=fixed_iters)

@@ -1,0 +1,241 @@
+"""Pins of the oracle's coarse levels (paper section 3).
+
+Invariants fixed by the paper: exactness of every coarse sequence (eq. (3.2)),
+commutativity (eq. (3.3)) in the form D P_i = P_{i+1} D^H, Pi P = I (eq. (3.4)),
+D^H = Pi D P, Galerkin consistency of the auxiliary matrices, reproduction of
+constants, the H1 example of Fig. 3.3 (value 1 at the coarse dof, 1/2 at the
+neighbouring finer dofs), the cube-complex dimensions of PV-only coarse spaces,
+and optimality of the local extensions checked by an independent KKT solve.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import hierarchy as hm
+from oracle.hierarchy import build_hierarchy, minmass_extend
+from paper_2107_05613_amd.workloads import entity_counts
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _ones(n):
+    return np.ones(n ** 3), np.ones(n ** 3)
+
+
+@pytest.fixture(scope="module")
+def curl4():
+    return build_hierarchy("curl", 4, 3, *_ones(4), spaces=(0, 1, 2, 3))
+
+
+@pytest.fixture(scope="module")
+def div4():
+    return build_hierarchy("div", 4, 3, *_ones(4))
+
+
+def _check_sequence(H, k):
+    """All sequence invariants between level k and k+1; returns the worst errors."""
+    P, Pi = H.Pall[k], H.Piall[k]
+    fine, coarse = H.levels[k], H.levels[k + 1]
+    err = {}
+    for i in P:
+        err[f"PiP{i}"] = abs((Pi[i] @ P[i]).toarray() - np.eye(P[i].shape[1])).max()
+        if i + 1 in P:
+            err[f"comm{i}"] = abs(fine.D[i] @ P[i] - P[i + 1] @ coarse.D[i]).max()
+            err[f"DH{i}"] = abs(Pi[i + 1] @ fine.D[i] @ P[i] - coarse.D[i]).max()
+            # cochain projectors commute too: D^H Pi_i = Pi_{i+1} D
+            err[f"piComm{i}"] = abs(coarse.D[i] @ Pi[i] - Pi[i + 1] @ fine.D[i]).max()
+    return err
+
+
+@pytest.mark.parametrize("which", ["curl4", "div4"])
+def test_sequence_invariants(which, request):
+    H = request.getfixturevalue(which)
+    for k in range(len(H.levels) - 1):
+        err = _check_sequence(H, k)
+        for name, e in err.items():
+            assert e < 1e-13, (k, name, e)
+        c = H.levels[k + 1]
+        assert abs(c.D[1] @ c.D[0]).max() == 0
+        assert abs(c.D[2] @ c.D[1]).max() == 0
+
+
+def test_coarse_exactness_ranks(curl4):
+    """Range(D^H_i) = Ker(D^H_{i+1}) (eq. (3.2)) on every coarse level."""
+    for lev in curl4.levels[1:]:
+        G, C, Dv = (x.toarray() for x in lev.D)
+        V, E, F, T = (lev.ndofs(d) for d in range(4))
+        assert np.linalg.matrix_rank(G) == V - 1
+        assert np.linalg.matrix_rank(C) == E - V + 1
+        assert np.linalg.matrix_rank(Dv) == T
+        assert V - E + F - T == 1
+
+
+def test_planted_mistakes_are_caught(curl4):
+    """A flipped sign or a perturbed entry in any prolongator breaks a pin."""
+    H = curl4
+    for i in (0, 1, 2, 3):
+        for mode in ("flip", "scale"):
+            Pbad = {s: H.Pall[0][s].copy() for s in H.Pall[0]}
+            M = Pbad[i].tocsr()
+            j = M.nnz // 3
+            M.data[j] = -M.data[j] if mode == "flip" else M.data[j] * 1.001
+            Pbad[i] = M
+
+            class _H:
+                Pall = [Pbad]
+                Piall = H.Piall
+                levels = H.levels
+            err = _check_sequence(_H, 0)
+            assert max(err.values()) > 1e-11, (i, mode)   # pins use 1e-13
+
+
+def test_constants_reproduced(curl4, div4):
+    """P Pi c = c for the interpolants of constants (PV-only spaces contain them)."""
+    for H in (curl4, div4):
+        t = hm.order0_targets(H.levels[0])
+        for k in range(len(H.levels) - 1):
+            P, Pi = H.Pall[k], H.Piall[k]
+            for i in P:
+                if i in t:
+                    assert np.allclose(P[i] @ (Pi[i] @ t[i]), t[i], atol=1e-13)
+            t = {i: Pi[i] @ t[i] for i in t if i in Pi}
+
+
+def test_h1_fig33_values(curl4):
+    """Fig. 3.3: a coarse H1 basis function is 1 at its vertex and 1/2 at the finer
+    dofs on the coarse edges leaving it (the golden fixture holds those values);
+    the coarse H1 functions form a partition of unity."""
+    vals = np.loadtxt(os.path.join(GOLDEN, "fig33_h1_column.txt"))
+    H = curl4
+    for k in range(2):
+        P0 = H.Pall[k][0].tocsc()
+        fine, coarse = H.levels[k], H.levels[k + 1]
+        assert np.allclose(np.asarray(P0.sum(axis=1)).ravel(), 1.0, atol=1e-14)
+        cls = hm.classify(fine, coarse)
+        dim, owner, _ = cls[0]
+        Gc = coarse.D[0].tocsr()
+        for V in range(coarse.ndofs(0)):
+            col = P0[:, V].toarray().ravel()
+            assert col[np.nonzero((dim == 0) & (owner == V))[0][0]] == vals[0]
+            edges = Gc[:, V].nonzero()[0]
+            for E in edges:
+                mids = np.nonzero((dim == 1) & (owner == E))[0]
+                assert np.allclose(col[mids], vals[1])
+
+
+@pytest.mark.parametrize("kind,n,L", [("curl", 8, 2), ("div", 8, 2), ("curl", 8, 3), ("div", 12, 3)])
+def test_pv_only_dimensions_and_complexity(kind, n, L):
+    """Order-0 targets add nothing: coarse dims are the cube-complex counts, and the
+    grid/operator complexities follow from them."""
+    H = build_hierarchy(kind, n, L, *_ones(n))
+    d = 1 if kind == "curl" else 2
+    for k in range(1, L):
+        N = n >> k
+        cnt = {1: 3 * N * (N + 1) ** 2, 2: 3 * N * N * (N + 1)}[d]
+        assert H.A[k].shape[0] == cnt
+    # coarse operators couple exactly the dofs whose closures share a coarse cell
+    for k in range(1, L):
+        c = H.levels[k]
+        if d == 1:
+            inc = abs(c.D[2]) @ abs(c.D[1])
+        else:
+            inc = abs(c.D[2])
+        pattern = (inc.T @ inc).tocsr()
+        assert H.A[k].nnz == pattern.nnz
+        assert (abs(H.A[k]) > 0).multiply(pattern).nnz == pattern.nnz
+    gc = sum(A.shape[0] for A in H.A) / H.A[0].shape[0]
+    assert abs(gc - (1 + sum(H.A[k].shape[0] for k in range(1, L)) / H.A[0].shape[0])) < 1e-15
+
+
+def test_galerkin_aux_consistency(curl4, div4):
+    """P_{i-1}^T (D^T A D) P_{i-1} = D_H^T A_H D_H, a consequence of commutativity."""
+    for H in (curl4, div4):
+        s = H.sys_space
+        for k in range(len(H.levels) - 1):
+            Pm = H.Pall[k].get(s - 1)
+            if Pm is None:
+                continue
+            Ah = (H.D[k].T @ H.A[k] @ H.D[k])
+            lhs = (Pm.T @ Ah @ Pm).toarray()
+            rhs = (H.D[k + 1].T @ H.A[k + 1] @ H.D[k + 1]).toarray()
+            assert np.allclose(lhs, rhs, atol=1e-12 * abs(rhs).max())
+
+
+def test_galerkin_coarse_operators_spd(div4):
+    for A in div4.A:
+        ev = np.linalg.eigvalsh(A.toarray())
+        assert ev.min() > 0
+
+
+def test_local_extension_against_kkt():
+    """The null-space solver equals the minimum-norm solution of the full KKT system."""
+    rng = np.random.default_rng(5)
+    nI, nB, m = 9, 4, 6
+    n = nI + nB
+    Q = rng.standard_normal((n, n))
+    M = Q @ Q.T + n * np.eye(n)
+    K = rng.standard_normal((m, n))
+    K[-1] = K[0] + K[1]                    # rank deficient, consistent data below
+    intr = np.zeros(n, bool); intr[:nI] = True
+    u_true = rng.standard_normal((n, 2))
+    rhs = K @ u_true
+    ub = u_true[~intr]
+    uI = minmass_extend(M, K, intr, rhs, ub)
+    KI, KB = K[:, intr], K[:, ~intr]
+    MII, MIB = M[np.ix_(intr, intr)], M[np.ix_(intr, ~intr)]
+    kkt = np.block([[MII, KI.T], [KI, np.zeros((m, m))]])
+    r = np.vstack([-MIB @ ub, rhs - KB @ ub])
+    sol = np.linalg.lstsq(kkt, r, rcond=None)[0][:nI]
+    assert np.allclose(uI, sol, atol=1e-10)
+    assert np.allclose(KI @ uI + KB @ ub, rhs, atol=1e-10)
+
+
+def test_extension_optimality_in_hierarchy(div4):
+    """RT cube extensions satisfy the KKT conditions: the mass-weighted extension is
+    orthogonal to every divergence-free interior bubble."""
+    H = div4
+    cg = hm._Coarsening(H.levels[0], 1.0 / 4)
+    P2 = H.Pall[0][2]
+    Zs = np.arange(cg.nc[3])
+    dofs, intr, M = cg.local(2, 3, Zs)
+    yrows = hm._rows2d(cg.interior[3][3], Zs)
+    K = hm.batched_block(H.levels[0].D[2], yrows, dofs)
+    Xs = hm._rows2d(cg.sub[(3, 2)], Zs)
+    for b in range(len(Zs)):
+        U = hm.batched_block(P2, dofs[b][None], Xs[b][None])[0]
+        _, s, Vt = np.linalg.svd(K[b][:, intr[b]])
+        N = Vt[np.sum(s > 1e-12 * s.max()):].T
+        g = (M[b] @ U)[intr[b]]
+        assert abs(N.T @ g).max() < 1e-12
+
+
+def test_batch_shortcut_changes_nothing():
+    """Solving every local problem separately gives bitwise the same prolongators."""
+    H1 = build_hierarchy("curl", 4, 2, *_ones(4), spaces=(1, 2, 3))
+    orig = hm._batches
+    try:
+        hm._batches = lambda Zs, size=1024: (Zs[i:i + 1] for i in range(len(Zs)))
+        H2 = build_hierarchy("curl", 4, 2, *_ones(4), spaces=(1, 2, 3))
+    finally:
+        hm._batches = orig
+    for i in (1, 2, 3):
+        assert (H1.Pall[0][i] != H2.Pall[0][i]).nnz == 0
+
+
+def test_targets_do_not_survive():
+    """Order-0 targets are removed completely (PV-only coarse spaces, A8 reading)."""
+    H = build_hierarchy("curl", 4, 3, *_ones(4), check_targets=True)
+    assert H.A[1].shape[0] == 3 * 2 * 9
+
+
+def test_coefficients_do_not_change_prolongators():
+    """With unweighted L2 masses in the extensions the prolongators do not depend
+    on alpha, beta (only the Galerkin operators do)."""
+    rng = np.random.default_rng(0)
+    a = 10 ** rng.uniform(-3, 3, 64)
+    H1 = build_hierarchy("div", 4, 2, *_ones(4))
+    H2 = build_hierarchy("div", 4, 2, a, np.ones(64))
+    assert (H1.P[0] != H2.P[0]).nnz == 0
+    assert abs(H1.A[1] - H2.A[1]).max() > 1e-3
