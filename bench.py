@@ -1,0 +1,224 @@
+"""Benchmark of the AMGe solve phase on one MI355X.
+
+One step = one complete PCG solve (FP32 V-cycle preconditioner inside FP64 inexact
+PCG, stopped at relative residual 1e-8 in the preconditioner norm) of the H(curl)
+system on the 64^3 x 6 Kuhn mesh with the 5-level hierarchy, starting from the
+right-hand side already resident in HBM.  The same solve with an all-FP64 V-cycle
+("plain FP64 PCG") is timed beside it, and the V-cycle's achieved bandwidth is
+reported from its algorithmic bytes.
+
+Prints one JSON line (rank 0).  Options: --gpus N (only 1 is supported), --steps K,
+--warmup W, --workload NAME, --no-cpu-baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solves/s + V-cycle HBM GB/s, FP32-precond vs FP64 PCG at rel-res 1e-8"
+PEAK_HBM_GBPS = 8000.0
+
+
+def cpu_baseline_worker(workload: str, budget_s: float):
+    """Oracle leg (separate process, one thread): hierarchy build untimed, then a bounded
+    number of FP64 PCG iterations timed; prints a JSON dict."""
+    import numpy as np
+    from paper_2107_05613_amd import workloads as W
+    from oracle.hierarchy import build_hierarchy
+    from oracle.solve import Multilevel, pcg
+    w = W.WORKLOADS[workload]
+    a, b = W.coefficients(w)
+    t0 = time.perf_counter()
+    H = build_hierarchy(w.kind, w.n, w.levels, a, b, check_targets=False)
+    ml = Multilevel.from_hierarchy(H)
+    t_build = time.perf_counter() - t0
+    rhs = W.rhs(H.A[0].shape[0], w.rhs_seed)[:, 0]
+    t0 = time.perf_counter()
+    pcg(H.A[0], rhs, ml, fixed_iters=1)                  # setup V-cycle + 1 iteration
+    t1 = time.perf_counter() - t0
+    iters = max(1, min(50, int(budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    pcg(H.A[0], rhs, ml, fixed_iters=iters)
+    t = time.perf_counter() - t0
+    # the fixed-iteration run costs (iters + 1) V-cycles and iters A-products
+    print(json.dumps({"t_build_s": t_build, "sample_iters": iters, "sample_s": t,
+                      "s_per_iter": t / (iters + 1)}), flush=True)
+
+
+def run_cpu_baseline(workload, iters_needed, budget_s=20.0):
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", "--workload", workload,
+           "--cpu-budget", str(budget_s)]
+    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=1500)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    s_per_solve = res["s_per_iter"] * (iters_needed + 1)
+    return {"value": 1.0 / s_per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"FP64 oracle (scipy CSR, 1 thread) PCG on the same hierarchy and rhs: "
+                       f"{res['sample_iters']} iterations timed ({res['sample_s']:.1f} s), scaled to "
+                       f"{iters_needed} iterations per solve (the FP64 GPU count); hierarchy build "
+                       f"{res['t_build_s']:.0f} s not timed")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="curl_n64_l5")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-worker", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+
+    if args.cpu_baseline_worker:
+        cpu_baseline_worker(args.workload, args.cpu_budget)
+        return 0
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one MI355X: the solve phase is not sharded across GPUs "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2107_05613_amd import amge
+    from paper_2107_05613_amd import workloads as W
+
+    w = W.WORKLOADS[args.workload]
+    a, b = W.coefficients(w)
+    t0 = time.perf_counter()
+    prod = amge.build_problem(w.kind, w.n, w.levels, a, b)
+    t_build = time.perf_counter() - t0
+    torch.cuda.init()
+    t0 = time.perf_counter()
+    H32 = amge.Hierarchy(prod, precond_bits=32)
+    H64 = amge.Hierarchy(prod, precond_bits=64)
+    t_setup = time.perf_counter() - t0
+    n1 = H32.rows[0]
+    rhs = torch.from_numpy(W.rhs(n1, w.rhs_seed)[:, 0]).cuda()
+    x32 = torch.zeros_like(rhs)
+    x64 = torch.zeros_like(rhs)
+    print(f"[bench] {w.name}: n1={n1} levels={H32.rows} build {t_build:.1f}s setup {t_setup:.1f}s",
+          file=sys.stderr, flush=True)
+
+    def solve(H, x):
+        st, it, rr = H.pcg(rhs, x, rtol=w.rtol, maxit=1000)
+        if st != 0:
+            raise RuntimeError("solve did not converge")
+        return it[0], rr[0]
+
+    # ---- FP32-preconditioned PCG (the product path)
+    for _ in range(args.warmup):
+        solve(H32, x32)
+    torch.cuda.synchronize()
+    H32.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        it32, rr32 = solve(H32, x32)
+    torch.cuda.synchronize()
+    dt32 = time.perf_counter() - t0
+    k_ms, k_launches, k_bytes = H32.timing_read()
+    H32.timing_enable(False)
+    print(f"[bench] fp32-precond: {it32} iters, {1e3 * dt32 / args.steps:.2f} ms/solve", file=sys.stderr, flush=True)
+
+    # ---- plain FP64 PCG on the same hierarchy
+    for _ in range(max(1, args.warmup)):
+        solve(H64, x64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        it64, rr64 = solve(H64, x64)
+    torch.cuda.synchronize()
+    dt64 = time.perf_counter() - t0
+    print(f"[bench] fp64: {it64} iters, {1e3 * dt64 / args.steps:.2f} ms/solve", file=sys.stderr, flush=True)
+
+    # ---- V-cycle bandwidth (FP32 and FP64), device time by events on the launch stream
+    z = torch.empty_like(rhs)
+    vc = {}
+    for bits, H in ((32, H32), (64, H64)):
+        for _ in range(3):
+            H.vcycle(rhs, z)
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            H.vcycle(rhs, z)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        by = H.vcycle_bytes(bits)
+        vc[bits] = (ms, by, by / (ms * 1e-3) / 1e9)
+    err = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+
+    value = args.steps / dt32
+    k_avg_ms = k_ms / max(k_launches, 1)
+    k_gbps = (k_bytes / max(k_launches, 1)) / (k_avg_ms * 1e-3) / 1e9 if k_launches else 0.0
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{w.name}: H({w.kind}) lowest-order "
+                         f"{'Nedelec' if w.kind == 'curl' else 'Raviart-Thomas'} on {w.n}^3x6 Kuhn tets, "
+                         f"{w.levels}-level AMGe (2x2x2 agglomerates), l1-Jacobi hybrid smoother 2+2, "
+                         f"FP32 V-cycle in FP64 inexact PCG to rel-res {w.rtol:g} (preconditioner norm)"),
+            "fine_dofs": n1,
+            "level_rows": H32.rows,
+            "rhs": f"uniform[-1,1] seed {w.rhs_seed}",
+            "coefficients": w.coef,
+        },
+        "dtype_detail": "V-cycle values and accumulation FP32; outer PCG, dots and coarsest Cholesky FP64",
+        "iters_fp32_precond": it32,
+        "iters_fp64": it64,
+        "relres_fp32_precond": rr32,
+        "fp64_solves_per_s": args.steps / dt64,
+        "speedup_fp32_vs_fp64": (args.steps / dt32) / (args.steps / dt64),
+        "solution_rel_diff_fp32_vs_fp64": err,
+        "vcycle": {
+            "fp32": {"ms": vc[32][0], "algorithmic_bytes": vc[32][1], "GBps": vc[32][2]},
+            "fp64": {"ms": vc[64][0], "algorithmic_bytes": vc[64][1], "GBps": vc[64][2]},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "fine-level A_1 CSR kernels (l1-Jacobi sweeps + residuals, FP32)",
+            "achieved": k_gbps,
+            "peak": PEAK_HBM_GBPS,
+            "unit": "GB/s",
+            "frac": k_gbps / PEAK_HBM_GBPS,
+            "traffic": None,
+            "avg_launch_us": 1e3 * k_avg_ms,
+            "bytes_per_launch": k_bytes / max(k_launches, 1),
+            "launches": k_launches,
+        },
+        "setup_s": {"build": t_build, "device_setup": t_setup},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = run_cpu_baseline(args.workload, it64, args.cpu_budget)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

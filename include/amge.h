@@ -1,0 +1,179 @@
+/*
+ * amge.h -- C ABI of the MI355X AMGe solve phase for lowest-order H(curl) and
+ * H(div) systems (element-based algebraic multigrid on an exact de Rham
+ * hierarchy).
+ *
+ * Method (paper: Kalchev, Vassilevski, Villa, "Parallel element-based algebraic
+ * multigrid for H(curl) and H(div) problems using the ParELAG library"):
+ *   - the preconditioner is one V-cycle of Algorithm 4.1 with zero initial guess;
+ *   - every non-coarsest level is relaxed by the hybrid smoother of eq. (4.1):
+ *     l1-Jacobi sweeps on A_k, then l1-Jacobi sweeps on the auxiliary matrix
+ *     D_k^T A_k D_k with the correction mapped back through D_k; the
+ *     post-smoother applies the two steps in reverse order;
+ *   - the coarsest level is solved exactly (dense FP64 Cholesky);
+ *   - the outer iteration is inexact PCG (section 5.1) stopped on the residual
+ *     measured in the preconditioner norm.
+ *
+ * Conventions for every entry point
+ *   - Host CSR inputs are read only during the call; the library copies them.
+ *     Column indices must be sorted and in range within each row.
+ *   - Device vectors are caller-owned HIP device pointers, row-major
+ *     (n x nrhs): entry (i, c) is at i*nrhs + c.
+ *   - `stream` is a hipStream_t (0 = the null stream).  Calls are ordered on it;
+ *     functions that return host scalars synchronise it before returning.
+ *   - Negative return values are errors, amge_last_error() gives a message for
+ *     the calling thread.  AMGE_NOT_CONVERGED is a warning: outputs are valid.
+ *   - A hierarchy is read-only after set-up apart from its work buffers: calls
+ *     that use one hierarchy must not overlap in time (use one hierarchy, or one
+ *     context, per concurrent stream).
+ */
+#ifndef AMGE_H
+#define AMGE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AMGE_OK = 0,
+    AMGE_NOT_CONVERGED = 1,
+    AMGE_ERR_ARG = -1,        /* invalid argument (null pointer, bad size, bad option)   */
+    AMGE_ERR_SHAPE = -2,      /* matrix dimensions do not chain, indices out of range    */
+    AMGE_ERR_NOT_SPD = -3,    /* coarsest matrix not symmetric positive definite         */
+    AMGE_ERR_OOM = -4,        /* device or host allocation failed                        */
+    AMGE_ERR_HIP = -5,        /* a HIP runtime call failed                               */
+    AMGE_ERR_BREAKDOWN = -6,  /* PCG breakdown: p.q <= 0 or preconditioner not positive  */
+    AMGE_ERR_NONFINITE = -7,  /* NaN or Inf in an input                                  */
+    AMGE_ERR_BUSY = -8        /* resource budget exceeded (serving admission)            */
+} amge_status;
+
+enum { AMGE_CURL = 0, AMGE_DIV = 1 };
+
+/* Host CSR matrix, FP64 values, int32 indices. */
+typedef struct {
+    int32_t nrows, ncols;
+    int64_t nnz;
+    const int32_t* rowptr;   /* nrows + 1 */
+    const int32_t* col;      /* nnz, sorted within each row */
+    const double* val;       /* nnz */
+} amge_csr;
+
+/* One level k of the hierarchy (Algorithm 4.1 inputs, section 3.2):
+ *   A  n_k x n_k    system matrix A_k (SPD); A_1 is the fine matrix, A_{k+1} = P_k^T A_k P_k
+ *   D  n_k x m_k    exterior derivative used by the hybrid smoother (eq. (4.1)):
+ *                   discrete gradient (H(curl)) or discrete curl (H(div)); entries +-1
+ *   P  n_k x n_{k+1} prolongator to the next level (section 3.2.1); nrows = 0 on the
+ *                   coarsest level. */
+typedef struct {
+    amge_csr A, D, P;
+} amge_level;
+
+typedef struct {
+    int32_t nu_primary;     /* l1-Jacobi sweeps on A_k per smoothing step (paper: 2)        */
+    int32_t nu_aux;         /* l1-Jacobi sweeps on D^T A D per smoothing step (paper: 2)    */
+    int32_t precond_bits;   /* 64: V-cycle in FP64; 32: FP32 values/accumulation in the
+                               V-cycle with the coarsest Cholesky solve kept in FP64        */
+    int32_t max_rhs;        /* largest nrhs the work buffers are sized for (>= 1)           */
+} amge_opts;
+
+typedef struct amge_hierarchy amge_hierarchy;
+
+/* Default options: nu = 2 + 2, FP32 preconditioner, max_rhs = 1. */
+void amge_default_opts(amge_opts* opts);
+
+/* Builds the device hierarchy from host level matrices (section 3.2, Algorithm 4.1 inputs).
+ * Host work: validation, D^T (for the auxiliary restriction), P^T, the auxiliary matrices
+ * D^T A D (FP64 sparse products), the l1 row sums, a dense FP64 Cholesky factor of the
+ * coarsest matrix and its inverse factor.  Device buffers are owned by the hierarchy.
+ * Errors: AMGE_ERR_ARG, AMGE_ERR_SHAPE, AMGE_ERR_NONFINITE, AMGE_ERR_NOT_SPD (coarsest
+ * matrix), AMGE_ERR_OOM, AMGE_ERR_HIP. */
+amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nlevels, const amge_opts* opts,
+                                 void* stream, amge_hierarchy** out);
+
+void amge_destroy(amge_hierarchy* h);
+
+/* Device memory held by the hierarchy (operators and work buffers), in bytes. */
+amge_status amge_footprint(const amge_hierarchy* h, size_t* bytes);
+
+/* z = B r: one V-cycle of Algorithm 4.1 with zero initial guess, on nrhs columns.
+ * r, z: device FP64, n_1 x nrhs row-major.  nrhs <= opts.max_rhs. */
+amge_status amge_vcycle(amge_hierarchy* h, const double* r, double* z, int32_t nrhs, void* stream);
+
+/* Inexact PCG (section 5.1) for A_1 x = b with x0 = 0 and one V-cycle per iteration.
+ *   b, x     device FP64, n_1 x nrhs row-major; x is overwritten
+ *   rtol     stop when sqrt(r.z / r0.z0) <= rtol (stop_norm = 0, preconditioner norm) or
+ *            ||r|| / ||b|| <= rtol (stop_norm = 1); rtol <= 0 runs exactly maxit iterations
+ *   iters    host, nrhs entries: products with A_1 per column
+ *   relres   host, nrhs entries: final relative residual in the chosen norm
+ * Returns AMGE_NOT_CONVERGED if a column missed rtol within maxit, AMGE_ERR_NONFINITE
+ * for a NaN/Inf right-hand side, AMGE_ERR_BREAKDOWN if p.q <= 0 occurs. */
+amge_status amge_pcg_solve(amge_hierarchy* h, const double* b, double* x, int32_t nrhs, double rtol,
+                           int32_t maxit, int32_t stop_norm, int32_t* iters, double* relres, void* stream);
+
+/* Single level operations, for testing each kernel of the path on its own.  Device FP64
+ * in/out vectors (one column); precision 32 runs the FP32 kernel on rounded inputs.
+ *   op  AMGE_OP_A       out = A_k in                 (CSR SpMV)
+ *       AMGE_OP_AHAT    out = (D^T A D)_k in          (auxiliary matrix)
+ *       AMGE_OP_D       out = D_k in                  (incidence)
+ *       AMGE_OP_DT      out = D_k^T in
+ *       AMGE_OP_P       out = P_k in                  (prolongation, in has n_{k+1} rows)
+ *       AMGE_OP_PT      out = P_k^T in                (restriction)
+ *       AMGE_OP_SMOOTH  out = x + Mbar^{-1}(b - A x) with b = in, x = in2 (eq. (4.1))
+ *       AMGE_OP_SMOOTHT out = x + Mbar^{-T}(b - A x) with b = in, x = in2 (reversed order)
+ *       AMGE_OP_COARSE  out = A_L^{-1} in on the coarsest level (Cholesky apply) */
+enum {
+    AMGE_OP_A = 0, AMGE_OP_AHAT = 1, AMGE_OP_D = 2, AMGE_OP_DT = 3, AMGE_OP_P = 4,
+    AMGE_OP_PT = 5, AMGE_OP_SMOOTH = 6, AMGE_OP_SMOOTHT = 7, AMGE_OP_COARSE = 8
+};
+amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_t op, int32_t precision,
+                             const double* in, const double* in2, double* out, void* stream);
+
+/* Event timing of the fine-level A_1 kernels of the V-cycle (the l1-Jacobi sweeps and
+ * residuals on level 1, the dominant kernel family of the path).  While enabled, every
+ * such launch is bracketed by HIP events on its own stream.  amge_timing_read waits for
+ * the recorded events and returns, since enabling or the previous read: the summed
+ * kernel time in ms, the number of launches, and their algorithmic bytes (values and
+ * column indices, row pointers, and each vector stream once).  Intended for measurement
+ * runs; reading resets the counters. */
+amge_status amge_timing_enable(amge_hierarchy* h, int32_t enable);
+amge_status amge_timing_read(amge_hierarchy* h, double* ms, int64_t* launches, double* bytes);
+
+/* Algorithmic bytes of one V-cycle (nrhs = 1) in the given precision (32 or 64): every
+ * matrix of every level read once per use (values + column indices + row pointers,
+ * incidences index-only), every vector stream once, and the coarsest inverse factor. */
+amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precision, double* bytes);
+
+/* Host sizes of a hierarchy: nlevels, and rows of A_k for k = 0..nlevels-1 (rows[] may be NULL). */
+amge_status amge_hierarchy_info(const amge_hierarchy* h, int32_t* nlevels, int32_t* rows);
+
+const char* amge_last_error(void);
+
+/* ------------------------------------------------------------------------------------
+ * Problem builder for the structured workloads: the unit cube split into n^3 hexes,
+ * 6 Kuhn tetrahedra each; lowest-order Nedelec (kind AMGE_CURL) or Raviart-Thomas
+ * (AMGE_DIV) discretisation of a(u,v) = (alpha Du, Dv) + (beta u, v) (eq. (2.2)), natural
+ * boundary conditions; hierarchy by 2x2x2 agglomeration of the hexes on every level,
+ * PV traces (eq. (3.5)) and minimum-mass extensions (eqs. (3.6), (3.8)), Galerkin
+ * coarse matrices.  Dofs are numbered canonically: entities sorted lexicographically by
+ * their sorted vertex indices, vertex (i,j,k) = i + (n+1)(j + (n+1)k).
+ *   alpha_hex, beta_hex  host, n^3 values, hex (i,j,k) at i + n(j + n k)
+ *   nlevels              >= 1; n must be divisible by 2^(nlevels-1)
+ * The returned problem owns host CSR arrays for every level (amge_level layout).
+ * ---------------------------------------------------------------------------------- */
+typedef struct amge_problem amge_problem;
+
+amge_status amge_kuhn_build(int32_t kind, int32_t n, int32_t nlevels, const double* alpha_hex,
+                            const double* beta_hex, amge_problem** out);
+int32_t amge_problem_nlevels(const amge_problem* p);
+/* Fills levels[0..nlevels-1] with pointers into p (valid until amge_problem_free). */
+amge_status amge_problem_levels(const amge_problem* p, amge_level* levels);
+void amge_problem_free(amge_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMGE_H */

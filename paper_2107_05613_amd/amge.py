@@ -1,0 +1,255 @@
+"""Thin ctypes binding of libamge.so (include/amge.h); argument marshalling only.
+
+Every numerical step of the solve phase runs in the library's HIP kernels; this
+module converts Python arguments to the C ABI.  Device vectors are torch CUDA
+(HIP) tensors passed by pointer; streams are torch streams.  There is no Python
+or CPU fallback: if the library is missing, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamge.so")
+
+CURL, DIV = 0, 1
+OP_A, OP_AHAT, OP_D, OP_DT, OP_P, OP_PT, OP_SMOOTH, OP_SMOOTHT, OP_COARSE = range(9)
+
+STATUS = {0: "AMGE_OK", 1: "AMGE_NOT_CONVERGED", -1: "AMGE_ERR_ARG", -2: "AMGE_ERR_SHAPE",
+          -3: "AMGE_ERR_NOT_SPD", -4: "AMGE_ERR_OOM", -5: "AMGE_ERR_HIP", -6: "AMGE_ERR_BREAKDOWN",
+          -7: "AMGE_ERR_NONFINITE", -8: "AMGE_ERR_BUSY"}
+
+
+class AmgeError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class CsrC(C.Structure):
+    _fields_ = [("nrows", C.c_int32), ("ncols", C.c_int32), ("nnz", C.c_int64),
+                ("rowptr", C.POINTER(C.c_int32)), ("col", C.POINTER(C.c_int32)),
+                ("val", C.POINTER(C.c_double))]
+
+
+class LevelC(C.Structure):
+    _fields_ = [("A", CsrC), ("D", CsrC), ("P", CsrC)]
+
+
+class OptsC(C.Structure):
+    _fields_ = [("nu_primary", C.c_int32), ("nu_aux", C.c_int32), ("precond_bits", C.c_int32),
+                ("max_rhs", C.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2107_05613_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, f64 = C.c_void_p, C.c_int32, C.c_double
+    sig = {
+        "amge_default_opts": (None, [C.POINTER(OptsC)]),
+        "amge_setup_hierarchy": (i32, [C.POINTER(LevelC), i32, C.POINTER(OptsC), vp, C.POINTER(vp)]),
+        "amge_destroy": (None, [vp]),
+        "amge_footprint": (i32, [vp, C.POINTER(C.c_size_t)]),
+        "amge_vcycle": (i32, [vp, vp, vp, i32, vp]),
+        "amge_pcg_solve": (i32, [vp, vp, vp, i32, f64, i32, i32, C.POINTER(i32), C.POINTER(f64), vp]),
+        "amge_level_apply": (i32, [vp, i32, i32, i32, vp, vp, vp, vp]),
+        "amge_hierarchy_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
+        "amge_timing_enable": (i32, [vp, i32]),
+        "amge_vcycle_bytes": (i32, [vp, i32, C.POINTER(f64)]),
+        "amge_timing_read": (i32, [vp, C.POINTER(f64), C.POINTER(C.c_int64), C.POINTER(f64)]),
+        "amge_last_error": (C.c_char_p, []),
+        "amge_kuhn_build": (i32, [i32, i32, i32, C.POINTER(f64), C.POINTER(f64), C.POINTER(vp)]),
+        "amge_problem_nlevels": (i32, [vp]),
+        "amge_problem_levels": (i32, [vp, C.POINTER(LevelC)]),
+        "amge_problem_free": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+# Names declared by include/amge.h (checked by the test suite against the header).
+EXPORTS = ("amge_default_opts", "amge_setup_hierarchy", "amge_destroy", "amge_footprint", "amge_vcycle",
+           "amge_pcg_solve", "amge_level_apply", "amge_hierarchy_info", "amge_last_error",
+           "amge_timing_enable", "amge_timing_read", "amge_vcycle_bytes",
+           "amge_kuhn_build", "amge_problem_nlevels", "amge_problem_levels", "amge_problem_free")
+
+
+def lib():
+    return _lib
+
+
+def _check(code, allow=(0,)):
+    if code in allow:
+        return code
+    raise AmgeError(code, _lib.amge_last_error().decode())
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or an int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ----------------------------------------------------------------------------- problems
+class HostCsr:
+    """Host CSR arrays (numpy), FP64 values, int32 indices."""
+
+    def __init__(self, nrows, ncols, rowptr, col, val):
+        self.shape = (int(nrows), int(ncols))
+        self.rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+        self.val = np.ascontiguousarray(val, dtype=np.float64)
+
+    @property
+    def nnz(self):
+        return len(self.col)
+
+    @classmethod
+    def from_scipy(cls, M):
+        M = M.tocsr()
+        M.sort_indices()
+        return cls(M.shape[0], M.shape[1], M.indptr, M.indices, M.data)
+
+    def to_c(self):
+        c = CsrC()
+        c.nrows, c.ncols, c.nnz = self.shape[0], self.shape[1], self.nnz
+        c.rowptr = self.rowptr.ctypes.data_as(C.POINTER(C.c_int32))
+        c.col = self.col.ctypes.data_as(C.POINTER(C.c_int32))
+        c.val = self.val.ctypes.data_as(C.POINTER(C.c_double))
+        return c
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        return sp.csr_matrix((self.val, self.col, self.rowptr), shape=self.shape)
+
+
+def _csr_copy(c: CsrC):
+    nr, nnz = c.nrows, c.nnz
+    rp = np.ctypeslib.as_array(c.rowptr, (nr + 1,)).copy() if nr else np.zeros(1, np.int32)
+    ci = np.ctypeslib.as_array(c.col, (nnz,)).copy() if nnz else np.zeros(0, np.int32)
+    va = np.ctypeslib.as_array(c.val, (nnz,)).copy() if nnz else np.zeros(0)
+    return HostCsr(nr, c.ncols, rp, ci, va)
+
+
+def build_problem(kind, n, nlevels, alpha_hex, beta_hex):
+    """Structured workload (amge_kuhn_build): per level (A, D, P) as HostCsr, P None on the last."""
+    k = {"curl": CURL, "div": DIV}.get(kind, kind)
+    a = np.ascontiguousarray(alpha_hex, dtype=np.float64)
+    b = np.ascontiguousarray(beta_hex, dtype=np.float64)
+    if a.size != n ** 3 or b.size != n ** 3:
+        raise ValueError("alpha_hex and beta_hex need n**3 values")
+    h = C.c_void_p()
+    _check(_lib.amge_kuhn_build(k, n, nlevels, a.ctypes.data_as(C.POINTER(C.c_double)),
+                                b.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)))
+    try:
+        L = _lib.amge_problem_nlevels(h)
+        arr = (LevelC * L)()
+        _check(_lib.amge_problem_levels(h, arr))
+        out = []
+        for i, lv in enumerate(arr):
+            P = _csr_copy(lv.P) if i + 1 < L else None
+            out.append((_csr_copy(lv.A), _csr_copy(lv.D), P))
+        return out
+    finally:
+        _lib.amge_problem_free(h)
+
+
+# ----------------------------------------------------------------------------- hierarchy
+class Hierarchy:
+    """Device-resident AMGe hierarchy (amge_setup_hierarchy)."""
+
+    def __init__(self, levels, nu_primary=2, nu_aux=2, precond_bits=32, max_rhs=1, stream=None):
+        L = len(levels)
+        arr = (LevelC * L)()
+        self._keep = []
+        for i, (A, D, P) in enumerate(levels):
+            mats = []
+            for M in (A, D, P):
+                if M is None:
+                    M = HostCsr(0, 0, np.zeros(1, np.int32), [], [])
+                elif not isinstance(M, HostCsr):
+                    M = HostCsr.from_scipy(M)
+                mats.append(M)
+            self._keep.extend(mats)
+            arr[i].A, arr[i].D, arr[i].P = (m.to_c() for m in mats)
+        opts = OptsC(nu_primary, nu_aux, precond_bits, max_rhs)
+        h = C.c_void_p()
+        _check(_lib.amge_setup_hierarchy(arr, L, C.byref(opts), _stream(stream), C.byref(h)))
+        self._h = h
+        self._keep = None
+        self.opts = opts
+        nl = C.c_int32()
+        rows = (C.c_int32 * L)()
+        _check(_lib.amge_hierarchy_info(h, C.byref(nl), rows))
+        self.rows = list(rows)
+        self.nlevels = nl.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.amge_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def footprint(self):
+        b = C.c_size_t()
+        _check(_lib.amge_footprint(self._h, C.byref(b)))
+        return b.value
+
+    def vcycle(self, r, z, nrhs=1, stream=None):
+        _check(_lib.amge_vcycle(self._h, _ptr(r), _ptr(z), nrhs, _stream(stream)))
+
+    def pcg(self, b, x, rtol=1e-8, maxit=500, stop_norm=0, nrhs=1, stream=None):
+        """Returns (status, iters[nrhs], relres[nrhs]); status 0 or 1 (not converged)."""
+        it = (C.c_int32 * nrhs)()
+        rr = (C.c_double * nrhs)()
+        code = _check(_lib.amge_pcg_solve(self._h, _ptr(b), _ptr(x), nrhs, float(rtol), int(maxit),
+                                          int(stop_norm), it, rr, _stream(stream)), allow=(0, 1))
+        return code, list(it), list(rr)
+
+    def vcycle_bytes(self, precision=32):
+        v = C.c_double()
+        _check(_lib.amge_vcycle_bytes(self._h, precision, C.byref(v)))
+        return v.value
+
+    def timing_enable(self, on=True):
+        _check(_lib.amge_timing_enable(self._h, 1 if on else 0))
+
+    def timing_read(self):
+        """(ms, launches, algorithmic bytes) of the fine-level A kernels since the last read."""
+        ms, n, by = C.c_double(), C.c_int64(), C.c_double()
+        _check(_lib.amge_timing_read(self._h, C.byref(ms), C.byref(n), C.byref(by)))
+        return ms.value, n.value, by.value
+
+    def level_apply(self, level, op, x, out, x2=None, precision=64, stream=None):
+        _check(_lib.amge_level_apply(self._h, level, op, precision, _ptr(x), _ptr(x2), _ptr(out),
+                                     _stream(stream)))

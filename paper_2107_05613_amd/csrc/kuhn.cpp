@@ -1,0 +1,1098 @@
+// Problem builder for the structured workloads: Kuhn-tetrahedral fine mesh of the unit
+// cube, lowest-order Nedelec / Raviart-Thomas matrices (eq. (2.2)), and the AMGe
+// hierarchy of section 3 for 2x2x2 agglomerates.
+//
+// Every agglomerate of a level is a translate of the same 2x2x2 block (uniform Kuhn
+// mesh, unweighted L2 extension masses), so the local problems of section 3.3 are
+// solved once per level on a reference block and the resulting local prolongators
+// are placed at every agglomerate.  Shared rows receive identical values from both
+// sides ("overwriting" assembly, section 2.2 footnote).
+//
+// Local extension problems (eqs. (3.6), (3.8)): minimise the L2 norm of the extension
+// subject to the derivative constraint on the entity's interior, with the trace on its
+// boundary fixed.  Solved by the range-space method: drop linearly dependent
+// constraint rows (Gaussian elimination with partial pivoting), Cholesky of the interior
+// mass, Schur complement on the multipliers.
+#include <array>
+#include <cmath>
+#include <map>
+#include <memory>
+
+#include "common.hpp"
+
+namespace amge {
+namespace {
+
+// ------------------------------------------------------------------ small dense algebra
+struct Mat {
+    int r = 0, c = 0;
+    std::vector<double> a;
+    Mat() = default;
+    Mat(int r_, int c_) : r(r_), c(c_), a((size_t)r_ * c_, 0.0) {}
+    double& operator()(int i, int j) { return a[(size_t)i * c + j]; }
+    double operator()(int i, int j) const { return a[(size_t)i * c + j]; }
+};
+
+Mat matmul(const Mat& A, const Mat& B) {
+    Mat C(A.r, B.c);
+    for (int i = 0; i < A.r; ++i)
+        for (int k = 0; k < A.c; ++k) {
+            double v = A(i, k);
+            if (v == 0) continue;
+            for (int j = 0; j < B.c; ++j) C(i, j) += v * B(k, j);
+        }
+    return C;
+}
+
+Mat tmatmul(const Mat& A, const Mat& B) {  // A^T B
+    Mat C(A.c, B.c);
+    for (int k = 0; k < A.r; ++k)
+        for (int i = 0; i < A.c; ++i) {
+            double v = A(k, i);
+            if (v == 0) continue;
+            for (int j = 0; j < B.c; ++j) C(i, j) += v * B(k, j);
+        }
+    return C;
+}
+
+// In-place Cholesky (lower), returns false if not positive definite.
+bool cholesky(Mat& L) {
+    int n = L.r;
+    for (int j = 0; j < n; ++j) {
+        double d = L(j, j);
+        for (int k = 0; k < j; ++k) d -= L(j, k) * L(j, k);
+        if (!(d > 0)) return false;
+        d = std::sqrt(d);
+        L(j, j) = d;
+        for (int i = j + 1; i < n; ++i) {
+            double s = L(i, j);
+            for (int k = 0; k < j; ++k) s -= L(i, k) * L(j, k);
+            L(i, j) = s / d;
+        }
+        for (int k = j + 1; k < n; ++k) L(j, k) = 0.0;
+    }
+    return true;
+}
+
+// Solve L L^T X = B in place (B: n x m).
+void chol_solve(const Mat& L, Mat& B) {
+    int n = L.r;
+    for (int col = 0; col < B.c; ++col) {
+        for (int i = 0; i < n; ++i) {
+            double s = B(i, col);
+            for (int k = 0; k < i; ++k) s -= L(i, k) * B(k, col);
+            B(i, col) = s / L(i, i);
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = B(i, col);
+            for (int k = i + 1; k < n; ++k) s -= L(k, i) * B(k, col);
+            B(i, col) = s / L(i, i);
+        }
+    }
+}
+
+// Indices of a maximal set of linearly independent rows of K (partial pivoting on rows).
+std::vector<int> independent_rows(const Mat& K, double tol) {
+    Mat W = K;
+    std::vector<int> rows;
+    std::vector<char> used(K.r, 0);
+    double scale = 0;
+    for (double v : K.a) scale = std::max(scale, std::fabs(v));
+    for (int j = 0; j < K.c && (int)rows.size() < K.r; ++j) {
+        int piv = -1;
+        double best = tol * scale;
+        for (int i = 0; i < K.r; ++i)
+            if (!used[i] && std::fabs(W(i, j)) > best) { best = std::fabs(W(i, j)); piv = i; }
+        if (piv < 0) continue;
+        used[piv] = 1;
+        rows.push_back(piv);
+        for (int i = 0; i < K.r; ++i) {
+            if (used[i] || W(i, j) == 0) continue;
+            double f = W(i, j) / W(piv, j);
+            for (int l = j; l < K.c; ++l) W(i, l) -= f * W(piv, l);
+        }
+    }
+    std::sort(rows.begin(), rows.end());
+    return rows;
+}
+
+// Minimum-mass extension on one entity.
+//   M     mass on the entity's closure dofs (nd x nd), or empty if the constraint alone
+//         determines the interior values
+//   K     constraint rows over the closure dofs (m x nd)
+//   intr  interior mask (nd)
+//   S     right-hand sides of the constraint (m x nrhs)
+//   UB    boundary values (nB x nrhs), in closure order of the non-interior dofs
+// Returns U_I (nI x nrhs).
+Mat extend(const Mat& M, const Mat& K, const std::vector<char>& intr, const Mat& S, const Mat& UB) {
+    int nd = K.c, m = K.r, nrhs = S.c;
+    std::vector<int> I, B;
+    for (int j = 0; j < nd; ++j) (intr[j] ? I : B).push_back(j);
+    int nI = (int)I.size();
+    Mat KI(m, nI), G(m, nrhs);
+    for (int i = 0; i < m; ++i) {
+        for (int a = 0; a < nI; ++a) KI(i, a) = K(i, I[a]);
+        for (int t = 0; t < nrhs; ++t) {
+            double s = S(i, t);
+            for (size_t b = 0; b < B.size(); ++b) s -= K(i, B[b]) * UB((int)b, t);
+            G(i, t) = s;
+        }
+    }
+    std::vector<int> R = independent_rows(KI, 1e-12);
+    int r = (int)R.size();
+    Mat KR(r, nI), GR(r, nrhs);
+    for (int i = 0; i < r; ++i) {
+        for (int a = 0; a < nI; ++a) KR(i, a) = KI(R[i], a);
+        for (int t = 0; t < nrhs; ++t) GR(i, t) = G(R[i], t);
+    }
+    Mat U(nI, nrhs);
+    if (r == nI) {
+        // square nonsingular: solve KR U = GR by Gaussian elimination with pivoting
+        Mat Aug = KR, X = GR;
+        std::vector<int> perm(nI);
+        for (int i = 0; i < nI; ++i) perm[i] = i;
+        for (int j = 0; j < nI; ++j) {
+            int piv = j;
+            for (int i = j + 1; i < nI; ++i)
+                if (std::fabs(Aug(i, j)) > std::fabs(Aug(piv, j))) piv = i;
+            if (piv != j) {
+                for (int l = 0; l < nI; ++l) std::swap(Aug(j, l), Aug(piv, l));
+                for (int t = 0; t < nrhs; ++t) std::swap(X(j, t), X(piv, t));
+            }
+            for (int i = j + 1; i < nI; ++i) {
+                double f = Aug(i, j) / Aug(j, j);
+                if (f == 0) continue;
+                for (int l = j; l < nI; ++l) Aug(i, l) -= f * Aug(j, l);
+                for (int t = 0; t < nrhs; ++t) X(i, t) -= f * X(j, t);
+            }
+        }
+        for (int t = 0; t < nrhs; ++t)
+            for (int i = nI - 1; i >= 0; --i) {
+                double s = X(i, t);
+                for (int l = i + 1; l < nI; ++l) s -= Aug(i, l) * U(l, t);
+                U(i, t) = s / Aug(i, i);
+            }
+    } else {
+        if (M.r == 0) fail(AMGE_ERR_ARG, "extension not determined by its constraint");
+        // KKT: M_II u + K_R^T lam = -M_IB u_B,  K_R u = g_R
+        Mat L(nI, nI), F(nI, nrhs);
+        for (int a = 0; a < nI; ++a) {
+            for (int b = 0; b < nI; ++b) L(a, b) = M(I[a], I[b]);
+            for (int t = 0; t < nrhs; ++t) {
+                double s = 0;
+                for (size_t b = 0; b < B.size(); ++b) s -= M(I[a], B[b]) * UB((int)b, t);
+                F(a, t) = s;
+            }
+        }
+        if (!cholesky(L)) fail(AMGE_ERR_NOT_SPD, "local mass not positive definite");
+        Mat Y(nI, r);                       // M_II^{-1} K_R^T
+        for (int a = 0; a < nI; ++a)
+            for (int i = 0; i < r; ++i) Y(a, i) = KR(i, a);
+        chol_solve(L, Y);
+        Mat Sch = matmul(KR, Y);            // K_R M^{-1} K_R^T
+        Mat MF = F;
+        chol_solve(L, MF);                  // M^{-1} f
+        Mat rhs = matmul(KR, MF);           // K_R M^{-1} f - g_R
+        for (int i = 0; i < r; ++i)
+            for (int t = 0; t < nrhs; ++t) rhs(i, t) -= GR(i, t);
+        if (!cholesky(Sch)) fail(AMGE_ERR_NOT_SPD, "extension Schur complement not positive definite");
+        chol_solve(Sch, rhs);               // lam
+        Mat YL = matmul(Y, rhs);
+        for (int a = 0; a < nI; ++a)
+            for (int t = 0; t < nrhs; ++t) U(a, t) = MF(a, t) - YL(a, t);
+    }
+    // consistency: every constraint row (including dropped ones) must hold
+    double res = 0, gn = 0;
+    for (int i = 0; i < m; ++i)
+        for (int t = 0; t < nrhs; ++t) {
+            double s = -G(i, t);
+            for (int a = 0; a < nI; ++a) s += KI(i, a) * U(a, t);
+            res = std::max(res, std::fabs(s));
+            gn = std::max(gn, std::fabs(G(i, t)));
+        }
+    if (res > 1e-10 * std::max(1.0, gn)) fail(AMGE_ERR_ARG, "inconsistent extension constraint");
+    return U;
+}
+
+// ------------------------------------------------------------------ geometry
+struct V3 {
+    double x, y, z;
+};
+V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+double comp(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+
+const int TE[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};   // local edges
+const int TF[4][3] = {{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 1, 2}};       // face opposite vertex i
+
+// Element data of one tetrahedron from its vertex lattice coordinates (ints) and h.
+struct Tet {
+    double vol;
+    V3 x[4], g[4];   // coordinates, barycentric gradients
+    double s[4];     // +1 if the face's orientation normal points outward
+};
+
+Tet make_tet(const std::array<std::array<int, 3>, 4>& P, double h) {
+    Tet t;
+    for (int i = 0; i < 4; ++i) t.x[i] = {P[i][0] * h, P[i][1] * h, P[i][2] * h};
+    // barycentric gradients from the cofactors of the edge vectors e_a = x_a - x_0
+    V3 e1 = t.x[1] - t.x[0], e2 = t.x[2] - t.x[0], e3 = t.x[3] - t.x[0];
+    double det = dot(e1, cross(e2, e3));
+    t.vol = std::fabs(det) / 6.0;
+    t.g[1] = (1.0 / det) * cross(e2, e3);
+    t.g[2] = (1.0 / det) * cross(e3, e1);
+    t.g[3] = (1.0 / det) * cross(e1, e2);
+    t.g[0] = -1.0 * (t.g[1] + t.g[2] + t.g[3]);
+    for (int i = 0; i < 4; ++i) {
+        const int* f = TF[i];
+        V3 nrm = cross(t.x[f[1]] - t.x[f[0]], t.x[f[2]] - t.x[f[0]]);
+        t.s[i] = dot(nrm, t.x[f[0]] - t.x[i]) > 0 ? 1.0 : -1.0;
+    }
+    return t;
+}
+
+// Whitney edge mass: w_p = sum_a lambda_a v_{p,a} with v_{p,i} = grad l_j, v_{p,j} = -grad l_i
+void nd_mass(const Tet& t, double M[6][6]) {
+    V3 v[6][4];
+    for (int p = 0; p < 6; ++p) {
+        for (int a = 0; a < 4; ++a) v[p][a] = {0, 0, 0};
+        v[p][TE[p][0]] = t.g[TE[p][1]];
+        v[p][TE[p][1]] = -1.0 * t.g[TE[p][0]];
+    }
+    for (int p = 0; p < 6; ++p)
+        for (int q = 0; q < 6; ++q) {
+            double s = 0;
+            for (int a = 0; a < 4; ++a)
+                for (int b = 0; b < 4; ++b) s += dot(v[p][a], v[q][b]) * (a == b ? 2.0 : 1.0);
+            M[p][q] = s * t.vol / 20.0;
+        }
+}
+
+// Curl-curl element matrix, curl w_ij = 2 grad l_i x grad l_j (constant).
+void curlcurl(const Tet& t, double K[6][6]) {
+    V3 c[6];
+    for (int p = 0; p < 6; ++p) c[p] = 2.0 * cross(t.g[TE[p][0]], t.g[TE[p][1]]);
+    for (int p = 0; p < 6; ++p)
+        for (int q = 0; q < 6; ++q) K[p][q] = t.vol * dot(c[p], c[q]);
+}
+
+// Face (RT) mass: w_i = s_i (x - x_i) / (3 vol); integral of (x-a).(x-b) over the tet is
+// vol [ (c-a).(c-b) + sum_k |x_k - c|^2 / 20 ] with c the centroid.
+void rt_mass(const Tet& t, double M[4][4]) {
+    V3 c = 0.25 * (t.x[0] + t.x[1] + t.x[2] + t.x[3]);
+    double mom = 0;
+    for (int k = 0; k < 4; ++k) mom += dot(t.x[k] - c, t.x[k] - c);
+    mom /= 20.0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double in = t.vol * (dot(c - t.x[i], c - t.x[j]) + mom);
+            M[i][j] = t.s[i] * t.s[j] * in / (9.0 * t.vol * t.vol);
+        }
+}
+
+// Tangential-trace (2D Whitney edge) mass on a triangle, local edges (01),(02),(12).
+void tri_trace_mass(V3 x0, V3 x1, V3 x2, double M[3][3]) {
+    V3 e1 = x1 - x0, e2 = x2 - x0;
+    V3 n = cross(e1, e2);
+    double nn = dot(n, n);
+    double area = 0.5 * std::sqrt(nn);
+    // in-plane barycentric gradients: grad l_1 = (e2 x n)/|n|^2 ... orthogonal to e2, dot e1 = 1
+    V3 g1 = (1.0 / nn) * cross(e2, n);
+    V3 g2 = (1.0 / nn) * cross(n, e1);
+    V3 g[3] = {-1.0 * (g1 + g2), g1, g2};
+    const int E[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    V3 v[3][3];
+    for (int p = 0; p < 3; ++p) {
+        for (int a = 0; a < 3; ++a) v[p][a] = {0, 0, 0};
+        v[p][E[p][0]] = g[E[p][1]];
+        v[p][E[p][1]] = -1.0 * g[E[p][0]];
+    }
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) {
+            double s = 0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) s += dot(v[p][a], v[q][b]) * (a == b ? 2.0 : 1.0);
+            M[p][q] = s * area / 12.0;
+        }
+}
+
+// ------------------------------------------------------------------ Kuhn mesh
+struct Kuhn {
+    int n = 0;
+    int64_t nv = 0;
+    std::vector<std::array<int32_t, 2>> E;
+    std::vector<std::array<int32_t, 3>> F;
+    std::vector<std::array<int32_t, 4>> T;
+    std::vector<int64_t> ekey, fkey;
+    std::vector<std::array<int32_t, 6>> te;
+    std::vector<std::array<int32_t, 4>> tf;
+    std::vector<std::array<int32_t, 3>> fe;
+    std::array<int, 3> coord(int64_t v) const {
+        int m = n + 1;
+        return {(int)(v % m), (int)((v / m) % m), (int)(v / ((int64_t)m * m))};
+    }
+    int64_t vid(int i, int j, int k) const { int64_t m = n + 1; return i + m * (j + m * k); }
+    int32_t edge(int64_t a, int64_t b) const {
+        int64_t k = a * nv + b;
+        auto it = std::lower_bound(ekey.begin(), ekey.end(), k);
+        if (it == ekey.end() || *it != k) fail(AMGE_ERR_ARG, "edge not in mesh");
+        return (int32_t)(it - ekey.begin());
+    }
+    int32_t face(int64_t a, int64_t b, int64_t c) const {
+        int64_t k = (a * nv + b) * nv + c;
+        auto it = std::lower_bound(fkey.begin(), fkey.end(), k);
+        if (it == fkey.end() || *it != k) fail(AMGE_ERR_ARG, "face not in mesh");
+        return (int32_t)(it - fkey.begin());
+    }
+};
+
+Kuhn build_kuhn(int n) {
+    Kuhn K;
+    K.n = n;
+    int64_t m = n + 1;
+    K.nv = m * m * m;
+    if ((double)K.nv * K.nv * K.nv > 9.0e18) fail(AMGE_ERR_ARG, "mesh too large");
+    const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int64_t step[3] = {1, m, m * m};
+    K.T.reserve((size_t)n * n * n * 6);
+    for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+                int64_t base = K.vid(i, j, k);
+                for (auto& p : perms) {
+                    int64_t v1 = base + step[p[0]], v2 = v1 + step[p[1]], v3 = v2 + step[p[2]];
+                    K.T.push_back({(int32_t)base, (int32_t)v1, (int32_t)v2, (int32_t)v3});
+                }
+            }
+    std::sort(K.T.begin(), K.T.end());
+    for (auto& t : K.T) {
+        for (auto& e : TE) K.ekey.push_back((int64_t)t[e[0]] * K.nv + t[e[1]]);
+        for (auto& f : TF) K.fkey.push_back(((int64_t)t[f[0]] * K.nv + t[f[1]]) * K.nv + t[f[2]]);
+    }
+    std::sort(K.ekey.begin(), K.ekey.end());
+    K.ekey.erase(std::unique(K.ekey.begin(), K.ekey.end()), K.ekey.end());
+    std::sort(K.fkey.begin(), K.fkey.end());
+    K.fkey.erase(std::unique(K.fkey.begin(), K.fkey.end()), K.fkey.end());
+    for (int64_t k : K.ekey) K.E.push_back({(int32_t)(k / K.nv), (int32_t)(k % K.nv)});
+    for (int64_t k : K.fkey)
+        K.F.push_back({(int32_t)(k / (K.nv * K.nv)), (int32_t)((k / K.nv) % K.nv), (int32_t)(k % K.nv)});
+    K.te.resize(K.T.size());
+    K.tf.resize(K.T.size());
+    parallel_for((int64_t)K.T.size(), [&](int64_t s, int64_t e) {
+        for (int64_t t = s; t < e; ++t) {
+            auto& v = K.T[t];
+            for (int p = 0; p < 6; ++p) K.te[t][p] = K.edge(v[TE[p][0]], v[TE[p][1]]);
+            for (int p = 0; p < 4; ++p) K.tf[t][p] = K.face(v[TF[p][0]], v[TF[p][1]], v[TF[p][2]]);
+        }
+    });
+    K.fe.resize(K.F.size());
+    parallel_for((int64_t)K.F.size(), [&](int64_t s, int64_t e) {
+        for (int64_t f = s; f < e; ++f) {
+            auto& v = K.F[f];
+            K.fe[f] = {K.edge(v[0], v[1]), K.edge(v[0], v[2]), K.edge(v[1], v[2])};
+        }
+    });
+    return K;
+}
+
+Tet kuhn_tet(const Kuhn& K, int64_t t, double h) {
+    std::array<std::array<int, 3>, 4> P;
+    for (int i = 0; i < 4; ++i) P[i] = K.coord(K.T[t][i]);
+    return make_tet(P, h);
+}
+
+// ------------------------------------------------------------------ cube complex
+// Canonical orders: vertices by i + M(j + M k); edges by (tail, head) vertex indices;
+// faces by their sorted vertex tuples (for one base vertex: normal z, then y, then x);
+// cubes by base vertex.  Edge (p,a) runs along +e_a; face (p,a) has normal +e_a.
+struct Cubes {
+    int N = 0;
+    int64_t M = 0;
+    std::vector<int32_t> e0, f0;   // first edge / face index per base vertex
+    int32_t nE = 0, nF = 0, nT = 0, nV = 0;
+    static bool edge_ok(int N, int p[3], int a) { return p[a] < N; }
+    static bool face_ok(int N, int p[3], int a) {
+        int b = (a + 1) % 3, c = (a + 2) % 3;
+        return p[b] < N && p[c] < N;
+    }
+    explicit Cubes(int N_) : N(N_), M(N_ + 1) {
+        nV = (int32_t)(M * M * M);
+        e0.resize(nV + 1);
+        f0.resize(nV + 1);
+        int32_t ce = 0, cf = 0;
+        for (int64_t v = 0; v < nV; ++v) {
+            int p[3] = {(int)(v % M), (int)((v / M) % M), (int)(v / (M * M))};
+            e0[v] = ce;
+            f0[v] = cf;
+            for (int a = 0; a < 3; ++a) ce += edge_ok(N, p, a);
+            for (int a = 0; a < 3; ++a) cf += face_ok(N, p, a);
+        }
+        e0[nV] = ce;
+        f0[nV] = cf;
+        nE = ce;
+        nF = cf;
+        nT = N * N * N;
+    }
+    int64_t vid(const int p[3]) const { return p[0] + M * (p[1] + M * (int64_t)p[2]); }
+    int32_t edge(const int p[3], int a) const {
+        int32_t id = e0[vid(p)];
+        for (int b = 0; b < a; ++b) id += (p[b] < N);
+        return id;
+    }
+    int32_t face(const int p[3], int a) const {   // order within a base vertex: a = 2, 1, 0
+        int32_t id = f0[vid(p)];
+        for (int b = 2; b > a; --b) id += face_ok(N, (int*)p, b);
+        return id;
+    }
+    int32_t cube(const int p[3]) const { return p[0] + N * (p[1] + N * p[2]); }
+    // incidences
+    Csr grad() const {
+        Csr G;
+        G.nrows = nE; G.ncols = nV;
+        for (int64_t v = 0; v < nV; ++v) {
+            int p[3] = {(int)(v % M), (int)((v / M) % M), (int)(v / (M * M))};
+            for (int a = 0; a < 3; ++a) {
+                if (p[a] >= N) continue;
+                int q[3] = {p[0], p[1], p[2]};
+                q[a]++;
+                G.col.push_back((int32_t)v); G.val.push_back(-1.0);
+                G.col.push_back((int32_t)vid(q)); G.val.push_back(1.0);
+                G.rowptr.push_back((int32_t)G.col.size());
+            }
+        }
+        return G;
+    }
+    Csr curl() const {
+        std::vector<int64_t> keys;
+        std::vector<double> vals;
+        for (int64_t v = 0; v < nV; ++v) {
+            int p[3] = {(int)(v % M), (int)((v / M) % M), (int)(v / (M * M))};
+            for (int a = 0; a < 3; ++a) {
+                if (!face_ok(N, p, a)) continue;
+                int b = (a + 1) % 3, c = (a + 2) % 3;
+                int32_t f = face(p, a);
+                int pb[3] = {p[0], p[1], p[2]}, pc[3] = {p[0], p[1], p[2]};
+                pb[b]++; pc[c]++;
+                int32_t es[4] = {edge(p, b), edge(pb, c), edge(pc, b), edge(p, c)};
+                double sg[4] = {1, 1, -1, -1};
+                for (int t = 0; t < 4; ++t) { keys.push_back((int64_t)f * nE + es[t]); vals.push_back(sg[t]); }
+            }
+        }
+        return from_triplets(nF, nE, keys, vals, true);
+    }
+    Csr div() const {
+        std::vector<int64_t> keys;
+        std::vector<double> vals;
+        for (int k = 0; k < N; ++k)
+            for (int j = 0; j < N; ++j)
+                for (int i = 0; i < N; ++i) {
+                    int p[3] = {i, j, k};
+                    int32_t t = cube(p);
+                    for (int a = 0; a < 3; ++a) {
+                        int q[3] = {i, j, k};
+                        q[a]++;
+                        keys.push_back((int64_t)t * nF + face(q, a)); vals.push_back(1.0);
+                        keys.push_back((int64_t)t * nF + face(p, a)); vals.push_back(-1.0);
+                    }
+                }
+        return from_triplets(nT, nF, keys, vals, true);
+    }
+};
+
+// ------------------------------------------------------------------ reference block
+// A 2x2x2 block of cells (Kuhn hexes on the fine level, cubes on coarser levels) and
+// the single coarse cube it forms.  Block entities are classified by the coarse entity
+// holding them in its relative interior: an axis is "pinned" when all vertices of the
+// entity have the same coordinate 0 or 2 on it; owner dimension = number of free axes.
+struct Owner {
+    int dim;        // 0..3
+    int id;         // index in the coarse cube's canonical local order (N = 1 complex)
+    double phi;     // orientation of the block entity relative to the coarse one
+    double ratio;   // measure(entity) / measure(owner) when dims agree
+};
+
+struct Block {
+    // block entity counts and incidences (block-local canonical orders)
+    int nV = 27, nE = 0, nF = 0, nC = 0;
+    Csr C, Dv;                         // block curl (F x E), div (C x F)
+    std::vector<Owner> eo, fo, co;     // owners of edges / faces / cells
+    Mat Mnd, Mrt;                      // block masses over all block edges / faces
+    std::vector<std::vector<int>> fedges;   // edges of each block face
+    std::vector<Mat> ftrace;           // tangential-trace mass of each block face
+};
+
+// Canonical local orders of the single coarse cube (N = 1 complex).
+struct Unit {
+    Cubes cc{1};
+    int edge(int o[3], int a) const { return cc.edge(o, a); }
+    int face(int o[3], int a) const { return cc.face(o, a); }
+};
+
+// Owner of a block entity given the lattice coordinates of its vertices (0..2).
+Owner classify(const std::vector<std::array<int, 3>>& X, const Unit& U) {
+    int pinned[3], val[3];
+    int nfree = 0, freeax = -1, pinax = -1;
+    for (int a = 0; a < 3; ++a) {
+        int v = X[0][a];
+        bool same = true;
+        for (auto& x : X) same &= (x[a] == v);
+        pinned[a] = same && (v == 0 || v == 2);
+        val[a] = pinned[a] ? v / 2 : 0;
+        if (!pinned[a]) { ++nfree; freeax = a; } else pinax = a;
+    }
+    Owner o{nfree, 0, 1.0, 0.0};
+    if (nfree == 0) o.id = (int)U.cc.vid(val);
+    if (nfree == 1) o.id = U.edge(val, freeax);
+    if (nfree == 2) o.id = U.face(val, pinax);
+    if (nfree == 3) o.id = 0;
+    return o;
+}
+
+// Level-1 block: the Kuhn mesh of a 2x2x2 hex block.
+Block kuhn_block(double h, const Kuhn& B, const Unit& U) {
+    Block blk;
+    blk.nE = (int)B.E.size(); blk.nF = (int)B.F.size(); blk.nC = (int)B.T.size();
+    // incidences
+    {
+        std::vector<int64_t> keys; std::vector<double> vals;
+        for (int f = 0; f < blk.nF; ++f) {
+            double sg[3] = {1, -1, 1};   // boundary of (a,b,c): (a,b) - (a,c) + (b,c)
+            for (int t = 0; t < 3; ++t) { keys.push_back((int64_t)f * blk.nE + B.fe[f][t]); vals.push_back(sg[t]); }
+        }
+        blk.C = from_triplets(blk.nF, blk.nE, keys, vals, true);
+        keys.clear(); vals.clear();
+        for (int t = 0; t < blk.nC; ++t) {
+            Tet g = kuhn_tet(B, t, h);
+            for (int i = 0; i < 4; ++i) { keys.push_back((int64_t)t * blk.nF + B.tf[t][i]); vals.push_back(g.s[i]); }
+        }
+        blk.Dv = from_triplets(blk.nC, blk.nF, keys, vals, true);
+    }
+    // owners
+    for (int e = 0; e < blk.nE; ++e) {
+        std::vector<std::array<int, 3>> X = {B.coord(B.E[e][0]), B.coord(B.E[e][1])};
+        Owner o = classify(X, U);
+        if (o.dim == 1) {
+            int a = -1;
+            for (int ax = 0; ax < 3; ++ax) if (X[0][ax] != X[1][ax]) a = ax;
+            double d = X[1][a] - X[0][a];
+            o.phi = d > 0 ? 1.0 : -1.0;
+            o.ratio = std::fabs(d) / 2.0;
+        }
+        blk.eo.push_back(o);
+    }
+    for (int f = 0; f < blk.nF; ++f) {
+        std::vector<std::array<int, 3>> X = {B.coord(B.F[f][0]), B.coord(B.F[f][1]), B.coord(B.F[f][2])};
+        Owner o = classify(X, U);
+        if (o.dim == 2) {
+            V3 x0{(double)X[0][0], (double)X[0][1], (double)X[0][2]}, x1{(double)X[1][0], (double)X[1][1], (double)X[1][2]},
+               x2{(double)X[2][0], (double)X[2][1], (double)X[2][2]};
+            V3 nrm = cross(x1 - x0, x2 - x0);
+            int a = -1;
+            for (int ax = 0; ax < 3; ++ax) if (X[0][ax] == X[1][ax] && X[1][ax] == X[2][ax]) a = ax;
+            o.phi = comp(nrm, a) > 0 ? 1.0 : -1.0;
+            o.ratio = 0.5 * std::sqrt(dot(nrm, nrm)) / 4.0;
+        }
+        blk.fo.push_back(o);
+    }
+    for (int t = 0; t < blk.nC; ++t) {
+        Owner o{3, 0, 1.0, (1.0 / 6.0) / 8.0};
+        blk.co.push_back(o);
+    }
+    // masses
+    blk.Mnd = Mat(blk.nE, blk.nE);
+    blk.Mrt = Mat(blk.nF, blk.nF);
+    for (int t = 0; t < blk.nC; ++t) {
+        Tet g = kuhn_tet(B, t, h);
+        double Mn[6][6], Mr[4][4];
+        nd_mass(g, Mn);
+        rt_mass(g, Mr);
+        for (int p = 0; p < 6; ++p)
+            for (int q = 0; q < 6; ++q) blk.Mnd(B.te[t][p], B.te[t][q]) += Mn[p][q];
+        for (int p = 0; p < 4; ++p)
+            for (int q = 0; q < 4; ++q) blk.Mrt(B.tf[t][p], B.tf[t][q]) += Mr[p][q];
+    }
+    for (int f = 0; f < blk.nF; ++f) {
+        auto c0 = B.coord(B.F[f][0]), c1 = B.coord(B.F[f][1]), c2 = B.coord(B.F[f][2]);
+        V3 x0{c0[0] * h, c0[1] * h, c0[2] * h}, x1{c1[0] * h, c1[1] * h, c1[2] * h}, x2{c2[0] * h, c2[1] * h, c2[2] * h};
+        double Mt[3][3];
+        tri_trace_mass(x0, x1, x2, Mt);
+        Mat m(3, 3);
+        for (int p = 0; p < 3; ++p) for (int q = 0; q < 3; ++q) m(p, q) = Mt[p][q];
+        blk.fedges.push_back({B.fe[f][0], B.fe[f][1], B.fe[f][2]});
+        blk.ftrace.push_back(m);
+    }
+    return blk;
+}
+
+// Element data of a cube-complex level, identical for every cell/face of the level:
+// ND mass of a cube over its 12 edges and RT mass over its 6 faces (unit-cube canonical
+// local order), ND trace mass of a face over its 4 edges in cyclic order
+// (p,b), (p+e_b,c), (p+e_c,b), (p,c) for each normal axis a.
+struct CubeElem {
+    Mat nd, rt;
+    Mat trace[3];
+};
+
+// Coarser-level block: the 2x2x2 cube complex with element data `el`.
+Block cube_block(const CubeElem& el, const Unit& U) {
+    Block blk;
+    Cubes c2(2);
+    blk.nE = c2.nE; blk.nF = c2.nF; blk.nC = c2.nT;
+    blk.C = c2.curl();
+    blk.Dv = c2.div();
+    // owners: entity vertex lists in block lattice coordinates
+    for (int64_t v = 0; v < c2.nV; ++v) {
+        int p[3] = {(int)(v % 3), (int)((v / 3) % 3), (int)(v / 9)};
+        for (int a = 0; a < 3; ++a) {
+            if (p[a] >= 2) continue;
+            std::array<int, 3> x0 = {p[0], p[1], p[2]}, x1 = x0;
+            x1[a]++;
+            Owner o = classify({x0, x1}, U);
+            if (o.dim == 1) { o.phi = 1.0; o.ratio = 0.5; }
+            blk.eo.push_back(o);
+        }
+    }
+    // faces in canonical order: per base vertex a = 2, 1, 0
+    std::vector<std::array<int, 4>> fdesc;   // p0, p1, p2, a
+    for (int64_t v = 0; v < c2.nV; ++v) {
+        int p[3] = {(int)(v % 3), (int)((v / 3) % 3), (int)(v / 9)};
+        for (int a = 2; a >= 0; --a) {
+            if (!Cubes::face_ok(2, p, a)) continue;
+            int b = (a + 1) % 3, c = (a + 2) % 3;
+            std::array<int, 3> x0 = {p[0], p[1], p[2]}, xb = x0, xc = x0, xbc = x0;
+            xb[b]++; xc[c]++; xbc[b]++; xbc[c]++;
+            Owner o = classify({x0, xb, xc, xbc}, U);
+            if (o.dim == 2) { o.phi = 1.0; o.ratio = 0.25; }
+            blk.fo.push_back(o);
+            fdesc.push_back({p[0], p[1], p[2], a});
+        }
+    }
+    for (int t = 0; t < blk.nC; ++t) blk.co.push_back(Owner{3, 0, 1.0, 0.125});
+    if ((int)blk.eo.size() != blk.nE || (int)blk.fo.size() != blk.nF) fail(AMGE_ERR_ARG, "block enumeration");
+    // masses: every cell carries the element masses, mapped through the unit-cube order
+    blk.Mnd = Mat(blk.nE, blk.nE);
+    blk.Mrt = Mat(blk.nF, blk.nF);
+    for (int k = 0; k < 2; ++k)
+        for (int j = 0; j < 2; ++j)
+            for (int i = 0; i < 2; ++i) {
+                int q[3] = {i, j, k};
+                std::vector<int> le(12), lf(6);
+                for (int a = 0; a < 3; ++a)
+                    for (int s = 0; s < 2; ++s)
+                        for (int r = 0; r < 2; ++r) {
+                            int o[3] = {0, 0, 0};
+                            o[(a + 1) % 3] = s; o[(a + 2) % 3] = r;
+                            int g[3] = {q[0] + o[0], q[1] + o[1], q[2] + o[2]};
+                            le[U.edge(o, a)] = c2.edge(g, a);
+                        }
+                for (int a = 0; a < 3; ++a)
+                    for (int s = 0; s < 2; ++s) {
+                        int o[3] = {0, 0, 0};
+                        o[a] = s;
+                        int g[3] = {q[0] + o[0], q[1] + o[1], q[2] + o[2]};
+                        lf[U.face(o, a)] = c2.face(g, a);
+                    }
+                if (el.nd.r)
+                    for (int p = 0; p < 12; ++p)
+                        for (int r = 0; r < 12; ++r) blk.Mnd(le[p], le[r]) += el.nd(p, r);
+                for (int p = 0; p < 6; ++p)
+                    for (int r = 0; r < 6; ++r) blk.Mrt(lf[p], lf[r]) += el.rt(p, r);
+            }
+    for (auto& d : fdesc) {
+        int p[3] = {d[0], d[1], d[2]}, a = d[3], b = (a + 1) % 3, c = (a + 2) % 3;
+        int pb[3] = {p[0], p[1], p[2]}, pc[3] = {p[0], p[1], p[2]};
+        pb[b]++; pc[c]++;
+        blk.fedges.push_back({c2.edge(p, b), c2.edge(pb, c), c2.edge(pc, b), c2.edge(p, c)});
+        blk.ftrace.push_back(el.trace[a].r ? el.trace[a] : Mat(4, 4));
+    }
+    return blk;
+}
+
+// Local prolongators of a block: rows = block entities, cols = unit-cube entities.
+struct LocalP {
+    Mat rt;   // nF x 6
+    Mat nd;   // nE x 12
+};
+
+LocalP solve_block(const Block& blk, const Unit& U, bool need_nd) {
+    const Cubes& cc = U.cc;
+    Csr CH = cc.curl(), DH = cc.div();   // unit-cube incidences: 6 x 12, 1 x 6
+    LocalP L;
+    // ---- RT: PV traces on the coarse faces, eq. (3.5)
+    L.rt = Mat(blk.nF, 6);
+    for (int f = 0; f < blk.nF; ++f)
+        if (blk.fo[f].dim == 2) L.rt(f, blk.fo[f].id) = blk.fo[f].phi * blk.fo[f].ratio;
+    // ---- RT: face -> cube extension, eq. (3.6): div u = D^H[T,F] PV_T on every cell
+    {
+        std::vector<char> intr(blk.nF);
+        for (int f = 0; f < blk.nF; ++f) intr[f] = blk.fo[f].dim == 3;
+        Mat K(blk.nC, blk.nF);
+        for (int t = 0; t < blk.nC; ++t)
+            for (int k = blk.Dv.rowptr[t]; k < blk.Dv.rowptr[t + 1]; ++k) K(t, blk.Dv.col[k]) = blk.Dv.val[k];
+        Mat S(blk.nC, 6), UB;
+        for (int F = 0; F < 6; ++F) {
+            double dh = 0;
+            for (int k = DH.rowptr[0]; k < DH.rowptr[1]; ++k) if (DH.col[k] == F) dh = DH.val[k];
+            for (int t = 0; t < blk.nC; ++t) S(t, F) = dh * blk.co[t].ratio;
+        }
+        int nB = 0;
+        for (int f = 0; f < blk.nF; ++f) nB += !intr[f];
+        UB = Mat(nB, 6);
+        for (int f = 0, b = 0; f < blk.nF; ++f)
+            if (!intr[f]) { for (int F = 0; F < 6; ++F) UB(b, F) = L.rt(f, F); ++b; }
+        Mat UI = extend(blk.Mrt, K, intr, S, UB);
+        for (int f = 0, a = 0; f < blk.nF; ++f)
+            if (intr[f]) { for (int F = 0; F < 6; ++F) L.rt(f, F) = UI(a, F); ++a; }
+    }
+    if (!need_nd) return L;
+    // ---- ND: PV traces on the coarse edges
+    L.nd = Mat(blk.nE, 12);
+    for (int e = 0; e < blk.nE; ++e)
+        if (blk.eo[e].dim == 1) L.nd(e, blk.eo[e].id) = blk.eo[e].phi * blk.eo[e].ratio;
+    // ---- ND: edge -> face extensions, eq. (3.6) in 2D: curl u = C^H[F,E] PV_F on F
+    for (int F = 0; F < 6; ++F) {
+        std::vector<int> dofs;           // block edges in the closure of F
+        for (int e = 0; e < blk.nE; ++e) {
+            const Owner& o = blk.eo[e];
+            bool in = (o.dim == 2 && o.id == F);
+            if (o.dim == 1)
+                for (int k = CH.rowptr[F]; k < CH.rowptr[F + 1]; ++k) in |= (CH.col[k] == o.id);
+            if (in) dofs.push_back(e);
+        }
+        std::vector<int> rows;           // block faces interior to F
+        for (int f = 0; f < blk.nF; ++f) if (blk.fo[f].dim == 2 && blk.fo[f].id == F) rows.push_back(f);
+        int nd = (int)dofs.size();
+        std::map<int, int> loc;
+        for (int i = 0; i < nd; ++i) loc[dofs[i]] = i;
+        std::vector<char> intr(nd);
+        for (int i = 0; i < nd; ++i) intr[i] = blk.eo[dofs[i]].dim == 2;
+        Mat M(nd, nd), K((int)rows.size(), nd);
+        for (int r = 0; r < (int)rows.size(); ++r) {
+            int f = rows[r];
+            const auto& fe = blk.fedges[f];
+            const Mat& T = blk.ftrace[f];
+            for (size_t p = 0; p < fe.size(); ++p)
+                for (size_t q = 0; q < fe.size(); ++q) M(loc[fe[p]], loc[fe[q]]) += T((int)p, (int)q);
+            for (int k = blk.C.rowptr[f]; k < blk.C.rowptr[f + 1]; ++k) K(r, loc[blk.C.col[k]]) = blk.C.val[k];
+        }
+        std::vector<int> Es;             // coarse edges of F
+        std::vector<double> cs;
+        for (int k = CH.rowptr[F]; k < CH.rowptr[F + 1]; ++k) { Es.push_back(CH.col[k]); cs.push_back(CH.val[k]); }
+        int ne = (int)Es.size();
+        Mat S((int)rows.size(), ne), UB(nd - [&] { int c = 0; for (char x : intr) c += x; return c; }(), ne);
+        for (int r = 0; r < (int)rows.size(); ++r)
+            for (int j = 0; j < ne; ++j) S(r, j) = cs[j] * L.rt(rows[r], F);
+        for (int i = 0, b = 0; i < nd; ++i)
+            if (!intr[i]) { for (int j = 0; j < ne; ++j) UB(b, j) = L.nd(dofs[i], Es[j]); ++b; }
+        Mat UI = extend(M, K, intr, S, UB);
+        for (int i = 0, a = 0; i < nd; ++i)
+            if (intr[i]) { for (int j = 0; j < ne; ++j) L.nd(dofs[i], Es[j]) = UI(a, j); ++a; }
+    }
+    // ---- ND: face -> cube extension, eq. (3.8): curl u = sum_F C^H[F,E] (RT basis of F)
+    {
+        std::vector<char> intr(blk.nE);
+        for (int e = 0; e < blk.nE; ++e) intr[e] = blk.eo[e].dim == 3;
+        std::vector<int> rows;
+        for (int f = 0; f < blk.nF; ++f) if (blk.fo[f].dim == 3) rows.push_back(f);
+        Mat K((int)rows.size(), blk.nE);
+        for (int r = 0; r < (int)rows.size(); ++r)
+            for (int k = blk.C.rowptr[rows[r]]; k < blk.C.rowptr[rows[r] + 1]; ++k) K(r, blk.C.col[k]) = blk.C.val[k];
+        Mat S((int)rows.size(), 12);
+        for (int F = 0; F < 6; ++F)
+            for (int k = CH.rowptr[F]; k < CH.rowptr[F + 1]; ++k)
+                for (int r = 0; r < (int)rows.size(); ++r) S(r, CH.col[k]) += CH.val[k] * L.rt(rows[r], F);
+        int nB = 0;
+        for (char x : intr) nB += !x;
+        Mat UB(nB, 12);
+        for (int e = 0, b = 0; e < blk.nE; ++e)
+            if (!intr[e]) { for (int E = 0; E < 12; ++E) UB(b, E) = L.nd(e, E); ++b; }
+        Mat UI = extend(blk.Mnd, K, intr, S, UB);
+        for (int e = 0, a = 0; e < blk.nE; ++e)
+            if (intr[e]) { for (int E = 0; E < 12; ++E) L.nd(e, E) = UI(a, E); ++a; }
+    }
+    return L;
+}
+
+// Element data of the next level: RAP of the block masses with the local prolongators.
+CubeElem next_elem(const Block& blk, const LocalP& L, const Unit& U, bool need_nd) {
+    CubeElem el;
+    el.rt = tmatmul(L.rt, matmul(blk.Mrt, L.rt));
+    if (!need_nd) return el;
+    el.nd = tmatmul(L.nd, matmul(blk.Mnd, L.nd));
+    const Cubes& cc = U.cc;
+    for (int a = 0; a < 3; ++a) {
+        int b = (a + 1) % 3, c = (a + 2) % 3;
+        int o[3] = {0, 0, 0};
+        int F = cc.face(o, a);
+        int ob[3] = {0, 0, 0}, oc[3] = {0, 0, 0};
+        ob[b] = 1; oc[c] = 1;
+        int Es[4] = {cc.edge(o, b), cc.edge(ob, c), cc.edge(oc, b), cc.edge(o, c)};
+        // trace mass on F: block faces interior to F, over their edges
+        std::map<int, int> loc;
+        std::vector<int> dofs;
+        for (int f = 0; f < blk.nF; ++f)
+            if (blk.fo[f].dim == 2 && blk.fo[f].id == F)
+                for (int e : blk.fedges[f])
+                    if (!loc.count(e)) { loc[e] = (int)dofs.size(); dofs.push_back(e); }
+        Mat M((int)dofs.size(), (int)dofs.size());
+        for (int f = 0; f < blk.nF; ++f)
+            if (blk.fo[f].dim == 2 && blk.fo[f].id == F) {
+                const auto& fe = blk.fedges[f];
+                for (size_t p = 0; p < fe.size(); ++p)
+                    for (size_t q = 0; q < fe.size(); ++q) M(loc[fe[p]], loc[fe[q]]) += blk.ftrace[f]((int)p, (int)q);
+            }
+        Mat PF((int)dofs.size(), 4);
+        for (size_t i = 0; i < dofs.size(); ++i)
+            for (int j = 0; j < 4; ++j) PF((int)i, j) = L.nd(dofs[i], Es[j]);
+        el.trace[a] = tmatmul(PF, matmul(M, PF));
+    }
+    return el;
+}
+
+// ------------------------------------------------------------------ global assembly
+struct Problem {
+    int kind, n, nlevels;
+    std::vector<Csr> A, D, P;
+};
+
+// Fine system matrix, eq. (2.2).
+Csr fine_matrix(const Kuhn& K, int kind, const double* alpha, const double* beta) {
+    const int n = K.n;
+    const double h = 1.0 / n;
+    int64_t nt = (int64_t)K.T.size();
+    int per = kind == AMGE_CURL ? 36 : 16;
+    int32_t ndof = kind == AMGE_CURL ? (int32_t)K.E.size() : (int32_t)K.F.size();
+    std::vector<int64_t> keys(nt * per);
+    std::vector<double> vals(nt * per);
+    parallel_for(nt, [&](int64_t s, int64_t e) {
+        for (int64_t t = s; t < e; ++t) {
+            Tet g = kuhn_tet(K, t, h);
+            auto c0 = K.coord(K.T[t][0]);          // lower hex corner
+            int64_t hx = c0[0] + (int64_t)n * (c0[1] + (int64_t)n * c0[2]);
+            double al = alpha[hx], be = beta[hx];
+            int64_t o = t * per;
+            if (kind == AMGE_CURL) {
+                double M[6][6], Kc[6][6];
+                nd_mass(g, M);
+                curlcurl(g, Kc);
+                for (int p = 0; p < 6; ++p)
+                    for (int q = 0; q < 6; ++q) {
+                        keys[o] = (int64_t)K.te[t][p] * ndof + K.te[t][q];
+                        vals[o++] = al * Kc[p][q] + be * M[p][q];
+                    }
+            } else {
+                double M[4][4];
+                rt_mass(g, M);
+                for (int p = 0; p < 4; ++p)
+                    for (int q = 0; q < 4; ++q) {
+                        keys[o] = (int64_t)K.tf[t][p] * ndof + K.tf[t][q];
+                        vals[o++] = al * g.s[p] * g.s[q] / g.vol + be * M[p][q];
+                    }
+            }
+        }
+    });
+    return from_triplets(ndof, ndof, keys, vals, true);
+}
+
+Csr kuhn_grad(const Kuhn& K) {
+    Csr G;
+    G.nrows = (int32_t)K.E.size();
+    G.ncols = (int32_t)K.nv;
+    for (auto& e : K.E) {
+        G.col.push_back(e[0]); G.val.push_back(-1.0);
+        G.col.push_back(e[1]); G.val.push_back(1.0);
+        G.rowptr.push_back((int32_t)G.col.size());
+    }
+    return G;
+}
+
+Csr kuhn_curl(const Kuhn& K) {
+    std::vector<int64_t> keys;
+    std::vector<double> vals;
+    int32_t nE = (int32_t)K.E.size();
+    for (size_t f = 0; f < K.F.size(); ++f) {
+        double sg[3] = {1, -1, 1};
+        for (int t = 0; t < 3; ++t) { keys.push_back((int64_t)f * nE + K.fe[f][t]); vals.push_back(sg[t]); }
+    }
+    return from_triplets((int32_t)K.F.size(), nE, keys, vals, true);
+}
+
+// Place the block prolongator at every agglomerate.  `fine_index(q, local)` maps a block
+// entity of the agglomerate with base q to its global index on the finer level;
+// coarse entities (unit-cube local order) map to the coarser cube complex.
+template <class FineIndex>
+Csr stamp(const Mat& Pl, int kind_dim, int Nc, int32_t nfine, const FineIndex& fine_index) {
+    Cubes coarse(Nc);
+    Unit U;
+    // unit-cube entity (o, a) -> global coarse entity (q + o, a)
+    std::vector<std::array<int, 4>> udesc(kind_dim == 1 ? 12 : 6);
+    for (int a = 0; a < 3; ++a)
+        for (int s = 0; s < 2; ++s)
+            for (int r = 0; r < 2; ++r) {
+                if (kind_dim == 1) {
+                    int o[3] = {0, 0, 0};
+                    o[(a + 1) % 3] = s; o[(a + 2) % 3] = r;
+                    udesc[U.edge(o, a)] = {o[0], o[1], o[2], a};
+                } else if (r == 0) {
+                    int o[3] = {0, 0, 0};
+                    o[a] = s;
+                    udesc[U.face(o, a)] = {o[0], o[1], o[2], a};
+                }
+            }
+    double mx = 0;
+    for (double v : Pl.a) mx = std::max(mx, std::fabs(v));
+    const double tiny = 1e-14 * mx;   // entries that vanish up to rounding are not stored
+    int32_t ncoarse = kind_dim == 1 ? coarse.nE : coarse.nF;
+    int64_t ncube = (int64_t)Nc * Nc * Nc;
+    std::vector<std::pair<int, int>> nz;
+    for (int i = 0; i < Pl.r; ++i)
+        for (int j = 0; j < Pl.c; ++j)
+            if (std::fabs(Pl(i, j)) > tiny) nz.push_back({i, j});
+    std::vector<int64_t> keys(ncube * nz.size());
+    std::vector<double> vals(ncube * nz.size());
+    parallel_for(ncube, [&](int64_t s, int64_t e) {
+        std::vector<int32_t> fi(Pl.r), ci(Pl.c);
+        for (int64_t t = s; t < e; ++t) {
+            int q[3] = {(int)(t % Nc), (int)((t / Nc) % Nc), (int)(t / ((int64_t)Nc * Nc))};
+            for (int i = 0; i < Pl.r; ++i) fi[i] = fine_index(q, i);
+            for (int j = 0; j < Pl.c; ++j) {
+                int g[3] = {q[0] + udesc[j][0], q[1] + udesc[j][1], q[2] + udesc[j][2]};
+                ci[j] = kind_dim == 1 ? coarse.edge(g, udesc[j][3]) : coarse.face(g, udesc[j][3]);
+            }
+            int64_t o = t * (int64_t)nz.size();
+            for (auto& z : nz) {
+                keys[o] = (int64_t)fi[z.first] * ncoarse + ci[z.second];
+                vals[o++] = Pl(z.first, z.second);
+            }
+        }
+    });
+    return from_triplets(nfine, ncoarse, keys, vals, false);
+}
+
+Problem build(int kind, int n, int nlevels, const double* alpha, const double* beta) {
+    if (kind != AMGE_CURL && kind != AMGE_DIV) fail(AMGE_ERR_ARG, "kind must be AMGE_CURL or AMGE_DIV");
+    if (n < 1 || nlevels < 1) fail(AMGE_ERR_ARG, "n and nlevels must be positive");
+    if (nlevels > 1 && (n % (1 << (nlevels - 1))) != 0) fail(AMGE_ERR_ARG, "n not divisible by 2^(nlevels-1)");
+    if (!alpha || !beta) fail(AMGE_ERR_ARG, "null coefficient array");
+    for (int64_t i = 0; i < (int64_t)n * n * n; ++i)
+        if (!(alpha[i] > 0) || !(beta[i] > 0) || !std::isfinite(alpha[i]) || !std::isfinite(beta[i]))
+            fail(AMGE_ERR_ARG, "coefficients must be positive and finite");
+    const bool curl = kind == AMGE_CURL;
+    const int sdim = curl ? 1 : 2;
+    Problem pr;
+    pr.kind = kind; pr.n = n; pr.nlevels = nlevels;
+    Kuhn K = build_kuhn(n);
+    pr.A.push_back(fine_matrix(K, kind, alpha, beta));
+    pr.D.push_back(curl ? kuhn_grad(K) : kuhn_curl(K));
+    Unit U;
+    // level 1 -> 2: reference Kuhn block
+    CubeElem el;
+    if (nlevels > 1) {
+        Kuhn B = build_kuhn(2);
+        Block blk = kuhn_block(1.0 / n, B, U);
+        LocalP L = solve_block(blk, U, curl);
+        el = next_elem(blk, L, U, curl);
+        const Mat& Pl = curl ? L.nd : L.rt;
+        int32_t nfine = curl ? (int32_t)K.E.size() : (int32_t)K.F.size();
+        auto fine_index = [&](const int q[3], int i) -> int32_t {
+            int64_t off[3] = {2 * q[0], 2 * q[1], 2 * q[2]};
+            auto gv = [&](int32_t bv) {
+                auto c = B.coord(bv);
+                return K.vid((int)(c[0] + off[0]), (int)(c[1] + off[1]), (int)(c[2] + off[2]));
+            };
+            if (curl) return K.edge(gv(B.E[i][0]), gv(B.E[i][1]));
+            return K.face(gv(B.F[i][0]), gv(B.F[i][1]), gv(B.F[i][2]));
+        };
+        pr.P.push_back(stamp(Pl, sdim, n / 2, nfine, fine_index));
+    }
+    // coarser levels: reference cube-complex block
+    for (int k = 2; k < nlevels; ++k) {
+        int Nf = n >> (k - 1);      // cubes per side on level k
+        Block blk = cube_block(el, U);
+        LocalP L = solve_block(blk, U, curl);
+        CubeElem next = next_elem(blk, L, U, curl);
+        Cubes fineC(Nf), c2(2);
+        const Mat& Pl = curl ? L.nd : L.rt;
+        // block entity descriptors (base, axis) in the 2x2x2 block's canonical order
+        std::vector<std::array<int, 4>> bdesc;
+        for (int64_t v = 0; v < c2.nV; ++v) {
+            int p[3] = {(int)(v % 3), (int)((v / 3) % 3), (int)(v / 9)};
+            if (curl) {
+                for (int a = 0; a < 3; ++a) if (p[a] < 2) bdesc.push_back({p[0], p[1], p[2], a});
+            } else {
+                for (int a = 2; a >= 0; --a) if (Cubes::face_ok(2, p, a)) bdesc.push_back({p[0], p[1], p[2], a});
+            }
+        }
+        auto fine_index = [&](const int q[3], int i) -> int32_t {
+            int g[3] = {2 * q[0] + bdesc[i][0], 2 * q[1] + bdesc[i][1], 2 * q[2] + bdesc[i][2]};
+            return curl ? fineC.edge(g, bdesc[i][3]) : fineC.face(g, bdesc[i][3]);
+        };
+        pr.P.push_back(stamp(Pl, sdim, Nf / 2, curl ? fineC.nE : fineC.nF, fine_index));
+        el = next;
+    }
+    // Galerkin coarse matrices and coarse derivatives
+    for (int k = 1; k < nlevels; ++k) {
+        const Csr& P = pr.P[k - 1];
+        Csr AP = spgemm(pr.A[k - 1], P);
+        pr.A.push_back(spgemm(transpose(P), AP));
+        Cubes c(n >> k);
+        pr.D.push_back(curl ? c.grad() : c.curl());
+    }
+    return pr;
+}
+
+}  // namespace
+}  // namespace amge
+
+struct amge_problem {
+    amge::Problem p;
+    amge::Csr empty;
+};
+
+extern "C" amge_status amge_kuhn_build(int32_t kind, int32_t n, int32_t nlevels, const double* alpha_hex,
+                                       const double* beta_hex, amge_problem** out) {
+    try {
+        if (!out) amge::fail(AMGE_ERR_ARG, "null output pointer");
+        auto* pp = new amge_problem;
+        try {
+            pp->p = amge::build(kind, n, nlevels, alpha_hex, beta_hex);
+        } catch (...) {
+            delete pp;
+            throw;
+        }
+        pp->empty.nrows = 0;
+        pp->empty.ncols = 0;
+        *out = pp;
+        return AMGE_OK;
+    } catch (const amge::Error& e) {
+        amge::set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        amge::set_last_error("host allocation failed");
+        return AMGE_ERR_OOM;
+    } catch (const std::exception& e) {
+        amge::set_last_error(e.what());
+        return AMGE_ERR_ARG;
+    }
+}
+
+extern "C" int32_t amge_problem_nlevels(const amge_problem* p) { return p ? p->p.nlevels : 0; }
+
+extern "C" amge_status amge_problem_levels(const amge_problem* p, amge_level* levels) {
+    if (!p || !levels) {
+        amge::set_last_error("null argument");
+        return AMGE_ERR_ARG;
+    }
+    for (int k = 0; k < p->p.nlevels; ++k) {
+        levels[k].A = p->p.A[k].view();
+        levels[k].D = p->p.D[k].view();
+        levels[k].P = k + 1 < p->p.nlevels ? p->p.P[k].view() : p->empty.view();
+        if (k + 1 == p->p.nlevels) levels[k].P.ncols = 0;
+    }
+    return AMGE_OK;
+}
+
+extern "C" void amge_problem_free(amge_problem* p) { delete p; }

@@ -1,0 +1,781 @@
+// Set-up, V-cycle and PCG drivers, and the C ABI of the solve phase.
+//
+// Algorithm 4.1 (V-cycle) with the hybrid smoother of eq. (4.1) on every
+// non-coarsest level and an exact FP64 Cholesky solve on the coarsest one; inexact
+// PCG of section 5.1 around it.  The host only orchestrates launches; every vector
+// operation of the path runs in the kernels of kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <memory>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace amge {
+
+#define HIPCHECK(expr)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            fail(e_ == hipErrorOutOfMemory ? AMGE_ERR_OOM : AMGE_ERR_HIP,                     \
+                 std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+    } while (0)
+
+struct DCsr {
+    int nrows = 0, ncols = 0;
+    int64_t nnz = 0;
+    int* rp = nullptr;
+    int* ci = nullptr;
+    double* v64 = nullptr;
+    float* v32 = nullptr;
+    int lanes = 1;
+};
+
+struct DInc {
+    int nrows = 0, ncols = 0;
+    int64_t nnz = 0;
+    int* rp = nullptr;
+    uint32_t* ent = nullptr;
+    int lanes = 1;
+};
+
+template <class T>
+struct Work {
+    T *b = nullptr, *x = nullptr, *xt = nullptr, *r = nullptr, *g = nullptr, *y = nullptr, *yt = nullptr;
+    T* dinv = nullptr;
+    T* dhinv = nullptr;
+};
+
+// Event timing of the fine-level A kernels (the dominant kernel family of the V-cycle).
+struct Probe {
+    bool on = false;
+    std::vector<hipEvent_t> ev;   // start/stop pairs, reused across reads
+    size_t used = 0;              // pairs recorded since the last read
+    double bytes = 0;             // algorithmic bytes of the recorded launches
+    ~Probe() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+struct DLevel {
+    int n = 0, m = 0;
+    Probe* probe = nullptr;
+    DCsr A, Ah, P, Pt;
+    DInc D, Dt;
+    Work<float> w32;
+    Work<double> w64;
+    template <class T> Work<T>& w();
+};
+template <> Work<float>& DLevel::w<float>() { return w32; }
+template <> Work<double>& DLevel::w<double>() { return w64; }
+
+int lanes_for(int64_t nnz, int64_t rows) {
+    if (rows <= 0) return 1;
+    double avg = (double)nnz / (double)rows;
+    int l = (int)std::lround(std::log2(std::max(1.0, avg / 2.0)));
+    return 1 << std::min(6, std::max(0, l));
+}
+
+}  // namespace amge
+
+struct amge_hierarchy {
+    std::vector<amge::DLevel> lv;
+    amge_opts opts{};
+    int nc = 0;                  // coarsest size
+    double *W = nullptr, *WT = nullptr;
+    // outer PCG buffers (FP64, level-1 length)
+    double *r = nullptr, *p = nullptr, *q = nullptr, *z[2] = {nullptr, nullptr};
+    double *part_pq = nullptr, *part_dots[2] = {nullptr, nullptr};
+    amge::dev::PcgStatus* st = nullptr;
+    int* flags = nullptr;        // [0] done, [1] breakdown
+    std::vector<void*> allocs;
+    size_t bytes = 0;
+    amge::Probe probe;
+    ~amge_hierarchy() {
+        for (void* a : allocs) (void)hipFree(a);
+    }
+    template <class T>
+    T* alloc(size_t n) {
+        if (n == 0) n = 1;
+        void* ptr = nullptr;
+        hipError_t e = hipMalloc(&ptr, n * sizeof(T));
+        if (e != hipSuccess) amge::fail(AMGE_ERR_OOM, "hipMalloc failed");
+        allocs.push_back(ptr);
+        bytes += n * sizeof(T);
+        return (T*)ptr;
+    }
+};
+
+namespace amge {
+
+using dev::BLOCK;
+
+template <class T>
+T* upload(amge_hierarchy* H, const T* src, size_t n, hipStream_t s) {
+    T* d = H->alloc<T>(n);
+    if (n) HIPCHECK(hipMemcpyAsync(d, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+    return d;
+}
+
+DCsr upload_csr(amge_hierarchy* H, const Csr& A, hipStream_t s) {
+    DCsr d;
+    d.nrows = A.nrows;
+    d.ncols = A.ncols;
+    d.nnz = A.nnz();
+    d.rp = upload(H, A.rowptr.data(), A.rowptr.size(), s);
+    d.ci = upload(H, A.col.data(), A.col.size(), s);
+    d.v64 = upload(H, A.val.data(), A.val.size(), s);
+    std::vector<float> v32(A.val.begin(), A.val.end());   // round to nearest
+    d.v32 = upload(H, v32.data(), v32.size(), s);
+    HIPCHECK(hipStreamSynchronize(s));
+    d.lanes = lanes_for(d.nnz, d.nrows);
+    return d;
+}
+
+DInc upload_inc(amge_hierarchy* H, const Csr& A, hipStream_t s) {
+    DInc d;
+    d.nrows = A.nrows;
+    d.ncols = A.ncols;
+    d.nnz = A.nnz();
+    std::vector<uint32_t> ent(A.nnz());
+    for (int64_t k = 0; k < A.nnz(); ++k) {
+        if (A.val[k] != 1.0 && A.val[k] != -1.0) fail(AMGE_ERR_ARG, "derivative matrix entries must be +-1");
+        ent[k] = (uint32_t)A.col[k] | (A.val[k] < 0 ? 0x80000000u : 0u);
+    }
+    d.rp = upload(H, A.rowptr.data(), A.rowptr.size(), s);
+    d.ent = upload(H, ent.data(), ent.size(), s);
+    HIPCHECK(hipStreamSynchronize(s));
+    d.lanes = lanes_for(d.nnz, d.nrows);
+    return d;
+}
+
+// ------------------------------------------------------------------ launches
+inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + BLOCK - 1) / BLOCK); }
+
+template <class T> const T* vals(const DCsr& M);
+template <> const float* vals<float>(const DCsr& M) { return M.v32; }
+template <> const double* vals<double>(const DCsr& M) { return M.v64; }
+
+template <class T, int L>
+void csr_l(const DCsr& M, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s) {
+    unsigned g = grid_for((int64_t)M.nrows * L);
+    if (g == 0) return;
+    const T* v = vals<T>(M);
+    switch (mode) {
+        case dev::SPMV: dev::k_csr<T, L, dev::SPMV><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ci, v, x, b, dinv, y); break;
+        case dev::SPMV_ADD: dev::k_csr<T, L, dev::SPMV_ADD><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ci, v, x, b, dinv, y); break;
+        case dev::RESID: dev::k_csr<T, L, dev::RESID><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ci, v, x, b, dinv, y); break;
+        case dev::JAC: dev::k_csr<T, L, dev::JAC><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ci, v, x, b, dinv, y); break;
+        default: dev::k_csr<T, L, dev::JAC2Z><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ci, v, x, b, dinv, y); break;
+    }
+}
+
+template <class T>
+void csr(const DCsr& M, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s) {
+    switch (M.lanes) {
+        case 1: csr_l<T, 1>(M, mode, x, b, dinv, y, s); break;
+        case 2: csr_l<T, 2>(M, mode, x, b, dinv, y, s); break;
+        case 4: csr_l<T, 4>(M, mode, x, b, dinv, y, s); break;
+        case 8: csr_l<T, 8>(M, mode, x, b, dinv, y, s); break;
+        case 16: csr_l<T, 16>(M, mode, x, b, dinv, y, s); break;
+        case 32: csr_l<T, 32>(M, mode, x, b, dinv, y, s); break;
+        default: csr_l<T, 64>(M, mode, x, b, dinv, y, s); break;
+    }
+}
+
+// Launch of an A_k kernel; on a probed level the launch is bracketed by events and its
+// algorithmic bytes are counted: values + column indices, row pointers, and the vector
+// streams of the mode (x gathered once, b, dinv, y).
+template <class T>
+void acsr(DLevel& L, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s) {
+    Probe* pr = L.probe;
+    if (!pr || !pr->on) {
+        csr<T>(L.A, mode, x, b, dinv, y, s);
+        return;
+    }
+    if (pr->ev.size() < 2 * (pr->used + 1)) {
+        hipEvent_t a, c;
+        HIPCHECK(hipEventCreate(&a));
+        HIPCHECK(hipEventCreate(&c));
+        pr->ev.push_back(a);
+        pr->ev.push_back(c);
+    }
+    HIPCHECK(hipEventRecord(pr->ev[2 * pr->used], s));
+    csr<T>(L.A, mode, x, b, dinv, y, s);
+    HIPCHECK(hipEventRecord(pr->ev[2 * pr->used + 1], s));
+    pr->used++;
+    const double nv = mode == dev::JAC ? 4 : 3;   // JAC: x, b, dinv, y; others: three streams
+    pr->bytes += (double)L.A.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) + nv * sizeof(T) * L.n;
+}
+
+template <class T, int L>
+void inc_l(const DInc& M, int add, const T* x, T* y, hipStream_t s) {
+    unsigned g = grid_for((int64_t)M.nrows * L);
+    if (g == 0) return;
+    if (add) dev::k_inc<T, L, 1><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ent, x, y);
+    else dev::k_inc<T, L, 0><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ent, x, y);
+}
+
+template <class T>
+void inc(const DInc& M, int add, const T* x, T* y, hipStream_t s) {
+    switch (M.lanes) {
+        case 1: inc_l<T, 1>(M, add, x, y, s); break;
+        case 2: inc_l<T, 2>(M, add, x, y, s); break;
+        case 4: inc_l<T, 4>(M, add, x, y, s); break;
+        case 8: inc_l<T, 8>(M, add, x, y, s); break;
+        case 16: inc_l<T, 16>(M, add, x, y, s); break;
+        case 32: inc_l<T, 32>(M, add, x, y, s); break;
+        default: inc_l<T, 64>(M, add, x, y, s); break;
+    }
+}
+
+template <class T>
+void scale(int n, const T* dinv, const T* x, T* y, hipStream_t s) {
+    if (n) dev::k_scale<T><<<grid_for(n), BLOCK, 0, s>>>(n, dinv, x, y);
+}
+
+template <class T>
+void coarse_solve(amge_hierarchy* H, const T* b, T* x, hipStream_t s) {
+    int n = H->nc;
+    dev::k_coarse<T><<<1, 1024, 2 * n * sizeof(double), s>>>(n, H->W, H->WT, b, x);
+}
+
+template <class S, class D>
+void convert(int64_t n, const S* a, D* b, hipStream_t s) {
+    if (n) dev::k_convert<S, D><<<(unsigned)std::min<int64_t>(grid_for(n), 4096), BLOCK, 0, s>>>(n, a, b);
+}
+
+// ------------------------------------------------------------------ smoother and V-cycle
+// Primary l1-Jacobi sweeps on A: x <- x + dinv (b - A x), nu times.  With from_zero the
+// first two sweeps are fused (the first one from zero is x = dinv b).  x and xt are
+// swapped by the ping-pong; the caller tracks where the result is.
+template <class T>
+void primary(DLevel& L, const T* b, T*& x, T*& xt, bool from_zero, int nu, hipStream_t s) {
+    Work<T>& w = L.w<T>();
+    int k = 0;
+    if (from_zero) {
+        if (nu >= 2) {
+            acsr<T>(L, dev::JAC2Z, nullptr, b, w.dinv, x, s);
+            k = 2;
+        } else if (nu == 1) {
+            scale<T>(L.n, w.dinv, b, x, s);
+            k = 1;
+        } else {
+            HIPCHECK(hipMemsetAsync(x, 0, sizeof(T) * L.n, s));
+        }
+    }
+    for (; k < nu; ++k) {
+        acsr<T>(L, dev::JAC, x, b, w.dinv, xt, s);
+        std::swap(x, xt);
+    }
+}
+
+// Auxiliary correction of eq. (4.1): x <- x + D Mhat^{-1} D^T (b - A x), Mhat^{-1} being
+// nu l1-Jacobi sweeps on D^T A D from zero.
+template <class T>
+void auxiliary(DLevel& L, const T* b, T* x, int nu, hipStream_t s) {
+    if (nu <= 0 || L.m == 0) return;
+    Work<T>& w = L.w<T>();
+    acsr<T>(L, dev::RESID, x, b, nullptr, w.r, s);
+    inc<T>(L.Dt, 0, w.r, w.g, s);
+    T* y = w.y;
+    T* yt = w.yt;
+    int k;
+    if (nu >= 2) {
+        csr<T>(L.Ah, dev::JAC2Z, nullptr, w.g, w.dhinv, y, s);
+        k = 2;
+    } else {
+        scale<T>(L.m, w.dhinv, w.g, y, s);
+        k = 1;
+    }
+    for (; k < nu; ++k) {
+        csr<T>(L.Ah, dev::JAC, y, w.g, w.dhinv, yt, s);
+        std::swap(y, yt);
+    }
+    inc<T>(L.D, 1, y, x, s);
+}
+
+template <class T>
+void vcycle_level(amge_hierarchy* H, int l, const T* b, T* xout, hipStream_t s) {
+    const int nl = (int)H->lv.size();
+    if (l == nl - 1) {
+        coarse_solve<T>(H, b, xout, s);
+        return;
+    }
+    DLevel& L = H->lv[l];
+    DLevel& C = H->lv[l + 1];
+    Work<T>& w = L.w<T>();
+    Work<T>& wc = C.w<T>();
+    T* x = xout;
+    T* xt = w.xt;
+    const int nup = H->opts.nu_primary, nua = H->opts.nu_aux;
+    // pre-smoothing with Mbar (eq. (4.1)): primary, then auxiliary
+    primary<T>(L, b, x, xt, true, nup, s);
+    auxiliary<T>(L, b, x, nua, s);
+    // restriction of the residual, coarse correction, prolongation
+    acsr<T>(L, dev::RESID, x, b, nullptr, w.r, s);
+    csr<T>(L.Pt, dev::SPMV, w.r, nullptr, nullptr, wc.b, s);
+    vcycle_level<T>(H, l + 1, wc.b, wc.x, s);
+    csr<T>(L.P, dev::SPMV_ADD, wc.x, nullptr, nullptr, x, s);
+    // post-smoothing with Mbar^T: auxiliary first, then primary
+    auxiliary<T>(L, b, x, nua, s);
+    primary<T>(L, b, x, xt, false, nup, s);
+    if (x != xout) HIPCHECK(hipMemcpyAsync(xout, x, sizeof(T) * L.n, hipMemcpyDeviceToDevice, s));
+}
+
+// z = B r on level-1 vectors in FP64; the FP32 path rounds r, runs the V-cycle in FP32
+// and widens the result.
+void precondition(amge_hierarchy* H, const double* r, double* z, hipStream_t s) {
+    DLevel& L = H->lv[0];
+    if (H->opts.precond_bits == 32) {
+        convert<double, float>(L.n, r, L.w32.b, s);
+        vcycle_level<float>(H, 0, L.w32.b, L.w32.x, s);
+        convert<float, double>(L.n, L.w32.x, z, s);
+    } else {
+        vcycle_level<double>(H, 0, r, z, s);
+    }
+}
+
+// ------------------------------------------------------------------ set-up
+void build_coarse(amge_hierarchy* H, const Csr& A, hipStream_t s) {
+    int n = A.nrows;
+    if (n > 8192) fail(AMGE_ERR_ARG, "coarsest level larger than 8192 rows");
+    std::vector<double> L((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) L[(size_t)i * n + A.col[k]] = A.val[k];
+    double amax = 0;
+    for (double v : L) amax = std::max(amax, std::fabs(v));
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j)
+            if (std::fabs(L[(size_t)i * n + j] - L[(size_t)j * n + i]) > 1e-12 * amax)
+                fail(AMGE_ERR_NOT_SPD, "coarsest matrix is not symmetric");
+    // Cholesky A = L L^T (lower, in place)
+    for (int j = 0; j < n; ++j) {
+        double d = L[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+        if (!(d > 0)) fail(AMGE_ERR_NOT_SPD, "coarsest matrix is not positive definite");
+        d = std::sqrt(d);
+        L[(size_t)j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double v = L[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) v -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+            L[(size_t)i * n + j] = v / d;
+        }
+    }
+    // W = L^{-1} (lower triangular), by forward substitution on the identity
+    std::vector<double> W((size_t)n * n, 0.0), WT((size_t)n * n, 0.0);
+    for (int c = 0; c < n; ++c)
+        for (int i = c; i < n; ++i) {
+            double v = (i == c) ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) v -= L[(size_t)i * n + k] * W[(size_t)k * n + c];
+            W[(size_t)i * n + c] = v / L[(size_t)i * n + i];
+        }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) WT[(size_t)j * n + i] = W[(size_t)i * n + j];
+    H->nc = n;
+    H->W = upload(H, W.data(), W.size(), s);
+    H->WT = upload(H, WT.data(), WT.size(), s);
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+template <class T>
+void alloc_work(amge_hierarchy* H, DLevel& L, Work<T>& w, const std::vector<double>& dinv,
+                const std::vector<double>& dhinv, hipStream_t s) {
+    size_t nr = (size_t)L.n * H->opts.max_rhs, mr = (size_t)L.m * H->opts.max_rhs;
+    w.b = H->alloc<T>(nr);
+    w.x = H->alloc<T>(nr);
+    w.xt = H->alloc<T>(nr);
+    w.r = H->alloc<T>(nr);
+    w.g = H->alloc<T>(mr);
+    w.y = H->alloc<T>(mr);
+    w.yt = H->alloc<T>(mr);
+    std::vector<T> a(dinv.begin(), dinv.end()), c(dhinv.begin(), dhinv.end());
+    w.dinv = upload(H, a.data(), a.size(), s);
+    w.dhinv = upload(H, c.data(), c.size(), s);
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
+    if (!levels || nl < 1) fail(AMGE_ERR_ARG, "need at least one level");
+    std::vector<Csr> A(nl), D(nl), P(nl);
+    for (int k = 0; k < nl; ++k) {
+        A[k] = csr_from_view(levels[k].A);
+        if (A[k].nrows != A[k].ncols || A[k].nrows == 0) fail(AMGE_ERR_SHAPE, "A_k must be square and non-empty");
+        if (k > 0 && A[k].nrows != P[k - 1].ncols) fail(AMGE_ERR_SHAPE, "P_{k-1} columns != rows of A_k");
+        if (k < nl - 1) {
+            D[k] = csr_from_view(levels[k].D);
+            if (D[k].nrows != A[k].nrows) fail(AMGE_ERR_SHAPE, "D_k rows != rows of A_k");
+            P[k] = csr_from_view(levels[k].P);
+            if (P[k].nrows != A[k].nrows) fail(AMGE_ERR_SHAPE, "P_k rows != rows of A_k");
+        }
+    }
+    H->lv.resize(nl);
+    for (int k = 0; k < nl; ++k) {
+        DLevel& L = H->lv[k];
+        L.n = A[k].nrows;
+        if (k == nl - 1) {
+            build_coarse(H, A[k], s);
+            std::vector<double> none;
+            alloc_work<float>(H, L, L.w32, none, none, s);
+            alloc_work<double>(H, L, L.w64, none, none, s);
+            continue;
+        }
+        L.m = D[k].ncols;
+        Csr Dt = transpose(D[k]);
+        Csr Ah = spgemm(Dt, spgemm(A[k], D[k]));   // auxiliary matrix D^T A D (eq. (4.1))
+        std::vector<double> d = l1_row_sums(A[k]), dh = l1_row_sums(Ah);
+        std::vector<double> dinv(d.size()), dhinv(dh.size());
+        for (size_t i = 0; i < d.size(); ++i) {
+            if (!(d[i] > 0)) fail(AMGE_ERR_NOT_SPD, "zero row in A_k");
+            dinv[i] = 1.0 / d[i];
+        }
+        for (size_t i = 0; i < dh.size(); ++i) dhinv[i] = dh[i] > 0 ? 1.0 / dh[i] : 0.0;
+        L.A = upload_csr(H, A[k], s);
+        L.Ah = upload_csr(H, Ah, s);
+        L.P = upload_csr(H, P[k], s);
+        L.Pt = upload_csr(H, transpose(P[k]), s);
+        L.D = upload_inc(H, D[k], s);
+        L.Dt = upload_inc(H, Dt, s);
+        alloc_work<float>(H, L, L.w32, dinv, dhinv, s);
+        alloc_work<double>(H, L, L.w64, dinv, dhinv, s);
+    }
+    if (nl == 1) {
+        // the fine matrix itself is needed by the outer PCG even on one level
+        H->lv[0].A = upload_csr(H, A[0], s);
+    }
+    size_t n1 = (size_t)H->lv[0].n * H->opts.max_rhs;
+    H->r = H->alloc<double>(n1);
+    H->p = H->alloc<double>(n1);
+    H->q = H->alloc<double>(n1);
+    H->z[0] = H->alloc<double>(n1);
+    H->z[1] = H->alloc<double>(n1);
+    H->part_pq = H->alloc<double>(dev::NRED);
+    H->part_dots[0] = H->alloc<double>(3 * dev::NRED);
+    H->part_dots[1] = H->alloc<double>(3 * dev::NRED);
+    H->st = H->alloc<dev::PcgStatus>(1);
+    H->flags = H->alloc<int>(2);
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------ PCG
+template <int L>
+void pcg_ap(amge_hierarchy* H, hipStream_t s) {
+    const DCsr& A = H->lv[0].A;
+    dev::k_pcg_ap<L><<<dev::NRED, BLOCK, 0, s>>>(A.nrows, A.rp, A.ci, A.v64, H->p, H->q, H->part_pq, H->flags);
+}
+
+void launch_pcg_ap(amge_hierarchy* H, hipStream_t s) {
+    switch (H->lv[0].A.lanes) {
+        case 1: pcg_ap<1>(H, s); break;
+        case 2: pcg_ap<2>(H, s); break;
+        case 4: pcg_ap<4>(H, s); break;
+        case 8: pcg_ap<8>(H, s); break;
+        case 16: pcg_ap<16>(H, s); break;
+        case 32: pcg_ap<32>(H, s); break;
+        default: pcg_ap<64>(H, s); break;
+    }
+}
+
+amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int maxit, int stop_l2,
+                int* iters, double* relres, hipStream_t s) {
+    const int n = H->lv[0].n;
+    const bool f32 = H->opts.precond_bits == 32;
+    const bool multilevel = H->lv.size() > 1;
+    float* r32 = f32 && multilevel ? H->lv[0].w32.b : nullptr;
+    float* z32 = f32 && multilevel ? H->lv[0].w32.x : nullptr;
+    auto precond_into = [&](double* z) {
+        if (!multilevel) {
+            coarse_solve<double>(H, H->r, z, s);
+        } else if (f32) {
+            vcycle_level<float>(H, 0, r32, z32, s);
+        } else {
+            vcycle_level<double>(H, 0, H->r, z, s);
+        }
+    };
+    HIPCHECK(hipMemcpyAsync(H->r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHECK(hipMemsetAsync(x, 0, sizeof(double) * n, s));
+    HIPCHECK(hipMemsetAsync(H->flags, 0, 2 * sizeof(int), s));
+    if (r32) convert<double, float>(n, H->r, r32, s);
+    // z_0 = B r_0, delta_0 = r_0 . z_0
+    precond_into(H->z[1]);
+    dev::k_pcg_dots<<<dev::NRED, BLOCK, 0, s>>>(n, z32, H->z[1], nullptr, H->r, H->part_dots[1], H->flags);
+    dev::k_pcg_init<<<1, BLOCK, 0, s>>>(H->part_dots[1], H->st);
+    dev::PcgStatus hs;
+    HIPCHECK(hipMemcpyAsync(&hs, H->st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (!std::isfinite(hs.bnorm) || !std::isfinite(hs.delta0)) fail(AMGE_ERR_NONFINITE, "non-finite right-hand side");
+    if (hs.bnorm == 0) {
+        *iters = 0;
+        *relres = 0;
+        return AMGE_OK;
+    }
+    if (!(hs.delta0 > 0)) fail(AMGE_ERR_BREAKDOWN, "preconditioner not positive on the right-hand side");
+    HIPCHECK(hipMemcpyAsync(H->p, H->z[1], sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    int it = 0;
+    for (; it < maxit; ++it) {
+        double* znew = H->z[it & 1];
+        double* zold = H->z[(it + 1) & 1];
+        double* dnew = H->part_dots[it & 1];
+        double* dold = H->part_dots[(it + 1) & 1];
+        launch_pcg_ap(H, s);
+        dev::k_pcg_xr<<<dev::NRED, BLOCK, 0, s>>>(n, H->part_pq, dold, H->p, H->q, x, H->r, r32, H->flags,
+                                                  H->flags + 1);
+        precond_into(znew);
+        dev::k_pcg_dots<<<dev::NRED, BLOCK, 0, s>>>(n, z32, znew, zold, H->r, dnew, H->flags);
+        dev::k_pcg_p<<<dev::NRED, BLOCK, 0, s>>>(n, dnew, dold, znew, H->p, H->st, H->flags, H->flags + 1, rtol,
+                                                 stop_l2, maxit, it);
+        dev::k_pcg_finish<<<1, 1, 0, s>>>(H->st, H->flags, rtol, maxit);
+        HIPCHECK(hipMemcpyAsync(&hs, H->st, sizeof(hs), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        if (hs.breakdown) break;
+        if ((rtol > 0 && hs.relres <= rtol) || !std::isfinite(hs.delta)) break;
+    }
+    HIPCHECK(hipGetLastError());
+    *iters = hs.iters;
+    *relres = hs.relres;
+    if (hs.breakdown) fail(AMGE_ERR_BREAKDOWN, "PCG breakdown (p.q <= 0)");
+    if (!std::isfinite(hs.delta)) fail(AMGE_ERR_NONFINITE, "non-finite PCG iterate");
+    if (rtol > 0 && !(hs.relres <= rtol)) return AMGE_NOT_CONVERGED;
+    return AMGE_OK;
+}
+
+template <class F>
+amge_status guard(F&& f) {
+    try {
+        return f();
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return AMGE_ERR_OOM;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return AMGE_ERR_ARG;
+    }
+}
+
+}  // namespace amge
+
+using namespace amge;
+
+extern "C" void amge_default_opts(amge_opts* o) {
+    if (!o) return;
+    o->nu_primary = 2;
+    o->nu_aux = 2;
+    o->precond_bits = 32;
+    o->max_rhs = 1;
+}
+
+extern "C" amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nlevels, const amge_opts* opts,
+                                            void* stream, amge_hierarchy** out) {
+    return guard([&]() -> amge_status {
+        if (!out) fail(AMGE_ERR_ARG, "null output pointer");
+        *out = nullptr;
+        auto H = std::make_unique<amge_hierarchy>();
+        if (opts) H->opts = *opts;
+        else amge_default_opts(&H->opts);
+        if (H->opts.nu_primary < 0 || H->opts.nu_aux < 0 || H->opts.max_rhs < 1 ||
+            (H->opts.precond_bits != 32 && H->opts.precond_bits != 64))
+            fail(AMGE_ERR_ARG, "invalid options");
+        setup(H.get(), levels, nlevels, (hipStream_t)stream);
+        *out = H.release();
+        return AMGE_OK;
+    });
+}
+
+extern "C" void amge_destroy(amge_hierarchy* h) { delete h; }
+
+extern "C" amge_status amge_footprint(const amge_hierarchy* h, size_t* bytes) {
+    if (!h || !bytes) {
+        set_last_error("null argument");
+        return AMGE_ERR_ARG;
+    }
+    *bytes = h->bytes;
+    return AMGE_OK;
+}
+
+extern "C" amge_status amge_hierarchy_info(const amge_hierarchy* h, int32_t* nlevels, int32_t* rows) {
+    if (!h || !nlevels) {
+        set_last_error("null argument");
+        return AMGE_ERR_ARG;
+    }
+    *nlevels = (int32_t)h->lv.size();
+    if (rows)
+        for (size_t k = 0; k < h->lv.size(); ++k) rows[k] = h->lv[k].n;
+    return AMGE_OK;
+}
+
+extern "C" amge_status amge_vcycle(amge_hierarchy* h, const double* r, double* z, int32_t nrhs, void* stream) {
+    return guard([&]() -> amge_status {
+        if (!h || !r || !z) fail(AMGE_ERR_ARG, "null argument");
+        if (nrhs != 1) fail(AMGE_ERR_ARG, "amge_vcycle: nrhs must be 1");
+        hipStream_t s = (hipStream_t)stream;
+        if (h->lv.size() == 1) coarse_solve<double>(h, r, z, s);
+        else precondition(h, r, z, s);
+        HIPCHECK(hipGetLastError());
+        return AMGE_OK;
+    });
+}
+
+extern "C" amge_status amge_pcg_solve(amge_hierarchy* h, const double* b, double* x, int32_t nrhs, double rtol,
+                                      int32_t maxit, int32_t stop_norm, int32_t* iters, double* relres,
+                                      void* stream) {
+    return guard([&]() -> amge_status {
+        if (!h || !b || !x || !iters || !relres) fail(AMGE_ERR_ARG, "null argument");
+        if (nrhs != 1) fail(AMGE_ERR_ARG, "amge_pcg_solve: nrhs must be 1");
+        if (maxit < 1) fail(AMGE_ERR_ARG, "maxit must be >= 1");
+        int it = 0;
+        double rr = 0;
+        amge_status st = pcg(h, b, x, rtol, maxit, stop_norm, &it, &rr, (hipStream_t)stream);
+        iters[0] = it;
+        relres[0] = rr;
+        return st;
+    });
+}
+
+extern "C" amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_t op, int32_t precision,
+                                        const double* in, const double* in2, double* out, void* stream) {
+    return guard([&]() -> amge_status {
+        if (!h || !in || !out) fail(AMGE_ERR_ARG, "null argument");
+        const int nl = (int)h->lv.size();
+        if (level < 0 || level >= nl) fail(AMGE_ERR_ARG, "level out of range");
+        if (precision != 32 && precision != 64) fail(AMGE_ERR_ARG, "precision must be 32 or 64");
+        hipStream_t s = (hipStream_t)stream;
+        DLevel& L = h->lv[level];
+        const bool last = level == nl - 1;
+        if (op == AMGE_OP_COARSE) {
+            if (!last) fail(AMGE_ERR_ARG, "coarse solve only on the coarsest level");
+            coarse_solve<double>(h, in, out, s);
+            HIPCHECK(hipGetLastError());
+            return AMGE_OK;
+        }
+        if (last) fail(AMGE_ERR_ARG, "operator not stored on the coarsest level");
+        if ((op == AMGE_OP_SMOOTH || op == AMGE_OP_SMOOTHT) && !in2) fail(AMGE_ERR_ARG, "smoother needs x");
+        // in / out lengths
+        int nin = L.n, nout = L.n;
+        switch (op) {
+            case AMGE_OP_A: break;
+            case AMGE_OP_AHAT: nin = nout = L.m; break;
+            case AMGE_OP_D: nin = L.m; break;
+            case AMGE_OP_DT: nout = L.m; break;
+            case AMGE_OP_P: nin = h->lv[level + 1].n; break;
+            case AMGE_OP_PT: nout = h->lv[level + 1].n; break;
+            case AMGE_OP_SMOOTH: case AMGE_OP_SMOOTHT: break;
+            default: fail(AMGE_ERR_ARG, "unknown op");
+        }
+        auto run = [&](auto tag, const auto* vin, const auto* vin2, auto* vout) {
+            using T = decltype(tag);
+            switch (op) {
+                case AMGE_OP_A: csr<T>(L.A, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
+                case AMGE_OP_AHAT: csr<T>(L.Ah, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
+                case AMGE_OP_D: inc<T>(L.D, 0, vin, vout, s); break;
+                case AMGE_OP_DT: inc<T>(L.Dt, 0, vin, vout, s); break;
+                case AMGE_OP_P: csr<T>(L.P, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
+                case AMGE_OP_PT: csr<T>(L.Pt, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
+                default: {
+                    Work<T>& w = L.w<T>();
+                    // x lives in w.x (copied in), result copied out
+                    HIPCHECK(hipMemcpyAsync(w.x, vin2, sizeof(T) * L.n, hipMemcpyDeviceToDevice, s));
+                    T* x = w.x;
+                    T* xt = w.xt;
+                    if (op == AMGE_OP_SMOOTH) {
+                        primary<T>(L, vin, x, xt, false, h->opts.nu_primary, s);
+                        auxiliary<T>(L, vin, x, h->opts.nu_aux, s);
+                    } else {
+                        auxiliary<T>(L, vin, x, h->opts.nu_aux, s);
+                        primary<T>(L, vin, x, xt, false, h->opts.nu_primary, s);
+                    }
+                    HIPCHECK(hipMemcpyAsync(vout, x, sizeof(T) * L.n, hipMemcpyDeviceToDevice, s));
+                }
+            }
+        };
+        if (precision == 64) {
+            run(double{}, in, in2, out);
+        } else {
+            // FP32 kernels on rounded copies held in temporary buffers
+            size_t nmax = (size_t)std::max(std::max(nin, nout), L.n);
+            float *fin = nullptr, *fin2 = nullptr, *fout = nullptr;
+            HIPCHECK(hipMalloc(&fin, nmax * sizeof(float)));
+            HIPCHECK(hipMalloc(&fin2, nmax * sizeof(float)));
+            HIPCHECK(hipMalloc(&fout, nmax * sizeof(float)));
+            convert<double, float>(nin, in, fin, s);
+            if (in2) convert<double, float>(L.n, in2, fin2, s);
+            run(float{}, (const float*)fin, (const float*)fin2, fout);
+            convert<float, double>(nout, fout, out, s);
+            HIPCHECK(hipStreamSynchronize(s));
+            (void)hipFree(fin);
+            (void)hipFree(fin2);
+            (void)hipFree(fout);
+        }
+        HIPCHECK(hipGetLastError());
+        return AMGE_OK;
+    });
+}
+
+extern "C" amge_status amge_timing_enable(amge_hierarchy* h, int32_t enable) {
+    return guard([&]() -> amge_status {
+        if (!h) fail(AMGE_ERR_ARG, "null argument");
+        h->probe.on = enable != 0;
+        h->probe.used = 0;
+        h->probe.bytes = 0;
+        h->lv[0].probe = h->lv.size() > 1 ? &h->probe : nullptr;
+        return AMGE_OK;
+    });
+}
+
+extern "C" amge_status amge_timing_read(amge_hierarchy* h, double* ms, int64_t* launches, double* bytes) {
+    return guard([&]() -> amge_status {
+        if (!h || !ms || !launches || !bytes) fail(AMGE_ERR_ARG, "null argument");
+        double tot = 0;
+        for (size_t i = 0; i < h->probe.used; ++i) {
+            HIPCHECK(hipEventSynchronize(h->probe.ev[2 * i + 1]));
+            float t = 0;
+            HIPCHECK(hipEventElapsedTime(&t, h->probe.ev[2 * i], h->probe.ev[2 * i + 1]));
+            tot += t;
+        }
+        *ms = tot;
+        *launches = (int64_t)h->probe.used;
+        *bytes = h->probe.bytes;
+        h->probe.used = 0;
+        h->probe.bytes = 0;
+        return AMGE_OK;
+    });
+}
+
+extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precision, double* bytes) {
+    return guard([&]() -> amge_status {
+        if (!h || !bytes) fail(AMGE_ERR_ARG, "null argument");
+        if (precision != 32 && precision != 64) fail(AMGE_ERR_ARG, "precision must be 32 or 64");
+        const double sv = precision == 32 ? 4.0 : 8.0;   // value / vector entry size
+        const int nup = h->opts.nu_primary, nua = h->opts.nu_aux;
+        double tot = 0;
+        const size_t nl = h->lv.size();
+        for (size_t k = 0; k + 1 < nl; ++k) {
+            const DLevel& L = h->lv[k];
+            const double n = L.n, m = L.m, nc = h->lv[k + 1].n;
+            auto mat = [&](const DCsr& M) { return (double)M.nnz * (sv + 4.0) + 4.0 * (M.nrows + 1); };
+            auto incb = [&](const DInc& M) { return (double)M.nnz * 4.0 + 4.0 * (M.nrows + 1); };
+            // primary sweeps: first two fused from zero (b, dinv, y), then x, b, dinv, y
+            const int sweeps = 2 * nup;
+            int fused = nup >= 2 ? 1 : 0;
+            tot += fused * (mat(L.A) + 3 * sv * n) + (sweeps - 2 * fused) * (mat(L.A) + 4 * sv * n);
+            // auxiliary step, pre and post: residual, D^T, aux sweeps, D add
+            if (nua > 0) {
+                double aux = mat(L.A) + 3 * sv * n + incb(L.Dt) + sv * (n + m);
+                aux += (nua >= 2 ? (mat(L.Ah) + 3 * sv * m) : 2 * sv * m);
+                aux += std::max(0, nua - 2) * (mat(L.Ah) + 4 * sv * m);
+                aux += incb(L.D) + sv * (m + 2 * n);
+                tot += 2 * aux;
+            }
+            // restriction residual, P^T, P add
+            tot += mat(L.A) + 3 * sv * n;
+            tot += mat(L.Pt) + sv * (n + nc);
+            tot += mat(L.P) + sv * (nc + 2 * n);
+        }
+        tot += 8.0 * (double)h->nc * h->nc;   // coarsest: both triangles of the inverse factor
+        *bytes = tot;
+        return AMGE_OK;
+    });
+}

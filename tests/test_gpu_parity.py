@@ -1,0 +1,220 @@
+"""GPU parity of the HIP solve path against the FP64 oracle, through the C ABI.
+
+The GPU side runs on hierarchies made by the library's own builder; the oracle
+side on hierarchies made by the oracle; the two builders agree to rounding
+(tests/test_library_cpu.py), so the whole path is compared end to end.
+
+Tolerances
+----------
+* FP64 kernels and the FP64 V-cycle: 1e-12 relative (max norm) -- reordered sums
+  of O(30) terms, accumulated over up to 5 levels.
+* FP32 kernels: |y - y_ref| <= 1e-5 (|A| |x|)_i per entry (FP32 unit roundoff 6e-8
+  times row length and a margin).
+* PCG, FP64: after the same number of iterations, relative solution error
+  <= 1e-10; iteration counts at rtol 1e-8 within +-1.
+* PCG with the FP32 preconditioner: converges to rtol 1e-8; its distance to the
+  FP64 oracle solution is reported and bounded by 1e-6 relative.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from paper_2107_05613_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _amge():
+    from paper_2107_05613_amd import amge
+    return amge
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+class Case:
+    def __init__(self, kind, n, L, coef, precond_bits=64):
+        from oracle.hierarchy import build_hierarchy
+        from oracle.solve import Multilevel
+        amge = _amge()
+        print(f"\n[case] {kind} n={n} levels={L} coef={coef} bits={precond_bits}", flush=True)
+        w = W.Workload("t", kind, n, L, coef)
+        self.alpha, self.beta = W.coefficients(w)
+        self.kind, self.n, self.L = kind, n, L
+        self.prod = amge.build_problem(kind, n, L, self.alpha, self.beta)
+        self.H = build_hierarchy(kind, n, L, self.alpha, self.beta, check_targets=False)
+        self.ml = Multilevel.from_hierarchy(self.H)
+        self.gpu = {bits: amge.Hierarchy(self.prod, precond_bits=bits) for bits in (64, 32)}
+        self.n1 = self.H.A[0].shape[0]
+        self.b = W.rhs(self.n1, 0)[:, 0]
+
+
+_CASES = {}
+
+
+def case(kind, n, L, coef):
+    key = (kind, n, L, coef)
+    if key not in _CASES:
+        _CASES[key] = Case(kind, n, L, coef)
+    return _CASES[key]
+
+
+SMALL = [("curl", 8, 3, "blocks"), ("div", 8, 3, "blocks"), ("curl", 12, 3, "unit")]
+
+
+@pytest.mark.parametrize("spec", SMALL)
+def test_level_operators(spec):
+    """a1, a3, a4, a5: CSR SpMV on A_k and D^T A D, incidences D / D^T, transfers P / P^T."""
+    amge = _amge()
+    c = case(*spec)
+    rng = np.random.default_rng(7)
+    for k in range(c.L - 1):
+        lv = c.ml.levels[k]
+        ops = {amge.OP_A: lv.A, amge.OP_AHAT: lv.Ahat, amge.OP_D: lv.D, amge.OP_DT: lv.D.T.tocsr(),
+               amge.OP_P: lv.P, amge.OP_PT: lv.P.T.tocsr()}
+        for op, M in ops.items():
+            x = rng.uniform(-1, 1, M.shape[1])
+            ref = M @ x
+            out = torch.empty(M.shape[0], dtype=torch.float64, device="cuda")
+            c.gpu[64].level_apply(k, op, dev(x), out, precision=64)
+            assert relerr(host(out), ref) <= 1e-12, (k, op)
+            c.gpu[64].level_apply(k, op, dev(x), out, precision=32)
+            bound = 1e-5 * (abs(M) @ np.abs(x)) + 1e-30
+            assert np.all(np.abs(host(out) - ref) <= bound), (k, op)
+
+
+@pytest.mark.parametrize("spec", SMALL)
+def test_hybrid_smoother(spec):
+    """a2 + a3 + a4: one application of Mbar and of Mbar^T (eq. (4.1)) against the oracle."""
+    amge = _amge()
+    c = case(*spec)
+    rng = np.random.default_rng(8)
+    for k in range(c.L - 1):
+        lv = c.ml.levels[k]
+        b = rng.uniform(-1, 1, lv.A.shape[0])
+        x0 = rng.uniform(-1, 1, lv.A.shape[0])
+        for op, fn in ((amge.OP_SMOOTH, c.ml.smooth), (amge.OP_SMOOTHT, c.ml.smooth_transpose)):
+            ref = fn(lv, b, x0)
+            out = torch.empty_like(dev(b))
+            c.gpu[64].level_apply(k, op, dev(b), out, x2=dev(x0), precision=64)
+            assert relerr(host(out), ref) <= 1e-12, (k, op)
+            c.gpu[64].level_apply(k, op, dev(b), out, x2=dev(x0), precision=32)
+            assert relerr(host(out), ref) <= 1e-4, (k, op)
+
+
+@pytest.mark.parametrize("spec", SMALL)
+def test_coarse_cholesky(spec):
+    """a6: the dense FP64 Cholesky apply on the coarsest level."""
+    amge = _amge()
+    c = case(*spec)
+    Ac = c.H.A[-1].toarray()
+    b = np.random.default_rng(9).uniform(-1, 1, Ac.shape[0])
+    ref = sla.solve(Ac, b, assume_a="pos")
+    out = torch.empty_like(dev(b))
+    c.gpu[64].level_apply(c.L - 1, amge.OP_COARSE, dev(b), out)
+    assert relerr(host(out), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("spec", SMALL + [("div", 32, 4, "blocks")])
+def test_vcycle(spec):
+    """Algorithm 4.1 with x0 = 0 in FP64 (parity) and FP32 (error stated)."""
+    c = case(*spec)
+    ref = c.ml.vcycle(c.b)
+    z = torch.empty_like(dev(c.b))
+    c.gpu[64].vcycle(dev(c.b), z)
+    assert relerr(host(z), ref) <= 1e-12
+    c.gpu[32].vcycle(dev(c.b), z)
+    e32 = relerr(host(z), ref)
+    print(f"FP32 V-cycle relative error vs FP64 oracle: {e32:.2e}")
+    assert e32 <= 1e-3
+
+
+@pytest.mark.parametrize("spec", [("curl", 8, 2, "unit"), ("div", 8, 3, "blocks"), ("div", 32, 4, "blocks")])
+def test_pcg_fp64_parity(spec):
+    """a7: inexact PCG in FP64; same iterates as the oracle after the same count, and
+    the same iteration count (+-1) at rtol 1e-8."""
+    from oracle.solve import pcg
+    c = case(*spec)
+    xo, ito, hist = pcg(c.H.A[0], c.b, c.ml, rtol=1e-8)
+    x = torch.zeros_like(dev(c.b))
+    status, it, rr = c.gpu[64].pcg(dev(c.b), x, rtol=1e-8, maxit=500)
+    assert status == 0 and abs(it[0] - ito) <= 1, (it, ito)
+    # fixed iteration count: rtol <= 0 runs exactly maxit iterations
+    status, it2, _ = c.gpu[64].pcg(dev(c.b), x, rtol=0.0, maxit=ito)
+    assert it2[0] == ito
+    err = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
+    print(f"{spec}: oracle iters {ito}, gpu iters {it[0]}, fixed-count solution error {err:.2e}")
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("spec", [("curl", 8, 3, "blocks"), ("div", 32, 4, "blocks")])
+def test_pcg_fp32_preconditioner(spec):
+    """FP32 V-cycle inside FP64 PCG reaches rtol 1e-8; error vs the FP64 oracle stated."""
+    from oracle.solve import pcg
+    c = case(*spec)
+    xo, ito, _ = pcg(c.H.A[0], c.b, c.ml, rtol=1e-8)
+    x = torch.zeros_like(dev(c.b))
+    status, it, rr = c.gpu[32].pcg(dev(c.b), x, rtol=1e-8, maxit=500)
+    xs = host(x)
+    assert status == 0 and rr[0] <= 1e-8
+    true_res = np.linalg.norm(c.b - c.H.A[0] @ xs) / np.linalg.norm(c.b)
+    err = np.linalg.norm(xs - xo) / np.linalg.norm(xo)
+    print(f"{spec}: FP32-precond iters {it[0]} (FP64 oracle {ito}); l2 residual {true_res:.2e}; "
+          f"error vs oracle {err:.2e}")
+    assert err <= 1e-6
+    assert it[0] <= ito + 3
+
+
+def test_pcg_dense_direct_cfg1():
+    """Configuration 1 solved to 1e-14 equals a dense direct solve."""
+    c = case("curl", 8, 2, "unit")
+    xd = sla.solve(c.H.A[0].toarray(), c.b, assume_a="pos")
+    x = torch.zeros_like(dev(c.b))
+    c.gpu[64].pcg(dev(c.b), x, rtol=1e-14, maxit=300)
+    assert np.linalg.norm(host(x) - xd) <= 1e-10 * np.linalg.norm(xd)
+
+
+def test_error_paths():
+    amge = _amge()
+    c = case("div", 8, 3, "blocks")
+    x = torch.zeros_like(dev(c.b))
+    bad = c.b.copy()
+    bad[5] = np.nan
+    with pytest.raises(amge.AmgeError) as e:
+        c.gpu[64].pcg(dev(bad), x)
+    assert e.value.code == -7
+    status, it, rr = c.gpu[64].pcg(dev(c.b), x, rtol=1e-8, maxit=1)
+    assert status == 1 and it[0] == 1
+    status, it, rr = c.gpu[64].pcg(dev(np.zeros_like(c.b)), x, rtol=1e-8)
+    assert status == 0 and it[0] == 0 and not torch.any(x != 0)
+    with pytest.raises(amge.AmgeError):
+        c.gpu[64].vcycle(dev(c.b), x, nrhs=2)
+    # an indefinite coarsest matrix is rejected at set-up
+    A, D, P = c.prod[-1]
+    Aneg = amge.HostCsr(A.shape[0], A.shape[1], A.rowptr, A.col, -A.val)
+    with pytest.raises(amge.AmgeError) as e:
+        amge.Hierarchy(c.prod[:-1] + [(Aneg, D, None)])
+    assert e.value.code == -3
+
+
+def test_deterministic():
+    """No atomics on the path: two solves are bitwise identical."""
+    c = case("curl", 12, 3, "unit")
+    xs = []
+    for _ in range(2):
+        x = torch.zeros_like(dev(c.b))
+        c.gpu[32].pcg(dev(c.b), x, rtol=1e-8)
+        xs.append(host(x))
+    assert np.array_equal(xs[0], xs[1])

@@ -1,0 +1,71 @@
+"""Host-side checks of the native library (no GPU needed).
+
+* libamge.so loads and exports every function include/amge.h declares;
+* the library's own hierarchy builder (C++, independent of the oracle) reproduces the
+  oracle's fine matrices, derivatives, prolongators and Galerkin coarse matrices.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2107_05613_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _amge():
+    from paper_2107_05613_amd import amge
+    return amge
+
+
+def test_exports_match_header():
+    amge = _amge()
+    hdr = open(os.path.join(ROOT, "include", "amge.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    declared = set(re.findall(r"\b(amge_[a-z_0-9]+)\s*\(", hdr))
+    assert declared, "no declarations parsed"
+    lib = amge.lib()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(amge.EXPORTS)
+
+
+@pytest.mark.parametrize("kind,n,L,coef", [("curl", 4, 3, "unit"), ("div", 4, 3, "blocks"),
+                                          ("curl", 8, 3, "blocks"), ("div", 8, 2, "unit"),
+                                          ("curl", 12, 3, "unit"), ("div", 16, 4, "blocks")])
+def test_builder_matches_oracle(kind, n, L, coef):
+    from oracle.hierarchy import build_hierarchy
+    amge = _amge()
+    w = W.Workload("t", kind, n, L, coef)
+    a, b = W.coefficients(w)
+    prod = amge.build_problem(kind, n, L, a, b)
+    H = build_hierarchy(kind, n, L, a, b, check_targets=False)
+    for k in range(L):
+        A, D, P = (None if M is None else M.to_scipy() for M in prod[k])
+        assert A.shape == H.A[k].shape
+        assert abs(A - H.A[k]).max() <= 1e-13 * abs(H.A[k]).max()
+        assert abs(D - H.D[k]).max() == 0
+        if k < L - 1:
+            assert abs(P - H.P[k]).max() <= 1e-13 * abs(H.P[k]).max()
+
+
+def test_builder_rejects_bad_arguments():
+    amge = _amge()
+    one = np.ones(27)
+    with pytest.raises(amge.AmgeError):
+        amge.build_problem("curl", 3, 2, one, one)          # 3 not divisible by 2
+    with pytest.raises(amge.AmgeError):
+        amge.build_problem("curl", 3, 1, -one, one)         # alpha must be positive
+    with pytest.raises(ValueError):
+        amge.build_problem("div", 3, 1, one[:5], one)
+
+
+def test_builder_sizes_match_closed_forms():
+    amge = _amge()
+    n = 8
+    prod = amge.build_problem("div", n, 3, np.ones(n ** 3), np.ones(n ** 3))
+    assert prod[0][0].shape[0] == W.entity_counts(n)["F"]
+    assert prod[1][0].shape[0] == 3 * 4 * 4 * 5
+    assert prod[2][0].shape[0] == 3 * 2 * 2 * 3
