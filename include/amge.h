@@ -85,8 +85,8 @@ typedef struct amge_hierarchy amge_hierarchy;
 void amge_default_opts(amge_opts* opts);
 
 /* Builds the device hierarchy from host level matrices (section 3.2, Algorithm 4.1 inputs).
- * Host work: validation, D^T (for the auxiliary restriction), P^T, the auxiliary matrices
- * D^T A D (FP64 sparse products), the l1 row sums, a dense FP64 Cholesky factor of the
+ * Host work: validation, D^T, P^T, the products D^T A and D^T A D (FP64 sparse products;
+ * the auxiliary residual D^T (b - A x) is evaluated as D^T b - (D^T A) x), the l1 row sums, a dense FP64 Cholesky factor of the
  * coarsest matrix and its inverse factor.  Device buffers are owned by the hierarchy.
  * Errors: AMGE_ERR_ARG, AMGE_ERR_SHAPE, AMGE_ERR_NONFINITE, AMGE_ERR_NOT_SPD (coarsest
  * matrix), AMGE_ERR_OOM, AMGE_ERR_HIP. */

@@ -1,12 +1,15 @@
 // Device kernels of the solve phase (gfx950, wave64).
 //
 // All level operations are HBM-bandwidth bound sparse products; nothing here is a
-// dense contraction, so no MFMA.  CSR rows are processed by LANES-wide lane groups
-// inside a 64-wide wavefront (LANES a power of two chosen per matrix from its mean row
-// length): consecutive lanes read consecutive nonzeros, so value/column loads are
-// coalesced, and the row sum is finished with cross-lane shuffles inside the group.
-// Signed incidence matrices (entries +-1) are stored index-only: bit 31 of a column
-// word is the sign.
+// dense contraction, so no MFMA.  Level matrices are stored in a sliced ELL layout
+// matched to the 64-wide wavefront: rows are grouped in slices of 64 (one row per
+// lane), stored column-major inside the slice so that every load instruction of a
+// wave reads 64 consecutive entries; rows are sorted by length inside windows of 8
+// slices to keep the padding small, and `srow` maps a slot back to its row.  Signed
+// incidence matrices (entries +-1) are stored index-only: bit 31 of a column word is
+// the sign.  Block indices are remapped so that each of the 8 XCDs (own L2) works on
+// a contiguous range of slices, which keeps the gathered vector entries of one range
+// in one L2.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,21 +19,24 @@ namespace amge {
 namespace dev {
 
 constexpr int BLOCK = 256;
-constexpr int NRED = 1024;        // blocks (and partial sums) of the streaming reductions
+constexpr int WAVES = BLOCK / 64;   // slices per block
+constexpr int NRED = 1024;          // blocks (and partial sums) of the streaming reductions
+constexpr int NXCD = 8;
 
-enum CsrMode : int {
+enum Mode : int {
     SPMV = 0,      // y = A x
     SPMV_ADD = 1,  // y += A x
     RESID = 2,     // y = b - A x
     JAC = 3,       // y = x + dinv * (b - A x)
     JAC2Z = 4,     // y = dinv*b + dinv*(b - A (dinv*b))   (two sweeps from x = 0)
+    SPLIT = 5,     // y = A [b; x]: columns < nsplit read b, the others x (column - nsplit)
 };
 
-template <int LANES, typename T>
-__device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-    for (int off = LANES / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, LANES);
-    return v;
+// Blocks are dispatched round-robin over the XCDs; give XCD k a contiguous range.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+    const int xcd = b % NXCD, idx = b / NXCD;
+    const int per = G / NXCD, rem = G % NXCD;
+    return xcd * per + min(xcd, rem) + idx;
 }
 
 template <typename T>
@@ -40,57 +46,64 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// ---------------------------------------------------------------- CSR level operator
-template <typename T, int LANES, int MODE>
+// One wave per 64-row slice.
+template <typename T, int MODE>
 __global__ void __launch_bounds__(BLOCK)
-k_csr(int n, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
-      const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv, T* __restrict__ y) {
-    const int64_t tid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int row = (int)(tid / LANES);
-    const int lane = threadIdx.x & (LANES - 1);
-    if (row >= n) return;          // whole lane groups leave together
-    const int s = rp[row], e = rp[row + 1];
+k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const int* __restrict__ ci,
+       const T* __restrict__ av, const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv,
+       T* __restrict__ y, int nsplit) {
+    const int slice = xcd_block(blockIdx.x, gridDim.x) * WAVES + (threadIdx.x >> 6);
+    if (slice >= nslices) return;
+    const int lane = threadIdx.x & 63;
+    const int base = sptr[slice];
+    const int width = (sptr[slice + 1] - base) >> 6;
+    const int row = srow[slice * 64 + lane];
+    const int* c = ci + base + lane;
+    const T* v = av + base + lane;
     T acc = 0;
-    for (int k = s + lane; k < e; k += LANES) {
-        const int j = ci[k];
-        const T xv = (MODE == JAC2Z) ? b[j] * dinv[j] : x[j];
-        acc = fma(av[k], xv, acc);
+#pragma unroll 4
+    for (int k = 0; k < width; ++k) {
+        const int j = c[k * 64];
+        T xv;
+        if (MODE == JAC2Z) xv = b[j] * dinv[j];
+        else if (MODE == SPLIT) xv = j < nsplit ? b[j] : x[j - nsplit];
+        else xv = x[j];
+        acc = fma(v[k * 64], xv, acc);
     }
-    acc = group_sum<LANES>(acc);
-    if (lane == 0) {
-        if (MODE == SPMV) y[row] = acc;
-        else if (MODE == SPMV_ADD) y[row] += acc;
-        else if (MODE == RESID) y[row] = b[row] - acc;
-        else if (MODE == JAC) y[row] = x[row] + dinv[row] * (b[row] - acc);
-        else {
-            const T x1 = dinv[row] * b[row];
-            y[row] = x1 + dinv[row] * (b[row] - acc);
-        }
+    if (row < 0) return;
+    if (MODE == SPMV || MODE == SPLIT) y[row] = acc;
+    else if (MODE == SPMV_ADD) y[row] += acc;
+    else if (MODE == RESID) y[row] = b[row] - acc;
+    else if (MODE == JAC) y[row] = x[row] + dinv[row] * (b[row] - acc);
+    else {
+        const T di = dinv[row], bi = b[row];
+        y[row] = di * bi + di * (bi - acc);
     }
 }
 
-// ---------------------------------------------------------------- signed incidences
-// y = D x (ADD = 0) or y += D x (ADD = 1); entries are +-1 encoded in the column word.
-template <typename T, int LANES, int ADD>
+// Signed incidence, index-only: y = D x (ADD = 0) or y += D x (ADD = 1).
+template <typename T, int ADD>
 __global__ void __launch_bounds__(BLOCK)
-k_inc(int n, const int* __restrict__ rp, const uint32_t* __restrict__ ent, const T* __restrict__ x,
-      T* __restrict__ y) {
-    const int64_t tid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    const int row = (int)(tid / LANES);
-    const int lane = threadIdx.x & (LANES - 1);
-    if (row >= n) return;
-    const int s = rp[row], e = rp[row + 1];
+k_sell_inc(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const uint32_t* __restrict__ ent,
+           const T* __restrict__ x, T* __restrict__ y) {
+    const int slice = xcd_block(blockIdx.x, gridDim.x) * WAVES + (threadIdx.x >> 6);
+    if (slice >= nslices) return;
+    const int lane = threadIdx.x & 63;
+    const int base = sptr[slice];
+    const int width = (sptr[slice + 1] - base) >> 6;
+    const int row = srow[slice * 64 + lane];
+    const uint32_t* e = ent + base + lane;
     T acc = 0;
-    for (int k = s + lane; k < e; k += LANES) {
-        const uint32_t w = ent[k];
+#pragma unroll 4
+    for (int k = 0; k < width; ++k) {
+        const uint32_t w = e[k * 64];
+        if (w == 0xffffffffu) continue;    // padding
         const T v = x[w & 0x7fffffffu];
         acc += (w >> 31) ? -v : v;
     }
-    acc = group_sum<LANES>(acc);
-    if (lane == 0) {
-        if (ADD) y[row] += acc;
-        else y[row] = acc;
-    }
+    if (row < 0) return;
+    if (ADD) y[row] += acc;
+    else y[row] = acc;
 }
 
 // y = dinv * x (one sweep from zero)
@@ -102,33 +115,19 @@ k_scale(int n, const T* __restrict__ dinv, const T* __restrict__ x, T* __restric
 }
 
 // ---------------------------------------------------------------- coarsest level
-// x = W^T (W b) with W = L^{-1} the inverse Cholesky factor (lower triangular, row
-// major) and WT its transpose; FP64 arithmetic whatever T is.  One workgroup.
+// x = Ainv b with Ainv = W^T W, W = L^{-1} from the FP64 Cholesky factor A = L L^T
+// formed at set-up; FP64 arithmetic whatever T is.  One wave per row.
 template <typename T>
-__global__ void __launch_bounds__(1024)
-k_coarse(int n, const double* __restrict__ W, const double* __restrict__ WT, const T* __restrict__ b,
-         T* __restrict__ x) {
-    extern __shared__ double sm[];
-    double* sb = sm;
-    double* st = sm + n;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    for (int i = tid; i < n; i += blockDim.x) sb[i] = (double)b[i];
-    __syncthreads();
-    for (int i = wave; i < n; i += nw) {
-        const double* w = W + (int64_t)i * n;
-        double acc = 0;
-        for (int j = lane; j <= i; j += 64) acc = fma(w[j], sb[j], acc);
-        acc = wave_sum(acc);
-        if (lane == 0) st[i] = acc;
-    }
-    __syncthreads();
-    for (int i = wave; i < n; i += nw) {
-        const double* w = WT + (int64_t)i * n;
-        double acc = 0;
-        for (int j = i + lane; j < n; j += 64) acc = fma(w[j], st[j], acc);
-        acc = wave_sum(acc);
-        if (lane == 0) x[i] = (T)acc;
-    }
+__global__ void __launch_bounds__(BLOCK)
+k_coarse(int n, const double* __restrict__ Ainv, const T* __restrict__ b, T* __restrict__ x) {
+    const int row = blockIdx.x * WAVES + (threadIdx.x >> 6);
+    if (row >= n) return;
+    const int lane = threadIdx.x & 63;
+    const double* a = Ainv + (int64_t)row * n;
+    double acc = 0;
+    for (int j = lane; j < n; j += 64) acc = fma(a[j], (double)b[j], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) x[row] = (T)acc;
 }
 
 // ---------------------------------------------------------------- conversions
@@ -163,23 +162,29 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
     return block_sum(v, sh);
 }
 
-// q = A p and partial sums of p.q (grid-stride over lane groups).
-template <int LANES>
+// q = A p (FP64 sliced ELL) and partial sums of p.q.  NRED blocks, each over a
+// contiguous range of slices.
 __global__ void __launch_bounds__(BLOCK)
-k_pcg_ap(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
-         const double* __restrict__ p, double* __restrict__ q, double* __restrict__ part,
-         const int* __restrict__ done) {
-    __shared__ double sh[BLOCK / 64 + 1];
+k_pcg_ap(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const int* __restrict__ ci,
+         const double* __restrict__ av, const double* __restrict__ p, double* __restrict__ q,
+         double* __restrict__ part, const int* __restrict__ done) {
+    __shared__ double sh[WAVES + 1];
     if (*done) return;
-    const int lane = threadIdx.x & (LANES - 1);
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int chunk = (nslices + gridDim.x - 1) / gridDim.x;
+    const int s0 = blk * chunk, s1 = min(nslices, s0 + chunk);
+    const int lane = threadIdx.x & 63;
     double mydot = 0;
-    const int groups_per_grid = gridDim.x * (BLOCK / LANES);
-    for (int row = blockIdx.x * (BLOCK / LANES) + threadIdx.x / LANES; row < n; row += groups_per_grid) {
-        const int s = rp[row], e = rp[row + 1];
+    for (int slice = s0 + (threadIdx.x >> 6); slice < s1; slice += WAVES) {
+        const int base = sptr[slice];
+        const int width = (sptr[slice + 1] - base) >> 6;
+        const int row = srow[slice * 64 + lane];
+        const int* c = ci + base + lane;
+        const double* v = av + base + lane;
         double acc = 0;
-        for (int k = s + lane; k < e; k += LANES) acc = fma(av[k], p[ci[k]], acc);
-        acc = group_sum<LANES>(acc);
-        if (lane == 0) {
+#pragma unroll 4
+        for (int k = 0; k < width; ++k) acc = fma(v[k * 64], p[c[k * 64]], acc);
+        if (row >= 0) {
             q[row] = acc;
             mydot = fma(p[row], acc, mydot);
         }
@@ -193,7 +198,7 @@ __global__ void __launch_bounds__(BLOCK)
 k_pcg_xr(int n, const double* __restrict__ part_pq, const double* __restrict__ part_delta,
          const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ x,
          double* __restrict__ r, float* __restrict__ r32, int* __restrict__ done, int* __restrict__ flag) {
-    __shared__ double sh[BLOCK / 64 + 1];
+    __shared__ double sh[WAVES + 1];
     if (*done) return;
     const double pq = sum_partials(part_pq, sh);
     const double delta = sum_partials(part_delta, sh);
@@ -214,7 +219,7 @@ k_pcg_xr(int n, const double* __restrict__ part_pq, const double* __restrict__ p
 __global__ void __launch_bounds__(BLOCK)
 k_pcg_dots(int n, const float* __restrict__ z32, double* __restrict__ z, const double* __restrict__ zold,
            const double* __restrict__ r, double* __restrict__ part, const int* __restrict__ done) {
-    __shared__ double sh[BLOCK / 64 + 1];
+    __shared__ double sh[WAVES + 1];
     if (*done) return;
     double a = 0, bsum = 0, c = 0;
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
@@ -247,7 +252,7 @@ __global__ void __launch_bounds__(BLOCK)
 k_pcg_p(int n, const double* __restrict__ part_new, const double* __restrict__ part_old,
         const double* __restrict__ z, double* __restrict__ p, PcgStatus* __restrict__ st,
         int* __restrict__ done, const int* __restrict__ flag, double rtol, int stop_l2, int maxit, int it) {
-    __shared__ double sh[BLOCK / 64 + 1];
+    __shared__ double sh[WAVES + 1];
     if (*done) return;
     const double dnew = sum_partials(part_new, sh);
     const double rzold = sum_partials(part_new + NRED, sh);
@@ -279,7 +284,7 @@ __global__ void k_pcg_finish(const PcgStatus* __restrict__ st, int* __restrict__
 
 // Initial quantities: delta0 = r.z, bnorm = ||b||, from the dots partials.
 __global__ void k_pcg_init(const double* __restrict__ part, PcgStatus* __restrict__ st) {
-    __shared__ double sh[BLOCK / 64 + 1];
+    __shared__ double sh[WAVES + 1];
     const double d = sum_partials(part, sh);
     const double rr = sum_partials(part + 2 * NRED, sh);
     if (threadIdx.x == 0) {

