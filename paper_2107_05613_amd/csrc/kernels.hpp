@@ -28,7 +28,6 @@ enum Mode : int {
     SPMV_ADD = 1,  // y += A x
     RESID = 2,     // y = b - A x
     JAC = 3,       // y = x + dinv * (b - A x)
-    JAC2Z = 4,     // y = dinv*b + dinv*(b - A (dinv*b))   (two sweeps from x = 0)
     SPLIT = 5,     // y = A [b; x]: columns < nsplit read b, the others x (column - nsplit)
 };
 
@@ -46,18 +45,31 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-// One wave per 64-row slice.
-template <typename T, int MODE>
+// Sliced ELL with K lanes per row (K | 64): a slice holds R = 64/K rows; entry t of
+// the slice's row rr is stored at base + (t / K) * 64 + rr * K + t % K, so every load
+// instruction of the wave reads 64 consecutive entries for every K.  Lane l works on
+// entries t = l % K (mod K) of row l / K; the K partial sums are combined with
+// cross-lane shuffles.  Small K suits many short rows, large K few long rows.
+template <int K, typename T>
+__device__ __forceinline__ T row_sum(T v) {
+#pragma unroll
+    for (int off = K / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, K);
+    return v;
+}
+
+template <typename T, int K, int MODE>
 __global__ void __launch_bounds__(BLOCK)
 k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const int* __restrict__ ci,
        const T* __restrict__ av, const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv,
-       T* __restrict__ y, int nsplit) {
+       T* __restrict__ y, T* __restrict__ yd, int nsplit) {
+    // SPMV / SPLIT with yd != null also write yd = dinv * y: the first l1-Jacobi sweep
+    // from zero on the next operator, produced where its right-hand side is produced.
     const int slice = xcd_block(blockIdx.x, gridDim.x) * WAVES + (threadIdx.x >> 6);
     if (slice >= nslices) return;
     const int lane = threadIdx.x & 63;
     const int base = sptr[slice];
     const int width = (sptr[slice + 1] - base) >> 6;
-    const int row = srow[slice * 64 + lane];
+    const int row = srow[slice * (64 / K) + lane / K];
     const int* c = ci + base + lane;
     const T* v = av + base + lane;
     T acc = 0;
@@ -65,24 +77,22 @@ k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, 
     for (int k = 0; k < width; ++k) {
         const int j = c[k * 64];
         T xv;
-        if (MODE == JAC2Z) xv = b[j] * dinv[j];
-        else if (MODE == SPLIT) xv = j < nsplit ? b[j] : x[j - nsplit];
+        if (MODE == SPLIT) xv = j < nsplit ? b[j] : x[j - nsplit];
         else xv = x[j];
         acc = fma(v[k * 64], xv, acc);
     }
-    if (row < 0) return;
-    if (MODE == SPMV || MODE == SPLIT) y[row] = acc;
-    else if (MODE == SPMV_ADD) y[row] += acc;
+    acc = row_sum<K>(acc);
+    if (row < 0 || (lane & (K - 1))) return;
+    if (MODE == SPMV || MODE == SPLIT) {
+        y[row] = acc;
+        if (yd) yd[row] = dinv[row] * acc;
+    } else if (MODE == SPMV_ADD) y[row] += acc;
     else if (MODE == RESID) y[row] = b[row] - acc;
-    else if (MODE == JAC) y[row] = x[row] + dinv[row] * (b[row] - acc);
-    else {
-        const T di = dinv[row], bi = b[row];
-        y[row] = di * bi + di * (bi - acc);
-    }
+    else y[row] = x[row] + dinv[row] * (b[row] - acc);
 }
 
-// Signed incidence, index-only: y = D x (ADD = 0) or y += D x (ADD = 1).
-template <typename T, int ADD>
+// Signed incidence, index-only (same layout): y = D x (ADD = 0) or y += D x (ADD = 1).
+template <typename T, int K, int ADD>
 __global__ void __launch_bounds__(BLOCK)
 k_sell_inc(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const uint32_t* __restrict__ ent,
            const T* __restrict__ x, T* __restrict__ y) {
@@ -91,7 +101,7 @@ k_sell_inc(int nslices, const int* __restrict__ sptr, const int* __restrict__ sr
     const int lane = threadIdx.x & 63;
     const int base = sptr[slice];
     const int width = (sptr[slice + 1] - base) >> 6;
-    const int row = srow[slice * 64 + lane];
+    const int row = srow[slice * (64 / K) + lane / K];
     const uint32_t* e = ent + base + lane;
     T acc = 0;
 #pragma unroll 4
@@ -101,7 +111,8 @@ k_sell_inc(int nslices, const int* __restrict__ sptr, const int* __restrict__ sr
         const T v = x[w & 0x7fffffffu];
         acc += (w >> 31) ? -v : v;
     }
-    if (row < 0) return;
+    acc = row_sum<K>(acc);
+    if (row < 0 || (lane & (K - 1))) return;
     if (ADD) y[row] += acc;
     else y[row] = acc;
 }
@@ -164,6 +175,7 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 
 // q = A p (FP64 sliced ELL) and partial sums of p.q.  NRED blocks, each over a
 // contiguous range of slices.
+template <int K>
 __global__ void __launch_bounds__(BLOCK)
 k_pcg_ap(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const int* __restrict__ ci,
          const double* __restrict__ av, const double* __restrict__ p, double* __restrict__ q,
@@ -178,13 +190,14 @@ k_pcg_ap(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow
     for (int slice = s0 + (threadIdx.x >> 6); slice < s1; slice += WAVES) {
         const int base = sptr[slice];
         const int width = (sptr[slice + 1] - base) >> 6;
-        const int row = srow[slice * 64 + lane];
+        const int row = srow[slice * (64 / K) + lane / K];
         const int* c = ci + base + lane;
         const double* v = av + base + lane;
         double acc = 0;
 #pragma unroll 4
         for (int k = 0; k < width; ++k) acc = fma(v[k * 64], p[c[k * 64]], acc);
-        if (row >= 0) {
+        acc = row_sum<K>(acc);
+        if (row >= 0 && !(lane & (K - 1))) {
             q[row] = acc;
             mydot = fma(p[row], acc, mydot);
         }
@@ -193,11 +206,15 @@ k_pcg_ap(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-// alpha = delta / (p.q); x += alpha p; r -= alpha q; r32 = (float) r (if r32 != null).
+// alpha = delta / (p.q); x += alpha p; r -= alpha q.  Also the level-1 inputs of the
+// V-cycle: r32 = (float) r and rd32 = dinv32 * r32 (FP32 preconditioner) or
+// rd64 = dinv64 * r (FP64 preconditioner), whichever pointers are non-null.
 __global__ void __launch_bounds__(BLOCK)
 k_pcg_xr(int n, const double* __restrict__ part_pq, const double* __restrict__ part_delta,
          const double* __restrict__ p, const double* __restrict__ q, double* __restrict__ x,
-         double* __restrict__ r, float* __restrict__ r32, int* __restrict__ done, int* __restrict__ flag) {
+         double* __restrict__ r, float* __restrict__ r32, float* __restrict__ rd32,
+         const float* __restrict__ dinv32, double* __restrict__ rd64, const double* __restrict__ dinv64,
+         int* __restrict__ done, int* __restrict__ flag) {
     __shared__ double sh[WAVES + 1];
     if (*done) return;
     const double pq = sum_partials(part_pq, sh);
@@ -211,7 +228,12 @@ k_pcg_xr(int n, const double* __restrict__ part_pq, const double* __restrict__ p
         x[i] = fma(alpha, p[i], x[i]);
         const double ri = fma(-alpha, q[i], r[i]);
         r[i] = ri;
-        if (r32) r32[i] = (float)ri;
+        if (r32) {
+            const float rf = (float)ri;
+            r32[i] = rf;
+            rd32[i] = dinv32[i] * rf;
+        }
+        if (rd64) rd64[i] = dinv64[i] * ri;
     }
 }
 

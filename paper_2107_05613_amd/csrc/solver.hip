@@ -7,8 +7,12 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <memory>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <tuple>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -26,6 +30,7 @@ namespace amge {
 // Sliced ELL matrix (64-row slices, column-major inside a slice) on the device.
 struct DSell {
     int nrows = 0, ncols = 0, nslices = 0;
+    int K = 1;                // lanes per row
     int64_t nnz = 0;          // stored nonzeros of the CSR input
     int64_t stored = 0;       // entries including padding
     int* sptr = nullptr;      // nslices + 1 entry offsets
@@ -39,6 +44,7 @@ struct DSell {
 template <class T>
 struct Work {
     T *b = nullptr, *x = nullptr, *xt = nullptr, *r = nullptr, *g = nullptr, *y = nullptr, *yt = nullptr;
+    T *bd = nullptr, *gd = nullptr;   // dinv * b, dhinv * g: first sweeps from zero
     T* dinv = nullptr;
     T* dhinv = nullptr;
 };
@@ -109,70 +115,86 @@ T* upload(amge_hierarchy* H, const T* src, size_t n, hipStream_t s) {
     return d;
 }
 
-// Host conversion CSR -> sliced ELL.  Rows are sorted by decreasing length inside
-// windows of 8 slices (512 rows); each slice is as wide as its longest row.
-DSell upload_sell(amge_hierarchy* H, const Csr& A, bool incidence, hipStream_t s) {
-    constexpr int C = 64, WIN = 512;
+// Host conversion CSR -> sliced ELL with K lanes per row.  Rows are sorted by
+// decreasing length inside windows of 8 slices; each slice is as wide as its longest
+// row (rounded up to a multiple of K).
+struct HostSell {
+    int K = 1, nslices = 0;
+    std::vector<int> sptr, srow, ci;
+    std::vector<uint32_t> ent;
+    std::vector<double> val;
+};
+
+HostSell make_sell(const Csr& A, bool incidence, int K) {
+    const int R = 64 / K;
+    HostSell h;
+    h.K = K;
+    h.nslices = (A.nrows + R - 1) / R;
+    h.srow.assign((size_t)h.nslices * R, -1);
+    const int win = 8 * R;
+    std::vector<int> order;
+    auto len = [&](int r) { return A.rowptr[r + 1] - A.rowptr[r]; };
+    for (int w0 = 0; w0 < A.nrows; w0 += win) {
+        int w1 = std::min(A.nrows, w0 + win);
+        order.resize(w1 - w0);
+        std::iota(order.begin(), order.end(), w0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return len(a) > len(b); });
+        for (int i = 0; i < w1 - w0; ++i) h.srow[w0 + i] = order[i];
+    }
+    h.sptr.assign(h.nslices + 1, 0);
+    for (int sl = 0; sl < h.nslices; ++sl) {
+        int mx = 0;
+        for (int l = 0; l < R; ++l) {
+            int r = h.srow[(size_t)sl * R + l];
+            if (r >= 0) mx = std::max(mx, len(r));
+        }
+        int64_t width = (mx + K - 1) / K;
+        if ((int64_t)h.sptr[sl] + width * 64 > INT32_MAX) fail(AMGE_ERR_SHAPE, "matrix too large for int32 offsets");
+        h.sptr[sl + 1] = h.sptr[sl] + (int)(width * 64);
+    }
+    const size_t stored = h.sptr[h.nslices];
+    if (incidence) h.ent.assign(stored, 0xffffffffu);
+    else {
+        h.ci.assign(stored, 0);
+        h.val.assign(stored, 0.0);
+    }
+    for (int sl = 0; sl < h.nslices; ++sl)
+        for (int rr = 0; rr < R; ++rr) {
+            int r = h.srow[(size_t)sl * R + rr];
+            if (r < 0) continue;
+            for (int t = 0; t < len(r); ++t) {
+                size_t idx = (size_t)h.sptr[sl] + (size_t)(t / K) * 64 + rr * K + t % K;
+                int c = A.col[A.rowptr[r] + t];
+                double v = A.val[A.rowptr[r] + t];
+                if (incidence) {
+                    if (v != 1.0 && v != -1.0) fail(AMGE_ERR_ARG, "derivative matrix entries must be +-1");
+                    h.ent[idx] = (uint32_t)c | (v < 0 ? 0x80000000u : 0u);
+                } else {
+                    h.ci[idx] = c;
+                    h.val[idx] = v;
+                }
+            }
+        }
+    return h;
+}
+
+DSell upload_sell(amge_hierarchy* H, const Csr& A, bool incidence, int K, hipStream_t s) {
+    HostSell h = make_sell(A, incidence, K);
     DSell d;
     d.nrows = A.nrows;
     d.ncols = A.ncols;
     d.nnz = A.nnz();
-    d.nslices = (A.nrows + C - 1) / C;
-    std::vector<int> srow((size_t)d.nslices * C, -1);
-    std::vector<int> order;
-    for (int w0 = 0; w0 < A.nrows; w0 += WIN) {
-        int w1 = std::min(A.nrows, w0 + WIN);
-        order.resize(w1 - w0);
-        std::iota(order.begin(), order.end(), w0);
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-            return A.rowptr[a + 1] - A.rowptr[a] > A.rowptr[b + 1] - A.rowptr[b];
-        });
-        for (int i = 0; i < w1 - w0; ++i) srow[w0 + i] = order[i];
-    }
-    std::vector<int> sptr(d.nslices + 1, 0);
-    for (int sl = 0; sl < d.nslices; ++sl) {
-        int width = 0;
-        for (int l = 0; l < C; ++l) {
-            int r = srow[(size_t)sl * C + l];
-            if (r >= 0) width = std::max(width, A.rowptr[r + 1] - A.rowptr[r]);
-        }
-        if ((int64_t)sptr[sl] + (int64_t)width * C > INT32_MAX) fail(AMGE_ERR_SHAPE, "matrix too large for int32 offsets");
-        sptr[sl + 1] = sptr[sl] + width * C;
-    }
-    d.stored = sptr[d.nslices];
-    std::vector<int> ci;
-    std::vector<uint32_t> ent;
-    std::vector<double> v64;
-    if (incidence) ent.assign(d.stored, 0xffffffffu);
-    else {
-        ci.assign(d.stored, 0);
-        v64.assign(d.stored, 0.0);
-    }
-    for (int sl = 0; sl < d.nslices; ++sl)
-        for (int l = 0; l < C; ++l) {
-            int r = srow[(size_t)sl * C + l];
-            if (r < 0) continue;
-            for (int k = 0; k < A.rowptr[r + 1] - A.rowptr[r]; ++k) {
-                size_t idx = (size_t)sptr[sl] + (size_t)k * C + l;
-                int c = A.col[A.rowptr[r] + k];
-                double v = A.val[A.rowptr[r] + k];
-                if (incidence) {
-                    if (v != 1.0 && v != -1.0) fail(AMGE_ERR_ARG, "derivative matrix entries must be +-1");
-                    ent[idx] = (uint32_t)c | (v < 0 ? 0x80000000u : 0u);
-                } else {
-                    ci[idx] = c;
-                    v64[idx] = v;
-                }
-            }
-        }
-    d.sptr = upload(H, sptr.data(), sptr.size(), s);
-    d.srow = upload(H, srow.data(), srow.size(), s);
+    d.K = K;
+    d.nslices = h.nslices;
+    d.stored = h.sptr[h.nslices];
+    d.sptr = upload(H, h.sptr.data(), h.sptr.size(), s);
+    d.srow = upload(H, h.srow.data(), h.srow.size(), s);
     if (incidence) {
-        d.ent = upload(H, ent.data(), ent.size(), s);
+        d.ent = upload(H, h.ent.data(), h.ent.size(), s);
     } else {
-        d.ci = upload(H, ci.data(), ci.size(), s);
-        d.v64 = upload(H, v64.data(), v64.size(), s);
-        std::vector<float> v32(v64.begin(), v64.end());   // round to nearest
+        d.ci = upload(H, h.ci.data(), h.ci.size(), s);
+        d.v64 = upload(H, h.val.data(), h.val.size(), s);
+        std::vector<float> v32(h.val.begin(), h.val.end());   // round to nearest
         d.v32 = upload(H, v32.data(), v32.size(), s);
     }
     HIPCHECK(hipStreamSynchronize(s));
@@ -187,29 +209,143 @@ template <class T> const T* vals(const DSell& M);
 template <> const float* vals<float>(const DSell& M) { return M.v32; }
 template <> const double* vals<double>(const DSell& M) { return M.v64; }
 
-template <class T>
-void sell(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s, int nsplit = 0) {
+template <class T, int K>
+void sell_k(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* y, T* yd, hipStream_t s,
+            int nsplit) {
     unsigned g = grid_slices(M.nslices);
     if (g == 0) return;
     const T* v = vals<T>(M);
-#define AMGE_SELL(MODE) dev::k_sell<T, MODE><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ci, v, x, b, dinv, y, nsplit)
+#define AMGE_SELL(MODE) \
+    dev::k_sell<T, K, MODE><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ci, v, x, b, dinv, y, yd, nsplit)
     switch (mode) {
         case dev::SPMV: AMGE_SELL(dev::SPMV); break;
         case dev::SPMV_ADD: AMGE_SELL(dev::SPMV_ADD); break;
         case dev::RESID: AMGE_SELL(dev::RESID); break;
         case dev::JAC: AMGE_SELL(dev::JAC); break;
-        case dev::JAC2Z: AMGE_SELL(dev::JAC2Z); break;
         default: AMGE_SELL(dev::SPLIT); break;
     }
 #undef AMGE_SELL
 }
 
+// mode as in dev::Mode; yd (SPMV, SPLIT) receives dinv * y when non-null.
 template <class T>
-void sell_inc(const DSell& M, int add, const T* x, T* y, hipStream_t s) {
+void sell(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s, int nsplit = 0,
+          T* yd = nullptr) {
+    switch (M.K) {
+        case 1: sell_k<T, 1>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
+        case 2: sell_k<T, 2>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
+        case 4: sell_k<T, 4>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
+        case 8: sell_k<T, 8>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
+        case 16: sell_k<T, 16>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
+        case 32: sell_k<T, 32>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
+        default: sell_k<T, 64>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
+    }
+}
+
+template <class T, int K>
+void sell_inc_k(const DSell& M, int add, const T* x, T* y, hipStream_t s) {
     unsigned g = grid_slices(M.nslices);
     if (g == 0) return;
-    if (add) dev::k_sell_inc<T, 1><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ent, x, y);
-    else dev::k_sell_inc<T, 0><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ent, x, y);
+    if (add) dev::k_sell_inc<T, K, 1><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ent, x, y);
+    else dev::k_sell_inc<T, K, 0><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ent, x, y);
+}
+
+template <class T>
+void sell_inc(const DSell& M, int add, const T* x, T* y, hipStream_t s) {
+    switch (M.K) {
+        case 1: sell_inc_k<T, 1>(M, add, x, y, s); break;
+        case 2: sell_inc_k<T, 2>(M, add, x, y, s); break;
+        case 4: sell_inc_k<T, 4>(M, add, x, y, s); break;
+        case 8: sell_inc_k<T, 8>(M, add, x, y, s); break;
+        case 16: sell_inc_k<T, 16>(M, add, x, y, s); break;
+        case 32: sell_inc_k<T, 32>(M, add, x, y, s); break;
+        default: sell_inc_k<T, 64>(M, add, x, y, s); break;
+    }
+}
+
+// ------------------------------------------------------------------ autotuning
+// Lanes per row K for one matrix: every candidate layout is built and its FP32 product
+// timed with HIP events; the fastest is kept.  Results are cached per matrix shape for
+// the process lifetime.
+struct TuneKey {
+    int nrows, ncols;
+    int64_t nnz;
+    bool inc;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(nrows, ncols, nnz, inc) < std::tie(o.nrows, o.ncols, o.nnz, o.inc);
+    }
+};
+
+static bool verbose() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("AMGE_VERBOSE");
+        v = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return v == 1;
+}
+
+static std::mutex g_tune_mu;
+static std::map<TuneKey, int> g_tune;
+
+int tune_lanes(const Csr& A, bool incidence, hipStream_t s) {
+    TuneKey key{A.nrows, A.ncols, A.nnz(), incidence};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) return it->second;
+    }
+    const double avg = A.nrows ? (double)A.nnz() / A.nrows : 0;
+    std::vector<int> cands = {1};
+    for (int K = 2; K <= 32; K *= 2)
+        if (avg >= 2.0 * K) cands.push_back(K);
+    int best = cands[0];
+    if (cands.size() > 1) {
+        amge_hierarchy tmp;   // owns the trial buffers
+        float* x = tmp.alloc<float>(A.ncols);
+        float* y = tmp.alloc<float>(A.nrows);
+        HIPCHECK(hipMemsetAsync(x, 0, sizeof(float) * A.ncols, s));
+        hipEvent_t e0, e1;
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        float best_ms = 1e30f;
+        for (int K : cands) {
+            amge_hierarchy t2;
+            DSell M = upload_sell(&t2, A, incidence, K, s);
+            auto run = [&]() {
+                if (incidence) sell_inc<float>(M, 0, x, y, s);
+                else sell<float>(M, dev::SPMV, x, nullptr, nullptr, y, s);
+            };
+            for (int i = 0; i < 2; ++i) run();
+            float ms = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {   // best of three rounds of five launches
+                HIPCHECK(hipEventRecord(e0, s));
+                for (int i = 0; i < 5; ++i) run();
+                HIPCHECK(hipEventRecord(e1, s));
+                HIPCHECK(hipEventSynchronize(e1));
+                float t = 0;
+                HIPCHECK(hipEventElapsedTime(&t, e0, e1));
+                ms = std::min(ms, t);
+            }
+            HIPCHECK(hipGetLastError());
+            if (verbose())
+                fprintf(stderr, "[amge tune] rows %d nnz %lld avg %.1f K=%d: %.2f us\n", A.nrows, (long long)A.nnz(),
+                        avg, K, 1e3 * ms / 5);
+            if (ms < best_ms * 0.97f) {   // prefer the smaller K unless clearly faster
+                best_ms = ms;
+                best = K;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best;
+    return best;
+}
+
+DSell upload_tuned(amge_hierarchy* H, const Csr& A, bool incidence, hipStream_t s) {
+    return upload_sell(H, A, incidence, tune_lanes(A, incidence, s), s);
 }
 
 // Launch of an A_k kernel; on a probed level the launch is bracketed by events and its
@@ -254,19 +390,20 @@ void convert(int64_t n, const S* a, D* b, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ smoother and V-cycle
-// Primary l1-Jacobi sweeps on A: x <- x + dinv (b - A x), nu times.  With from_zero the
-// first two sweeps are fused (the first one from zero is x = dinv b).  x and xt are
-// swapped by the ping-pong; the caller tracks where the result is.
+// Primary l1-Jacobi sweeps on A: x <- x + dinv (b - A x), nu times.  From zero, the
+// first sweep is x = dinv b, which the producer of b has already written to bd, so the
+// first launched sweep starts from bd.  x and xt are swapped by the ping-pong; the
+// caller tracks where the result is.
 template <class T>
-void primary(DLevel& L, const T* b, T*& x, T*& xt, bool from_zero, int nu, hipStream_t s) {
+void primary(DLevel& L, const T* b, const T* bd, T*& x, T*& xt, bool from_zero, int nu, hipStream_t s) {
     Work<T>& w = L.w<T>();
     int k = 0;
     if (from_zero) {
         if (nu >= 2) {
-            asell<T>(L, dev::JAC2Z, nullptr, b, w.dinv, x, s);
+            asell<T>(L, dev::JAC, bd, b, w.dinv, x, s);
             k = 2;
         } else if (nu == 1) {
-            scale<T>(L.n, w.dinv, b, x, s);
+            HIPCHECK(hipMemcpyAsync(x, bd, sizeof(T) * L.n, hipMemcpyDeviceToDevice, s));
             k = 1;
         } else {
             HIPCHECK(hipMemsetAsync(x, 0, sizeof(T) * L.n, s));
@@ -279,31 +416,28 @@ void primary(DLevel& L, const T* b, T*& x, T*& xt, bool from_zero, int nu, hipSt
 }
 
 // Auxiliary correction of eq. (4.1): x <- x + D Mhat^{-1} D^T (b - A x), Mhat^{-1} being
-// nu l1-Jacobi sweeps on D^T A D from zero.
+// nu l1-Jacobi sweeps on D^T A D from zero.  The residual kernel also writes the first
+// sweep gd = dhinv g.
 template <class T>
 void auxiliary(DLevel& L, const T* b, T* x, int nu, hipStream_t s) {
     if (nu <= 0 || L.m == 0) return;
     Work<T>& w = L.w<T>();
-    sell<T>(L.Aux, dev::SPLIT, x, b, nullptr, w.g, s, L.n);
-    T* y = w.y;
-    T* yt = w.yt;
-    int k;
-    if (nu >= 2) {
-        sell<T>(L.Ah, dev::JAC2Z, nullptr, w.g, w.dhinv, y, s);
-        k = 2;
-    } else {
-        scale<T>(L.m, w.dhinv, w.g, y, s);
-        k = 1;
-    }
-    for (; k < nu; ++k) {
-        sell<T>(L.Ah, dev::JAC, y, w.g, w.dhinv, yt, s);
-        std::swap(y, yt);
+    sell<T>(L.Aux, dev::SPLIT, x, b, w.dhinv, w.g, s, L.n, w.gd);
+    const T* y = w.gd;
+    T* ya = w.y;
+    T* yb = w.yt;
+    for (int k = 1; k < nu; ++k) {
+        sell<T>(L.Ah, dev::JAC, y, w.g, w.dhinv, ya, s);
+        y = ya;
+        std::swap(ya, yb);
     }
     sell_inc<T>(L.D, 1, y, x, s);
 }
 
+// One V-cycle (Algorithm 4.1, x0 = 0) from level l down: b and bd = dinv b are the
+// level's right-hand side and first sweep, the result goes to xout.
 template <class T>
-void vcycle_level(amge_hierarchy* H, int l, const T* b, T* xout, hipStream_t s) {
+void vcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, hipStream_t s) {
     const int nl = (int)H->lv.size();
     if (l == nl - 1) {
         coarse_solve<T>(H, b, xout, s);
@@ -316,17 +450,20 @@ void vcycle_level(amge_hierarchy* H, int l, const T* b, T* xout, hipStream_t s) 
     T* x = xout;
     T* xt = w.xt;
     const int nup = H->opts.nu_primary, nua = H->opts.nu_aux;
+    const bool next_coarsest = l + 1 == nl - 1;
     // pre-smoothing with Mbar (eq. (4.1)): primary, then auxiliary
-    primary<T>(L, b, x, xt, true, nup, s);
+    primary<T>(L, b, bd, x, xt, true, nup, s);
     auxiliary<T>(L, b, x, nua, s);
-    // restriction of the residual, coarse correction, prolongation
+    // restriction of the residual (and the coarse first sweep), coarse correction,
+    // prolongation
     asell<T>(L, dev::RESID, x, b, nullptr, w.r, s);
-    sell<T>(L.Pt, dev::SPMV, w.r, nullptr, nullptr, wc.b, s);
-    vcycle_level<T>(H, l + 1, wc.b, wc.x, s);
+    sell<T>(L.Pt, dev::SPMV, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, s, 0,
+            next_coarsest ? nullptr : wc.bd);
+    vcycle_level<T>(H, l + 1, wc.b, wc.bd, wc.x, s);
     sell<T>(L.P, dev::SPMV_ADD, wc.x, nullptr, nullptr, x, s);
     // post-smoothing with Mbar^T: auxiliary first, then primary
     auxiliary<T>(L, b, x, nua, s);
-    primary<T>(L, b, x, xt, false, nup, s);
+    primary<T>(L, b, nullptr, x, xt, false, nup, s);
     if (x != xout) HIPCHECK(hipMemcpyAsync(xout, x, sizeof(T) * L.n, hipMemcpyDeviceToDevice, s));
 }
 
@@ -336,10 +473,12 @@ void precondition(amge_hierarchy* H, const double* r, double* z, hipStream_t s) 
     DLevel& L = H->lv[0];
     if (H->opts.precond_bits == 32) {
         convert<double, float>(L.n, r, L.w32.b, s);
-        vcycle_level<float>(H, 0, L.w32.b, L.w32.x, s);
+        scale<float>(L.n, L.w32.dinv, L.w32.b, L.w32.bd, s);
+        vcycle_level<float>(H, 0, L.w32.b, L.w32.bd, L.w32.x, s);
         convert<float, double>(L.n, L.w32.x, z, s);
     } else {
-        vcycle_level<double>(H, 0, r, z, s);
+        scale<double>(L.n, L.w64.dinv, r, L.w64.bd, s);
+        vcycle_level<double>(H, 0, r, L.w64.bd, z, s);
     }
 }
 
@@ -402,6 +541,8 @@ void alloc_work(amge_hierarchy* H, DLevel& L, Work<T>& w, const std::vector<doub
     w.g = H->alloc<T>(mr);
     w.y = H->alloc<T>(mr);
     w.yt = H->alloc<T>(mr);
+    w.bd = H->alloc<T>(nr);
+    w.gd = H->alloc<T>(mr);
     std::vector<T> a(dinv.begin(), dinv.end()), c(dhinv.begin(), dhinv.end());
     w.dinv = upload(H, a.data(), a.size(), s);
     w.dhinv = upload(H, c.data(), c.size(), s);
@@ -444,12 +585,12 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
             dinv[i] = 1.0 / d[i];
         }
         for (size_t i = 0; i < dh.size(); ++i) dhinv[i] = dh[i] > 0 ? 1.0 / dh[i] : 0.0;
-        L.A = upload_sell(H, A[k], false, s);
-        L.Ah = upload_sell(H, Ah, false, s);
-        L.P = upload_sell(H, P[k], false, s);
-        L.Pt = upload_sell(H, transpose(P[k]), false, s);
-        L.D = upload_sell(H, D[k], true, s);
-        L.Dt = upload_sell(H, Dt, true, s);
+        L.A = upload_tuned(H, A[k], false, s);
+        L.Ah = upload_tuned(H, Ah, false, s);
+        L.P = upload_tuned(H, P[k], false, s);
+        L.Pt = upload_tuned(H, transpose(P[k]), false, s);
+        L.D = upload_tuned(H, D[k], true, s);
+        L.Dt = upload_tuned(H, Dt, true, s);
         {
             // [D^T | -D^T A] over the columns [b; x]
             Csr X;
@@ -467,14 +608,14 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
                 }
                 X.rowptr[i + 1] = (int32_t)X.col.size();
             }
-            L.Aux = upload_sell(H, X, false, s);
+            L.Aux = upload_tuned(H, X, false, s);
         }
         alloc_work<float>(H, L, L.w32, dinv, dhinv, s);
         alloc_work<double>(H, L, L.w64, dinv, dhinv, s);
     }
     if (nl == 1) {
         // the fine matrix itself is needed by the outer PCG even on one level
-        H->lv[0].A = upload_sell(H, A[0], false, s);
+        H->lv[0].A = upload_tuned(H, A[0], false, s);
     }
     size_t n1 = (size_t)H->lv[0].n * H->opts.max_rhs;
     H->r = H->alloc<double>(n1);
@@ -491,10 +632,23 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ PCG
-void launch_pcg_ap(amge_hierarchy* H, hipStream_t s) {
+template <int K>
+void pcg_ap_k(amge_hierarchy* H, hipStream_t s) {
     const DSell& A = H->lv[0].A;
-    dev::k_pcg_ap<<<dev::NRED, BLOCK, 0, s>>>(A.nslices, A.sptr, A.srow, A.ci, A.v64, H->p, H->q, H->part_pq,
-                                             H->flags);
+    dev::k_pcg_ap<K><<<dev::NRED, BLOCK, 0, s>>>(A.nslices, A.sptr, A.srow, A.ci, A.v64, H->p, H->q, H->part_pq,
+                                                H->flags);
+}
+
+void launch_pcg_ap(amge_hierarchy* H, hipStream_t s) {
+    switch (H->lv[0].A.K) {
+        case 1: pcg_ap_k<1>(H, s); break;
+        case 2: pcg_ap_k<2>(H, s); break;
+        case 4: pcg_ap_k<4>(H, s); break;
+        case 8: pcg_ap_k<8>(H, s); break;
+        case 16: pcg_ap_k<16>(H, s); break;
+        case 32: pcg_ap_k<32>(H, s); break;
+        default: pcg_ap_k<64>(H, s); break;
+    }
 }
 
 amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int maxit, int stop_l2,
@@ -502,21 +656,28 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
     const int n = H->lv[0].n;
     const bool f32 = H->opts.precond_bits == 32;
     const bool multilevel = H->lv.size() > 1;
-    float* r32 = f32 && multilevel ? H->lv[0].w32.b : nullptr;
-    float* z32 = f32 && multilevel ? H->lv[0].w32.x : nullptr;
+    DLevel& L1 = H->lv[0];
+    float* r32 = f32 && multilevel ? L1.w32.b : nullptr;
+    float* rd32 = f32 && multilevel ? L1.w32.bd : nullptr;
+    float* z32 = f32 && multilevel ? L1.w32.x : nullptr;
+    double* rd64 = !f32 && multilevel ? L1.w64.bd : nullptr;
     auto precond_into = [&](double* z) {
         if (!multilevel) {
             coarse_solve<double>(H, H->r, z, s);
         } else if (f32) {
-            vcycle_level<float>(H, 0, r32, z32, s);
+            vcycle_level<float>(H, 0, r32, rd32, z32, s);
         } else {
-            vcycle_level<double>(H, 0, H->r, z, s);
+            vcycle_level<double>(H, 0, H->r, rd64, z, s);
         }
     };
     HIPCHECK(hipMemcpyAsync(H->r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     HIPCHECK(hipMemsetAsync(x, 0, sizeof(double) * n, s));
     HIPCHECK(hipMemsetAsync(H->flags, 0, 2 * sizeof(int), s));
-    if (r32) convert<double, float>(n, H->r, r32, s);
+    if (r32) {
+        convert<double, float>(n, H->r, r32, s);
+        scale<float>(n, L1.w32.dinv, r32, rd32, s);
+    }
+    if (rd64) scale<double>(n, L1.w64.dinv, H->r, rd64, s);
     // z_0 = B r_0, delta_0 = r_0 . z_0
     precond_into(H->z[1]);
     dev::k_pcg_dots<<<dev::NRED, BLOCK, 0, s>>>(n, z32, H->z[1], nullptr, H->r, H->part_dots[1], H->flags);
@@ -539,8 +700,9 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
         double* dnew = H->part_dots[it & 1];
         double* dold = H->part_dots[(it + 1) & 1];
         launch_pcg_ap(H, s);
-        dev::k_pcg_xr<<<dev::NRED, BLOCK, 0, s>>>(n, H->part_pq, dold, H->p, H->q, x, H->r, r32, H->flags,
-                                                  H->flags + 1);
+        dev::k_pcg_xr<<<dev::NRED, BLOCK, 0, s>>>(n, H->part_pq, dold, H->p, H->q, x, H->r, r32, rd32,
+                                                  f32 ? L1.w32.dinv : nullptr, rd64,
+                                                  f32 ? nullptr : L1.w64.dinv, H->flags, H->flags + 1);
         precond_into(znew);
         dev::k_pcg_dots<<<dev::NRED, BLOCK, 0, s>>>(n, z32, znew, zold, H->r, dnew, H->flags);
         dev::k_pcg_p<<<dev::NRED, BLOCK, 0, s>>>(n, dnew, dold, znew, H->p, H->st, H->flags, H->flags + 1, rtol,
@@ -701,11 +863,11 @@ extern "C" amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_
                     T* x = w.x;
                     T* xt = w.xt;
                     if (op == AMGE_OP_SMOOTH) {
-                        primary<T>(L, vin, x, xt, false, h->opts.nu_primary, s);
+                        primary<T>(L, vin, nullptr, x, xt, false, h->opts.nu_primary, s);
                         auxiliary<T>(L, vin, x, h->opts.nu_aux, s);
                     } else {
                         auxiliary<T>(L, vin, x, h->opts.nu_aux, s);
-                        primary<T>(L, vin, x, xt, false, h->opts.nu_primary, s);
+                        primary<T>(L, vin, nullptr, x, xt, false, h->opts.nu_primary, s);
                     }
                     HIPCHECK(hipMemcpyAsync(vout, x, sizeof(T) * L.n, hipMemcpyDeviceToDevice, s));
                 }
@@ -777,15 +939,14 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
             const double n = L.n, m = L.m, nc = h->lv[k + 1].n;
             auto mat = [&](const DSell& M) { return (double)M.nnz * (sv + 4.0) + 4.0 * M.nrows; };
             auto incb = [&](const DSell& M) { return (double)M.nnz * 4.0 + 4.0 * M.nrows; };
-            // primary sweeps: first two fused from zero (b, dinv, y), then x, b, dinv, y
-            const int sweeps = 2 * nup;
-            int fused = nup >= 2 ? 1 : 0;
-            tot += fused * (mat(L.A) + 3 * sv * n) + (sweeps - 2 * fused) * (mat(L.A) + 4 * sv * n);
-            // auxiliary step, pre and post: residual, D^T, aux sweeps, D add
+            // primary sweeps: the first one from zero is the producer's bd = dinv b (two
+            // extra streams there), every launched sweep reads x, b, dinv and writes y
+            const int launched = std::max(0, nup - 1) + nup;
+            tot += launched * (mat(L.A) + 4 * sv * n) + 2 * sv * n;
+            // auxiliary step, pre and post: residual [D^T | -D^T A][b; x] (+ gd), sweeps, D add
             if (nua > 0) {
-                double aux = mat(L.Aux) + sv * (2 * n + m);
-                aux += (nua >= 2 ? (mat(L.Ah) + 3 * sv * m) : 2 * sv * m);
-                aux += std::max(0, nua - 2) * (mat(L.Ah) + 4 * sv * m);
+                double aux = mat(L.Aux) + sv * (2 * n + m) + 2 * sv * m;
+                aux += (nua - 1) * (mat(L.Ah) + 4 * sv * m);
                 aux += incb(L.D) + sv * (m + 2 * n);
                 tot += 2 * aux;
             }
