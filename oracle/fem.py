@@ -78,12 +78,14 @@ class FineMesh:
         self.tets = tets[order]
         self.tet_hex = thex[order]
 
-        pairs = np.concatenate([self.tets[:, list(e)] for e in TET_EDGES])
-        self.edges = np.unique(pairs, axis=0)
-        tris = np.concatenate([self.tets[:, list(f)] for f in TET_FACES])
-        self.faces = np.unique(tris, axis=0)
-        self.ekey = _keys(self.edges, nv)
-        self.fkey = _keys(self.faces, nv)
+        # unique sorted entities: the int64 key order is the lexicographic tuple order
+        ekeys = np.unique(np.concatenate([_keys(self.tets[:, list(e)], nv) for e in TET_EDGES]))
+        self.edges = np.stack([ekeys // nv, ekeys % nv], axis=1)
+        fkeys = np.unique(np.concatenate([_keys(self.tets[:, list(f)], nv) for f in TET_FACES]))
+        self.faces = np.stack([fkeys // (nv * nv), (fkeys // nv) % nv, fkeys % nv], axis=1)
+        self.ekey = ekeys
+        self.fkey = fkeys
+        self._signs = None
 
         # element -> global entity maps
         self.tet_edges = np.stack([np.searchsorted(self.ekey, _keys(self.tets[:, list(e)], nv))
@@ -118,6 +120,8 @@ class FineMesh:
 
     def tet_face_signs(self):
         """+1 where the face's orientation normal points out of the tet, else -1."""
+        if self._signs is not None:
+            return self._signs
         X = self.X
         sgn = np.empty((len(self.tets), 4))
         for i, f in enumerate(TET_FACES):
@@ -128,6 +132,7 @@ class FineMesh:
             s = np.einsum("ij,ij->i", nrm, outward)
             assert np.all(s != 0)
             sgn[:, i] = np.sign(s)
+        self._signs = sgn
         return sgn
 
     def div(self):
@@ -180,19 +185,17 @@ class FineMesh:
         h = self.h
         vol = vol6 * h ** 3 / 6.0
         s = self.tet_face_signs()
+        # int (x - x_i).(x - x_j) = |tau| sum_ab I_ab (x_a - x_i).(x_b - x_j), I_ab = (1 + d_ab)/20.
+        # With the Gram matrix Gr_ab = y_a.y_b of y_a = x_a - x_0 (integers) and
+        # sum_b I_ab = 1/4, sum_ab I_ab = 1 this is
+        #   sum_ab I_ab Gr_ab - (colsum_j + rowsum_i) / 4 + Gr_ij.
+        Y = (X - X[:, :1, :]).astype(np.float64)
+        Gr = np.einsum("tad,tbd->tab", Y, Y)
         I = (np.ones((4, 4)) + np.eye(4)) / 20.0
-        M = np.empty((len(self.tets), 4, 4))
-        for i in range(4):
-            for j in range(4):
-                acc = np.zeros(len(self.tets))
-                for a in range(4):
-                    for b in range(4):
-                        # integer lattice differences, scaled by h afterwards
-                        dai = (X[:, a] - X[:, i]).astype(np.float64)
-                        dbj = (X[:, b] - X[:, j]).astype(np.float64)
-                        acc += I[a, b] * np.einsum("td,td->t", dai, dbj) * h * h
-                M[:, i, j] = s[:, i] * s[:, j] * acc * vol / (9.0 * vol ** 2)
-        return M
+        c0 = np.einsum("ab,tab->t", I, Gr)
+        rs = Gr.sum(axis=2)                                  # sum_b Gr_ib
+        acc = (c0[:, None, None] - 0.25 * (rs[:, None, :] + rs[:, :, None]) + Gr) * h * h
+        return s[:, :, None] * s[:, None, :] * acc * (vol / (9.0 * vol ** 2))[:, None, None]
 
     def nd_face_trace_mass(self):
         """Tangential-trace (2D Whitney edge) mass per face, (F, 3, 3), local edges TRI_EDGES."""

@@ -288,9 +288,6 @@ def batched_mass(cells2d, idx, mats, dofs2d):
     return np.bincount(flat.reshape(-1), weights=w.reshape(-1), minlength=nb * nd * nd).reshape(nb, nd, nd)
 
 
-_MIX = np.random.default_rng(20210712).integers(1, 2 ** 63, size=1 << 16, dtype=np.uint64) | np.uint64(1)
-
-
 def _unique_rows(*arrays):
     """Indices of the distinct rows of the concatenated per-batch inputs, and the inverse map.
 
@@ -298,24 +295,31 @@ def _unique_rows(*arrays):
     compared element by element, so only bitwise-equal rows are merged.
     """
     nb = arrays[0].shape[0]
-    flat = np.concatenate([np.ascontiguousarray(a, dtype=np.float64).reshape(nb, -1) for a in arrays], axis=1)
-    bits = np.ascontiguousarray(flat).view(np.uint64)
-    mix = np.resize(_MIX, bits.shape[1])
-    with np.errstate(over="ignore"):
-        fp = (bits * mix[None, :]).sum(axis=1, dtype=np.uint64)
+    parts = [np.ascontiguousarray(a, dtype=np.float64).reshape(nb, -1) for a in arrays]
+    # candidate groups from a random projection (rows with equal bits project equally);
+    # membership is then confirmed bit for bit below
+    fp = np.zeros(nb)
+    rng = np.random.default_rng(20210712)
+    for b in parts:
+        fp += b @ rng.standard_normal(b.shape[1])
     _, first, inv = np.unique(fp, return_index=True, return_inverse=True)
     inv = inv.reshape(-1)
-    if np.all(bits == bits[first[inv]]):
+    rep = first[inv]
+    def same(b):
+        bu = b.view(np.uint64)
+        return all(np.array_equal(bu[i:i + 64], bu[rep[i:i + 64]]) for i in range(0, nb, 64))
+    if all(same(b) for b in parts):
         return first, inv
     # fingerprint collision between different rows: fall back to exact byte keys
+    flat = np.concatenate([b.view(np.uint64) for b in parts], axis=1)
     seen, firsts, inv = {}, [], np.empty(nb, dtype=np.int64)
-    for b in range(nb):
-        key = flat[b].tobytes()
+    for r in range(nb):
+        key = flat[r].tobytes()
         j = seen.get(key)
         if j is None:
             j = seen[key] = len(firsts)
-            firsts.append(b)
-        inv[b] = j
+            firsts.append(r)
+        inv[r] = j
     return np.array(firsts, dtype=np.int64), inv
 
 

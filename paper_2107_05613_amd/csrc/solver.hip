@@ -296,9 +296,13 @@ int tune_lanes(const Csr& A, bool incidence, hipStream_t s) {
         if (it != g_tune.end()) return it->second;
     }
     const double avg = A.nrows ? (double)A.nnz() / A.nrows : 0;
-    std::vector<int> cands = {1};
-    for (int K = 2; K <= 32; K *= 2)
-        if (avg >= 2.0 * K) cands.push_back(K);
+    // starting point: long loops per lane on large matrices (bandwidth), more lanes per
+    // row on small ones (latency); then the neighbours K/2, 2K are timed against it
+    auto p2 = [](double v) { return 1 << std::min(5, std::max(0, (int)std::lround(std::log2(std::max(1.0, v))))); };
+    const int k0 = p2(A.nrows >= 65536 ? avg / 16.0 : avg / 6.0);
+    std::vector<int> cands = {k0};
+    for (int K : {k0 / 2, k0 * 2})
+        if (K >= 1 && K <= 32 && avg >= 2.0 * K) cands.push_back(K);
     int best = cands[0];
     if (cands.size() > 1) {
         amge_hierarchy tmp;   // owns the trial buffers
@@ -331,7 +335,7 @@ int tune_lanes(const Csr& A, bool incidence, hipStream_t s) {
             if (verbose())
                 fprintf(stderr, "[amge tune] rows %d nnz %lld avg %.1f K=%d: %.2f us\n", A.nrows, (long long)A.nnz(),
                         avg, K, 1e3 * ms / 5);
-            if (ms < best_ms * 0.97f) {   // prefer the smaller K unless clearly faster
+            if (ms < best_ms * 0.9f) {    // keep the starting point unless clearly faster
                 best_ms = ms;
                 best = K;
             }
