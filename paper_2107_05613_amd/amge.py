@@ -102,6 +102,17 @@ def _ptr(t):
     return t.data_ptr()
 
 
+def _vec(t, n):
+    """Device pointer of a contiguous FP64 CUDA tensor holding at least n entries."""
+    if isinstance(t, int):
+        return t
+    if t.dtype.itemsize != 8 or not t.is_floating_point() or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    if t.numel() < n:
+        raise ValueError(f"tensor holds {t.numel()} entries, need {n}")
+    return t.data_ptr()
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -226,13 +237,16 @@ class Hierarchy:
         return b.value
 
     def vcycle(self, r, z, nrhs=1, stream=None):
-        _check(_lib.amge_vcycle(self._h, _ptr(r), _ptr(z), nrhs, _stream(stream)))
+        """z = B r (one V-cycle) on n_1 x nrhs row-major FP64 device blocks."""
+        n = self.rows[0] * nrhs
+        _check(_lib.amge_vcycle(self._h, _vec(r, n), _vec(z, n), nrhs, _stream(stream)))
 
     def pcg(self, b, x, rtol=1e-8, maxit=500, stop_norm=0, nrhs=1, stream=None):
         """Returns (status, iters[nrhs], relres[nrhs]); status 0 or 1 (not converged)."""
         it = (C.c_int32 * nrhs)()
         rr = (C.c_double * nrhs)()
-        code = _check(_lib.amge_pcg_solve(self._h, _ptr(b), _ptr(x), nrhs, float(rtol), int(maxit),
+        n = self.rows[0] * nrhs
+        code = _check(_lib.amge_pcg_solve(self._h, _vec(b, n), _vec(x, n), nrhs, float(rtol), int(maxit),
                                           int(stop_norm), it, rr, _stream(stream)), allow=(0, 1))
         return code, list(it), list(rr)
 

@@ -1,0 +1,415 @@
+// Batched (multiple right-hand sides) kernels: the V-cycle and PCG on NC columns at once.
+//
+// Vectors are row-major n x NC.  A row of a level matrix is read once for all NC
+// columns: the lanes of a row own disjoint groups of V consecutive columns (V-wide
+// vector loads), so every matrix entry is a broadcast load shared by the row's lanes
+// and each gathered vector row is a contiguous NC-entry segment.  No cross-lane
+// reduction is needed; each lane runs the row's nonzeros sequentially.  The matrix is
+// in plain CSR here (rows contiguous), which suits the broadcast access.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace amge {
+namespace dev {
+
+template <typename T, int V> struct Vec;
+template <> struct Vec<float, 1> { using type = float; };
+template <> struct Vec<float, 2> { using type = float2; };
+template <> struct Vec<float, 4> { using type = float4; };
+template <> struct Vec<double, 1> { using type = double; };
+template <> struct Vec<double, 2> { using type = double2; };
+template <> struct Vec<double, 4> { using type = double4; };
+
+template <typename T, int V>
+struct Pack {
+    T v[V];
+    __device__ __forceinline__ void load(const T* p) {
+        using VT = typename Vec<T, V>::type;
+        const VT w = *reinterpret_cast<const VT*>(p);
+        const T* s = reinterpret_cast<const T*>(&w);
+#pragma unroll
+        for (int i = 0; i < V; ++i) v[i] = s[i];
+    }
+    __device__ __forceinline__ void store(T* p) const {
+        using VT = typename Vec<T, V>::type;
+        VT w;
+        T* s = reinterpret_cast<T*>(&w);
+#pragma unroll
+        for (int i = 0; i < V; ++i) s[i] = v[i];
+        *reinterpret_cast<VT*>(p) = w;
+    }
+};
+
+// Row-major SpMM level operator.  L = NC / V lanes per row (power of two dividing the
+// block), one row per L lanes.  Modes as in Mode (kernels.hpp); yd (SPMV, SPLIT) also
+// receives dinv * y.
+template <typename T, int V, int MODE>
+__global__ void __launch_bounds__(BLOCK)
+k_csr_mm(int n, int L, int NC, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
+         const T* __restrict__ X, const T* __restrict__ B, const T* __restrict__ dinv, T* __restrict__ Y,
+         T* __restrict__ YD, int nsplit, const int* __restrict__ stop) {
+    if (*stop) return;   // every column of the batch has converged
+    const int rows_per_block = BLOCK / L;
+    const int row = xcd_block(blockIdx.x, gridDim.x) * rows_per_block + (int)threadIdx.x / L;
+    if (row >= n) return;
+    const int col = ((int)threadIdx.x % L) * V;
+    Pack<T, V> acc;
+#pragma unroll
+    for (int i = 0; i < V; ++i) acc.v[i] = 0;
+    const int s = rp[row], e = rp[row + 1];
+#pragma unroll 4
+    for (int k = s; k < e; ++k) {
+        const int j = ci[k];
+        const T a = av[k];
+        Pack<T, V> xv;
+        if (MODE == SPLIT) {
+            if (j < nsplit) xv.load(B + (int64_t)j * NC + col);
+            else xv.load(X + (int64_t)(j - nsplit) * NC + col);
+        } else {
+            xv.load(X + (int64_t)j * NC + col);
+        }
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc.v[i] = fma(a, xv.v[i], acc.v[i]);
+    }
+    const int64_t o = (int64_t)row * NC + col;
+    Pack<T, V> out;
+    if (MODE == SPMV || MODE == SPLIT) {
+        acc.store(Y + o);
+        if (YD) {
+            const T d = dinv[row];
+#pragma unroll
+            for (int i = 0; i < V; ++i) out.v[i] = d * acc.v[i];
+            out.store(YD + o);
+        }
+    } else if (MODE == SPMV_ADD) {
+        out.load(Y + o);
+#pragma unroll
+        for (int i = 0; i < V; ++i) out.v[i] += acc.v[i];
+        out.store(Y + o);
+    } else if (MODE == RESID) {
+        Pack<T, V> bv;
+        bv.load(B + o);
+#pragma unroll
+        for (int i = 0; i < V; ++i) out.v[i] = bv.v[i] - acc.v[i];
+        out.store(Y + o);
+    } else {   // JAC
+        Pack<T, V> bv, xv;
+        bv.load(B + o);
+        xv.load(X + o);
+        const T d = dinv[row];
+#pragma unroll
+        for (int i = 0; i < V; ++i) out.v[i] = xv.v[i] + d * (bv.v[i] - acc.v[i]);
+        out.store(Y + o);
+    }
+}
+
+// Y += D X for a signed incidence in CSR (index-only entries, bit 31 = sign).
+template <typename T, int V>
+__global__ void __launch_bounds__(BLOCK)
+k_inc_mm_add(int n, int L, int NC, const int* __restrict__ rp, const uint32_t* __restrict__ ent,
+             const T* __restrict__ X, T* __restrict__ Y, const int* __restrict__ stop) {
+    if (*stop) return;
+    const int rows_per_block = BLOCK / L;
+    const int row = xcd_block(blockIdx.x, gridDim.x) * rows_per_block + (int)threadIdx.x / L;
+    if (row >= n) return;
+    const int col = ((int)threadIdx.x % L) * V;
+    Pack<T, V> acc;
+    acc.load(Y + (int64_t)row * NC + col);
+    for (int k = rp[row]; k < rp[row + 1]; ++k) {
+        const uint32_t w = ent[k];
+        Pack<T, V> xv;
+        xv.load(X + (int64_t)(w & 0x7fffffffu) * NC + col);
+        const bool neg = w >> 31;
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc.v[i] += neg ? -xv.v[i] : xv.v[i];
+    }
+    acc.store(Y + (int64_t)row * NC + col);
+}
+
+// Coarsest level: X = Ainv B, one thread per (row, column); FP64 arithmetic.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK)
+k_coarse_mm(int n, int lg, const double* __restrict__ Ainv, const T* __restrict__ B, T* __restrict__ X,
+            const int* __restrict__ stop) {
+    if (*stop) return;
+    const int NC = 1 << lg;
+    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    if (t >= ((int64_t)n << lg)) return;
+    const int row = (int)(t >> lg), c = (int)(t & (NC - 1));
+    const double* a = Ainv + (int64_t)row * n;
+    double acc = 0;
+    for (int j = 0; j < n; ++j) acc = fma(a[j], (double)B[(int64_t)j * NC + c], acc);
+    X[t] = (T)acc;
+}
+
+// ---------------------------------------------------------------- batched PCG
+// Per-column state, written only by the single-block finalize kernels.
+struct ColState {
+    double delta0, delta, bnorm, relres, pq, rz, rzold, rr, alpha, beta;
+    int iters, done, breakdown, pad;
+};
+
+struct BatchStatus {
+    int it;          // iterations performed so far
+    int all_done;    // every column finished
+    int any_breakdown;
+    int stop_l2;     // 0: preconditioner norm, 1: l2 norm
+    int maxit;
+    int pad;
+    double rtol;
+};
+
+// Per-column partial sums over the rows of a block: the block's threads hold column
+// (tid % NC) sums for row group tid / NC; reduced over row groups through LDS.
+__device__ __forceinline__ void column_partials(double v, int NC, double* sh, double* part, int nblk) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    if ((int)threadIdx.x < NC) {
+        double t = 0;
+        for (int g = threadIdx.x; g < BLOCK; g += NC) t += sh[g];
+        part[(int64_t)threadIdx.x * nblk + blockIdx.x] = t;
+    }
+    __syncthreads();
+}
+
+// Q = A P (FP64 CSR, one column per thread) and partial p.q per column.  Grid-stride
+// over row groups; NC must divide BLOCK.
+__global__ void __launch_bounds__(BLOCK)
+k_bpcg_ap(int n, int NC, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
+          const double* __restrict__ P, double* __restrict__ Q, double* __restrict__ part,
+          const BatchStatus* __restrict__ bs) {
+    __shared__ double sh[BLOCK];
+    if (bs->all_done) return;
+    const int rpb = BLOCK / NC;
+    const int c = threadIdx.x % NC;
+    double dot = 0;
+    for (int row = blockIdx.x * rpb + threadIdx.x / NC; row < n; row += gridDim.x * rpb) {
+        double acc = 0;
+        for (int k = rp[row]; k < rp[row + 1]; ++k) acc = fma(av[k], P[(int64_t)ci[k] * NC + c], acc);
+        Q[(int64_t)row * NC + c] = acc;
+        dot = fma(P[(int64_t)row * NC + c], acc, dot);
+    }
+    column_partials(dot, NC, sh, part, gridDim.x);
+}
+
+// Per-column totals of nq quantities from their block partials, stored at
+// part[(q * NC + c) * nblk + block]: one wave per (q, c), fixed summation order
+// (strided lane sums, then the butterfly).  Results in sh[q * NC + c].
+__device__ __forceinline__ void col_totals(const double* __restrict__ part, int nblk, int nq, int NC, double* sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int qc = wave; qc < nq * NC; qc += WAVES) {
+        const double* p = part + (int64_t)qc * nblk;
+        double t = 0;
+        for (int i = lane; i < nblk; i += 64) t += p[i];
+        t = wave_sum(t);
+        if (lane == 0) sh[qc] = t;
+    }
+    __syncthreads();
+}
+
+// alpha_c = delta_c / pq_c for live columns (breakdown if pq_c <= 0).  One block.
+__global__ void __launch_bounds__(BLOCK)
+k_bpcg_alpha(int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
+             BatchStatus* __restrict__ bs) {
+    __shared__ double sh[64];
+    if (bs->all_done) return;
+    col_totals(part, nblk, 1, NC, sh);
+    const int c = threadIdx.x;
+    if (c < NC) {
+        ColState& s = cs[c];
+        const double pq = sh[c];
+        s.pq = pq;
+        if (s.done) s.alpha = 0;
+        else if (!(pq > 0) || !isfinite(pq)) {
+            s.alpha = 0;
+            s.breakdown = 1;
+            s.done = 1;
+        } else s.alpha = s.delta / pq;
+    }
+}
+
+// X += alpha P, R -= alpha Q per column; R32 = (float) R, RD32 = dinv32 * R32 (FP32
+// preconditioner) or RD64 = dinv64 * R (FP64 preconditioner).
+__global__ void __launch_bounds__(BLOCK)
+k_bpcg_xr(int64_t nn, int lg, const ColState* __restrict__ cs, const double* __restrict__ P,
+          const double* __restrict__ Q, double* __restrict__ X, double* __restrict__ R, float* __restrict__ R32,
+          float* __restrict__ RD32, const float* __restrict__ dinv32, double* __restrict__ RD64,
+          const double* __restrict__ dinv64, const BatchStatus* __restrict__ bs) {
+    if (bs->all_done) return;
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < nn; t += (int64_t)gridDim.x * BLOCK) {
+        const int c = (int)(t & ((1 << lg) - 1));
+        const double a = cs[c].alpha;
+        double r = R[t];
+        if (a != 0) {
+            X[t] = fma(a, P[t], X[t]);
+            r = fma(-a, Q[t], r);
+            R[t] = r;
+        }
+        const int64_t row = t >> lg;
+        if (R32) {
+            const float rf = (float)r;
+            R32[t] = rf;
+            if (RD32) RD32[t] = dinv32[row] * rf;
+        }
+        if (RD64) RD64[t] = dinv64[row] * r;
+    }
+}
+
+// Z = Zv (widened) after using the old Z: partials of r.z_new, r.z_old, r.r per column.
+template <typename TZ>
+__global__ void __launch_bounds__(BLOCK)
+k_bpcg_dots(int n, int NC, const TZ* __restrict__ Zv, double* __restrict__ Z, const double* __restrict__ R,
+            double* __restrict__ part, const BatchStatus* __restrict__ bs) {
+    __shared__ double sh[BLOCK];
+    if (bs->all_done) return;
+    const int rpb = BLOCK / NC;
+    const int c = threadIdx.x % NC;
+    double a = 0, b = 0, d = 0;
+    for (int row = blockIdx.x * rpb + threadIdx.x / NC; row < n; row += gridDim.x * rpb) {
+        const int64_t t = (int64_t)row * NC + c;
+        const double zn = (double)Zv[t], zo = Z[t], r = R[t];
+        Z[t] = zn;
+        a = fma(r, zn, a);
+        b = fma(r, zo, b);
+        d = fma(r, r, d);
+    }
+    const int nb = gridDim.x;
+    column_partials(a, NC, sh, part, nb);
+    column_partials(b, NC, sh, part + (int64_t)NC * nb, nb);
+    column_partials(d, NC, sh, part + (int64_t)2 * NC * nb, nb);
+}
+
+// Per-column stopping test and beta (one block).  init = 1: first call after z_0 = B r_0
+// (sets delta0 and bnorm; zero right-hand sides are finished with 0 iterations).
+__global__ void __launch_bounds__(BLOCK)
+k_bpcg_update(int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
+              BatchStatus* __restrict__ bs, int init) {
+    __shared__ double sh[3 * 64];
+    __shared__ int flags[2 * 64];
+    if (!init && bs->all_done) return;
+    col_totals(part, nblk, 3, NC, sh);
+    const double rtol = bs->rtol;
+    const int stop_l2 = bs->stop_l2, maxit = bs->maxit;
+    const int c = threadIdx.x;
+    if (c < NC) {
+        ColState& s = cs[c];
+        const double rz = sh[c], rzo = sh[NC + c], rr = sh[2 * NC + c];
+        if (init) {
+            s.delta0 = rz;
+            s.delta = rz;
+            s.bnorm = sqrt(rr);
+            s.rr = rr;
+            s.rz = rz;
+            s.rzold = 0;
+            s.relres = 1.0;
+            s.iters = 0;
+            s.breakdown = 0;
+            s.alpha = 0;
+            s.beta = 0;
+            s.done = 0;
+            if (rr == 0) {
+                s.done = 1;
+                s.relres = 0;
+            } else if (!(rz > 0) || !isfinite(rz) || !isfinite(rr)) {
+                s.breakdown = !(rz > 0) && isfinite(rz) && isfinite(rr);
+                s.done = 1;
+            }
+        } else if (!s.done) {
+            s.rz = rz;
+            s.rzold = rzo;
+            s.rr = rr;
+            s.iters = bs->it + 1;
+            const double rel = stop_l2 ? sqrt(rr) / s.bnorm : sqrt(fmax(rz, 0.0) / s.delta0);
+            s.relres = rel;
+            if ((rtol > 0 && rel <= rtol) || s.iters >= maxit || !isfinite(rz)) {
+                s.done = 1;
+                s.beta = 0;
+            } else {
+                s.beta = (rz - rzo) / s.delta;
+                s.delta = rz;
+            }
+        }
+        flags[c] = s.done;
+        flags[64 + c] = s.breakdown;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int live = 0, brk = 0;
+        for (int j = 0; j < NC; ++j) {
+            live += flags[j] ? 0 : 1;
+            brk |= flags[64 + j];
+        }
+        if (!init) bs->it += 1;
+        bs->all_done = live == 0;
+        bs->any_breakdown = brk;
+    }
+}
+
+// P = Z + beta P for live columns (P = Z on the first call).
+__global__ void __launch_bounds__(BLOCK)
+k_bpcg_p(int64_t nn, int lg, const ColState* __restrict__ cs, const double* __restrict__ Z, double* __restrict__ P,
+         const BatchStatus* __restrict__ bs, int init) {
+    if (!init && bs->all_done) return;
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < nn; t += (int64_t)gridDim.x * BLOCK) {
+        const int c = (int)(t & ((1 << lg) - 1));
+        if (init) P[t] = Z[t];
+        else if (!cs[c].done) P[t] = fma(cs[c].beta, P[t], Z[t]);
+    }
+}
+
+// Caller layout n x nrhs (FP64) -> internal n x NC of type T, extra columns zero;
+// optionally BD = dinv[row] * B (the first l1-Jacobi sweep from zero).
+template <typename T>
+__global__ void __launch_bounds__(BLOCK)
+k_pack(int64_t n, int nrhs, int lg, const double* __restrict__ src, const T* __restrict__ dinv, T* __restrict__ B,
+       T* __restrict__ BD) {
+    const int NC = 1 << lg;
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < (n << lg); t += (int64_t)gridDim.x * BLOCK) {
+        const int c = (int)(t & (NC - 1));
+        const int64_t row = t >> lg;
+        const T v = c < nrhs ? (T)src[row * nrhs + c] : (T)0;
+        B[t] = v;
+        if (BD) BD[t] = dinv[row] * v;
+    }
+}
+
+// Internal n x NC (type T) -> caller layout n x nrhs (FP64).
+template <typename T>
+__global__ void __launch_bounds__(BLOCK)
+k_unpack(int64_t n, int nrhs, int lg, const T* __restrict__ src, double* __restrict__ dst) {
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < n * nrhs; t += (int64_t)gridDim.x * BLOCK)
+        dst[t] = (double)src[((t / nrhs) << lg) + t % nrhs];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK)
+k_fill(int64_t n, T* __restrict__ x, const int* __restrict__ stop) {
+    if (*stop) return;
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLOCK) x[t] = (T)0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK)
+k_copy(int64_t n, const T* __restrict__ a, T* __restrict__ b, const int* __restrict__ stop) {
+    if (*stop) return;
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLOCK) b[t] = a[t];
+}
+
+// Row scaling of an n x NC block: Y = dinv[row] * (D) X, and Xc = (D) X if given.
+template <typename S, typename D>
+__global__ void __launch_bounds__(BLOCK)
+k_scale_rows(int64_t n, int lg, const S* __restrict__ X, const D* __restrict__ dinv, D* __restrict__ Y,
+             D* __restrict__ Xc) {
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < (n << lg); t += (int64_t)gridDim.x * BLOCK) {
+        const D v = (D)X[t];
+        if (Xc) Xc[t] = v;
+        Y[t] = dinv[t >> lg] * v;
+    }
+}
+
+}  // namespace dev
+}  // namespace amge

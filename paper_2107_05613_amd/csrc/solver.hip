@@ -16,6 +16,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "kernels_batched.hpp"
 
 namespace amge {
 
@@ -60,6 +61,18 @@ struct Probe {
     }
 };
 
+// CSR matrix on the device for the batched (several right-hand sides) kernels.
+struct DCsrB {
+    int nrows = 0, ncols = 0;
+    int64_t nnz = 0;
+    int* rp = nullptr;
+    int* ci = nullptr;         // value matrices
+    uint32_t* ent = nullptr;   // incidence matrices: column | sign << 31
+    double* v64 = nullptr;
+    float* v32 = nullptr;
+    int V = 1;                 // columns per lane (vector width), tuned
+};
+
 struct DLevel {
     int n = 0, m = 0;
     Probe* probe = nullptr;
@@ -68,10 +81,18 @@ struct DLevel {
     DSell D, Dt;              // signed incidences
     Work<float> w32;
     Work<double> w64;
+    // batched path (max_rhs > 1): CSR copies and n x NC work buffers of the
+    // preconditioner precision
+    DCsrB bA, bAh, bP, bPt, bAux, bD;
+    Work<float> bw32;
+    Work<double> bw64;
     template <class T> Work<T>& w();
+    template <class T> Work<T>& bw();
 };
 template <> Work<float>& DLevel::w<float>() { return w32; }
 template <> Work<double>& DLevel::w<double>() { return w64; }
+template <> Work<float>& DLevel::bw<float>() { return bw32; }
+template <> Work<double>& DLevel::bw<double>() { return bw64; }
 
 }  // namespace amge
 
@@ -85,10 +106,25 @@ struct amge_hierarchy {
     double *part_pq = nullptr, *part_dots[2] = {nullptr, nullptr};
     amge::dev::PcgStatus* st = nullptr;
     int* flags = nullptr;        // [0] done, [1] breakdown
+    // batched PCG (NC = max_rhs rounded up to a power of two, columns beyond nrhs are zero)
+    int NC = 1, lgNC = 0;
+    double *bX = nullptr, *bR = nullptr, *bP = nullptr, *bQ = nullptr, *bZ = nullptr, *bZv = nullptr;
+    double* bpart = nullptr;
+    int bnblk = 0;
+    amge::dev::ColState* cs = nullptr;
+    amge::dev::BatchStatus* bs = nullptr;
+    int* zero_flag = nullptr;    // a device 0 for batched kernels run outside PCG
+    hipStream_t gstream = nullptr;   // stream for graph capture / replay
+    hipGraphExec_t gexec = nullptr;  // one captured batched PCG iteration
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<void*> allocs;
     size_t bytes = 0;
     amge::Probe probe;
     ~amge_hierarchy() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (gstream) (void)hipStreamDestroy(gstream);
         for (void* a : allocs) (void)hipFree(a);
     }
     template <class T>
@@ -486,6 +522,250 @@ void precondition(amge_hierarchy* H, const double* r, double* z, hipStream_t s) 
     }
 }
 
+// ------------------------------------------------------------------ batched path
+constexpr int BPCG_BLOCKS = 512;   // blocks of the per-column dot products
+constexpr int BPCG_CHUNK = 4;      // graph replays between status polls
+// Several right-hand sides at once (n x NC row-major blocks, NC a power of two): every
+// level operator is one CSR SpMM launch whose lanes own V consecutive columns of a
+// row.  V is tuned per matrix at set-up.
+template <class T> const T* bvals(const DCsrB& M);
+template <> const float* bvals<float>(const DCsrB& M) { return M.v32; }
+template <> const double* bvals<double>(const DCsrB& M) { return M.v64; }
+
+DCsrB upload_csr_b(amge_hierarchy* H, const Csr& A, bool incidence, bool f32, bool f64, hipStream_t s) {
+    DCsrB M;
+    M.nrows = A.nrows;
+    M.ncols = A.ncols;
+    M.nnz = A.nnz();
+    M.rp = upload(H, A.rowptr.data(), A.rowptr.size(), s);
+    if (incidence) {
+        std::vector<uint32_t> e(A.col.size());
+        for (size_t k = 0; k < e.size(); ++k) e[k] = (uint32_t)A.col[k] | (A.val[k] < 0 ? 0x80000000u : 0u);
+        M.ent = upload(H, e.data(), e.size(), s);
+    } else {
+        M.ci = upload(H, A.col.data(), A.col.size(), s);
+        if (f64) M.v64 = upload(H, A.val.data(), A.val.size(), s);
+        if (f32) {
+            std::vector<float> v(A.val.begin(), A.val.end());
+            M.v32 = upload(H, v.data(), v.size(), s);
+        }
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+    return M;
+}
+
+template <class T, int V, int MODE>
+void csr_mm_v(const DCsrB& M, int NC, const T* X, const T* B, const T* dinv, T* Y, T* YD, int nsplit,
+              const int* stop, hipStream_t s) {
+    const int L = NC / V;
+    const int rpb = BLOCK / L;
+    const unsigned grid = (unsigned)((M.nrows + rpb - 1) / rpb);
+    if (grid)
+        dev::k_csr_mm<T, V, MODE><<<grid, BLOCK, 0, s>>>(M.nrows, L, NC, M.rp, M.ci, bvals<T>(M), X, B, dinv, Y, YD,
+                                                         nsplit, stop);
+}
+
+template <class T, int V>
+void csr_mm_m(const DCsrB& M, int mode, int NC, const T* X, const T* B, const T* dinv, T* Y, T* YD, int nsplit,
+              const int* stop, hipStream_t s) {
+    switch (mode) {
+        case dev::SPMV: csr_mm_v<T, V, dev::SPMV>(M, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case dev::SPMV_ADD: csr_mm_v<T, V, dev::SPMV_ADD>(M, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case dev::RESID: csr_mm_v<T, V, dev::RESID>(M, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case dev::JAC: csr_mm_v<T, V, dev::JAC>(M, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case dev::SPLIT: csr_mm_v<T, V, dev::SPLIT>(M, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        default: fail(AMGE_ERR_ARG, "bad SpMM mode");
+    }
+}
+
+template <class T>
+void csr_mm(const DCsrB& M, int mode, int NC, const T* X, const T* B, const T* dinv, T* Y, const int* stop,
+            hipStream_t s, int nsplit = 0, T* YD = nullptr) {
+    switch (M.V) {
+        case 1: csr_mm_m<T, 1>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case 2: csr_mm_m<T, 2>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        default: csr_mm_m<T, 4>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+    }
+}
+
+template <class T, int V>
+void inc_mm_v(const DCsrB& M, int NC, const T* X, T* Y, const int* stop, hipStream_t s) {
+    const int L = NC / V;
+    const int rpb = BLOCK / L;
+    const unsigned grid = (unsigned)((M.nrows + rpb - 1) / rpb);
+    if (grid) dev::k_inc_mm_add<T, V><<<grid, BLOCK, 0, s>>>(M.nrows, L, NC, M.rp, M.ent, X, Y, stop);
+}
+
+template <class T>
+void inc_mm_add(const DCsrB& M, int NC, const T* X, T* Y, const int* stop, hipStream_t s) {
+    switch (M.V) {
+        case 1: inc_mm_v<T, 1>(M, NC, X, Y, stop, s); break;
+        case 2: inc_mm_v<T, 2>(M, NC, X, Y, stop, s); break;
+        default: inc_mm_v<T, 4>(M, NC, X, Y, stop, s); break;
+    }
+}
+
+inline unsigned grid_stride(int64_t threads) { return (unsigned)std::min<int64_t>(grid_for(threads), 4096); }
+
+template <class T>
+void bfill(int64_t n, T* x, const int* stop, hipStream_t s) {
+    if (n) dev::k_fill<T><<<grid_stride(n), BLOCK, 0, s>>>(n, x, stop);
+}
+
+template <class T>
+void bcopy(int64_t n, const T* a, T* b, const int* stop, hipStream_t s) {
+    if (n) dev::k_copy<T><<<grid_stride(n), BLOCK, 0, s>>>(n, a, b, stop);
+}
+
+// Columns per lane V for one matrix and block width NC: the default (16-byte lane
+// loads) is timed against the other widths with HIP events and replaced only by a
+// clearly faster one.  Cached per matrix shape, width and precision.
+struct BTuneKey {
+    int nrows, ncols;
+    int64_t nnz;
+    int inc, NC, bits;
+    bool operator<(const BTuneKey& o) const {
+        return std::tie(nrows, ncols, nnz, inc, NC, bits) < std::tie(o.nrows, o.ncols, o.nnz, o.inc, o.NC, o.bits);
+    }
+};
+static std::map<BTuneKey, int> g_btune;
+
+template <class T>
+int tune_cols(DCsrB& M, bool incidence, int NC, T* X, T* Y, const int* stop, hipStream_t s) {
+    BTuneKey key{M.nrows, M.ncols, M.nnz, incidence ? 1 : 0, NC, (int)(8 * sizeof(T))};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_btune.find(key);
+        if (it != g_btune.end()) return it->second;
+    }
+    const int v0 = std::min(NC, (int)(16 / sizeof(T)));
+    std::vector<int> cands = {v0};
+    for (int V : {1, 2, 4})
+        if (V != v0 && V <= NC) cands.push_back(V);
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    int best = v0;
+    float best_ms = 1e30f;
+    for (int V : cands) {
+        M.V = V;
+        auto run = [&]() {
+            if (incidence) inc_mm_add<T>(M, NC, X, Y, stop, s);
+            else csr_mm<T>(M, dev::SPMV, NC, X, nullptr, nullptr, Y, stop, s);
+        };
+        run();
+        float ms = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCHECK(hipEventRecord(e0, s));
+            for (int i = 0; i < 3; ++i) run();
+            HIPCHECK(hipEventRecord(e1, s));
+            HIPCHECK(hipEventSynchronize(e1));
+            float t = 0;
+            HIPCHECK(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, t);
+        }
+        HIPCHECK(hipGetLastError());
+        if (verbose())
+            fprintf(stderr, "[amge tune-mm] rows %d nnz %lld NC %d fp%d V=%d: %.2f us\n", M.nrows, (long long)M.nnz, NC,
+                    (int)(8 * sizeof(T)), V, 1e3 * ms / 3);
+        if (V == v0 || ms < best_ms * 0.9f) {   // keep the default unless clearly faster
+            best_ms = ms;
+            best = V;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    M.V = best;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_btune[key] = best;
+    return best;
+}
+
+// ---- batched smoother and V-cycle: the single-column steps on n x NC blocks; every
+// kernel returns at once when *stop is set (all columns of a PCG batch converged).
+template <class T>
+void bprimary(amge_hierarchy* H, DLevel& L, const T* b, const T* bd, T*& x, T*& xt, bool from_zero, int nu,
+              const int* stop, hipStream_t s) {
+    Work<T>& w = L.bw<T>();
+    const int NC = H->NC;
+    int k = 0;
+    if (from_zero) {
+        if (nu >= 2) {
+            csr_mm<T>(L.bA, dev::JAC, NC, bd, b, w.dinv, x, stop, s);
+            k = 2;
+        } else if (nu == 1) {
+            bcopy<T>((int64_t)L.n * NC, bd, x, stop, s);
+            k = 1;
+        } else {
+            bfill<T>((int64_t)L.n * NC, x, stop, s);
+        }
+    }
+    for (; k < nu; ++k) {
+        csr_mm<T>(L.bA, dev::JAC, NC, x, b, w.dinv, xt, stop, s);
+        std::swap(x, xt);
+    }
+}
+
+template <class T>
+void bauxiliary(amge_hierarchy* H, DLevel& L, const T* b, T* x, int nu, const int* stop, hipStream_t s) {
+    if (nu <= 0 || L.m == 0) return;
+    Work<T>& w = L.bw<T>();
+    const int NC = H->NC;
+    csr_mm<T>(L.bAux, dev::SPLIT, NC, x, b, w.dhinv, w.g, stop, s, L.n, w.gd);
+    const T* y = w.gd;
+    T* ya = w.y;
+    T* yb = w.yt;
+    for (int k = 1; k < nu; ++k) {
+        csr_mm<T>(L.bAh, dev::JAC, NC, y, w.g, w.dhinv, ya, stop, s);
+        y = ya;
+        std::swap(ya, yb);
+    }
+    inc_mm_add<T>(L.bD, NC, y, x, stop, s);
+}
+
+template <class T>
+void bvcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, const int* stop, hipStream_t s) {
+    const int nl = (int)H->lv.size();
+    const int NC = H->NC;
+    if (l == nl - 1) {
+        const int64_t t = (int64_t)H->nc * NC;
+        dev::k_coarse_mm<T><<<grid_for(t), BLOCK, 0, s>>>(H->nc, H->lgNC, H->Ainv, b, xout, stop);
+        return;
+    }
+    DLevel& L = H->lv[l];
+    DLevel& C = H->lv[l + 1];
+    Work<T>& w = L.bw<T>();
+    Work<T>& wc = C.bw<T>();
+    T* x = xout;
+    T* xt = w.xt;
+    const int nup = H->opts.nu_primary, nua = H->opts.nu_aux;
+    const bool next_coarsest = l + 1 == nl - 1;
+    bprimary<T>(H, L, b, bd, x, xt, true, nup, stop, s);
+    bauxiliary<T>(H, L, b, x, nua, stop, s);
+    csr_mm<T>(L.bA, dev::RESID, NC, x, b, nullptr, w.r, stop, s);
+    csr_mm<T>(L.bPt, dev::SPMV, NC, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, stop, s, 0,
+              next_coarsest ? nullptr : wc.bd);
+    bvcycle_level<T>(H, l + 1, wc.b, wc.bd, wc.x, stop, s);
+    csr_mm<T>(L.bP, dev::SPMV_ADD, NC, wc.x, nullptr, nullptr, x, stop, s);
+    bauxiliary<T>(H, L, b, x, nua, stop, s);
+    bprimary<T>(H, L, b, nullptr, x, xt, false, nup, stop, s);
+    if (x != xout) bcopy<T>((int64_t)L.n * NC, x, xout, stop, s);
+}
+
+// Batched V-cycle on the caller's n x nrhs FP64 block.
+template <class T>
+void bprecondition(amge_hierarchy* H, const double* r, double* z, int nrhs, hipStream_t s) {
+    DLevel& L = H->lv[0];
+    Work<T>& w = L.bw<T>();
+    const int64_t n = L.n;
+    const bool ml = H->lv.size() > 1;
+    dev::k_pack<T><<<grid_stride(n * H->NC), BLOCK, 0, s>>>(n, nrhs, H->lgNC, r, ml ? w.dinv : nullptr, w.b,
+                                                           ml ? w.bd : nullptr);
+    bvcycle_level<T>(H, 0, w.b, w.bd, w.x, H->zero_flag, s);
+    dev::k_unpack<T><<<grid_stride(n * nrhs), BLOCK, 0, s>>>(n, nrhs, H->lgNC, w.x, z);
+}
+
+
 // ------------------------------------------------------------------ set-up
 void build_coarse(amge_hierarchy* H, const Csr& A, hipStream_t s) {
     int n = A.nrows;
@@ -537,7 +817,7 @@ void build_coarse(amge_hierarchy* H, const Csr& A, hipStream_t s) {
 template <class T>
 void alloc_work(amge_hierarchy* H, DLevel& L, Work<T>& w, const std::vector<double>& dinv,
                 const std::vector<double>& dhinv, hipStream_t s) {
-    size_t nr = (size_t)L.n * H->opts.max_rhs, mr = (size_t)L.m * H->opts.max_rhs;
+    size_t nr = (size_t)L.n, mr = (size_t)L.m;
     w.b = H->alloc<T>(nr);
     w.x = H->alloc<T>(nr);
     w.xt = H->alloc<T>(nr);
@@ -551,6 +831,100 @@ void alloc_work(amge_hierarchy* H, DLevel& L, Work<T>& w, const std::vector<doub
     w.dinv = upload(H, a.data(), a.size(), s);
     w.dhinv = upload(H, c.data(), c.size(), s);
     HIPCHECK(hipStreamSynchronize(s));
+}
+
+// Batched work block of one level (n x NC, m x NC) in the preconditioner precision;
+// the l1 scalings are shared with the single-column buffers.
+template <class T>
+void alloc_bwork(amge_hierarchy* H, DLevel& L, const Work<T>& w1, Work<T>& w) {
+    const size_t nr = (size_t)L.n * H->NC, mr = (size_t)L.m * H->NC;
+    w.b = H->alloc<T>(nr);
+    w.x = H->alloc<T>(nr);
+    w.xt = H->alloc<T>(nr);
+    w.r = H->alloc<T>(nr);
+    w.bd = H->alloc<T>(nr);
+    if (mr) {
+        w.g = H->alloc<T>(mr);
+        w.y = H->alloc<T>(mr);
+        w.yt = H->alloc<T>(mr);
+        w.gd = H->alloc<T>(mr);
+    }
+    w.dinv = w1.dinv;
+    w.dhinv = w1.dhinv;
+}
+
+// Level matrices kept on the host during set-up for the batched uploads.
+struct HostLevel {
+    Csr A, Ah, P, Pt, Aux, D;
+};
+
+template <class T>
+void tune_batched(amge_hierarchy* H, hipStream_t s) {
+    size_t mx = 0, my = 0;
+    for (DLevel& L : H->lv)
+        for (DCsrB* M : {&L.bA, &L.bAh, &L.bP, &L.bPt, &L.bAux, &L.bD})
+            if (M->nrows) {
+                mx = std::max(mx, (size_t)M->ncols * H->NC);
+                my = std::max(my, (size_t)M->nrows * H->NC);
+            }
+    if (!mx) return;
+    amge_hierarchy tmp;   // owns the trial buffers
+    T* X = tmp.alloc<T>(mx);
+    T* Y = tmp.alloc<T>(my);
+    HIPCHECK(hipMemsetAsync(X, 0, sizeof(T) * mx, s));
+    HIPCHECK(hipMemsetAsync(Y, 0, sizeof(T) * my, s));
+    for (DLevel& L : H->lv) {
+        for (DCsrB* M : {&L.bA, &L.bAh, &L.bP, &L.bPt, &L.bAux})
+            if (M->nrows) tune_cols<T>(*M, false, H->NC, X, Y, H->zero_flag, s);
+        if (L.bD.nrows) tune_cols<T>(L.bD, true, H->NC, X, Y, H->zero_flag, s);
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+void setup_batched(amge_hierarchy* H, const std::vector<HostLevel>& hl, hipStream_t s) {
+    int NC = 2, lg = 1;
+    while (NC < H->opts.max_rhs) {
+        NC *= 2;
+        ++lg;
+    }
+    H->NC = NC;
+    H->lgNC = lg;
+    const bool f32 = H->opts.precond_bits == 32;
+    const int nl = (int)H->lv.size();
+    H->zero_flag = H->alloc<int>(1);
+    HIPCHECK(hipMemsetAsync(H->zero_flag, 0, sizeof(int), s));
+    for (int k = 0; k < nl; ++k) {
+        DLevel& L = H->lv[k];
+        const HostLevel& h = hl[k];
+        if (k < nl - 1 || nl == 1) {
+            // A_1 is also the outer PCG operator (FP64)
+            L.bA = upload_csr_b(H, h.A, false, f32, !f32 || k == 0, s);
+        }
+        if (k < nl - 1) {
+            L.bAh = upload_csr_b(H, h.Ah, false, f32, !f32, s);
+            L.bP = upload_csr_b(H, h.P, false, f32, !f32, s);
+            L.bPt = upload_csr_b(H, h.Pt, false, f32, !f32, s);
+            L.bAux = upload_csr_b(H, h.Aux, false, f32, !f32, s);
+            L.bD = upload_csr_b(H, h.D, true, false, false, s);
+        }
+        if (f32 && nl > 1) alloc_bwork<float>(H, L, L.w32, L.bw32);
+        else alloc_bwork<double>(H, L, L.w64, L.bw64);
+    }
+    const size_t nn = (size_t)H->lv[0].n * NC;
+    H->bX = H->alloc<double>(nn);
+    H->bR = H->alloc<double>(nn);
+    H->bP = H->alloc<double>(nn);
+    H->bQ = H->alloc<double>(nn);
+    H->bZ = H->alloc<double>(nn);
+    H->bZv = H->alloc<double>(nn);
+    H->bpart = H->alloc<double>((size_t)3 * NC * BPCG_BLOCKS);
+    H->cs = H->alloc<dev::ColState>(NC);
+    H->bs = H->alloc<dev::BatchStatus>(1);
+    HIPCHECK(hipStreamCreateWithFlags(&H->gstream, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&H->ev_in, hipEventDisableTiming));
+    HIPCHECK(hipEventCreateWithFlags(&H->ev_out, hipEventDisableTiming));
+    if (f32 && nl > 1) tune_batched<float>(H, s);
+    else tune_batched<double>(H, s);
 }
 
 void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
@@ -568,9 +942,12 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         }
     }
     H->lv.resize(nl);
+    const bool batched = H->opts.max_rhs > 1;
+    std::vector<HostLevel> hl(batched ? nl : 0);
     for (int k = 0; k < nl; ++k) {
         DLevel& L = H->lv[k];
         L.n = A[k].nrows;
+        if (batched) hl[k].A = A[k];
         if (k == nl - 1) {
             build_coarse(H, A[k], s);
             std::vector<double> none;
@@ -613,6 +990,13 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
                 X.rowptr[i + 1] = (int32_t)X.col.size();
             }
             L.Aux = upload_tuned(H, X, false, s);
+            if (batched) {
+                hl[k].Ah = Ah;
+                hl[k].P = P[k];
+                hl[k].Pt = transpose(P[k]);
+                hl[k].Aux = std::move(X);
+                hl[k].D = D[k];
+            }
         }
         alloc_work<float>(H, L, L.w32, dinv, dhinv, s);
         alloc_work<double>(H, L, L.w64, dinv, dhinv, s);
@@ -621,7 +1005,7 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         // the fine matrix itself is needed by the outer PCG even on one level
         H->lv[0].A = upload_tuned(H, A[0], false, s);
     }
-    size_t n1 = (size_t)H->lv[0].n * H->opts.max_rhs;
+    size_t n1 = (size_t)H->lv[0].n;
     H->r = H->alloc<double>(n1);
     H->p = H->alloc<double>(n1);
     H->q = H->alloc<double>(n1);
@@ -632,6 +1016,7 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     H->part_dots[1] = H->alloc<double>(3 * dev::NRED);
     H->st = H->alloc<dev::PcgStatus>(1);
     H->flags = H->alloc<int>(2);
+    if (batched) setup_batched(H, hl, s);
     HIPCHECK(hipStreamSynchronize(s));
 }
 
@@ -726,6 +1111,139 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
     return AMGE_OK;
 }
 
+// ---- batched inexact PCG: the single-column recurrences per column, with the
+// stopping test per column on the device (a finished column gets alpha = beta = 0 and
+// keeps its iterate).  One iteration is captured once as a HIP graph on the hierarchy's
+// own stream and replayed in chunks; the host polls the batch status between chunks.
+
+void bpcg_ap(amge_hierarchy* H, hipStream_t s) {
+    const DCsrB& A = H->lv[0].bA;
+    dev::k_bpcg_ap<<<BPCG_BLOCKS, BLOCK, 0, s>>>(A.nrows, H->NC, A.rp, A.ci, A.v64, H->bP, H->bQ, H->bpart, H->bs);
+}
+
+// z = B r for the batched PCG: the V-cycle (or the coarse solve on a one-level
+// hierarchy) in the preconditioner precision on the residual block; writes zv.
+// The FP32 V-cycle reads its input from the level-1 FP32 block; a one-level hierarchy
+// (coarse solve only) always works in FP64, like the single-column path.
+bool bz32(const amge_hierarchy* H) { return H->opts.precond_bits == 32 && H->lv.size() > 1; }
+
+void bpcg_precond(amge_hierarchy* H, const int* stop, hipStream_t s) {
+    DLevel& L = H->lv[0];
+    if (bz32(H)) bvcycle_level<float>(H, 0, L.bw32.b, L.bw32.bd, L.bw32.x, stop, s);
+    else bvcycle_level<double>(H, 0, H->bR, L.bw64.bd, H->bZv, stop, s);
+}
+
+void bpcg_dots(amge_hierarchy* H, hipStream_t s) {
+    DLevel& L = H->lv[0];
+    const int n = L.n;
+    if (bz32(H))
+        dev::k_bpcg_dots<float><<<BPCG_BLOCKS, BLOCK, 0, s>>>(n, H->NC, L.bw32.x, H->bZ, H->bR, H->bpart, H->bs);
+    else
+        dev::k_bpcg_dots<double><<<BPCG_BLOCKS, BLOCK, 0, s>>>(n, H->NC, H->bZv, H->bZ, H->bR, H->bpart, H->bs);
+}
+
+// One PCG iteration (the captured body): q = A p, alpha, x/r update with the next
+// preconditioner input, z = B r, dots, stopping test and beta, p update.
+void bpcg_iteration(amge_hierarchy* H, hipStream_t s) {
+    DLevel& L = H->lv[0];
+    const int64_t nn = (int64_t)L.n * H->NC;
+    const bool f32 = bz32(H);
+    const bool ml = H->lv.size() > 1;
+    const unsigned g = grid_stride(nn);
+    bpcg_ap(H, s);
+    dev::k_bpcg_alpha<<<1, BLOCK, 0, s>>>(H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
+    dev::k_bpcg_xr<<<g, BLOCK, 0, s>>>(nn, H->lgNC, H->cs, H->bP, H->bQ, H->bX, H->bR, f32 ? L.bw32.b : nullptr,
+                                       f32 ? L.bw32.bd : nullptr, f32 ? L.bw32.dinv : nullptr,
+                                       !f32 && ml ? L.bw64.bd : nullptr, !f32 && ml ? L.bw64.dinv : nullptr, H->bs);
+    bpcg_precond(H, &H->bs->all_done, s);
+    bpcg_dots(H, s);
+    dev::k_bpcg_update<<<1, BLOCK, 0, s>>>(H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs, 0);
+    dev::k_bpcg_p<<<g, BLOCK, 0, s>>>(nn, H->lgNC, H->cs, H->bZ, H->bP, H->bs, 0);
+}
+
+void capture_iteration(amge_hierarchy* H) {
+    hipGraph_t graph = nullptr;
+    HIPCHECK(hipStreamBeginCapture(H->gstream, hipStreamCaptureModeThreadLocal));
+    bpcg_iteration(H, H->gstream);
+    hipError_t e = hipStreamEndCapture(H->gstream, &graph);
+    if (e != hipSuccess || !graph) fail(AMGE_ERR_HIP, "graph capture of the batched PCG iteration failed");
+    e = hipGraphInstantiate(&H->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        H->gexec = nullptr;
+        fail(AMGE_ERR_HIP, "graph instantiation failed");
+    }
+}
+
+amge_status bpcg(amge_hierarchy* H, const double* b, double* x, int nrhs, double rtol, int maxit, int stop_l2,
+                 int* iters, double* relres, hipStream_t s) {
+    DLevel& L = H->lv[0];
+    const int64_t n = L.n;
+    const int NC = H->NC;
+    const int64_t nn = n * NC;
+    const bool f32 = bz32(H);
+    const bool ml = H->lv.size() > 1;
+    hipStream_t gs = H->gstream;
+    // order the internal stream after the caller's work
+    HIPCHECK(hipEventRecord(H->ev_in, s));
+    HIPCHECK(hipStreamWaitEvent(gs, H->ev_in, 0));
+    dev::BatchStatus init{};
+    init.stop_l2 = stop_l2;
+    init.maxit = maxit;
+    init.rtol = rtol;
+    HIPCHECK(hipMemcpyAsync(H->bs, &init, sizeof(init), hipMemcpyHostToDevice, gs));
+    const unsigned g = grid_stride(nn);
+    dev::k_pack<double><<<g, BLOCK, 0, gs>>>(n, nrhs, H->lgNC, b, nullptr, H->bR, nullptr);
+    bfill<double>(nn, H->bX, H->zero_flag, gs);
+    bfill<double>(nn, H->bZ, H->zero_flag, gs);
+    if (f32) dev::k_scale_rows<double, float><<<g, BLOCK, 0, gs>>>(n, H->lgNC, H->bR, L.bw32.dinv, L.bw32.bd, L.bw32.b);
+    else if (ml) dev::k_scale_rows<double, double><<<g, BLOCK, 0, gs>>>(n, H->lgNC, H->bR, L.bw64.dinv, L.bw64.bd, nullptr);
+    bpcg_precond(H, H->zero_flag, gs);
+    bpcg_dots(H, gs);
+    dev::k_bpcg_update<<<1, BLOCK, 0, gs>>>(NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs, 1);
+    dev::k_bpcg_p<<<g, BLOCK, 0, gs>>>(nn, H->lgNC, H->cs, H->bZ, H->bP, H->bs, 1);
+    HIPCHECK(hipGetLastError());
+    std::vector<dev::ColState> cs(NC);
+    dev::BatchStatus st{};
+    HIPCHECK(hipMemcpyAsync(cs.data(), H->cs, sizeof(dev::ColState) * NC, hipMemcpyDeviceToHost, gs));
+    HIPCHECK(hipMemcpyAsync(&st, H->bs, sizeof(st), hipMemcpyDeviceToHost, gs));
+    HIPCHECK(hipStreamSynchronize(gs));
+    for (int c = 0; c < nrhs; ++c)
+        if (!std::isfinite(cs[c].bnorm) || !std::isfinite(cs[c].delta0)) {
+            HIPCHECK(hipEventRecord(H->ev_out, gs));
+            HIPCHECK(hipStreamWaitEvent(s, H->ev_out, 0));
+            fail(AMGE_ERR_NONFINITE, "non-finite right-hand side");
+        }
+    if (!st.all_done) {
+        if (!H->gexec) capture_iteration(H);
+        while (true) {
+            const int chunk = std::min(BPCG_CHUNK, maxit - st.it);
+            for (int i = 0; i < chunk; ++i) HIPCHECK(hipGraphLaunch(H->gexec, gs));
+            HIPCHECK(hipMemcpyAsync(&st, H->bs, sizeof(st), hipMemcpyDeviceToHost, gs));
+            HIPCHECK(hipStreamSynchronize(gs));
+            if (st.all_done || st.it >= maxit) break;
+        }
+        HIPCHECK(hipMemcpyAsync(cs.data(), H->cs, sizeof(dev::ColState) * NC, hipMemcpyDeviceToHost, gs));
+    }
+    dev::k_unpack<double><<<grid_stride(n * nrhs), BLOCK, 0, gs>>>(n, nrhs, H->lgNC, H->bX, x);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(gs));
+    HIPCHECK(hipEventRecord(H->ev_out, gs));
+    HIPCHECK(hipStreamWaitEvent(s, H->ev_out, 0));
+    bool brk = false, nonfin = false, unconv = false;
+    for (int c = 0; c < nrhs; ++c) {
+        iters[c] = cs[c].iters;
+        relres[c] = cs[c].relres;
+        brk |= cs[c].breakdown != 0;
+        nonfin |= !std::isfinite(cs[c].rz) || !std::isfinite(cs[c].relres);
+        unconv |= rtol > 0 && !(cs[c].relres <= rtol);
+    }
+    if (brk) fail(AMGE_ERR_BREAKDOWN, "PCG breakdown (p.q <= 0 or preconditioner not positive) in a column");
+    if (nonfin) fail(AMGE_ERR_NONFINITE, "non-finite PCG iterate");
+    if (unconv) return AMGE_NOT_CONVERGED;
+    return AMGE_OK;
+}
+
 template <class F>
 amge_status guard(F&& f) {
     try {
@@ -762,7 +1280,7 @@ extern "C" amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nl
         auto H = std::make_unique<amge_hierarchy>();
         if (opts) H->opts = *opts;
         else amge_default_opts(&H->opts);
-        if (H->opts.nu_primary < 0 || H->opts.nu_aux < 0 || H->opts.max_rhs < 1 ||
+        if (H->opts.nu_primary < 0 || H->opts.nu_aux < 0 || H->opts.max_rhs < 1 || H->opts.max_rhs > 64 ||
             (H->opts.precond_bits != 32 && H->opts.precond_bits != 64))
             fail(AMGE_ERR_ARG, "invalid options");
         setup(H.get(), levels, nlevels, (hipStream_t)stream);
@@ -796,10 +1314,16 @@ extern "C" amge_status amge_hierarchy_info(const amge_hierarchy* h, int32_t* nle
 extern "C" amge_status amge_vcycle(amge_hierarchy* h, const double* r, double* z, int32_t nrhs, void* stream) {
     return guard([&]() -> amge_status {
         if (!h || !r || !z) fail(AMGE_ERR_ARG, "null argument");
-        if (nrhs != 1) fail(AMGE_ERR_ARG, "amge_vcycle: nrhs must be 1");
+        if (nrhs < 1 || nrhs > h->opts.max_rhs) fail(AMGE_ERR_ARG, "amge_vcycle: need 1 <= nrhs <= max_rhs");
         hipStream_t s = (hipStream_t)stream;
-        if (h->lv.size() == 1) coarse_solve<double>(h, r, z, s);
-        else precondition(h, r, z, s);
+        if (nrhs > 1) {
+            if (h->opts.precond_bits == 32 && h->lv.size() > 1) bprecondition<float>(h, r, z, nrhs, s);
+            else bprecondition<double>(h, r, z, nrhs, s);
+        } else if (h->lv.size() == 1) {
+            coarse_solve<double>(h, r, z, s);
+        } else {
+            precondition(h, r, z, s);
+        }
         HIPCHECK(hipGetLastError());
         return AMGE_OK;
     });
@@ -810,8 +1334,9 @@ extern "C" amge_status amge_pcg_solve(amge_hierarchy* h, const double* b, double
                                       void* stream) {
     return guard([&]() -> amge_status {
         if (!h || !b || !x || !iters || !relres) fail(AMGE_ERR_ARG, "null argument");
-        if (nrhs != 1) fail(AMGE_ERR_ARG, "amge_pcg_solve: nrhs must be 1");
+        if (nrhs < 1 || nrhs > h->opts.max_rhs) fail(AMGE_ERR_ARG, "amge_pcg_solve: need 1 <= nrhs <= max_rhs");
         if (maxit < 1) fail(AMGE_ERR_ARG, "maxit must be >= 1");
+        if (nrhs > 1) return bpcg(h, b, x, nrhs, rtol, maxit, stop_norm, iters, relres, (hipStream_t)stream);
         int it = 0;
         double rr = 0;
         amge_status st = pcg(h, b, x, rtol, maxit, stop_norm, &it, &rr, (hipStream_t)stream);

@@ -236,8 +236,10 @@ def test_error_paths():
     assert status == 1 and it[0] == 1
     status, it, rr = c.gpu[64].pcg(dev(np.zeros_like(c.b)), x, rtol=1e-8)
     assert status == 0 and it[0] == 0 and not torch.any(x != 0)
-    with pytest.raises(amge.AmgeError):
-        c.gpu[64].vcycle(dev(c.b), x, nrhs=2)
+    # more columns than the hierarchy was set up for
+    with pytest.raises(amge.AmgeError) as e:
+        c.gpu[64].vcycle(dev(np.tile(c.b, 2)), torch.zeros(2 * c.n1, dtype=torch.float64, device="cuda"), nrhs=2)
+    assert e.value.code == -1
     # an indefinite coarsest matrix is rejected at set-up
     A, D, P = c.prod[-1]
     Aneg = amge.HostCsr(A.shape[0], A.shape[1], A.rowptr, A.col, -A.val)
