@@ -87,6 +87,86 @@ def run_cpu_baseline(workload, iters_needed, budget_s=20.0):
                        f"{res['t_build_s']:.0f} s not timed")}
 
 
+def run_batched(args, amge, W):
+    """Block solve of the multi-right-hand-side workload: all columns in one batched
+    FP32-preconditioned PCG call, against the same columns solved one at a time on the
+    same hierarchy; plus the batched V-cycle's bandwidth from its algorithmic bytes."""
+    import torch
+    w = W.WORKLOADS[args.batched_workload]
+    a, b = W.coefficients(w)
+    t0 = time.perf_counter()
+    prod = amge.build_problem(w.kind, w.n, w.levels, a, b)
+    t_build = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    H = amge.Hierarchy(prod, precond_bits=32, max_rhs=w.nrhs)
+    t_setup = time.perf_counter() - t0
+    n1, k = H.rows[0], w.nrhs
+    B = torch.from_numpy(W.rhs(n1, w.rhs_seed, k)).cuda().reshape(-1)
+    X = torch.zeros_like(B)
+    print(f"[bench] {w.name}: n1={n1} x {k} columns, build {t_build:.1f}s setup {t_setup:.1f}s",
+          file=sys.stderr, flush=True)
+
+    def block_solve():
+        st, its, rrs = H.pcg(B, X, rtol=w.rtol, maxit=1000, nrhs=k)
+        if st != 0:
+            raise RuntimeError("batched solve did not converge")
+        return its, rrs
+
+    for _ in range(args.warmup):
+        block_solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        its, rrs = block_solve()
+    torch.cuda.synchronize()
+    dt_b = (time.perf_counter() - t0) / args.steps
+    # the same columns one at a time (a few of them), same hierarchy and precision
+    ncol = min(k, 4)
+    cols = [B.view(n1, k)[:, j].contiguous() for j in range(ncol)]
+    x1 = torch.zeros(n1, dtype=torch.float64, device="cuda")
+    H.pcg(cols[0], x1, rtol=w.rtol, maxit=1000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it1 = []
+    for c in cols:
+        st, it, _ = H.pcg(c, x1, rtol=w.rtol, maxit=1000)
+        it1.append(it[0])
+    torch.cuda.synchronize()
+    dt_1 = (time.perf_counter() - t0) / ncol
+    # batched V-cycle bandwidth (FP32)
+    Z = torch.empty_like(B)
+    for _ in range(3):
+        H.vcycle(B, Z, nrhs=k)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        H.vcycle(B, Z, nrhs=k)
+    e1.record()
+    torch.cuda.synchronize()
+    vms = e0.elapsed_time(e1) / reps
+    by = H.vcycle_bytes(32, nrhs=k)
+    print(f"[bench] batched: {k / dt_b:.1f} solves/s ({1e3 * dt_b:.1f} ms per block, iterations "
+          f"{min(its)}..{max(its)}); one at a time {1 / dt_1:.1f} solves/s; V-cycle {vms:.2f} ms",
+          file=sys.stderr, flush=True)
+    H.close()
+    return {
+        "workload": (f"{w.name}: H({w.kind}) on {w.n}^3x6 Kuhn tets, {w.levels}-level AMGe, {k} right-hand "
+                     f"sides (uniform[-1,1] seed {w.rhs_seed}) in one call, FP32 V-cycle in per-column FP64 "
+                     f"PCG to rel-res {w.rtol:g}"),
+        "fine_dofs": n1,
+        "solves_per_s": k / dt_b,
+        "ms_per_block": 1e3 * dt_b,
+        "iters": [min(its), max(its)],
+        "single_column_solves_per_s": 1.0 / dt_1,
+        "single_column_iters": it1,
+        "batching_speedup": dt_1 * k / dt_b,
+        "vcycle": {"ms": vms, "algorithmic_bytes": by, "GBps": by / (vms * 1e-3) / 1e9,
+                   "ms_per_column": vms / k},
+        "setup_s": {"build": t_build, "device_setup": t_setup},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +174,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="curl_n64_l5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-workload", default="div_n48_l5_rhs32",
+                    help="multi-right-hand-side workload timed beside the main one ('' to skip)")
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -181,9 +263,12 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        by = H.vcycle_bytes(bits)
+        by = H.vcycle_bytes(bits, nrhs=1)
         vc[bits] = (ms, by, by / (ms * 1e-3) / 1e9)
     err = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+
+    del H64
+    batched = run_batched(args, amge, W) if args.batched_workload else None
 
     value = args.steps / dt32
     k_avg_ms = k_ms / max(k_launches, 1)
@@ -235,6 +320,7 @@ def main():
             "launches": k_launches,
         },
         "setup_s": {"build": t_build, "device_setup": t_setup},
+        "batched": batched,
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

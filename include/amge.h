@@ -141,10 +141,12 @@ amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_t op, int32
 amge_status amge_timing_enable(amge_hierarchy* h, int32_t enable);
 amge_status amge_timing_read(amge_hierarchy* h, double* ms, int64_t* launches, double* bytes);
 
-/* Algorithmic bytes of one V-cycle (nrhs = 1) in the given precision (32 or 64): every
- * matrix of every level read once per use (values + column indices + row pointers,
- * incidences index-only), every vector stream once, and the coarsest inverse factor. */
-amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precision, double* bytes);
+/* Algorithmic bytes of one V-cycle on nrhs columns (1 <= nrhs <= max_rhs) in the given
+ * precision (32 or 64): every matrix of every level read once per use (values + column
+ * indices + row pointers, incidences index-only; the batched path reads each matrix
+ * once for all columns), every vector stream once per column, the l1 scalings once,
+ * and the coarsest inverse. */
+amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precision, int32_t nrhs, double* bytes);
 
 /* Host sizes of a hierarchy: nlevels, and rows of A_k for k = 0..nlevels-1 (rows[] may be NULL). */
 amge_status amge_hierarchy_info(const amge_hierarchy* h, int32_t* nlevels, int32_t* rows);

@@ -59,7 +59,7 @@ def _load():
         "amge_level_apply": (i32, [vp, i32, i32, i32, vp, vp, vp, vp]),
         "amge_hierarchy_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
         "amge_timing_enable": (i32, [vp, i32]),
-        "amge_vcycle_bytes": (i32, [vp, i32, C.POINTER(f64)]),
+        "amge_vcycle_bytes": (i32, [vp, i32, i32, C.POINTER(f64)]),
         "amge_timing_read": (i32, [vp, C.POINTER(f64), C.POINTER(C.c_int64), C.POINTER(f64)]),
         "amge_last_error": (C.c_char_p, []),
         "amge_kuhn_build": (i32, [i32, i32, i32, C.POINTER(f64), C.POINTER(f64), C.POINTER(vp)]),
@@ -250,9 +250,9 @@ class Hierarchy:
                                           int(stop_norm), it, rr, _stream(stream)), allow=(0, 1))
         return code, list(it), list(rr)
 
-    def vcycle_bytes(self, precision=32):
+    def vcycle_bytes(self, precision=32, nrhs=1):
         v = C.c_double()
-        _check(_lib.amge_vcycle_bytes(self._h, precision, C.byref(v)))
+        _check(_lib.amge_vcycle_bytes(self._h, precision, nrhs, C.byref(v)))
         return v.value
 
     def timing_enable(self, on=True):

@@ -16,31 +16,38 @@
 namespace amge {
 namespace dev {
 
+// V consecutive values of one row of a vector block, moved with 16-byte (or narrower)
+// vector loads and stores.
 template <typename T, int V> struct Vec;
 template <> struct Vec<float, 1> { using type = float; };
 template <> struct Vec<float, 2> { using type = float2; };
 template <> struct Vec<float, 4> { using type = float4; };
 template <> struct Vec<double, 1> { using type = double; };
 template <> struct Vec<double, 2> { using type = double2; };
-template <> struct Vec<double, 4> { using type = double4; };
 
 template <typename T, int V>
 struct Pack {
+    static constexpr int W = (V * (int)sizeof(T) > 16) ? 16 / (int)sizeof(T) : V;   // values per access
+    using VT = typename Vec<T, W>::type;
     T v[V];
     __device__ __forceinline__ void load(const T* p) {
-        using VT = typename Vec<T, V>::type;
-        const VT w = *reinterpret_cast<const VT*>(p);
-        const T* s = reinterpret_cast<const T*>(&w);
 #pragma unroll
-        for (int i = 0; i < V; ++i) v[i] = s[i];
+        for (int c = 0; c < V; c += W) {
+            const VT w = *reinterpret_cast<const VT*>(p + c);
+            const T* s = reinterpret_cast<const T*>(&w);
+#pragma unroll
+            for (int i = 0; i < W; ++i) v[c + i] = s[i];
+        }
     }
     __device__ __forceinline__ void store(T* p) const {
-        using VT = typename Vec<T, V>::type;
-        VT w;
-        T* s = reinterpret_cast<T*>(&w);
 #pragma unroll
-        for (int i = 0; i < V; ++i) s[i] = v[i];
-        *reinterpret_cast<VT*>(p) = w;
+        for (int c = 0; c < V; c += W) {
+            VT w;
+            T* s = reinterpret_cast<T*>(&w);
+#pragma unroll
+            for (int i = 0; i < W; ++i) s[i] = v[c + i];
+            *reinterpret_cast<VT*>(p + c) = w;
+        }
     }
 };
 
@@ -176,32 +183,60 @@ __device__ __forceinline__ void column_partials(double v, int NC, double* sh, do
     __syncthreads();
 }
 
-// Q = A P (FP64 CSR, one column per thread) and partial p.q per column.  Grid-stride
-// over row groups; NC must divide BLOCK.
+// Q = A P (FP64 CSR) and block partials of p.q per column.  Lanes as in k_csr_mm
+// (L = NC / V lanes per row, V columns each); every block owns a contiguous range of
+// rows, so its gathers of P stay close together.  NC * V <= BLOCK * V entries of LDS.
+template <int V>
 __global__ void __launch_bounds__(BLOCK)
 k_bpcg_ap(int n, int NC, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
           const double* __restrict__ P, double* __restrict__ Q, double* __restrict__ part,
           const BatchStatus* __restrict__ bs) {
-    __shared__ double sh[BLOCK];
+    __shared__ double sh[BLOCK * V];
     if (bs->all_done) return;
-    const int rpb = BLOCK / NC;
-    const int c = threadIdx.x % NC;
-    double dot = 0;
-    for (int row = blockIdx.x * rpb + threadIdx.x / NC; row < n; row += gridDim.x * rpb) {
-        double acc = 0;
-        for (int k = rp[row]; k < rp[row + 1]; ++k) acc = fma(av[k], P[(int64_t)ci[k] * NC + c], acc);
-        Q[(int64_t)row * NC + c] = acc;
-        dot = fma(P[(int64_t)row * NC + c], acc, dot);
+    const int L = NC / V, rpb = BLOCK / L;
+    const int g = (int)threadIdx.x / L, col = ((int)threadIdx.x % L) * V;
+    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int r0 = xcd_block(blockIdx.x, gridDim.x) * per;
+    const int r1 = min(n, r0 + per);
+    Pack<double, V> dot;
+#pragma unroll
+    for (int i = 0; i < V; ++i) dot.v[i] = 0;
+    for (int row = r0 + g; row < r1; row += rpb) {
+        Pack<double, V> acc;
+#pragma unroll
+        for (int i = 0; i < V; ++i) acc.v[i] = 0;
+        const int e = rp[row + 1];
+#pragma unroll 4
+        for (int k = rp[row]; k < e; ++k) {
+            const double a = av[k];
+            Pack<double, V> xv;
+            xv.load(P + (int64_t)ci[k] * NC + col);
+#pragma unroll
+            for (int i = 0; i < V; ++i) acc.v[i] = fma(a, xv.v[i], acc.v[i]);
+        }
+        const int64_t o = (int64_t)row * NC + col;
+        acc.store(Q + o);
+        Pack<double, V> pv;
+        pv.load(P + o);
+#pragma unroll
+        for (int i = 0; i < V; ++i) dot.v[i] = fma(pv.v[i], acc.v[i], dot.v[i]);
     }
-    column_partials(dot, NC, sh, part, gridDim.x);
+#pragma unroll
+    for (int i = 0; i < V; ++i) sh[g * NC + col + i] = dot.v[i];
+    __syncthreads();
+    if ((int)threadIdx.x < NC) {
+        double t = 0;
+        for (int q = 0; q < rpb; ++q) t += sh[q * NC + threadIdx.x];
+        part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    }
 }
 
 // Per-column totals of nq quantities from their block partials, stored at
 // part[(q * NC + c) * nblk + block]: one wave per (q, c), fixed summation order
 // (strided lane sums, then the butterfly).  Results in sh[q * NC + c].
 __device__ __forceinline__ void col_totals(const double* __restrict__ part, int nblk, int nq, int NC, double* sh) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int qc = wave; qc < nq * NC; qc += WAVES) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    for (int qc = wave; qc < nq * NC; qc += nwaves) {
         const double* p = part + (int64_t)qc * nblk;
         double t = 0;
         for (int i = lane; i < nblk; i += 64) t += p[i];
@@ -211,8 +246,11 @@ __device__ __forceinline__ void col_totals(const double* __restrict__ part, int 
     __syncthreads();
 }
 
+// Block size of the single-block finalize kernels (one wave per column sum).
+constexpr int FIN_BLOCK = 1024;
+
 // alpha_c = delta_c / pq_c for live columns (breakdown if pq_c <= 0).  One block.
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(FIN_BLOCK)
 k_bpcg_alpha(int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
              BatchStatus* __restrict__ bs) {
     __shared__ double sh[64];
@@ -285,7 +323,7 @@ k_bpcg_dots(int n, int NC, const TZ* __restrict__ Zv, double* __restrict__ Z, co
 
 // Per-column stopping test and beta (one block).  init = 1: first call after z_0 = B r_0
 // (sets delta0 and bnorm; zero right-hand sides are finished with 0 iterations).
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(FIN_BLOCK)
 k_bpcg_update(int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
               BatchStatus* __restrict__ bs, int init) {
     __shared__ double sh[3 * 64];

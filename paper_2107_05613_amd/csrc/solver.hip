@@ -523,7 +523,7 @@ void precondition(amge_hierarchy* H, const double* r, double* z, hipStream_t s) 
 }
 
 // ------------------------------------------------------------------ batched path
-constexpr int BPCG_BLOCKS = 512;   // blocks of the per-column dot products
+constexpr int BPCG_BLOCKS = 2048;  // blocks of the per-column dot products
 constexpr int BPCG_CHUNK = 4;      // graph replays between status polls
 // Several right-hand sides at once (n x NC row-major blocks, NC a power of two): every
 // level operator is one CSR SpMM launch whose lanes own V consecutive columns of a
@@ -584,7 +584,9 @@ void csr_mm(const DCsrB& M, int mode, int NC, const T* X, const T* B, const T* d
     switch (M.V) {
         case 1: csr_mm_m<T, 1>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
         case 2: csr_mm_m<T, 2>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        default: csr_mm_m<T, 4>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case 4: csr_mm_m<T, 4>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case 8: csr_mm_m<T, 8>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        default: csr_mm_m<T, 16>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
     }
 }
 
@@ -601,7 +603,9 @@ void inc_mm_add(const DCsrB& M, int NC, const T* X, T* Y, const int* stop, hipSt
     switch (M.V) {
         case 1: inc_mm_v<T, 1>(M, NC, X, Y, stop, s); break;
         case 2: inc_mm_v<T, 2>(M, NC, X, Y, stop, s); break;
-        default: inc_mm_v<T, 4>(M, NC, X, Y, stop, s); break;
+        case 4: inc_mm_v<T, 4>(M, NC, X, Y, stop, s); break;
+        case 8: inc_mm_v<T, 8>(M, NC, X, Y, stop, s); break;
+        default: inc_mm_v<T, 16>(M, NC, X, Y, stop, s); break;
     }
 }
 
@@ -640,8 +644,8 @@ int tune_cols(DCsrB& M, bool incidence, int NC, T* X, T* Y, const int* stop, hip
     }
     const int v0 = std::min(NC, (int)(16 / sizeof(T)));
     std::vector<int> cands = {v0};
-    for (int V : {1, 2, 4})
-        if (V != v0 && V <= NC) cands.push_back(V);
+    for (int V : {1, 2, 4, 8, 16})
+        if (V != v0 && V <= NC && V * sizeof(T) <= 64) cands.push_back(V);
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     HIPCHECK(hipEventCreate(&e1));
@@ -668,7 +672,7 @@ int tune_cols(DCsrB& M, bool incidence, int NC, T* X, T* Y, const int* stop, hip
         if (verbose())
             fprintf(stderr, "[amge tune-mm] rows %d nnz %lld NC %d fp%d V=%d: %.2f us\n", M.nrows, (long long)M.nnz, NC,
                     (int)(8 * sizeof(T)), V, 1e3 * ms / 3);
-        if (V == v0 || ms < best_ms * 0.9f) {   // keep the default unless clearly faster
+        if (V == v0 || ms < best_ms * 0.95f) {   // keep the default unless clearly faster
             best_ms = ms;
             best = V;
         }
@@ -1118,7 +1122,12 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
 
 void bpcg_ap(amge_hierarchy* H, hipStream_t s) {
     const DCsrB& A = H->lv[0].bA;
-    dev::k_bpcg_ap<<<BPCG_BLOCKS, BLOCK, 0, s>>>(A.nrows, H->NC, A.rp, A.ci, A.v64, H->bP, H->bQ, H->bpart, H->bs);
+    if (H->NC >= 2)   // 16-byte lane loads
+        dev::k_bpcg_ap<2><<<BPCG_BLOCKS, BLOCK, 0, s>>>(A.nrows, H->NC, A.rp, A.ci, A.v64, H->bP, H->bQ, H->bpart,
+                                                        H->bs);
+    else
+        dev::k_bpcg_ap<1><<<BPCG_BLOCKS, BLOCK, 0, s>>>(A.nrows, H->NC, A.rp, A.ci, A.v64, H->bP, H->bQ, H->bpart,
+                                                        H->bs);
 }
 
 // z = B r for the batched PCG: the V-cycle (or the coarse solve on a one-level
@@ -1151,13 +1160,13 @@ void bpcg_iteration(amge_hierarchy* H, hipStream_t s) {
     const bool ml = H->lv.size() > 1;
     const unsigned g = grid_stride(nn);
     bpcg_ap(H, s);
-    dev::k_bpcg_alpha<<<1, BLOCK, 0, s>>>(H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
+    dev::k_bpcg_alpha<<<1, dev::FIN_BLOCK, 0, s>>>(H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
     dev::k_bpcg_xr<<<g, BLOCK, 0, s>>>(nn, H->lgNC, H->cs, H->bP, H->bQ, H->bX, H->bR, f32 ? L.bw32.b : nullptr,
                                        f32 ? L.bw32.bd : nullptr, f32 ? L.bw32.dinv : nullptr,
                                        !f32 && ml ? L.bw64.bd : nullptr, !f32 && ml ? L.bw64.dinv : nullptr, H->bs);
     bpcg_precond(H, &H->bs->all_done, s);
     bpcg_dots(H, s);
-    dev::k_bpcg_update<<<1, BLOCK, 0, s>>>(H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs, 0);
+    dev::k_bpcg_update<<<1, dev::FIN_BLOCK, 0, s>>>(H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs, 0);
     dev::k_bpcg_p<<<g, BLOCK, 0, s>>>(nn, H->lgNC, H->cs, H->bZ, H->bP, H->bs, 0);
 }
 
@@ -1200,7 +1209,7 @@ amge_status bpcg(amge_hierarchy* H, const double* b, double* x, int nrhs, double
     else if (ml) dev::k_scale_rows<double, double><<<g, BLOCK, 0, gs>>>(n, H->lgNC, H->bR, L.bw64.dinv, L.bw64.bd, nullptr);
     bpcg_precond(H, H->zero_flag, gs);
     bpcg_dots(H, gs);
-    dev::k_bpcg_update<<<1, BLOCK, 0, gs>>>(NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs, 1);
+    dev::k_bpcg_update<<<1, dev::FIN_BLOCK, 0, gs>>>(NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs, 1);
     dev::k_bpcg_p<<<g, BLOCK, 0, gs>>>(nn, H->lgNC, H->cs, H->bZ, H->bP, H->bs, 1);
     HIPCHECK(hipGetLastError());
     std::vector<dev::ColState> cs(NC);
@@ -1455,36 +1464,47 @@ extern "C" amge_status amge_timing_read(amge_hierarchy* h, double* ms, int64_t* 
     });
 }
 
-extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precision, double* bytes) {
+extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precision, int32_t nrhs, double* bytes) {
     return guard([&]() -> amge_status {
         if (!h || !bytes) fail(AMGE_ERR_ARG, "null argument");
         if (precision != 32 && precision != 64) fail(AMGE_ERR_ARG, "precision must be 32 or 64");
-        const double sv = precision == 32 ? 4.0 : 8.0;   // value / vector entry size
+        if (nrhs < 1 || nrhs > h->opts.max_rhs) fail(AMGE_ERR_ARG, "need 1 <= nrhs <= max_rhs");
+        const bool batched = nrhs > 1;
+        const double sv = precision == 32 ? 4.0 : 8.0;   // value size
+        const double sx = sv * nrhs;                       // one row of a vector block
         const int nup = h->opts.nu_primary, nua = h->opts.nu_aux;
         double tot = 0;
         const size_t nl = h->lv.size();
         for (size_t k = 0; k + 1 < nl; ++k) {
             const DLevel& L = h->lv[k];
             const double n = L.n, m = L.m, nc = h->lv[k + 1].n;
-            auto mat = [&](const DSell& M) { return (double)M.nnz * (sv + 4.0) + 4.0 * M.nrows; };
-            auto incb = [&](const DSell& M) { return (double)M.nnz * 4.0 + 4.0 * M.nrows; };
+            // matrix streams: values + column indices + one row pointer (sliced ELL: one
+            // row index) per row; incidences are index-only
+            auto mat = [&](const DSell& M, const DCsrB& B) {
+                return batched ? (double)B.nnz * (sv + 4.0) + 4.0 * (B.nrows + 1)
+                               : (double)M.nnz * (sv + 4.0) + 4.0 * M.nrows;
+            };
+            auto incb = [&](const DSell& M, const DCsrB& B) {
+                return batched ? (double)B.nnz * 4.0 + 4.0 * (B.nrows + 1) : (double)M.nnz * 4.0 + 4.0 * M.nrows;
+            };
             // primary sweeps: the first one from zero is the producer's bd = dinv b (two
-            // extra streams there), every launched sweep reads x, b, dinv and writes y
+            // extra streams there), every launched sweep reads x, b and writes y (+ dinv)
             const int launched = std::max(0, nup - 1) + nup;
-            tot += launched * (mat(L.A) + 4 * sv * n) + 2 * sv * n;
+            tot += launched * (mat(L.A, L.bA) + 3 * sx * n + sv * n) + 2 * sx * n;
             // auxiliary step, pre and post: residual [D^T | -D^T A][b; x] (+ gd), sweeps, D add
             if (nua > 0) {
-                double aux = mat(L.Aux) + sv * (2 * n + m) + 2 * sv * m;
-                aux += (nua - 1) * (mat(L.Ah) + 4 * sv * m);
-                aux += incb(L.D) + sv * (m + 2 * n);
+                double aux = mat(L.Aux, L.bAux) + sx * (2 * n + m) + sx * m + sv * m;   // b, x; g, gd; dhinv
+                aux += (nua - 1) * (mat(L.Ah, L.bAh) + 3 * sx * m + sv * m);
+                aux += incb(L.D, L.bD) + sx * (m + 2 * n);
                 tot += 2 * aux;
             }
             // restriction residual, P^T, P add
-            tot += mat(L.A) + 3 * sv * n;
-            tot += mat(L.Pt) + sv * (n + nc);
-            tot += mat(L.P) + sv * (nc + 2 * n);
+            tot += mat(L.A, L.bA) + 3 * sx * n;
+            tot += mat(L.Pt, L.bPt) + sx * (n + nc);
+            tot += mat(L.P, L.bP) + sx * (nc + 2 * n);
         }
-        tot += 8.0 * (double)h->nc * h->nc;   // coarsest: both triangles of the inverse factor
+        // coarsest: the inverse read once, the right-hand side and solution blocks
+        tot += 8.0 * (double)h->nc * h->nc + 2 * sx * h->nc;
         *bytes = tot;
         return AMGE_OK;
     });
