@@ -154,6 +154,73 @@ amge_status amge_hierarchy_info(const amge_hierarchy* h, int32_t* nlevels, int32
 const char* amge_last_error(void);
 
 /* ------------------------------------------------------------------------------------
+ * Serving engine: many resident hierarchies and a stream of single right-hand-side
+ * solve requests (inexact PCG of section 5.1 with one V-cycle per step, x0 = 0).
+ * The hierarchies are reused across many right-hand sides, the regime where the setup
+ * cost of the method pays off (section 5).
+ *
+ * Every hierarchy added to a server runs the batched PCG on its own stream, one column
+ * per request.  Between chunks of iterations a request is loaded into a free column of
+ * its hierarchy while the other columns stay in flight (continuous batching), and the
+ * hierarchies advance concurrently on the device.  The arithmetic of a column does not
+ * depend on the other columns, so a request's result is the same alone and in a mix.
+ *
+ * Admission by device memory:
+ *   hierarchy_budget  bytes; amge_server_add fails with AMGE_ERR_BUSY if the sum of the
+ *                     footprints (amge_footprint) of the added hierarchies would exceed
+ *                     it (0 = no limit)
+ *   inflight_budget   bytes; a request is admitted only while the work footprint of all
+ *                     admitted requests (amge_server_request_bytes each: its column of
+ *                     the work blocks) stays within it (0 = no limit); requests are
+ *                     admitted in submission order, a request that does not fit waits
+ *                     and holds back those behind it, one whose hierarchy has no free
+ *                     column does not
+ *   chunk             PCG iterations per hierarchy between two looks at its columns
+ *
+ * Single-threaded: calls on one server must not overlap.  A hierarchy added to a
+ * server (it needs max_rhs >= 2: its max_rhs is the number of columns) is used only by
+ * the server until amge_server_destroy, which waits for the server's work; the
+ * hierarchies outlive the server and are destroyed by the caller.
+ * ---------------------------------------------------------------------------------- */
+typedef struct amge_server amge_server;
+
+typedef struct {
+    int64_t tag;         /* the caller's request id                                        */
+    int32_t hierarchy;   /* id from amge_server_add                                         */
+    int32_t status;      /* AMGE_OK, AMGE_NOT_CONVERGED, AMGE_ERR_BREAKDOWN, AMGE_ERR_NONFINITE */
+    int32_t iters;       /* PCG steps                                                       */
+    int32_t pad;
+    double relres;       /* final relative residual in the chosen norm                      */
+} amge_completion;
+
+amge_status amge_server_create(size_t hierarchy_budget, size_t inflight_budget, int32_t chunk,
+                               amge_server** out);
+void amge_server_destroy(amge_server* s);
+/* Makes h resident in the server; *id numbers the hierarchies 0, 1, ...
+ * Errors: AMGE_ERR_ARG (max_rhs < 2, added twice), AMGE_ERR_BUSY (budget). */
+amge_status amge_server_add(amge_server* s, amge_hierarchy* h, int32_t* id);
+/* Work footprint of one request on hierarchy id, in bytes. */
+amge_status amge_server_request_bytes(const amge_server* s, int32_t id, size_t* bytes);
+/* Queues the solve A_1 x = b on hierarchy id.  b, x: device FP64, n_1 entries each,
+ * caller-owned; b is read after the work already queued on `stream` (an event is
+ * recorded there) and must stay valid, and x untouched, until the request's completion
+ * is returned.  rtol, maxit, stop_norm as for amge_pcg_solve.  Errors: AMGE_ERR_ARG,
+ * AMGE_ERR_BUSY (the request alone exceeds the in-flight budget). */
+amge_status amge_server_submit(amge_server* s, int32_t id, const double* b, double* x, double rtol,
+                               int32_t maxit, int32_t stop_norm, int64_t tag, void* stream);
+/* Advances the server: looks at every hierarchy whose chunk has finished, copies
+ * finished requests out, admits queued requests into free columns and starts the next
+ * chunks.  With wait != 0 it returns once at least one request has completed or
+ * nothing is left to do; with wait = 0 after one pass.  Up to cap completions are
+ * written to out (*nout of them); x of a returned request is final. */
+amge_status amge_server_progress(amge_server* s, int32_t wait, amge_completion* out, int32_t cap,
+                                 int32_t* nout);
+/* Queued and in-flight request counts, in-flight work bytes and resident hierarchy bytes
+ * (any pointer may be NULL). */
+amge_status amge_server_stats(const amge_server* s, int32_t* queued, int32_t* inflight,
+                              size_t* inflight_bytes, size_t* resident_bytes);
+
+/* ------------------------------------------------------------------------------------
  * Problem builder for the structured workloads: the unit cube split into n^3 hexes,
  * 6 Kuhn tetrahedra each; lowest-order Nedelec (kind AMGE_CURL) or Raviart-Thomas
  * (AMGE_DIV) discretisation of a(u,v) = (alpha Du, Dv) + (beta u, v) (eq. (2.2)), natural

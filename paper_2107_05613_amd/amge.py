@@ -44,6 +44,11 @@ class OptsC(C.Structure):
                 ("max_rhs", C.c_int32)]
 
 
+class CompletionC(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("hierarchy", C.c_int32), ("status", C.c_int32), ("iters", C.c_int32),
+                ("pad", C.c_int32), ("relres", C.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with python -m paper_2107_05613_amd.build")
@@ -66,6 +71,14 @@ def _load():
         "amge_problem_nlevels": (i32, [vp]),
         "amge_problem_levels": (i32, [vp, C.POINTER(LevelC)]),
         "amge_problem_free": (None, [vp]),
+        "amge_server_create": (i32, [C.c_size_t, C.c_size_t, i32, C.POINTER(vp)]),
+        "amge_server_destroy": (None, [vp]),
+        "amge_server_add": (i32, [vp, vp, C.POINTER(i32)]),
+        "amge_server_request_bytes": (i32, [vp, i32, C.POINTER(C.c_size_t)]),
+        "amge_server_submit": (i32, [vp, i32, vp, vp, f64, i32, i32, C.c_int64, vp]),
+        "amge_server_progress": (i32, [vp, i32, C.POINTER(CompletionC), i32, C.POINTER(i32)]),
+        "amge_server_stats": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_size_t),
+                                    C.POINTER(C.c_size_t)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -80,7 +93,9 @@ _lib = _load()
 EXPORTS = ("amge_default_opts", "amge_setup_hierarchy", "amge_destroy", "amge_footprint", "amge_vcycle",
            "amge_pcg_solve", "amge_level_apply", "amge_hierarchy_info", "amge_last_error",
            "amge_timing_enable", "amge_timing_read", "amge_vcycle_bytes",
-           "amge_kuhn_build", "amge_problem_nlevels", "amge_problem_levels", "amge_problem_free")
+           "amge_kuhn_build", "amge_problem_nlevels", "amge_problem_levels", "amge_problem_free",
+           "amge_server_create", "amge_server_destroy", "amge_server_add", "amge_server_request_bytes",
+           "amge_server_submit", "amge_server_progress", "amge_server_stats")
 
 
 def lib():
@@ -267,3 +282,65 @@ class Hierarchy:
     def level_apply(self, level, op, x, out, x2=None, precision=64, stream=None):
         _check(_lib.amge_level_apply(self._h, level, op, precision, _ptr(x), _ptr(x2), _ptr(out),
                                      _stream(stream)))
+
+
+# ----------------------------------------------------------------------------- serving
+class Server:
+    """Serving engine (amge_server_*): resident hierarchies, continuous batching of
+    single right-hand-side requests.  Hierarchies passed to add() must have max_rhs >= 2
+    and must outlive the server; they are used only by it."""
+
+    def __init__(self, hierarchy_budget=0, inflight_budget=0, chunk=2):
+        h = C.c_void_p()
+        _check(_lib.amge_server_create(int(hierarchy_budget), int(inflight_budget), int(chunk), C.byref(h)))
+        self._h = h
+        self._rows = []
+        self._hier = []
+        self._cap = 256
+        self._buf = (CompletionC * self._cap)()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.amge_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, H: "Hierarchy") -> int:
+        i = C.c_int32()
+        _check(_lib.amge_server_add(self._h, H.handle, C.byref(i)))
+        self._rows.append(H.rows[0])
+        self._hier.append(H)
+        return i.value
+
+    def request_bytes(self, hid) -> int:
+        b = C.c_size_t()
+        _check(_lib.amge_server_request_bytes(self._h, hid, C.byref(b)))
+        return b.value
+
+    def submit(self, hid, b, x, tag, rtol=1e-8, maxit=500, stop_norm=0, stream=None):
+        n = self._rows[hid]
+        _check(_lib.amge_server_submit(self._h, hid, _vec(b, n), _vec(x, n), float(rtol), int(maxit),
+                                       int(stop_norm), int(tag), _stream(stream)))
+
+    def progress(self, wait=True):
+        """Completed requests as a list of (tag, hierarchy, status, iters, relres)."""
+        out = []
+        while True:
+            k = C.c_int32()
+            _check(_lib.amge_server_progress(self._h, 1 if (wait and not out) else 0, self._buf, self._cap,
+                                             C.byref(k)))
+            for c in self._buf[:k.value]:
+                out.append((c.tag, c.hierarchy, c.status, c.iters, c.relres))
+            if k.value < self._cap:
+                return out
+
+    def stats(self):
+        q, f = C.c_int32(), C.c_int32()
+        fb, rb = C.c_size_t(), C.c_size_t()
+        _check(_lib.amge_server_stats(self._h, C.byref(q), C.byref(f), C.byref(fb), C.byref(rb)))
+        return {"queued": q.value, "inflight": f.value, "inflight_bytes": fb.value, "resident_bytes": rb.value}

@@ -1,0 +1,136 @@
+// Device-side data of a hierarchy (shared by the solver and the serving engine).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "state.hpp"
+#include "common.hpp"
+
+namespace amge {
+
+#define HIPCHECK(expr)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            fail(e_ == hipErrorOutOfMemory ? AMGE_ERR_OOM : AMGE_ERR_HIP,                     \
+                 std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+    } while (0)
+
+// Sliced ELL matrix (64-row slices, column-major inside a slice) on the device.
+struct DSell {
+    int nrows = 0, ncols = 0, nslices = 0;
+    int K = 1;                // lanes per row
+    int64_t nnz = 0;          // stored nonzeros of the CSR input
+    int64_t stored = 0;       // entries including padding
+    int* sptr = nullptr;      // nslices + 1 entry offsets
+    int* srow = nullptr;      // slot -> row (-1: empty slot)
+    int* ci = nullptr;        // value matrices: column indices
+    uint32_t* ent = nullptr;  // incidence matrices: column | sign << 31, padding 0xffffffff
+    double* v64 = nullptr;
+    float* v32 = nullptr;
+};
+
+template <class T>
+struct Work {
+    T *b = nullptr, *x = nullptr, *xt = nullptr, *r = nullptr, *g = nullptr, *y = nullptr, *yt = nullptr;
+    T *bd = nullptr, *gd = nullptr;   // dinv * b, dhinv * g: first sweeps from zero
+    T* dinv = nullptr;
+    T* dhinv = nullptr;
+};
+
+// Event timing of the fine-level A kernels (the dominant kernel family of the V-cycle).
+struct Probe {
+    bool on = false;
+    std::vector<hipEvent_t> ev;   // start/stop pairs, reused across reads
+    size_t used = 0;              // pairs recorded since the last read
+    double bytes = 0;             // algorithmic bytes of the recorded launches
+    ~Probe() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+// CSR matrix on the device for the batched (several right-hand sides) kernels.
+struct DCsrB {
+    int nrows = 0, ncols = 0;
+    int64_t nnz = 0;
+    int* rp = nullptr;
+    int* ci = nullptr;         // value matrices
+    uint32_t* ent = nullptr;   // incidence matrices: column | sign << 31
+    double* v64 = nullptr;
+    float* v32 = nullptr;
+    int V = 1;                 // columns per lane (vector width), tuned
+};
+
+struct DLevel {
+    int n = 0, m = 0;
+    Probe* probe = nullptr;
+    DSell A, Ah, P, Pt;
+    DSell Aux;                // [D^T | -D^T A]: auxiliary residual D^T b - (D^T A) x
+    DSell D, Dt;              // signed incidences
+    Work<float> w32;
+    Work<double> w64;
+    // batched path (max_rhs > 1): CSR copies and n x NC work buffers of the
+    // preconditioner precision
+    DCsrB bA, bAh, bP, bPt, bAux, bD;
+    Work<float> bw32;
+    Work<double> bw64;
+    template <class T> Work<T>& w();
+    template <class T> Work<T>& bw();
+};
+template <> inline Work<float>& DLevel::w<float>() { return w32; }
+template <> inline Work<double>& DLevel::w<double>() { return w64; }
+template <> inline Work<float>& DLevel::bw<float>() { return bw32; }
+template <> inline Work<double>& DLevel::bw<double>() { return bw64; }
+
+}  // namespace amge
+
+struct amge_hierarchy {
+    std::vector<amge::DLevel> lv;
+    amge_opts opts{};
+    int nc = 0;                  // coarsest size
+    double* Ainv = nullptr;      // coarsest inverse from the Cholesky factor
+    // outer PCG buffers (FP64, level-1 length)
+    double *r = nullptr, *p = nullptr, *q = nullptr, *z[2] = {nullptr, nullptr};
+    double *part_pq = nullptr, *part_dots[2] = {nullptr, nullptr};
+    amge::dev::PcgStatus* st = nullptr;
+    int* flags = nullptr;        // [0] done, [1] breakdown
+    // batched PCG (NC = max_rhs rounded up to a power of two, columns beyond nrhs are zero)
+    int NC = 1, lgNC = 0;
+    double *bX = nullptr, *bR = nullptr, *bP = nullptr, *bQ = nullptr, *bZ = nullptr, *bZv = nullptr;
+    double* bpart = nullptr;
+    int bnblk = 0;
+    amge::dev::ColState* cs = nullptr;
+    amge::dev::BatchStatus* bs = nullptr;
+    int* zero_flag = nullptr;    // a device 0 for batched kernels run outside PCG
+    hipStream_t gstream = nullptr;   // stream for graph capture / replay
+    hipGraphExec_t gexec = nullptr;  // one captured batched PCG iteration
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::vector<void*> allocs;
+    size_t bytes = 0;
+    amge::Probe probe;
+    ~amge_hierarchy() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (ev_in) (void)hipEventDestroy(ev_in);
+        if (ev_out) (void)hipEventDestroy(ev_out);
+        if (gstream) (void)hipStreamDestroy(gstream);
+        for (void* a : allocs) (void)hipFree(a);
+    }
+    template <class T>
+    T* alloc(size_t n) {
+        if (n == 0) n = 1;
+        void* ptr = nullptr;
+        hipError_t e = hipMalloc(&ptr, n * sizeof(T));
+        if (e != hipSuccess) amge::fail(AMGE_ERR_OOM, "hipMalloc failed");
+        allocs.push_back(ptr);
+        bytes += n * sizeof(T);
+        return (T*)ptr;
+    }
+};
+
+namespace amge {
+// Captures one batched PCG iteration of a hierarchy as a HIP graph on its own stream
+// (done once, on first use).
+void capture_iteration(amge_hierarchy* H);
+}  // namespace amge

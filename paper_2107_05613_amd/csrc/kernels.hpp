@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "state.hpp"
+
 namespace amge {
 namespace dev {
 
@@ -264,10 +266,6 @@ k_pcg_dots(int n, const float* __restrict__ z32, double* __restrict__ z, const d
 }
 
 // Status written by the last kernel of every iteration (read by the host).
-struct PcgStatus {
-    double delta0, delta, rr, relres, bnorm;
-    int iters, done, breakdown, pad;
-};
 
 // beta = (r.z - r.zold) / delta_old; p = z + beta p; stopping test.
 __global__ void __launch_bounds__(BLOCK)

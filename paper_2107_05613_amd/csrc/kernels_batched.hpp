@@ -154,22 +154,6 @@ k_coarse_mm(int n, int lg, const double* __restrict__ Ainv, const T* __restrict_
 }
 
 // ---------------------------------------------------------------- batched PCG
-// Per-column state, written only by the single-block finalize kernels.
-struct ColState {
-    double delta0, delta, bnorm, relres, pq, rz, rzold, rr, alpha, beta;
-    int iters, done, breakdown, pad;
-};
-
-struct BatchStatus {
-    int it;          // iterations performed so far
-    int all_done;    // every column finished
-    int any_breakdown;
-    int stop_l2;     // 0: preconditioner norm, 1: l2 norm
-    int maxit;
-    int pad;
-    double rtol;
-};
-
 // Per-column partial sums over the rows of a block: the block's threads hold column
 // (tid % NC) sums for row group tid / NC; reduced over row groups through LDS.
 __device__ __forceinline__ void column_partials(double v, int NC, double* sh, double* part, int nblk) {
@@ -249,7 +233,8 @@ __device__ __forceinline__ void col_totals(const double* __restrict__ part, int 
 // Block size of the single-block finalize kernels (one wave per column sum).
 constexpr int FIN_BLOCK = 1024;
 
-// alpha_c = delta_c / pq_c for live columns (breakdown if pq_c <= 0).  One block.
+// alpha_c = delta_c / pq_c for live columns (breakdown if pq_c <= 0); fresh and idle
+// columns take no step.  One block.
 __global__ void __launch_bounds__(FIN_BLOCK)
 k_bpcg_alpha(int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
              BatchStatus* __restrict__ bs) {
@@ -261,12 +246,17 @@ k_bpcg_alpha(int NC, const double* __restrict__ part, int nblk, ColState* __rest
         ColState& s = cs[c];
         const double pq = sh[c];
         s.pq = pq;
-        if (s.done) s.alpha = 0;
-        else if (!(pq > 0) || !isfinite(pq)) {
-            s.alpha = 0;
-            s.breakdown = 1;
-            s.done = 1;
-        } else s.alpha = s.delta / pq;
+        s.pinit = 0;
+        s.alpha = 0;
+        if (!s.done && !s.fresh) {
+            if (pq > 0 && isfinite(pq)) {
+                s.alpha = s.delta / pq;
+            } else {
+                s.breakdown = isfinite(pq) ? 1 : 0;
+                s.nonfinite = isfinite(pq) ? 0 : 1;
+                s.done = 1;
+            }
+        }
     }
 }
 
@@ -321,22 +311,23 @@ k_bpcg_dots(int n, int NC, const TZ* __restrict__ Zv, double* __restrict__ Z, co
     column_partials(d, NC, sh, part + (int64_t)2 * NC * nb, nb);
 }
 
-// Per-column stopping test and beta (one block).  init = 1: first call after z_0 = B r_0
-// (sets delta0 and bnorm; zero right-hand sides are finished with 0 iterations).
+// Per-column stopping test and beta (one block).  A fresh column takes its initial
+// quantities here (delta0 = r.z0, ||b||) and becomes live; a zero right-hand side is
+// finished with 0 steps.
 __global__ void __launch_bounds__(FIN_BLOCK)
 k_bpcg_update(int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
-              BatchStatus* __restrict__ bs, int init) {
+              BatchStatus* __restrict__ bs) {
     __shared__ double sh[3 * 64];
     __shared__ int flags[2 * 64];
-    if (!init && bs->all_done) return;
+    if (bs->all_done) return;
     col_totals(part, nblk, 3, NC, sh);
-    const double rtol = bs->rtol;
-    const int stop_l2 = bs->stop_l2, maxit = bs->maxit;
     const int c = threadIdx.x;
     if (c < NC) {
         ColState& s = cs[c];
         const double rz = sh[c], rzo = sh[NC + c], rr = sh[2 * NC + c];
-        if (init) {
+        if (s.done) {
+        } else if (s.fresh) {
+            s.fresh = 0;
             s.delta0 = rz;
             s.delta = rz;
             s.bnorm = sqrt(rr);
@@ -345,25 +336,30 @@ k_bpcg_update(int NC, const double* __restrict__ part, int nblk, ColState* __res
             s.rzold = 0;
             s.relres = 1.0;
             s.iters = 0;
-            s.breakdown = 0;
-            s.alpha = 0;
             s.beta = 0;
-            s.done = 0;
-            if (rr == 0) {
+            if (!isfinite(rz) || !isfinite(rr)) {
+                s.nonfinite = 1;
                 s.done = 1;
+            } else if (rr == 0) {
                 s.relres = 0;
-            } else if (!(rz > 0) || !isfinite(rz) || !isfinite(rr)) {
-                s.breakdown = !(rz > 0) && isfinite(rz) && isfinite(rr);
                 s.done = 1;
+            } else if (!(rz > 0)) {
+                s.breakdown = 1;
+                s.done = 1;
+            } else {
+                s.pinit = 1;
             }
-        } else if (!s.done) {
+        } else {
             s.rz = rz;
             s.rzold = rzo;
             s.rr = rr;
-            s.iters = bs->it + 1;
-            const double rel = stop_l2 ? sqrt(rr) / s.bnorm : sqrt(fmax(rz, 0.0) / s.delta0);
+            s.iters += 1;
+            const double rel = s.stop_l2 ? sqrt(rr) / s.bnorm : sqrt(fmax(rz, 0.0) / s.delta0);
             s.relres = rel;
-            if ((rtol > 0 && rel <= rtol) || s.iters >= maxit || !isfinite(rz)) {
+            if (!isfinite(rz)) {
+                s.nonfinite = 1;
+                s.done = 1;
+            } else if ((s.rtol > 0 && rel <= s.rtol) || s.iters >= s.maxit) {
                 s.done = 1;
                 s.beta = 0;
             } else {
@@ -381,21 +377,54 @@ k_bpcg_update(int NC, const double* __restrict__ part, int nblk, ColState* __res
             live += flags[j] ? 0 : 1;
             brk |= flags[64 + j];
         }
-        if (!init) bs->it += 1;
+        bs->it += 1;
         bs->all_done = live == 0;
         bs->any_breakdown = brk;
     }
 }
 
-// P = Z + beta P for live columns (P = Z on the first call).
+// P = Z + beta P for live columns; P = Z for a column that has just taken its initial
+// quantities.
 __global__ void __launch_bounds__(BLOCK)
 k_bpcg_p(int64_t nn, int lg, const ColState* __restrict__ cs, const double* __restrict__ Z, double* __restrict__ P,
-         const BatchStatus* __restrict__ bs, int init) {
-    if (!init && bs->all_done) return;
+         const BatchStatus* __restrict__ bs) {
+    if (bs->all_done) return;
     for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < nn; t += (int64_t)gridDim.x * BLOCK) {
-        const int c = (int)(t & ((1 << lg) - 1));
-        if (init) P[t] = Z[t];
-        else if (!cs[c].done) P[t] = fma(cs[c].beta, P[t], Z[t]);
+        const ColState& s = cs[t & ((1 << lg) - 1)];
+        if (s.pinit) P[t] = Z[t];
+        else if (!s.done) P[t] = fma(s.beta, P[t], Z[t]);
+    }
+}
+
+// Loads a block of right-hand sides (caller layout n x nrhs) as fresh columns: R = b,
+// X = P = 0; columns nrhs..NC-1 are idle and zero.
+__global__ void __launch_bounds__(BLOCK)
+k_bpcg_load(int64_t n, int nrhs, int lg, const double* __restrict__ b, double* __restrict__ R, double* __restrict__ X,
+            double* __restrict__ P, ColState* __restrict__ cs, BatchStatus* __restrict__ bs, double rtol, int maxit,
+            int stop_l2) {
+    const int NC = 1 << lg;
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < (n << lg); t += (int64_t)gridDim.x * BLOCK) {
+        const int c = (int)(t & (NC - 1));
+        R[t] = c < nrhs ? b[(t >> lg) * nrhs + c] : 0.0;
+        X[t] = 0.0;
+        P[t] = 0.0;
+    }
+    if (blockIdx.x == 0) {
+        const int c = threadIdx.x;
+        if (c < NC) {
+            ColState s = {};
+            s.rtol = rtol;
+            s.maxit = maxit;
+            s.stop_l2 = stop_l2;
+            s.fresh = c < nrhs ? 1 : 0;
+            s.done = c < nrhs ? 0 : 1;
+            cs[c] = s;
+        }
+        if (c == 0) {
+            bs->it = 0;
+            bs->all_done = nrhs > 0 ? 0 : 1;
+            bs->any_breakdown = 0;
+        }
     }
 }
 
@@ -435,18 +464,6 @@ __global__ void __launch_bounds__(BLOCK)
 k_copy(int64_t n, const T* __restrict__ a, T* __restrict__ b, const int* __restrict__ stop) {
     if (*stop) return;
     for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLOCK) b[t] = a[t];
-}
-
-// Row scaling of an n x NC block: Y = dinv[row] * (D) X, and Xc = (D) X if given.
-template <typename S, typename D>
-__global__ void __launch_bounds__(BLOCK)
-k_scale_rows(int64_t n, int lg, const S* __restrict__ X, const D* __restrict__ dinv, D* __restrict__ Y,
-             D* __restrict__ Xc) {
-    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < (n << lg); t += (int64_t)gridDim.x * BLOCK) {
-        const D v = (D)X[t];
-        if (Xc) Xc[t] = v;
-        Y[t] = dinv[t >> lg] * v;
-    }
 }
 
 }  // namespace dev

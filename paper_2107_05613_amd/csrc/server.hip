@@ -1,0 +1,405 @@
+// Serving engine: many resident hierarchies and a stream of single right-hand-side
+// solve requests.
+//
+// Each hierarchy added to a server runs the batched PCG (one column per request) on its
+// own stream, replaying its captured iteration graph in chunks.  Between chunks the
+// host reads the per-column states (pinned memory, no stall of the other hierarchies),
+// copies finished columns out, and loads queued requests into the freed columns while
+// the other columns stay in flight: continuous batching at the granularity of a PCG
+// iteration.  Different hierarchies advance concurrently on their own streams.
+//
+// Admission: a hierarchy is made resident only if its device footprint fits the
+// hierarchy budget; a request is admitted when its hierarchy has a free column and the
+// work footprint of all admitted requests (their share of the batched work blocks)
+// stays within the in-flight budget.  Requests are admitted in arrival order; one that
+// does not fit the in-flight budget blocks those behind it, one whose hierarchy is full
+// does not.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <deque>
+#include <memory>
+#include <thread>
+#include <vector>
+
+#include "common.hpp"
+#include "hierarchy.hpp"
+
+namespace amge {
+namespace dev {
+
+constexpr int SBLOCK = 256;
+
+// Loads one right-hand side (n contiguous values) into column c as a fresh column.
+__global__ void __launch_bounds__(SBLOCK)
+k_serve_insert(int64_t n, int lg, int c, const double* __restrict__ b, double* __restrict__ R, double* __restrict__ X,
+               double* __restrict__ P, ColState* __restrict__ cs, BatchStatus* __restrict__ bs, double rtol, int maxit,
+               int stop_l2) {
+    for (int64_t i = (int64_t)blockIdx.x * SBLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * SBLOCK) {
+        const int64_t t = (i << lg) + c;
+        R[t] = b[i];
+        X[t] = 0.0;
+        P[t] = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ColState s = {};
+        s.rtol = rtol;
+        s.maxit = maxit;
+        s.stop_l2 = stop_l2;
+        s.fresh = 1;
+        cs[c] = s;
+        bs->all_done = 0;
+    }
+}
+
+// x = column c of X.
+__global__ void __launch_bounds__(SBLOCK)
+k_serve_extract(int64_t n, int lg, int c, const double* __restrict__ X, double* __restrict__ x) {
+    for (int64_t i = (int64_t)blockIdx.x * SBLOCK + threadIdx.x; i < n; i += (int64_t)gridDim.x * SBLOCK)
+        x[i] = X[(i << lg) + c];
+}
+
+// Every column idle.
+__global__ void k_serve_reset(int NC, ColState* __restrict__ cs, BatchStatus* __restrict__ bs) {
+    const int c = threadIdx.x;
+    if (c < NC) {
+        ColState s = {};
+        s.done = 1;
+        cs[c] = s;
+    }
+    if (c == 0) {
+        bs->it = 0;
+        bs->all_done = 1;
+        bs->any_breakdown = 0;
+    }
+}
+
+}  // namespace dev
+
+namespace {
+
+unsigned sgrid(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + dev::SBLOCK - 1) / dev::SBLOCK, 2048));
+}
+
+struct Request {
+    int64_t tag = 0;
+    int hid = 0;
+    const double* b = nullptr;
+    double* x = nullptr;
+    double rtol = 0;
+    int maxit = 0, stop_l2 = 0;
+    hipEvent_t ready = nullptr;   // recorded on the caller's stream at submission
+    amge_completion done{};
+};
+
+// One resident hierarchy and its columns.
+struct Group {
+    amge_hierarchy* H = nullptr;
+    size_t footprint = 0;          // device bytes of the hierarchy
+    size_t col_bytes = 0;          // work bytes of one column
+    std::vector<int> slot;         // column -> index into the server's request table, -1 free
+    dev::ColState* cs_host = nullptr;   // pinned copy of the column states after a chunk
+    hipEvent_t ev_chunk = nullptr, ev_extract = nullptr;
+    bool chunk_busy = false;
+    std::vector<int> extracting;   // requests whose copy-out is in flight
+    int active = 0;                // columns holding a request
+};
+
+}  // namespace
+}  // namespace amge
+
+using namespace amge;
+
+struct amge_server {
+    size_t hierarchy_budget = 0, inflight_budget = 0;
+    size_t resident = 0, inflight = 0;
+    int chunk = 2;
+    std::vector<std::unique_ptr<Group>> groups;
+    std::vector<Request> reqs;        // request table (indices stay valid)
+    std::vector<int> free_reqs;       // reusable entries of the table
+    std::deque<int> queue;            // submitted, not admitted, in arrival order
+    std::deque<amge_completion> done; // finished, not yet returned
+    std::vector<hipEvent_t> event_pool;
+
+    ~amge_server() {
+        for (auto& g : groups) {
+            (void)hipStreamSynchronize(g->H->gstream);
+            if (g->cs_host) (void)hipHostFree(g->cs_host);
+            if (g->ev_chunk) (void)hipEventDestroy(g->ev_chunk);
+            if (g->ev_extract) (void)hipEventDestroy(g->ev_extract);
+        }
+        for (Request& r : reqs)
+            if (r.ready) event_pool.push_back(r.ready);
+        for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    }
+
+    hipEvent_t take_event() {
+        if (!event_pool.empty()) {
+            hipEvent_t e = event_pool.back();
+            event_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        return e;
+    }
+
+    int new_request() {
+        if (!free_reqs.empty()) {
+            int i = free_reqs.back();
+            free_reqs.pop_back();
+            return i;
+        }
+        reqs.emplace_back();
+        return (int)reqs.size() - 1;
+    }
+
+    void release(int i) {
+        if (reqs[i].ready) event_pool.push_back(reqs[i].ready);
+        reqs[i] = Request{};
+        free_reqs.push_back(i);
+    }
+
+    // Completion of copy-outs: report every request of a finished extraction.
+    bool reap_extractions(Group& g) {
+        if (g.extracting.empty()) return false;
+        hipError_t e = hipEventQuery(g.ev_extract);
+        if (e == hipErrorNotReady) return false;
+        HIPCHECK(e);
+        for (int i : g.extracting) {
+            done.push_back(reqs[i].done);
+            release(i);
+        }
+        g.extracting.clear();
+        return true;
+    }
+
+    // A chunk has finished: copy finished columns out and free them.
+    bool reap_chunk(Group& g) {
+        if (!g.chunk_busy) return false;
+        hipError_t e = hipEventQuery(g.ev_chunk);
+        if (e == hipErrorNotReady) return false;
+        HIPCHECK(e);
+        g.chunk_busy = false;
+        amge_hierarchy* H = g.H;
+        const int64_t n = H->lv[0].n;
+        bool any = false;
+        for (int c = 0; c < H->NC; ++c) {
+            const int i = g.slot[c];
+            if (i < 0) continue;
+            const dev::ColState& s = g.cs_host[c];
+            if (!s.done) continue;
+            Request& r = reqs[i];
+            r.done.tag = r.tag;
+            r.done.hierarchy = r.hid;
+            r.done.iters = s.iters;
+            r.done.relres = s.relres;
+            r.done.status = s.nonfinite ? AMGE_ERR_NONFINITE
+                            : s.breakdown ? AMGE_ERR_BREAKDOWN
+                            : (r.rtol > 0 && !(s.relres <= r.rtol)) ? AMGE_NOT_CONVERGED
+                                                                     : AMGE_OK;
+            dev::k_serve_extract<<<sgrid(n), dev::SBLOCK, 0, H->gstream>>>(n, H->lgNC, c, H->bX, r.x);
+            g.extracting.push_back(i);
+            g.slot[c] = -1;
+            g.active -= 1;
+            inflight -= g.col_bytes;
+            any = true;
+        }
+        if (any) {
+            HIPCHECK(hipGetLastError());
+            HIPCHECK(hipEventRecord(g.ev_extract, H->gstream));
+        }
+        return true;
+    }
+
+    // Loads queued requests into free columns of idle groups.
+    bool admit() {
+        bool any = false;
+        for (auto it = queue.begin(); it != queue.end();) {
+            Request& r = reqs[*it];
+            Group& g = *groups[r.hid];
+            if (inflight_budget && inflight + g.col_bytes > inflight_budget) break;   // keeps arrival order
+            if (g.chunk_busy || g.active == g.H->NC) {
+                ++it;
+                continue;
+            }
+            int c = 0;
+            while (g.slot[c] >= 0) ++c;
+            amge_hierarchy* H = g.H;
+            const int64_t n = H->lv[0].n;
+            HIPCHECK(hipStreamWaitEvent(H->gstream, r.ready, 0));
+            dev::k_serve_insert<<<sgrid(n), dev::SBLOCK, 0, H->gstream>>>(n, H->lgNC, c, r.b, H->bR, H->bX, H->bP,
+                                                                         H->cs, H->bs, r.rtol, r.maxit, r.stop_l2);
+            HIPCHECK(hipGetLastError());
+            g.slot[c] = *it;
+            g.active += 1;
+            inflight += g.col_bytes;
+            it = queue.erase(it);
+            any = true;
+        }
+        return any;
+    }
+
+    // Starts a chunk of iterations on every idle group that holds requests.
+    bool launch() {
+        bool any = false;
+        for (auto& gp : groups) {
+            Group& g = *gp;
+            if (g.chunk_busy || g.active == 0) continue;
+            amge_hierarchy* H = g.H;
+            for (int i = 0; i < chunk; ++i) HIPCHECK(hipGraphLaunch(H->gexec, H->gstream));
+            HIPCHECK(hipMemcpyAsync(g.cs_host, H->cs, sizeof(dev::ColState) * H->NC, hipMemcpyDeviceToHost,
+                                    H->gstream));
+            HIPCHECK(hipEventRecord(g.ev_chunk, H->gstream));
+            g.chunk_busy = true;
+            any = true;
+        }
+        return any;
+    }
+
+    bool busy() const {
+        if (!queue.empty()) return true;
+        for (auto& g : groups)
+            if (g->chunk_busy || g->active || !g->extracting.empty()) return true;
+        return false;
+    }
+};
+
+namespace {
+template <class F>
+amge_status sguard(F&& f) {
+    try {
+        return f();
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return AMGE_ERR_OOM;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return AMGE_ERR_ARG;
+    }
+}
+}  // namespace
+
+extern "C" amge_status amge_server_create(size_t hierarchy_budget, size_t inflight_budget, int32_t chunk,
+                                          amge_server** out) {
+    return sguard([&]() -> amge_status {
+        if (!out) fail(AMGE_ERR_ARG, "null output pointer");
+        if (chunk < 1) fail(AMGE_ERR_ARG, "chunk must be >= 1");
+        auto S = std::make_unique<amge_server>();
+        S->hierarchy_budget = hierarchy_budget;
+        S->inflight_budget = inflight_budget;
+        S->chunk = chunk;
+        *out = S.release();
+        return AMGE_OK;
+    });
+}
+
+extern "C" void amge_server_destroy(amge_server* s) { delete s; }
+
+extern "C" amge_status amge_server_add(amge_server* s, amge_hierarchy* h, int32_t* id) {
+    return sguard([&]() -> amge_status {
+        if (!s || !h || !id) fail(AMGE_ERR_ARG, "null argument");
+        if (h->NC < 2) fail(AMGE_ERR_ARG, "hierarchy needs max_rhs >= 2 to serve");
+        for (auto& g : s->groups)
+            if (g->H == h) fail(AMGE_ERR_ARG, "hierarchy already added");
+        if (s->hierarchy_budget && s->resident + h->bytes > s->hierarchy_budget)
+            fail(AMGE_ERR_BUSY, "hierarchy does not fit the device memory budget");
+        auto g = std::make_unique<Group>();
+        g->H = h;
+        g->footprint = h->bytes;
+        // one column of the work blocks: six FP64 PCG blocks and the V-cycle's level blocks
+        size_t cb = 6 * sizeof(double) * (size_t)h->lv[0].n;
+        const size_t vs = (h->opts.precond_bits == 32 && h->lv.size() > 1) ? sizeof(float) : sizeof(double);
+        for (const DLevel& L : h->lv) cb += vs * (5 * (size_t)L.n + 4 * (size_t)L.m);
+        g->col_bytes = cb;
+        g->slot.assign(h->NC, -1);
+        HIPCHECK(hipHostMalloc((void**)&g->cs_host, sizeof(dev::ColState) * h->NC, hipHostMallocDefault));
+        HIPCHECK(hipEventCreateWithFlags(&g->ev_chunk, hipEventDisableTiming));
+        HIPCHECK(hipEventCreateWithFlags(&g->ev_extract, hipEventDisableTiming));
+        capture_iteration(h);
+        dev::k_serve_reset<<<1, 64, 0, h->gstream>>>(h->NC, h->cs, h->bs);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(h->gstream));
+        s->resident += g->footprint;
+        *id = (int32_t)s->groups.size();
+        s->groups.push_back(std::move(g));
+        return AMGE_OK;
+    });
+}
+
+extern "C" amge_status amge_server_request_bytes(const amge_server* s, int32_t id, size_t* bytes) {
+    return sguard([&]() -> amge_status {
+        if (!s || !bytes) fail(AMGE_ERR_ARG, "null argument");
+        if (id < 0 || id >= (int32_t)s->groups.size()) fail(AMGE_ERR_ARG, "unknown hierarchy id");
+        *bytes = s->groups[id]->col_bytes;
+        return AMGE_OK;
+    });
+}
+
+extern "C" amge_status amge_server_submit(amge_server* s, int32_t id, const double* b, double* x, double rtol,
+                                          int32_t maxit, int32_t stop_norm, int64_t tag, void* stream) {
+    return sguard([&]() -> amge_status {
+        if (!s || !b || !x) fail(AMGE_ERR_ARG, "null argument");
+        if (id < 0 || id >= (int32_t)s->groups.size()) fail(AMGE_ERR_ARG, "unknown hierarchy id");
+        if (maxit < 1) fail(AMGE_ERR_ARG, "maxit must be >= 1");
+        if (s->inflight_budget && s->groups[id]->col_bytes > s->inflight_budget)
+            fail(AMGE_ERR_BUSY, "request work footprint exceeds the in-flight budget");
+        const int i = s->new_request();
+        Request& r = s->reqs[i];
+        r.tag = tag;
+        r.hid = id;
+        r.b = b;
+        r.x = x;
+        r.rtol = rtol;
+        r.maxit = maxit;
+        r.stop_l2 = stop_norm ? 1 : 0;
+        r.ready = s->take_event();
+        HIPCHECK(hipEventRecord(r.ready, (hipStream_t)stream));
+        s->queue.push_back(i);
+        return AMGE_OK;
+    });
+}
+
+extern "C" amge_status amge_server_progress(amge_server* s, int32_t wait, amge_completion* out, int32_t cap,
+                                            int32_t* nout) {
+    return sguard([&]() -> amge_status {
+        if (!s || !nout || (cap > 0 && !out)) fail(AMGE_ERR_ARG, "null argument");
+        *nout = 0;
+        while (true) {
+            bool moved = false;
+            for (auto& g : s->groups) {
+                moved |= s->reap_extractions(*g);
+                moved |= s->reap_chunk(*g);
+            }
+            moved |= s->admit();
+            moved |= s->launch();
+            if (!s->done.empty() || !wait || !s->busy()) break;
+            if (!moved) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+        int k = 0;
+        while (k < cap && !s->done.empty()) {
+            out[k++] = s->done.front();
+            s->done.pop_front();
+        }
+        *nout = k;
+        return AMGE_OK;
+    });
+}
+
+extern "C" amge_status amge_server_stats(const amge_server* s, int32_t* queued, int32_t* inflight,
+                                         size_t* inflight_bytes, size_t* resident_bytes) {
+    return sguard([&]() -> amge_status {
+        if (!s) fail(AMGE_ERR_ARG, "null argument");
+        int act = 0;
+        for (auto& g : s->groups) act += g->active + (int)g->extracting.size();
+        if (queued) *queued = (int32_t)s->queue.size();
+        if (inflight) *inflight = act;
+        if (inflight_bytes) *inflight_bytes = s->inflight;
+        if (resident_bytes) *resident_bytes = s->resident;
+        return AMGE_OK;
+    });
+}

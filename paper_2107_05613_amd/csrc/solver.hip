@@ -15,129 +15,10 @@
 #include <tuple>
 
 #include "common.hpp"
+#include "hierarchy.hpp"
 #include "kernels.hpp"
 #include "kernels_batched.hpp"
 
-namespace amge {
-
-#define HIPCHECK(expr)                                                                        \
-    do {                                                                                      \
-        hipError_t e_ = (expr);                                                               \
-        if (e_ != hipSuccess)                                                                 \
-            fail(e_ == hipErrorOutOfMemory ? AMGE_ERR_OOM : AMGE_ERR_HIP,                     \
-                 std::string(#expr) + ": " + hipGetErrorString(e_));                          \
-    } while (0)
-
-// Sliced ELL matrix (64-row slices, column-major inside a slice) on the device.
-struct DSell {
-    int nrows = 0, ncols = 0, nslices = 0;
-    int K = 1;                // lanes per row
-    int64_t nnz = 0;          // stored nonzeros of the CSR input
-    int64_t stored = 0;       // entries including padding
-    int* sptr = nullptr;      // nslices + 1 entry offsets
-    int* srow = nullptr;      // slot -> row (-1: empty slot)
-    int* ci = nullptr;        // value matrices: column indices
-    uint32_t* ent = nullptr;  // incidence matrices: column | sign << 31, padding 0xffffffff
-    double* v64 = nullptr;
-    float* v32 = nullptr;
-};
-
-template <class T>
-struct Work {
-    T *b = nullptr, *x = nullptr, *xt = nullptr, *r = nullptr, *g = nullptr, *y = nullptr, *yt = nullptr;
-    T *bd = nullptr, *gd = nullptr;   // dinv * b, dhinv * g: first sweeps from zero
-    T* dinv = nullptr;
-    T* dhinv = nullptr;
-};
-
-// Event timing of the fine-level A kernels (the dominant kernel family of the V-cycle).
-struct Probe {
-    bool on = false;
-    std::vector<hipEvent_t> ev;   // start/stop pairs, reused across reads
-    size_t used = 0;              // pairs recorded since the last read
-    double bytes = 0;             // algorithmic bytes of the recorded launches
-    ~Probe() {
-        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-    }
-};
-
-// CSR matrix on the device for the batched (several right-hand sides) kernels.
-struct DCsrB {
-    int nrows = 0, ncols = 0;
-    int64_t nnz = 0;
-    int* rp = nullptr;
-    int* ci = nullptr;         // value matrices
-    uint32_t* ent = nullptr;   // incidence matrices: column | sign << 31
-    double* v64 = nullptr;
-    float* v32 = nullptr;
-    int V = 1;                 // columns per lane (vector width), tuned
-};
-
-struct DLevel {
-    int n = 0, m = 0;
-    Probe* probe = nullptr;
-    DSell A, Ah, P, Pt;
-    DSell Aux;                // [D^T | -D^T A]: auxiliary residual D^T b - (D^T A) x
-    DSell D, Dt;              // signed incidences
-    Work<float> w32;
-    Work<double> w64;
-    // batched path (max_rhs > 1): CSR copies and n x NC work buffers of the
-    // preconditioner precision
-    DCsrB bA, bAh, bP, bPt, bAux, bD;
-    Work<float> bw32;
-    Work<double> bw64;
-    template <class T> Work<T>& w();
-    template <class T> Work<T>& bw();
-};
-template <> Work<float>& DLevel::w<float>() { return w32; }
-template <> Work<double>& DLevel::w<double>() { return w64; }
-template <> Work<float>& DLevel::bw<float>() { return bw32; }
-template <> Work<double>& DLevel::bw<double>() { return bw64; }
-
-}  // namespace amge
-
-struct amge_hierarchy {
-    std::vector<amge::DLevel> lv;
-    amge_opts opts{};
-    int nc = 0;                  // coarsest size
-    double* Ainv = nullptr;      // coarsest inverse from the Cholesky factor
-    // outer PCG buffers (FP64, level-1 length)
-    double *r = nullptr, *p = nullptr, *q = nullptr, *z[2] = {nullptr, nullptr};
-    double *part_pq = nullptr, *part_dots[2] = {nullptr, nullptr};
-    amge::dev::PcgStatus* st = nullptr;
-    int* flags = nullptr;        // [0] done, [1] breakdown
-    // batched PCG (NC = max_rhs rounded up to a power of two, columns beyond nrhs are zero)
-    int NC = 1, lgNC = 0;
-    double *bX = nullptr, *bR = nullptr, *bP = nullptr, *bQ = nullptr, *bZ = nullptr, *bZv = nullptr;
-    double* bpart = nullptr;
-    int bnblk = 0;
-    amge::dev::ColState* cs = nullptr;
-    amge::dev::BatchStatus* bs = nullptr;
-    int* zero_flag = nullptr;    // a device 0 for batched kernels run outside PCG
-    hipStream_t gstream = nullptr;   // stream for graph capture / replay
-    hipGraphExec_t gexec = nullptr;  // one captured batched PCG iteration
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    std::vector<void*> allocs;
-    size_t bytes = 0;
-    amge::Probe probe;
-    ~amge_hierarchy() {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        if (ev_in) (void)hipEventDestroy(ev_in);
-        if (ev_out) (void)hipEventDestroy(ev_out);
-        if (gstream) (void)hipStreamDestroy(gstream);
-        for (void* a : allocs) (void)hipFree(a);
-    }
-    template <class T>
-    T* alloc(size_t n) {
-        if (n == 0) n = 1;
-        void* ptr = nullptr;
-        hipError_t e = hipMalloc(&ptr, n * sizeof(T));
-        if (e != hipSuccess) amge::fail(AMGE_ERR_OOM, "hipMalloc failed");
-        allocs.push_back(ptr);
-        bytes += n * sizeof(T);
-        return (T*)ptr;
-    }
-};
 
 namespace amge {
 
@@ -1116,9 +997,12 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
 }
 
 // ---- batched inexact PCG: the single-column recurrences per column, with the
-// stopping test per column on the device (a finished column gets alpha = beta = 0 and
-// keeps its iterate).  One iteration is captured once as a HIP graph on the hierarchy's
-// own stream and replayed in chunks; the host polls the batch status between chunks.
+// stopping test per column on the device (a finished column takes alpha = 0 and keeps
+// its iterate).  Columns are loaded as "fresh": their first pass through an iteration
+// computes z0 = B b and the initial quantities, so columns loaded at different times
+// share every launch (the serving engine inserts requests into free columns between
+// chunks).  One iteration is captured once as a HIP graph on the hierarchy's own
+// stream and replayed in chunks; the host polls the batch status between chunks.
 
 void bpcg_ap(amge_hierarchy* H, hipStream_t s) {
     const DCsrB& A = H->lv[0].bA;
@@ -1130,12 +1014,11 @@ void bpcg_ap(amge_hierarchy* H, hipStream_t s) {
                                                         H->bs);
 }
 
-// z = B r for the batched PCG: the V-cycle (or the coarse solve on a one-level
-// hierarchy) in the preconditioner precision on the residual block; writes zv.
 // The FP32 V-cycle reads its input from the level-1 FP32 block; a one-level hierarchy
 // (coarse solve only) always works in FP64, like the single-column path.
 bool bz32(const amge_hierarchy* H) { return H->opts.precond_bits == 32 && H->lv.size() > 1; }
 
+// z = B r on the residual block in the preconditioner precision; writes zv.
 void bpcg_precond(amge_hierarchy* H, const int* stop, hipStream_t s) {
     DLevel& L = H->lv[0];
     if (bz32(H)) bvcycle_level<float>(H, 0, L.bw32.b, L.bw32.bd, L.bw32.x, stop, s);
@@ -1166,11 +1049,13 @@ void bpcg_iteration(amge_hierarchy* H, hipStream_t s) {
                                        !f32 && ml ? L.bw64.bd : nullptr, !f32 && ml ? L.bw64.dinv : nullptr, H->bs);
     bpcg_precond(H, &H->bs->all_done, s);
     bpcg_dots(H, s);
-    dev::k_bpcg_update<<<1, dev::FIN_BLOCK, 0, s>>>(H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs, 0);
-    dev::k_bpcg_p<<<g, BLOCK, 0, s>>>(nn, H->lgNC, H->cs, H->bZ, H->bP, H->bs, 0);
+    dev::k_bpcg_update<<<1, dev::FIN_BLOCK, 0, s>>>(H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
+    dev::k_bpcg_p<<<g, BLOCK, 0, s>>>(nn, H->lgNC, H->cs, H->bZ, H->bP, H->bs);
 }
 
 void capture_iteration(amge_hierarchy* H) {
+    if (H->gexec) return;
+    if (H->NC < 2 || !H->gstream) fail(AMGE_ERR_ARG, "hierarchy has no batched path (max_rhs = 1)");
     hipGraph_t graph = nullptr;
     HIPCHECK(hipStreamBeginCapture(H->gstream, hipStreamCaptureModeThreadLocal));
     bpcg_iteration(H, H->gstream);
@@ -1189,51 +1074,26 @@ amge_status bpcg(amge_hierarchy* H, const double* b, double* x, int nrhs, double
     DLevel& L = H->lv[0];
     const int64_t n = L.n;
     const int NC = H->NC;
-    const int64_t nn = n * NC;
-    const bool f32 = bz32(H);
-    const bool ml = H->lv.size() > 1;
     hipStream_t gs = H->gstream;
+    capture_iteration(H);
     // order the internal stream after the caller's work
     HIPCHECK(hipEventRecord(H->ev_in, s));
     HIPCHECK(hipStreamWaitEvent(gs, H->ev_in, 0));
-    dev::BatchStatus init{};
-    init.stop_l2 = stop_l2;
-    init.maxit = maxit;
-    init.rtol = rtol;
-    HIPCHECK(hipMemcpyAsync(H->bs, &init, sizeof(init), hipMemcpyHostToDevice, gs));
-    const unsigned g = grid_stride(nn);
-    dev::k_pack<double><<<g, BLOCK, 0, gs>>>(n, nrhs, H->lgNC, b, nullptr, H->bR, nullptr);
-    bfill<double>(nn, H->bX, H->zero_flag, gs);
-    bfill<double>(nn, H->bZ, H->zero_flag, gs);
-    if (f32) dev::k_scale_rows<double, float><<<g, BLOCK, 0, gs>>>(n, H->lgNC, H->bR, L.bw32.dinv, L.bw32.bd, L.bw32.b);
-    else if (ml) dev::k_scale_rows<double, double><<<g, BLOCK, 0, gs>>>(n, H->lgNC, H->bR, L.bw64.dinv, L.bw64.bd, nullptr);
-    bpcg_precond(H, H->zero_flag, gs);
-    bpcg_dots(H, gs);
-    dev::k_bpcg_update<<<1, dev::FIN_BLOCK, 0, gs>>>(NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs, 1);
-    dev::k_bpcg_p<<<g, BLOCK, 0, gs>>>(nn, H->lgNC, H->cs, H->bZ, H->bP, H->bs, 1);
+    dev::k_bpcg_load<<<grid_stride(n * NC), BLOCK, 0, gs>>>(n, nrhs, H->lgNC, b, H->bR, H->bX, H->bP, H->cs, H->bs,
+                                                            rtol, maxit, stop_l2);
     HIPCHECK(hipGetLastError());
-    std::vector<dev::ColState> cs(NC);
     dev::BatchStatus st{};
-    HIPCHECK(hipMemcpyAsync(cs.data(), H->cs, sizeof(dev::ColState) * NC, hipMemcpyDeviceToHost, gs));
-    HIPCHECK(hipMemcpyAsync(&st, H->bs, sizeof(st), hipMemcpyDeviceToHost, gs));
-    HIPCHECK(hipStreamSynchronize(gs));
-    for (int c = 0; c < nrhs; ++c)
-        if (!std::isfinite(cs[c].bnorm) || !std::isfinite(cs[c].delta0)) {
-            HIPCHECK(hipEventRecord(H->ev_out, gs));
-            HIPCHECK(hipStreamWaitEvent(s, H->ev_out, 0));
-            fail(AMGE_ERR_NONFINITE, "non-finite right-hand side");
-        }
-    if (!st.all_done) {
-        if (!H->gexec) capture_iteration(H);
-        while (true) {
-            const int chunk = std::min(BPCG_CHUNK, maxit - st.it);
-            for (int i = 0; i < chunk; ++i) HIPCHECK(hipGraphLaunch(H->gexec, gs));
-            HIPCHECK(hipMemcpyAsync(&st, H->bs, sizeof(st), hipMemcpyDeviceToHost, gs));
-            HIPCHECK(hipStreamSynchronize(gs));
-            if (st.all_done || st.it >= maxit) break;
-        }
-        HIPCHECK(hipMemcpyAsync(cs.data(), H->cs, sizeof(dev::ColState) * NC, hipMemcpyDeviceToHost, gs));
+    // every column finishes within maxit steps after its initial pass
+    for (int launched = 0;;) {
+        if (launched > maxit + 1) fail(AMGE_ERR_HIP, "batched PCG did not terminate");
+        for (int i = 0; i < BPCG_CHUNK; ++i) HIPCHECK(hipGraphLaunch(H->gexec, gs));
+        launched += BPCG_CHUNK;
+        HIPCHECK(hipMemcpyAsync(&st, H->bs, sizeof(st), hipMemcpyDeviceToHost, gs));
+        HIPCHECK(hipStreamSynchronize(gs));
+        if (st.all_done) break;
     }
+    std::vector<dev::ColState> cs(NC);
+    HIPCHECK(hipMemcpyAsync(cs.data(), H->cs, sizeof(dev::ColState) * NC, hipMemcpyDeviceToHost, gs));
     dev::k_unpack<double><<<grid_stride(n * nrhs), BLOCK, 0, gs>>>(n, nrhs, H->lgNC, H->bX, x);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(gs));
@@ -1244,11 +1104,11 @@ amge_status bpcg(amge_hierarchy* H, const double* b, double* x, int nrhs, double
         iters[c] = cs[c].iters;
         relres[c] = cs[c].relres;
         brk |= cs[c].breakdown != 0;
-        nonfin |= !std::isfinite(cs[c].rz) || !std::isfinite(cs[c].relres);
+        nonfin |= cs[c].nonfinite != 0;
         unconv |= rtol > 0 && !(cs[c].relres <= rtol);
     }
+    if (nonfin) fail(AMGE_ERR_NONFINITE, "non-finite right-hand side or PCG iterate in a column");
     if (brk) fail(AMGE_ERR_BREAKDOWN, "PCG breakdown (p.q <= 0 or preconditioner not positive) in a column");
-    if (nonfin) fail(AMGE_ERR_NONFINITE, "non-finite PCG iterate");
     if (unconv) return AMGE_NOT_CONVERGED;
     return AMGE_OK;
 }

@@ -1,0 +1,36 @@
+// PCG state records written by the kernels and read by the host.
+#pragma once
+
+#include <stdint.h>
+
+namespace amge {
+namespace dev {
+
+// Single-column PCG status.
+struct PcgStatus {
+    double delta0, delta, rr, relres, bnorm;
+    int iters, done, breakdown, pad;
+};
+
+// Per-column state of the batched PCG (written only by the single-block finalize
+// kernels and by the kernels that load a column).  A column is idle (done = 1), fresh
+// (just loaded: its next pass through an iteration computes z0 = B b and the initial
+// quantities instead of a step) or live.
+struct ColState {
+    double delta0, delta, bnorm, relres, pq, rz, rzold, rr, alpha, beta;
+    double rtol;      // stopping tolerance of the column (<= 0: exactly maxit iterations)
+    int iters;        // PCG steps taken since the column was loaded
+    int maxit;
+    int stop_l2;      // 0: preconditioner norm, 1: l2 norm of the residual
+    int done, fresh, pinit, breakdown, nonfinite;
+};
+
+struct BatchStatus {
+    int it;          // iterations run since the last load
+    int all_done;    // no fresh or live column: every kernel of an iteration returns at once
+    int any_breakdown;
+    int pad;
+};
+
+}  // namespace dev
+}  // namespace amge

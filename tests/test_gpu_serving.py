@@ -1,0 +1,195 @@
+"""Serving engine (amge_server_*, through the C ABI): resident hierarchies, admission by
+device memory, continuous batching of single right-hand-side requests.
+
+Bars
+* Solo vs mix: every request solved alone (the only request in the server) and inside
+  a mix of requests on several hierarchies, arriving while others are in flight, gives
+  the same solution, iteration count and residual.  Columns of the batched PCG share no
+  arithmetic, so the bar is bitwise equality.
+* Parity: requests on an FP64-preconditioner hierarchy, stopped after a fixed number of
+  iterations, equal the oracle's PCG iterate within max(1e-10, u * kappa) (the bound of
+  the single-column tests).
+* Admission: the in-flight budget caps the admitted requests' work footprint at every
+  moment; hierarchies beyond the resident budget and requests beyond the in-flight
+  budget are refused with AMGE_ERR_BUSY.
+"""
+import numpy as np
+import pytest
+
+from paper_2107_05613_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SPECS = [("curl", 8, 3, "blocks", 0), ("div", 8, 3, "blocks", 1), ("curl", 12, 3, "unit", 0)]
+SLOTS = 4
+
+
+class Resident:
+    def __init__(self, precond_bits):
+        from paper_2107_05613_amd import amge
+        self.prods, self.H, self.n1 = [], [], []
+        for kind, n, L, coef, cs in SPECS:
+            w = W.Workload("t", kind, n, L, coef, coef_seed=cs)
+            a, b = W.coefficients(w)
+            prod = amge.build_problem(kind, n, L, a, b)
+            self.prods.append((w, a, b))
+            self.H.append(amge.Hierarchy(prod, precond_bits=precond_bits, max_rhs=SLOTS))
+            self.n1.append(self.H[-1].rows[0])
+
+
+_RES = {}
+
+
+def resident(bits):
+    if bits not in _RES:
+        _RES[bits] = Resident(bits)
+    return _RES[bits]
+
+
+def requests(res, num, seed=0):
+    """(hierarchy index, device rhs) per request, hierarchies drawn at random."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(num):
+        h = int(rng.integers(0, len(res.H)))
+        out.append((h, torch.from_numpy(W.rhs(res.n1[h], 100 + r)[:, 0]).cuda()))
+    torch.cuda.synchronize()
+    return out
+
+
+def serve(res, reqs, order, inflight_budget=0, maxit=None, watch=None):
+    """Serves the requests of `order` (all submitted at once, in that order); returns
+    {request: (status, iters, relres, x)}."""
+    from paper_2107_05613_amd import amge
+    srv = amge.Server(inflight_budget=inflight_budget, chunk=2)
+    ids = [srv.add(H) for H in res.H]
+    xs = {j: torch.full((res.n1[reqs[j][0]],), 3.0, dtype=torch.float64, device="cuda") for j in order}
+    for j in order:
+        h, b = reqs[j]
+        mi = maxit[j] if maxit and j in maxit else 500
+        srv.submit(ids[h], b, xs[j], tag=j, rtol=1e-8, maxit=mi)
+    out = {}
+    while len(out) < len(order):
+        for tag, hid, status, iters, relres in srv.progress(wait=True):
+            out[tag] = (status, iters, relres)
+        if watch is not None:
+            watch(srv)
+    srv.close()
+    torch.cuda.synchronize()
+    return {j: (*out[j], xs[j].cpu().numpy()) for j in order}
+
+
+def test_solo_vs_mix_bitwise():
+    """a9: each result is the same alone and in the mix (continuous batching: requests
+    enter free columns while the other columns of their hierarchy are in flight)."""
+    res = resident(32)
+    reqs = requests(res, 14, seed=1)
+    mix = serve(res, reqs, list(range(len(reqs))))
+    for j in range(len(reqs)):
+        solo = serve(res, reqs, [j])[j]
+        m = mix[j]
+        assert m[0] == 0 and solo[0] == 0
+        assert m[1] == solo[1] and m[2] == solo[2], (j, m[:3], solo[:3])
+        assert np.array_equal(m[3], solo[3]), j
+        assert m[2] <= 1e-8
+    # the served result is the hierarchy's own batched solve of that column
+    j = 0
+    h, b = reqs[j]
+    x = torch.zeros(res.n1[h] * 2, dtype=torch.float64, device="cuda")
+    B = torch.stack([b, torch.zeros_like(b)], 1).reshape(-1).contiguous()
+    status, its, rrs = res.H[h].pcg(B, x, rtol=1e-8, nrhs=2)
+    assert its[0] == mix[j][1]
+    assert np.array_equal(x.view(-1, 2)[:, 0].cpu().numpy(), mix[j][3])
+
+
+def test_served_fp64_matches_oracle():
+    """Served requests on FP64-preconditioner hierarchies, fixed iteration count, against
+    the oracle's PCG iterate."""
+    from oracle.hierarchy import build_hierarchy
+    from oracle.solve import Multilevel, pcg
+    res = resident(64)
+    reqs = requests(res, 6, seed=2)
+    k = 9
+    out = serve(res, reqs, list(range(len(reqs))), maxit={j: k for j in range(len(reqs))})
+    oracles = {}
+    for j, (h, b) in enumerate(reqs):
+        w, a, be = res.prods[h]
+        if h not in oracles:
+            H = build_hierarchy(w.kind, w.n, w.levels, a, be, check_targets=False)
+            oracles[h] = (H, Multilevel.from_hierarchy(H))
+        H, ml = oracles[h]
+        kap = 1.0
+        for lvl in range(w.levels - 1):
+            A, D = H.A[lvl], H.D[lvl]
+            num = abs(D).T @ (abs(A) @ (abs(D) @ np.ones(D.shape[1])))
+            den = abs((D.T @ A @ D).tocsr()) @ np.ones(D.shape[1])
+            kap = max(kap, float(np.max(num / den)))
+        tol = max(1e-10, 2.0 ** -53 * kap)
+        status, iters, relres, x = out[j]
+        assert status == 1 and iters == k    # rtol 1e-8 not reached in k steps
+        xo, _, _ = pcg(H.A[0], b.cpu().numpy(), ml, fixed_iters=k)
+        err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+        print(f"request {j} (hierarchy {h}): {k} iterations, error vs oracle {err:.1e} (tol {tol:.1e})")
+        assert err <= tol
+
+
+def test_admission_by_inflight_budget():
+    """At most two requests' work footprint admitted at any moment; the results are still
+    those of the unconstrained mix."""
+    from paper_2107_05613_amd import amge
+    res = resident(32)
+    reqs = requests(res, 8, seed=3)
+    srv = amge.Server()
+    ids = [srv.add(H) for H in res.H]
+    per = [srv.request_bytes(i) for i in ids]
+    srv.close()
+    budget = 2 * max(per)
+    seen = []
+
+    def watch(s):
+        st = s.stats()
+        seen.append(st["inflight_bytes"])
+        assert st["inflight_bytes"] <= budget
+
+    lim = serve(res, reqs, list(range(len(reqs))), inflight_budget=budget, watch=watch)
+    free = serve(res, reqs, list(range(len(reqs))))
+    for j in range(len(reqs)):
+        assert lim[j][1] == free[j][1] and np.array_equal(lim[j][3], free[j][3])
+    assert max(seen) <= budget
+
+
+def test_budget_refusals_and_failed_requests():
+    """AMGE_ERR_BUSY for a hierarchy beyond the resident budget and for a request beyond
+    the in-flight budget; a NaN right-hand side and a maxit cut finish with their own
+    status while the other requests of the batch are unaffected."""
+    from paper_2107_05613_amd import amge
+    res = resident(32)
+    fp = [H.footprint() for H in res.H]
+    srv = amge.Server(hierarchy_budget=fp[0] + fp[1])
+    srv.add(res.H[0])
+    srv.add(res.H[1])
+    with pytest.raises(amge.AmgeError) as e:
+        srv.add(res.H[2])
+    assert e.value.code == -8
+    srv.close()
+    srv = amge.Server(inflight_budget=1024)
+    hid = srv.add(res.H[0])
+    b = torch.ones(res.n1[0], dtype=torch.float64, device="cuda")
+    with pytest.raises(amge.AmgeError) as e:
+        srv.submit(hid, b, torch.zeros_like(b), tag=0)
+    assert e.value.code == -8
+    srv.close()
+    # failures stay in their own column
+    reqs = [(0, torch.from_numpy(W.rhs(res.n1[0], 500 + i)[:, 0]).cuda()) for i in range(5)]
+    bad = reqs[1][1].clone()
+    bad[7] = float("nan")
+    reqs_bad = list(reqs)
+    reqs_bad[1] = (0, bad)
+    got = serve(res, reqs_bad, list(range(5)), maxit={3: 2})
+    ref = serve(res, reqs, [0, 2, 4])
+    assert got[1][0] == -7
+    assert got[3][0] == 1 and got[3][1] == 2
+    for j in (0, 2, 4):
+        assert got[j][0] == 0 and np.array_equal(got[j][3], ref[j][3])
