@@ -167,6 +167,62 @@ def run_batched(args, amge, W):
     }
 
 
+def run_serving(args):
+    """Serving mix: seeded requests over 20 resident hierarchies (H(curl)/H(div),
+    n in {16,24,32,48,64}, two coefficient-jump fields each), 8 columns per hierarchy.
+    First all requests at once (closed batch: capacity), then Poisson arrivals at 0.8 x
+    that capacity (open loop: p50/p99 latency)."""
+    import numpy as np
+    import torch
+    from paper_2107_05613_amd import serve
+    t0 = time.perf_counter()
+    mix = serve.build_mix(num=args.serving_requests, seed=0, slots=8, precond_bits=0)
+    print(f"[bench] serving: {len(mix.keys)} hierarchies built in {time.perf_counter() - t0:.1f}s "
+          f"(build {mix.build_s:.1f}s, device setup {mix.setup_s:.1f}s)", file=sys.stderr, flush=True)
+    srv, ids = serve.make_server(mix, chunk=2)
+    resident = srv.stats()["resident_bytes"]
+    prec = [h.precision_info() for h in mix.hierarchies]
+    n32 = sum(1 for k, b in prec if b == 32)
+    # warm-up: one request per hierarchy
+    first = {}
+    for j, h in enumerate(mix.hid_of):
+        first.setdefault(h, j)
+    serve.run(srv, ids, mix, order=list(first.values()))
+    done, lat, makespan = serve.run(srv, ids, mix)
+    capacity = len(done) / makespan
+    bad = sum(1 for v in done.values() if v[0] != 0)
+    print(f"[bench] serving closed batch: {capacity:.1f} solves/s ({makespan:.2f}s for {len(done)})",
+          file=sys.stderr, flush=True)
+    rate = 0.8 * capacity
+    arrivals = np.array([r["t_arrive"] for r in mix.requests]) / rate
+    done2, lat2, makespan2 = serve.run(srv, ids, mix, arrivals=arrivals)
+    st = serve.latency_stats(lat2)
+    bad += sum(1 for v in done2.values() if v[0] != 0)
+    iters = [v[1] for v in done2.values()]
+    print(f"[bench] serving open loop at {rate:.1f}/s: p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms",
+          file=sys.stderr, flush=True)
+    srv.close()
+    out = {
+        "workload": (f"{len(mix.requests)} seeded requests, H(curl)/H(div) on n^3x6 Kuhn tets with n in "
+                     f"{{16,24,32,48,64}} drawn uniformly, per-4^3-block coefficient jumps 10^U(-3,3) from a pool "
+                     f"of 2 seeds per (type, n): {len(mix.keys)} resident hierarchies, 8 PCG columns each; "
+                     f"V-cycle precision per hierarchy from its cancellation factor, per-column FP64 PCG "
+                     f"to rel-res 1e-8"),
+        "precision": {"fp32_hierarchies": n32, "fp64_hierarchies": len(prec) - n32,
+                      "kappa_range": [min(k for k, b in prec), max(k for k, b in prec)]},
+        "resident_bytes": resident,
+        "closed_batch": {"solves_per_s": capacity, "makespan_s": makespan,
+                         **{k: v for k, v in serve.latency_stats(lat).items()}},
+        "open_loop": {"arrival_rate_per_s": rate, "solves_per_s": len(done2) / makespan2, **st},
+        "iters": [int(min(iters)), int(max(iters))],
+        "failed_requests": bad,
+        "setup_s": {"build": mix.build_s, "device_setup": mix.setup_s},
+    }
+    del mix
+    torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +232,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-workload", default="div_n48_l5_rhs32",
                     help="multi-right-hand-side workload timed beside the main one ('' to skip)")
+    ap.add_argument("--serving-requests", type=int, default=256,
+                    help="requests of the serving mix run beside the main workload (0 to skip)")
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -269,6 +327,7 @@ def main():
 
     del H64
     batched = run_batched(args, amge, W) if args.batched_workload else None
+    serving = run_serving(args) if args.serving_requests > 0 else None
 
     value = args.steps / dt32
     k_avg_ms = k_ms / max(k_launches, 1)
@@ -321,6 +380,7 @@ def main():
         },
         "setup_s": {"build": t_build, "device_setup": t_setup},
         "batched": batched,
+        "serving": serving,
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

@@ -75,7 +75,9 @@ typedef struct {
     int32_t nu_primary;     /* l1-Jacobi sweeps on A_k per smoothing step (paper: 2)        */
     int32_t nu_aux;         /* l1-Jacobi sweeps on D^T A D per smoothing step (paper: 2)    */
     int32_t precond_bits;   /* 64: V-cycle in FP64; 32: FP32 values/accumulation in the
-                               V-cycle with the coarsest Cholesky solve kept in FP64        */
+                               V-cycle with the coarsest Cholesky solve kept in FP64;
+                               0: chosen at set-up, 32 unless 2^-24 * kappa > 0.1, kappa
+                               being the cancellation factor of amge_precision_info         */
     int32_t max_rhs;        /* largest nrhs the work buffers are sized for (>= 1)           */
 } amge_opts;
 
@@ -147,6 +149,13 @@ amge_status amge_timing_read(amge_hierarchy* h, double* ms, int64_t* launches, d
  * once for all columns), every vector stream once per column, the l1 scalings once,
  * and the coarsest inverse. */
 amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precision, int32_t nrhs, double* bytes);
+
+/* Cancellation factor kappa = max over levels and rows e of (|D|^T |A| |D| 1)_e /
+ * (|D^T A D| 1)_e (D^T A D keeps only the mass part of A, so products of A with vectors
+ * near the range of D cancel up to this factor; their rounding error is ~ u * kappa
+ * relative), and the preconditioner precision in use (32 or 64).  Either pointer may be
+ * NULL. */
+amge_status amge_precision_info(const amge_hierarchy* h, double* kappa, int32_t* precond_bits);
 
 /* Host sizes of a hierarchy: nlevels, and rows of A_k for k = 0..nlevels-1 (rows[] may be NULL). */
 amge_status amge_hierarchy_info(const amge_hierarchy* h, int32_t* nlevels, int32_t* rows);

@@ -63,6 +63,7 @@ def _load():
         "amge_pcg_solve": (i32, [vp, vp, vp, i32, f64, i32, i32, C.POINTER(i32), C.POINTER(f64), vp]),
         "amge_level_apply": (i32, [vp, i32, i32, i32, vp, vp, vp, vp]),
         "amge_hierarchy_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
+        "amge_precision_info": (i32, [vp, C.POINTER(f64), C.POINTER(i32)]),
         "amge_timing_enable": (i32, [vp, i32]),
         "amge_vcycle_bytes": (i32, [vp, i32, i32, C.POINTER(f64)]),
         "amge_timing_read": (i32, [vp, C.POINTER(f64), C.POINTER(C.c_int64), C.POINTER(f64)]),
@@ -91,7 +92,7 @@ _lib = _load()
 
 # Names declared by include/amge.h (checked by the test suite against the header).
 EXPORTS = ("amge_default_opts", "amge_setup_hierarchy", "amge_destroy", "amge_footprint", "amge_vcycle",
-           "amge_pcg_solve", "amge_level_apply", "amge_hierarchy_info", "amge_last_error",
+           "amge_pcg_solve", "amge_level_apply", "amge_hierarchy_info", "amge_precision_info", "amge_last_error",
            "amge_timing_enable", "amge_timing_read", "amge_vcycle_bytes",
            "amge_kuhn_build", "amge_problem_nlevels", "amge_problem_levels", "amge_problem_free",
            "amge_server_create", "amge_server_destroy", "amge_server_add", "amge_server_request_bytes",
@@ -245,6 +246,12 @@ class Hierarchy:
     @property
     def handle(self):
         return self._h
+
+    def precision_info(self):
+        """(kappa, precond_bits in use)."""
+        k, b = C.c_double(), C.c_int32()
+        _check(_lib.amge_precision_info(self._h, C.byref(k), C.byref(b)))
+        return k.value, b.value
 
     def footprint(self):
         b = C.c_size_t()

@@ -90,6 +90,7 @@ struct amge_hierarchy {
     std::vector<amge::DLevel> lv;
     amge_opts opts{};
     int nc = 0;                  // coarsest size
+    double kappa = 1.0;          // largest cancellation factor of the auxiliary matrices
     double* Ainv = nullptr;      // coarsest inverse from the Cholesky factor
     // outer PCG buffers (FP64, level-1 length)
     double *r = nullptr, *p = nullptr, *q = nullptr, *z[2] = {nullptr, nullptr};

@@ -812,6 +812,31 @@ void setup_batched(amge_hierarchy* H, const std::vector<HostLevel>& hl, hipStrea
     else tune_batched<double>(H, s);
 }
 
+// Cancellation factor of the auxiliary matrix on one level:
+//   max_e (|D|^T |A| |D| 1)_e / (|D^T A D| 1)_e.
+// D^T A D only keeps the mass part of A (the derivative part vanishes on the range of
+// D), so applying A to a vector near that range cancels terms up to this factor larger
+// than the result.  Evaluated in a precision with unit roundoff u, such products carry
+// relative errors up to u * kappa in exactly the components the auxiliary space of the
+// smoother and the coarse levels must resolve.
+double cancellation_factor(const Csr& A, const Csr& D, const Csr& Dt, const std::vector<double>& dh) {
+    const std::vector<double> v = l1_row_sums(D);
+    std::vector<double> w(A.nrows, 0.0);
+    for (int i = 0; i < A.nrows; ++i)
+        for (int k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) w[i] += std::fabs(A.val[k]) * v[A.col[k]];
+    double kap = 1.0;
+    for (int e = 0; e < Dt.nrows; ++e) {
+        double num = 0;
+        for (int k = Dt.rowptr[e]; k < Dt.rowptr[e + 1]; ++k) num += std::fabs(Dt.val[k]) * w[Dt.col[k]];
+        if (dh[e] > 0) kap = std::max(kap, num / dh[e]);
+    }
+    return kap;
+}
+
+// Automatic preconditioner precision: FP32 unless the cancellation factor would let
+// FP32 rounding reach a tenth of the near-kernel components.
+constexpr double AUTO_FP32_LIMIT = 0.1;
+
 void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     if (!levels || nl < 1) fail(AMGE_ERR_ARG, "need at least one level");
     std::vector<Csr> A(nl), D(nl), P(nl);
@@ -845,6 +870,7 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         Csr DtA = spgemm(Dt, A[k]);                 // D^T A, for the auxiliary residual
         Csr Ah = spgemm(DtA, D[k]);                 // auxiliary matrix D^T A D (eq. (4.1))
         std::vector<double> d = l1_row_sums(A[k]), dh = l1_row_sums(Ah);
+        H->kappa = std::max(H->kappa, cancellation_factor(A[k], D[k], Dt, dh));
         std::vector<double> dinv(d.size()), dhinv(dh.size());
         for (size_t i = 0; i < d.size(); ++i) {
             if (!(d[i] > 0)) fail(AMGE_ERR_NOT_SPD, "zero row in A_k");
@@ -901,6 +927,8 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     H->part_dots[1] = H->alloc<double>(3 * dev::NRED);
     H->st = H->alloc<dev::PcgStatus>(1);
     H->flags = H->alloc<int>(2);
+    if (H->opts.precond_bits == 0)
+        H->opts.precond_bits = std::ldexp(H->kappa, -24) <= AUTO_FP32_LIMIT ? 32 : 64;
     if (batched) setup_batched(H, hl, s);
     HIPCHECK(hipStreamSynchronize(s));
 }
@@ -1150,7 +1178,7 @@ extern "C" amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nl
         if (opts) H->opts = *opts;
         else amge_default_opts(&H->opts);
         if (H->opts.nu_primary < 0 || H->opts.nu_aux < 0 || H->opts.max_rhs < 1 || H->opts.max_rhs > 64 ||
-            (H->opts.precond_bits != 32 && H->opts.precond_bits != 64))
+            (H->opts.precond_bits != 0 && H->opts.precond_bits != 32 && H->opts.precond_bits != 64))
             fail(AMGE_ERR_ARG, "invalid options");
         setup(H.get(), levels, nlevels, (hipStream_t)stream);
         *out = H.release();
@@ -1166,6 +1194,16 @@ extern "C" amge_status amge_footprint(const amge_hierarchy* h, size_t* bytes) {
         return AMGE_ERR_ARG;
     }
     *bytes = h->bytes;
+    return AMGE_OK;
+}
+
+extern "C" amge_status amge_precision_info(const amge_hierarchy* h, double* kappa, int32_t* precond_bits) {
+    if (!h) {
+        set_last_error("null argument");
+        return AMGE_ERR_ARG;
+    }
+    if (kappa) *kappa = h->kappa;
+    if (precond_bits) *precond_bits = h->opts.precond_bits;
     return AMGE_OK;
 }
 

@@ -28,11 +28,12 @@ class Mix:
     setup_s: float = 0.0
 
 
-def build_mix(num=256, seed=0, sizes=(16, 24, 32, 48, 64), coef_pool=2, slots=8, precond_bits=32,
+def build_mix(num=256, seed=0, sizes=(16, 24, 32, 48, 64), coef_pool=2, slots=8, precond_bits=0,
               nu_primary=2, nu_aux=2):
     """Hierarchies for every (kind, n, coefficient seed) of the stream (coefficients as the
     jump workload: per 4^3-hex block 10^U(-3,3)), and one right-hand side per request
-    (seed = request id)."""
+    (seed = request id).  precond_bits 0 lets every hierarchy pick its V-cycle precision
+    from its cancellation factor."""
     import torch
     reqs = W.serving_requests(num, seed, sizes, coef_pool, rate=1.0)
     keys = sorted({(r["kind"], r["n"], r["coef_seed"]) for r in reqs})
@@ -64,7 +65,7 @@ def make_server(mix, hierarchy_budget=0, inflight_budget=0, chunk=2):
     return srv, ids
 
 
-def run(srv, ids, mix, arrivals=None, order=None, rtol=1e-8, maxit=500, poll_sleep=20e-6):
+def run(srv, ids, mix, arrivals=None, order=None, rtol=1e-8, maxit=1000, poll_sleep=20e-6):
     """Feeds the requests of `order` (default: all) to the server at their arrival times
     (seconds from the start; None: all at once, a closed batch) and waits for all of them.
 

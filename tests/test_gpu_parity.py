@@ -257,3 +257,17 @@ def test_deterministic():
         c.gpu[32].pcg(dev(c.b), x, rtol=1e-8)
         xs.append(host(x))
     assert np.array_equal(xs[0], xs[1])
+
+
+@pytest.mark.parametrize("spec", [("curl", 12, 3, "unit"), ("div", 8, 3, "blocks"), ("div", 32, 4, "blocks")])
+def test_cancellation_factor_and_auto_precision(spec):
+    """The library's cancellation factor equals the one computed from the oracle's
+    hierarchy, and precond_bits = 0 picks FP32 exactly when 2^-24 kappa <= 0.1."""
+    amge = _amge()
+    c = case(*spec)
+    H = amge.Hierarchy(c.prod, precond_bits=0)
+    kap, bits = H.precision_info()
+    print(f"{spec}: kappa library {kap:.6e}, oracle {c.kappa:.6e}, auto precision FP{bits}")
+    assert abs(kap - c.kappa) <= 1e-9 * c.kappa
+    assert bits == (32 if 2.0 ** -24 * c.kappa <= 0.1 else 64)
+    H.close()
