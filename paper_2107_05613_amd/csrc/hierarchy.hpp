@@ -26,7 +26,9 @@ struct DSell {
     int64_t stored = 0;       // entries including padding
     int* sptr = nullptr;      // nslices + 1 entry offsets
     int* srow = nullptr;      // slot -> row (-1: empty slot)
-    int* ci = nullptr;        // value matrices: column indices
+    int* ci = nullptr;        // value matrices: column indices (or, when every slice's
+    uint16_t* c16 = nullptr;  //   columns span < 65536: 16-bit offsets from a per-slice
+    int* cbase = nullptr;     //   base column, ci = nullptr)
     uint32_t* ent = nullptr;  // incidence matrices: column | sign << 31, padding 0xffffffff
     double* v64 = nullptr;
     float* v32 = nullptr;
@@ -93,7 +95,7 @@ struct amge_hierarchy {
     double kappa = 1.0;          // largest cancellation factor of the auxiliary matrices
     double* Ainv = nullptr;      // coarsest inverse from the Cholesky factor
     // outer PCG buffers (FP64, level-1 length)
-    double *r = nullptr, *p = nullptr, *q = nullptr, *z[2] = {nullptr, nullptr};
+    double *r = nullptr, *p = nullptr, *q = nullptr, *z[2] = {nullptr, nullptr}, *x = nullptr;
     double *part_pq = nullptr, *part_dots[2] = {nullptr, nullptr};
     amge::dev::PcgStatus* st = nullptr;
     int* flags = nullptr;        // [0] done, [1] breakdown
@@ -104,15 +106,18 @@ struct amge_hierarchy {
     int bnblk = 0;
     amge::dev::ColState* cs = nullptr;
     amge::dev::BatchStatus* bs = nullptr;
-    int* zero_flag = nullptr;    // a device 0 for batched kernels run outside PCG
-    hipStream_t gstream = nullptr;   // stream for graph capture / replay
+    int* zero_flag = nullptr;    // a device 0: the stop flag of launches outside PCG iterations
+    hipStream_t gstream = nullptr;   // the hierarchy's stream for graph capture / replay
     hipGraphExec_t gexec = nullptr;  // one captured batched PCG iteration
+    hipGraphExec_t pexec = nullptr;  // two captured single-column PCG iterations
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<void*> allocs;
     size_t bytes = 0;
     amge::Probe probe;
     ~amge_hierarchy() {
+        if (gstream) (void)hipStreamSynchronize(gstream);
         if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (pexec) (void)hipGraphExecDestroy(pexec);
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (gstream) (void)hipStreamDestroy(gstream);

@@ -59,25 +59,37 @@ __device__ __forceinline__ T row_sum(T v) {
     return v;
 }
 
-template <typename T, int K, int MODE>
+// Column index of stored entry e of a slice: 32-bit indices, or (C16) a 16-bit offset
+// from the slice's base column.
+template <bool C16>
+__device__ __forceinline__ int col_at(const int* __restrict__ ci, const uint16_t* __restrict__ c16, int cb, int e) {
+    if (C16) return cb + (int)c16[e];
+    return ci[e];
+}
+
+template <typename T, int K, int MODE, bool C16>
 __global__ void __launch_bounds__(BLOCK)
 k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const int* __restrict__ ci,
-       const T* __restrict__ av, const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv,
-       T* __restrict__ y, T* __restrict__ yd, int nsplit) {
+       const uint16_t* __restrict__ c16, const int* __restrict__ cbase, const T* __restrict__ av,
+       const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv, T* __restrict__ y,
+       T* __restrict__ yd, int nsplit, const int* __restrict__ stop) {
     // SPMV / SPLIT with yd != null also write yd = dinv * y: the first l1-Jacobi sweep
     // from zero on the next operator, produced where its right-hand side is produced.
+    // Every launch of the PCG iteration returns at once when *stop is set (converged).
+    if (*stop) return;
     const int slice = xcd_block(blockIdx.x, gridDim.x) * WAVES + (threadIdx.x >> 6);
     if (slice >= nslices) return;
     const int lane = threadIdx.x & 63;
     const int base = sptr[slice];
     const int width = (sptr[slice + 1] - base) >> 6;
     const int row = srow[slice * (64 / K) + lane / K];
-    const int* c = ci + base + lane;
-    const T* v = av + base + lane;
+    const int cb = C16 ? cbase[slice] : 0;
+    const int e0 = base + lane;
+    const T* v = av + e0;
     T acc = 0;
 #pragma unroll 4
     for (int k = 0; k < width; ++k) {
-        const int j = c[k * 64];
+        const int j = col_at<C16>(ci, c16, cb, e0 + k * 64);
         T xv;
         if (MODE == SPLIT) xv = j < nsplit ? b[j] : x[j - nsplit];
         else xv = x[j];
@@ -97,7 +109,8 @@ k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, 
 template <typename T, int K, int ADD>
 __global__ void __launch_bounds__(BLOCK)
 k_sell_inc(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const uint32_t* __restrict__ ent,
-           const T* __restrict__ x, T* __restrict__ y) {
+           const T* __restrict__ x, T* __restrict__ y, const int* __restrict__ stop) {
+    if (*stop) return;
     const int slice = xcd_block(blockIdx.x, gridDim.x) * WAVES + (threadIdx.x >> 6);
     if (slice >= nslices) return;
     const int lane = threadIdx.x & 63;
@@ -132,7 +145,9 @@ k_scale(int n, const T* __restrict__ dinv, const T* __restrict__ x, T* __restric
 // formed at set-up; FP64 arithmetic whatever T is.  One wave per row.
 template <typename T>
 __global__ void __launch_bounds__(BLOCK)
-k_coarse(int n, const double* __restrict__ Ainv, const T* __restrict__ b, T* __restrict__ x) {
+k_coarse(int n, const double* __restrict__ Ainv, const T* __restrict__ b, T* __restrict__ x,
+         const int* __restrict__ stop) {
+    if (*stop) return;
     const int row = blockIdx.x * WAVES + (threadIdx.x >> 6);
     if (row >= n) return;
     const int lane = threadIdx.x & 63;
@@ -177,11 +192,12 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 
 // q = A p (FP64 sliced ELL) and partial sums of p.q.  NRED blocks, each over a
 // contiguous range of slices.
-template <int K>
+template <int K, bool C16>
 __global__ void __launch_bounds__(BLOCK)
 k_pcg_ap(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const int* __restrict__ ci,
-         const double* __restrict__ av, const double* __restrict__ p, double* __restrict__ q,
-         double* __restrict__ part, const int* __restrict__ done) {
+         const uint16_t* __restrict__ c16, const int* __restrict__ cbase, const double* __restrict__ av,
+         const double* __restrict__ p, double* __restrict__ q, double* __restrict__ part,
+         const int* __restrict__ done) {
     __shared__ double sh[WAVES + 1];
     if (*done) return;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
@@ -193,11 +209,12 @@ k_pcg_ap(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow
         const int base = sptr[slice];
         const int width = (sptr[slice + 1] - base) >> 6;
         const int row = srow[slice * (64 / K) + lane / K];
-        const int* c = ci + base + lane;
-        const double* v = av + base + lane;
+        const int cb = C16 ? cbase[slice] : 0;
+        const int e0 = base + lane;
+        const double* v = av + e0;
         double acc = 0;
 #pragma unroll 4
-        for (int k = 0; k < width; ++k) acc = fma(v[k * 64], p[c[k * 64]], acc);
+        for (int k = 0; k < width; ++k) acc = fma(v[k * 64], p[col_at<C16>(ci, c16, cb, e0 + k * 64)], acc);
         acc = row_sum<K>(acc);
         if (row >= 0 && !(lane & (K - 1))) {
             q[row] = acc;
@@ -271,9 +288,12 @@ k_pcg_dots(int n, const float* __restrict__ z32, double* __restrict__ z, const d
 __global__ void __launch_bounds__(BLOCK)
 k_pcg_p(int n, const double* __restrict__ part_new, const double* __restrict__ part_old,
         const double* __restrict__ z, double* __restrict__ p, PcgStatus* __restrict__ st,
-        int* __restrict__ done, const int* __restrict__ flag, double rtol, int stop_l2, int maxit, int it) {
+        int* __restrict__ done, const int* __restrict__ flag) {
     __shared__ double sh[WAVES + 1];
     if (*done) return;
+    // iteration count and stopping parameters: st->iters changes only in k_pcg_finish
+    const int it = st->iters, maxit = st->maxit, stop_l2 = st->stop_l2;
+    const double rtol = st->rtol;
     const double dnew = sum_partials(part_new, sh);
     const double rzold = sum_partials(part_new + NRED, sh);
     const double rr = sum_partials(part_new + 2 * NRED, sh);
@@ -289,21 +309,27 @@ k_pcg_p(int n, const double* __restrict__ part_new, const double* __restrict__ p
         st->delta = dnew;
         st->rr = rr;
         st->relres = rel;
-        st->iters = it + 1;
         st->breakdown = *flag;
     }
 }
 
-// Marks the iteration loop finished (separate launch, so no block of k_pcg_p can
-// observe the flag change mid-kernel).
-__global__ void k_pcg_finish(const PcgStatus* __restrict__ st, int* __restrict__ done, double rtol, int maxit) {
+// Counts the iteration and marks the loop finished (separate launch, so no block of
+// k_pcg_p can observe the changes mid-kernel).
+__global__ void k_pcg_finish(PcgStatus* __restrict__ st, int* __restrict__ done) {
     if (*done) return;
-    const bool stop = st->breakdown || (rtol > 0 && st->relres <= rtol) || (st->iters >= maxit) || !isfinite(st->delta);
-    if (stop) *done = 1;
+    st->iters += 1;
+    const bool stop = st->breakdown || (st->rtol > 0 && st->relres <= st->rtol) || (st->iters >= st->maxit) ||
+                      !isfinite(st->delta);
+    if (stop) {
+        *done = 1;
+        st->done = 1;
+    }
 }
 
-// Initial quantities: delta0 = r.z, bnorm = ||b||, from the dots partials.
-__global__ void k_pcg_init(const double* __restrict__ part, PcgStatus* __restrict__ st) {
+// Initial quantities: delta0 = r.z, bnorm = ||b||, from the dots partials; stopping
+// parameters of the solve.
+__global__ void k_pcg_init(const double* __restrict__ part, PcgStatus* __restrict__ st, double rtol, int maxit,
+                           int stop_l2) {
     __shared__ double sh[WAVES + 1];
     const double d = sum_partials(part, sh);
     const double rr = sum_partials(part + 2 * NRED, sh);
@@ -314,7 +340,11 @@ __global__ void k_pcg_init(const double* __restrict__ part, PcgStatus* __restric
         st->bnorm = sqrt(rr);
         st->relres = 1.0;
         st->iters = 0;
+        st->done = 0;
         st->breakdown = 0;
+        st->rtol = rtol;
+        st->maxit = maxit;
+        st->stop_l2 = stop_l2;
     }
 }
 

@@ -40,7 +40,22 @@ struct HostSell {
     std::vector<int> sptr, srow, ci;
     std::vector<uint32_t> ent;
     std::vector<double> val;
+    // compact column indices: per-slice base + 16-bit offsets, used when every slice's
+    // columns fit in 65536 consecutive indices (padding entries: offset 0)
+    bool compact = false;
+    std::vector<int> cbase;
+    std::vector<uint16_t> c16;
 };
+
+// 16-bit column offsets on (default); AMGE_INDEX32=1 keeps 32-bit indices everywhere.
+static bool compact_indices() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = getenv("AMGE_INDEX32");
+        v = (e && *e && *e != '0') ? 0 : 1;
+    }
+    return v == 1;
+}
 
 HostSell make_sell(const Csr& A, bool incidence, int K) {
     const int R = 64 / K;
@@ -92,6 +107,37 @@ HostSell make_sell(const Csr& A, bool incidence, int K) {
                 }
             }
         }
+    if (!incidence) {
+        h.cbase.assign(h.nslices, 0);
+        bool fits = true;
+        for (int sl = 0; sl < h.nslices && fits; ++sl) {
+            int lo = INT32_MAX, hi = -1;
+            for (int rr = 0; rr < R; ++rr) {
+                int r = h.srow[(size_t)sl * R + rr];
+                if (r < 0) continue;
+                for (int t = A.rowptr[r]; t < A.rowptr[r + 1]; ++t) {
+                    lo = std::min(lo, A.col[t]);
+                    hi = std::max(hi, A.col[t]);
+                }
+            }
+            if (hi < 0) continue;
+            h.cbase[sl] = lo;
+            fits = hi - lo <= 65535;
+        }
+        if (fits) {
+            h.compact = true;
+            h.c16.assign(stored, 0);
+            for (int sl = 0; sl < h.nslices; ++sl)
+                for (int rr = 0; rr < R; ++rr) {
+                    int r = h.srow[(size_t)sl * R + rr];
+                    if (r < 0) continue;
+                    for (int t = 0; t < len(r); ++t) {
+                        size_t idx = (size_t)h.sptr[sl] + (size_t)(t / K) * 64 + rr * K + t % K;
+                        h.c16[idx] = (uint16_t)(A.col[A.rowptr[r] + t] - h.cbase[sl]);
+                    }
+                }
+        }
+    }
     return h;
 }
 
@@ -109,7 +155,12 @@ DSell upload_sell(amge_hierarchy* H, const Csr& A, bool incidence, int K, hipStr
     if (incidence) {
         d.ent = upload(H, h.ent.data(), h.ent.size(), s);
     } else {
-        d.ci = upload(H, h.ci.data(), h.ci.size(), s);
+        if (h.compact && compact_indices()) {
+            d.c16 = upload(H, h.c16.data(), h.c16.size(), s);
+            d.cbase = upload(H, h.cbase.data(), h.cbase.size(), s);
+        } else {
+            d.ci = upload(H, h.ci.data(), h.ci.size(), s);
+        }
         d.v64 = upload(H, h.val.data(), h.val.size(), s);
         std::vector<float> v32(h.val.begin(), h.val.end());   // round to nearest
         d.v32 = upload(H, v32.data(), v32.size(), s);
@@ -128,55 +179,67 @@ template <> const double* vals<double>(const DSell& M) { return M.v64; }
 
 template <class T, int K>
 void sell_k(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* y, T* yd, hipStream_t s,
-            int nsplit) {
+            int nsplit, const int* stop) {
     unsigned g = grid_slices(M.nslices);
     if (g == 0) return;
     const T* v = vals<T>(M);
-#define AMGE_SELL(MODE) \
-    dev::k_sell<T, K, MODE><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ci, v, x, b, dinv, y, yd, nsplit)
-    switch (mode) {
-        case dev::SPMV: AMGE_SELL(dev::SPMV); break;
-        case dev::SPMV_ADD: AMGE_SELL(dev::SPMV_ADD); break;
-        case dev::RESID: AMGE_SELL(dev::RESID); break;
-        case dev::JAC: AMGE_SELL(dev::JAC); break;
-        default: AMGE_SELL(dev::SPLIT); break;
+#define AMGE_SELL(MODE, C16)                                                                              \
+    dev::k_sell<T, K, MODE, C16><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ci, M.c16, M.cbase, v, x, b, \
+                                                     dinv, y, yd, nsplit, stop)
+    if (M.c16) {
+        switch (mode) {
+            case dev::SPMV: AMGE_SELL(dev::SPMV, true); break;
+            case dev::SPMV_ADD: AMGE_SELL(dev::SPMV_ADD, true); break;
+            case dev::RESID: AMGE_SELL(dev::RESID, true); break;
+            case dev::JAC: AMGE_SELL(dev::JAC, true); break;
+            default: AMGE_SELL(dev::SPLIT, true); break;
+        }
+    } else {
+        switch (mode) {
+            case dev::SPMV: AMGE_SELL(dev::SPMV, false); break;
+            case dev::SPMV_ADD: AMGE_SELL(dev::SPMV_ADD, false); break;
+            case dev::RESID: AMGE_SELL(dev::RESID, false); break;
+            case dev::JAC: AMGE_SELL(dev::JAC, false); break;
+            default: AMGE_SELL(dev::SPLIT, false); break;
+        }
     }
 #undef AMGE_SELL
 }
 
-// mode as in dev::Mode; yd (SPMV, SPLIT) receives dinv * y when non-null.
+// mode as in dev::Mode; yd (SPMV, SPLIT) receives dinv * y when non-null.  stop: device
+// flag, the launch does nothing while it is set (PCG iterations after convergence).
 template <class T>
-void sell(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s, int nsplit = 0,
-          T* yd = nullptr) {
+void sell(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s, const int* stop,
+          int nsplit = 0, T* yd = nullptr) {
     switch (M.K) {
-        case 1: sell_k<T, 1>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
-        case 2: sell_k<T, 2>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
-        case 4: sell_k<T, 4>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
-        case 8: sell_k<T, 8>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
-        case 16: sell_k<T, 16>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
-        case 32: sell_k<T, 32>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
-        default: sell_k<T, 64>(M, mode, x, b, dinv, y, yd, s, nsplit); break;
+        case 1: sell_k<T, 1>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
+        case 2: sell_k<T, 2>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
+        case 4: sell_k<T, 4>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
+        case 8: sell_k<T, 8>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
+        case 16: sell_k<T, 16>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
+        case 32: sell_k<T, 32>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
+        default: sell_k<T, 64>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
     }
 }
 
 template <class T, int K>
-void sell_inc_k(const DSell& M, int add, const T* x, T* y, hipStream_t s) {
+void sell_inc_k(const DSell& M, int add, const T* x, T* y, hipStream_t s, const int* stop) {
     unsigned g = grid_slices(M.nslices);
     if (g == 0) return;
-    if (add) dev::k_sell_inc<T, K, 1><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ent, x, y);
-    else dev::k_sell_inc<T, K, 0><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ent, x, y);
+    if (add) dev::k_sell_inc<T, K, 1><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ent, x, y, stop);
+    else dev::k_sell_inc<T, K, 0><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ent, x, y, stop);
 }
 
 template <class T>
-void sell_inc(const DSell& M, int add, const T* x, T* y, hipStream_t s) {
+void sell_inc(const DSell& M, int add, const T* x, T* y, hipStream_t s, const int* stop) {
     switch (M.K) {
-        case 1: sell_inc_k<T, 1>(M, add, x, y, s); break;
-        case 2: sell_inc_k<T, 2>(M, add, x, y, s); break;
-        case 4: sell_inc_k<T, 4>(M, add, x, y, s); break;
-        case 8: sell_inc_k<T, 8>(M, add, x, y, s); break;
-        case 16: sell_inc_k<T, 16>(M, add, x, y, s); break;
-        case 32: sell_inc_k<T, 32>(M, add, x, y, s); break;
-        default: sell_inc_k<T, 64>(M, add, x, y, s); break;
+        case 1: sell_inc_k<T, 1>(M, add, x, y, s, stop); break;
+        case 2: sell_inc_k<T, 2>(M, add, x, y, s, stop); break;
+        case 4: sell_inc_k<T, 4>(M, add, x, y, s, stop); break;
+        case 8: sell_inc_k<T, 8>(M, add, x, y, s, stop); break;
+        case 16: sell_inc_k<T, 16>(M, add, x, y, s, stop); break;
+        case 32: sell_inc_k<T, 32>(M, add, x, y, s, stop); break;
+        default: sell_inc_k<T, 64>(M, add, x, y, s, stop); break;
     }
 }
 
@@ -225,7 +288,9 @@ int tune_lanes(const Csr& A, bool incidence, hipStream_t s) {
         amge_hierarchy tmp;   // owns the trial buffers
         float* x = tmp.alloc<float>(A.ncols);
         float* y = tmp.alloc<float>(A.nrows);
+        int* zero = tmp.alloc<int>(1);
         HIPCHECK(hipMemsetAsync(x, 0, sizeof(float) * A.ncols, s));
+        HIPCHECK(hipMemsetAsync(zero, 0, sizeof(int), s));
         hipEvent_t e0, e1;
         HIPCHECK(hipEventCreate(&e0));
         HIPCHECK(hipEventCreate(&e1));
@@ -234,8 +299,8 @@ int tune_lanes(const Csr& A, bool incidence, hipStream_t s) {
             amge_hierarchy t2;
             DSell M = upload_sell(&t2, A, incidence, K, s);
             auto run = [&]() {
-                if (incidence) sell_inc<float>(M, 0, x, y, s);
-                else sell<float>(M, dev::SPMV, x, nullptr, nullptr, y, s);
+                if (incidence) sell_inc<float>(M, 0, x, y, s, zero);
+                else sell<float>(M, dev::SPMV, x, nullptr, nullptr, y, s, zero);
             };
             for (int i = 0; i < 2; ++i) run();
             float ms = 1e30f;
@@ -273,10 +338,10 @@ DSell upload_tuned(amge_hierarchy* H, const Csr& A, bool incidence, hipStream_t 
 // algorithmic bytes are counted: values + column indices, one row index per row, and
 // the vector streams of the mode (x gathered once, b, dinv, y).
 template <class T>
-void asell(DLevel& L, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s) {
+void asell(DLevel& L, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s, const int* stop) {
     Probe* pr = L.probe;
     if (!pr || !pr->on) {
-        sell<T>(L.A, mode, x, b, dinv, y, s);
+        sell<T>(L.A, mode, x, b, dinv, y, s, stop);
         return;
     }
     if (pr->ev.size() < 2 * (pr->used + 1)) {
@@ -287,11 +352,11 @@ void asell(DLevel& L, int mode, const T* x, const T* b, const T* dinv, T* y, hip
         pr->ev.push_back(c);
     }
     HIPCHECK(hipEventRecord(pr->ev[2 * pr->used], s));
-    sell<T>(L.A, mode, x, b, dinv, y, s);
+    sell<T>(L.A, mode, x, b, dinv, y, s, stop);
     HIPCHECK(hipEventRecord(pr->ev[2 * pr->used + 1], s));
     pr->used++;
     const double nv = mode == dev::JAC ? 4 : 3;   // JAC: x, b, dinv, y; others: three streams
-    pr->bytes += (double)L.A.nnz * (sizeof(T) + 4) + 4.0 * L.n + nv * sizeof(T) * L.n;
+    pr->bytes += (double)L.A.nnz * (sizeof(T) + (L.A.c16 ? 2 : 4)) + 4.0 * L.n + nv * sizeof(T) * L.n;
 }
 
 template <class T>
@@ -300,9 +365,19 @@ void scale(int n, const T* dinv, const T* x, T* y, hipStream_t s) {
 }
 
 template <class T>
-void coarse_solve(amge_hierarchy* H, const T* b, T* x, hipStream_t s) {
+void coarse_solve(amge_hierarchy* H, const T* b, T* x, hipStream_t s, const int* stop) {
     int n = H->nc;
-    dev::k_coarse<T><<<(unsigned)((n + WAVES - 1) / WAVES), BLOCK, 0, s>>>(n, H->Ainv, b, x);
+    dev::k_coarse<T><<<(unsigned)((n + WAVES - 1) / WAVES), BLOCK, 0, s>>>(n, H->Ainv, b, x, stop);
+}
+
+template <class T>
+void copy_vec(int64_t n, const T* a, T* b, hipStream_t s, const int* stop) {
+    if (n) dev::k_copy<T><<<(unsigned)std::min<int64_t>(grid_for(n), 4096), BLOCK, 0, s>>>(n, a, b, stop);
+}
+
+template <class T>
+void fill_zero(int64_t n, T* x, hipStream_t s, const int* stop) {
+    if (n) dev::k_fill<T><<<(unsigned)std::min<int64_t>(grid_for(n), 4096), BLOCK, 0, s>>>(n, x, stop);
 }
 
 template <class S, class D>
@@ -316,22 +391,23 @@ void convert(int64_t n, const S* a, D* b, hipStream_t s) {
 // first launched sweep starts from bd.  x and xt are swapped by the ping-pong; the
 // caller tracks where the result is.
 template <class T>
-void primary(DLevel& L, const T* b, const T* bd, T*& x, T*& xt, bool from_zero, int nu, hipStream_t s) {
+void primary(DLevel& L, const T* b, const T* bd, T*& x, T*& xt, bool from_zero, int nu, hipStream_t s,
+             const int* stop) {
     Work<T>& w = L.w<T>();
     int k = 0;
     if (from_zero) {
         if (nu >= 2) {
-            asell<T>(L, dev::JAC, bd, b, w.dinv, x, s);
+            asell<T>(L, dev::JAC, bd, b, w.dinv, x, s, stop);
             k = 2;
         } else if (nu == 1) {
-            HIPCHECK(hipMemcpyAsync(x, bd, sizeof(T) * L.n, hipMemcpyDeviceToDevice, s));
+            copy_vec<T>(L.n, bd, x, s, stop);
             k = 1;
         } else {
-            HIPCHECK(hipMemsetAsync(x, 0, sizeof(T) * L.n, s));
+            fill_zero<T>(L.n, x, s, stop);
         }
     }
     for (; k < nu; ++k) {
-        asell<T>(L, dev::JAC, x, b, w.dinv, xt, s);
+        asell<T>(L, dev::JAC, x, b, w.dinv, xt, s, stop);
         std::swap(x, xt);
     }
 }
@@ -340,28 +416,28 @@ void primary(DLevel& L, const T* b, const T* bd, T*& x, T*& xt, bool from_zero, 
 // nu l1-Jacobi sweeps on D^T A D from zero.  The residual kernel also writes the first
 // sweep gd = dhinv g.
 template <class T>
-void auxiliary(DLevel& L, const T* b, T* x, int nu, hipStream_t s) {
+void auxiliary(DLevel& L, const T* b, T* x, int nu, hipStream_t s, const int* stop) {
     if (nu <= 0 || L.m == 0) return;
     Work<T>& w = L.w<T>();
-    sell<T>(L.Aux, dev::SPLIT, x, b, w.dhinv, w.g, s, L.n, w.gd);
+    sell<T>(L.Aux, dev::SPLIT, x, b, w.dhinv, w.g, s, stop, L.n, w.gd);
     const T* y = w.gd;
     T* ya = w.y;
     T* yb = w.yt;
     for (int k = 1; k < nu; ++k) {
-        sell<T>(L.Ah, dev::JAC, y, w.g, w.dhinv, ya, s);
+        sell<T>(L.Ah, dev::JAC, y, w.g, w.dhinv, ya, s, stop);
         y = ya;
         std::swap(ya, yb);
     }
-    sell_inc<T>(L.D, 1, y, x, s);
+    sell_inc<T>(L.D, 1, y, x, s, stop);
 }
 
 // One V-cycle (Algorithm 4.1, x0 = 0) from level l down: b and bd = dinv b are the
 // level's right-hand side and first sweep, the result goes to xout.
 template <class T>
-void vcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, hipStream_t s) {
+void vcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, hipStream_t s, const int* stop) {
     const int nl = (int)H->lv.size();
     if (l == nl - 1) {
-        coarse_solve<T>(H, b, xout, s);
+        coarse_solve<T>(H, b, xout, s, stop);
         return;
     }
     DLevel& L = H->lv[l];
@@ -373,19 +449,19 @@ void vcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, hi
     const int nup = H->opts.nu_primary, nua = H->opts.nu_aux;
     const bool next_coarsest = l + 1 == nl - 1;
     // pre-smoothing with Mbar (eq. (4.1)): primary, then auxiliary
-    primary<T>(L, b, bd, x, xt, true, nup, s);
-    auxiliary<T>(L, b, x, nua, s);
+    primary<T>(L, b, bd, x, xt, true, nup, s, stop);
+    auxiliary<T>(L, b, x, nua, s, stop);
     // restriction of the residual (and the coarse first sweep), coarse correction,
     // prolongation
-    asell<T>(L, dev::RESID, x, b, nullptr, w.r, s);
-    sell<T>(L.Pt, dev::SPMV, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, s, 0,
+    asell<T>(L, dev::RESID, x, b, nullptr, w.r, s, stop);
+    sell<T>(L.Pt, dev::SPMV, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, s, stop, 0,
             next_coarsest ? nullptr : wc.bd);
-    vcycle_level<T>(H, l + 1, wc.b, wc.bd, wc.x, s);
-    sell<T>(L.P, dev::SPMV_ADD, wc.x, nullptr, nullptr, x, s);
+    vcycle_level<T>(H, l + 1, wc.b, wc.bd, wc.x, s, stop);
+    sell<T>(L.P, dev::SPMV_ADD, wc.x, nullptr, nullptr, x, s, stop);
     // post-smoothing with Mbar^T: auxiliary first, then primary
-    auxiliary<T>(L, b, x, nua, s);
-    primary<T>(L, b, nullptr, x, xt, false, nup, s);
-    if (x != xout) HIPCHECK(hipMemcpyAsync(xout, x, sizeof(T) * L.n, hipMemcpyDeviceToDevice, s));
+    auxiliary<T>(L, b, x, nua, s, stop);
+    primary<T>(L, b, nullptr, x, xt, false, nup, s, stop);
+    if (x != xout) copy_vec<T>(L.n, x, xout, s, stop);
 }
 
 // z = B r on level-1 vectors in FP64; the FP32 path rounds r, runs the V-cycle in FP32
@@ -395,11 +471,11 @@ void precondition(amge_hierarchy* H, const double* r, double* z, hipStream_t s) 
     if (H->opts.precond_bits == 32) {
         convert<double, float>(L.n, r, L.w32.b, s);
         scale<float>(L.n, L.w32.dinv, L.w32.b, L.w32.bd, s);
-        vcycle_level<float>(H, 0, L.w32.b, L.w32.bd, L.w32.x, s);
+        vcycle_level<float>(H, 0, L.w32.b, L.w32.bd, L.w32.x, s, H->zero_flag);
         convert<float, double>(L.n, L.w32.x, z, s);
     } else {
         scale<double>(L.n, L.w64.dinv, r, L.w64.bd, s);
-        vcycle_level<double>(H, 0, r, L.w64.bd, z, s);
+        vcycle_level<double>(H, 0, r, L.w64.bd, z, s, H->zero_flag);
     }
 }
 
@@ -776,8 +852,6 @@ void setup_batched(amge_hierarchy* H, const std::vector<HostLevel>& hl, hipStrea
     H->lgNC = lg;
     const bool f32 = H->opts.precond_bits == 32;
     const int nl = (int)H->lv.size();
-    H->zero_flag = H->alloc<int>(1);
-    HIPCHECK(hipMemsetAsync(H->zero_flag, 0, sizeof(int), s));
     for (int k = 0; k < nl; ++k) {
         DLevel& L = H->lv[k];
         const HostLevel& h = hl[k];
@@ -805,9 +879,6 @@ void setup_batched(amge_hierarchy* H, const std::vector<HostLevel>& hl, hipStrea
     H->bpart = H->alloc<double>((size_t)3 * NC * BPCG_BLOCKS);
     H->cs = H->alloc<dev::ColState>(NC);
     H->bs = H->alloc<dev::BatchStatus>(1);
-    HIPCHECK(hipStreamCreateWithFlags(&H->gstream, hipStreamNonBlocking));
-    HIPCHECK(hipEventCreateWithFlags(&H->ev_in, hipEventDisableTiming));
-    HIPCHECK(hipEventCreateWithFlags(&H->ev_out, hipEventDisableTiming));
     if (f32 && nl > 1) tune_batched<float>(H, s);
     else tune_batched<double>(H, s);
 }
@@ -852,6 +923,11 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         }
     }
     H->lv.resize(nl);
+    H->zero_flag = H->alloc<int>(1);
+    HIPCHECK(hipMemsetAsync(H->zero_flag, 0, sizeof(int), s));
+    HIPCHECK(hipStreamCreateWithFlags(&H->gstream, hipStreamNonBlocking));
+    HIPCHECK(hipEventCreateWithFlags(&H->ev_in, hipEventDisableTiming));
+    HIPCHECK(hipEventCreateWithFlags(&H->ev_out, hipEventDisableTiming));
     const bool batched = H->opts.max_rhs > 1;
     std::vector<HostLevel> hl(batched ? nl : 0);
     for (int k = 0; k < nl; ++k) {
@@ -922,6 +998,7 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     H->q = H->alloc<double>(n1);
     H->z[0] = H->alloc<double>(n1);
     H->z[1] = H->alloc<double>(n1);
+    H->x = H->alloc<double>(n1);
     H->part_pq = H->alloc<double>(dev::NRED);
     H->part_dots[0] = H->alloc<double>(3 * dev::NRED);
     H->part_dots[1] = H->alloc<double>(3 * dev::NRED);
@@ -937,8 +1014,12 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
 template <int K>
 void pcg_ap_k(amge_hierarchy* H, hipStream_t s) {
     const DSell& A = H->lv[0].A;
-    dev::k_pcg_ap<K><<<dev::NRED, BLOCK, 0, s>>>(A.nslices, A.sptr, A.srow, A.ci, A.v64, H->p, H->q, H->part_pq,
-                                                H->flags);
+    if (A.c16)
+        dev::k_pcg_ap<K, true><<<dev::NRED, BLOCK, 0, s>>>(A.nslices, A.sptr, A.srow, A.ci, A.c16, A.cbase, A.v64,
+                                                           H->p, H->q, H->part_pq, H->flags);
+    else
+        dev::k_pcg_ap<K, false><<<dev::NRED, BLOCK, 0, s>>>(A.nslices, A.sptr, A.srow, A.ci, A.c16, A.cbase, A.v64,
+                                                            H->p, H->q, H->part_pq, H->flags);
 }
 
 void launch_pcg_ap(amge_hierarchy* H, hipStream_t s) {
@@ -953,8 +1034,11 @@ void launch_pcg_ap(amge_hierarchy* H, hipStream_t s) {
     }
 }
 
-amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int maxit, int stop_l2,
-                int* iters, double* relres, hipStream_t s) {
+// One PCG iteration with buffer parity `par` (z and the dot partials alternate between
+// iterations): q = A p and p.q; x, r update with the preconditioner input; z = B r;
+// dots; beta, p update and the stopping test.  Every launch returns at once after
+// convergence (device flag), so iterations can be queued ahead of the test.
+void pcg_iteration(amge_hierarchy* H, int par, hipStream_t s) {
     const int n = H->lv[0].n;
     const bool f32 = H->opts.precond_bits == 32;
     const bool multilevel = H->lv.size() > 1;
@@ -963,59 +1047,110 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
     float* rd32 = f32 && multilevel ? L1.w32.bd : nullptr;
     float* z32 = f32 && multilevel ? L1.w32.x : nullptr;
     double* rd64 = !f32 && multilevel ? L1.w64.bd : nullptr;
-    auto precond_into = [&](double* z) {
-        if (!multilevel) {
-            coarse_solve<double>(H, H->r, z, s);
-        } else if (f32) {
-            vcycle_level<float>(H, 0, r32, rd32, z32, s);
-        } else {
-            vcycle_level<double>(H, 0, H->r, rd64, z, s);
+    const int* done = H->flags;
+    double* znew = H->z[par];
+    double* zold = H->z[par ^ 1];
+    double* dnew = H->part_dots[par];
+    double* dold = H->part_dots[par ^ 1];
+    launch_pcg_ap(H, s);
+    dev::k_pcg_xr<<<dev::NRED, BLOCK, 0, s>>>(n, H->part_pq, dold, H->p, H->q, H->x, H->r, r32, rd32,
+                                              f32 ? L1.w32.dinv : nullptr, rd64, f32 ? nullptr : L1.w64.dinv,
+                                              H->flags, H->flags + 1);
+    if (!multilevel) coarse_solve<double>(H, H->r, znew, s, done);
+    else if (f32) vcycle_level<float>(H, 0, r32, rd32, z32, s, done);
+    else vcycle_level<double>(H, 0, H->r, rd64, znew, s, done);
+    dev::k_pcg_dots<<<dev::NRED, BLOCK, 0, s>>>(n, z32, znew, zold, H->r, dnew, H->flags);
+    dev::k_pcg_p<<<dev::NRED, BLOCK, 0, s>>>(n, dnew, dold, znew, H->p, H->st, H->flags, H->flags + 1);
+    dev::k_pcg_finish<<<1, 1, 0, s>>>(H->st, H->flags);
+}
+
+// Two iterations (both parities) captured once as a HIP graph on the hierarchy's stream.
+void capture_pcg_pair(amge_hierarchy* H) {
+    if (H->pexec) return;
+    hipGraph_t graph = nullptr;
+    HIPCHECK(hipStreamBeginCapture(H->gstream, hipStreamCaptureModeThreadLocal));
+    pcg_iteration(H, 0, H->gstream);
+    pcg_iteration(H, 1, H->gstream);
+    hipError_t e = hipStreamEndCapture(H->gstream, &graph);
+    if (e != hipSuccess || !graph) fail(AMGE_ERR_HIP, "graph capture of the PCG iterations failed");
+    e = hipGraphInstantiate(&H->pexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        H->pexec = nullptr;
+        fail(AMGE_ERR_HIP, "graph instantiation failed");
+    }
+}
+
+amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int maxit, int stop_l2,
+                int* iters, double* relres, hipStream_t s) {
+    const int n = H->lv[0].n;
+    const bool f32 = H->opts.precond_bits == 32;
+    const bool multilevel = H->lv.size() > 1;
+    DLevel& L1 = H->lv[0];
+    // the iteration kernels use the hierarchy's x buffer; the caller's x is written at the end
+    const bool timed = L1.probe && L1.probe->on;   // probed launches are recorded eagerly
+    hipStream_t gs = timed ? s : H->gstream;
+    if (!timed) {
+        capture_pcg_pair(H);
+        HIPCHECK(hipEventRecord(H->ev_in, s));
+        HIPCHECK(hipStreamWaitEvent(gs, H->ev_in, 0));
+    }
+    copy_vec<double>(n, b, H->r, gs, H->zero_flag);
+    fill_zero<double>(n, H->x, gs, H->zero_flag);
+    fill_zero<int>(2, H->flags, gs, H->zero_flag);
+    if (f32 && multilevel) {
+        convert<double, float>(n, H->r, L1.w32.b, gs);
+        scale<float>(n, L1.w32.dinv, L1.w32.b, L1.w32.bd, gs);
+    }
+    if (!f32 && multilevel) scale<double>(n, L1.w64.dinv, H->r, L1.w64.bd, gs);
+    // z_0 = B r_0 into z[1] (the "old" z of the first iteration), delta_0 = r_0 . z_0
+    float* z32 = f32 && multilevel ? L1.w32.x : nullptr;
+    if (!multilevel) coarse_solve<double>(H, H->r, H->z[1], gs, H->zero_flag);
+    else if (f32) vcycle_level<float>(H, 0, L1.w32.b, L1.w32.bd, z32, gs, H->zero_flag);
+    else vcycle_level<double>(H, 0, H->r, L1.w64.bd, H->z[1], gs, H->zero_flag);
+    dev::k_pcg_dots<<<dev::NRED, BLOCK, 0, gs>>>(n, z32, H->z[1], nullptr, H->r, H->part_dots[1], H->zero_flag);
+    dev::k_pcg_init<<<1, BLOCK, 0, gs>>>(H->part_dots[1], H->st, rtol, maxit, stop_l2);
+    dev::PcgStatus hs;
+    HIPCHECK(hipMemcpyAsync(&hs, H->st, sizeof(hs), hipMemcpyDeviceToHost, gs));
+    HIPCHECK(hipStreamSynchronize(gs));
+    auto finish = [&]() {
+        if (!timed) {
+            HIPCHECK(hipEventRecord(H->ev_out, gs));
+            HIPCHECK(hipStreamWaitEvent(s, H->ev_out, 0));
         }
     };
-    HIPCHECK(hipMemcpyAsync(H->r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    HIPCHECK(hipMemsetAsync(x, 0, sizeof(double) * n, s));
-    HIPCHECK(hipMemsetAsync(H->flags, 0, 2 * sizeof(int), s));
-    if (r32) {
-        convert<double, float>(n, H->r, r32, s);
-        scale<float>(n, L1.w32.dinv, r32, rd32, s);
+    if (!std::isfinite(hs.bnorm) || !std::isfinite(hs.delta0)) {
+        finish();
+        fail(AMGE_ERR_NONFINITE, "non-finite right-hand side");
     }
-    if (rd64) scale<double>(n, L1.w64.dinv, H->r, rd64, s);
-    // z_0 = B r_0, delta_0 = r_0 . z_0
-    precond_into(H->z[1]);
-    dev::k_pcg_dots<<<dev::NRED, BLOCK, 0, s>>>(n, z32, H->z[1], nullptr, H->r, H->part_dots[1], H->flags);
-    dev::k_pcg_init<<<1, BLOCK, 0, s>>>(H->part_dots[1], H->st);
-    dev::PcgStatus hs;
-    HIPCHECK(hipMemcpyAsync(&hs, H->st, sizeof(hs), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    if (!std::isfinite(hs.bnorm) || !std::isfinite(hs.delta0)) fail(AMGE_ERR_NONFINITE, "non-finite right-hand side");
     if (hs.bnorm == 0) {
+        copy_vec<double>(n, H->x, x, gs, H->zero_flag);
+        finish();
         *iters = 0;
         *relres = 0;
         return AMGE_OK;
     }
-    if (!(hs.delta0 > 0)) fail(AMGE_ERR_BREAKDOWN, "preconditioner not positive on the right-hand side");
-    HIPCHECK(hipMemcpyAsync(H->p, H->z[1], sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-    int it = 0;
-    for (; it < maxit; ++it) {
-        double* znew = H->z[it & 1];
-        double* zold = H->z[(it + 1) & 1];
-        double* dnew = H->part_dots[it & 1];
-        double* dold = H->part_dots[(it + 1) & 1];
-        launch_pcg_ap(H, s);
-        dev::k_pcg_xr<<<dev::NRED, BLOCK, 0, s>>>(n, H->part_pq, dold, H->p, H->q, x, H->r, r32, rd32,
-                                                  f32 ? L1.w32.dinv : nullptr, rd64,
-                                                  f32 ? nullptr : L1.w64.dinv, H->flags, H->flags + 1);
-        precond_into(znew);
-        dev::k_pcg_dots<<<dev::NRED, BLOCK, 0, s>>>(n, z32, znew, zold, H->r, dnew, H->flags);
-        dev::k_pcg_p<<<dev::NRED, BLOCK, 0, s>>>(n, dnew, dold, znew, H->p, H->st, H->flags, H->flags + 1, rtol,
-                                                 stop_l2, maxit, it);
-        dev::k_pcg_finish<<<1, 1, 0, s>>>(H->st, H->flags, rtol, maxit);
-        HIPCHECK(hipMemcpyAsync(&hs, H->st, sizeof(hs), hipMemcpyDeviceToHost, s));
-        HIPCHECK(hipStreamSynchronize(s));
-        if (hs.breakdown) break;
-        if ((rtol > 0 && hs.relres <= rtol) || !std::isfinite(hs.delta)) break;
+    if (!(hs.delta0 > 0)) {
+        finish();
+        fail(AMGE_ERR_BREAKDOWN, "preconditioner not positive on the right-hand side");
     }
+    copy_vec<double>(n, H->z[1], H->p, gs, H->zero_flag);
+    // pairs of iterations (graph replays, or direct launches when timing is on), then a
+    // look at the status; iterations past convergence do nothing
+    for (int launched = 0; !hs.done; launched += 2) {
+        if (launched > maxit + 2) fail(AMGE_ERR_HIP, "PCG did not terminate");
+        if (timed) {
+            pcg_iteration(H, 0, gs);
+            pcg_iteration(H, 1, gs);
+        } else {
+            HIPCHECK(hipGraphLaunch(H->pexec, gs));
+        }
+        HIPCHECK(hipMemcpyAsync(&hs, H->st, sizeof(hs), hipMemcpyDeviceToHost, gs));
+        HIPCHECK(hipStreamSynchronize(gs));
+    }
+    copy_vec<double>(n, H->x, x, gs, H->zero_flag);
     HIPCHECK(hipGetLastError());
+    finish();
     *iters = hs.iters;
     *relres = hs.relres;
     if (hs.breakdown) fail(AMGE_ERR_BREAKDOWN, "PCG breakdown (p.q <= 0)");
@@ -1227,7 +1362,7 @@ extern "C" amge_status amge_vcycle(amge_hierarchy* h, const double* r, double* z
             if (h->opts.precond_bits == 32 && h->lv.size() > 1) bprecondition<float>(h, r, z, nrhs, s);
             else bprecondition<double>(h, r, z, nrhs, s);
         } else if (h->lv.size() == 1) {
-            coarse_solve<double>(h, r, z, s);
+            coarse_solve<double>(h, r, z, s, h->zero_flag);
         } else {
             precondition(h, r, z, s);
         }
@@ -1265,7 +1400,7 @@ extern "C" amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_
         const bool last = level == nl - 1;
         if (op == AMGE_OP_COARSE) {
             if (!last) fail(AMGE_ERR_ARG, "coarse solve only on the coarsest level");
-            coarse_solve<double>(h, in, out, s);
+            coarse_solve<double>(h, in, out, s, h->zero_flag);
             HIPCHECK(hipGetLastError());
             return AMGE_OK;
         }
@@ -1283,15 +1418,16 @@ extern "C" amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_
             case AMGE_OP_SMOOTH: case AMGE_OP_SMOOTHT: break;
             default: fail(AMGE_ERR_ARG, "unknown op");
         }
+        const int* z0 = h->zero_flag;
         auto run = [&](auto tag, const auto* vin, const auto* vin2, auto* vout) {
             using T = decltype(tag);
             switch (op) {
-                case AMGE_OP_A: sell<T>(L.A, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
-                case AMGE_OP_AHAT: sell<T>(L.Ah, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
-                case AMGE_OP_D: sell_inc<T>(L.D, 0, vin, vout, s); break;
-                case AMGE_OP_DT: sell_inc<T>(L.Dt, 0, vin, vout, s); break;
-                case AMGE_OP_P: sell<T>(L.P, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
-                case AMGE_OP_PT: sell<T>(L.Pt, dev::SPMV, vin, nullptr, nullptr, vout, s); break;
+                case AMGE_OP_A: sell<T>(L.A, dev::SPMV, vin, nullptr, nullptr, vout, s, z0); break;
+                case AMGE_OP_AHAT: sell<T>(L.Ah, dev::SPMV, vin, nullptr, nullptr, vout, s, z0); break;
+                case AMGE_OP_D: sell_inc<T>(L.D, 0, vin, vout, s, z0); break;
+                case AMGE_OP_DT: sell_inc<T>(L.Dt, 0, vin, vout, s, z0); break;
+                case AMGE_OP_P: sell<T>(L.P, dev::SPMV, vin, nullptr, nullptr, vout, s, z0); break;
+                case AMGE_OP_PT: sell<T>(L.Pt, dev::SPMV, vin, nullptr, nullptr, vout, s, z0); break;
                 default: {
                     Work<T>& w = L.w<T>();
                     // x lives in w.x (copied in), result copied out
@@ -1299,11 +1435,11 @@ extern "C" amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_
                     T* x = w.x;
                     T* xt = w.xt;
                     if (op == AMGE_OP_SMOOTH) {
-                        primary<T>(L, vin, nullptr, x, xt, false, h->opts.nu_primary, s);
-                        auxiliary<T>(L, vin, x, h->opts.nu_aux, s);
+                        primary<T>(L, vin, nullptr, x, xt, false, h->opts.nu_primary, s, z0);
+                        auxiliary<T>(L, vin, x, h->opts.nu_aux, s, z0);
                     } else {
-                        auxiliary<T>(L, vin, x, h->opts.nu_aux, s);
-                        primary<T>(L, vin, nullptr, x, xt, false, h->opts.nu_primary, s);
+                        auxiliary<T>(L, vin, x, h->opts.nu_aux, s, z0);
+                        primary<T>(L, vin, nullptr, x, xt, false, h->opts.nu_primary, s, z0);
                     }
                     HIPCHECK(hipMemcpyAsync(vout, x, sizeof(T) * L.n, hipMemcpyDeviceToDevice, s));
                 }
@@ -1380,7 +1516,7 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
             // row index) per row; incidences are index-only
             auto mat = [&](const DSell& M, const DCsrB& B) {
                 return batched ? (double)B.nnz * (sv + 4.0) + 4.0 * (B.nrows + 1)
-                               : (double)M.nnz * (sv + 4.0) + 4.0 * M.nrows;
+                               : (double)M.nnz * (sv + (M.c16 ? 2.0 : 4.0)) + 4.0 * M.nrows;
             };
             auto incb = [&](const DSell& M, const DCsrB& B) {
                 return batched ? (double)B.nnz * 4.0 + 4.0 * (B.nrows + 1) : (double)M.nnz * 4.0 + 4.0 * M.nrows;

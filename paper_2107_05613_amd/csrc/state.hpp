@@ -9,7 +9,8 @@ namespace dev {
 // Single-column PCG status.
 struct PcgStatus {
     double delta0, delta, rr, relres, bnorm;
-    int iters, done, breakdown, pad;
+    double rtol;     // stopping tolerance (<= 0: exactly maxit iterations)
+    int iters, done, breakdown, maxit, stop_l2, pad;
 };
 
 // Per-column state of the batched PCG (written only by the single-block finalize

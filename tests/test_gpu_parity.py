@@ -271,3 +271,29 @@ def test_cancellation_factor_and_auto_precision(spec):
     assert abs(kap - c.kappa) <= 1e-9 * c.kappa
     assert bits == (32 if 2.0 ** -24 * c.kappa <= 0.1 else 64)
     H.close()
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_pcg_graph_replays_match_direct_launches(bits):
+    """The PCG iterations run as replays of a captured graph (pairs of iterations); with
+    kernel timing on they are launched directly.  Both give bitwise the same iterate and
+    count, also with other GPU work and solves on other right-hand sides in between."""
+    c = case("div", 8, 3, "blocks")
+    H = c.gpu[bits]
+    b2 = W.rhs(c.n1, 99)[:, 0]
+    outs = []
+    for k in range(3):
+        x = torch.zeros_like(dev(c.b))
+        status, it, rr = H.pcg(dev(c.b), x, rtol=1e-8)
+        outs.append((it[0], rr[0], host(x)))
+        y = torch.ones(1 << 20, dtype=torch.float64, device="cuda")
+        assert float(y.sum()) == float(1 << 20)
+        H.pcg(dev(b2), torch.zeros_like(x), rtol=1e-8, maxit=3 + k)
+    H.timing_enable(True)
+    x = torch.zeros_like(dev(c.b))
+    status, it, rr = H.pcg(dev(c.b), x, rtol=1e-8)
+    H.timing_read()
+    H.timing_enable(False)
+    outs.append((it[0], rr[0], host(x)))
+    for o in outs[1:]:
+        assert o[0] == outs[0][0] and o[1] == outs[0][1] and np.array_equal(o[2], outs[0][2])
