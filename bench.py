@@ -28,15 +28,16 @@ PEAK_HBM_GBPS = 8000.0
 
 def measured_traffic():
     """HBM bytes per launch of the dominant kernel family from the committed rocprofv3
-    counter runs (profiles/hbm_traffic.json), or None if the library source changed
-    since the counters were taken."""
+    counter runs (profiles/hbm_traffic.json), or None if the kernel source or the
+    matrix layout builder changed since the counters were taken."""
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic.json")))
     except (OSError, ValueError):
         return None
     h = hashlib.sha256()
-    for f in ("paper_2107_05613_amd/csrc/kernels.hpp", "paper_2107_05613_amd/csrc/solver.hip"):
+    for f in ("paper_2107_05613_amd/csrc/kernels.hpp", "paper_2107_05613_amd/csrc/sell_layout.hpp",
+              "paper_2107_05613_amd/csrc/sell_layout.cpp"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest()[:16] != rec.get("source_hash"):
         return None

@@ -1,0 +1,33 @@
+// Host construction of the sliced-ELL layout of the level matrices.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "common.hpp"
+
+namespace amge {
+
+// Host conversion CSR -> sliced ELL with K lanes per row.  Rows are sorted by
+// decreasing length inside windows of 8 slices; each slice is as wide as its longest
+// row (rounded up to a multiple of K).
+struct HostSell {
+    int K = 1, nslices = 0;
+    std::vector<int> sptr, srow, ci;
+    std::vector<uint32_t> ent;
+    std::vector<double> val;
+    // compact column indices: per-slice base + 16-bit offsets, used when every slice's
+    // columns fit in 65536 consecutive indices (padding entries: offset 0)
+    bool compact = false;
+    std::vector<int> cbase;
+    std::vector<uint16_t> c16;
+};
+
+// Sliced ELL of A with K lanes per row (K | 64).  incidence: entries must be +-1 and are
+// stored index-only with the sign in bit 31.
+HostSell make_sell(const Csr& A, bool incidence, int K);
+
+// Whether compact (16-bit) column offsets may be used: on unless AMGE_INDEX32 is set.
+bool compact_indices();
+
+}  // namespace amge
