@@ -297,3 +297,60 @@ def test_pcg_graph_replays_match_direct_launches(bits):
     outs.append((it[0], rr[0], host(x)))
     for o in outs[1:]:
         assert o[0] == outs[0][0] and o[1] == outs[0][1] and np.array_equal(o[2], outs[0][2])
+
+
+@pytest.mark.parametrize("nus", [(1, 0), (1, 1), (3, 3), (0, 2)])
+def test_other_sweep_counts(nus):
+    """Sweep counts other than 2 + 2 (odd counts take the copy / ping-pong paths, zero
+    counts skip a smoother): single-column and batched V-cycles and fixed-count PCG
+    against the oracle built with the same counts."""
+    from oracle.solve import Multilevel, pcg
+    amge = _amge()
+    nup, nua = nus
+    c = case("curl", 8, 3, "blocks")
+    ml = Multilevel.from_hierarchy(c.H, nu_primary=nup, nu_aux=nua)
+    H = amge.Hierarchy(c.prod, precond_bits=64, nu_primary=nup, nu_aux=nua, max_rhs=2)
+    ref = ml.vcycle(c.b)
+    z = torch.empty_like(dev(c.b))
+    H.vcycle(dev(c.b), z)
+    assert relerr(host(z), ref) <= c.tol64
+    B = np.stack([c.b, W.rhs(c.n1, 5)[:, 0]], 1)
+    Z = torch.empty(2 * c.n1, dtype=torch.float64, device="cuda")
+    H.vcycle(dev(B), Z, nrhs=2)
+    Zs = host(Z).reshape(c.n1, 2)
+    assert relerr(Zs[:, 0], ref) <= c.tol64
+    assert relerr(Zs[:, 1], ml.vcycle(B[:, 1])) <= c.tol64
+    k = 8
+    xo, _, _ = pcg(c.H.A[0], c.b, ml, fixed_iters=k)
+    x = torch.zeros_like(dev(c.b))
+    status, it, _ = H.pcg(dev(c.b), x, rtol=0.0, maxit=k)
+    assert it[0] == k
+    assert np.linalg.norm(host(x) - xo) <= c.tol64 * np.linalg.norm(xo)
+    X = torch.zeros(2 * c.n1, dtype=torch.float64, device="cuda")
+    status, its, _ = H.pcg(dev(B), X, rtol=0.0, maxit=k, nrhs=2)
+    assert its == [k, k]
+    assert np.linalg.norm(host(X).reshape(c.n1, 2)[:, 0] - xo) <= c.tol64 * np.linalg.norm(xo)
+    H.close()
+
+
+def test_one_level_hierarchy():
+    """A single level: the preconditioner is the exact FP64 Cholesky solve, so PCG takes
+    one step, single-column and batched."""
+    amge = _amge()
+    c = case("curl", 8, 2, "unit")
+    A, D, P = c.prod[0]
+    H = amge.Hierarchy([(A, D, None)], precond_bits=32, max_rhs=3)
+    import scipy.linalg as sl
+    xd = sl.solve(c.H.A[0].toarray(), c.b, assume_a="pos")
+    x = torch.zeros_like(dev(c.b))
+    status, it, rr = H.pcg(dev(c.b), x, rtol=1e-8)
+    assert status == 0 and it[0] == 1
+    assert np.linalg.norm(host(x) - xd) <= 1e-10 * np.linalg.norm(xd)
+    B = np.stack([c.b, 2 * c.b, np.zeros_like(c.b)], 1)
+    X = torch.zeros(3 * c.n1, dtype=torch.float64, device="cuda")
+    status, its, rrs = H.pcg(dev(B), X, rtol=1e-8, nrhs=3)
+    Xs = host(X).reshape(c.n1, 3)
+    assert status == 0 and its == [1, 1, 0]
+    assert np.linalg.norm(Xs[:, 1] - 2 * xd) <= 1e-10 * np.linalg.norm(xd)
+    assert not np.any(Xs[:, 2])
+    H.close()
