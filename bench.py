@@ -147,10 +147,21 @@ def run_batched(args, amge, W):
     torch.cuda.synchronize()
     vms = e0.elapsed_time(e1) / reps
     by = H.vcycle_bytes(32, nrhs=k)
-    print(f"[bench] batched: {k / dt_b:.1f} solves/s ({1e3 * dt_b:.1f} ms per block, iterations "
-          f"{min(its)}..{max(its)}); one at a time {1 / dt_1:.1f} solves/s; V-cycle {vms:.2f} ms",
-          file=sys.stderr, flush=True)
     H.close()
+    # the same block with the all-FP64 V-cycle (plain FP64 PCG)
+    H64 = amge.Hierarchy(prod, precond_bits=64, max_rhs=w.nrhs)
+    X.zero_()
+    st, its64, _ = H64.pcg(B, X, rtol=w.rtol, maxit=1000, nrhs=k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        st, its64, _ = H64.pcg(B, X, rtol=w.rtol, maxit=1000, nrhs=k)
+    torch.cuda.synchronize()
+    dt_64 = (time.perf_counter() - t0) / max(1, args.steps // 2)
+    H64.close()
+    print(f"[bench] batched: {k / dt_b:.1f} solves/s ({1e3 * dt_b:.1f} ms per block, iterations "
+          f"{min(its)}..{max(its)}); FP64 block {k / dt_64:.1f} solves/s; one at a time {1 / dt_1:.1f} solves/s; "
+          f"V-cycle {vms:.2f} ms", file=sys.stderr, flush=True)
     return {
         "workload": (f"{w.name}: H({w.kind}) on {w.n}^3x6 Kuhn tets, {w.levels}-level AMGe, {k} right-hand "
                      f"sides (uniform[-1,1] seed {w.rhs_seed}) in one call, FP32 V-cycle in per-column FP64 "
@@ -162,6 +173,9 @@ def run_batched(args, amge, W):
         "single_column_solves_per_s": 1.0 / dt_1,
         "single_column_iters": it1,
         "batching_speedup": dt_1 * k / dt_b,
+        "fp64_block_solves_per_s": k / dt_64,
+        "fp64_block_iters": [min(its64), max(its64)],
+        "speedup_fp32_vs_fp64_block": dt_64 / dt_b,
         "vcycle": {"ms": vms, "algorithmic_bytes": by, "GBps": by / (vms * 1e-3) / 1e9,
                    "ms_per_column": vms / k},
         "setup_s": {"build": t_build, "device_setup": t_setup},

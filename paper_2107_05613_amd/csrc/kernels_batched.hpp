@@ -287,10 +287,11 @@ k_bpcg_xr(int64_t nn, int lg, const ColState* __restrict__ cs, const double* __r
     }
 }
 
-// Z = Zv (widened) after using the old Z: partials of r.z_new, r.z_old, r.r per column.
+// Z = Zv after using the old Z: partials of r.z_new, r.z_old, r.r per column.  Z has the
+// preconditioner's precision (an FP32 z is exact in FP32), sums are FP64.
 template <typename TZ>
 __global__ void __launch_bounds__(BLOCK)
-k_bpcg_dots(int n, int NC, const TZ* __restrict__ Zv, double* __restrict__ Z, const double* __restrict__ R,
+k_bpcg_dots(int n, int NC, const TZ* __restrict__ Zv, TZ* __restrict__ Z, const double* __restrict__ R,
             double* __restrict__ part, const BatchStatus* __restrict__ bs) {
     __shared__ double sh[BLOCK];
     if (bs->all_done) return;
@@ -299,8 +300,9 @@ k_bpcg_dots(int n, int NC, const TZ* __restrict__ Zv, double* __restrict__ Z, co
     double a = 0, b = 0, d = 0;
     for (int row = blockIdx.x * rpb + threadIdx.x / NC; row < n; row += gridDim.x * rpb) {
         const int64_t t = (int64_t)row * NC + c;
-        const double zn = (double)Zv[t], zo = Z[t], r = R[t];
-        Z[t] = zn;
+        const TZ znv = Zv[t];
+        const double zn = (double)znv, zo = (double)Z[t], r = R[t];
+        Z[t] = znv;
         a = fma(r, zn, a);
         b = fma(r, zo, b);
         d = fma(r, r, d);
@@ -385,14 +387,16 @@ k_bpcg_update(int NC, const double* __restrict__ part, int nblk, ColState* __res
 
 // P = Z + beta P for live columns; P = Z for a column that has just taken its initial
 // quantities.
+template <typename TZ>
 __global__ void __launch_bounds__(BLOCK)
-k_bpcg_p(int64_t nn, int lg, const ColState* __restrict__ cs, const double* __restrict__ Z, double* __restrict__ P,
+k_bpcg_p(int64_t nn, int lg, const ColState* __restrict__ cs, const TZ* __restrict__ Z, double* __restrict__ P,
          const BatchStatus* __restrict__ bs) {
     if (bs->all_done) return;
     for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < nn; t += (int64_t)gridDim.x * BLOCK) {
         const ColState& s = cs[t & ((1 << lg) - 1)];
-        if (s.pinit) P[t] = Z[t];
-        else if (!s.done) P[t] = fma(s.beta, P[t], Z[t]);
+        const double z = (double)Z[t];
+        if (s.pinit) P[t] = z;
+        else if (!s.done) P[t] = fma(s.beta, P[t], z);
     }
 }
 

@@ -766,7 +766,7 @@ void setup_batched(amge_hierarchy* H, const std::vector<HostLevel>& hl, hipStrea
     H->bR = H->alloc<double>(nn);
     H->bP = H->alloc<double>(nn);
     H->bQ = H->alloc<double>(nn);
-    H->bZ = H->alloc<double>(nn);
+    H->bZ = H->alloc<double>(nn);   // z in the preconditioner precision (FP32: first half used)
     H->bZv = H->alloc<double>(nn);
     H->bpart = H->alloc<double>((size_t)3 * NC * BPCG_BLOCKS);
     H->cs = H->alloc<dev::ColState>(NC);
@@ -1084,7 +1084,8 @@ void bpcg_dots(amge_hierarchy* H, hipStream_t s) {
     DLevel& L = H->lv[0];
     const int n = L.n;
     if (bz32(H))
-        dev::k_bpcg_dots<float><<<BPCG_BLOCKS, BLOCK, 0, s>>>(n, H->NC, L.bw32.x, H->bZ, H->bR, H->bpart, H->bs);
+        dev::k_bpcg_dots<float><<<BPCG_BLOCKS, BLOCK, 0, s>>>(n, H->NC, L.bw32.x, (float*)H->bZ, H->bR, H->bpart,
+                                                              H->bs);
     else
         dev::k_bpcg_dots<double><<<BPCG_BLOCKS, BLOCK, 0, s>>>(n, H->NC, H->bZv, H->bZ, H->bR, H->bpart, H->bs);
 }
@@ -1105,7 +1106,8 @@ void bpcg_iteration(amge_hierarchy* H, hipStream_t s) {
     bpcg_precond(H, &H->bs->all_done, s);
     bpcg_dots(H, s);
     dev::k_bpcg_update<<<1, dev::FIN_BLOCK, 0, s>>>(H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
-    dev::k_bpcg_p<<<g, BLOCK, 0, s>>>(nn, H->lgNC, H->cs, H->bZ, H->bP, H->bs);
+    if (f32) dev::k_bpcg_p<float><<<g, BLOCK, 0, s>>>(nn, H->lgNC, H->cs, (const float*)H->bZ, H->bP, H->bs);
+    else dev::k_bpcg_p<double><<<g, BLOCK, 0, s>>>(nn, H->lgNC, H->cs, H->bZ, H->bP, H->bs);
 }
 
 void capture_iteration(amge_hierarchy* H) {
