@@ -53,16 +53,20 @@ struct Probe {
     }
 };
 
-// CSR matrix on the device for the batched (several right-hand sides) kernels.
-struct DCsrB {
-    int nrows = 0, ncols = 0;
+// Sliced ELL with one lane per row (K = 1) for the batched kernels: entry t of slot rr
+// of a slice at sptr[slice] + t * 64 + rr, so every row keeps its CSR entry order.
+struct DSellB {
+    int nrows = 0, ncols = 0, nslices = 0;
     int64_t nnz = 0;
-    int* rp = nullptr;
-    int* ci = nullptr;         // value matrices
-    uint32_t* ent = nullptr;   // incidence matrices: column | sign << 31
+    int* sptr = nullptr;
+    int* srow = nullptr;       // slot -> row (-1: empty slot)
+    int* ci = nullptr;         // value matrices: column indices, or
+    uint16_t* c16 = nullptr;   //   16-bit offsets from a per-slice base column
+    int* cbase = nullptr;
+    uint32_t* ent = nullptr;   // incidence matrices: column | sign << 31, padding 0xffffffff
     double* v64 = nullptr;
     float* v32 = nullptr;
-    int V = 1;                 // columns per lane (vector width), tuned
+    int V = 1;                 // columns per lane, tuned
 };
 
 struct DLevel {
@@ -73,9 +77,9 @@ struct DLevel {
     DSell D, Dt;              // signed incidences
     Work<float> w32;
     Work<double> w64;
-    // batched path (max_rhs > 1): CSR copies and n x NC work buffers of the
+    // batched path (max_rhs > 1): one-lane-per-row copies and n x NC work buffers of the
     // preconditioner precision
-    DCsrB bA, bAh, bP, bPt, bAux, bD;
+    DSellB bA, bAh, bP, bPt, bAux, bD;
     Work<float> bw32;
     Work<double> bw64;
     template <class T> Work<T>& w();
@@ -108,7 +112,7 @@ struct amge_hierarchy {
     amge::dev::BatchStatus* bs = nullptr;
     int* zero_flag = nullptr;    // a device 0: the stop flag of launches outside PCG iterations
     hipStream_t gstream = nullptr;   // the hierarchy's stream for graph capture / replay
-    hipGraphExec_t gexec = nullptr;  // one captured batched PCG iteration
+    hipGraphExec_t gexec[7] = {};    // one captured batched PCG iteration per active width 2^i
     hipGraphExec_t pexec = nullptr;  // two captured single-column PCG iterations
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<void*> allocs;
@@ -116,7 +120,8 @@ struct amge_hierarchy {
     amge::Probe probe;
     ~amge_hierarchy() {
         if (gstream) (void)hipStreamSynchronize(gstream);
-        if (gexec) (void)hipGraphExecDestroy(gexec);
+        for (hipGraphExec_t g : gexec)
+            if (g) (void)hipGraphExecDestroy(g);
         if (pexec) (void)hipGraphExecDestroy(pexec);
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
@@ -136,7 +141,7 @@ struct amge_hierarchy {
 };
 
 namespace amge {
-// Captures one batched PCG iteration of a hierarchy as a HIP graph on its own stream
-// (done once, on first use).
-void capture_iteration(amge_hierarchy* H);
+// One batched PCG iteration on the first W columns (W a power of two <= NC) of a
+// hierarchy, captured as a HIP graph on its own stream on first use.
+hipGraphExec_t capture_iteration(amge_hierarchy* H, int W);
 }  // namespace amge

@@ -1,11 +1,12 @@
 // Batched (multiple right-hand sides) kernels: the V-cycle and PCG on NC columns at once.
 //
-// Vectors are row-major n x NC.  A row of a level matrix is read once for all NC
+// Vectors are row-major n x NC.  A row of a level matrix is read once for all active
 // columns: the lanes of a row own disjoint groups of V consecutive columns (V-wide
 // vector loads), so every matrix entry is a broadcast load shared by the row's lanes
-// and each gathered vector row is a contiguous NC-entry segment.  No cross-lane
-// reduction is needed; each lane runs the row's nonzeros sequentially.  The matrix is
-// in plain CSR here (rows contiguous), which suits the broadcast access.
+// and each gathered vector row is a contiguous segment.  No cross-lane reduction is
+// needed; each lane runs the row's entries sequentially, in CSR order.  The matrices
+// are in the sliced-ELL layout with one lane per row (K = 1), so the entries read by a
+// wave are consecutive.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -51,27 +52,39 @@ struct Pack {
     }
 };
 
-// Row-major SpMM level operator.  L = NC / V lanes per row (power of two dividing the
-// block), one row per L lanes.  Modes as in Mode (kernels.hpp); yd (SPMV, SPLIT) also
-// receives dinv * y.
-template <typename T, int V, int MODE>
+// Row-major SpMM level operator on the sliced-ELL layout with one lane per row (K = 1:
+// entry t of slot rr of a slice at base + t * 64 + rr, rows in CSR entry order).  The
+// first W of the NC columns are computed: L = W / V lanes share a row, each owning V
+// consecutive columns (16- to 64-byte vector loads of the gathered rows), so a wave
+// covers 64 / L consecutive slots of one slice and a slice takes L waves; the matrix
+// entries of those slots are consecutive (coalesced), each broadcast to the L lanes of
+// its row.  Every column sums its row's entries in CSR order whatever W, L and V are.
+// Modes as in Mode (kernels.hpp); YD (SPMV, SPLIT) also receives dinv * y.
+template <typename T, int V, int MODE, bool C16>
 __global__ void __launch_bounds__(BLOCK)
-k_csr_mm(int n, int L, int NC, const int* __restrict__ rp, const int* __restrict__ ci, const T* __restrict__ av,
-         const T* __restrict__ X, const T* __restrict__ B, const T* __restrict__ dinv, T* __restrict__ Y,
-         T* __restrict__ YD, int nsplit, const int* __restrict__ stop) {
+k_sell_mm(int nslices, int L, int NC, const int* __restrict__ sptr, const int* __restrict__ srow,
+          const int* __restrict__ ci, const uint16_t* __restrict__ c16, const int* __restrict__ cbase,
+          const T* __restrict__ av, const T* __restrict__ X, const T* __restrict__ B, const T* __restrict__ dinv,
+          T* __restrict__ Y, T* __restrict__ YD, int nsplit, const int* __restrict__ stop) {
     if (*stop) return;   // every column of the batch has converged
-    const int rows_per_block = BLOCK / L;
-    const int row = xcd_block(blockIdx.x, gridDim.x) * rows_per_block + (int)threadIdx.x / L;
-    if (row >= n) return;
-    const int col = ((int)threadIdx.x % L) * V;
+    const int gw = xcd_block(blockIdx.x, gridDim.x) * WAVES + ((int)threadIdx.x >> 6);
+    const int slice = gw / L;
+    if (slice >= nslices) return;
+    const int lane = threadIdx.x & 63;
+    const int rr = (gw % L) * (64 / L) + lane / L;
+    const int col = (lane % L) * V;
+    const int base = sptr[slice];
+    const int width = (sptr[slice + 1] - base) >> 6;
+    const int row = srow[slice * 64 + rr];
+    const int cb = C16 ? cbase[slice] : 0;
     Pack<T, V> acc;
 #pragma unroll
     for (int i = 0; i < V; ++i) acc.v[i] = 0;
-    const int s = rp[row], e = rp[row + 1];
 #pragma unroll 4
-    for (int k = s; k < e; ++k) {
-        const int j = ci[k];
-        const T a = av[k];
+    for (int k = 0; k < width; ++k) {
+        const int e = base + k * 64 + rr;
+        const int j = C16 ? cb + (int)c16[e] : ci[e];
+        const T a = av[e];
         Pack<T, V> xv;
         if (MODE == SPLIT) {
             if (j < nsplit) xv.load(B + (int64_t)j * NC + col);
@@ -82,6 +95,7 @@ k_csr_mm(int n, int L, int NC, const int* __restrict__ rp, const int* __restrict
 #pragma unroll
         for (int i = 0; i < V; ++i) acc.v[i] = fma(a, xv.v[i], acc.v[i]);
     }
+    if (row < 0) return;
     const int64_t o = (int64_t)row * NC + col;
     Pack<T, V> out;
     if (MODE == SPMV || MODE == SPLIT) {
@@ -114,20 +128,29 @@ k_csr_mm(int n, int L, int NC, const int* __restrict__ rp, const int* __restrict
     }
 }
 
-// Y += D X for a signed incidence in CSR (index-only entries, bit 31 = sign).
+// Y += D X for a signed incidence in the same layout (index-only entries, bit 31 =
+// sign, padding 0xffffffff).
 template <typename T, int V>
 __global__ void __launch_bounds__(BLOCK)
-k_inc_mm_add(int n, int L, int NC, const int* __restrict__ rp, const uint32_t* __restrict__ ent,
-             const T* __restrict__ X, T* __restrict__ Y, const int* __restrict__ stop) {
+k_sell_inc_mm_add(int nslices, int L, int NC, const int* __restrict__ sptr, const int* __restrict__ srow,
+                  const uint32_t* __restrict__ ent, const T* __restrict__ X, T* __restrict__ Y,
+                  const int* __restrict__ stop) {
     if (*stop) return;
-    const int rows_per_block = BLOCK / L;
-    const int row = xcd_block(blockIdx.x, gridDim.x) * rows_per_block + (int)threadIdx.x / L;
-    if (row >= n) return;
-    const int col = ((int)threadIdx.x % L) * V;
+    const int gw = xcd_block(blockIdx.x, gridDim.x) * WAVES + ((int)threadIdx.x >> 6);
+    const int slice = gw / L;
+    if (slice >= nslices) return;
+    const int lane = threadIdx.x & 63;
+    const int rr = (gw % L) * (64 / L) + lane / L;
+    const int col = (lane % L) * V;
+    const int base = sptr[slice];
+    const int width = (sptr[slice + 1] - base) >> 6;
+    const int row = srow[slice * 64 + rr];
+    if (row < 0) return;
     Pack<T, V> acc;
     acc.load(Y + (int64_t)row * NC + col);
-    for (int k = rp[row]; k < rp[row + 1]; ++k) {
-        const uint32_t w = ent[k];
+    for (int k = 0; k < width; ++k) {
+        const uint32_t w = ent[base + k * 64 + rr];
+        if (w == 0xffffffffu) continue;   // padding
         Pack<T, V> xv;
         xv.load(X + (int64_t)(w & 0x7fffffffu) * NC + col);
         const bool neg = w >> 31;
@@ -137,29 +160,30 @@ k_inc_mm_add(int n, int L, int NC, const int* __restrict__ rp, const uint32_t* _
     acc.store(Y + (int64_t)row * NC + col);
 }
 
-// Coarsest level: X = Ainv B, one thread per (row, column); FP64 arithmetic.
+// Coarsest level: X = Ainv B, one thread per (row, column) for the first W = 2^lgW
+// columns of the NC = 2^lg stored ones; FP64 arithmetic.
 template <typename T>
 __global__ void __launch_bounds__(BLOCK)
-k_coarse_mm(int n, int lg, const double* __restrict__ Ainv, const T* __restrict__ B, T* __restrict__ X,
+k_coarse_mm(int n, int lgW, int lg, const double* __restrict__ Ainv, const T* __restrict__ B, T* __restrict__ X,
             const int* __restrict__ stop) {
     if (*stop) return;
     const int NC = 1 << lg;
     const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (t >= ((int64_t)n << lg)) return;
-    const int row = (int)(t >> lg), c = (int)(t & (NC - 1));
+    if (t >= ((int64_t)n << lgW)) return;
+    const int row = (int)(t >> lgW), c = (int)(t & ((1 << lgW) - 1));
     const double* a = Ainv + (int64_t)row * n;
     double acc = 0;
     for (int j = 0; j < n; ++j) acc = fma(a[j], (double)B[(int64_t)j * NC + c], acc);
-    X[t] = (T)acc;
+    X[(int64_t)row * NC + c] = (T)acc;
 }
 
 // ---------------------------------------------------------------- batched PCG
 // Per-column partial sums over the rows of a block: the block's threads hold column
 // (tid % NC) sums for row group tid / NC; reduced over row groups through LDS.
-__device__ __forceinline__ void column_partials(double v, int NC, double* sh, double* part, int nblk) {
+__device__ __forceinline__ void column_partials(double v, int W, int NC, double* sh, double* part, int nblk) {
     sh[threadIdx.x] = v;
     __syncthreads();
-    if ((int)threadIdx.x < NC) {
+    if ((int)threadIdx.x < W) {
         double t = 0;
         for (int g = threadIdx.x; g < BLOCK; g += NC) t += sh[g];
         part[(int64_t)threadIdx.x * nblk + blockIdx.x] = t;
@@ -167,37 +191,47 @@ __device__ __forceinline__ void column_partials(double v, int NC, double* sh, do
     __syncthreads();
 }
 
-// Q = A P (FP64 CSR) and block partials of p.q per column.  Lanes as in k_csr_mm
-// (L = NC / V lanes per row, V columns each); every block owns a contiguous range of
-// rows, so its gathers of P stay close together.  NC * V <= BLOCK * V entries of LDS.
-template <int V>
+// Q = A P (FP64, the one-lane-per-row sliced ELL of A) and block partials of p.q per
+// column.  Every block owns a contiguous range of slices; its threads are laid out for
+// all NC columns (L = NC / V lanes per row, V columns each), so every column's sums run
+// in the same order whatever the active width W is; lanes of columns >= W do no work.
+template <int V, bool C16>
 __global__ void __launch_bounds__(BLOCK)
-k_bpcg_ap(int n, int NC, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ av,
-          const double* __restrict__ P, double* __restrict__ Q, double* __restrict__ part,
-          const BatchStatus* __restrict__ bs) {
+k_bpcg_ap(int nslices, int W, int NC, const int* __restrict__ sptr, const int* __restrict__ srow,
+          const int* __restrict__ ci, const uint16_t* __restrict__ c16, const int* __restrict__ cbase,
+          const double* __restrict__ av, const double* __restrict__ P, double* __restrict__ Q,
+          double* __restrict__ part, const BatchStatus* __restrict__ bs) {
     __shared__ double sh[BLOCK * V];
     if (bs->all_done) return;
-    const int L = NC / V, rpb = BLOCK / L;
+    const int L = NC / V, rpb = BLOCK / L;   // rpb: row slots per step (a multiple of 64 / L)
     const int g = (int)threadIdx.x / L, col = ((int)threadIdx.x % L) * V;
-    const int per = (n + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int r0 = xcd_block(blockIdx.x, gridDim.x) * per;
-    const int r1 = min(n, r0 + per);
+    const bool active = col < W;
+    const int per = (nslices + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int s0 = xcd_block(blockIdx.x, gridDim.x) * per;
+    const int s1 = min(nslices, s0 + per);
     Pack<double, V> dot;
 #pragma unroll
     for (int i = 0; i < V; ++i) dot.v[i] = 0;
-    for (int row = r0 + g; row < r1; row += rpb) {
+    for (int u = s0 * 64 + g; active && u < s1 * 64; u += rpb) {
+        const int slice = u >> 6, rr = u & 63;
+        const int base = sptr[slice];
+        const int width = (sptr[slice + 1] - base) >> 6;
+        const int row = srow[slice * 64 + rr];
+        const int cb = C16 ? cbase[slice] : 0;
         Pack<double, V> acc;
 #pragma unroll
         for (int i = 0; i < V; ++i) acc.v[i] = 0;
-        const int e = rp[row + 1];
 #pragma unroll 4
-        for (int k = rp[row]; k < e; ++k) {
-            const double a = av[k];
+        for (int k = 0; k < width; ++k) {
+            const int e = base + k * 64 + rr;
+            const int j = C16 ? cb + (int)c16[e] : ci[e];
+            const double a = av[e];
             Pack<double, V> xv;
-            xv.load(P + (int64_t)ci[k] * NC + col);
+            xv.load(P + (int64_t)j * NC + col);
 #pragma unroll
             for (int i = 0; i < V; ++i) acc.v[i] = fma(a, xv.v[i], acc.v[i]);
         }
+        if (row < 0) continue;
         const int64_t o = (int64_t)row * NC + col;
         acc.store(Q + o);
         Pack<double, V> pv;
@@ -208,7 +242,7 @@ k_bpcg_ap(int n, int NC, const int* __restrict__ rp, const int* __restrict__ ci,
 #pragma unroll
     for (int i = 0; i < V; ++i) sh[g * NC + col + i] = dot.v[i];
     __syncthreads();
-    if ((int)threadIdx.x < NC) {
+    if ((int)threadIdx.x < W) {
         double t = 0;
         for (int q = 0; q < rpb; ++q) t += sh[q * NC + threadIdx.x];
         part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
@@ -218,9 +252,11 @@ k_bpcg_ap(int n, int NC, const int* __restrict__ rp, const int* __restrict__ ci,
 // Per-column totals of nq quantities from their block partials, stored at
 // part[(q * NC + c) * nblk + block]: one wave per (q, c), fixed summation order
 // (strided lane sums, then the butterfly).  Results in sh[q * NC + c].
-__device__ __forceinline__ void col_totals(const double* __restrict__ part, int nblk, int nq, int NC, double* sh) {
+__device__ __forceinline__ void col_totals(const double* __restrict__ part, int nblk, int nq, int W, int NC,
+                                           double* sh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     for (int qc = wave; qc < nq * NC; qc += nwaves) {
+        if (qc % NC >= W) continue;   // idle columns beyond the active width
         const double* p = part + (int64_t)qc * nblk;
         double t = 0;
         for (int i = lane; i < nblk; i += 64) t += p[i];
@@ -236,13 +272,13 @@ constexpr int FIN_BLOCK = 1024;
 // alpha_c = delta_c / pq_c for live columns (breakdown if pq_c <= 0); fresh and idle
 // columns take no step.  One block.
 __global__ void __launch_bounds__(FIN_BLOCK)
-k_bpcg_alpha(int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
+k_bpcg_alpha(int W, int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
              BatchStatus* __restrict__ bs) {
     __shared__ double sh[64];
     if (bs->all_done) return;
-    col_totals(part, nblk, 1, NC, sh);
+    col_totals(part, nblk, 1, W, NC, sh);
     const int c = threadIdx.x;
-    if (c < NC) {
+    if (c < W) {
         ColState& s = cs[c];
         const double pq = sh[c];
         s.pq = pq;
@@ -263,13 +299,15 @@ k_bpcg_alpha(int NC, const double* __restrict__ part, int nblk, ColState* __rest
 // X += alpha P, R -= alpha Q per column; R32 = (float) R, RD32 = dinv32 * R32 (FP32
 // preconditioner) or RD64 = dinv64 * R (FP64 preconditioner).
 __global__ void __launch_bounds__(BLOCK)
-k_bpcg_xr(int64_t nn, int lg, const ColState* __restrict__ cs, const double* __restrict__ P,
+k_bpcg_xr(int64_t nn, int lgW, int lg, const ColState* __restrict__ cs, const double* __restrict__ P,
           const double* __restrict__ Q, double* __restrict__ X, double* __restrict__ R, float* __restrict__ R32,
           float* __restrict__ RD32, const float* __restrict__ dinv32, double* __restrict__ RD64,
           const double* __restrict__ dinv64, const BatchStatus* __restrict__ bs) {
     if (bs->all_done) return;
-    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < nn; t += (int64_t)gridDim.x * BLOCK) {
-        const int c = (int)(t & ((1 << lg) - 1));
+    for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < nn; u += (int64_t)gridDim.x * BLOCK) {
+        const int c = (int)(u & ((1 << lgW) - 1));
+        const int64_t row = u >> lgW;
+        const int64_t t = (row << lg) + c;
         const double a = cs[c].alpha;
         double r = R[t];
         if (a != 0) {
@@ -277,7 +315,6 @@ k_bpcg_xr(int64_t nn, int lg, const ColState* __restrict__ cs, const double* __r
             r = fma(-a, Q[t], r);
             R[t] = r;
         }
-        const int64_t row = t >> lg;
         if (R32) {
             const float rf = (float)r;
             R32[t] = rf;
@@ -291,14 +328,14 @@ k_bpcg_xr(int64_t nn, int lg, const ColState* __restrict__ cs, const double* __r
 // preconditioner's precision (an FP32 z is exact in FP32), sums are FP64.
 template <typename TZ>
 __global__ void __launch_bounds__(BLOCK)
-k_bpcg_dots(int n, int NC, const TZ* __restrict__ Zv, TZ* __restrict__ Z, const double* __restrict__ R,
+k_bpcg_dots(int n, int W, int NC, const TZ* __restrict__ Zv, TZ* __restrict__ Z, const double* __restrict__ R,
             double* __restrict__ part, const BatchStatus* __restrict__ bs) {
     __shared__ double sh[BLOCK];
     if (bs->all_done) return;
     const int rpb = BLOCK / NC;
-    const int c = threadIdx.x % NC;
+    const int c = threadIdx.x % NC;   // layout of all NC columns; columns >= W idle
     double a = 0, b = 0, d = 0;
-    for (int row = blockIdx.x * rpb + threadIdx.x / NC; row < n; row += gridDim.x * rpb) {
+    for (int row = blockIdx.x * rpb + threadIdx.x / NC; c < W && row < n; row += gridDim.x * rpb) {
         const int64_t t = (int64_t)row * NC + c;
         const TZ znv = Zv[t];
         const double zn = (double)znv, zo = (double)Z[t], r = R[t];
@@ -308,23 +345,27 @@ k_bpcg_dots(int n, int NC, const TZ* __restrict__ Zv, TZ* __restrict__ Z, const 
         d = fma(r, r, d);
     }
     const int nb = gridDim.x;
-    column_partials(a, NC, sh, part, nb);
-    column_partials(b, NC, sh, part + (int64_t)NC * nb, nb);
-    column_partials(d, NC, sh, part + (int64_t)2 * NC * nb, nb);
+    column_partials(a, W, NC, sh, part, nb);
+    column_partials(b, W, NC, sh, part + (int64_t)NC * nb, nb);
+    column_partials(d, W, NC, sh, part + (int64_t)2 * NC * nb, nb);
 }
 
 // Per-column stopping test and beta (one block).  A fresh column takes its initial
 // quantities here (delta0 = r.z0, ||b||) and becomes live; a zero right-hand side is
 // finished with 0 steps.
 __global__ void __launch_bounds__(FIN_BLOCK)
-k_bpcg_update(int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
+k_bpcg_update(int W, int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
               BatchStatus* __restrict__ bs) {
     __shared__ double sh[3 * 64];
     __shared__ int flags[2 * 64];
     if (bs->all_done) return;
-    col_totals(part, nblk, 3, NC, sh);
+    col_totals(part, nblk, 3, W, NC, sh);
     const int c = threadIdx.x;
-    if (c < NC) {
+    if (c >= W && c < NC) {   // idle columns beyond the active width
+        flags[c] = cs[c].done;
+        flags[64 + c] = cs[c].breakdown;
+    }
+    if (c < W) {
         ColState& s = cs[c];
         const double rz = sh[c], rzo = sh[NC + c], rr = sh[2 * NC + c];
         if (s.done) {
@@ -389,11 +430,13 @@ k_bpcg_update(int NC, const double* __restrict__ part, int nblk, ColState* __res
 // quantities.
 template <typename TZ>
 __global__ void __launch_bounds__(BLOCK)
-k_bpcg_p(int64_t nn, int lg, const ColState* __restrict__ cs, const TZ* __restrict__ Z, double* __restrict__ P,
-         const BatchStatus* __restrict__ bs) {
+k_bpcg_p(int64_t nn, int lgW, int lg, const ColState* __restrict__ cs, const TZ* __restrict__ Z,
+         double* __restrict__ P, const BatchStatus* __restrict__ bs) {
     if (bs->all_done) return;
-    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < nn; t += (int64_t)gridDim.x * BLOCK) {
-        const ColState& s = cs[t & ((1 << lg) - 1)];
+    for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < nn; u += (int64_t)gridDim.x * BLOCK) {
+        const int c = (int)(u & ((1 << lgW) - 1));
+        const int64_t t = ((u >> lgW) << lg) + c;
+        const ColState& s = cs[c];
         const double z = (double)Z[t];
         if (s.pinit) P[t] = z;
         else if (!s.done) P[t] = fma(s.beta, P[t], z);

@@ -248,7 +248,15 @@ struct amge_server {
             Group& g = *gp;
             if (g.chunk_busy || g.active == 0) continue;
             amge_hierarchy* H = g.H;
-            for (int i = 0; i < chunk; ++i) HIPCHECK(hipGraphLaunch(H->gexec, H->gstream));
+            // active width: the columns up to the highest occupied one (requests take the
+            // lowest free column)
+            int hi = 0;
+            for (int c = 0; c < H->NC; ++c)
+                if (g.slot[c] >= 0) hi = c + 1;
+            int W = 1;
+            while (W < hi) W *= 2;
+            hipGraphExec_t ex = capture_iteration(H, W);
+            for (int i = 0; i < chunk; ++i) HIPCHECK(hipGraphLaunch(ex, H->gstream));
             HIPCHECK(hipMemcpyAsync(g.cs_host, H->cs, sizeof(dev::ColState) * H->NC, hipMemcpyDeviceToHost,
                                     H->gstream));
             HIPCHECK(hipEventRecord(g.ev_chunk, H->gstream));
@@ -320,7 +328,7 @@ extern "C" amge_status amge_server_add(amge_server* s, amge_hierarchy* h, int32_
         HIPCHECK(hipHostMalloc((void**)&g->cs_host, sizeof(dev::ColState) * h->NC, hipHostMallocDefault));
         HIPCHECK(hipEventCreateWithFlags(&g->ev_chunk, hipEventDisableTiming));
         HIPCHECK(hipEventCreateWithFlags(&g->ev_extract, hipEventDisableTiming));
-        capture_iteration(h);
+        for (int W = 1; W <= h->NC; W *= 2) capture_iteration(h, W);
         dev::k_serve_reset<<<1, 64, 0, h->gstream>>>(h->NC, h->cs, h->bs);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipStreamSynchronize(h->gstream));

@@ -377,25 +377,31 @@ constexpr int BPCG_CHUNK = 4;      // graph replays between status polls
 // Several right-hand sides at once (n x NC row-major blocks, NC a power of two): every
 // level operator is one CSR SpMM launch whose lanes own V consecutive columns of a
 // row.  V is tuned per matrix at set-up.
-template <class T> const T* bvals(const DCsrB& M);
-template <> const float* bvals<float>(const DCsrB& M) { return M.v32; }
-template <> const double* bvals<double>(const DCsrB& M) { return M.v64; }
+template <class T> const T* bvals(const DSellB& M);
+template <> const float* bvals<float>(const DSellB& M) { return M.v32; }
+template <> const double* bvals<double>(const DSellB& M) { return M.v64; }
 
-DCsrB upload_csr_b(amge_hierarchy* H, const Csr& A, bool incidence, bool f32, bool f64, hipStream_t s) {
-    DCsrB M;
+DSellB upload_sell_b(amge_hierarchy* H, const Csr& A, bool incidence, bool f32, bool f64, hipStream_t s) {
+    HostSell h = make_sell(A, incidence, 1);
+    DSellB M;
     M.nrows = A.nrows;
     M.ncols = A.ncols;
     M.nnz = A.nnz();
-    M.rp = upload(H, A.rowptr.data(), A.rowptr.size(), s);
+    M.nslices = h.nslices;
+    M.sptr = upload(H, h.sptr.data(), h.sptr.size(), s);
+    M.srow = upload(H, h.srow.data(), h.srow.size(), s);
     if (incidence) {
-        std::vector<uint32_t> e(A.col.size());
-        for (size_t k = 0; k < e.size(); ++k) e[k] = (uint32_t)A.col[k] | (A.val[k] < 0 ? 0x80000000u : 0u);
-        M.ent = upload(H, e.data(), e.size(), s);
+        M.ent = upload(H, h.ent.data(), h.ent.size(), s);
     } else {
-        M.ci = upload(H, A.col.data(), A.col.size(), s);
-        if (f64) M.v64 = upload(H, A.val.data(), A.val.size(), s);
+        if (h.compact && compact_indices()) {
+            M.c16 = upload(H, h.c16.data(), h.c16.size(), s);
+            M.cbase = upload(H, h.cbase.data(), h.cbase.size(), s);
+        } else {
+            M.ci = upload(H, h.ci.data(), h.ci.size(), s);
+        }
+        if (f64) M.v64 = upload(H, h.val.data(), h.val.size(), s);
         if (f32) {
-            std::vector<float> v(A.val.begin(), A.val.end());
+            std::vector<float> v(h.val.begin(), h.val.end());
             M.v32 = upload(H, v.data(), v.size(), s);
         }
     }
@@ -404,57 +410,66 @@ DCsrB upload_csr_b(amge_hierarchy* H, const Csr& A, bool incidence, bool f32, bo
 }
 
 template <class T, int V, int MODE>
-void csr_mm_v(const DCsrB& M, int NC, const T* X, const T* B, const T* dinv, T* Y, T* YD, int nsplit,
-              const int* stop, hipStream_t s) {
-    const int L = NC / V;
-    const int rpb = BLOCK / L;
-    const unsigned grid = (unsigned)((M.nrows + rpb - 1) / rpb);
-    if (grid)
-        dev::k_csr_mm<T, V, MODE><<<grid, BLOCK, 0, s>>>(M.nrows, L, NC, M.rp, M.ci, bvals<T>(M), X, B, dinv, Y, YD,
-                                                         nsplit, stop);
+void bmm_v(const DSellB& M, int W, int NC, const T* X, const T* B, const T* dinv, T* Y, T* YD, int nsplit,
+           const int* stop, hipStream_t s) {
+    const int L = W / V;
+    const unsigned grid = (unsigned)(((int64_t)M.nslices * L + WAVES - 1) / WAVES);
+    if (!grid) return;
+    if (M.c16)
+        dev::k_sell_mm<T, V, MODE, true><<<grid, BLOCK, 0, s>>>(M.nslices, L, NC, M.sptr, M.srow, M.ci, M.c16,
+                                                                M.cbase, bvals<T>(M), X, B, dinv, Y, YD, nsplit,
+                                                                stop);
+    else
+        dev::k_sell_mm<T, V, MODE, false><<<grid, BLOCK, 0, s>>>(M.nslices, L, NC, M.sptr, M.srow, M.ci, M.c16,
+                                                                 M.cbase, bvals<T>(M), X, B, dinv, Y, YD, nsplit,
+                                                                 stop);
 }
 
 template <class T, int V>
-void csr_mm_m(const DCsrB& M, int mode, int NC, const T* X, const T* B, const T* dinv, T* Y, T* YD, int nsplit,
-              const int* stop, hipStream_t s) {
+void bmm_m(const DSellB& M, int mode, int W, int NC, const T* X, const T* B, const T* dinv, T* Y, T* YD,
+           int nsplit, const int* stop, hipStream_t s) {
     switch (mode) {
-        case dev::SPMV: csr_mm_v<T, V, dev::SPMV>(M, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case dev::SPMV_ADD: csr_mm_v<T, V, dev::SPMV_ADD>(M, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case dev::RESID: csr_mm_v<T, V, dev::RESID>(M, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case dev::JAC: csr_mm_v<T, V, dev::JAC>(M, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case dev::SPLIT: csr_mm_v<T, V, dev::SPLIT>(M, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case dev::SPMV: bmm_v<T, V, dev::SPMV>(M, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case dev::SPMV_ADD: bmm_v<T, V, dev::SPMV_ADD>(M, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case dev::RESID: bmm_v<T, V, dev::RESID>(M, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case dev::JAC: bmm_v<T, V, dev::JAC>(M, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case dev::SPLIT: bmm_v<T, V, dev::SPLIT>(M, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
         default: fail(AMGE_ERR_ARG, "bad SpMM mode");
     }
 }
 
+// Columns per lane actually used: the tuned V, at most the active width W.
+inline int lane_cols(int V, int W) { return std::min(V, W); }
+
+// Block product on the first W (active) of the NC stored columns.
 template <class T>
-void csr_mm(const DCsrB& M, int mode, int NC, const T* X, const T* B, const T* dinv, T* Y, const int* stop,
-            hipStream_t s, int nsplit = 0, T* YD = nullptr) {
-    switch (M.V) {
-        case 1: csr_mm_m<T, 1>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case 2: csr_mm_m<T, 2>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case 4: csr_mm_m<T, 4>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case 8: csr_mm_m<T, 8>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        default: csr_mm_m<T, 16>(M, mode, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+void bmm(const DSellB& M, int mode, int W, int NC, const T* X, const T* B, const T* dinv, T* Y, const int* stop,
+         hipStream_t s, int nsplit = 0, T* YD = nullptr) {
+    switch (lane_cols(M.V, W)) {
+        case 1: bmm_m<T, 1>(M, mode, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case 2: bmm_m<T, 2>(M, mode, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case 4: bmm_m<T, 4>(M, mode, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case 8: bmm_m<T, 8>(M, mode, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        default: bmm_m<T, 16>(M, mode, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
     }
 }
 
 template <class T, int V>
-void inc_mm_v(const DCsrB& M, int NC, const T* X, T* Y, const int* stop, hipStream_t s) {
-    const int L = NC / V;
-    const int rpb = BLOCK / L;
-    const unsigned grid = (unsigned)((M.nrows + rpb - 1) / rpb);
-    if (grid) dev::k_inc_mm_add<T, V><<<grid, BLOCK, 0, s>>>(M.nrows, L, NC, M.rp, M.ent, X, Y, stop);
+void inc_mm_v(const DSellB& M, int W, int NC, const T* X, T* Y, const int* stop, hipStream_t s) {
+    const int L = W / V;
+    const unsigned grid = (unsigned)(((int64_t)M.nslices * L + WAVES - 1) / WAVES);
+    if (grid)
+        dev::k_sell_inc_mm_add<T, V><<<grid, BLOCK, 0, s>>>(M.nslices, L, NC, M.sptr, M.srow, M.ent, X, Y, stop);
 }
 
 template <class T>
-void inc_mm_add(const DCsrB& M, int NC, const T* X, T* Y, const int* stop, hipStream_t s) {
-    switch (M.V) {
-        case 1: inc_mm_v<T, 1>(M, NC, X, Y, stop, s); break;
-        case 2: inc_mm_v<T, 2>(M, NC, X, Y, stop, s); break;
-        case 4: inc_mm_v<T, 4>(M, NC, X, Y, stop, s); break;
-        case 8: inc_mm_v<T, 8>(M, NC, X, Y, stop, s); break;
-        default: inc_mm_v<T, 16>(M, NC, X, Y, stop, s); break;
+void inc_mm_add(const DSellB& M, int W, int NC, const T* X, T* Y, const int* stop, hipStream_t s) {
+    switch (lane_cols(M.V, W)) {
+        case 1: inc_mm_v<T, 1>(M, W, NC, X, Y, stop, s); break;
+        case 2: inc_mm_v<T, 2>(M, W, NC, X, Y, stop, s); break;
+        case 4: inc_mm_v<T, 4>(M, W, NC, X, Y, stop, s); break;
+        case 8: inc_mm_v<T, 8>(M, W, NC, X, Y, stop, s); break;
+        default: inc_mm_v<T, 16>(M, W, NC, X, Y, stop, s); break;
     }
 }
 
@@ -484,7 +499,7 @@ struct BTuneKey {
 static std::map<BTuneKey, int> g_btune;
 
 template <class T>
-int tune_cols(DCsrB& M, bool incidence, int NC, T* X, T* Y, const int* stop, hipStream_t s) {
+int tune_cols(DSellB& M, bool incidence, int NC, T* X, T* Y, const int* stop, hipStream_t s) {
     BTuneKey key{M.nrows, M.ncols, M.nnz, incidence ? 1 : 0, NC, (int)(8 * sizeof(T))};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -503,8 +518,8 @@ int tune_cols(DCsrB& M, bool incidence, int NC, T* X, T* Y, const int* stop, hip
     for (int V : cands) {
         M.V = V;
         auto run = [&]() {
-            if (incidence) inc_mm_add<T>(M, NC, X, Y, stop, s);
-            else csr_mm<T>(M, dev::SPMV, NC, X, nullptr, nullptr, Y, stop, s);
+            if (incidence) inc_mm_add<T>(M, NC, NC, X, Y, stop, s);
+            else bmm<T>(M, dev::SPMV, NC, NC, X, nullptr, nullptr, Y, stop, s);
         };
         run();
         float ms = 1e30f;
@@ -534,17 +549,18 @@ int tune_cols(DCsrB& M, bool incidence, int NC, T* X, T* Y, const int* stop, hip
     return best;
 }
 
-// ---- batched smoother and V-cycle: the single-column steps on n x NC blocks; every
-// kernel returns at once when *stop is set (all columns of a PCG batch converged).
+// ---- batched smoother and V-cycle: the single-column steps on n x NC blocks, of which
+// the first W columns are computed (the others are idle); every kernel returns at once
+// when *stop is set (all columns of a PCG batch converged).
 template <class T>
-void bprimary(amge_hierarchy* H, DLevel& L, const T* b, const T* bd, T*& x, T*& xt, bool from_zero, int nu,
+void bprimary(amge_hierarchy* H, DLevel& L, const T* b, const T* bd, T*& x, T*& xt, bool from_zero, int nu, int W,
               const int* stop, hipStream_t s) {
     Work<T>& w = L.bw<T>();
     const int NC = H->NC;
     int k = 0;
     if (from_zero) {
         if (nu >= 2) {
-            csr_mm<T>(L.bA, dev::JAC, NC, bd, b, w.dinv, x, stop, s);
+            bmm<T>(L.bA, dev::JAC, W, NC, bd, b, w.dinv, x, stop, s);
             k = 2;
         } else if (nu == 1) {
             bcopy<T>((int64_t)L.n * NC, bd, x, stop, s);
@@ -554,35 +570,42 @@ void bprimary(amge_hierarchy* H, DLevel& L, const T* b, const T* bd, T*& x, T*& 
         }
     }
     for (; k < nu; ++k) {
-        csr_mm<T>(L.bA, dev::JAC, NC, x, b, w.dinv, xt, stop, s);
+        bmm<T>(L.bA, dev::JAC, W, NC, x, b, w.dinv, xt, stop, s);
         std::swap(x, xt);
     }
 }
 
 template <class T>
-void bauxiliary(amge_hierarchy* H, DLevel& L, const T* b, T* x, int nu, const int* stop, hipStream_t s) {
+void bauxiliary(amge_hierarchy* H, DLevel& L, const T* b, T* x, int nu, int W, const int* stop, hipStream_t s) {
     if (nu <= 0 || L.m == 0) return;
     Work<T>& w = L.bw<T>();
     const int NC = H->NC;
-    csr_mm<T>(L.bAux, dev::SPLIT, NC, x, b, w.dhinv, w.g, stop, s, L.n, w.gd);
+    bmm<T>(L.bAux, dev::SPLIT, W, NC, x, b, w.dhinv, w.g, stop, s, L.n, w.gd);
     const T* y = w.gd;
     T* ya = w.y;
     T* yb = w.yt;
     for (int k = 1; k < nu; ++k) {
-        csr_mm<T>(L.bAh, dev::JAC, NC, y, w.g, w.dhinv, ya, stop, s);
+        bmm<T>(L.bAh, dev::JAC, W, NC, y, w.g, w.dhinv, ya, stop, s);
         y = ya;
         std::swap(ya, yb);
     }
-    inc_mm_add<T>(L.bD, NC, y, x, stop, s);
+    inc_mm_add<T>(L.bD, W, NC, y, x, stop, s);
+}
+
+inline int log2i(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
 }
 
 template <class T>
-void bvcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, const int* stop, hipStream_t s) {
+void bvcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, int W, const int* stop,
+                   hipStream_t s) {
     const int nl = (int)H->lv.size();
     const int NC = H->NC;
     if (l == nl - 1) {
-        const int64_t t = (int64_t)H->nc * NC;
-        dev::k_coarse_mm<T><<<grid_for(t), BLOCK, 0, s>>>(H->nc, H->lgNC, H->Ainv, b, xout, stop);
+        const int64_t t = (int64_t)H->nc * W;
+        dev::k_coarse_mm<T><<<grid_for(t), BLOCK, 0, s>>>(H->nc, log2i(W), H->lgNC, H->Ainv, b, xout, stop);
         return;
     }
     DLevel& L = H->lv[l];
@@ -593,16 +616,23 @@ void bvcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, c
     T* xt = w.xt;
     const int nup = H->opts.nu_primary, nua = H->opts.nu_aux;
     const bool next_coarsest = l + 1 == nl - 1;
-    bprimary<T>(H, L, b, bd, x, xt, true, nup, stop, s);
-    bauxiliary<T>(H, L, b, x, nua, stop, s);
-    csr_mm<T>(L.bA, dev::RESID, NC, x, b, nullptr, w.r, stop, s);
-    csr_mm<T>(L.bPt, dev::SPMV, NC, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, stop, s, 0,
+    bprimary<T>(H, L, b, bd, x, xt, true, nup, W, stop, s);
+    bauxiliary<T>(H, L, b, x, nua, W, stop, s);
+    bmm<T>(L.bA, dev::RESID, W, NC, x, b, nullptr, w.r, stop, s);
+    bmm<T>(L.bPt, dev::SPMV, W, NC, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, stop, s, 0,
               next_coarsest ? nullptr : wc.bd);
-    bvcycle_level<T>(H, l + 1, wc.b, wc.bd, wc.x, stop, s);
-    csr_mm<T>(L.bP, dev::SPMV_ADD, NC, wc.x, nullptr, nullptr, x, stop, s);
-    bauxiliary<T>(H, L, b, x, nua, stop, s);
-    bprimary<T>(H, L, b, nullptr, x, xt, false, nup, stop, s);
+    bvcycle_level<T>(H, l + 1, wc.b, wc.bd, wc.x, W, stop, s);
+    bmm<T>(L.bP, dev::SPMV_ADD, W, NC, wc.x, nullptr, nullptr, x, stop, s);
+    bauxiliary<T>(H, L, b, x, nua, W, stop, s);
+    bprimary<T>(H, L, b, nullptr, x, xt, false, nup, W, stop, s);
     if (x != xout) bcopy<T>((int64_t)L.n * NC, x, xout, stop, s);
+}
+
+// Active width for nrhs columns: the power of two >= nrhs (at most NC).
+inline int active_width(const amge_hierarchy* H, int nrhs) {
+    int W = 1;
+    while (W < nrhs) W *= 2;
+    return std::min(W, H->NC);
 }
 
 // Batched V-cycle on the caller's n x nrhs FP64 block.
@@ -614,10 +644,9 @@ void bprecondition(amge_hierarchy* H, const double* r, double* z, int nrhs, hipS
     const bool ml = H->lv.size() > 1;
     dev::k_pack<T><<<grid_stride(n * H->NC), BLOCK, 0, s>>>(n, nrhs, H->lgNC, r, ml ? w.dinv : nullptr, w.b,
                                                            ml ? w.bd : nullptr);
-    bvcycle_level<T>(H, 0, w.b, w.bd, w.x, H->zero_flag, s);
+    bvcycle_level<T>(H, 0, w.b, w.bd, w.x, active_width(H, nrhs), H->zero_flag, s);
     dev::k_unpack<T><<<grid_stride(n * nrhs), BLOCK, 0, s>>>(n, nrhs, H->lgNC, w.x, z);
 }
-
 
 // ------------------------------------------------------------------ set-up
 void build_coarse(amge_hierarchy* H, const Csr& A, hipStream_t s) {
@@ -715,7 +744,7 @@ template <class T>
 void tune_batched(amge_hierarchy* H, hipStream_t s) {
     size_t mx = 0, my = 0;
     for (DLevel& L : H->lv)
-        for (DCsrB* M : {&L.bA, &L.bAh, &L.bP, &L.bPt, &L.bAux, &L.bD})
+        for (DSellB* M : {&L.bA, &L.bAh, &L.bP, &L.bPt, &L.bAux, &L.bD})
             if (M->nrows) {
                 mx = std::max(mx, (size_t)M->ncols * H->NC);
                 my = std::max(my, (size_t)M->nrows * H->NC);
@@ -727,7 +756,7 @@ void tune_batched(amge_hierarchy* H, hipStream_t s) {
     HIPCHECK(hipMemsetAsync(X, 0, sizeof(T) * mx, s));
     HIPCHECK(hipMemsetAsync(Y, 0, sizeof(T) * my, s));
     for (DLevel& L : H->lv) {
-        for (DCsrB* M : {&L.bA, &L.bAh, &L.bP, &L.bPt, &L.bAux})
+        for (DSellB* M : {&L.bA, &L.bAh, &L.bP, &L.bPt, &L.bAux})
             if (M->nrows) tune_cols<T>(*M, false, H->NC, X, Y, H->zero_flag, s);
         if (L.bD.nrows) tune_cols<T>(L.bD, true, H->NC, X, Y, H->zero_flag, s);
     }
@@ -749,14 +778,14 @@ void setup_batched(amge_hierarchy* H, const std::vector<HostLevel>& hl, hipStrea
         const HostLevel& h = hl[k];
         if (k < nl - 1 || nl == 1) {
             // A_1 is also the outer PCG operator (FP64)
-            L.bA = upload_csr_b(H, h.A, false, f32, !f32 || k == 0, s);
+            L.bA = upload_sell_b(H, h.A, false, f32, !f32 || k == 0, s);
         }
         if (k < nl - 1) {
-            L.bAh = upload_csr_b(H, h.Ah, false, f32, !f32, s);
-            L.bP = upload_csr_b(H, h.P, false, f32, !f32, s);
-            L.bPt = upload_csr_b(H, h.Pt, false, f32, !f32, s);
-            L.bAux = upload_csr_b(H, h.Aux, false, f32, !f32, s);
-            L.bD = upload_csr_b(H, h.D, true, false, false, s);
+            L.bAh = upload_sell_b(H, h.Ah, false, f32, !f32, s);
+            L.bP = upload_sell_b(H, h.P, false, f32, !f32, s);
+            L.bPt = upload_sell_b(H, h.Pt, false, f32, !f32, s);
+            L.bAux = upload_sell_b(H, h.Aux, false, f32, !f32, s);
+            L.bD = upload_sell_b(H, h.D, true, false, false, s);
         }
         if (f32 && nl > 1) alloc_bwork<float>(H, L, L.w32, L.bw32);
         else alloc_bwork<double>(H, L, L.w64, L.bw64);
@@ -1054,19 +1083,29 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
 // ---- batched inexact PCG: the single-column recurrences per column, with the
 // stopping test per column on the device (a finished column takes alpha = 0 and keeps
 // its iterate).  Columns are loaded as "fresh": their first pass through an iteration
-// computes z0 = B b and the initial quantities, so columns loaded at different times
-// share every launch (the serving engine inserts requests into free columns between
-// chunks).  One iteration is captured once as a HIP graph on the hierarchy's own
-// stream and replayed in chunks; the host polls the batch status between chunks.
+// computes z0 = B b and the initial quantities instead of a step, so columns loaded at
+// different times share every launch (the serving engine inserts requests into free
+// columns between chunks).  One iteration per active width W (the first W of the NC
+// columns) is captured as a HIP graph on the hierarchy's own stream and replayed in
+// chunks; the host polls the batch status between chunks.  Sums over rows run in the
+// same order whatever W is, so a column's result does not depend on the width.
 
-void bpcg_ap(amge_hierarchy* H, hipStream_t s) {
-    const DCsrB& A = H->lv[0].bA;
-    if (H->NC >= 2)   // 16-byte lane loads
-        dev::k_bpcg_ap<2><<<BPCG_BLOCKS, BLOCK, 0, s>>>(A.nrows, H->NC, A.rp, A.ci, A.v64, H->bP, H->bQ, H->bpart,
-                                                        H->bs);
-    else
-        dev::k_bpcg_ap<1><<<BPCG_BLOCKS, BLOCK, 0, s>>>(A.nrows, H->NC, A.rp, A.ci, A.v64, H->bP, H->bQ, H->bpart,
-                                                        H->bs);
+template <int V, bool C16>
+void bpcg_ap_v(amge_hierarchy* H, int W, hipStream_t s) {
+    const DSellB& A = H->lv[0].bA;
+    dev::k_bpcg_ap<V, C16><<<BPCG_BLOCKS, BLOCK, 0, s>>>(A.nslices, W, H->NC, A.sptr, A.srow, A.ci, A.c16, A.cbase,
+                                                         A.v64, H->bP, H->bQ, H->bpart, H->bs);
+}
+
+void bpcg_ap(amge_hierarchy* H, int W, hipStream_t s) {
+    const bool c16 = H->lv[0].bA.c16 != nullptr;
+    if (H->NC >= 2) {   // 16-byte lane loads
+        if (c16) bpcg_ap_v<2, true>(H, W, s);
+        else bpcg_ap_v<2, false>(H, W, s);
+    } else {
+        if (c16) bpcg_ap_v<1, true>(H, W, s);
+        else bpcg_ap_v<1, false>(H, W, s);
+    }
 }
 
 // The FP32 V-cycle reads its input from the level-1 FP32 block; a one-level hierarchy
@@ -1074,56 +1113,64 @@ void bpcg_ap(amge_hierarchy* H, hipStream_t s) {
 bool bz32(const amge_hierarchy* H) { return H->opts.precond_bits == 32 && H->lv.size() > 1; }
 
 // z = B r on the residual block in the preconditioner precision; writes zv.
-void bpcg_precond(amge_hierarchy* H, const int* stop, hipStream_t s) {
+void bpcg_precond(amge_hierarchy* H, int W, const int* stop, hipStream_t s) {
     DLevel& L = H->lv[0];
-    if (bz32(H)) bvcycle_level<float>(H, 0, L.bw32.b, L.bw32.bd, L.bw32.x, stop, s);
-    else bvcycle_level<double>(H, 0, H->bR, L.bw64.bd, H->bZv, stop, s);
+    if (bz32(H)) bvcycle_level<float>(H, 0, L.bw32.b, L.bw32.bd, L.bw32.x, W, stop, s);
+    else bvcycle_level<double>(H, 0, H->bR, L.bw64.bd, H->bZv, W, stop, s);
 }
 
-void bpcg_dots(amge_hierarchy* H, hipStream_t s) {
+void bpcg_dots(amge_hierarchy* H, int W, hipStream_t s) {
     DLevel& L = H->lv[0];
     const int n = L.n;
     if (bz32(H))
-        dev::k_bpcg_dots<float><<<BPCG_BLOCKS, BLOCK, 0, s>>>(n, H->NC, L.bw32.x, (float*)H->bZ, H->bR, H->bpart,
+        dev::k_bpcg_dots<float><<<BPCG_BLOCKS, BLOCK, 0, s>>>(n, W, H->NC, L.bw32.x, (float*)H->bZ, H->bR, H->bpart,
                                                               H->bs);
     else
-        dev::k_bpcg_dots<double><<<BPCG_BLOCKS, BLOCK, 0, s>>>(n, H->NC, H->bZv, H->bZ, H->bR, H->bpart, H->bs);
+        dev::k_bpcg_dots<double><<<BPCG_BLOCKS, BLOCK, 0, s>>>(n, W, H->NC, H->bZv, H->bZ, H->bR, H->bpart, H->bs);
 }
 
-// One PCG iteration (the captured body): q = A p, alpha, x/r update with the next
-// preconditioner input, z = B r, dots, stopping test and beta, p update.
-void bpcg_iteration(amge_hierarchy* H, hipStream_t s) {
+// One PCG iteration on the first W columns (the captured body): q = A p, alpha, x/r
+// update with the next preconditioner input, z = B r, dots, stopping test and beta,
+// p update.
+void bpcg_iteration(amge_hierarchy* H, int W, hipStream_t s) {
     DLevel& L = H->lv[0];
-    const int64_t nn = (int64_t)L.n * H->NC;
+    const int lgW = log2i(W);
+    const int64_t nn = (int64_t)L.n * W;
     const bool f32 = bz32(H);
     const bool ml = H->lv.size() > 1;
     const unsigned g = grid_stride(nn);
-    bpcg_ap(H, s);
-    dev::k_bpcg_alpha<<<1, dev::FIN_BLOCK, 0, s>>>(H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
-    dev::k_bpcg_xr<<<g, BLOCK, 0, s>>>(nn, H->lgNC, H->cs, H->bP, H->bQ, H->bX, H->bR, f32 ? L.bw32.b : nullptr,
-                                       f32 ? L.bw32.bd : nullptr, f32 ? L.bw32.dinv : nullptr,
-                                       !f32 && ml ? L.bw64.bd : nullptr, !f32 && ml ? L.bw64.dinv : nullptr, H->bs);
-    bpcg_precond(H, &H->bs->all_done, s);
-    bpcg_dots(H, s);
-    dev::k_bpcg_update<<<1, dev::FIN_BLOCK, 0, s>>>(H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
-    if (f32) dev::k_bpcg_p<float><<<g, BLOCK, 0, s>>>(nn, H->lgNC, H->cs, (const float*)H->bZ, H->bP, H->bs);
-    else dev::k_bpcg_p<double><<<g, BLOCK, 0, s>>>(nn, H->lgNC, H->cs, H->bZ, H->bP, H->bs);
+    bpcg_ap(H, W, s);
+    dev::k_bpcg_alpha<<<1, dev::FIN_BLOCK, 0, s>>>(W, H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
+    dev::k_bpcg_xr<<<g, BLOCK, 0, s>>>(nn, lgW, H->lgNC, H->cs, H->bP, H->bQ, H->bX, H->bR,
+                                       f32 ? L.bw32.b : nullptr, f32 ? L.bw32.bd : nullptr,
+                                       f32 ? L.bw32.dinv : nullptr, !f32 && ml ? L.bw64.bd : nullptr,
+                                       !f32 && ml ? L.bw64.dinv : nullptr, H->bs);
+    bpcg_precond(H, W, &H->bs->all_done, s);
+    bpcg_dots(H, W, s);
+    dev::k_bpcg_update<<<1, dev::FIN_BLOCK, 0, s>>>(W, H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
+    if (f32)
+        dev::k_bpcg_p<float><<<g, BLOCK, 0, s>>>(nn, lgW, H->lgNC, H->cs, (const float*)H->bZ, H->bP, H->bs);
+    else
+        dev::k_bpcg_p<double><<<g, BLOCK, 0, s>>>(nn, lgW, H->lgNC, H->cs, H->bZ, H->bP, H->bs);
 }
 
-void capture_iteration(amge_hierarchy* H) {
-    if (H->gexec) return;
+hipGraphExec_t capture_iteration(amge_hierarchy* H, int W) {
     if (H->NC < 2 || !H->gstream) fail(AMGE_ERR_ARG, "hierarchy has no batched path (max_rhs = 1)");
+    if (W < 1 || W > H->NC || (W & (W - 1))) fail(AMGE_ERR_ARG, "active width must be a power of two <= NC");
+    hipGraphExec_t& ex = H->gexec[log2i(W)];
+    if (ex) return ex;
     hipGraph_t graph = nullptr;
     HIPCHECK(hipStreamBeginCapture(H->gstream, hipStreamCaptureModeThreadLocal));
-    bpcg_iteration(H, H->gstream);
+    bpcg_iteration(H, W, H->gstream);
     hipError_t e = hipStreamEndCapture(H->gstream, &graph);
     if (e != hipSuccess || !graph) fail(AMGE_ERR_HIP, "graph capture of the batched PCG iteration failed");
-    e = hipGraphInstantiate(&H->gexec, graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
-        H->gexec = nullptr;
+        ex = nullptr;
         fail(AMGE_ERR_HIP, "graph instantiation failed");
     }
+    return ex;
 }
 
 amge_status bpcg(amge_hierarchy* H, const double* b, double* x, int nrhs, double rtol, int maxit, int stop_l2,
@@ -1132,7 +1179,8 @@ amge_status bpcg(amge_hierarchy* H, const double* b, double* x, int nrhs, double
     const int64_t n = L.n;
     const int NC = H->NC;
     hipStream_t gs = H->gstream;
-    capture_iteration(H);
+    const int W = active_width(H, nrhs);
+    hipGraphExec_t ex = capture_iteration(H, W);
     // order the internal stream after the caller's work
     HIPCHECK(hipEventRecord(H->ev_in, s));
     HIPCHECK(hipStreamWaitEvent(gs, H->ev_in, 0));
@@ -1143,7 +1191,7 @@ amge_status bpcg(amge_hierarchy* H, const double* b, double* x, int nrhs, double
     // every column finishes within maxit steps after its initial pass
     for (int launched = 0;;) {
         if (launched > maxit + 1) fail(AMGE_ERR_HIP, "batched PCG did not terminate");
-        for (int i = 0; i < BPCG_CHUNK; ++i) HIPCHECK(hipGraphLaunch(H->gexec, gs));
+        for (int i = 0; i < BPCG_CHUNK; ++i) HIPCHECK(hipGraphLaunch(ex, gs));
         launched += BPCG_CHUNK;
         HIPCHECK(hipMemcpyAsync(&st, H->bs, sizeof(st), hipMemcpyDeviceToHost, gs));
         HIPCHECK(hipStreamSynchronize(gs));
@@ -1408,12 +1456,12 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
             const double n = L.n, m = L.m, nc = h->lv[k + 1].n;
             // matrix streams: values + column indices + one row pointer (sliced ELL: one
             // row index) per row; incidences are index-only
-            auto mat = [&](const DSell& M, const DCsrB& B) {
-                return batched ? (double)B.nnz * (sv + 4.0) + 4.0 * (B.nrows + 1)
+            auto mat = [&](const DSell& M, const DSellB& B) {
+                return batched ? (double)B.nnz * (sv + (B.c16 ? 2.0 : 4.0)) + 4.0 * B.nrows
                                : (double)M.nnz * (sv + (M.c16 ? 2.0 : 4.0)) + 4.0 * M.nrows;
             };
-            auto incb = [&](const DSell& M, const DCsrB& B) {
-                return batched ? (double)B.nnz * 4.0 + 4.0 * (B.nrows + 1) : (double)M.nnz * 4.0 + 4.0 * M.nrows;
+            auto incb = [&](const DSell& M, const DSellB& B) {
+                return batched ? (double)B.nnz * 4.0 + 4.0 * B.nrows : (double)M.nnz * 4.0 + 4.0 * M.nrows;
             };
             // primary sweeps: the first one from zero is the producer's bd = dinv b (two
             // extra streams there), every launched sweep reads x, b and writes y (+ dinv)

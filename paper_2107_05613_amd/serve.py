@@ -104,6 +104,42 @@ def run(srv, ids, mix, arrivals=None, order=None, rtol=1e-8, maxit=1000, poll_sl
     return done, lat, makespan
 
 
+def run_closed(srv, ids, mix, concurrency, rtol=1e-8, maxit=1000, poll_sleep=20e-6):
+    """Closed loop: `concurrency` requests outstanding at all times; each completion
+    submits the next request of the stream.  Returns completions, latencies (completion
+    - submission) and the makespan."""
+    import torch
+    order = list(range(len(mix.requests)))
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sub_t, done, done_t = {}, {}, {}
+    nxt = 0
+
+    def submit_one():
+        nonlocal nxt
+        j = order[nxt]
+        srv.submit(ids[mix.hid_of[j]], mix.rhs[j], mix.x[j], tag=j, rtol=rtol, maxit=maxit, stream=stream)
+        sub_t[j] = time.perf_counter() - t0
+        nxt += 1
+
+    while nxt < min(concurrency, len(order)):
+        submit_one()
+    while len(done) < len(order):
+        got = srv.progress(wait=False)
+        tnow = time.perf_counter() - t0
+        for tag, hid, status, iters, relres in got:
+            done[tag] = (status, iters, relres)
+            done_t[tag] = tnow
+            if nxt < len(order):
+                submit_one()
+        if not got:
+            time.sleep(poll_sleep)
+    makespan = max(done_t.values()) if done_t else 0.0
+    lat = {j: done_t[j] - sub_t[j] for j in order}
+    return done, lat, makespan
+
+
 def latency_stats(lat):
     v = np.sort(np.asarray(list(lat.values())))
     return {"p50_ms": 1e3 * float(np.percentile(v, 50)), "p99_ms": 1e3 * float(np.percentile(v, 99)),
