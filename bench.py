@@ -195,7 +195,7 @@ def run_serving(args):
     mix = serve.build_mix(num=args.serving_requests, seed=0, slots=8, precond_bits=0)
     print(f"[bench] serving: {len(mix.keys)} hierarchies built in {time.perf_counter() - t0:.1f}s "
           f"(build {mix.build_s:.1f}s, device setup {mix.setup_s:.1f}s)", file=sys.stderr, flush=True)
-    srv, ids = serve.make_server(mix, chunk=2)
+    srv, ids = serve.make_server(mix, chunk=8)
     resident = srv.stats()["resident_bytes"]
     prec = [h.precision_info() for h in mix.hierarchies]
     n32 = sum(1 for k, b in prec if b == 32)

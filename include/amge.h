@@ -184,7 +184,10 @@ const char* amge_last_error(void);
  *                     admitted in submission order, a request that does not fit waits
  *                     and holds back those behind it, one whose hierarchy has no free
  *                     column does not
- *   chunk             PCG iterations per hierarchy between two looks at its columns
+ *   chunk             at most this many PCG iterations per hierarchy between two looks at
+ *                     its columns (fewer on large hierarchies: chunks are sized to about
+ *                     2 ms of estimated GPU time, and chunks of different hierarchies are
+ *                     started in turn while the estimated queued GPU time stays under 8 ms)
  *
  * Single-threaded: calls on one server must not overlap.  A hierarchy added to a
  * server (it needs max_rhs >= 2: its max_rhs is the number of columns) is used only by

@@ -297,7 +297,7 @@ class Server:
     single right-hand-side requests.  Hierarchies passed to add() must have max_rhs >= 2
     and must outlive the server; they are used only by it."""
 
-    def __init__(self, hierarchy_budget=0, inflight_budget=0, chunk=2):
+    def __init__(self, hierarchy_budget=0, inflight_budget=0, chunk=8):
         h = C.c_void_p()
         _check(_lib.amge_server_create(int(hierarchy_budget), int(inflight_budget), int(chunk), C.byref(h)))
         self._h = h

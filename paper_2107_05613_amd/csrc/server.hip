@@ -16,6 +16,7 @@
 // does not.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <deque>
 #include <memory>
@@ -104,7 +105,18 @@ struct Group {
     bool chunk_busy = false;
     std::vector<int> extracting;   // requests whose copy-out is in flight
     int active = 0;                // columns holding a request
+    // cost model of one PCG iteration on W columns: fixed + W * per_col milliseconds
+    // (launch overhead, matrix bytes, vector bytes at a nominal bandwidth)
+    double fixed_ms = 0, per_col_ms = 0;
+    double chunk_ms = 0;           // estimate for the chunk in flight
+    uint64_t turn = 0;             // when the group last finished a chunk (scheduling order)
 };
+
+// Nominal figures of the scheduling cost model.
+constexpr double SCHED_BW_BYTES_PER_MS = 3.0e9;   // 3 TB/s
+constexpr double SCHED_LAUNCH_MS = 0.003;          // per kernel of an iteration
+constexpr double SCHED_CHUNK_MS = 2.0;             // target length of a chunk
+constexpr double SCHED_QUEUE_MS = 8.0;             // estimated work allowed in flight
 
 }  // namespace
 }  // namespace amge
@@ -114,7 +126,9 @@ using namespace amge;
 struct amge_server {
     size_t hierarchy_budget = 0, inflight_budget = 0;
     size_t resident = 0, inflight = 0;
-    int chunk = 2;
+    int chunk = 2;                    // upper bound on iterations per chunk
+    double queued_ms = 0;             // estimated GPU time of the chunks in flight
+    uint64_t clock = 0;               // scheduling turns
     std::vector<std::unique_ptr<Group>> groups;
     std::vector<Request> reqs;        // request table (indices stay valid)
     std::vector<int> free_reqs;       // reusable entries of the table
@@ -182,6 +196,9 @@ struct amge_server {
         if (e == hipErrorNotReady) return false;
         HIPCHECK(e);
         g.chunk_busy = false;
+        queued_ms -= g.chunk_ms;
+        if (queued_ms < 1e-9) queued_ms = 0;
+        g.turn = ++clock;
         amge_hierarchy* H = g.H;
         const int64_t n = H->lv[0].n;
         bool any = false;
@@ -241,12 +258,20 @@ struct amge_server {
         return any;
     }
 
-    // Starts a chunk of iterations on every idle group that holds requests.
+    // Starts chunks of iterations on idle groups that hold requests, in the order in which
+    // they last finished one (every group gets its turn), while the estimated GPU time of
+    // the chunks in flight stays within SCHED_QUEUE_MS (at least one chunk always runs).
+    // Hardware queues run kernels in order, so bounding the queued work bounds how long a
+    // new chunk of a small hierarchy waits behind the chunks of large ones.  A chunk has as
+    // many iterations as fit SCHED_CHUNK_MS (at least one, at most `chunk`).
     bool launch() {
+        std::vector<Group*> cand;
+        for (auto& gp : groups)
+            if (!gp->chunk_busy && gp->active > 0) cand.push_back(gp.get());
+        std::sort(cand.begin(), cand.end(), [](const Group* a, const Group* b) { return a->turn < b->turn; });
         bool any = false;
-        for (auto& gp : groups) {
+        for (Group* gp : cand) {
             Group& g = *gp;
-            if (g.chunk_busy || g.active == 0) continue;
             amge_hierarchy* H = g.H;
             // active width: the columns up to the highest occupied one (requests take the
             // lowest free column)
@@ -255,12 +280,18 @@ struct amge_server {
                 if (g.slot[c] >= 0) hi = c + 1;
             int W = 1;
             while (W < hi) W *= 2;
+            const double it_ms = g.fixed_ms + W * g.per_col_ms;
+            const int k = std::max(1, std::min(chunk, (int)(SCHED_CHUNK_MS / it_ms)));
+            const double est = k * it_ms;
+            if (queued_ms > 0 && queued_ms + est > SCHED_QUEUE_MS) break;
             hipGraphExec_t ex = capture_iteration(H, W);
-            for (int i = 0; i < chunk; ++i) HIPCHECK(hipGraphLaunch(ex, H->gstream));
+            for (int i = 0; i < k; ++i) HIPCHECK(hipGraphLaunch(ex, H->gstream));
             HIPCHECK(hipMemcpyAsync(g.cs_host, H->cs, sizeof(dev::ColState) * H->NC, hipMemcpyDeviceToHost,
                                     H->gstream));
             HIPCHECK(hipEventRecord(g.ev_chunk, H->gstream));
             g.chunk_busy = true;
+            g.chunk_ms = est;
+            queued_ms += est;
             any = true;
         }
         return any;
@@ -325,6 +356,20 @@ extern "C" amge_status amge_server_add(amge_server* s, amge_hierarchy* h, int32_
         for (const DLevel& L : h->lv) cb += vs * (5 * (size_t)L.n + 4 * (size_t)L.m);
         g->col_bytes = cb;
         g->slot.assign(h->NC, -1);
+        {
+            // cost model: V-cycle bytes on one and two columns (amge_vcycle_bytes), the FP64
+            // product with A_1 and about twelve FP64 vector streams of the PCG updates
+            const int bits = h->opts.precond_bits == 32 && h->lv.size() > 1 ? 32 : 64;
+            double b1 = 0, b2 = 0;
+            if (amge_vcycle_bytes(h, bits, 1, &b1) != AMGE_OK || amge_vcycle_bytes(h, bits, 2, &b2) != AMGE_OK)
+                fail(AMGE_ERR_ARG, "cost model");
+            const double n1 = h->lv[0].n;
+            const double col = (b2 - b1) + 12 * 8 * n1;
+            const double mat = (b1 - (b2 - b1)) + 12.0 * (double)h->lv[0].A.nnz;
+            const int kernels = 16 * ((int)h->lv.size() - 1) + 8;
+            g->fixed_ms = kernels * SCHED_LAUNCH_MS + std::max(0.0, mat) / SCHED_BW_BYTES_PER_MS;
+            g->per_col_ms = col / SCHED_BW_BYTES_PER_MS;
+        }
         HIPCHECK(hipHostMalloc((void**)&g->cs_host, sizeof(dev::ColState) * h->NC, hipHostMallocDefault));
         HIPCHECK(hipEventCreateWithFlags(&g->ev_chunk, hipEventDisableTiming));
         HIPCHECK(hipEventCreateWithFlags(&g->ev_extract, hipEventDisableTiming));

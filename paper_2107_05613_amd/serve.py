@@ -59,7 +59,7 @@ def build_mix(num=256, seed=0, sizes=(16, 24, 32, 48, 64), coef_pool=2, slots=8,
     return Mix(reqs, keys, hs, hid_of, rhs, xs, tb, ts)
 
 
-def make_server(mix, hierarchy_budget=0, inflight_budget=0, chunk=2):
+def make_server(mix, hierarchy_budget=0, inflight_budget=0, chunk=8):
     srv = amge.Server(hierarchy_budget, inflight_budget, chunk)
     ids = [srv.add(h) for h in mix.hierarchies]
     return srv, ids
