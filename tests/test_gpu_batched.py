@@ -219,3 +219,23 @@ def test_batched_edge_cases():
     # the hierarchy still solves after the rejected calls
     status, its, rrs = c.gpu[32].pcg(dev(B), X, rtol=1e-8, nrhs=nrhs)
     assert status == 0 and max(rrs) <= 1e-8
+
+
+@pytest.mark.parametrize("nrhs", [33, 64])
+def test_batched_widest_block(nrhs):
+    """The widest block (max_rhs = 64, the largest supported): 33 columns (padded to 64)
+    and 64 columns; sampled columns against the oracle's fixed-count PCG iterate."""
+    from oracle.solve import pcg
+    c = bcase("div", 8, 3, "blocks", 64)
+    B = W.rhs(c.n1, 71, nrhs)
+    X = torch.zeros(c.n1 * nrhs, dtype=torch.float64, device="cuda")
+    k = 10
+    status, its, _ = c.gpu[64].pcg(dev(B), X, rtol=0.0, maxit=k, nrhs=nrhs)
+    assert its == [k] * nrhs
+    Xs = host(X).reshape(c.n1, nrhs)
+    for j in (0, nrhs // 2, nrhs - 1):
+        xo, _, _ = pcg(c.H.A[0], B[:, j], c.ml, fixed_iters=k)
+        assert np.linalg.norm(Xs[:, j] - xo) <= c.tol64 * np.linalg.norm(xo), j
+    # FP32 preconditioner converges in every column
+    status, its, rrs = c.gpu[32].pcg(dev(B), X, rtol=1e-8, nrhs=nrhs)
+    assert status == 0 and max(rrs) <= 1e-8
