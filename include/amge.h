@@ -88,10 +88,14 @@ void amge_default_opts(amge_opts* opts);
 
 /* Builds the device hierarchy from host level matrices (section 3.2, Algorithm 4.1 inputs).
  * Host work: validation, D^T, P^T, the products D^T A and D^T A D (FP64 sparse products;
- * the auxiliary residual D^T (b - A x) is evaluated as D^T b - (D^T A) x), the l1 row sums, a dense FP64 Cholesky factor of the
- * coarsest matrix and its inverse factor.  Device buffers are owned by the hierarchy.
- * Errors: AMGE_ERR_ARG, AMGE_ERR_SHAPE, AMGE_ERR_NONFINITE, AMGE_ERR_NOT_SPD (coarsest
- * matrix), AMGE_ERR_OOM, AMGE_ERR_HIP. */
+ * the auxiliary residual D^T (b - A x) is evaluated as D^T b - (D^T A) x), the l1 row
+ * sums, the cancellation factor, a dense FP64 Cholesky factor of the coarsest matrix and
+ * the inverse it gives (coarsest level at most 8192 rows).  The device layouts are tuned
+ * by timing candidate launches on `stream`.  Device buffers and a private stream (for the
+ * captured PCG iterations) are owned by the hierarchy.
+ * Errors: AMGE_ERR_ARG, AMGE_ERR_SHAPE, AMGE_ERR_NONFINITE (NaN/Inf value),
+ * AMGE_ERR_NOT_SPD (coarsest matrix not symmetric positive definite, or a zero row),
+ * AMGE_ERR_OOM, AMGE_ERR_HIP. */
 amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nlevels, const amge_opts* opts,
                                  void* stream, amge_hierarchy** out);
 
@@ -101,17 +105,26 @@ void amge_destroy(amge_hierarchy* h);
 amge_status amge_footprint(const amge_hierarchy* h, size_t* bytes);
 
 /* z = B r: one V-cycle of Algorithm 4.1 with zero initial guess, on nrhs columns.
- * r, z: device FP64, n_1 x nrhs row-major.  nrhs <= opts.max_rhs. */
+ * r, z: device FP64, n_1 x nrhs row-major.  1 <= nrhs <= opts.max_rhs; nrhs > 1 runs
+ * the batched kernels (one launch per level operator for all columns).  Asynchronous
+ * on `stream`. */
 amge_status amge_vcycle(amge_hierarchy* h, const double* r, double* z, int32_t nrhs, void* stream);
 
 /* Inexact PCG (section 5.1) for A_1 x = b with x0 = 0 and one V-cycle per iteration.
  *   b, x     device FP64, n_1 x nrhs row-major; x is overwritten
+ *   nrhs     1 <= nrhs <= opts.max_rhs; every column follows its own recurrences and
+ *            stopping test (nrhs > 1: batched kernels, a column that has stopped keeps
+ *            its iterate while the others go on)
  *   rtol     stop when sqrt(r.z / r0.z0) <= rtol (stop_norm = 0, preconditioner norm) or
  *            ||r|| / ||b|| <= rtol (stop_norm = 1); rtol <= 0 runs exactly maxit iterations
- *   iters    host, nrhs entries: products with A_1 per column
+ *   iters    host, nrhs entries: PCG steps per column (0 for a zero right-hand side)
  *   relres   host, nrhs entries: final relative residual in the chosen norm
- * Returns AMGE_NOT_CONVERGED if a column missed rtol within maxit, AMGE_ERR_NONFINITE
- * for a NaN/Inf right-hand side, AMGE_ERR_BREAKDOWN if p.q <= 0 occurs. */
+ * The iterations run as replays of a HIP graph captured on the hierarchy's own stream
+ * (ordered after `stream` and before later work on it by events); the call returns after
+ * the solve.  Returns AMGE_NOT_CONVERGED if a column missed rtol within maxit,
+ * AMGE_ERR_NONFINITE for a NaN/Inf right-hand side (nrhs > 1: in any column; the other
+ * columns are still solved and written), AMGE_ERR_BREAKDOWN if p.q <= 0 or r.z <= 0
+ * occurs. */
 amge_status amge_pcg_solve(amge_hierarchy* h, const double* b, double* x, int32_t nrhs, double rtol,
                            int32_t maxit, int32_t stop_norm, int32_t* iters, double* relres, void* stream);
 
