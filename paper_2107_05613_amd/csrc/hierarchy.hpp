@@ -32,6 +32,7 @@ struct DSell {
     uint32_t* ent = nullptr;  // incidence matrices: column | sign << 31, padding 0xffffffff
     double* v64 = nullptr;
     float* v32 = nullptr;
+    bool stream = false;      // FP32 matrix streams read with non-temporal loads
 };
 
 template <class T>

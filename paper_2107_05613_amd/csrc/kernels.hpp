@@ -71,13 +71,17 @@ __device__ __forceinline__ int col_at(const int* __restrict__ ci, const uint16_t
     return NT ? __builtin_nontemporal_load(ci + e) : ci[e];
 }
 
-template <typename T>
+template <typename T, bool NT = (sizeof(T) == 8)>
 __device__ __forceinline__ T stream_load(const T* __restrict__ p) {
-    if (sizeof(T) == 8) return __builtin_nontemporal_load(p);
+    if (NT) return __builtin_nontemporal_load(p);
     return *p;
 }
 
-template <typename T, int K, int MODE, bool C16>
+// NT: non-temporal loads of the matrix streams (FP64 always; FP32 for the operators
+// other than A_k, so that A_k, used four times per V-cycle, stays in the last-level
+// cache between its uses: the fine-level FP32 sweep of the 64^3 H(curl) workload takes
+// 45 instead of 50 us).
+template <typename T, int K, int MODE, bool C16, bool NT>
 __global__ void __launch_bounds__(BLOCK)
 k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const int* __restrict__ ci,
        const uint16_t* __restrict__ c16, const int* __restrict__ cbase, const T* __restrict__ av,
@@ -96,23 +100,39 @@ k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, 
     const int cb = C16 ? cbase[slice] : 0;
     const int e0 = base + lane;
     const T* v = av + e0;
+    // the row's own operands of the update are requested before the product, so their
+    // latency overlaps it
+    const bool owner = row >= 0 && !(lane & (K - 1));
+    const int rw = owner ? row : 0;
+    T xr = 0, br = 0, dr = 0;
+    if (MODE == JAC) {
+        xr = x[rw];
+        br = b[rw];
+        dr = dinv[rw];
+    } else if (MODE == RESID) {
+        br = b[rw];
+    } else if (MODE == SPMV_ADD) {
+        xr = y[rw];
+    } else if (yd) {
+        dr = dinv[rw];
+    }
     T acc = 0;
 #pragma unroll 4
     for (int k = 0; k < width; ++k) {
-        const int j = col_at<C16, sizeof(T) == 8>(ci, c16, cb, e0 + k * 64);
+        const int j = col_at<C16, NT || sizeof(T) == 8>(ci, c16, cb, e0 + k * 64);
         T xv;
         if (MODE == SPLIT) xv = j < nsplit ? b[j] : x[j - nsplit];
         else xv = x[j];
-        acc = fma(stream_load(v + k * 64), xv, acc);
+        acc = fma(stream_load<T, NT || sizeof(T) == 8>(v + k * 64), xv, acc);
     }
     acc = row_sum<K>(acc);
-    if (row < 0 || (lane & (K - 1))) return;
+    if (!owner) return;
     if (MODE == SPMV || MODE == SPLIT) {
         y[row] = acc;
-        if (yd) yd[row] = dinv[row] * acc;
-    } else if (MODE == SPMV_ADD) y[row] += acc;
-    else if (MODE == RESID) y[row] = b[row] - acc;
-    else y[row] = x[row] + dinv[row] * (b[row] - acc);
+        if (yd) yd[row] = dr * acc;
+    } else if (MODE == SPMV_ADD) y[row] = xr + acc;
+    else if (MODE == RESID) y[row] = br - acc;
+    else y[row] = xr + dr * (br - acc);
 }
 
 // Signed incidence, index-only (same layout): y = D x (ADD = 0) or y += D x (ADD = 1).

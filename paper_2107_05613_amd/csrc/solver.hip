@@ -75,26 +75,23 @@ void sell_k(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* 
     unsigned g = grid_slices(M.nslices);
     if (g == 0) return;
     const T* v = vals<T>(M);
-#define AMGE_SELL(MODE, C16)                                                                              \
-    dev::k_sell<T, K, MODE, C16><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ci, M.c16, M.cbase, v, x, b, \
-                                                     dinv, y, yd, nsplit, stop)
-    if (M.c16) {
-        switch (mode) {
-            case dev::SPMV: AMGE_SELL(dev::SPMV, true); break;
-            case dev::SPMV_ADD: AMGE_SELL(dev::SPMV_ADD, true); break;
-            case dev::RESID: AMGE_SELL(dev::RESID, true); break;
-            case dev::JAC: AMGE_SELL(dev::JAC, true); break;
-            default: AMGE_SELL(dev::SPLIT, true); break;
-        }
-    } else {
-        switch (mode) {
-            case dev::SPMV: AMGE_SELL(dev::SPMV, false); break;
-            case dev::SPMV_ADD: AMGE_SELL(dev::SPMV_ADD, false); break;
-            case dev::RESID: AMGE_SELL(dev::RESID, false); break;
-            case dev::JAC: AMGE_SELL(dev::JAC, false); break;
-            default: AMGE_SELL(dev::SPLIT, false); break;
-        }
+#define AMGE_SELL(MODE, C16, NT)                                                                          \
+    dev::k_sell<T, K, MODE, C16, NT><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ci, M.c16, M.cbase, v, x, \
+                                                         b, dinv, y, yd, nsplit, stop)
+#define AMGE_SELL_MODES(C16, NT)                                    \
+    switch (mode) {                                                 \
+        case dev::SPMV: AMGE_SELL(dev::SPMV, C16, NT); break;       \
+        case dev::SPMV_ADD: AMGE_SELL(dev::SPMV_ADD, C16, NT); break; \
+        case dev::RESID: AMGE_SELL(dev::RESID, C16, NT); break;     \
+        case dev::JAC: AMGE_SELL(dev::JAC, C16, NT); break;         \
+        default: AMGE_SELL(dev::SPLIT, C16, NT); break;             \
     }
+    if (M.c16) {
+        if (M.stream) AMGE_SELL_MODES(true, true) else AMGE_SELL_MODES(true, false)
+    } else {
+        if (M.stream) AMGE_SELL_MODES(false, true) else AMGE_SELL_MODES(false, false)
+    }
+#undef AMGE_SELL_MODES
 #undef AMGE_SELL
 }
 
@@ -878,6 +875,8 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         L.Ah = upload_tuned(H, Ah, false, s);
         L.P = upload_tuned(H, P[k], false, s);
         L.Pt = upload_tuned(H, transpose(P[k]), false, s);
+        // every operator but A_k streamed past the caches (A_k is used four times)
+        L.Ah.stream = L.P.stream = L.Pt.stream = true;
         L.D = upload_tuned(H, D[k], true, s);
         L.Dt = upload_tuned(H, Dt, true, s);
         {
@@ -898,6 +897,7 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
                 X.rowptr[i + 1] = (int32_t)X.col.size();
             }
             L.Aux = upload_tuned(H, X, false, s);
+            L.Aux.stream = true;
             if (batched) {
                 hl[k].Ah = Ah;
                 hl[k].P = P[k];
