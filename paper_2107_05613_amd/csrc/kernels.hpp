@@ -61,10 +61,11 @@ __device__ __forceinline__ T row_sum(T v) {
 
 // Column index of stored entry e of a slice: 32-bit indices, or (C16) a 16-bit offset
 // from the slice's base column.
-// Matrix streams are read once per launch.  With FP64 values (12 or 10 bytes per entry)
-// non-temporal loads, which keep them from evicting the gathered vector, are faster
-// (measured: fine-level FP64 sweep 95 -> 90 us); with FP32 values plain loads are
-// (52 vs 55 us).
+// Matrix value streams: FP64 values are read with non-temporal loads (they cannot stay
+// cache-resident and would evict what can); FP32 values of A_k and the column indices of
+// A_k are read with plain loads so that they stay in the last-level cache between the
+// uses of A_k (measured on the 64^3 H(curl) workload: FP32 sweep 52 -> 43 us, FP64
+// sweep 95 -> 84 us together with the non-temporal loads of the other operators).
 template <bool C16, bool NT>
 __device__ __forceinline__ int col_at(const int* __restrict__ ci, const uint16_t* __restrict__ c16, int cb, int e) {
     if (C16) return cb + (int)(NT ? __builtin_nontemporal_load(c16 + e) : c16[e]);
@@ -119,7 +120,7 @@ k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, 
     T acc = 0;
 #pragma unroll 4
     for (int k = 0; k < width; ++k) {
-        const int j = col_at<C16, NT || sizeof(T) == 8>(ci, c16, cb, e0 + k * 64);
+        const int j = col_at<C16, NT>(ci, c16, cb, e0 + k * 64);
         T xv;
         if (MODE == SPLIT) xv = j < nsplit ? b[j] : x[j - nsplit];
         else xv = x[j];
@@ -245,7 +246,7 @@ k_pcg_ap(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow
         double acc = 0;
 #pragma unroll 4
         for (int k = 0; k < width; ++k)
-            acc = fma(stream_load(v + k * 64), p[col_at<C16, true>(ci, c16, cb, e0 + k * 64)], acc);
+            acc = fma(stream_load(v + k * 64), p[col_at<C16, false>(ci, c16, cb, e0 + k * 64)], acc);
         acc = row_sum<K>(acc);
         if (row >= 0 && !(lane & (K - 1))) {
             q[row] = acc;
