@@ -396,7 +396,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "fine-level A_1 CSR kernels (l1-Jacobi sweeps + residuals, FP32)",
+            "kernel": "fine-level A_1 sliced-ELL kernels (l1-Jacobi sweeps + residual, FP32, 16-bit column offsets)",
             "achieved": k_gbps,
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",
