@@ -130,7 +130,7 @@ amge_status amge_pcg_solve(amge_hierarchy* h, const double* b, double* x, int32_
 
 /* Single level operations, for testing each kernel of the path on its own.  Device FP64
  * in/out vectors (one column); precision 32 runs the FP32 kernel on rounded inputs.
- *   op  AMGE_OP_A       out = A_k in                 (CSR SpMV)
+ *   op  AMGE_OP_A       out = A_k in                 (sparse product)
  *       AMGE_OP_AHAT    out = (D^T A D)_k in          (auxiliary matrix)
  *       AMGE_OP_D       out = D_k in                  (incidence)
  *       AMGE_OP_DT      out = D_k^T in

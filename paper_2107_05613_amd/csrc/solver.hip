@@ -369,11 +369,11 @@ void precondition(amge_hierarchy* H, const double* r, double* z, hipStream_t s) 
 }
 
 // ------------------------------------------------------------------ batched path
+// Several right-hand sides at once (n x NC row-major blocks, NC a power of two): every
+// level operator is one SpMM launch over the one-lane-per-row sliced ELL, whose lanes
+// own V consecutive columns of a row.  V is tuned per matrix at set-up.
 constexpr int BPCG_BLOCKS = 2048;  // blocks of the per-column dot products
 constexpr int BPCG_CHUNK = 4;      // graph replays between status polls
-// Several right-hand sides at once (n x NC row-major blocks, NC a power of two): every
-// level operator is one CSR SpMM launch whose lanes own V consecutive columns of a
-// row.  V is tuned per matrix at set-up.
 template <class T> const T* bvals(const DSellB& M);
 template <> const float* bvals<float>(const DSellB& M) { return M.v32; }
 template <> const double* bvals<double>(const DSellB& M) { return M.v64; }
