@@ -81,7 +81,16 @@ def run_cpu_baseline(workload, iters_needed, budget_s=20.0):
         return {"error": r.stderr[-500:]}
     res = json.loads(r.stdout.strip().splitlines()[-1])
     s_per_solve = res["s_per_iter"] * (iters_needed + 1)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": 1.0 / s_per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "host_cores_available": len(os.sched_getaffinity(0)), "cpu_model": model,
             "sample": (f"FP64 oracle (scipy CSR, 1 thread) PCG on the same hierarchy and rhs: "
                        f"{res['sample_iters']} iterations timed ({res['sample_s']:.1f} s), scaled to "
                        f"{iters_needed} iterations per solve (the FP64 GPU count); hierarchy build "
