@@ -90,15 +90,23 @@ k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, 
        T* __restrict__ yd, int nsplit, const int* __restrict__ stop) {
     // SPMV / SPLIT with yd != null also write yd = dinv * y: the first l1-Jacobi sweep
     // from zero on the next operator, produced where its right-hand side is produced.
-    // Every launch of the PCG iteration returns at once when *stop is set (converged).
-    if (*stop) return;
+    // Every launch of the PCG iteration returns without writing when *stop is set
+    // (converged).
     const int slice = xcd_block(blockIdx.x, gridDim.x) * WAVES + (threadIdx.x >> 6);
-    if (slice >= nslices) return;
     const int lane = threadIdx.x & 63;
-    const int base = sptr[slice];
-    const int width = (sptr[slice + 1] - base) >> 6;
-    const int row = srow[slice * (64 / K) + lane / K];
-    const int cb = C16 ? cbase[slice] : 0;
+    // The stop flag and the slice's layout words are requested together (the slice index
+    // is clamped so every address is valid; nslices >= 1 for every launch): on the small
+    // coarse levels a launch is one chain of dependent loads, and each link costs a
+    // memory latency.
+    const int sl = min(slice, nslices - 1);
+    const int stopped = *stop;
+    const int base = sptr[sl];
+    const int end = sptr[sl + 1];
+    const int row = srow[sl * (64 / K) + lane / K];
+    const int cb = C16 ? cbase[sl] : 0;
+    // (end < base, row < -1 and cb < 0 never hold: they keep the loads ahead of the branch)
+    if (stopped | (slice >= nslices) | (end < base) | (row < -1) | (cb < 0)) return;
+    const int width = (end - base) >> 6;
     const int e0 = base + lane;
     const T* v = av + e0;
     // the row's own operands of the update are requested before the product, so their
@@ -141,13 +149,18 @@ template <typename T, int K, int ADD>
 __global__ void __launch_bounds__(BLOCK)
 k_sell_inc(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const uint32_t* __restrict__ ent,
            const T* __restrict__ x, T* __restrict__ y, const int* __restrict__ stop) {
-    if (*stop) return;
     const int slice = xcd_block(blockIdx.x, gridDim.x) * WAVES + (threadIdx.x >> 6);
-    if (slice >= nslices) return;
     const int lane = threadIdx.x & 63;
-    const int base = sptr[slice];
-    const int width = (sptr[slice + 1] - base) >> 6;
-    const int row = srow[slice * (64 / K) + lane / K];
+    // flag and layout words requested together, as in k_sell
+    const int sl = min(slice, nslices - 1);
+    const int stopped = *stop;
+    const int base = sptr[sl];
+    const int end = sptr[sl + 1];
+    const int row = srow[sl * (64 / K) + lane / K];
+    if (stopped | (slice >= nslices) | (end < base) | (row < -1)) return;
+    const int width = (end - base) >> 6;
+    const bool owner = row >= 0 && !(lane & (K - 1));
+    const T yr = ADD ? y[owner ? row : 0] : T(0);   // requested before the product
     const uint32_t* e = ent + base + lane;
     T acc = 0;
 #pragma unroll 4
@@ -158,9 +171,8 @@ k_sell_inc(int nslices, const int* __restrict__ sptr, const int* __restrict__ sr
         acc += (w >> 31) ? -v : v;
     }
     acc = row_sum<K>(acc);
-    if (row < 0 || (lane & (K - 1))) return;
-    if (ADD) y[row] += acc;
-    else y[row] = acc;
+    if (!owner) return;
+    y[row] = ADD ? yr + acc : acc;
 }
 
 // y = dinv * x (one sweep from zero)
@@ -178,7 +190,7 @@ template <typename T>
 __global__ void __launch_bounds__(BLOCK)
 k_coarse(int n, const double* __restrict__ Ainv, const T* __restrict__ b, T* __restrict__ x,
          const int* __restrict__ stop) {
-    if (*stop) return;
+    const int stopped = *stop;
     const int row = blockIdx.x * WAVES + (threadIdx.x >> 6);
     if (row >= n) return;
     const int lane = threadIdx.x & 63;
@@ -186,7 +198,9 @@ k_coarse(int n, const double* __restrict__ Ainv, const T* __restrict__ b, T* __r
     double acc = 0;
     for (int j = lane; j < n; j += 64) acc = fma(a[j], (double)b[j], acc);
     acc = wave_sum(acc);
-    if (lane == 0) x[row] = (T)acc;
+    // the stop flag is tested only before the store: its load overlaps the product
+    // (a stopped launch reads the small inverse once and writes nothing)
+    if (lane == 0 && !stopped) x[row] = (T)acc;
 }
 
 // ---------------------------------------------------------------- conversions
@@ -267,9 +281,10 @@ k_pcg_xr(int n, const double* __restrict__ part_pq, const double* __restrict__ p
          const float* __restrict__ dinv32, double* __restrict__ rd64, const double* __restrict__ dinv64,
          int* __restrict__ done, int* __restrict__ flag) {
     __shared__ double sh[WAVES + 1];
-    if (*done) return;
+    const int stopped = *done;   // tested after the reductions, whose loads it overlaps
     const double pq = sum_partials(part_pq, sh);
     const double delta = sum_partials(part_delta, sh);
+    if (stopped) return;
     if (!(pq > 0) || !isfinite(pq)) {      // breakdown: recorded, iterate no further
         if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
         return;
@@ -322,7 +337,7 @@ k_pcg_p(int n, const double* __restrict__ part_new, const double* __restrict__ p
         const double* __restrict__ z, double* __restrict__ p, PcgStatus* __restrict__ st,
         int* __restrict__ done, const int* __restrict__ flag) {
     __shared__ double sh[WAVES + 1];
-    if (*done) return;
+    const int stopped = *done;   // tested after the reductions, whose loads it overlaps
     // iteration count and stopping parameters: st->iters changes only in k_pcg_finish
     const int it = st->iters, maxit = st->maxit, stop_l2 = st->stop_l2;
     const double rtol = st->rtol;
@@ -330,6 +345,7 @@ k_pcg_p(int n, const double* __restrict__ part_new, const double* __restrict__ p
     const double rzold = sum_partials(part_new + NRED, sh);
     const double rr = sum_partials(part_new + 2 * NRED, sh);
     const double dold = sum_partials(part_old, sh);
+    if (stopped) return;
     const double rel = stop_l2 ? sqrt(rr) / st->bnorm : sqrt(fmax(dnew, 0.0) / st->delta0);
     const bool stop = (*flag != 0) || (rtol > 0 && rel <= rtol) || (it + 1 >= maxit) || !isfinite(dnew);
     if (!stop) {

@@ -66,17 +66,21 @@ k_sell_mm(int nslices, int L, int NC, const int* __restrict__ sptr, const int* _
           const int* __restrict__ ci, const uint16_t* __restrict__ c16, const int* __restrict__ cbase,
           const T* __restrict__ av, const T* __restrict__ X, const T* __restrict__ B, const T* __restrict__ dinv,
           T* __restrict__ Y, T* __restrict__ YD, int nsplit, const int* __restrict__ stop) {
-    if (*stop) return;   // every column of the batch has converged
     const int gw = xcd_block(blockIdx.x, gridDim.x) * WAVES + ((int)threadIdx.x >> 6);
     const int slice = gw / L;
-    if (slice >= nslices) return;
     const int lane = threadIdx.x & 63;
     const int rr = (gw % L) * (64 / L) + lane / L;
     const int col = (lane % L) * V;
-    const int base = sptr[slice];
-    const int width = (sptr[slice + 1] - base) >> 6;
-    const int row = srow[slice * 64 + rr];
-    const int cb = C16 ? cbase[slice] : 0;
+    // stop flag (every column of the batch has converged) and layout words requested
+    // together, from a clamped (valid) slice index, as in k_sell
+    const int sl = min(slice, nslices - 1);
+    const int stopped = *stop;
+    const int base = sptr[sl];
+    const int end = sptr[sl + 1];
+    const int row = srow[sl * 64 + rr];
+    const int cb = C16 ? cbase[sl] : 0;
+    if (stopped | (slice >= nslices) | (end < base) | (row < -1) | (cb < 0)) return;   // last three never hold
+    const int width = (end - base) >> 6;
     Pack<T, V> acc;
 #pragma unroll
     for (int i = 0; i < V; ++i) acc.v[i] = 0;
@@ -135,17 +139,18 @@ __global__ void __launch_bounds__(BLOCK)
 k_sell_inc_mm_add(int nslices, int L, int NC, const int* __restrict__ sptr, const int* __restrict__ srow,
                   const uint32_t* __restrict__ ent, const T* __restrict__ X, T* __restrict__ Y,
                   const int* __restrict__ stop) {
-    if (*stop) return;
     const int gw = xcd_block(blockIdx.x, gridDim.x) * WAVES + ((int)threadIdx.x >> 6);
     const int slice = gw / L;
-    if (slice >= nslices) return;
     const int lane = threadIdx.x & 63;
     const int rr = (gw % L) * (64 / L) + lane / L;
     const int col = (lane % L) * V;
-    const int base = sptr[slice];
-    const int width = (sptr[slice + 1] - base) >> 6;
-    const int row = srow[slice * 64 + rr];
-    if (row < 0) return;
+    const int sl = min(slice, nslices - 1);
+    const int stopped = *stop;
+    const int base = sptr[sl];
+    const int end = sptr[sl + 1];
+    const int row = srow[sl * 64 + rr];
+    if (stopped | (slice >= nslices) | (end < base) | (row < 0)) return;
+    const int width = (end - base) >> 6;
     Pack<T, V> acc;
     acc.load(Y + (int64_t)row * NC + col);
     for (int k = 0; k < width; ++k) {
@@ -166,7 +171,7 @@ template <typename T>
 __global__ void __launch_bounds__(BLOCK)
 k_coarse_mm(int n, int lgW, int lg, const double* __restrict__ Ainv, const T* __restrict__ B, T* __restrict__ X,
             const int* __restrict__ stop) {
-    if (*stop) return;
+    const int stopped = *stop;   // tested before the store: its load overlaps the product
     const int NC = 1 << lg;
     const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     if (t >= ((int64_t)n << lgW)) return;
@@ -174,7 +179,7 @@ k_coarse_mm(int n, int lgW, int lg, const double* __restrict__ Ainv, const T* __
     const double* a = Ainv + (int64_t)row * n;
     double acc = 0;
     for (int j = 0; j < n; ++j) acc = fma(a[j], (double)B[(int64_t)j * NC + c], acc);
-    X[(int64_t)row * NC + c] = (T)acc;
+    if (!stopped) X[(int64_t)row * NC + c] = (T)acc;
 }
 
 // ---------------------------------------------------------------- batched PCG
