@@ -114,8 +114,15 @@ struct amge_hierarchy {
     int* zero_flag = nullptr;    // a device 0: the stop flag of launches outside PCG iterations
     hipStream_t gstream = nullptr;   // the hierarchy's stream for graph capture / replay
     hipGraphExec_t gexec[7] = {};    // one captured batched PCG iteration per active width 2^i
-    hipGraphExec_t pexec = nullptr;  // two captured single-column PCG iterations
+    hipGraphExec_t pexec[2] = {};    // one captured single-column PCG iteration per buffer parity
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // single-column PCG: host ring of iteration records (pinned, written by the device)
+    // and one event per queued iteration
+    static constexpr int NPEV = 8;
+    amge::dev::PcgRecord* ring = nullptr;     // host address
+    amge::dev::PcgRecord* ring_dev = nullptr; // its device address
+    uint32_t epoch = 0;
+    hipEvent_t pev[NPEV] = {};
     std::vector<void*> allocs;
     size_t bytes = 0;
     amge::Probe probe;
@@ -123,7 +130,11 @@ struct amge_hierarchy {
         if (gstream) (void)hipStreamSynchronize(gstream);
         for (hipGraphExec_t g : gexec)
             if (g) (void)hipGraphExecDestroy(g);
-        if (pexec) (void)hipGraphExecDestroy(pexec);
+        for (hipGraphExec_t g : pexec)
+            if (g) (void)hipGraphExecDestroy(g);
+        for (hipEvent_t e : pev)
+            if (e) (void)hipEventDestroy(e);
+        if (ring) (void)hipHostFree(ring);
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (gstream) (void)hipStreamDestroy(gstream);

@@ -303,20 +303,20 @@ k_pcg_xr(int n, const double* __restrict__ part_pq, const double* __restrict__ p
     }
 }
 
-// z = (double) z32 (if z32 != null); partials of r.z, r.zold, r.r.
+// Partials of r.z, r.zold, r.r.  z and zold are in the preconditioner's precision TZ
+// (an FP32 V-cycle output is used as it is: widening it to FP64 is exact).
+template <typename TZ>
 __global__ void __launch_bounds__(BLOCK)
-k_pcg_dots(int n, const float* __restrict__ z32, double* __restrict__ z, const double* __restrict__ zold,
-           const double* __restrict__ r, double* __restrict__ part, const int* __restrict__ done) {
+k_pcg_dots(int n, const TZ* __restrict__ z, const TZ* __restrict__ zold, const double* __restrict__ r,
+           double* __restrict__ part, const int* __restrict__ done) {
     __shared__ double sh[WAVES + 1];
     if (*done) return;
     double a = 0, bsum = 0, c = 0;
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
-        double zi;
-        if (z32) { zi = (double)z32[i]; z[i] = zi; }
-        else zi = z[i];
+        const double zi = (double)z[i];
         const double ri = r[i];
         a = fma(ri, zi, a);
-        if (zold) bsum = fma(ri, zold[i], bsum);
+        if (zold) bsum = fma(ri, (double)zold[i], bsum);
         c = fma(ri, ri, c);
     }
     a = block_sum(a, sh);
@@ -332,9 +332,10 @@ k_pcg_dots(int n, const float* __restrict__ z32, double* __restrict__ z, const d
 // Status written by the last kernel of every iteration (read by the host).
 
 // beta = (r.z - r.zold) / delta_old; p = z + beta p; stopping test.
+template <typename TZ>
 __global__ void __launch_bounds__(BLOCK)
 k_pcg_p(int n, const double* __restrict__ part_new, const double* __restrict__ part_old,
-        const double* __restrict__ z, double* __restrict__ p, PcgStatus* __restrict__ st,
+        const TZ* __restrict__ z, double* __restrict__ p, PcgStatus* __restrict__ st,
         int* __restrict__ done, const int* __restrict__ flag) {
     __shared__ double sh[WAVES + 1];
     const int stopped = *done;   // tested after the reductions, whose loads it overlaps
@@ -350,7 +351,8 @@ k_pcg_p(int n, const double* __restrict__ part_new, const double* __restrict__ p
     const bool stop = (*flag != 0) || (rtol > 0 && rel <= rtol) || (it + 1 >= maxit) || !isfinite(dnew);
     if (!stop) {
         const double beta = (dnew - rzold) / dold;
-        for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) p[i] = fma(beta, p[i], z[i]);
+        for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK)
+            p[i] = fma(beta, p[i], (double)z[i]);
     }
     // every block has finished reading `done` at entry; only one block publishes
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -362,8 +364,10 @@ k_pcg_p(int n, const double* __restrict__ part_new, const double* __restrict__ p
 }
 
 // Counts the iteration and marks the loop finished (separate launch, so no block of
-// k_pcg_p can observe the changes mid-kernel).
-__global__ void k_pcg_finish(PcgStatus* __restrict__ st, int* __restrict__ done) {
+// k_pcg_p can observe the changes mid-kernel), then publishes the status to the host
+// ring: the record first, the tag after a system-scope fence, so a host that sees the
+// tag of iteration k reads the status of iteration k.
+__global__ void k_pcg_finish(PcgStatus* __restrict__ st, int* __restrict__ done, PcgRecord* __restrict__ ring) {
     if (*done) return;
     st->iters += 1;
     const bool stop = st->breakdown || (st->rtol > 0 && st->relres <= st->rtol) || (st->iters >= st->maxit) ||
@@ -372,12 +376,16 @@ __global__ void k_pcg_finish(PcgStatus* __restrict__ st, int* __restrict__ done)
         *done = 1;
         st->done = 1;
     }
+    PcgRecord* rec = ring + st->iters % PCG_RING;
+    rec->st = *st;
+    __threadfence_system();
+    rec->tag = ((uint64_t)st->epoch << 32) | (uint32_t)st->iters;
 }
 
 // Initial quantities: delta0 = r.z, bnorm = ||b||, from the dots partials; stopping
 // parameters of the solve.
 __global__ void k_pcg_init(const double* __restrict__ part, PcgStatus* __restrict__ st, double rtol, int maxit,
-                           int stop_l2) {
+                           int stop_l2, uint32_t epoch) {
     __shared__ double sh[WAVES + 1];
     const double d = sum_partials(part, sh);
     const double rr = sum_partials(part + 2 * NRED, sh);
@@ -393,6 +401,7 @@ __global__ void k_pcg_init(const double* __restrict__ part, PcgStatus* __restric
         st->rtol = rtol;
         st->maxit = maxit;
         st->stop_l2 = stop_l2;
+        st->epoch = epoch;
     }
 }
 

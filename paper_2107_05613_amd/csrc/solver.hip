@@ -6,7 +6,9 @@
 // operation of the path runs in the kernels of kernels.hpp.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
+#include <cstring>
 #include <cstdlib>
 #include <memory>
 #include <map>
@@ -846,6 +848,11 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     HIPCHECK(hipStreamCreateWithFlags(&H->gstream, hipStreamNonBlocking));
     HIPCHECK(hipEventCreateWithFlags(&H->ev_in, hipEventDisableTiming));
     HIPCHECK(hipEventCreateWithFlags(&H->ev_out, hipEventDisableTiming));
+    for (hipEvent_t& e : H->pev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHECK(hipHostMalloc((void**)&H->ring, sizeof(dev::PcgRecord) * dev::PCG_RING,
+                           hipHostMallocMapped | hipHostMallocCoherent));
+    memset((void*)H->ring, 0, sizeof(dev::PcgRecord) * dev::PCG_RING);
+    HIPCHECK(hipHostGetDevicePointer((void**)&H->ring_dev, H->ring, 0));
     const bool batched = H->opts.max_rhs > 1;
     std::vector<HostLevel> hl(batched ? nl : 0);
     for (int k = 0; k < nl; ++k) {
@@ -966,7 +973,6 @@ void pcg_iteration(amge_hierarchy* H, int par, hipStream_t s) {
     DLevel& L1 = H->lv[0];
     float* r32 = f32 && multilevel ? L1.w32.b : nullptr;
     float* rd32 = f32 && multilevel ? L1.w32.bd : nullptr;
-    float* z32 = f32 && multilevel ? L1.w32.x : nullptr;
     double* rd64 = !f32 && multilevel ? L1.w64.bd : nullptr;
     const int* done = H->flags;
     double* znew = H->z[par];
@@ -977,29 +983,58 @@ void pcg_iteration(amge_hierarchy* H, int par, hipStream_t s) {
     dev::k_pcg_xr<<<dev::NRED, BLOCK, 0, s>>>(n, H->part_pq, dold, H->p, H->q, H->x, H->r, r32, rd32,
                                               f32 ? L1.w32.dinv : nullptr, rd64, f32 ? nullptr : L1.w64.dinv,
                                               H->flags, H->flags + 1);
-    if (!multilevel) coarse_solve<double>(H, H->r, znew, s, done);
-    else if (f32) vcycle_level<float>(H, 0, r32, rd32, z32, s, done);
-    else vcycle_level<double>(H, 0, H->r, rd64, znew, s, done);
-    dev::k_pcg_dots<<<dev::NRED, BLOCK, 0, s>>>(n, z32, znew, zold, H->r, dnew, H->flags);
-    dev::k_pcg_p<<<dev::NRED, BLOCK, 0, s>>>(n, dnew, dold, znew, H->p, H->st, H->flags, H->flags + 1);
-    dev::k_pcg_finish<<<1, 1, 0, s>>>(H->st, H->flags);
+    if (f32 && multilevel) {
+        // FP32 V-cycle: z stays FP32, in the first half of the z buffer of its parity
+        float* z32 = reinterpret_cast<float*>(znew);
+        vcycle_level<float>(H, 0, r32, rd32, z32, s, done);
+        dev::k_pcg_dots<float><<<dev::NRED, BLOCK, 0, s>>>(n, z32, reinterpret_cast<const float*>(zold), H->r, dnew,
+                                                           H->flags);
+        dev::k_pcg_p<float><<<dev::NRED, BLOCK, 0, s>>>(n, dnew, dold, z32, H->p, H->st, H->flags, H->flags + 1);
+    } else {
+        if (!multilevel) coarse_solve<double>(H, H->r, znew, s, done);
+        else vcycle_level<double>(H, 0, H->r, rd64, znew, s, done);
+        dev::k_pcg_dots<double><<<dev::NRED, BLOCK, 0, s>>>(n, znew, zold, H->r, dnew, H->flags);
+        dev::k_pcg_p<double><<<dev::NRED, BLOCK, 0, s>>>(n, dnew, dold, znew, H->p, H->st, H->flags, H->flags + 1);
+    }
+    dev::k_pcg_finish<<<1, 1, 0, s>>>(H->st, H->flags, H->ring_dev);
 }
 
-// Two iterations (both parities) captured once as a HIP graph on the hierarchy's stream.
-void capture_pcg_pair(amge_hierarchy* H) {
-    if (H->pexec) return;
-    hipGraph_t graph = nullptr;
-    HIPCHECK(hipStreamBeginCapture(H->gstream, hipStreamCaptureModeThreadLocal));
-    pcg_iteration(H, 0, H->gstream);
-    pcg_iteration(H, 1, H->gstream);
-    hipError_t e = hipStreamEndCapture(H->gstream, &graph);
-    if (e != hipSuccess || !graph) fail(AMGE_ERR_HIP, "graph capture of the PCG iterations failed");
-    e = hipGraphInstantiate(&H->pexec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) {
-        H->pexec = nullptr;
-        fail(AMGE_ERR_HIP, "graph instantiation failed");
+// One iteration of each buffer parity captured once as a HIP graph on the hierarchy's
+// stream.
+void capture_pcg(amge_hierarchy* H) {
+    for (int par = 0; par < 2; ++par) {
+        if (H->pexec[par]) continue;
+        hipGraph_t graph = nullptr;
+        HIPCHECK(hipStreamBeginCapture(H->gstream, hipStreamCaptureModeThreadLocal));
+        pcg_iteration(H, par, H->gstream);
+        hipError_t e = hipStreamEndCapture(H->gstream, &graph);
+        if (e != hipSuccess || !graph) fail(AMGE_ERR_HIP, "graph capture of the PCG iteration failed");
+        e = hipGraphInstantiate(&H->pexec[par], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            H->pexec[par] = nullptr;
+            fail(AMGE_ERR_HIP, "graph instantiation failed");
+        }
     }
+}
+
+// Iterations the host may queue beyond the last one it has seen.  Iterations run after
+// convergence do nothing but still cost their launches (~0.2 ms for a five-level
+// hierarchy), and an empty queue costs a host round trip (~40 us), so the queue is kept
+// at most as long as the iterations still needed, predicted from the mean contraction
+// of the stopping quantity over the last (up to) four iterations.  rel[k] is that
+// quantity after iteration k (rel[0] = 1).
+int pcg_lookahead(const std::vector<double>& rel, double rtol) {
+    constexpr int MAXQ = 4;
+    if (rtol <= 0) return MAXQ;   // a fixed number of iterations
+    const int k = (int)rel.size() - 1;
+    if (k == 0) return 2;
+    const int m = std::min(k, 4);
+    const double cur = rel[k], prev = rel[k - m];
+    if (!(cur > 0) || !(prev > cur) || !std::isfinite(prev)) return 2;   // no contraction seen
+    const double need = std::log(rtol / cur) / (std::log(cur / prev) / m);
+    if (!(need >= 1)) return 1;
+    return (int)std::min<double>(MAXQ, std::floor(need));
 }
 
 amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int maxit, int stop_l2,
@@ -1012,7 +1047,7 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
     const bool timed = L1.probe && L1.probe->on;   // probed launches are recorded eagerly
     hipStream_t gs = timed ? s : H->gstream;
     if (!timed) {
-        capture_pcg_pair(H);
+        capture_pcg(H);
         HIPCHECK(hipEventRecord(H->ev_in, s));
         HIPCHECK(hipStreamWaitEvent(gs, H->ev_in, 0));
     }
@@ -1024,13 +1059,20 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
         scale<float>(n, L1.w32.dinv, L1.w32.b, L1.w32.bd, gs);
     }
     if (!f32 && multilevel) scale<double>(n, L1.w64.dinv, H->r, L1.w64.bd, gs);
-    // z_0 = B r_0 into z[1] (the "old" z of the first iteration), delta_0 = r_0 . z_0
-    float* z32 = f32 && multilevel ? L1.w32.x : nullptr;
-    if (!multilevel) coarse_solve<double>(H, H->r, H->z[1], gs, H->zero_flag);
-    else if (f32) vcycle_level<float>(H, 0, L1.w32.b, L1.w32.bd, z32, gs, H->zero_flag);
-    else vcycle_level<double>(H, 0, H->r, L1.w64.bd, H->z[1], gs, H->zero_flag);
-    dev::k_pcg_dots<<<dev::NRED, BLOCK, 0, gs>>>(n, z32, H->z[1], nullptr, H->r, H->part_dots[1], H->zero_flag);
-    dev::k_pcg_init<<<1, BLOCK, 0, gs>>>(H->part_dots[1], H->st, rtol, maxit, stop_l2);
+    // z_0 = B r_0 into z[1] (the "old" z of the first iteration; FP32 in its first half
+    // for an FP32 V-cycle), delta_0 = r_0 . z_0
+    float* z32 = f32 && multilevel ? reinterpret_cast<float*>(H->z[1]) : nullptr;
+    if (z32) {
+        vcycle_level<float>(H, 0, L1.w32.b, L1.w32.bd, z32, gs, H->zero_flag);
+        dev::k_pcg_dots<float><<<dev::NRED, BLOCK, 0, gs>>>(n, z32, nullptr, H->r, H->part_dots[1], H->zero_flag);
+    } else {
+        if (!multilevel) coarse_solve<double>(H, H->r, H->z[1], gs, H->zero_flag);
+        else vcycle_level<double>(H, 0, H->r, L1.w64.bd, H->z[1], gs, H->zero_flag);
+        dev::k_pcg_dots<double><<<dev::NRED, BLOCK, 0, gs>>>(n, H->z[1], nullptr, H->r, H->part_dots[1],
+                                                             H->zero_flag);
+    }
+    const uint32_t epoch = ++H->epoch == 0 ? ++H->epoch : H->epoch;   // never 0 (the ring's initial tags)
+    dev::k_pcg_init<<<1, BLOCK, 0, gs>>>(H->part_dots[1], H->st, rtol, maxit, stop_l2, epoch);
     dev::PcgStatus hs;
     HIPCHECK(hipMemcpyAsync(&hs, H->st, sizeof(hs), hipMemcpyDeviceToHost, gs));
     HIPCHECK(hipStreamSynchronize(gs));
@@ -1055,20 +1097,37 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
         finish();
         fail(AMGE_ERR_BREAKDOWN, "preconditioner not positive on the right-hand side");
     }
-    copy_vec<double>(n, H->z[1], H->p, gs, H->zero_flag);
-    // pairs of iterations (graph replays, or direct launches when timing is on), then a
-    // look at the status; iterations past convergence do nothing
-    for (int launched = 0; !hs.done; launched += 2) {
-        if (launched > maxit + 2) fail(AMGE_ERR_HIP, "PCG did not terminate");
-        if (timed) {
-            pcg_iteration(H, 0, gs);
-            pcg_iteration(H, 1, gs);
-        } else {
-            HIPCHECK(hipGraphLaunch(H->pexec, gs));
+    if (z32) convert<float, double>(n, z32, H->p, gs);
+    else copy_vec<double>(n, H->z[1], H->p, gs, H->zero_flag);
+    // Iterations are queued ahead (graph replays, or direct launches when timing is on)
+    // while the host follows the records they leave in the pinned ring: iteration k's
+    // record is read once the event queued after it has completed.  Iterations queued
+    // past convergence do nothing; the queue length comes from pcg_lookahead.
+    std::vector<double> rel(1, 1.0);
+    int launched = 0, seen = 0;
+    while (!hs.done) {
+        // timed runs keep the pairs of direct launches of the event-timed path: the host
+        // enqueues a pair, then waits for it, so the GPU never waits on the enqueue
+        // inside a timed launch
+        int upto = launched;
+        if (!timed) upto = std::min(maxit, seen + pcg_lookahead(rel, rtol));
+        else if (launched == seen) upto = std::min(maxit, seen + 2);
+        for (; launched < upto; ++launched) {
+            if (timed) pcg_iteration(H, launched & 1, gs);
+            else HIPCHECK(hipGraphLaunch(H->pexec[launched & 1], gs));
+            HIPCHECK(hipEventRecord(H->pev[launched % amge_hierarchy::NPEV], gs));
         }
-        HIPCHECK(hipMemcpyAsync(&hs, H->st, sizeof(hs), hipMemcpyDeviceToHost, gs));
-        HIPCHECK(hipStreamSynchronize(gs));
+        if (launched == seen) fail(AMGE_ERR_HIP, "PCG did not terminate");
+        HIPCHECK(hipEventSynchronize(H->pev[seen % amge_hierarchy::NPEV]));
+        ++seen;
+        const volatile dev::PcgRecord* rec = H->ring + seen % dev::PCG_RING;
+        if (rec->tag != (((uint64_t)epoch << 32) | (uint32_t)seen))
+            fail(AMGE_ERR_HIP, "PCG iteration record missing");
+        std::atomic_thread_fence(std::memory_order_acquire);
+        memcpy(&hs, (const void*)&rec->st, sizeof(hs));
+        rel.push_back(hs.relres);
     }
+    if (verbose()) fprintf(stderr, "[amge pcg] %d iterations, %d queued\n", hs.iters, launched);
     copy_vec<double>(n, H->x, x, gs, H->zero_flag);
     HIPCHECK(hipGetLastError());
     finish();

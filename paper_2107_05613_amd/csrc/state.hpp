@@ -10,7 +10,17 @@ namespace dev {
 struct PcgStatus {
     double delta0, delta, rr, relres, bnorm;
     double rtol;     // stopping tolerance (<= 0: exactly maxit iterations)
-    int iters, done, breakdown, maxit, stop_l2, pad;
+    int iters, done, breakdown, maxit, stop_l2;
+    uint32_t epoch;  // number of the solve, tags the host records of its iterations
+};
+
+// Host-visible record of one finished single-column PCG iteration, kept in a ring of
+// pinned host memory indexed by the iteration number: the status after the iteration,
+// then (after a system-scope fence) tag = epoch << 32 | iteration.
+constexpr int PCG_RING = 64;
+struct alignas(128) PcgRecord {
+    PcgStatus st;
+    uint64_t tag;
 };
 
 // Per-column state of the batched PCG (written only by the single-block finalize
