@@ -32,6 +32,7 @@ struct DSell {
     uint32_t* ent = nullptr;  // incidence matrices: column | sign << 31, padding 0xffffffff
     double* v64 = nullptr;
     float* v32 = nullptr;
+    uint16_t* lead = nullptr; // split rows: leading entries per slot that read the first operand
     bool stream = false;      // FP32 matrix streams read with non-temporal loads
 };
 
@@ -67,6 +68,7 @@ struct DSellB {
     uint32_t* ent = nullptr;   // incidence matrices: column | sign << 31, padding 0xffffffff
     double* v64 = nullptr;
     float* v32 = nullptr;
+    uint16_t* lead = nullptr;  // split rows, as in DSell
     int V = 1;                 // columns per lane, tuned
 };
 

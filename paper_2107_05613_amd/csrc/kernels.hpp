@@ -30,7 +30,7 @@ enum Mode : int {
     SPMV_ADD = 1,  // y += A x
     RESID = 2,     // y = b - A x
     JAC = 3,       // y = x + dinv * (b - A x)
-    SPLIT = 5,     // y = A [b; x]: columns < nsplit read b, the others x (column - nsplit)
+    SPLIT = 5,     // y = A [b; x]: the first lead entries of a row read b, the others x
 };
 
 // Blocks are dispatched round-robin over the XCDs; give XCD k a contiguous range.
@@ -87,7 +87,7 @@ __global__ void __launch_bounds__(BLOCK)
 k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const int* __restrict__ ci,
        const uint16_t* __restrict__ c16, const int* __restrict__ cbase, const T* __restrict__ av,
        const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv, T* __restrict__ y,
-       T* __restrict__ yd, int nsplit, const int* __restrict__ stop) {
+       T* __restrict__ yd, const uint16_t* __restrict__ lead, const int* __restrict__ stop) {
     // SPMV / SPLIT with yd != null also write yd = dinv * y: the first l1-Jacobi sweep
     // from zero on the next operator, produced where its right-hand side is produced.
     // Every launch of the PCG iteration returns without writing when *stop is set
@@ -104,6 +104,7 @@ k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, 
     const int end = sptr[sl + 1];
     const int row = srow[sl * (64 / K) + lane / K];
     const int cb = C16 ? cbase[sl] : 0;
+    const int nlead = MODE == SPLIT ? lead[sl * (64 / K) + lane / K] : 0;
     // (end < base, row < -1 and cb < 0 never hold: they keep the loads ahead of the branch)
     if (stopped | (slice >= nslices) | (end < base) | (row < -1) | (cb < 0)) return;
     const int width = (end - base) >> 6;
@@ -130,7 +131,7 @@ k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, 
     for (int k = 0; k < width; ++k) {
         const int j = col_at<C16, NT>(ci, c16, cb, e0 + k * 64);
         T xv;
-        if (MODE == SPLIT) xv = j < nsplit ? b[j] : x[j - nsplit];
+        if (MODE == SPLIT) xv = (k * K + (lane & (K - 1)) < nlead ? b : x)[j];   // entry k*K + lane%K
         else xv = x[j];
         acc = fma(stream_load<T, NT || sizeof(T) == 8>(v + k * 64), xv, acc);
     }

@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(BLOCK)
 k_sell_mm(int nslices, int L, int NC, const int* __restrict__ sptr, const int* __restrict__ srow,
           const int* __restrict__ ci, const uint16_t* __restrict__ c16, const int* __restrict__ cbase,
           const T* __restrict__ av, const T* __restrict__ X, const T* __restrict__ B, const T* __restrict__ dinv,
-          T* __restrict__ Y, T* __restrict__ YD, int nsplit, const int* __restrict__ stop) {
+          T* __restrict__ Y, T* __restrict__ YD, const uint16_t* __restrict__ lead, const int* __restrict__ stop) {
     const int gw = xcd_block(blockIdx.x, gridDim.x) * WAVES + ((int)threadIdx.x >> 6);
     const int slice = gw / L;
     const int lane = threadIdx.x & 63;
@@ -79,6 +79,7 @@ k_sell_mm(int nslices, int L, int NC, const int* __restrict__ sptr, const int* _
     const int end = sptr[sl + 1];
     const int row = srow[sl * 64 + rr];
     const int cb = C16 ? cbase[sl] : 0;
+    const int nlead = MODE == SPLIT ? lead[sl * 64 + rr] : 0;
     if (stopped | (slice >= nslices) | (end < base) | (row < -1) | (cb < 0)) return;   // last three never hold
     const int width = (end - base) >> 6;
     Pack<T, V> acc;
@@ -91,8 +92,7 @@ k_sell_mm(int nslices, int L, int NC, const int* __restrict__ sptr, const int* _
         const T a = av[e];
         Pack<T, V> xv;
         if (MODE == SPLIT) {
-            if (j < nsplit) xv.load(B + (int64_t)j * NC + col);
-            else xv.load(X + (int64_t)(j - nsplit) * NC + col);
+            xv.load((k < nlead ? B : X) + (int64_t)j * NC + col);
         } else {
             xv.load(X + (int64_t)j * NC + col);
         }

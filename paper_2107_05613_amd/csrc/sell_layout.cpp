@@ -18,7 +18,7 @@ bool compact_indices() {
     return v == 1;
 }
 
-HostSell make_sell(const Csr& A, bool incidence, int K) {
+HostSell make_sell(const Csr& A, bool incidence, int K, const std::vector<int>* lead) {
     const int R = 64 / K;
     HostSell h;
     h.K = K;
@@ -44,6 +44,17 @@ HostSell make_sell(const Csr& A, bool incidence, int K) {
         int64_t width = (mx + K - 1) / K;
         if ((int64_t)h.sptr[sl] + width * 64 > INT32_MAX) fail(AMGE_ERR_SHAPE, "matrix too large for int32 offsets");
         h.sptr[sl + 1] = h.sptr[sl] + (int)(width * 64);
+    }
+    if (lead) {
+        if ((int)lead->size() != A.nrows) fail(AMGE_ERR_SHAPE, "split counts: one per row needed");
+        h.lead.assign(h.srow.size(), 0);
+        for (size_t i = 0; i < h.srow.size(); ++i) {
+            const int r = h.srow[i];
+            if (r < 0) continue;
+            const int c = (*lead)[r];
+            if (c < 0 || c > len(r) || c > 65535) fail(AMGE_ERR_SHAPE, "split count out of range");
+            h.lead[i] = (uint16_t)c;
+        }
     }
     const size_t stored = h.sptr[h.nslices];
     if (incidence) h.ent.assign(stored, 0xffffffffu);

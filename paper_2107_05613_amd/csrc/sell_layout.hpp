@@ -21,11 +21,16 @@ struct HostSell {
     bool compact = false;
     std::vector<int> cbase;
     std::vector<uint16_t> c16;
+    // split rows (lead != null): per slot, how many leading entries of its row read the
+    // first operand (the others read the second one)
+    std::vector<uint16_t> lead;
 };
 
 // Sliced ELL of A with K lanes per row (K | 64).  incidence: entries must be +-1 and are
-// stored index-only with the sign in bit 31.
-HostSell make_sell(const Csr& A, bool incidence, int K);
+// stored index-only with the sign in bit 31.  lead (optional, one count per row): the
+// first lead[r] entries of row r act on a first operand and the rest on a second one
+// of the same length (both index the same column range, A.ncols).
+HostSell make_sell(const Csr& A, bool incidence, int K, const std::vector<int>* lead = nullptr);
 
 // Whether compact (16-bit) column offsets may be used: on unless AMGE_INDEX32 is set.
 bool compact_indices();

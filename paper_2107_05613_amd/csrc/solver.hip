@@ -35,8 +35,9 @@ T* upload(amge_hierarchy* H, const T* src, size_t n, hipStream_t s) {
     return d;
 }
 
-DSell upload_sell(amge_hierarchy* H, const Csr& A, bool incidence, int K, hipStream_t s) {
-    HostSell h = make_sell(A, incidence, K);
+DSell upload_sell(amge_hierarchy* H, const Csr& A, bool incidence, int K, hipStream_t s,
+                  const std::vector<int>* lead = nullptr) {
+    HostSell h = make_sell(A, incidence, K, lead);
     DSell d;
     d.nrows = A.nrows;
     d.ncols = A.ncols;
@@ -58,6 +59,7 @@ DSell upload_sell(amge_hierarchy* H, const Csr& A, bool incidence, int K, hipStr
         d.v64 = upload(H, h.val.data(), h.val.size(), s);
         std::vector<float> v32(h.val.begin(), h.val.end());   // round to nearest
         d.v32 = upload(H, v32.data(), v32.size(), s);
+        if (lead) d.lead = upload(H, h.lead.data(), h.lead.size(), s);
     }
     HIPCHECK(hipStreamSynchronize(s));
     return d;
@@ -73,13 +75,13 @@ template <> const double* vals<double>(const DSell& M) { return M.v64; }
 
 template <class T, int K>
 void sell_k(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* y, T* yd, hipStream_t s,
-            int nsplit, const int* stop) {
+            const int* stop) {
     unsigned g = grid_slices(M.nslices);
     if (g == 0) return;
     const T* v = vals<T>(M);
 #define AMGE_SELL(MODE, C16, NT)                                                                          \
     dev::k_sell<T, K, MODE, C16, NT><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ci, M.c16, M.cbase, v, x, \
-                                                         b, dinv, y, yd, nsplit, stop)
+                                                         b, dinv, y, yd, M.lead, stop)
 #define AMGE_SELL_MODES(C16, NT)                                    \
     switch (mode) {                                                 \
         case dev::SPMV: AMGE_SELL(dev::SPMV, C16, NT); break;       \
@@ -97,19 +99,21 @@ void sell_k(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* 
 #undef AMGE_SELL
 }
 
-// mode as in dev::Mode; yd (SPMV, SPLIT) receives dinv * y when non-null.  stop: device
-// flag, the launch does nothing while it is set (PCG iterations after convergence).
+// mode as in dev::Mode (SPLIT needs a matrix with split rows); yd (SPMV, SPLIT) receives
+// dinv * y when non-null.  stop: device flag, the launch does nothing while it is set
+// (PCG iterations after convergence).
 template <class T>
 void sell(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s, const int* stop,
-          int nsplit = 0, T* yd = nullptr) {
+          T* yd = nullptr) {
+    if (mode == dev::SPLIT && !M.lead) fail(AMGE_ERR_ARG, "split product on a matrix without split rows");
     switch (M.K) {
-        case 1: sell_k<T, 1>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
-        case 2: sell_k<T, 2>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
-        case 4: sell_k<T, 4>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
-        case 8: sell_k<T, 8>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
-        case 16: sell_k<T, 16>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
-        case 32: sell_k<T, 32>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
-        default: sell_k<T, 64>(M, mode, x, b, dinv, y, yd, s, nsplit, stop); break;
+        case 1: sell_k<T, 1>(M, mode, x, b, dinv, y, yd, s, stop); break;
+        case 2: sell_k<T, 2>(M, mode, x, b, dinv, y, yd, s, stop); break;
+        case 4: sell_k<T, 4>(M, mode, x, b, dinv, y, yd, s, stop); break;
+        case 8: sell_k<T, 8>(M, mode, x, b, dinv, y, yd, s, stop); break;
+        case 16: sell_k<T, 16>(M, mode, x, b, dinv, y, yd, s, stop); break;
+        case 32: sell_k<T, 32>(M, mode, x, b, dinv, y, yd, s, stop); break;
+        default: sell_k<T, 64>(M, mode, x, b, dinv, y, yd, s, stop); break;
     }
 }
 
@@ -221,8 +225,9 @@ int tune_lanes(const Csr& A, bool incidence, hipStream_t s) {
     return best;
 }
 
-DSell upload_tuned(amge_hierarchy* H, const Csr& A, bool incidence, hipStream_t s) {
-    return upload_sell(H, A, incidence, tune_lanes(A, incidence, s), s);
+DSell upload_tuned(amge_hierarchy* H, const Csr& A, bool incidence, hipStream_t s,
+                   const std::vector<int>* lead = nullptr) {
+    return upload_sell(H, A, incidence, tune_lanes(A, incidence, s), s, lead);
 }
 
 // Launch of an A_k kernel; on a probed level the launch is bracketed by events and its
@@ -310,7 +315,7 @@ template <class T>
 void auxiliary(DLevel& L, const T* b, T* x, int nu, hipStream_t s, const int* stop) {
     if (nu <= 0 || L.m == 0) return;
     Work<T>& w = L.w<T>();
-    sell<T>(L.Aux, dev::SPLIT, x, b, w.dhinv, w.g, s, stop, L.n, w.gd);
+    sell<T>(L.Aux, dev::SPLIT, x, b, w.dhinv, w.g, s, stop, w.gd);
     const T* y = w.gd;
     T* ya = w.y;
     T* yb = w.yt;
@@ -345,7 +350,7 @@ void vcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, hi
     // restriction of the residual (and the coarse first sweep), coarse correction,
     // prolongation
     asell<T>(L, dev::RESID, x, b, nullptr, w.r, s, stop);
-    sell<T>(L.Pt, dev::SPMV, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, s, stop, 0,
+    sell<T>(L.Pt, dev::SPMV, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, s, stop,
             next_coarsest ? nullptr : wc.bd);
     vcycle_level<T>(H, l + 1, wc.b, wc.bd, wc.x, s, stop);
     sell<T>(L.P, dev::SPMV_ADD, wc.x, nullptr, nullptr, x, s, stop);
@@ -380,8 +385,9 @@ template <class T> const T* bvals(const DSellB& M);
 template <> const float* bvals<float>(const DSellB& M) { return M.v32; }
 template <> const double* bvals<double>(const DSellB& M) { return M.v64; }
 
-DSellB upload_sell_b(amge_hierarchy* H, const Csr& A, bool incidence, bool f32, bool f64, hipStream_t s) {
-    HostSell h = make_sell(A, incidence, 1);
+DSellB upload_sell_b(amge_hierarchy* H, const Csr& A, bool incidence, bool f32, bool f64, hipStream_t s,
+                     const std::vector<int>* lead = nullptr) {
+    HostSell h = make_sell(A, incidence, 1, lead);
     DSellB M;
     M.nrows = A.nrows;
     M.ncols = A.ncols;
@@ -403,36 +409,40 @@ DSellB upload_sell_b(amge_hierarchy* H, const Csr& A, bool incidence, bool f32, 
             std::vector<float> v(h.val.begin(), h.val.end());
             M.v32 = upload(H, v.data(), v.size(), s);
         }
+        if (lead) M.lead = upload(H, h.lead.data(), h.lead.size(), s);
     }
     HIPCHECK(hipStreamSynchronize(s));
     return M;
 }
 
 template <class T, int V, int MODE>
-void bmm_v(const DSellB& M, int W, int NC, const T* X, const T* B, const T* dinv, T* Y, T* YD, int nsplit,
+void bmm_v(const DSellB& M, int W, int NC, const T* X, const T* B, const T* dinv, T* Y, T* YD,
            const int* stop, hipStream_t s) {
     const int L = W / V;
     const unsigned grid = (unsigned)(((int64_t)M.nslices * L + WAVES - 1) / WAVES);
     if (!grid) return;
     if (M.c16)
         dev::k_sell_mm<T, V, MODE, true><<<grid, BLOCK, 0, s>>>(M.nslices, L, NC, M.sptr, M.srow, M.ci, M.c16,
-                                                                M.cbase, bvals<T>(M), X, B, dinv, Y, YD, nsplit,
+                                                                M.cbase, bvals<T>(M), X, B, dinv, Y, YD, M.lead,
                                                                 stop);
     else
         dev::k_sell_mm<T, V, MODE, false><<<grid, BLOCK, 0, s>>>(M.nslices, L, NC, M.sptr, M.srow, M.ci, M.c16,
-                                                                 M.cbase, bvals<T>(M), X, B, dinv, Y, YD, nsplit,
+                                                                 M.cbase, bvals<T>(M), X, B, dinv, Y, YD, M.lead,
                                                                  stop);
 }
 
 template <class T, int V>
 void bmm_m(const DSellB& M, int mode, int W, int NC, const T* X, const T* B, const T* dinv, T* Y, T* YD,
-           int nsplit, const int* stop, hipStream_t s) {
+           const int* stop, hipStream_t s) {
     switch (mode) {
-        case dev::SPMV: bmm_v<T, V, dev::SPMV>(M, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case dev::SPMV_ADD: bmm_v<T, V, dev::SPMV_ADD>(M, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case dev::RESID: bmm_v<T, V, dev::RESID>(M, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case dev::JAC: bmm_v<T, V, dev::JAC>(M, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case dev::SPLIT: bmm_v<T, V, dev::SPLIT>(M, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case dev::SPMV: bmm_v<T, V, dev::SPMV>(M, W, NC, X, B, dinv, Y, YD, stop, s); break;
+        case dev::SPMV_ADD: bmm_v<T, V, dev::SPMV_ADD>(M, W, NC, X, B, dinv, Y, YD, stop, s); break;
+        case dev::RESID: bmm_v<T, V, dev::RESID>(M, W, NC, X, B, dinv, Y, YD, stop, s); break;
+        case dev::JAC: bmm_v<T, V, dev::JAC>(M, W, NC, X, B, dinv, Y, YD, stop, s); break;
+        case dev::SPLIT:
+            if (!M.lead) fail(AMGE_ERR_ARG, "split product on a matrix without split rows");
+            bmm_v<T, V, dev::SPLIT>(M, W, NC, X, B, dinv, Y, YD, stop, s);
+            break;
         default: fail(AMGE_ERR_ARG, "bad SpMM mode");
     }
 }
@@ -443,13 +453,13 @@ inline int lane_cols(int V, int W) { return std::min(V, W); }
 // Block product on the first W (active) of the NC stored columns.
 template <class T>
 void bmm(const DSellB& M, int mode, int W, int NC, const T* X, const T* B, const T* dinv, T* Y, const int* stop,
-         hipStream_t s, int nsplit = 0, T* YD = nullptr) {
+         hipStream_t s, T* YD = nullptr) {
     switch (lane_cols(M.V, W)) {
-        case 1: bmm_m<T, 1>(M, mode, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case 2: bmm_m<T, 2>(M, mode, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case 4: bmm_m<T, 4>(M, mode, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        case 8: bmm_m<T, 8>(M, mode, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
-        default: bmm_m<T, 16>(M, mode, W, NC, X, B, dinv, Y, YD, nsplit, stop, s); break;
+        case 1: bmm_m<T, 1>(M, mode, W, NC, X, B, dinv, Y, YD, stop, s); break;
+        case 2: bmm_m<T, 2>(M, mode, W, NC, X, B, dinv, Y, YD, stop, s); break;
+        case 4: bmm_m<T, 4>(M, mode, W, NC, X, B, dinv, Y, YD, stop, s); break;
+        case 8: bmm_m<T, 8>(M, mode, W, NC, X, B, dinv, Y, YD, stop, s); break;
+        default: bmm_m<T, 16>(M, mode, W, NC, X, B, dinv, Y, YD, stop, s); break;
     }
 }
 
@@ -579,7 +589,7 @@ void bauxiliary(amge_hierarchy* H, DLevel& L, const T* b, T* x, int nu, int W, c
     if (nu <= 0 || L.m == 0) return;
     Work<T>& w = L.bw<T>();
     const int NC = H->NC;
-    bmm<T>(L.bAux, dev::SPLIT, W, NC, x, b, w.dhinv, w.g, stop, s, L.n, w.gd);
+    bmm<T>(L.bAux, dev::SPLIT, W, NC, x, b, w.dhinv, w.g, stop, s, w.gd);
     const T* y = w.gd;
     T* ya = w.y;
     T* yb = w.yt;
@@ -618,7 +628,7 @@ void bvcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, i
     bprimary<T>(H, L, b, bd, x, xt, true, nup, W, stop, s);
     bauxiliary<T>(H, L, b, x, nua, W, stop, s);
     bmm<T>(L.bA, dev::RESID, W, NC, x, b, nullptr, w.r, stop, s);
-    bmm<T>(L.bPt, dev::SPMV, W, NC, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, stop, s, 0,
+    bmm<T>(L.bPt, dev::SPMV, W, NC, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, stop, s,
               next_coarsest ? nullptr : wc.bd);
     bvcycle_level<T>(H, l + 1, wc.b, wc.bd, wc.x, W, stop, s);
     bmm<T>(L.bP, dev::SPMV_ADD, W, NC, wc.x, nullptr, nullptr, x, stop, s);
@@ -737,6 +747,7 @@ void alloc_bwork(amge_hierarchy* H, DLevel& L, const Work<T>& w1, Work<T>& w) {
 // Level matrices kept on the host during set-up for the batched uploads.
 struct HostLevel {
     Csr A, Ah, P, Pt, Aux, D;
+    std::vector<int> aux_lead;   // split rows of Aux: entries of D^T per row
 };
 
 template <class T>
@@ -783,7 +794,7 @@ void setup_batched(amge_hierarchy* H, const std::vector<HostLevel>& hl, hipStrea
             L.bAh = upload_sell_b(H, h.Ah, false, f32, !f32, s);
             L.bP = upload_sell_b(H, h.P, false, f32, !f32, s);
             L.bPt = upload_sell_b(H, h.Pt, false, f32, !f32, s);
-            L.bAux = upload_sell_b(H, h.Aux, false, f32, !f32, s);
+            L.bAux = upload_sell_b(H, h.Aux, false, f32, !f32, s, &h.aux_lead);
             L.bD = upload_sell_b(H, h.D, true, false, false, s);
         }
         if (f32 && nl > 1) alloc_bwork<float>(H, L, L.w32, L.bw32);
@@ -887,29 +898,34 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         L.D = upload_tuned(H, D[k], true, s);
         L.Dt = upload_tuned(H, Dt, true, s);
         {
-            // [D^T | -D^T A] over the columns [b; x]
+            // [D^T | -D^T A] acting on [b; x]: split rows, the D^T entries of a row first
+            // (they read b), then those of -D^T A (they read x); both index 0..n-1, so the
+            // 16-bit column offsets apply as for A_k
             Csr X;
             X.nrows = L.m;
-            X.ncols = 2 * L.n;
+            X.ncols = L.n;
             X.rowptr.assign(L.m + 1, 0);
+            std::vector<int> lead(L.m);
             for (int i = 0; i < L.m; ++i) {
                 for (int q = Dt.rowptr[i]; q < Dt.rowptr[i + 1]; ++q) {
                     X.col.push_back(Dt.col[q]);
                     X.val.push_back(Dt.val[q]);
                 }
+                lead[i] = Dt.rowptr[i + 1] - Dt.rowptr[i];
                 for (int q = DtA.rowptr[i]; q < DtA.rowptr[i + 1]; ++q) {
-                    X.col.push_back(L.n + DtA.col[q]);
+                    X.col.push_back(DtA.col[q]);
                     X.val.push_back(-DtA.val[q]);
                 }
                 X.rowptr[i + 1] = (int32_t)X.col.size();
             }
-            L.Aux = upload_tuned(H, X, false, s);
+            L.Aux = upload_tuned(H, X, false, s, &lead);
             L.Aux.stream = true;
             if (batched) {
                 hl[k].Ah = Ah;
                 hl[k].P = P[k];
                 hl[k].Pt = transpose(P[k]);
                 hl[k].Aux = std::move(X);
+                hl[k].aux_lead = std::move(lead);
                 hl[k].D = D[k];
             }
         }
@@ -1528,7 +1544,8 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
             tot += launched * (mat(L.A, L.bA) + 3 * sx * n + sv * n) + 2 * sx * n;
             // auxiliary step, pre and post: residual [D^T | -D^T A][b; x] (+ gd), sweeps, D add
             if (nua > 0) {
-                double aux = mat(L.Aux, L.bAux) + sx * (2 * n + m) + sx * m + sv * m;   // b, x; g, gd; dhinv
+                // [D^T | -D^T A] with its split counts (2 bytes a row); b, x; g, gd; dhinv
+                double aux = mat(L.Aux, L.bAux) + 2.0 * m + sx * (2 * n + m) + sx * m + sv * m;
                 aux += (nua - 1) * (mat(L.Ah, L.bAh) + 3 * sx * m + sv * m);
                 aux += incb(L.D, L.bD) + sx * (m + 2 * n);
                 tot += 2 * aux;
