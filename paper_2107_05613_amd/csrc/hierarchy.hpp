@@ -105,7 +105,7 @@ struct amge_hierarchy {
     double *r = nullptr, *p = nullptr, *q = nullptr, *z[2] = {nullptr, nullptr}, *x = nullptr;
     double *part_pq = nullptr, *part_dots[2] = {nullptr, nullptr};
     amge::dev::PcgStatus* st = nullptr;
-    int* flags = nullptr;        // [0] done, [1] breakdown
+    int* flags = nullptr;        // [0] done, [1] breakdown, [2..3] iteration count by buffer parity
     // batched PCG (NC = max_rhs rounded up to a power of two, columns beyond nrhs are zero)
     int NC = 1, lgNC = 0;
     double *bX = nullptr, *bR = nullptr, *bP = nullptr, *bQ = nullptr, *bZ = nullptr, *bZv = nullptr;

@@ -332,16 +332,24 @@ k_pcg_dots(int n, const TZ* __restrict__ z, const TZ* __restrict__ zold, const d
 
 // Status written by the last kernel of every iteration (read by the host).
 
-// beta = (r.z - r.zold) / delta_old; p = z + beta p; stopping test.
+// beta = (r.z - r.zold) / delta_old; p = z + beta p; stopping test, then (one thread)
+// the iteration's status, the stop flag and the host record.
+// Every block takes the same decision from the same partial sums.  The blocks read only
+// fields of st that are fixed during a solve, and the iteration count from it_in, while
+// the count is written to it_out (the two alternate with the buffer parity): so no
+// block sees a value written by this launch.  The stop flag may be set while late
+// blocks start; they then return early, which changes nothing, since p is left as it
+// is when the loop stops.  The host record is written first and its tag after a
+// system-scope fence, so a host that sees the tag of iteration k reads its status.
 template <typename TZ>
 __global__ void __launch_bounds__(BLOCK)
 k_pcg_p(int n, const double* __restrict__ part_new, const double* __restrict__ part_old,
         const TZ* __restrict__ z, double* __restrict__ p, PcgStatus* __restrict__ st,
-        int* __restrict__ done, const int* __restrict__ flag) {
+        int* __restrict__ done, const int* __restrict__ flag, const int* __restrict__ it_in,
+        int* __restrict__ it_out, PcgRecord* __restrict__ ring) {
     __shared__ double sh[WAVES + 1];
     const int stopped = *done;   // tested after the reductions, whose loads it overlaps
-    // iteration count and stopping parameters: st->iters changes only in k_pcg_finish
-    const int it = st->iters, maxit = st->maxit, stop_l2 = st->stop_l2;
+    const int it = *it_in, maxit = st->maxit, stop_l2 = st->stop_l2;
     const double rtol = st->rtol;
     const double dnew = sum_partials(part_new, sh);
     const double rzold = sum_partials(part_new + NRED, sh);
@@ -355,32 +363,22 @@ k_pcg_p(int n, const double* __restrict__ part_new, const double* __restrict__ p
         for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK)
             p[i] = fma(beta, p[i], (double)z[i]);
     }
-    // every block has finished reading `done` at entry; only one block publishes
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->delta = dnew;
         st->rr = rr;
         st->relres = rel;
         st->breakdown = *flag;
+        st->iters = it + 1;
+        *it_out = it + 1;
+        if (stop) {
+            *done = 1;
+            st->done = 1;
+        }
+        PcgRecord* rec = ring + (it + 1) % PCG_RING;
+        rec->st = *st;
+        __threadfence_system();
+        rec->tag = ((uint64_t)st->epoch << 32) | (uint32_t)(it + 1);
     }
-}
-
-// Counts the iteration and marks the loop finished (separate launch, so no block of
-// k_pcg_p can observe the changes mid-kernel), then publishes the status to the host
-// ring: the record first, the tag after a system-scope fence, so a host that sees the
-// tag of iteration k reads the status of iteration k.
-__global__ void k_pcg_finish(PcgStatus* __restrict__ st, int* __restrict__ done, PcgRecord* __restrict__ ring) {
-    if (*done) return;
-    st->iters += 1;
-    const bool stop = st->breakdown || (st->rtol > 0 && st->relres <= st->rtol) || (st->iters >= st->maxit) ||
-                      !isfinite(st->delta);
-    if (stop) {
-        *done = 1;
-        st->done = 1;
-    }
-    PcgRecord* rec = ring + st->iters % PCG_RING;
-    rec->st = *st;
-    __threadfence_system();
-    rec->tag = ((uint64_t)st->epoch << 32) | (uint32_t)st->iters;
 }
 
 // Initial quantities: delta0 = r.z, bnorm = ||b||, from the dots partials; stopping

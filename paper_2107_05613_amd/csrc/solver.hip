@@ -947,7 +947,7 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     H->part_dots[0] = H->alloc<double>(3 * dev::NRED);
     H->part_dots[1] = H->alloc<double>(3 * dev::NRED);
     H->st = H->alloc<dev::PcgStatus>(1);
-    H->flags = H->alloc<int>(2);
+    H->flags = H->alloc<int>(4);
     if (H->opts.precond_bits == 0)
         H->opts.precond_bits = std::ldexp(H->kappa, -24) <= AUTO_FP32_LIMIT ? 32 : 64;
     if (batched) setup_batched(H, hl, s);
@@ -1005,14 +1005,15 @@ void pcg_iteration(amge_hierarchy* H, int par, hipStream_t s) {
         vcycle_level<float>(H, 0, r32, rd32, z32, s, done);
         dev::k_pcg_dots<float><<<dev::NRED, BLOCK, 0, s>>>(n, z32, reinterpret_cast<const float*>(zold), H->r, dnew,
                                                            H->flags);
-        dev::k_pcg_p<float><<<dev::NRED, BLOCK, 0, s>>>(n, dnew, dold, z32, H->p, H->st, H->flags, H->flags + 1);
+        dev::k_pcg_p<float><<<dev::NRED, BLOCK, 0, s>>>(n, dnew, dold, z32, H->p, H->st, H->flags, H->flags + 1,
+                                                        H->flags + 2 + par, H->flags + 2 + (par ^ 1), H->ring_dev);
     } else {
         if (!multilevel) coarse_solve<double>(H, H->r, znew, s, done);
         else vcycle_level<double>(H, 0, H->r, rd64, znew, s, done);
         dev::k_pcg_dots<double><<<dev::NRED, BLOCK, 0, s>>>(n, znew, zold, H->r, dnew, H->flags);
-        dev::k_pcg_p<double><<<dev::NRED, BLOCK, 0, s>>>(n, dnew, dold, znew, H->p, H->st, H->flags, H->flags + 1);
+        dev::k_pcg_p<double><<<dev::NRED, BLOCK, 0, s>>>(n, dnew, dold, znew, H->p, H->st, H->flags, H->flags + 1,
+                                                         H->flags + 2 + par, H->flags + 2 + (par ^ 1), H->ring_dev);
     }
-    dev::k_pcg_finish<<<1, 1, 0, s>>>(H->st, H->flags, H->ring_dev);
 }
 
 // One iteration of each buffer parity captured once as a HIP graph on the hierarchy's
@@ -1069,7 +1070,7 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
     }
     copy_vec<double>(n, b, H->r, gs, H->zero_flag);
     fill_zero<double>(n, H->x, gs, H->zero_flag);
-    fill_zero<int>(2, H->flags, gs, H->zero_flag);
+    fill_zero<int>(4, H->flags, gs, H->zero_flag);
     if (f32 && multilevel) {
         convert<double, float>(n, H->r, L1.w32.b, gs);
         scale<float>(n, L1.w32.dinv, L1.w32.b, L1.w32.bd, gs);
