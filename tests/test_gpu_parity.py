@@ -275,9 +275,10 @@ def test_cancellation_factor_and_auto_precision(spec):
 
 @pytest.mark.parametrize("bits", [32, 64])
 def test_pcg_graph_replays_match_direct_launches(bits):
-    """The PCG iterations run as replays of a captured graph (pairs of iterations); with
-    kernel timing on they are launched directly.  Both give bitwise the same iterate and
-    count, also with other GPU work and solves on other right-hand sides in between."""
+    """The PCG iterations run as replays of captured one-iteration graphs, queued ahead of
+    the host's stopping test; with kernel timing on they are launched directly, in pairs.
+    Both give bitwise the same iterate and count, also with other GPU work and solves on
+    other right-hand sides (stopped by maxit) in between."""
     c = case("div", 8, 3, "blocks")
     H = c.gpu[bits]
     b2 = W.rhs(c.n1, 99)[:, 0]
