@@ -176,6 +176,62 @@ k_sell_inc(int nslices, const int* __restrict__ sptr, const int* __restrict__ sr
     y[row] = ADD ? yr + acc : acc;
 }
 
+// Signed incidence with the same number W of entries in every row (the fine-level
+// derivatives: an edge has two vertices, a triangle three edges), stored row-major as
+// n x W words (column | sign << 31), no padding and no slice layout: y = D x (ADD = 0)
+// or y += D x (ADD = 1), summed in entry order like k_sell_inc.  Thread t takes rows t,
+// t + S, ... (S = grid size), INC_ROWS of them per step with all their loads issued
+// before any is used, so a wave keeps several rows' loads in flight.
+constexpr int INC_ROWS = 4;
+
+template <typename T, int W, int ADD>
+__device__ __forceinline__ T inc_row(const uint32_t (&e)[W], const T (&v)[W]) {
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) acc += (e[k] >> 31) ? -v[k] : v[k];
+    return acc;
+}
+
+template <typename T, int W, int ADD>
+__global__ void __launch_bounds__(BLOCK)
+k_inc_fixed(int n, const uint32_t* __restrict__ ent, const T* __restrict__ x, T* __restrict__ y,
+            const int* __restrict__ stop) {
+    constexpr int R = INC_ROWS;
+    if (*stop) return;
+    const int64_t S = (int64_t)gridDim.x * BLOCK;
+    int64_t r0 = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+    for (; r0 + (R - 1) * S < n; r0 += R * S) {
+        uint32_t e[R][W];
+        T yr[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+#pragma unroll
+            for (int k = 0; k < W; ++k) e[u][k] = ent[(r0 + u * S) * W + k];
+            yr[u] = ADD ? y[r0 + u * S] : T(0);
+        }
+        T v[R][W];
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+#pragma unroll
+            for (int k = 0; k < W; ++k) v[u][k] = x[e[u][k] & 0x7fffffffu];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const T acc = inc_row<T, W, ADD>(e[u], v[u]);
+            y[r0 + u * S] = ADD ? yr[u] + acc : acc;
+        }
+    }
+    for (; r0 < n; r0 += S) {
+        uint32_t e[W];
+        T v[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) e[k] = ent[r0 * W + k];
+#pragma unroll
+        for (int k = 0; k < W; ++k) v[k] = x[e[k] & 0x7fffffffu];
+        const T acc = inc_row<T, W, ADD>(e, v);
+        y[r0] = ADD ? y[r0] + acc : acc;
+    }
+}
+
 // y = dinv * x (one sweep from zero)
 template <typename T>
 __global__ void __launch_bounds__(BLOCK)

@@ -125,8 +125,23 @@ void sell_inc_k(const DSell& M, int add, const T* x, T* y, hipStream_t s, const 
     else dev::k_sell_inc<T, K, 0><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ent, x, y, stop);
 }
 
+template <class T, int W>
+void inc_fixed_w(const DSell& M, int add, const T* x, T* y, hipStream_t s, const int* stop) {
+    const unsigned g = grid_for((M.nrows + dev::INC_ROWS - 1) / dev::INC_ROWS);
+    if (add) dev::k_inc_fixed<T, W, 1><<<g, BLOCK, 0, s>>>(M.nrows, M.fent, x, y, stop);
+    else dev::k_inc_fixed<T, W, 0><<<g, BLOCK, 0, s>>>(M.nrows, M.fent, x, y, stop);
+}
+
 template <class T>
 void sell_inc(const DSell& M, int add, const T* x, T* y, hipStream_t s, const int* stop) {
+    if (M.nrows == 0) return;
+    switch (M.fixedw) {
+        case 0: break;
+        case 1: inc_fixed_w<T, 1>(M, add, x, y, s, stop); return;
+        case 2: inc_fixed_w<T, 2>(M, add, x, y, s, stop); return;
+        case 3: inc_fixed_w<T, 3>(M, add, x, y, s, stop); return;
+        default: inc_fixed_w<T, 4>(M, add, x, y, s, stop); return;
+    }
     switch (M.K) {
         case 1: sell_inc_k<T, 1>(M, add, x, y, s, stop); break;
         case 2: sell_inc_k<T, 2>(M, add, x, y, s, stop); break;
@@ -228,6 +243,31 @@ int tune_lanes(const Csr& A, bool incidence, hipStream_t s) {
 DSell upload_tuned(amge_hierarchy* H, const Csr& A, bool incidence, hipStream_t s,
                    const std::vector<int>* lead = nullptr) {
     return upload_sell(H, A, incidence, tune_lanes(A, incidence, s), s, lead);
+}
+
+// A signed incidence (entries +-1): rows of one common length W <= 4 (the fine-level
+// derivatives) are stored row-major as n x W words for k_inc_fixed; others in the
+// tuned sliced layout.
+DSell upload_incidence(amge_hierarchy* H, const Csr& D, hipStream_t s) {
+    int W = D.nrows ? D.rowptr[1] - D.rowptr[0] : 0;
+    for (int i = 0; i < D.nrows && W; ++i)
+        if (D.rowptr[i + 1] - D.rowptr[i] != W) W = 0;
+    if (W < 1 || W > 4) return upload_tuned(H, D, true, s);
+    std::vector<uint32_t> w((size_t)D.nrows * W);
+    for (size_t q = 0; q < w.size(); ++q) {
+        const double v = D.val[q];
+        if (v != 1.0 && v != -1.0) fail(AMGE_ERR_ARG, "derivative matrix entries must be +-1");
+        w[q] = (uint32_t)D.col[q] | (v < 0 ? 0x80000000u : 0u);
+    }
+    DSell d;
+    d.nrows = D.nrows;
+    d.ncols = D.ncols;
+    d.nnz = D.nnz();
+    d.stored = D.nnz();
+    d.fixedw = W;
+    d.fent = upload(H, w.data(), w.size(), s);
+    HIPCHECK(hipStreamSynchronize(s));
+    return d;
 }
 
 // Launch of an A_k kernel; on a probed level the launch is bracketed by events and its
@@ -895,7 +935,7 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         L.Pt = upload_tuned(H, transpose(P[k]), false, s);
         // every operator but A_k streamed past the caches (A_k is used four times)
         L.Ah.stream = L.P.stream = L.Pt.stream = true;
-        L.D = upload_tuned(H, D[k], true, s);
+        L.D = upload_incidence(H, D[k], s);
         L.Dt = upload_tuned(H, Dt, true, s);
         {
             // [D^T | -D^T A] acting on [b; x]: split rows, the D^T entries of a row first
@@ -1537,7 +1577,8 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
                                : (double)M.nnz * (sv + (M.c16 ? 2.0 : 4.0)) + 4.0 * M.nrows;
             };
             auto incb = [&](const DSell& M, const DSellB& B) {
-                return batched ? (double)B.nnz * 4.0 + 4.0 * B.nrows : (double)M.nnz * 4.0 + 4.0 * M.nrows;
+                return batched ? (double)B.nnz * 4.0 + 4.0 * B.nrows
+                               : (double)M.nnz * 4.0 + (M.fixedw ? 0.0 : 4.0 * M.nrows);
             };
             // primary sweeps: the first one from zero is the producer's bd = dinv b (two
             // extra streams there), every launched sweep reads x, b and writes y (+ dinv)
