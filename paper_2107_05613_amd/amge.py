@@ -41,7 +41,7 @@ class LevelC(C.Structure):
 
 class OptsC(C.Structure):
     _fields_ = [("nu_primary", C.c_int32), ("nu_aux", C.c_int32), ("precond_bits", C.c_int32),
-                ("max_rhs", C.c_int32)]
+                ("max_rhs", C.c_int32), ("tail_rows", C.c_int32)]
 
 
 class CompletionC(C.Structure):
@@ -206,7 +206,7 @@ def build_problem(kind, n, nlevels, alpha_hex, beta_hex):
 class Hierarchy:
     """Device-resident AMGe hierarchy (amge_setup_hierarchy)."""
 
-    def __init__(self, levels, nu_primary=2, nu_aux=2, precond_bits=32, max_rhs=1, stream=None):
+    def __init__(self, levels, nu_primary=2, nu_aux=2, precond_bits=32, max_rhs=1, tail_rows=2048, stream=None):
         L = len(levels)
         arr = (LevelC * L)()
         self._keep = []
@@ -220,7 +220,7 @@ class Hierarchy:
                 mats.append(M)
             self._keep.extend(mats)
             arr[i].A, arr[i].D, arr[i].P = (m.to_c() for m in mats)
-        opts = OptsC(nu_primary, nu_aux, precond_bits, max_rhs)
+        opts = OptsC(nu_primary, nu_aux, precond_bits, max_rhs, tail_rows)
         h = C.c_void_p()
         _check(_lib.amge_setup_hierarchy(arr, L, C.byref(opts), _stream(stream), C.byref(h)))
         self._h = h

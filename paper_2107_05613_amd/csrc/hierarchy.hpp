@@ -103,6 +103,10 @@ struct amge_hierarchy {
     int nc = 0;                  // coarsest size
     double kappa = 1.0;          // largest cancellation factor of the auxiliary matrices
     double* Ainv = nullptr;      // coarsest inverse from the Cholesky factor
+    // single-column V-cycle: levels >= tail are applied as the dense FP64 operator
+    // tail_op (tail_n x tail_n): the coarsest inverse, or a folded coarse tail
+    int tail = 0, tail_n = 0;
+    double* tail_op = nullptr;
     // outer PCG buffers (FP64, level-1 length)
     double *r = nullptr, *p = nullptr, *q = nullptr, *z[2] = {nullptr, nullptr}, *x = nullptr;
     double *part_pq = nullptr, *part_dots[2] = {nullptr, nullptr};

@@ -240,9 +240,12 @@ k_scale(int n, const T* __restrict__ dinv, const T* __restrict__ x, T* __restric
     if (i < n) y[i] = dinv[i] * x[i];
 }
 
-// ---------------------------------------------------------------- coarsest level
-// x = Ainv b with Ainv = W^T W, W = L^{-1} from the FP64 Cholesky factor A = L L^T
-// formed at set-up; FP64 arithmetic whatever T is.  One wave per row.
+// ---------------------------------------------------------------- dense operators
+// x = M b for a dense row-major FP64 n x n operator: the coarsest inverse Ainv = W^T W,
+// W = L^{-1} from the FP64 Cholesky factor A = L L^T formed at set-up, or the folded
+// coarse tail of the V-cycle.  FP64 arithmetic whatever T is.  One wave per row; lane l
+// sums j = l, l + 64, ... in order, eight terms' loads issued at a time.  The operator is
+// read with non-temporal loads (a folded tail is tens of MB, read once per V-cycle).
 template <typename T>
 __global__ void __launch_bounds__(BLOCK)
 k_coarse(int n, const double* __restrict__ Ainv, const T* __restrict__ b, T* __restrict__ x,
@@ -253,11 +256,32 @@ k_coarse(int n, const double* __restrict__ Ainv, const T* __restrict__ b, T* __r
     const int lane = threadIdx.x & 63;
     const double* a = Ainv + (int64_t)row * n;
     double acc = 0;
-    for (int j = lane; j < n; j += 64) acc = fma(a[j], (double)b[j], acc);
+    int j = lane;
+    for (; j + 7 * 64 < n; j += 8 * 64) {
+        double av[8], bv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            av[u] = __builtin_nontemporal_load(a + j + u * 64);
+            bv[u] = (double)b[j + u * 64];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma(av[u], bv[u], acc);
+    }
+    for (; j < n; j += 64) acc = fma(__builtin_nontemporal_load(a + j), (double)b[j], acc);
     acc = wave_sum(acc);
     // the stop flag is tested only before the store: its load overlaps the product
     // (a stopped launch reads the small inverse once and writes nothing)
     if (lane == 0 && !stopped) x[row] = (T)acc;
+}
+
+// b = e_i and bd = dinv_i e_i (a unit right-hand side and its first sweep from zero)
+template <typename T>
+__global__ void __launch_bounds__(BLOCK)
+k_unit(int n, int i, const T* __restrict__ dinv, T* __restrict__ b, T* __restrict__ bd) {
+    const int j = blockIdx.x * BLOCK + threadIdx.x;
+    if (j >= n) return;
+    b[j] = j == i ? T(1) : T(0);
+    bd[j] = j == i ? dinv[i] : T(0);
 }
 
 // ---------------------------------------------------------------- conversions

@@ -165,21 +165,32 @@ k_sell_inc_mm_add(int nslices, int L, int NC, const int* __restrict__ sptr, cons
     acc.store(Y + (int64_t)row * NC + col);
 }
 
-// Coarsest level: X = Ainv B, one thread per (row, column) for the first W = 2^lgW
-// columns of the NC = 2^lg stored ones; FP64 arithmetic.
+// Coarsest level: X = Ainv B on the first W = 2^lgW of the NC = 2^lg stored columns;
+// FP64 arithmetic.  One block per row: thread t owns column t % NC and the terms
+// j = g, g + G, ... with g = t / NC, G = BLOCK / NC (summed in order), and the G partial
+// sums of a column are added in the order of g.  The layout depends on NC only, so a
+// column's result does not depend on W.
 template <typename T>
 __global__ void __launch_bounds__(BLOCK)
 k_coarse_mm(int n, int lgW, int lg, const double* __restrict__ Ainv, const T* __restrict__ B, T* __restrict__ X,
             const int* __restrict__ stop) {
+    __shared__ double sh[BLOCK];
     const int stopped = *stop;   // tested before the store: its load overlaps the product
-    const int NC = 1 << lg;
-    const int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-    if (t >= ((int64_t)n << lgW)) return;
-    const int row = (int)(t >> lgW), c = (int)(t & ((1 << lgW) - 1));
-    const double* a = Ainv + (int64_t)row * n;
+    const int NC = 1 << lg, W = 1 << lgW, G = BLOCK >> lg;
+    const int row = blockIdx.x;
+    const int c = threadIdx.x & (NC - 1), g = threadIdx.x >> lg;
     double acc = 0;
-    for (int j = 0; j < n; ++j) acc = fma(a[j], (double)B[(int64_t)j * NC + c], acc);
-    if (!stopped) X[(int64_t)row * NC + c] = (T)acc;
+    if (c < W) {
+        const double* a = Ainv + (int64_t)row * n;
+        for (int j = g; j < n; j += G) acc = fma(a[j], (double)B[(int64_t)j * NC + c], acc);
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (g == 0 && c < W && !stopped) {
+        double t = 0;
+        for (int k = 0; k < G; ++k) t += sh[k * NC + c];
+        X[(int64_t)row * NC + c] = (T)t;
+    }
 }
 
 // ---------------------------------------------------------------- batched PCG

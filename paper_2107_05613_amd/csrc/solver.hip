@@ -300,10 +300,16 @@ void scale(int n, const T* dinv, const T* x, T* y, hipStream_t s) {
     if (n) dev::k_scale<T><<<grid_for(n), BLOCK, 0, s>>>(n, dinv, x, y);
 }
 
+// x = M b for a dense FP64 n x n operator (k_coarse)
+template <class T>
+void dense_apply(int n, const double* M, const T* b, T* x, hipStream_t s, const int* stop) {
+    if (n) dev::k_coarse<T><<<(unsigned)((n + WAVES - 1) / WAVES), BLOCK, 0, s>>>(n, M, b, x, stop);
+}
+
+// The coarsest solve with the inverse from the Cholesky factor
 template <class T>
 void coarse_solve(amge_hierarchy* H, const T* b, T* x, hipStream_t s, const int* stop) {
-    int n = H->nc;
-    dev::k_coarse<T><<<(unsigned)((n + WAVES - 1) / WAVES), BLOCK, 0, s>>>(n, H->Ainv, b, x, stop);
+    dense_apply<T>(H->nc, H->Ainv, b, x, s, stop);
 }
 
 template <class T>
@@ -371,9 +377,8 @@ void auxiliary(DLevel& L, const T* b, T* x, int nu, hipStream_t s, const int* st
 // level's right-hand side and first sweep, the result goes to xout.
 template <class T>
 void vcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, hipStream_t s, const int* stop) {
-    const int nl = (int)H->lv.size();
-    if (l == nl - 1) {
-        coarse_solve<T>(H, b, xout, s, stop);
+    if (l == H->tail) {   // the coarsest solve, or the folded coarse tail
+        dense_apply<T>(H->tail_n, H->tail_op, b, xout, s, stop);
         return;
     }
     DLevel& L = H->lv[l];
@@ -383,7 +388,7 @@ void vcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, hi
     T* x = xout;
     T* xt = w.xt;
     const int nup = H->opts.nu_primary, nua = H->opts.nu_aux;
-    const bool next_coarsest = l + 1 == nl - 1;
+    const bool next_coarsest = l + 1 == H->tail;   // needs no first sweep of its own
     // pre-smoothing with Mbar (eq. (4.1)): primary, then auxiliary
     primary<T>(L, b, bd, x, xt, true, nup, s, stop);
     auxiliary<T>(L, b, x, nua, s, stop);
@@ -653,8 +658,7 @@ void bvcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, i
     const int nl = (int)H->lv.size();
     const int NC = H->NC;
     if (l == nl - 1) {
-        const int64_t t = (int64_t)H->nc * W;
-        dev::k_coarse_mm<T><<<grid_for(t), BLOCK, 0, s>>>(H->nc, log2i(W), H->lgNC, H->Ainv, b, xout, stop);
+        if (H->nc) dev::k_coarse_mm<T><<<H->nc, BLOCK, 0, s>>>(H->nc, log2i(W), H->lgNC, H->Ainv, b, xout, stop);
         return;
     }
     DLevel& L = H->lv[l];
@@ -879,6 +883,40 @@ double cancellation_factor(const Csr& A, const Csr& D, const Csr& Dt, const std:
 // FP32 rounding reach a tenth of the near-kernel components.
 constexpr double AUTO_FP32_LIMIT = 0.1;
 
+// Folding of the coarse tail of the single-column V-cycle.  With a zero initial guess
+// the V-cycle from level l down is a fixed linear map B_l of the level's right-hand
+// side; while the level above the current tail has at most opts.tail_rows rows (and is
+// not the fine level), B_l is formed column by column, by running the FP64 V-cycle from
+// level l on the unit vectors, and from then on applied as one dense FP64 product: the
+// same operator with one launch instead of every launch of those levels.
+void fold_tail(amge_hierarchy* H, hipStream_t s) {
+    const int lim = H->opts.tail_rows;
+    while (lim > 0 && H->tail >= 2 && H->lv[H->tail - 1].n <= lim) {
+        const int l = H->tail - 1;
+        const int n = H->lv[l].n;
+        Work<double>& w = H->lv[l].w64;
+        double* M = H->alloc<double>((size_t)n * n);
+        for (int i = 0; i < n; ++i) {
+            dev::k_unit<double><<<grid_for(n), BLOCK, 0, s>>>(n, i, w.dinv, w.b, w.bd);
+            vcycle_level<double>(H, l, w.b, w.bd, M + (size_t)i * n, s, H->zero_flag);
+        }
+        HIPCHECK(hipGetLastError());
+        // row i of M holds B_l e_i, column i of B_l: store B_l row-major
+        std::vector<double> h((size_t)n * n), t((size_t)n * n);
+        HIPCHECK(hipMemcpyAsync(h.data(), M, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) t[(size_t)j * n + i] = h[(size_t)i * n + j];
+        for (double v : t)
+            if (!std::isfinite(v)) fail(AMGE_ERR_NONFINITE, "non-finite folded coarse tail");
+        HIPCHECK(hipMemcpyAsync(M, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        H->tail = l;
+        H->tail_n = n;
+        H->tail_op = M;
+    }
+}
+
 void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     if (!levels || nl < 1) fail(AMGE_ERR_ARG, "need at least one level");
     std::vector<Csr> A(nl), D(nl), P(nl);
@@ -991,6 +1029,10 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     if (H->opts.precond_bits == 0)
         H->opts.precond_bits = std::ldexp(H->kappa, -24) <= AUTO_FP32_LIMIT ? 32 : 64;
     if (batched) setup_batched(H, hl, s);
+    H->tail = nl - 1;
+    H->tail_n = H->nc;
+    H->tail_op = H->Ainv;
+    fold_tail(H, s);
     HIPCHECK(hipStreamSynchronize(s));
 }
 
@@ -1360,6 +1402,7 @@ extern "C" void amge_default_opts(amge_opts* o) {
     o->nu_aux = 2;
     o->precond_bits = 32;
     o->max_rhs = 1;
+    o->tail_rows = 2048;
 }
 
 extern "C" amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nlevels, const amge_opts* opts,
@@ -1371,6 +1414,7 @@ extern "C" amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nl
         if (opts) H->opts = *opts;
         else amge_default_opts(&H->opts);
         if (H->opts.nu_primary < 0 || H->opts.nu_aux < 0 || H->opts.max_rhs < 1 || H->opts.max_rhs > 64 ||
+            H->opts.tail_rows < 0 || H->opts.tail_rows > 8192 ||
             (H->opts.precond_bits != 0 && H->opts.precond_bits != 32 && H->opts.precond_bits != 64))
             fail(AMGE_ERR_ARG, "invalid options");
         setup(H.get(), levels, nlevels, (hipStream_t)stream);
@@ -1566,8 +1610,10 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
         const double sx = sv * nrhs;                       // one row of a vector block
         const int nup = h->opts.nu_primary, nua = h->opts.nu_aux;
         double tot = 0;
-        const size_t nl = h->lv.size();
-        for (size_t k = 0; k + 1 < nl; ++k) {
+        // levels run by their kernels: all but the coarsest (batched), or those above the
+        // dense tail (single column: the coarsest inverse or the folded coarse tail)
+        const size_t last = batched ? h->lv.size() - 1 : (size_t)h->tail;
+        for (size_t k = 0; k < last; ++k) {
             const DLevel& L = h->lv[k];
             const double n = L.n, m = L.m, nc = h->lv[k + 1].n;
             // matrix streams: values + column indices + one row pointer (sliced ELL: one
@@ -1597,8 +1643,9 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
             tot += mat(L.Pt, L.bPt) + sx * (n + nc);
             tot += mat(L.P, L.bP) + sx * (nc + 2 * n);
         }
-        // coarsest: the inverse read once, the right-hand side and solution blocks
-        tot += 8.0 * (double)h->nc * h->nc + 2 * sx * h->nc;
+        // the dense operator read once, the right-hand side and solution blocks
+        const double nd = batched ? h->nc : h->tail_n;
+        tot += 8.0 * nd * nd + 2 * sx * nd;
         *bytes = tot;
         return AMGE_OK;
     });

@@ -178,6 +178,42 @@ def test_vcycle(spec):
     assert en <= (1e-3 if c.kappa < 1e6 else 5e-2)
 
 
+@pytest.mark.parametrize("spec", SMALL + [("div", 32, 4, "blocks")])
+def test_folded_tail(spec):
+    """The single-column V-cycle applies its coarse tail (the levels of at most
+    tail_rows rows below the fine one, down to the coarsest) as one dense FP64 operator
+    formed at set-up.  With tail_rows = 0 every level runs its kernels: that cycle
+    matches the oracle to the same bars as the folded one, the two agree to FP64
+    rounding, and PCG takes the same number of iterations."""
+    amge = _amge()
+    c = case(*spec)
+    ref = c.ml.vcycle(c.b)
+    A = c.H.A[0]
+    z = torch.empty_like(dev(c.b))
+    for bits in (64, 32):
+        H0 = amge.Hierarchy(c.prod, precond_bits=bits, tail_rows=0)
+        H0.vcycle(dev(c.b), z)
+        z0 = host(z)
+        c.gpu[bits].vcycle(dev(c.b), z)
+        zf = host(z)
+        d = z0 - ref
+        en = float(np.sqrt(d @ (A @ d)) / np.sqrt(ref @ (A @ ref)))
+        e0, ef = relerr(z0, ref), relerr(zf, z0)
+        print(f"{spec} FP{bits}: unfolded vs oracle {e0:.2e} (energy {en:.2e}); folded vs unfolded {ef:.2e}")
+        if bits == 64:
+            assert e0 <= c.tol64
+            assert ef <= c.tol64
+        else:
+            assert en <= (1e-3 if c.kappa < 1e6 else 5e-2)
+        x0, xf = torch.zeros_like(dev(c.b)), torch.zeros_like(dev(c.b))
+        _, it0, _ = H0.pcg(dev(c.b), x0, rtol=1e-8)
+        _, itf, _ = c.gpu[bits].pcg(dev(c.b), xf, rtol=1e-8)
+        assert abs(it0[0] - itf[0]) <= 1, (it0, itf)
+        H0.close()
+    with pytest.raises(amge.AmgeError):
+        amge.Hierarchy(c.prod, tail_rows=-1)
+
+
 @pytest.mark.parametrize("spec", [("curl", 8, 2, "unit"), ("div", 8, 3, "blocks"), ("div", 32, 4, "blocks")])
 def test_pcg_fp64_parity(spec):
     """a7: inexact PCG in FP64; same iterates as the oracle after the same count, and
