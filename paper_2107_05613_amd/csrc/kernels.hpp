@@ -274,16 +274,6 @@ k_coarse(int n, const double* __restrict__ Ainv, const T* __restrict__ b, T* __r
     if (lane == 0 && !stopped) x[row] = (T)acc;
 }
 
-// b = e_i and bd = dinv_i e_i (a unit right-hand side and its first sweep from zero)
-template <typename T>
-__global__ void __launch_bounds__(BLOCK)
-k_unit(int n, int i, const T* __restrict__ dinv, T* __restrict__ b, T* __restrict__ bd) {
-    const int j = blockIdx.x * BLOCK + threadIdx.x;
-    if (j >= n) return;
-    b[j] = j == i ? T(1) : T(0);
-    bd[j] = j == i ? dinv[i] : T(0);
-}
-
 // ---------------------------------------------------------------- conversions
 template <typename S, typename D>
 __global__ void __launch_bounds__(BLOCK) k_convert(int64_t n, const S* __restrict__ a, D* __restrict__ b) {

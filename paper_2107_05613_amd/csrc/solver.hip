@@ -14,6 +14,7 @@
 #include <map>
 #include <mutex>
 #include <numeric>
+#include <thread>
 #include <tuple>
 
 #include "common.hpp"
@@ -702,7 +703,9 @@ void bprecondition(amge_hierarchy* H, const double* r, double* z, int nrhs, hipS
 }
 
 // ------------------------------------------------------------------ set-up
-void build_coarse(amge_hierarchy* H, const Csr& A, hipStream_t s) {
+// Dense FP64 Cholesky factor of the coarsest matrix and the inverse it gives; the host
+// copy of the inverse goes to ainv.
+void build_coarse(amge_hierarchy* H, const Csr& A, hipStream_t s, std::vector<double>& ainv) {
     int n = A.nrows;
     if (n > 8192) fail(AMGE_ERR_ARG, "coarsest level larger than 8192 rows");
     std::vector<double> L((size_t)n * n, 0.0);
@@ -747,6 +750,7 @@ void build_coarse(amge_hierarchy* H, const Csr& A, hipStream_t s) {
     H->nc = n;
     H->Ainv = upload(H, Ainv.data(), Ainv.size(), s);
     HIPCHECK(hipStreamSynchronize(s));
+    ainv.swap(Ainv);
 }
 
 template <class T>
@@ -883,38 +887,124 @@ double cancellation_factor(const Csr& A, const Csr& D, const Csr& Dt, const std:
 // FP32 rounding reach a tenth of the near-kernel components.
 constexpr double AUTO_FP32_LIMIT = 0.1;
 
-// Folding of the coarse tail of the single-column V-cycle.  With a zero initial guess
-// the V-cycle from level l down is a fixed linear map B_l of the level's right-hand
-// side; while the level above the current tail has at most opts.tail_rows rows (and is
-// not the fine level), B_l is formed column by column, by running the FP64 V-cycle from
-// level l on the unit vectors, and from then on applied as one dense FP64 product: the
-// same operator with one launch instead of every launch of those levels.
-void fold_tail(amge_hierarchy* H, hipStream_t s) {
-    const int lim = H->opts.tail_rows;
-    while (lim > 0 && H->tail >= 2 && H->lv[H->tail - 1].n <= lim) {
-        const int l = H->tail - 1;
-        const int n = H->lv[l].n;
-        Work<double>& w = H->lv[l].w64;
-        double* M = H->alloc<double>((size_t)n * n);
-        for (int i = 0; i < n; ++i) {
-            dev::k_unit<double><<<grid_for(n), BLOCK, 0, s>>>(n, i, w.dinv, w.b, w.bd);
-            vcycle_level<double>(H, l, w.b, w.bd, M + (size_t)i * n, s, H->zero_flag);
-        }
-        HIPCHECK(hipGetLastError());
-        // row i of M holds B_l e_i, column i of B_l: store B_l row-major
-        std::vector<double> h((size_t)n * n), t((size_t)n * n);
-        HIPCHECK(hipMemcpyAsync(h.data(), M, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHECK(hipStreamSynchronize(s));
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) t[(size_t)j * n + i] = h[(size_t)i * n + j];
-        for (double v : t)
-            if (!std::isfinite(v)) fail(AMGE_ERR_NONFINITE, "non-finite folded coarse tail");
-        HIPCHECK(hipMemcpyAsync(M, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, s));
-        HIPCHECK(hipStreamSynchronize(s));
-        H->tail = l;
-        H->tail_n = n;
-        H->tail_op = M;
+// ------------------------------------------------------------------ coarse-tail folding
+// With a zero initial guess the V-cycle from level l down is a fixed linear map B_l of
+// the level's right-hand side.  While the level above the current tail (first the
+// coarsest level, B = A^{-1}) is not the fine level and has at most opts.tail_rows rows,
+// B_l is formed at set-up, one unit vector at a time, by an FP64 host evaluation of the
+// V-cycle at level l (the steps of vcycle_level) around the dense B of the level below;
+// the single-column V-cycle then applies it as one dense FP64 product (k_coarse), the
+// same operator in one launch instead of every launch of those levels.
+
+// Host copy of a level that may be folded.
+struct TailLevel {
+    Csr A, D, Dt, DtA, Ah, P, Pt;
+    std::vector<double> dinv, dhinv;
+};
+
+namespace {
+
+void host_spmv(const Csr& M, const double* x, double* y) {
+    for (int i = 0; i < M.nrows; ++i) {
+        double a = 0;
+        for (int q = M.rowptr[i]; q < M.rowptr[i + 1]; ++q) a += M.val[q] * x[M.col[q]];
+        y[i] = a;
     }
+}
+
+struct TailScratch {
+    std::vector<double> ax, g, y, ay, r, bc, xc;
+    TailScratch(int n, int m, int nc) : ax(n), g(m), y(m), ay(m), r(n), bc(nc), xc(nc) {}
+};
+
+// nu l1-Jacobi sweeps x <- x + dinv (b - A x)
+void host_sweeps(const TailLevel& L, int nu, const double* b, double* x, TailScratch& w) {
+    const int n = L.A.nrows;
+    for (int k = 0; k < nu; ++k) {
+        host_spmv(L.A, x, w.ax.data());
+        for (int i = 0; i < n; ++i) x[i] += L.dinv[i] * (b[i] - w.ax[i]);
+    }
+}
+
+// x <- x + D Mhat^{-1} (D^T b - (D^T A) x), Mhat^{-1}: nua sweeps on D^T A D from zero
+void host_aux(const TailLevel& L, int nua, const double* b, double* x, TailScratch& w) {
+    const int n = L.A.nrows, m = L.D.ncols;
+    if (nua <= 0 || m == 0) return;
+    host_spmv(L.Dt, b, w.g.data());
+    host_spmv(L.DtA, x, w.ay.data());
+    for (int i = 0; i < m; ++i) w.g[i] -= w.ay[i];
+    for (int i = 0; i < m; ++i) w.y[i] = L.dhinv[i] * w.g[i];
+    for (int k = 1; k < nua; ++k) {
+        host_spmv(L.Ah, w.y.data(), w.ay.data());
+        for (int i = 0; i < m; ++i) w.y[i] += L.dhinv[i] * (w.g[i] - w.ay[i]);
+    }
+    host_spmv(L.D, w.y.data(), w.ax.data());
+    for (int i = 0; i < n; ++i) x[i] += w.ax[i];
+}
+
+// x = V-cycle at level L applied to b, with the dense operator Bc (nc x nc) below
+void host_tail_vcycle(const TailLevel& L, int nu, int nua, const std::vector<double>& Bc, int nc,
+                      const double* b, double* x, TailScratch& w) {
+    const int n = L.A.nrows;
+    if (nu >= 1) {   // the first sweep from zero is dinv b
+        for (int i = 0; i < n; ++i) x[i] = L.dinv[i] * b[i];
+        host_sweeps(L, nu - 1, b, x, w);
+    } else {
+        std::fill(x, x + n, 0.0);
+    }
+    host_aux(L, nua, b, x, w);
+    host_spmv(L.A, x, w.ax.data());
+    for (int i = 0; i < n; ++i) w.r[i] = b[i] - w.ax[i];
+    host_spmv(L.Pt, w.r.data(), w.bc.data());
+    for (int i = 0; i < nc; ++i) {
+        double a = 0;
+        for (int j = 0; j < nc; ++j) a += Bc[(size_t)i * nc + j] * w.bc[j];
+        w.xc[i] = a;
+    }
+    host_spmv(L.P, w.xc.data(), w.ax.data());
+    for (int i = 0; i < n; ++i) x[i] += w.ax[i];
+    host_aux(L, nua, b, x, w);
+    host_sweeps(L, nu, b, x, w);
+}
+
+}  // namespace
+
+// tl: host copies of the levels that may be folded; ainv: the coarsest inverse (row-major)
+void fold_tail(amge_hierarchy* H, const std::vector<TailLevel>& tl, const std::vector<double>& ainv,
+               hipStream_t s) {
+    const int lim = H->opts.tail_rows, nl = (int)H->lv.size();
+    const int nu = H->opts.nu_primary, nua = H->opts.nu_aux;
+    int t = nl - 1, nb = H->nc;
+    std::vector<double> B = ainv;
+    while (lim > 0 && t >= 2 && H->lv[t - 1].n <= lim) {
+        const TailLevel& L = tl[t - 1];
+        const int n = L.A.nrows, m = L.D.ncols;
+        std::vector<double> Bl((size_t)n * n);
+        const int nthr = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+        std::vector<std::thread> pool;
+        for (int id = 0; id < nthr; ++id)
+            pool.emplace_back([&, id]() {
+                TailScratch w(n, m, nb);
+                std::vector<double> e(n, 0.0), x(n);
+                for (int i = id; i < n; i += nthr) {   // column i = B_l e_i
+                    e[i] = 1.0;
+                    host_tail_vcycle(L, nu, nua, B, nb, e.data(), x.data(), w);
+                    e[i] = 0.0;
+                    for (int j = 0; j < n; ++j) Bl[(size_t)j * n + i] = x[j];
+                }
+            });
+        for (std::thread& th : pool) th.join();
+        B.swap(Bl);
+        nb = n;
+        t -= 1;
+    }
+    if (t == nl - 1) return;
+    for (double v : B)
+        if (!std::isfinite(v)) fail(AMGE_ERR_NONFINITE, "non-finite folded coarse tail");
+    H->tail = t;
+    H->tail_n = nb;
+    H->tail_op = upload(H, B.data(), B.size(), s);
+    HIPCHECK(hipStreamSynchronize(s));
 }
 
 void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
@@ -944,12 +1034,14 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     HIPCHECK(hipHostGetDevicePointer((void**)&H->ring_dev, H->ring, 0));
     const bool batched = H->opts.max_rhs > 1;
     std::vector<HostLevel> hl(batched ? nl : 0);
+    std::vector<TailLevel> tl(nl);   // host copies of the levels that may be folded
+    std::vector<double> ainv;
     for (int k = 0; k < nl; ++k) {
         DLevel& L = H->lv[k];
         L.n = A[k].nrows;
         if (batched) hl[k].A = A[k];
         if (k == nl - 1) {
-            build_coarse(H, A[k], s);
+            build_coarse(H, A[k], s, ainv);
             std::vector<double> none;
             alloc_work<float>(H, L, L.w32, none, none, s);
             alloc_work<double>(H, L, L.w64, none, none, s);
@@ -967,6 +1059,18 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
             dinv[i] = 1.0 / d[i];
         }
         for (size_t i = 0; i < dh.size(); ++i) dhinv[i] = dh[i] > 0 ? 1.0 / dh[i] : 0.0;
+        if (k >= 1 && A[k].nrows <= H->opts.tail_rows) {
+            TailLevel& T = tl[k];
+            T.A = A[k];
+            T.D = D[k];
+            T.Dt = Dt;
+            T.DtA = DtA;
+            T.Ah = Ah;
+            T.P = P[k];
+            T.Pt = transpose(P[k]);
+            T.dinv = dinv;
+            T.dhinv = dhinv;
+        }
         L.A = upload_tuned(H, A[k], false, s);
         L.Ah = upload_tuned(H, Ah, false, s);
         L.P = upload_tuned(H, P[k], false, s);
@@ -1032,7 +1136,7 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     H->tail = nl - 1;
     H->tail_n = H->nc;
     H->tail_op = H->Ainv;
-    fold_tail(H, s);
+    fold_tail(H, tl, ainv, s);
     HIPCHECK(hipStreamSynchronize(s));
 }
 
