@@ -274,8 +274,17 @@ __device__ __forceinline__ void col_totals(const double* __restrict__ part, int 
     for (int qc = wave; qc < nq * NC; qc += nwaves) {
         if (qc % NC >= W) continue;   // idle columns beyond the active width
         const double* p = part + (int64_t)qc * nblk;
+        // lane-wise sums in index order, eight loads issued at a time
         double t = 0;
-        for (int i = lane; i < nblk; i += 64) t += p[i];
+        int i = lane;
+        for (; i + 7 * 64 < nblk; i += 8 * 64) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = p[i + u * 64];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t += v[u];
+        }
+        for (; i < nblk; i += 64) t += p[i];
         t = wave_sum(t);
         if (lane == 0) sh[qc] = t;
     }
