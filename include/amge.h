@@ -79,13 +79,13 @@ typedef struct {
                                0: chosen at set-up, 32 unless 2^-24 * kappa > 0.1, kappa
                                being the cancellation factor of amge_precision_info         */
     int32_t max_rhs;        /* largest nrhs the work buffers are sized for (>= 1)           */
-    int32_t tail_rows;      /* single-column V-cycle: while the level above the coarse tail
+    int32_t tail_rows;      /* coarse-tail folding: while the level above the coarse tail
                                (initially the coarsest level) is not the fine level and has
                                at most tail_rows rows, the V-cycle from that level down (a
                                fixed linear map: zero initial guess) is formed at set-up in
-                               FP64, one unit vector at a time, and applied in the solve as
-                               one dense FP64 product.  Same operator, fewer launches.
-                               0: off.  Batched V-cycles always run every level.          */
+                               FP64, one unit vector at a time, and applied in every V-cycle
+                               (single-column and batched) as one dense FP64 product.  Same
+                               operator, fewer launches.  0: off (0 <= tail_rows <= 8192). */
 } amge_opts;
 
 typedef struct amge_hierarchy amge_hierarchy;

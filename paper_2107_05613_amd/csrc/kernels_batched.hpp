@@ -165,11 +165,12 @@ k_sell_inc_mm_add(int nslices, int L, int NC, const int* __restrict__ sptr, cons
     acc.store(Y + (int64_t)row * NC + col);
 }
 
-// Coarsest level: X = Ainv B on the first W = 2^lgW of the NC = 2^lg stored columns;
-// FP64 arithmetic.  One block per row: thread t owns column t % NC and the terms
-// j = g, g + G, ... with g = t / NC, G = BLOCK / NC (summed in order), and the G partial
-// sums of a column are added in the order of g.  The layout depends on NC only, so a
-// column's result does not depend on W.
+// Dense FP64 operator (the coarsest inverse or the folded coarse tail): X = M B on the
+// first W = 2^lgW of the NC = 2^lg stored columns; FP64 arithmetic.  One block per row:
+// thread t owns column t % NC and the terms j = g, g + G, ... with g = t / NC,
+// G = BLOCK / NC (summed in order, eight terms' loads issued at a time), and the G
+// partial sums of a column are added in the order of g.  The layout depends on NC only,
+// so a column's result does not depend on W.
 template <typename T>
 __global__ void __launch_bounds__(BLOCK)
 k_coarse_mm(int n, int lgW, int lg, const double* __restrict__ Ainv, const T* __restrict__ B, T* __restrict__ X,
@@ -182,7 +183,18 @@ k_coarse_mm(int n, int lgW, int lg, const double* __restrict__ Ainv, const T* __
     double acc = 0;
     if (c < W) {
         const double* a = Ainv + (int64_t)row * n;
-        for (int j = g; j < n; j += G) acc = fma(a[j], (double)B[(int64_t)j * NC + c], acc);
+        int j = g;
+        for (; j + 7 * G < n; j += 8 * G) {
+            double av[8], bv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                av[u] = __builtin_nontemporal_load(a + j + u * G);
+                bv[u] = (double)B[(int64_t)(j + u * G) * NC + c];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = fma(av[u], bv[u], acc);
+        }
+        for (; j < n; j += G) acc = fma(__builtin_nontemporal_load(a + j), (double)B[(int64_t)j * NC + c], acc);
     }
     sh[threadIdx.x] = acc;
     __syncthreads();

@@ -656,10 +656,10 @@ inline int log2i(int v) {
 template <class T>
 void bvcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, int W, const int* stop,
                    hipStream_t s) {
-    const int nl = (int)H->lv.size();
     const int NC = H->NC;
-    if (l == nl - 1) {
-        if (H->nc) dev::k_coarse_mm<T><<<H->nc, BLOCK, 0, s>>>(H->nc, log2i(W), H->lgNC, H->Ainv, b, xout, stop);
+    if (l == H->tail) {   // the coarsest solve, or the folded coarse tail
+        if (H->tail_n)
+            dev::k_coarse_mm<T><<<H->tail_n, BLOCK, 0, s>>>(H->tail_n, log2i(W), H->lgNC, H->tail_op, b, xout, stop);
         return;
     }
     DLevel& L = H->lv[l];
@@ -669,7 +669,7 @@ void bvcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, i
     T* x = xout;
     T* xt = w.xt;
     const int nup = H->opts.nu_primary, nua = H->opts.nu_aux;
-    const bool next_coarsest = l + 1 == nl - 1;
+    const bool next_coarsest = l + 1 == H->tail;   // needs no first sweep of its own
     bprimary<T>(H, L, b, bd, x, xt, true, nup, W, stop, s);
     bauxiliary<T>(H, L, b, x, nua, W, stop, s);
     bmm<T>(L.bA, dev::RESID, W, NC, x, b, nullptr, w.r, stop, s);
@@ -1714,9 +1714,9 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
         const double sx = sv * nrhs;                       // one row of a vector block
         const int nup = h->opts.nu_primary, nua = h->opts.nu_aux;
         double tot = 0;
-        // levels run by their kernels: all but the coarsest (batched), or those above the
-        // dense tail (single column: the coarsest inverse or the folded coarse tail)
-        const size_t last = batched ? h->lv.size() - 1 : (size_t)h->tail;
+        // levels run by their kernels: those above the dense tail (the coarsest inverse or
+        // the folded coarse tail)
+        const size_t last = (size_t)h->tail;
         for (size_t k = 0; k < last; ++k) {
             const DLevel& L = h->lv[k];
             const double n = L.n, m = L.m, nc = h->lv[k + 1].n;
@@ -1748,7 +1748,7 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
             tot += mat(L.P, L.bP) + sx * (nc + 2 * n);
         }
         // the dense operator read once, the right-hand side and solution blocks
-        const double nd = batched ? h->nc : h->tail_n;
+        const double nd = h->tail_n;
         tot += 8.0 * nd * nd + 2 * sx * nd;
         *bytes = tot;
         return AMGE_OK;

@@ -99,6 +99,31 @@ def test_batched_vcycle(spec, nrhs):
 
 
 @pytest.mark.parametrize("spec,nrhs", SPECS[:2])
+def test_batched_folded_tail(spec, nrhs):
+    """The batched V-cycle applies the folded coarse tail as a dense block product; with
+    tail_rows = 0 it runs every level.  Both match the oracle column by column (FP64) and
+    agree to FP64 rounding, also in FP32."""
+    from paper_2107_05613_amd import amge
+    c = bcase(*spec)
+    B = W.rhs(c.n1, 12, nrhs)
+    Z = torch.zeros(c.n1 * nrhs, dtype=torch.float64, device="cuda")
+    for bits in (64, 32):
+        H0 = amge.Hierarchy(c.prod, precond_bits=bits, max_rhs=spec[-1], tail_rows=0)
+        H0.vcycle(dev(B), Z, nrhs=nrhs)
+        z0 = host(Z).reshape(c.n1, nrhs)
+        c.gpu[bits].vcycle(dev(B), Z, nrhs=nrhs)
+        zf = host(Z).reshape(c.n1, nrhs)
+        H0.close()
+        worst0 = max(relerr(z0[:, j], c.ml.vcycle(B[:, j])) for j in range(nrhs))
+        diff = relerr(zf, z0)
+        print(f"{spec} nrhs={nrhs} FP{bits}: unfolded vs oracle {worst0:.2e}, folded vs unfolded {diff:.2e}")
+        if bits == 64:
+            assert worst0 <= c.tol64 and diff <= c.tol64
+        else:
+            assert diff <= 1e-3
+
+
+@pytest.mark.parametrize("spec,nrhs", SPECS[:2])
 def test_batched_pcg_fp64(spec, nrhs):
     """a7 + a8: per-column inexact PCG in FP64; counts within +-1 of the oracle's, and the
     oracle's iterate after the same fixed count."""
