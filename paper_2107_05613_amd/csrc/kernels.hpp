@@ -30,6 +30,7 @@ enum Mode : int {
     SPMV_ADD = 1,  // y += A x
     RESID = 2,     // y = b - A x
     JAC = 3,       // y = x + dinv * (b - A x)
+    JAC0 = 4,      // batched only: JAC from x = dinv * b, formed where x is read
     SPLIT = 5,     // y = A [b; x]: the first lead entries of a row read b, the others x
 };
 

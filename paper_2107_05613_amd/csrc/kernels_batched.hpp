@@ -17,6 +17,10 @@
 namespace amge {
 namespace dev {
 
+// Product rounded on its own (never contracted into a following addition).
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+
 // V consecutive values of one row of a vector block, moved with 16-byte (or narrower)
 // vector loads and stores.
 template <typename T, int V> struct Vec;
@@ -93,6 +97,11 @@ k_sell_mm(int nslices, int L, int NC, const int* __restrict__ sptr, const int* _
         Pack<T, V> xv;
         if (MODE == SPLIT) {
             xv.load((k < nlead ? B : X) + (int64_t)j * NC + col);
+        } else if (MODE == JAC0) {   // x_j = dinv_j b_j, the product the producer of b would store
+            xv.load(B + (int64_t)j * NC + col);
+            const T dj = dinv[j];
+#pragma unroll
+            for (int i = 0; i < V; ++i) xv.v[i] = dj * xv.v[i];
         } else {
             xv.load(X + (int64_t)j * NC + col);
         }
@@ -120,6 +129,14 @@ k_sell_mm(int nslices, int L, int NC, const int* __restrict__ sptr, const int* _
         bv.load(B + o);
 #pragma unroll
         for (int i = 0; i < V; ++i) out.v[i] = bv.v[i] - acc.v[i];
+        out.store(Y + o);
+    } else if (MODE == JAC0) {
+        Pack<T, V> bv;
+        bv.load(B + o);
+        const T d = dinv[row];
+        // x0 = dinv b rounded on its own (not contracted into the update), as if stored
+#pragma unroll
+        for (int i = 0; i < V; ++i) out.v[i] = mul_rn(d, bv.v[i]) + d * (bv.v[i] - acc.v[i]);
         out.store(Y + o);
     } else {   // JAC
         Pack<T, V> bv, xv;

@@ -485,6 +485,7 @@ void bmm_m(const DSellB& M, int mode, int W, int NC, const T* X, const T* B, con
         case dev::SPMV_ADD: bmm_v<T, V, dev::SPMV_ADD>(M, W, NC, X, B, dinv, Y, YD, stop, s); break;
         case dev::RESID: bmm_v<T, V, dev::RESID>(M, W, NC, X, B, dinv, Y, YD, stop, s); break;
         case dev::JAC: bmm_v<T, V, dev::JAC>(M, W, NC, X, B, dinv, Y, YD, stop, s); break;
+        case dev::JAC0: bmm_v<T, V, dev::JAC0>(M, W, NC, X, B, dinv, Y, YD, stop, s); break;
         case dev::SPLIT:
             if (!M.lead) fail(AMGE_ERR_ARG, "split product on a matrix without split rows");
             bmm_v<T, V, dev::SPLIT>(M, W, NC, X, B, dinv, Y, YD, stop, s);
@@ -615,9 +616,12 @@ void bprimary(amge_hierarchy* H, DLevel& L, const T* b, const T* bd, T*& x, T*& 
     int k = 0;
     if (from_zero) {
         if (nu >= 2) {
-            bmm<T>(L.bA, dev::JAC, W, NC, bd, b, w.dinv, x, stop, s);
+            // bd = dinv b from the producer of b, or (bd null) formed by the sweep itself
+            if (bd) bmm<T>(L.bA, dev::JAC, W, NC, bd, b, w.dinv, x, stop, s);
+            else bmm<T>(L.bA, dev::JAC0, W, NC, nullptr, b, w.dinv, x, stop, s);
             k = 2;
         } else if (nu == 1) {
+            if (!bd) fail(AMGE_ERR_ARG, "one sweep from zero needs dinv b");
             bcopy<T>((int64_t)L.n * NC, bd, x, stop, s);
             k = 1;
         } else {
@@ -1375,10 +1379,15 @@ void bpcg_ap(amge_hierarchy* H, int W, hipStream_t s) {
 bool bz32(const amge_hierarchy* H) { return H->opts.precond_bits == 32 && H->lv.size() > 1; }
 
 // z = B r on the residual block in the preconditioner precision; writes zv.
+// With two or more primary sweeps the fine level's first launched sweep forms dinv r
+// itself (JAC0), so the PCG update does not store it.
+bool bpcg_fused_bd(const amge_hierarchy* H) { return H->lv.size() > 1 && H->opts.nu_primary >= 2; }
+
 void bpcg_precond(amge_hierarchy* H, int W, const int* stop, hipStream_t s) {
     DLevel& L = H->lv[0];
-    if (bz32(H)) bvcycle_level<float>(H, 0, L.bw32.b, L.bw32.bd, L.bw32.x, W, stop, s);
-    else bvcycle_level<double>(H, 0, H->bR, L.bw64.bd, H->bZv, W, stop, s);
+    const bool fused = bpcg_fused_bd(H);
+    if (bz32(H)) bvcycle_level<float>(H, 0, L.bw32.b, fused ? nullptr : L.bw32.bd, L.bw32.x, W, stop, s);
+    else bvcycle_level<double>(H, 0, H->bR, fused ? nullptr : L.bw64.bd, H->bZv, W, stop, s);
 }
 
 void bpcg_dots(amge_hierarchy* H, int W, hipStream_t s) {
@@ -1403,9 +1412,10 @@ void bpcg_iteration(amge_hierarchy* H, int W, hipStream_t s) {
     const unsigned g = grid_stride(nn);
     bpcg_ap(H, W, s);
     dev::k_bpcg_alpha<<<1, dev::FIN_BLOCK, 0, s>>>(W, H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
+    const bool fused = bpcg_fused_bd(H);
     dev::k_bpcg_xr<<<g, BLOCK, 0, s>>>(nn, lgW, H->lgNC, H->cs, H->bP, H->bQ, H->bX, H->bR,
-                                       f32 ? L.bw32.b : nullptr, f32 ? L.bw32.bd : nullptr,
-                                       f32 ? L.bw32.dinv : nullptr, !f32 && ml ? L.bw64.bd : nullptr,
+                                       f32 ? L.bw32.b : nullptr, f32 && !fused ? L.bw32.bd : nullptr,
+                                       f32 ? L.bw32.dinv : nullptr, !f32 && ml && !fused ? L.bw64.bd : nullptr,
                                        !f32 && ml ? L.bw64.dinv : nullptr, H->bs);
     bpcg_precond(H, W, &H->bs->all_done, s);
     bpcg_dots(H, W, s);
