@@ -353,10 +353,10 @@ k_bpcg_alpha(int W, int NC, const double* __restrict__ part, int nblk, ColState*
 // X += alpha P, R -= alpha Q per column; R32 = (float) R, RD32 = dinv32 * R32 (FP32
 // preconditioner) or RD64 = dinv64 * R (FP64 preconditioner).
 __global__ void __launch_bounds__(BLOCK)
-k_bpcg_xr(int64_t nn, int lgW, int lg, const ColState* __restrict__ cs, const double* __restrict__ P,
-          const double* __restrict__ Q, double* __restrict__ X, double* __restrict__ R, float* __restrict__ R32,
-          float* __restrict__ RD32, const float* __restrict__ dinv32, double* __restrict__ RD64,
-          const double* __restrict__ dinv64, const BatchStatus* __restrict__ bs) {
+k_bpcg_xr(int64_t nn, int lgW, int lg, const ColState* __restrict__ cs, const double* __restrict__ Q,
+          double* __restrict__ R, float* __restrict__ R32, float* __restrict__ RD32,
+          const float* __restrict__ dinv32, double* __restrict__ RD64, const double* __restrict__ dinv64,
+          const BatchStatus* __restrict__ bs) {
     if (bs->all_done) return;
     for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < nn; u += (int64_t)gridDim.x * BLOCK) {
         const int c = (int)(u & ((1 << lgW) - 1));
@@ -365,7 +365,6 @@ k_bpcg_xr(int64_t nn, int lgW, int lg, const ColState* __restrict__ cs, const do
         const double a = cs[c].alpha;
         double r = R[t];
         if (a != 0) {
-            X[t] = fma(a, P[t], X[t]);
             r = fma(-a, Q[t], r);
             R[t] = r;
         }
@@ -475,7 +474,7 @@ k_bpcg_update(int W, int NC, const double* __restrict__ part, int nblk, ColState
             brk |= flags[64 + j];
         }
         bs->it += 1;
-        bs->all_done = live == 0;
+        bs->all_done_next = live == 0;
         bs->any_breakdown = brk;
     }
 }
@@ -485,16 +484,28 @@ k_bpcg_update(int W, int NC, const double* __restrict__ part, int nblk, ColState
 template <typename TZ>
 __global__ void __launch_bounds__(BLOCK)
 k_bpcg_p(int64_t nn, int lgW, int lg, const ColState* __restrict__ cs, const TZ* __restrict__ Z,
-         double* __restrict__ P, const BatchStatus* __restrict__ bs) {
-    if (bs->all_done) return;
+         double* __restrict__ P, double* __restrict__ X, const BatchStatus* __restrict__ bs) {
+    if (bs->all_done) return;   // the value at the start of the iteration (see k_bpcg_finish)
     for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < nn; u += (int64_t)gridDim.x * BLOCK) {
         const int c = (int)(u & ((1 << lgW) - 1));
         const int64_t t = ((u >> lgW) << lg) + c;
         const ColState& s = cs[c];
         const double z = (double)Z[t];
+        const double p = P[t];
+        // the step of this iteration, taken with the p it used (alpha is 0 for a column
+        // that took none: idle, fresh, or stopped before the step)
+        if (s.alpha != 0) X[t] = fma(s.alpha, p, X[t]);
         if (s.pinit) P[t] = z;
-        else if (!s.done) P[t] = fma(s.beta, P[t], z);
+        else if (!s.done) P[t] = fma(s.beta, p, z);
     }
+}
+
+// Last kernel of a batched iteration: the stop flag computed by k_bpcg_update becomes
+// current (k_bpcg_p, which applies the iteration's step to X, must still run in the
+// iteration that finishes the last column).
+__global__ void k_bpcg_finish(BatchStatus* __restrict__ bs) {
+    if (bs->all_done) return;
+    bs->all_done = bs->all_done_next;
 }
 
 // Loads a block of right-hand sides (caller layout n x nrhs) as fresh columns: R = b,

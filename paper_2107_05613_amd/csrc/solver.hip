@@ -1413,7 +1413,7 @@ void bpcg_iteration(amge_hierarchy* H, int W, hipStream_t s) {
     bpcg_ap(H, W, s);
     dev::k_bpcg_alpha<<<1, dev::FIN_BLOCK, 0, s>>>(W, H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
     const bool fused = bpcg_fused_bd(H);
-    dev::k_bpcg_xr<<<g, BLOCK, 0, s>>>(nn, lgW, H->lgNC, H->cs, H->bP, H->bQ, H->bX, H->bR,
+    dev::k_bpcg_xr<<<g, BLOCK, 0, s>>>(nn, lgW, H->lgNC, H->cs, H->bQ, H->bR,
                                        f32 ? L.bw32.b : nullptr, f32 && !fused ? L.bw32.bd : nullptr,
                                        f32 ? L.bw32.dinv : nullptr, !f32 && ml && !fused ? L.bw64.bd : nullptr,
                                        !f32 && ml ? L.bw64.dinv : nullptr, H->bs);
@@ -1421,9 +1421,11 @@ void bpcg_iteration(amge_hierarchy* H, int W, hipStream_t s) {
     bpcg_dots(H, W, s);
     dev::k_bpcg_update<<<1, dev::FIN_BLOCK, 0, s>>>(W, H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
     if (f32)
-        dev::k_bpcg_p<float><<<g, BLOCK, 0, s>>>(nn, lgW, H->lgNC, H->cs, (const float*)H->bZ, H->bP, H->bs);
+        dev::k_bpcg_p<float><<<g, BLOCK, 0, s>>>(nn, lgW, H->lgNC, H->cs, (const float*)H->bZ, H->bP, H->bX,
+                                                 H->bs);
     else
-        dev::k_bpcg_p<double><<<g, BLOCK, 0, s>>>(nn, lgW, H->lgNC, H->cs, H->bZ, H->bP, H->bs);
+        dev::k_bpcg_p<double><<<g, BLOCK, 0, s>>>(nn, lgW, H->lgNC, H->cs, H->bZ, H->bP, H->bX, H->bs);
+    dev::k_bpcg_finish<<<1, 1, 0, s>>>(H->bs);
 }
 
 hipGraphExec_t capture_iteration(amge_hierarchy* H, int W) {

@@ -40,7 +40,7 @@ struct BatchStatus {
     int it;          // iterations run since the last load
     int all_done;    // no fresh or live column: every kernel of an iteration returns at once
     int any_breakdown;
-    int pad;
+    int all_done_next;   // all_done after the current iteration (made current by its last kernel)
 };
 
 }  // namespace dev
