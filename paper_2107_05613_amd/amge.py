@@ -204,7 +204,11 @@ def build_problem(kind, n, nlevels, alpha_hex, beta_hex):
 
 # ----------------------------------------------------------------------------- hierarchy
 class Hierarchy:
-    """Device-resident AMGe hierarchy (amge_setup_hierarchy)."""
+    """Device-resident AMGe hierarchy (amge_setup_hierarchy).
+
+    precond_bits: 32, 64 or 0 (chosen from the cancellation factor); max_rhs: widest
+    block for the batched path; tail_rows: levels of at most this many rows below the
+    fine one are folded into one dense FP64 operator (0: every level runs its kernels)."""
 
     def __init__(self, levels, nu_primary=2, nu_aux=2, precond_bits=32, max_rhs=1, tail_rows=2048, stream=None):
         L = len(levels)
