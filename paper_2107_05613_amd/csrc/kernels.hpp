@@ -182,7 +182,8 @@ k_sell_inc(int nslices, const int* __restrict__ sptr, const int* __restrict__ sr
 // n x W words (column | sign << 31), no padding and no slice layout: y = D x (ADD = 0)
 // or y += D x (ADD = 1), summed in entry order like k_sell_inc.  Thread t takes rows t,
 // t + S, ... (S = grid size), INC_ROWS of them per step with all their loads issued
-// before any is used, so a wave keeps several rows' loads in flight.
+// before any is used, so a wave keeps several rows' loads in flight.  The words are read
+// with non-temporal loads, like every fine-level operator but A_k.
 constexpr int INC_ROWS = 4;
 
 template <typename T, int W, int ADD>
@@ -207,7 +208,7 @@ k_inc_fixed(int n, const uint32_t* __restrict__ ent, const T* __restrict__ x, T*
 #pragma unroll
         for (int u = 0; u < R; ++u) {
 #pragma unroll
-            for (int k = 0; k < W; ++k) e[u][k] = ent[(r0 + u * S) * W + k];
+            for (int k = 0; k < W; ++k) e[u][k] = __builtin_nontemporal_load(ent + (r0 + u * S) * W + k);
             yr[u] = ADD ? y[r0 + u * S] : T(0);
         }
         T v[R][W];
@@ -225,7 +226,7 @@ k_inc_fixed(int n, const uint32_t* __restrict__ ent, const T* __restrict__ x, T*
         uint32_t e[W];
         T v[W];
 #pragma unroll
-        for (int k = 0; k < W; ++k) e[k] = ent[r0 * W + k];
+        for (int k = 0; k < W; ++k) e[k] = __builtin_nontemporal_load(ent + r0 * W + k);
 #pragma unroll
         for (int k = 0; k < W; ++k) v[k] = x[e[k] & 0x7fffffffu];
         const T acc = inc_row<T, W, ADD>(e, v);
@@ -363,7 +364,8 @@ k_pcg_xr(int n, const double* __restrict__ part_pq, const double* __restrict__ p
     }
     const double alpha = delta / pq;
     for (int i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
-        x[i] = fma(alpha, p[i], x[i]);
+        // x is used by this kernel only: streamed past the caches (non-temporal load and store)
+        __builtin_nontemporal_store(fma(alpha, p[i], __builtin_nontemporal_load(x + i)), x + i);
         const double ri = fma(-alpha, q[i], r[i]);
         r[i] = ri;
         if (r32) {
