@@ -1324,12 +1324,17 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
             else HIPCHECK(hipGraphLaunch(H->pexec[launched & 1], gs));
             HIPCHECK(hipEventRecord(H->pev[launched % amge_hierarchy::NPEV], gs));
         }
-        if (launched == seen) fail(AMGE_ERR_HIP, "PCG did not terminate");
+        if (launched == seen) {
+            finish();
+            fail(AMGE_ERR_HIP, "PCG did not terminate");
+        }
         HIPCHECK(hipEventSynchronize(H->pev[seen % amge_hierarchy::NPEV]));
         ++seen;
         const volatile dev::PcgRecord* rec = H->ring + seen % dev::PCG_RING;
-        if (rec->tag != (((uint64_t)epoch << 32) | (uint32_t)seen))
+        if (rec->tag != (((uint64_t)epoch << 32) | (uint32_t)seen)) {
+            finish();
             fail(AMGE_ERR_HIP, "PCG iteration record missing");
+        }
         std::atomic_thread_fence(std::memory_order_acquire);
         memcpy(&hs, (const void*)&rec->st, sizeof(hs));
         rel.push_back(hs.relres);
