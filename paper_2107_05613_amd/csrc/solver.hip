@@ -1313,9 +1313,7 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
     std::vector<double> rel(1, 1.0);
     int launched = 0, seen = 0;
     while (!hs.done) {
-        // timed runs keep the pairs of direct launches of the event-timed path: the host
-        // enqueues a pair, then waits for it, so the GPU never waits on the enqueue
-        // inside a timed launch
+        // timed runs launch the iterations directly, two at a time, and wait for each pair
         int upto = launched;
         if (!timed) upto = std::min(maxit, seen + pcg_lookahead(rel, rtol));
         else if (launched == seen) upto = std::min(maxit, seen + 2);
