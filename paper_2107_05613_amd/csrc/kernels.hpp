@@ -186,7 +186,7 @@ k_sell_inc(int nslices, const int* __restrict__ sptr, const int* __restrict__ sr
 // with non-temporal loads, like every fine-level operator but A_k.
 constexpr int INC_ROWS = 4;
 
-template <typename T, int W, int ADD>
+template <typename T, int W>
 __device__ __forceinline__ T inc_row(const uint32_t (&e)[W], const T (&v)[W]) {
     T acc = 0;
 #pragma unroll
@@ -218,7 +218,7 @@ k_inc_fixed(int n, const uint32_t* __restrict__ ent, const T* __restrict__ x, T*
             for (int k = 0; k < W; ++k) v[u][k] = x[e[u][k] & 0x7fffffffu];
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-            const T acc = inc_row<T, W, ADD>(e[u], v[u]);
+            const T acc = inc_row<T, W>(e[u], v[u]);
             y[r0 + u * S] = ADD ? yr[u] + acc : acc;
         }
     }
@@ -229,7 +229,7 @@ k_inc_fixed(int n, const uint32_t* __restrict__ ent, const T* __restrict__ x, T*
         for (int k = 0; k < W; ++k) e[k] = __builtin_nontemporal_load(ent + r0 * W + k);
 #pragma unroll
         for (int k = 0; k < W; ++k) v[k] = x[e[k] & 0x7fffffffu];
-        const T acc = inc_row<T, W, ADD>(e, v);
+        const T acc = inc_row<T, W>(e, v);
         y[r0] = ADD ? y[r0] + acc : acc;
     }
 }
