@@ -82,8 +82,9 @@ __device__ __forceinline__ T stream_load(const T* __restrict__ p) {
 // NT: non-temporal loads of the matrix streams (FP64 always; FP32 for the operators
 // other than A_k, so that A_k, used four times per V-cycle, stays in the last-level
 // cache between its uses: the fine-level FP32 sweep of the 64^3 H(curl) workload takes
-// 45 instead of 50 us).
-template <typename T, int K, int MODE, bool C16, bool NT>
+// 45 instead of 50 us).  UNR: entries per lane whose loads are issued together (8 for
+// the long rows of a large fine level, 4 otherwise).
+template <typename T, int K, int MODE, bool C16, bool NT, int UNR = 4>
 __global__ void __launch_bounds__(BLOCK)
 k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const int* __restrict__ ci,
        const uint16_t* __restrict__ c16, const int* __restrict__ cbase, const T* __restrict__ av,
@@ -128,7 +129,7 @@ k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, 
         dr = dinv[rw];
     }
     T acc = 0;
-#pragma unroll 4
+#pragma unroll UNR
     for (int k = 0; k < width; ++k) {
         const int j = col_at<C16, NT>(ci, c16, cb, e0 + k * 64);
         T xv;
@@ -309,8 +310,8 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 }
 
 // q = A p (FP64 sliced ELL) and partial sums of p.q.  NRED blocks, each over a
-// contiguous range of slices.
-template <int K, bool C16>
+// contiguous range of slices; UNR as in k_sell.
+template <int K, bool C16, int UNR = 4>
 __global__ void __launch_bounds__(BLOCK)
 k_pcg_ap(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const int* __restrict__ ci,
          const uint16_t* __restrict__ c16, const int* __restrict__ cbase, const double* __restrict__ av,
@@ -331,7 +332,7 @@ k_pcg_ap(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow
         const int e0 = base + lane;
         const double* v = av + e0;
         double acc = 0;
-#pragma unroll 4
+#pragma unroll UNR
         for (int k = 0; k < width; ++k)
             acc = fma(stream_load(v + k * 64), p[col_at<C16, false>(ci, c16, cb, e0 + k * 64)], acc);
         acc = row_sum<K>(acc);

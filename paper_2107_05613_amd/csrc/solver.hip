@@ -46,6 +46,10 @@ DSell upload_sell(amge_hierarchy* H, const Csr& A, bool incidence, int K, hipStr
     d.K = K;
     d.nslices = h.nslices;
     d.stored = h.sptr[h.nslices];
+    // one lane per row with long rows on a large level (the fine A_k): eight entries'
+    // loads in flight per lane (measured on the 64^3 H(curl) fine level: FP32 sweep 40.8
+    // -> 38.4 us, FP64 83.5 -> 77.9 us; four stay better for short rows and small levels)
+    d.deep = !incidence && K == 1 && A.nrows >= (1 << 20) && A.nnz() >= 12 * (int64_t)A.nrows;
     d.sptr = upload(H, h.sptr.data(), h.sptr.size(), s);
     d.srow = upload(H, h.srow.data(), h.srow.size(), s);
     if (incidence) {
@@ -74,15 +78,15 @@ template <class T> const T* vals(const DSell& M);
 template <> const float* vals<float>(const DSell& M) { return M.v32; }
 template <> const double* vals<double>(const DSell& M) { return M.v64; }
 
-template <class T, int K>
-void sell_k(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* y, T* yd, hipStream_t s,
-            const int* stop) {
+template <class T, int K, int UNR>
+void sell_ku(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* y, T* yd, hipStream_t s,
+             const int* stop) {
     unsigned g = grid_slices(M.nslices);
     if (g == 0) return;
     const T* v = vals<T>(M);
-#define AMGE_SELL(MODE, C16, NT)                                                                          \
-    dev::k_sell<T, K, MODE, C16, NT><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ci, M.c16, M.cbase, v, x, \
-                                                         b, dinv, y, yd, M.lead, stop)
+#define AMGE_SELL(MODE, C16, NT)                                                                         \
+    dev::k_sell<T, K, MODE, C16, NT, UNR><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ci, M.c16, M.cbase, v, \
+                                                              x, b, dinv, y, yd, M.lead, stop)
 #define AMGE_SELL_MODES(C16, NT)                                    \
     switch (mode) {                                                 \
         case dev::SPMV: AMGE_SELL(dev::SPMV, C16, NT); break;       \
@@ -98,6 +102,18 @@ void sell_k(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* 
     }
 #undef AMGE_SELL_MODES
 #undef AMGE_SELL
+}
+
+template <class T, int K>
+void sell_k(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* y, T* yd, hipStream_t s,
+            const int* stop) {
+    if constexpr (K == 1) {
+        if (M.deep) {
+            sell_ku<T, 1, 8>(M, mode, x, b, dinv, y, yd, s, stop);
+            return;
+        }
+    }
+    sell_ku<T, K, 4>(M, mode, x, b, dinv, y, yd, s, stop);
 }
 
 // mode as in dev::Mode (SPLIT needs a matrix with split rows); yd (SPMV, SPLIT) receives
@@ -1145,15 +1161,26 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ PCG
-template <int K>
-void pcg_ap_k(amge_hierarchy* H, hipStream_t s) {
+template <int K, int UNR>
+void pcg_ap_ku(amge_hierarchy* H, hipStream_t s) {
     const DSell& A = H->lv[0].A;
     if (A.c16)
-        dev::k_pcg_ap<K, true><<<dev::NRED, BLOCK, 0, s>>>(A.nslices, A.sptr, A.srow, A.ci, A.c16, A.cbase, A.v64,
-                                                           H->p, H->q, H->part_pq, H->flags);
+        dev::k_pcg_ap<K, true, UNR><<<dev::NRED, BLOCK, 0, s>>>(A.nslices, A.sptr, A.srow, A.ci, A.c16, A.cbase,
+                                                                A.v64, H->p, H->q, H->part_pq, H->flags);
     else
-        dev::k_pcg_ap<K, false><<<dev::NRED, BLOCK, 0, s>>>(A.nslices, A.sptr, A.srow, A.ci, A.c16, A.cbase, A.v64,
-                                                            H->p, H->q, H->part_pq, H->flags);
+        dev::k_pcg_ap<K, false, UNR><<<dev::NRED, BLOCK, 0, s>>>(A.nslices, A.sptr, A.srow, A.ci, A.c16, A.cbase,
+                                                                 A.v64, H->p, H->q, H->part_pq, H->flags);
+}
+
+template <int K>
+void pcg_ap_k(amge_hierarchy* H, hipStream_t s) {
+    if constexpr (K == 1) {
+        if (H->lv[0].A.deep) {
+            pcg_ap_ku<1, 8>(H, s);
+            return;
+        }
+    }
+    pcg_ap_ku<K, 4>(H, s);
 }
 
 void launch_pcg_ap(amge_hierarchy* H, hipStream_t s) {
