@@ -10,7 +10,9 @@
  *     l1-Jacobi sweeps on A_k, then l1-Jacobi sweeps on the auxiliary matrix
  *     D_k^T A_k D_k with the correction mapped back through D_k; the
  *     post-smoother applies the two steps in reverse order;
- *   - the coarsest level is solved exactly (dense FP64 Cholesky);
+ *   - the coarsest level is solved exactly (dense FP64 Cholesky); the small levels
+ *     just above it may be folded with it into one dense FP64 operator formed at
+ *     set-up (the same linear map; opts.tail_rows);
  *   - the outer iteration is inexact PCG (section 5.1) stopped on the residual
  *     measured in the preconditioner norm.
  *
