@@ -233,11 +233,16 @@ def run_serving(args):
     iters = [v[1] for v in done2.values()]
     print(f"[bench] serving open loop at {rate:.1f}/s: p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms",
           file=sys.stderr, flush=True)
+    mix_desc = {"requests": mix.requests, "keys": len(mix.keys),
+                "setup_s": {"build": mix.build_s, "device_setup": mix.setup_s}}
     srv.close()
+    del mix
+    torch.cuda.synchronize()
+    grouped = run_grouped_ab()
     out = {
-        "workload": (f"{len(mix.requests)} seeded requests, H(curl)/H(div) on n^3x6 Kuhn tets with n in "
+        "workload": (f"{len(mix_desc['requests'])} seeded requests, H(curl)/H(div) on n^3x6 Kuhn tets with n in "
                      f"{{16,24,32,48,64}} drawn uniformly, per-4^3-block coefficient jumps 10^U(-3,3) from a pool "
-                     f"of 2 seeds per (type, n): {len(mix.keys)} resident hierarchies, 8 PCG columns each; "
+                     f"of 2 seeds per (type, n): {mix_desc['keys']} resident hierarchies, 8 PCG columns each; "
                      f"V-cycle precision per hierarchy from its cancellation factor, per-column FP64 PCG "
                      f"to rel-res 1e-8"),
         "precision": {"fp32_hierarchies": n32, "fp64_hierarchies": len(prec) - n32,
@@ -248,10 +253,34 @@ def run_serving(args):
         "open_loop": {"arrival_rate_per_s": rate, "solves_per_s": len(done2) / makespan2, **st},
         "iters": [int(min(iters)), int(max(iters))],
         "failed_requests": bad,
-        "setup_s": {"build": mix.build_s, "device_setup": mix.setup_s},
+        "setup_s": mix_desc["setup_s"],
+        "grouped_launches": grouped,
     }
-    del mix
-    torch.cuda.synchronize()
+    return out
+
+
+def run_grouped_ab():
+    """Solo streams vs the grouped ensemble on 16 resident 16^3 hierarchies (both types,
+    8 coefficient fields), 128 requests at once, 8 columns each."""
+    from paper_2107_05613_amd import serve
+    mix = serve.build_mix(num=128, seed=0, sizes=(16,), coef_pool=8, slots=8, precond_bits=0)
+    first = {}
+    for j, h in enumerate(mix.hid_of):
+        first.setdefault(h, j)
+    out = {"workload": f"{len(mix.requests)} requests at once on {len(mix.keys)} resident 16^3 hierarchies "
+                       f"(H(curl)/H(div), 8 coefficient-jump fields each), 8 columns each"}
+    for name, gmax in (("solo", 0), ("grouped", 16)):
+        srv, ids = serve.make_server(mix, chunk=8, grouped_max_n=gmax)
+        serve.run(srv, ids, mix, order=list(first.values()))
+        done, lat, mk = serve.run(srv, ids, mix)
+        members, launches, solo_launches = srv.ensemble()
+        srv.close()
+        r = {"solves_per_s": len(done) / mk, **serve.latency_stats(lat),
+             "failed_requests": sum(1 for v in done.values() if v[0] != 0)}
+        if gmax:
+            r.update(members=members, kernels_per_iteration=launches, kernels_alone=solo_launches)
+        out[name] = r
+        print(f"[bench] {name} small-hierarchy burst: {r['solves_per_s']:.1f} solves/s", file=sys.stderr, flush=True)
     return out
 
 

@@ -75,6 +75,8 @@ def _load():
         "amge_server_create": (i32, [C.c_size_t, C.c_size_t, i32, C.POINTER(vp)]),
         "amge_server_destroy": (None, [vp]),
         "amge_server_add": (i32, [vp, vp, C.POINTER(i32)]),
+        "amge_server_add_grouped": (i32, [vp, vp, C.POINTER(i32)]),
+        "amge_server_ensemble": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "amge_server_request_bytes": (i32, [vp, i32, C.POINTER(C.c_size_t)]),
         "amge_server_submit": (i32, [vp, i32, vp, vp, f64, i32, i32, C.c_int64, vp]),
         "amge_server_progress": (i32, [vp, i32, C.POINTER(CompletionC), i32, C.POINTER(i32)]),
@@ -95,8 +97,9 @@ EXPORTS = ("amge_default_opts", "amge_setup_hierarchy", "amge_destroy", "amge_fo
            "amge_pcg_solve", "amge_level_apply", "amge_hierarchy_info", "amge_precision_info", "amge_last_error",
            "amge_timing_enable", "amge_timing_read", "amge_vcycle_bytes",
            "amge_kuhn_build", "amge_problem_nlevels", "amge_problem_levels", "amge_problem_free",
-           "amge_server_create", "amge_server_destroy", "amge_server_add", "amge_server_request_bytes",
-           "amge_server_submit", "amge_server_progress", "amge_server_stats")
+           "amge_server_create", "amge_server_destroy", "amge_server_add", "amge_server_add_grouped",
+           "amge_server_ensemble", "amge_server_request_bytes", "amge_server_submit", "amge_server_progress",
+           "amge_server_stats")
 
 
 def lib():
@@ -321,9 +324,11 @@ class Server:
         except Exception:
             pass
 
-    def add(self, H: "Hierarchy") -> int:
+    def add(self, H: "Hierarchy", grouped=False) -> int:
+        """grouped: H joins the ensemble, whose members' iterations share grouped launches."""
         i = C.c_int32()
-        _check(_lib.amge_server_add(self._h, H.handle, C.byref(i)))
+        add = _lib.amge_server_add_grouped if grouped else _lib.amge_server_add
+        _check(add(self._h, H.handle, C.byref(i)))
         self._rows.append(H.rows[0])
         self._hier.append(H)
         return i.value
@@ -349,6 +354,12 @@ class Server:
                 out.append((c.tag, c.hierarchy, c.status, c.iters, c.relres))
             if k.value < self._cap:
                 return out
+
+    def ensemble(self):
+        """(members, kernels per grouped iteration, kernels of the members' own iterations)."""
+        m, k, k1 = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(_lib.amge_server_ensemble(self._h, C.byref(m), C.byref(k), C.byref(k1)))
+        return m.value, k.value, k1.value
 
     def stats(self):
         q, f = C.c_int32(), C.c_int32()

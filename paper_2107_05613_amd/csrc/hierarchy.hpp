@@ -165,4 +165,11 @@ namespace amge {
 // One batched PCG iteration on the first W columns (W a power of two <= NC) of a
 // hierarchy, captured as a HIP graph on its own stream on first use.
 hipGraphExec_t capture_iteration(amge_hierarchy* H, int W);
+
+// One batched PCG iteration of every hierarchy of hs (all NC columns of each), with the
+// same level operator of several hierarchies run in one grouped launch, captured as one
+// graph on stream s.  Every hierarchy computes exactly what its own captured iteration
+// computes.  launches / solo_launches: kernels in the graph / in the separate graphs.
+hipGraphExec_t capture_grouped_iteration(const std::vector<amge_hierarchy*>& hs, hipStream_t s, int* launches,
+                                         int* solo_launches);
 }  // namespace amge

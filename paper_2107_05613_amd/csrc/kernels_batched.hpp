@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "grouped.hpp"
 #include "kernels.hpp"
 
 namespace amge {
@@ -64,13 +65,13 @@ struct Pack {
 // entries of those slots are consecutive (coalesced), each broadcast to the L lanes of
 // its row.  Every column sums its row's entries in CSR order whatever W, L and V are.
 // Modes as in Mode (kernels.hpp); YD (SPMV, SPLIT) also receives dinv * y.
-template <typename T, int V, int MODE, bool C16>
-__global__ void __launch_bounds__(BLOCK)
-k_sell_mm(int nslices, int L, int NC, const int* __restrict__ sptr, const int* __restrict__ srow,
+template <typename T, int V, int MODE, bool C16, class G>
+__device__ __forceinline__ void
+sell_mm(G g, int nslices, int L, int NC, const int* __restrict__ sptr, const int* __restrict__ srow,
           const int* __restrict__ ci, const uint16_t* __restrict__ c16, const int* __restrict__ cbase,
           const T* __restrict__ av, const T* __restrict__ X, const T* __restrict__ B, const T* __restrict__ dinv,
           T* __restrict__ Y, T* __restrict__ YD, const uint16_t* __restrict__ lead, const int* __restrict__ stop) {
-    const int gw = xcd_block(blockIdx.x, gridDim.x) * WAVES + ((int)threadIdx.x >> 6);
+    const int gw = xcd_block(g.bid(), g.nb()) * WAVES + ((int)threadIdx.x >> 6);
     const int slice = gw / L;
     const int lane = threadIdx.x & 63;
     const int rr = (gw % L) * (64 / L) + lane / L;
@@ -149,14 +150,23 @@ k_sell_mm(int nslices, int L, int NC, const int* __restrict__ sptr, const int* _
     }
 }
 
+// Launch tags of the batched bodies: block size, the solo signature, the body.
+template <typename T, int V, int MODE, bool C16>
+struct SellMM {
+    static constexpr int block = BLOCK;
+    using sig = decltype(&sell_mm<T, V, MODE, C16, HwGrid>);
+    template <class G, class... A>
+    __device__ static void run(G g, A... a) { sell_mm<T, V, MODE, C16>(g, a...); }
+};
+
 // Y += D X for a signed incidence in the same layout (index-only entries, bit 31 =
 // sign, padding 0xffffffff).
-template <typename T, int V>
-__global__ void __launch_bounds__(BLOCK)
-k_sell_inc_mm_add(int nslices, int L, int NC, const int* __restrict__ sptr, const int* __restrict__ srow,
-                  const uint32_t* __restrict__ ent, const T* __restrict__ X, T* __restrict__ Y,
-                  const int* __restrict__ stop) {
-    const int gw = xcd_block(blockIdx.x, gridDim.x) * WAVES + ((int)threadIdx.x >> 6);
+template <typename T, int V, class G>
+__device__ __forceinline__ void
+sell_inc_mm_add(G g, int nslices, int L, int NC, const int* __restrict__ sptr, const int* __restrict__ srow,
+                const uint32_t* __restrict__ ent, const T* __restrict__ X, T* __restrict__ Y,
+                const int* __restrict__ stop) {
+    const int gw = xcd_block(g.bid(), g.nb()) * WAVES + ((int)threadIdx.x >> 6);
     const int slice = gw / L;
     const int lane = threadIdx.x & 63;
     const int rr = (gw % L) * (64 / L) + lane / L;
@@ -182,20 +192,28 @@ k_sell_inc_mm_add(int nslices, int L, int NC, const int* __restrict__ sptr, cons
     acc.store(Y + (int64_t)row * NC + col);
 }
 
+template <typename T, int V>
+struct IncMMAdd {
+    static constexpr int block = BLOCK;
+    using sig = decltype(&sell_inc_mm_add<T, V, HwGrid>);
+    template <class G, class... A>
+    __device__ static void run(G g, A... a) { sell_inc_mm_add<T, V>(g, a...); }
+};
+
 // Dense FP64 operator (the coarsest inverse or the folded coarse tail): X = M B on the
 // first W = 2^lgW of the NC = 2^lg stored columns; FP64 arithmetic.  One block per row:
 // thread t owns column t % NC and the terms j = g, g + G, ... with g = t / NC,
 // G = BLOCK / NC (summed in order, eight terms' loads issued at a time), and the G
 // partial sums of a column are added in the order of g.  The layout depends on NC only,
 // so a column's result does not depend on W.
-template <typename T>
-__global__ void __launch_bounds__(BLOCK)
-k_coarse_mm(int n, int lgW, int lg, const double* __restrict__ Ainv, const T* __restrict__ B, T* __restrict__ X,
-            const int* __restrict__ stop) {
+template <typename T, class Grid>
+__device__ __forceinline__ void
+coarse_mm(Grid gr, int n, int lgW, int lg, const double* __restrict__ Ainv, const T* __restrict__ B,
+          T* __restrict__ X, const int* __restrict__ stop) {
     __shared__ double sh[BLOCK];
     const int stopped = *stop;   // tested before the store: its load overlaps the product
     const int NC = 1 << lg, W = 1 << lgW, G = BLOCK >> lg;
-    const int row = blockIdx.x;
+    const int row = gr.bid();
     const int c = threadIdx.x & (NC - 1), g = threadIdx.x >> lg;
     double acc = 0;
     if (c < W) {
@@ -222,16 +240,25 @@ k_coarse_mm(int n, int lgW, int lg, const double* __restrict__ Ainv, const T* __
     }
 }
 
+template <typename T>
+struct CoarseMM {
+    static constexpr int block = BLOCK;
+    using sig = decltype(&coarse_mm<T, HwGrid>);
+    template <class G, class... A>
+    __device__ static void run(G g, A... a) { coarse_mm<T>(g, a...); }
+};
+
 // ---------------------------------------------------------------- batched PCG
 // Per-column partial sums over the rows of a block: the block's threads hold column
 // (tid % NC) sums for row group tid / NC; reduced over row groups through LDS.
-__device__ __forceinline__ void column_partials(double v, int W, int NC, double* sh, double* part, int nblk) {
+__device__ __forceinline__ void column_partials(double v, int W, int NC, double* sh, double* part, int nblk,
+                                                unsigned bid) {
     sh[threadIdx.x] = v;
     __syncthreads();
     if ((int)threadIdx.x < W) {
         double t = 0;
         for (int g = threadIdx.x; g < BLOCK; g += NC) t += sh[g];
-        part[(int64_t)threadIdx.x * nblk + blockIdx.x] = t;
+        part[(int64_t)threadIdx.x * nblk + bid] = t;
     }
     __syncthreads();
 }
@@ -240,9 +267,9 @@ __device__ __forceinline__ void column_partials(double v, int W, int NC, double*
 // column.  Every block owns a contiguous range of slices; its threads are laid out for
 // all NC columns (L = NC / V lanes per row, V columns each), so every column's sums run
 // in the same order whatever the active width W is; lanes of columns >= W do no work.
-template <int V, bool C16>
-__global__ void __launch_bounds__(BLOCK)
-k_bpcg_ap(int nslices, int W, int NC, const int* __restrict__ sptr, const int* __restrict__ srow,
+template <int V, bool C16, class G>
+__device__ __forceinline__ void
+bpcg_ap(G gr, int nslices, int W, int NC, const int* __restrict__ sptr, const int* __restrict__ srow,
           const int* __restrict__ ci, const uint16_t* __restrict__ c16, const int* __restrict__ cbase,
           const double* __restrict__ av, const double* __restrict__ P, double* __restrict__ Q,
           double* __restrict__ part, const BatchStatus* __restrict__ bs) {
@@ -251,8 +278,8 @@ k_bpcg_ap(int nslices, int W, int NC, const int* __restrict__ sptr, const int* _
     const int L = NC / V, rpb = BLOCK / L;   // rpb: row slots per step (a multiple of 64 / L)
     const int g = (int)threadIdx.x / L, col = ((int)threadIdx.x % L) * V;
     const bool active = col < W;
-    const int per = (nslices + (int)gridDim.x - 1) / (int)gridDim.x;
-    const int s0 = xcd_block(blockIdx.x, gridDim.x) * per;
+    const int per = (nslices + (int)gr.nb() - 1) / (int)gr.nb();
+    const int s0 = xcd_block(gr.bid(), gr.nb()) * per;
     const int s1 = min(nslices, s0 + per);
     Pack<double, V> dot;
 #pragma unroll
@@ -290,9 +317,17 @@ k_bpcg_ap(int nslices, int W, int NC, const int* __restrict__ sptr, const int* _
     if ((int)threadIdx.x < W) {
         double t = 0;
         for (int q = 0; q < rpb; ++q) t += sh[q * NC + threadIdx.x];
-        part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+        part[(int64_t)threadIdx.x * gr.nb() + gr.bid()] = t;
     }
 }
+
+template <int V, bool C16>
+struct BpcgAp {
+    static constexpr int block = BLOCK;
+    using sig = decltype(&bpcg_ap<V, C16, HwGrid>);
+    template <class G, class... A>
+    __device__ static void run(G g, A... a) { bpcg_ap<V, C16>(g, a...); }
+};
 
 // Per-column totals of nq quantities from their block partials, stored at
 // part[(q * NC + c) * nblk + block]: one wave per (q, c), fixed summation order
@@ -325,8 +360,9 @@ constexpr int FIN_BLOCK = 1024;
 
 // alpha_c = delta_c / pq_c for live columns (breakdown if pq_c <= 0); fresh and idle
 // columns take no step.  One block.
-__global__ void __launch_bounds__(FIN_BLOCK)
-k_bpcg_alpha(int W, int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
+template <class G>
+__device__ __forceinline__ void
+bpcg_alpha(G, int W, int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
              BatchStatus* __restrict__ bs) {
     __shared__ double sh[64];
     if (bs->all_done) return;
@@ -350,15 +386,23 @@ k_bpcg_alpha(int W, int NC, const double* __restrict__ part, int nblk, ColState*
     }
 }
 
+struct BpcgAlpha {
+    static constexpr int block = FIN_BLOCK;
+    using sig = decltype(&bpcg_alpha<HwGrid>);
+    template <class G, class... A>
+    __device__ static void run(G g, A... a) { bpcg_alpha(g, a...); }
+};
+
 // X += alpha P, R -= alpha Q per column; R32 = (float) R, RD32 = dinv32 * R32 (FP32
 // preconditioner) or RD64 = dinv64 * R (FP64 preconditioner).
-__global__ void __launch_bounds__(BLOCK)
-k_bpcg_xr(int64_t nn, int lgW, int lg, const ColState* __restrict__ cs, const double* __restrict__ Q,
+template <class G>
+__device__ __forceinline__ void
+bpcg_xr(G g, int64_t nn, int lgW, int lg, const ColState* __restrict__ cs, const double* __restrict__ Q,
           double* __restrict__ R, float* __restrict__ R32, float* __restrict__ RD32,
           const float* __restrict__ dinv32, double* __restrict__ RD64, const double* __restrict__ dinv64,
           const BatchStatus* __restrict__ bs) {
     if (bs->all_done) return;
-    for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < nn; u += (int64_t)gridDim.x * BLOCK) {
+    for (int64_t u = (int64_t)g.bid() * BLOCK + threadIdx.x; u < nn; u += (int64_t)g.nb() * BLOCK) {
         const int c = (int)(u & ((1 << lgW) - 1));
         const int64_t row = u >> lgW;
         const int64_t t = (row << lg) + c;
@@ -377,18 +421,25 @@ k_bpcg_xr(int64_t nn, int lgW, int lg, const ColState* __restrict__ cs, const do
     }
 }
 
+struct BpcgXr {
+    static constexpr int block = BLOCK;
+    using sig = decltype(&bpcg_xr<HwGrid>);
+    template <class G, class... A>
+    __device__ static void run(G g, A... a) { bpcg_xr(g, a...); }
+};
+
 // Z = Zv after using the old Z: partials of r.z_new, r.z_old, r.r per column.  Z has the
 // preconditioner's precision (an FP32 z is exact in FP32), sums are FP64.
-template <typename TZ>
-__global__ void __launch_bounds__(BLOCK)
-k_bpcg_dots(int n, int W, int NC, const TZ* __restrict__ Zv, TZ* __restrict__ Z, const double* __restrict__ R,
+template <typename TZ, class G>
+__device__ __forceinline__ void
+bpcg_dots(G g, int n, int W, int NC, const TZ* __restrict__ Zv, TZ* __restrict__ Z, const double* __restrict__ R,
             double* __restrict__ part, const BatchStatus* __restrict__ bs) {
     __shared__ double sh[BLOCK];
     if (bs->all_done) return;
     const int rpb = BLOCK / NC;
     const int c = threadIdx.x % NC;   // layout of all NC columns; columns >= W idle
     double a = 0, b = 0, d = 0;
-    for (int row = blockIdx.x * rpb + threadIdx.x / NC; c < W && row < n; row += gridDim.x * rpb) {
+    for (int row = g.bid() * rpb + threadIdx.x / NC; c < W && row < n; row += g.nb() * rpb) {
         const int64_t t = (int64_t)row * NC + c;
         const TZ znv = Zv[t];
         const double zn = (double)znv, zo = (double)Z[t], r = R[t];
@@ -397,17 +448,26 @@ k_bpcg_dots(int n, int W, int NC, const TZ* __restrict__ Zv, TZ* __restrict__ Z,
         b = fma(r, zo, b);
         d = fma(r, r, d);
     }
-    const int nb = gridDim.x;
-    column_partials(a, W, NC, sh, part, nb);
-    column_partials(b, W, NC, sh, part + (int64_t)NC * nb, nb);
-    column_partials(d, W, NC, sh, part + (int64_t)2 * NC * nb, nb);
+    const int nb = g.nb();
+    column_partials(a, W, NC, sh, part, nb, g.bid());
+    column_partials(b, W, NC, sh, part + (int64_t)NC * nb, nb, g.bid());
+    column_partials(d, W, NC, sh, part + (int64_t)2 * NC * nb, nb, g.bid());
 }
+
+template <typename TZ>
+struct BpcgDots {
+    static constexpr int block = BLOCK;
+    using sig = decltype(&bpcg_dots<TZ, HwGrid>);
+    template <class G, class... A>
+    __device__ static void run(G g, A... a) { bpcg_dots<TZ>(g, a...); }
+};
 
 // Per-column stopping test and beta (one block).  A fresh column takes its initial
 // quantities here (delta0 = r.z0, ||b||) and becomes live; a zero right-hand side is
 // finished with 0 steps.
-__global__ void __launch_bounds__(FIN_BLOCK)
-k_bpcg_update(int W, int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
+template <class G>
+__device__ __forceinline__ void
+bpcg_update(G, int W, int NC, const double* __restrict__ part, int nblk, ColState* __restrict__ cs,
               BatchStatus* __restrict__ bs) {
     __shared__ double sh[3 * 64];
     __shared__ int flags[2 * 64];
@@ -479,14 +539,21 @@ k_bpcg_update(int W, int NC, const double* __restrict__ part, int nblk, ColState
     }
 }
 
+struct BpcgUpdate {
+    static constexpr int block = FIN_BLOCK;
+    using sig = decltype(&bpcg_update<HwGrid>);
+    template <class G, class... A>
+    __device__ static void run(G g, A... a) { bpcg_update(g, a...); }
+};
+
 // P = Z + beta P for live columns; P = Z for a column that has just taken its initial
 // quantities.
-template <typename TZ>
-__global__ void __launch_bounds__(BLOCK)
-k_bpcg_p(int64_t nn, int lgW, int lg, const ColState* __restrict__ cs, const TZ* __restrict__ Z,
+template <typename TZ, class G>
+__device__ __forceinline__ void
+bpcg_p(G g, int64_t nn, int lgW, int lg, const ColState* __restrict__ cs, const TZ* __restrict__ Z,
          double* __restrict__ P, double* __restrict__ X, const BatchStatus* __restrict__ bs) {
-    if (bs->all_done) return;   // the value at the start of the iteration (see k_bpcg_finish)
-    for (int64_t u = (int64_t)blockIdx.x * BLOCK + threadIdx.x; u < nn; u += (int64_t)gridDim.x * BLOCK) {
+    if (bs->all_done) return;   // the value at the start of the iteration (see bpcg_finish)
+    for (int64_t u = (int64_t)g.bid() * BLOCK + threadIdx.x; u < nn; u += (int64_t)g.nb() * BLOCK) {
         const int c = (int)(u & ((1 << lgW) - 1));
         const int64_t t = ((u >> lgW) << lg) + c;
         const ColState& s = cs[c];
@@ -500,13 +567,29 @@ k_bpcg_p(int64_t nn, int lgW, int lg, const ColState* __restrict__ cs, const TZ*
     }
 }
 
-// Last kernel of a batched iteration: the stop flag computed by k_bpcg_update becomes
-// current (k_bpcg_p, which applies the iteration's step to X, must still run in the
-// iteration that finishes the last column).
-__global__ void k_bpcg_finish(BatchStatus* __restrict__ bs) {
+template <typename TZ>
+struct BpcgP {
+    static constexpr int block = BLOCK;
+    using sig = decltype(&bpcg_p<TZ, HwGrid>);
+    template <class G, class... A>
+    __device__ static void run(G g, A... a) { bpcg_p<TZ>(g, a...); }
+};
+
+// Last kernel of a batched iteration (one thread): the stop flag computed by
+// bpcg_update becomes current (bpcg_p, which applies the iteration's step to X, must
+// still run in the iteration that finishes the last column).
+template <class G>
+__device__ __forceinline__ void bpcg_finish(G, BatchStatus* __restrict__ bs) {
     if (bs->all_done) return;
     bs->all_done = bs->all_done_next;
 }
+
+struct BpcgFinish {
+    static constexpr int block = 1;
+    using sig = decltype(&bpcg_finish<HwGrid>);
+    template <class G, class... A>
+    __device__ static void run(G g, A... a) { bpcg_finish(g, a...); }
+};
 
 // Loads a block of right-hand sides (caller layout n x nrhs) as fresh columns: R = b,
 // X = P = 0; columns nrhs..NC-1 are idle and zero.
@@ -564,19 +647,34 @@ k_unpack(int64_t n, int nrhs, int lg, const T* __restrict__ src, double* __restr
         dst[t] = (double)src[((t / nrhs) << lg) + t % nrhs];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(BLOCK)
-k_fill(int64_t n, T* __restrict__ x, const int* __restrict__ stop) {
+template <typename T, class G>
+__device__ __forceinline__ void fill(G g, int64_t n, T* __restrict__ x, const int* __restrict__ stop) {
     if (*stop) return;
-    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLOCK) x[t] = (T)0;
+    for (int64_t t = (int64_t)g.bid() * BLOCK + threadIdx.x; t < n; t += (int64_t)g.nb() * BLOCK) x[t] = (T)0;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(BLOCK)
-k_copy(int64_t n, const T* __restrict__ a, T* __restrict__ b, const int* __restrict__ stop) {
+struct Fill {
+    static constexpr int block = BLOCK;
+    using sig = decltype(&fill<T, HwGrid>);
+    template <class G, class... A>
+    __device__ static void run(G g, A... a) { fill<T>(g, a...); }
+};
+
+template <typename T, class G>
+__device__ __forceinline__ void copy(G g, int64_t n, const T* __restrict__ a, T* __restrict__ b,
+                                     const int* __restrict__ stop) {
     if (*stop) return;
-    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < n; t += (int64_t)gridDim.x * BLOCK) b[t] = a[t];
+    for (int64_t t = (int64_t)g.bid() * BLOCK + threadIdx.x; t < n; t += (int64_t)g.nb() * BLOCK) b[t] = a[t];
 }
+
+template <typename T>
+struct Copy {
+    static constexpr int block = BLOCK;
+    using sig = decltype(&copy<T, HwGrid>);
+    template <class G, class... A>
+    __device__ static void run(G g, A... a) { copy<T>(g, a...); }
+};
 
 }  // namespace dev
 }  // namespace amge

@@ -8,6 +8,12 @@
 // the other columns stay in flight: continuous batching at the granularity of a PCG
 // iteration.  Different hierarchies advance concurrently on their own streams.
 //
+// Hierarchies added as grouped form the server's ensemble instead: one PCG iteration of
+// every member is captured as a single graph in which the same level operator of the
+// members runs as one grouped launch (grouped.hpp), so small hierarchies, whose
+// iterations are chains of short launches, share their launches.  The ensemble runs its
+// chunks on its own stream; every member computes exactly what it computes alone.
+//
 // Admission: a hierarchy is made resident only if its device footprint fits the
 // hierarchy budget; a request is admitted when its hierarchy has a free column and the
 // work footprint of all admitted requests (their share of the batched work blocks)
@@ -97,6 +103,8 @@ struct Request {
 // One resident hierarchy and its columns.
 struct Group {
     amge_hierarchy* H = nullptr;
+    bool grouped = false;          // member of the ensemble
+    hipStream_t stream = nullptr;  // where its inserts, chunks and copy-outs run
     size_t footprint = 0;          // device bytes of the hierarchy
     size_t col_bytes = 0;          // work bytes of one column
     std::vector<int> slot;         // column -> index into the server's request table, -1 free
@@ -106,10 +114,25 @@ struct Group {
     std::vector<int> extracting;   // requests whose copy-out is in flight
     int active = 0;                // columns holding a request
     // cost model of one PCG iteration on W columns: fixed + W * per_col milliseconds
-    // (launch overhead, matrix bytes, vector bytes at a nominal bandwidth)
-    double fixed_ms = 0, per_col_ms = 0;
+    // (launch overhead, matrix bytes, vector bytes at a nominal bandwidth); mat_ms is
+    // the matrix part of fixed_ms
+    double fixed_ms = 0, per_col_ms = 0, mat_ms = 0;
     double chunk_ms = 0;           // estimate for the chunk in flight
     uint64_t turn = 0;             // when the group last finished a chunk (scheduling order)
+};
+
+// The grouped hierarchies: one captured graph runs an iteration of all of them (on all
+// their columns), recaptured when a member joins.
+struct Ensemble {
+    std::vector<Group*> members;
+    hipStream_t stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool stale = false;            // a member joined since the capture
+    bool busy = false;             // a chunk is in flight
+    hipEvent_t ev_chunk = nullptr;
+    double chunk_ms = 0;
+    uint64_t turn = 0;
+    int launches = 0, solo_launches = 0;   // kernels per iteration: grouped, and run alone
 };
 
 // Nominal figures of the scheduling cost model.
@@ -130,6 +153,7 @@ struct amge_server {
     double queued_ms = 0;             // estimated GPU time of the chunks in flight
     uint64_t clock = 0;               // scheduling turns
     std::vector<std::unique_ptr<Group>> groups;
+    Ensemble ens;
     std::vector<Request> reqs;        // request table (indices stay valid)
     std::vector<int> free_reqs;       // reusable entries of the table
     std::deque<int> queue;            // submitted, not admitted, in arrival order
@@ -137,6 +161,10 @@ struct amge_server {
     std::vector<hipEvent_t> event_pool;
 
     ~amge_server() {
+        if (ens.stream) (void)hipStreamSynchronize(ens.stream);
+        if (ens.exec) (void)hipGraphExecDestroy(ens.exec);
+        if (ens.ev_chunk) (void)hipEventDestroy(ens.ev_chunk);
+        if (ens.stream) (void)hipStreamDestroy(ens.stream);
         for (auto& g : groups) {
             (void)hipStreamSynchronize(g->H->gstream);
             if (g->cs_host) (void)hipHostFree(g->cs_host);
@@ -191,14 +219,33 @@ struct amge_server {
 
     // A chunk has finished: copy finished columns out and free them.
     bool reap_chunk(Group& g) {
-        if (!g.chunk_busy) return false;
+        if (!g.chunk_busy || g.grouped) return false;
         hipError_t e = hipEventQuery(g.ev_chunk);
         if (e == hipErrorNotReady) return false;
         HIPCHECK(e);
-        g.chunk_busy = false;
         queued_ms -= g.chunk_ms;
         if (queued_ms < 1e-9) queued_ms = 0;
         g.turn = ++clock;
+        collect(g);
+        return true;
+    }
+
+    bool reap_ensemble() {
+        if (!ens.busy) return false;
+        hipError_t e = hipEventQuery(ens.ev_chunk);
+        if (e == hipErrorNotReady) return false;
+        HIPCHECK(e);
+        ens.busy = false;
+        queued_ms -= ens.chunk_ms;
+        if (queued_ms < 1e-9) queued_ms = 0;
+        ens.turn = ++clock;
+        for (Group* g : ens.members) collect(*g);
+        return true;
+    }
+
+    // After a chunk: report finished columns, copy them out and free them.
+    void collect(Group& g) {
+        g.chunk_busy = false;
         amge_hierarchy* H = g.H;
         const int64_t n = H->lv[0].n;
         bool any = false;
@@ -216,7 +263,7 @@ struct amge_server {
                             : s.breakdown ? AMGE_ERR_BREAKDOWN
                             : (r.rtol > 0 && !(s.relres <= r.rtol)) ? AMGE_NOT_CONVERGED
                                                                      : AMGE_OK;
-            dev::k_serve_extract<<<sgrid(n), dev::SBLOCK, 0, H->gstream>>>(n, H->lgNC, c, H->bX, r.x);
+            dev::k_serve_extract<<<sgrid(n), dev::SBLOCK, 0, g.stream>>>(n, H->lgNC, c, H->bX, r.x);
             g.extracting.push_back(i);
             g.slot[c] = -1;
             g.active -= 1;
@@ -225,9 +272,8 @@ struct amge_server {
         }
         if (any) {
             HIPCHECK(hipGetLastError());
-            HIPCHECK(hipEventRecord(g.ev_extract, H->gstream));
+            HIPCHECK(hipEventRecord(g.ev_extract, g.stream));
         }
-        return true;
     }
 
     // Loads queued requests into free columns of idle groups.
@@ -245,8 +291,8 @@ struct amge_server {
             while (g.slot[c] >= 0) ++c;
             amge_hierarchy* H = g.H;
             const int64_t n = H->lv[0].n;
-            HIPCHECK(hipStreamWaitEvent(H->gstream, r.ready, 0));
-            dev::k_serve_insert<<<sgrid(n), dev::SBLOCK, 0, H->gstream>>>(n, H->lgNC, c, r.b, H->bR, H->bX, H->bP,
+            HIPCHECK(hipStreamWaitEvent(g.stream, r.ready, 0));
+            dev::k_serve_insert<<<sgrid(n), dev::SBLOCK, 0, g.stream>>>(n, H->lgNC, c, r.b, H->bR, H->bX, H->bP,
                                                                          H->cs, H->bs, r.rtol, r.maxit, r.stop_l2);
             HIPCHECK(hipGetLastError());
             g.slot[c] = *it;
@@ -265,12 +311,24 @@ struct amge_server {
     // new chunk of a small hierarchy waits behind the chunks of large ones.  A chunk has as
     // many iterations as fit SCHED_CHUNK_MS (at least one, at most `chunk`).
     bool launch() {
-        std::vector<Group*> cand;
+        std::vector<Group*> cand;   // null: the ensemble
         for (auto& gp : groups)
-            if (!gp->chunk_busy && gp->active > 0) cand.push_back(gp.get());
-        std::sort(cand.begin(), cand.end(), [](const Group* a, const Group* b) { return a->turn < b->turn; });
+            if (!gp->grouped && !gp->chunk_busy && gp->active > 0) cand.push_back(gp.get());
+        if (!ens.busy)
+            for (Group* g : ens.members)
+                if (g->active > 0) {
+                    cand.push_back(nullptr);
+                    break;
+                }
+        auto turn = [&](const Group* g) { return g ? g->turn : ens.turn; };
+        std::sort(cand.begin(), cand.end(), [&](const Group* a, const Group* b) { return turn(a) < turn(b); });
         bool any = false;
         for (Group* gp : cand) {
+            if (!gp) {
+                if (!launch_ensemble()) break;
+                any = true;
+                continue;
+            }
             Group& g = *gp;
             amge_hierarchy* H = g.H;
             // active width: the columns up to the highest occupied one (requests take the
@@ -297,8 +355,42 @@ struct amge_server {
         return any;
     }
 
+    // A chunk of the ensemble (all members, all columns); false if the queue is full.
+    bool launch_ensemble() {
+        if (ens.stale || !ens.exec) {
+            std::vector<amge_hierarchy*> hs;
+            for (Group* g : ens.members) hs.push_back(g->H);
+            hipGraphExecDestroy_if(ens.exec);
+            ens.exec = capture_grouped_iteration(hs, ens.stream, &ens.launches, &ens.solo_launches);
+            ens.stale = false;
+        }
+        // members without requests return from every kernel at once
+        double it_ms = ens.launches * SCHED_LAUNCH_MS;
+        for (Group* g : ens.members)
+            if (g->active > 0) it_ms += g->mat_ms + g->H->NC * g->per_col_ms;
+        const int k = std::max(1, std::min(chunk, (int)(SCHED_CHUNK_MS / it_ms)));
+        const double est = k * it_ms;
+        if (queued_ms > 0 && queued_ms + est > SCHED_QUEUE_MS) return false;
+        for (int i = 0; i < k; ++i) HIPCHECK(hipGraphLaunch(ens.exec, ens.stream));
+        for (Group* g : ens.members) {
+            HIPCHECK(hipMemcpyAsync(g->cs_host, g->H->cs, sizeof(dev::ColState) * g->H->NC, hipMemcpyDeviceToHost,
+                                    ens.stream));
+            g->chunk_busy = true;
+        }
+        HIPCHECK(hipEventRecord(ens.ev_chunk, ens.stream));
+        ens.busy = true;
+        ens.chunk_ms = est;
+        queued_ms += est;
+        return true;
+    }
+
+    static void hipGraphExecDestroy_if(hipGraphExec_t& ex) {
+        if (ex) (void)hipGraphExecDestroy(ex);
+        ex = nullptr;
+    }
+
     bool busy() const {
-        if (!queue.empty()) return true;
+        if (!queue.empty() || ens.busy) return true;
         for (auto& g : groups)
             if (g->chunk_busy || g->active || !g->extracting.empty()) return true;
         return false;
@@ -339,7 +431,8 @@ extern "C" amge_status amge_server_create(size_t hierarchy_budget, size_t inflig
 
 extern "C" void amge_server_destroy(amge_server* s) { delete s; }
 
-extern "C" amge_status amge_server_add(amge_server* s, amge_hierarchy* h, int32_t* id) {
+namespace {
+amge_status server_add(amge_server* s, amge_hierarchy* h, int32_t* id, bool grouped) {
     return sguard([&]() -> amge_status {
         if (!s || !h || !id) fail(AMGE_ERR_ARG, "null argument");
         if (h->NC < 2) fail(AMGE_ERR_ARG, "hierarchy needs max_rhs >= 2 to serve");
@@ -367,19 +460,54 @@ extern "C" amge_status amge_server_add(amge_server* s, amge_hierarchy* h, int32_
             const double col = (b2 - b1) + 12 * 8 * n1;
             const double mat = (b1 - (b2 - b1)) + 12.0 * (double)h->lv[0].A.nnz;
             const int kernels = 16 * ((int)h->lv.size() - 1) + 8;
-            g->fixed_ms = kernels * SCHED_LAUNCH_MS + std::max(0.0, mat) / SCHED_BW_BYTES_PER_MS;
+            g->mat_ms = std::max(0.0, mat) / SCHED_BW_BYTES_PER_MS;
+            g->fixed_ms = kernels * SCHED_LAUNCH_MS + g->mat_ms;
             g->per_col_ms = col / SCHED_BW_BYTES_PER_MS;
         }
         HIPCHECK(hipHostMalloc((void**)&g->cs_host, sizeof(dev::ColState) * h->NC, hipHostMallocDefault));
         HIPCHECK(hipEventCreateWithFlags(&g->ev_chunk, hipEventDisableTiming));
         HIPCHECK(hipEventCreateWithFlags(&g->ev_extract, hipEventDisableTiming));
-        for (int W = 1; W <= h->NC; W *= 2) capture_iteration(h, W);
+        if (grouped) {
+            if (!s->ens.stream) {
+                HIPCHECK(hipStreamCreateWithFlags(&s->ens.stream, hipStreamNonBlocking));
+                HIPCHECK(hipEventCreateWithFlags(&s->ens.ev_chunk, hipEventDisableTiming));
+            }
+            g->grouped = true;
+            g->stream = s->ens.stream;
+        } else {
+            g->stream = h->gstream;
+            for (int W = 1; W <= h->NC; W *= 2) capture_iteration(h, W);
+        }
         dev::k_serve_reset<<<1, 64, 0, h->gstream>>>(h->NC, h->cs, h->bs);
         HIPCHECK(hipGetLastError());
         HIPCHECK(hipStreamSynchronize(h->gstream));
         s->resident += g->footprint;
         *id = (int32_t)s->groups.size();
+        if (grouped) {
+            s->ens.members.push_back(g.get());
+            s->ens.stale = true;
+        }
         s->groups.push_back(std::move(g));
+        return AMGE_OK;
+    });
+}
+}  // namespace
+
+extern "C" amge_status amge_server_add(amge_server* s, amge_hierarchy* h, int32_t* id) {
+    return server_add(s, h, id, false);
+}
+
+extern "C" amge_status amge_server_add_grouped(amge_server* s, amge_hierarchy* h, int32_t* id) {
+    return server_add(s, h, id, true);
+}
+
+extern "C" amge_status amge_server_ensemble(const amge_server* s, int32_t* members, int32_t* launches,
+                                            int32_t* solo_launches) {
+    return sguard([&]() -> amge_status {
+        if (!s) fail(AMGE_ERR_ARG, "null argument");
+        if (members) *members = (int32_t)s->ens.members.size();
+        if (launches) *launches = s->ens.launches;
+        if (solo_launches) *solo_launches = s->ens.solo_launches;
         return AMGE_OK;
     });
 }
@@ -428,6 +556,7 @@ extern "C" amge_status amge_server_progress(amge_server* s, int32_t wait, amge_c
                 moved |= s->reap_extractions(*g);
                 moved |= s->reap_chunk(*g);
             }
+            moved |= s->reap_ensemble();
             moved |= s->admit();
             moved |= s->launch();
             if (!s->done.empty() || !wait || !s->busy()) break;

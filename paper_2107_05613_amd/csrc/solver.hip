@@ -331,12 +331,12 @@ void coarse_solve(amge_hierarchy* H, const T* b, T* x, hipStream_t s, const int*
 
 template <class T>
 void copy_vec(int64_t n, const T* a, T* b, hipStream_t s, const int* stop) {
-    if (n) dev::k_copy<T><<<(unsigned)std::min<int64_t>(grid_for(n), 4096), BLOCK, 0, s>>>(n, a, b, stop);
+    if (n) launch<dev::Copy<T>>((unsigned)std::min<int64_t>(grid_for(n), 4096), s, n, a, b, stop);
 }
 
 template <class T>
 void fill_zero(int64_t n, T* x, hipStream_t s, const int* stop) {
-    if (n) dev::k_fill<T><<<(unsigned)std::min<int64_t>(grid_for(n), 4096), BLOCK, 0, s>>>(n, x, stop);
+    if (n) launch<dev::Fill<T>>((unsigned)std::min<int64_t>(grid_for(n), 4096), s, n, x, stop);
 }
 
 template <class S, class D>
@@ -484,13 +484,11 @@ void bmm_v(const DSellB& M, int W, int NC, const T* X, const T* B, const T* dinv
     const unsigned grid = (unsigned)(((int64_t)M.nslices * L + WAVES - 1) / WAVES);
     if (!grid) return;
     if (M.c16)
-        dev::k_sell_mm<T, V, MODE, true><<<grid, BLOCK, 0, s>>>(M.nslices, L, NC, M.sptr, M.srow, M.ci, M.c16,
-                                                                M.cbase, bvals<T>(M), X, B, dinv, Y, YD, M.lead,
-                                                                stop);
+        launch<dev::SellMM<T, V, MODE, true>>(grid, s, M.nslices, L, NC, M.sptr, M.srow, M.ci, M.c16, M.cbase,
+                                              bvals<T>(M), X, B, dinv, Y, YD, M.lead, stop);
     else
-        dev::k_sell_mm<T, V, MODE, false><<<grid, BLOCK, 0, s>>>(M.nslices, L, NC, M.sptr, M.srow, M.ci, M.c16,
-                                                                 M.cbase, bvals<T>(M), X, B, dinv, Y, YD, M.lead,
-                                                                 stop);
+        launch<dev::SellMM<T, V, MODE, false>>(grid, s, M.nslices, L, NC, M.sptr, M.srow, M.ci, M.c16, M.cbase,
+                                               bvals<T>(M), X, B, dinv, Y, YD, M.lead, stop);
 }
 
 template <class T, int V>
@@ -530,8 +528,7 @@ template <class T, int V>
 void inc_mm_v(const DSellB& M, int W, int NC, const T* X, T* Y, const int* stop, hipStream_t s) {
     const int L = W / V;
     const unsigned grid = (unsigned)(((int64_t)M.nslices * L + WAVES - 1) / WAVES);
-    if (grid)
-        dev::k_sell_inc_mm_add<T, V><<<grid, BLOCK, 0, s>>>(M.nslices, L, NC, M.sptr, M.srow, M.ent, X, Y, stop);
+    launch<dev::IncMMAdd<T, V>>(grid, s, M.nslices, L, NC, M.sptr, M.srow, M.ent, X, Y, stop);
 }
 
 template <class T>
@@ -549,12 +546,12 @@ inline unsigned grid_stride(int64_t threads) { return (unsigned)std::min<int64_t
 
 template <class T>
 void bfill(int64_t n, T* x, const int* stop, hipStream_t s) {
-    if (n) dev::k_fill<T><<<grid_stride(n), BLOCK, 0, s>>>(n, x, stop);
+    if (n) launch<dev::Fill<T>>(grid_stride(n), s, n, x, stop);
 }
 
 template <class T>
 void bcopy(int64_t n, const T* a, T* b, const int* stop, hipStream_t s) {
-    if (n) dev::k_copy<T><<<grid_stride(n), BLOCK, 0, s>>>(n, a, b, stop);
+    if (n) launch<dev::Copy<T>>(grid_stride(n), s, n, a, b, stop);
 }
 
 // Columns per lane V for one matrix and block width NC: the default (16-byte lane
@@ -679,7 +676,7 @@ void bvcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, i
     const int NC = H->NC;
     if (l == H->tail) {   // the coarsest solve, or the folded coarse tail
         if (H->tail_n)
-            dev::k_coarse_mm<T><<<H->tail_n, BLOCK, 0, s>>>(H->tail_n, log2i(W), H->lgNC, H->tail_op, b, xout, stop);
+            launch<dev::CoarseMM<T>>(H->tail_n, s, H->tail_n, log2i(W), H->lgNC, H->tail_op, b, xout, stop);
         return;
     }
     DLevel& L = H->lv[l];
@@ -1389,8 +1386,8 @@ amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int 
 template <int V, bool C16>
 void bpcg_ap_v(amge_hierarchy* H, int W, hipStream_t s) {
     const DSellB& A = H->lv[0].bA;
-    dev::k_bpcg_ap<V, C16><<<BPCG_BLOCKS, BLOCK, 0, s>>>(A.nslices, W, H->NC, A.sptr, A.srow, A.ci, A.c16, A.cbase,
-                                                         A.v64, H->bP, H->bQ, H->bpart, H->bs);
+    launch<dev::BpcgAp<V, C16>>(BPCG_BLOCKS, s, A.nslices, W, H->NC, A.sptr, A.srow, A.ci, A.c16, A.cbase, A.v64,
+                                H->bP, H->bQ, H->bpart, H->bs);
 }
 
 void bpcg_ap(amge_hierarchy* H, int W, hipStream_t s) {
@@ -1424,10 +1421,9 @@ void bpcg_dots(amge_hierarchy* H, int W, hipStream_t s) {
     DLevel& L = H->lv[0];
     const int n = L.n;
     if (bz32(H))
-        dev::k_bpcg_dots<float><<<BPCG_BLOCKS, BLOCK, 0, s>>>(n, W, H->NC, L.bw32.x, (float*)H->bZ, H->bR, H->bpart,
-                                                              H->bs);
+        launch<dev::BpcgDots<float>>(BPCG_BLOCKS, s, n, W, H->NC, L.bw32.x, (float*)H->bZ, H->bR, H->bpart, H->bs);
     else
-        dev::k_bpcg_dots<double><<<BPCG_BLOCKS, BLOCK, 0, s>>>(n, W, H->NC, H->bZv, H->bZ, H->bR, H->bpart, H->bs);
+        launch<dev::BpcgDots<double>>(BPCG_BLOCKS, s, n, W, H->NC, H->bZv, H->bZ, H->bR, H->bpart, H->bs);
 }
 
 // One PCG iteration on the first W columns (the captured body): q = A p, alpha, x/r
@@ -1441,21 +1437,17 @@ void bpcg_iteration(amge_hierarchy* H, int W, hipStream_t s) {
     const bool ml = H->lv.size() > 1;
     const unsigned g = grid_stride(nn);
     bpcg_ap(H, W, s);
-    dev::k_bpcg_alpha<<<1, dev::FIN_BLOCK, 0, s>>>(W, H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
+    launch<dev::BpcgAlpha>(1, s, W, H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
     const bool fused = bpcg_fused_bd(H);
-    dev::k_bpcg_xr<<<g, BLOCK, 0, s>>>(nn, lgW, H->lgNC, H->cs, H->bQ, H->bR,
-                                       f32 ? L.bw32.b : nullptr, f32 && !fused ? L.bw32.bd : nullptr,
-                                       f32 ? L.bw32.dinv : nullptr, !f32 && ml && !fused ? L.bw64.bd : nullptr,
-                                       !f32 && ml ? L.bw64.dinv : nullptr, H->bs);
+    launch<dev::BpcgXr>(g, s, nn, lgW, H->lgNC, H->cs, H->bQ, H->bR, f32 ? L.bw32.b : nullptr,
+                        f32 && !fused ? L.bw32.bd : nullptr, f32 ? L.bw32.dinv : nullptr,
+                        !f32 && ml && !fused ? L.bw64.bd : nullptr, !f32 && ml ? L.bw64.dinv : nullptr, H->bs);
     bpcg_precond(H, W, &H->bs->all_done, s);
     bpcg_dots(H, W, s);
-    dev::k_bpcg_update<<<1, dev::FIN_BLOCK, 0, s>>>(W, H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
-    if (f32)
-        dev::k_bpcg_p<float><<<g, BLOCK, 0, s>>>(nn, lgW, H->lgNC, H->cs, (const float*)H->bZ, H->bP, H->bX,
-                                                 H->bs);
-    else
-        dev::k_bpcg_p<double><<<g, BLOCK, 0, s>>>(nn, lgW, H->lgNC, H->cs, H->bZ, H->bP, H->bX, H->bs);
-    dev::k_bpcg_finish<<<1, 1, 0, s>>>(H->bs);
+    launch<dev::BpcgUpdate>(1, s, W, H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
+    if (f32) launch<dev::BpcgP<float>>(g, s, nn, lgW, H->lgNC, H->cs, (const float*)H->bZ, H->bP, H->bX, H->bs);
+    else launch<dev::BpcgP<double>>(g, s, nn, lgW, H->lgNC, H->cs, H->bZ, H->bP, H->bX, H->bs);
+    launch<dev::BpcgFinish>(1, s, H->bs);
 }
 
 hipGraphExec_t capture_iteration(amge_hierarchy* H, int W) {
@@ -1474,6 +1466,70 @@ hipGraphExec_t capture_iteration(amge_hierarchy* H, int W) {
         ex = nullptr;
         fail(AMGE_ERR_HIP, "graph instantiation failed");
     }
+    return ex;
+}
+
+LaunchRecorder*& launch_recorder() {
+    static thread_local LaunchRecorder* r = nullptr;
+    return r;
+}
+
+int group_launches(const std::vector<LaunchRecorder>& mem, hipStream_t s) {
+    const int M = (int)mem.size();
+    std::vector<size_t> next(M, 0);
+    std::vector<const LaunchRec*> ops;
+    int launches = 0;
+    for (;;) {
+        const void* best = nullptr;
+        int best_count = 0;
+        size_t best_left = 0;
+        for (int m = 0; m < M; ++m) {
+            if (next[m] >= mem[m].ops.size()) continue;
+            const void* k = mem[m].ops[next[m]].key;
+            int count = 0;
+            size_t left = 0;
+            for (int q = 0; q < M; ++q)
+                if (next[q] < mem[q].ops.size() && mem[q].ops[next[q]].key == k) {
+                    ++count;
+                    left = std::max(left, mem[q].ops.size() - next[q]);
+                }
+            if (count > best_count || (count == best_count && left > best_left)) {
+                best = k;
+                best_count = count;
+                best_left = left;
+            }
+        }
+        if (!best) break;
+        ops.clear();
+        for (int m = 0; m < M; ++m)
+            if (next[m] < mem[m].ops.size() && mem[m].ops[next[m]].key == best) ops.push_back(&mem[m].ops[next[m]++]);
+        launches += ops[0]->emit(ops.data(), (int)ops.size(), s);
+    }
+    return launches;
+}
+
+hipGraphExec_t capture_grouped_iteration(const std::vector<amge_hierarchy*>& hs, hipStream_t s, int* launches,
+                                         int* solo_launches) {
+    std::vector<LaunchRecorder> rec(hs.size());
+    int solo = 0;
+    for (size_t i = 0; i < hs.size(); ++i) {
+        amge_hierarchy* H = hs[i];
+        if (H->NC < 2 || !H->gstream) fail(AMGE_ERR_ARG, "hierarchy has no batched path (max_rhs = 1)");
+        RecordLaunches scope(&rec[i]);
+        bpcg_iteration(H, H->NC, s);
+        solo += (int)rec[i].ops.size();
+    }
+    hipGraph_t graph = nullptr;
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const int n = group_launches(rec, s);
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (e != hipSuccess || !graph) fail(AMGE_ERR_HIP, "graph capture of the grouped PCG iteration failed");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) fail(AMGE_ERR_HIP, "graph instantiation failed");
+    if (launches) *launches = n;
+    if (solo_launches) *solo_launches = solo;
     return ex;
 }
 

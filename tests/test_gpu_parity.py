@@ -336,17 +336,20 @@ def test_pcg_graph_replays_match_direct_launches(bits):
         assert o[0] == outs[0][0] and o[1] == outs[0][1] and np.array_equal(o[2], outs[0][2])
 
 
+@pytest.mark.parametrize("tail", [2048, 0])
 @pytest.mark.parametrize("nus", [(1, 0), (1, 1), (3, 3), (0, 2)])
-def test_other_sweep_counts(nus):
+def test_other_sweep_counts(nus, tail):
     """Sweep counts other than 2 + 2 (odd counts take the copy / ping-pong paths, zero
     counts skip a smoother): single-column and batched V-cycles and fixed-count PCG
-    against the oracle built with the same counts."""
+    against the oracle built with the same counts.  With tail_rows = 2048 the levels
+    below the fine one are folded into the dense operator (formed with the same
+    counts); with 0 every level runs its kernels."""
     from oracle.solve import Multilevel, pcg
     amge = _amge()
     nup, nua = nus
     c = case("curl", 8, 3, "blocks")
     ml = Multilevel.from_hierarchy(c.H, nu_primary=nup, nu_aux=nua)
-    H = amge.Hierarchy(c.prod, precond_bits=64, nu_primary=nup, nu_aux=nua, max_rhs=2)
+    H = amge.Hierarchy(c.prod, precond_bits=64, nu_primary=nup, nu_aux=nua, max_rhs=2, tail_rows=tail)
     ref = ml.vcycle(c.b)
     z = torch.empty_like(dev(c.b))
     H.vcycle(dev(c.b), z)

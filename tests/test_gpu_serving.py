@@ -9,6 +9,9 @@ Bars
 * Parity: requests on an FP64-preconditioner hierarchy, stopped after a fixed number of
   iterations, equal the oracle's PCG iterate within max(1e-10, u * kappa) (the bound of
   the single-column tests).
+* Grouped launches: hierarchies added as the server's ensemble (one captured graph of
+  grouped launches for an iteration of all of them) give bitwise the results of the
+  same hierarchies served one by one.
 * Admission: the in-flight budget caps the admitted requests' work footprint at every
   moment; hierarchies beyond the resident budget and requests beyond the in-flight
   budget are refused with AMGE_ERR_BUSY.
@@ -59,12 +62,13 @@ def requests(res, num, seed=0):
     return out
 
 
-def serve(res, reqs, order, inflight_budget=0, maxit=None, watch=None):
+def serve(res, reqs, order, inflight_budget=0, maxit=None, watch=None, grouped=None, info=None):
     """Serves the requests of `order` (all submitted at once, in that order); returns
-    {request: (status, iters, relres, x)}."""
+    {request: (status, iters, relres, x)}.  grouped[i]: hierarchy i joins the ensemble;
+    info (a list) receives the server's ensemble figures."""
     from paper_2107_05613_amd import amge
     srv = amge.Server(inflight_budget=inflight_budget, chunk=2)
-    ids = [srv.add(H) for H in res.H]
+    ids = [srv.add(H, grouped=bool(grouped and grouped[i])) for i, H in enumerate(res.H)]
     xs = {j: torch.full((res.n1[reqs[j][0]],), 3.0, dtype=torch.float64, device="cuda") for j in order}
     for j in order:
         h, b = reqs[j]
@@ -76,6 +80,8 @@ def serve(res, reqs, order, inflight_budget=0, maxit=None, watch=None):
             out[tag] = (status, iters, relres)
         if watch is not None:
             watch(srv)
+    if info is not None:
+        info.append(srv.ensemble())
     srv.close()
     torch.cuda.synchronize()
     return {j: (*out[j], xs[j].cpu().numpy()) for j in order}
@@ -102,6 +108,36 @@ def test_solo_vs_mix_bitwise():
     status, its, rrs = res.H[h].pcg(B, x, rtol=1e-8, nrhs=2)
     assert its[0] == mix[j][1]
     assert np.array_equal(x.view(-1, 2)[:, 0].cpu().numpy(), mix[j][3])
+
+
+class _Joined:
+    def __init__(self, *rs):
+        self.H = [H for r in rs for H in r.H]
+        self.n1 = [n for r in rs for n in r.n1]
+
+
+def test_grouped_ensemble_bitwise():
+    """a9 grouped launches: the six hierarchies (H(curl) and H(div), FP32 and FP64
+    V-cycles) served as one ensemble, and half of them grouped beside solo ones, give
+    every request bitwise the result it gets with every hierarchy served on its own; the
+    ensemble's graph has fewer kernels than its members' own graphs together."""
+    res = _Joined(resident(32), resident(64))
+    reqs = requests(res, 24, seed=3)
+    order = list(range(len(reqs)))
+    solo = serve(res, reqs, order)
+    info = []
+    allg = serve(res, reqs, order, grouped=[True] * len(res.H), info=info)
+    half = serve(res, reqs, order, grouped=[i % 2 == 0 for i in range(len(res.H))])
+    for j in order:
+        for other in (allg, half):
+            o = other[j]
+            assert o[0] == solo[j][0] == 0, (j, o[:3], solo[j][:3])
+            assert o[1] == solo[j][1] and o[2] == solo[j][2], (j, o[:3], solo[j][:3])
+            assert np.array_equal(o[3], solo[j][3]), j
+    members, launches, solo_launches = info[0]
+    print(f"\n[ensemble] {members} members: {launches} kernels per iteration vs {solo_launches} alone", flush=True)
+    assert members == len(res.H)
+    assert 0 < launches < solo_launches
 
 
 def test_served_fp64_matches_oracle():
