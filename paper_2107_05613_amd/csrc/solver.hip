@@ -675,8 +675,16 @@ void bvcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, i
                    hipStream_t s) {
     const int NC = H->NC;
     if (l == H->tail) {   // the coarsest solve, or the folded coarse tail
-        if (H->tail_n)
-            launch<dev::CoarseMM<T>>(H->tail_n, s, H->tail_n, log2i(W), H->lgNC, H->tail_op, b, xout, stop);
+        if (H->tail_n) {
+            const unsigned grid = (unsigned)((H->tail_n + dev::CROWS - 1) / dev::CROWS);
+            const int lgW = log2i(W);
+            switch (std::min(H->NC, 8)) {   // columns per thread
+                case 1: launch<dev::CoarseMM<T, 1>>(grid, s, H->tail_n, lgW, H->lgNC, H->tail_op, b, xout, stop); break;
+                case 2: launch<dev::CoarseMM<T, 2>>(grid, s, H->tail_n, lgW, H->lgNC, H->tail_op, b, xout, stop); break;
+                case 4: launch<dev::CoarseMM<T, 4>>(grid, s, H->tail_n, lgW, H->lgNC, H->tail_op, b, xout, stop); break;
+                default: launch<dev::CoarseMM<T, 8>>(grid, s, H->tail_n, lgW, H->lgNC, H->tail_op, b, xout, stop);
+            }
+        }
         return;
     }
     DLevel& L = H->lv[l];
