@@ -140,6 +140,63 @@ def test_grouped_ensemble_bitwise():
     assert 0 < launches < solo_launches
 
 
+def test_grouped_ensemble_recapture_and_split():
+    """An ensemble that grows while it serves (members join after its first chunks, so
+    its graph is captured again) and has more members than one grouped launch takes (the
+    launches are split): every request bitwise equal to the same request served on a
+    server of solo hierarchies."""
+    from paper_2107_05613_amd import amge
+    hs, n1 = [], []
+    for i in range(18):
+        kind = "curl" if i % 2 == 0 else "div"
+        w = W.Workload("t", kind, 8, 3, "blocks", coef_seed=10 + i)
+        a, b = W.coefficients(w)
+        hs.append(amge.Hierarchy(amge.build_problem(kind, 8, 3, a, b), precond_bits=32 if i % 3 else 64,
+                                 max_rhs=2))
+        n1.append(hs[-1].rows[0])
+    reqs = []
+    for j in range(36):
+        h = j % 18 if j < 18 else (j * 7) % 18
+        reqs.append((h, torch.from_numpy(W.rhs(n1[h], 500 + j)[:, 0]).cuda()))
+    torch.cuda.synchronize()
+
+    def run(srv, ids, order, xs, out):
+        for j in order:
+            h, b = reqs[j]
+            srv.submit(ids[h], b, xs[j], tag=j, rtol=1e-8, maxit=500)
+        got = 0
+        while got < len(order):
+            for tag, hid, status, iters, relres in srv.progress(wait=True):
+                out[tag] = (status, iters, relres)
+                got += 1
+
+    def fresh():
+        return {j: torch.full((n1[reqs[j][0]],), 3.0, dtype=torch.float64, device="cuda") for j in range(36)}
+
+    solo_x, solo = fresh(), {}
+    srv = amge.Server(chunk=2)
+    ids = [srv.add(H) for H in hs]
+    run(srv, ids, range(36), solo_x, solo)
+    srv.close()
+
+    grp_x, grp = fresh(), {}
+    srv = amge.Server(chunk=2)
+    ids = [srv.add(H, grouped=True) for H in hs[:10]]
+    first = [j for j in range(36) if reqs[j][0] < 10]
+    run(srv, ids, first, grp_x, grp)
+    m0 = srv.ensemble()
+    ids += [srv.add(H, grouped=True) for H in hs[10:]]
+    run(srv, ids, [j for j in range(36) if j not in grp], grp_x, grp)
+    m1 = srv.ensemble()
+    srv.close()
+    torch.cuda.synchronize()
+    print(f"\n[ensemble] 10 members: {m0[1]} kernels vs {m0[2]}; 18 members: {m1[1]} vs {m1[2]}", flush=True)
+    assert m0[0] == 10 and m1[0] == 18 and m1[2] > m0[2] and 0 < m1[1] < m1[2]
+    for j in range(36):
+        assert grp[j] == solo[j] and grp[j][0] == 0, (j, grp[j], solo[j])
+        assert torch.equal(grp_x[j], solo_x[j]), j
+
+
 def test_served_fp64_matches_oracle():
     """Served requests on FP64-preconditioner hierarchies, fixed iteration count, against
     the oracle's PCG iterate."""
