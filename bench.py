@@ -259,6 +259,28 @@ def run_serving(args):
     return out
 
 
+def stream_reference(nbytes=1 << 30, reps=10):
+    """Bandwidth this GPU reaches on a plain stream: a 1 GiB device copy (torch, read +
+    write bytes, HIP events on torch's stream)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for name, fn, moved in (("copy", lambda: dst.copy_(src), 2 * nbytes),):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = moved / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_grouped_ab():
     """Solo streams vs the grouped ensemble on 16 resident 16^3 hierarchies (both types,
     8 coefficient fields), 128 requests at once, 8 columns each."""
@@ -392,6 +414,7 @@ def main():
     err = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
 
     del H64
+    stream_ref = stream_reference()
     batched = run_batched(args, amge, W) if args.batched_workload else None
     serving = run_serving(args) if args.serving_requests > 0 else None
 
@@ -443,6 +466,7 @@ def main():
             "avg_launch_us": 1e3 * k_avg_ms,
             "bytes_per_launch": k_bytes / max(k_launches, 1),
             "launches": k_launches,
+            "stream_reference_GBps": stream_ref,
         },
         "setup_s": {"build": t_build, "device_setup": t_setup},
         "batched": batched,

@@ -11,6 +11,10 @@ import ctypes as C
 import os
 
 import numpy as np
+# torch is loaded before the library: torch ships its own HIP runtime, and the library's
+# runtime dependency then resolves to that one (a process that loads the library first
+# holds two HIP runtimes, and device allocations through the library's can fail).
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libamge.so")

@@ -1,6 +1,8 @@
 // Device-side data of a hierarchy (shared by the solver and the serving engine).
 #pragma once
 
+#include <cstdio>
+
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -108,6 +110,7 @@ struct amge_hierarchy {
     // tail_op (tail_n x tail_n): the coarsest inverse, or a folded coarse tail
     int tail = 0, tail_n = 0;
     double* tail_op = nullptr;
+    int tail_rpb = 4;            // rows per block of the batched dense tail product (tuned)
     // outer PCG buffers (FP64, level-1 length)
     double *r = nullptr, *p = nullptr, *q = nullptr, *z[2] = {nullptr, nullptr}, *x = nullptr;
     double *part_pq = nullptr, *part_dots[2] = {nullptr, nullptr};
@@ -154,7 +157,15 @@ struct amge_hierarchy {
         if (n == 0) n = 1;
         void* ptr = nullptr;
         hipError_t e = hipMalloc(&ptr, n * sizeof(T));
-        if (e != hipSuccess) amge::fail(AMGE_ERR_OOM, "hipMalloc failed");
+        if (e != hipSuccess) {
+            size_t fr = 0, tot = 0;
+            (void)hipGetLastError();
+            (void)hipMemGetInfo(&fr, &tot);
+            char msg[160];
+            snprintf(msg, sizeof(msg), "hipMalloc of %zu bytes failed (%s; device memory free %zu of %zu bytes)",
+                     n * sizeof(T), hipGetErrorString(e), fr, tot);
+            amge::fail(AMGE_ERR_OOM, msg);
+        }
         allocs.push_back(ptr);
         bytes += n * sizeof(T);
         return (T*)ptr;

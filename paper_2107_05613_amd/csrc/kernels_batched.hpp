@@ -202,48 +202,47 @@ struct IncMMAdd {
 
 // Dense FP64 operator (the coarsest inverse or the folded coarse tail): X = M B on the
 // first W = 2^lgW of the NC = 2^lg stored columns; FP64 arithmetic.  A block computes
-// CROWS rows.  Thread t owns columns c0 .. c0 + CPT - 1 (c0 = (t % TPJ) CPT, TPJ = NC /
+// R rows (R tuned per hierarchy; a row's sums do not depend on it).  Thread t owns columns c0 .. c0 + CPT - 1 (c0 = (t % TPJ) CPT, TPJ = NC /
 // CPT threads per term) and the terms j = s, s + J, ... with s = t / TPJ, J = BLOCK /
 // TPJ: the lanes of a wave read different entries of a row of M (coalesced), and a row of
 // B in CPT-wide vector loads; four terms' loads of every row are issued at a time and
 // summed in order.  The partial sums are then added over the terms' slots of a wave (a
 // fixed butterfly) and over the waves in order.  The layout depends on NC only, so a
 // column's result does not depend on W.
-constexpr int CROWS = 4;
-template <typename T, int CPT, class Grid>
+template <typename T, int CPT, int R, class Grid>
 __device__ __forceinline__ void
 coarse_mm(Grid gr, int n, int lgW, int lg, const double* __restrict__ Ainv, const T* __restrict__ B,
           T* __restrict__ X, const int* __restrict__ stop) {
-    __shared__ double sh[WAVES * CROWS * 64];   // per wave: CROWS x NC sums (NC <= 64)
+    __shared__ double sh[WAVES * R * 64];   // per wave: R x NC sums (NC <= 64)
     const int stopped = *stop;   // tested before the store: its load overlaps the product
     const int NC = 1 << lg, W = 1 << lgW;
     const int TPJ = NC / CPT, J = BLOCK / TPJ;
     const int t = threadIdx.x;
     const int c0 = (t % TPJ) * CPT;
-    const int r0 = (int)gr.bid() * CROWS;
-    const double* a[CROWS];
+    const int r0 = (int)gr.bid() * R;
+    const double* a[R];
 #pragma unroll
-    for (int r = 0; r < CROWS; ++r) a[r] = Ainv + (int64_t)min(r0 + r, n - 1) * n;   // rows >= n: not stored
-    double acc[CROWS][CPT];
+    for (int r = 0; r < R; ++r) a[r] = Ainv + (int64_t)min(r0 + r, n - 1) * n;   // rows >= n: not stored
+    double acc[R][CPT];
 #pragma unroll
-    for (int r = 0; r < CROWS; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int i = 0; i < CPT; ++i) acc[r][i] = 0;
     if (c0 < W) {
         int j = t / TPJ;
         for (; j + 3 * J < n; j += 4 * J) {
-            double av[4][CROWS];
+            double av[4][R];
             Pack<T, CPT> bv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
 #pragma unroll
-                for (int r = 0; r < CROWS; ++r) av[u][r] = __builtin_nontemporal_load(a[r] + j + u * J);
+                for (int r = 0; r < R; ++r) av[u][r] = __builtin_nontemporal_load(a[r] + j + u * J);
                 bv[u].load(B + (int64_t)(j + u * J) * NC + c0);
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int r = 0; r < CROWS; ++r)
+                for (int r = 0; r < R; ++r)
 #pragma unroll
                     for (int i = 0; i < CPT; ++i) acc[r][i] = fma(av[u][r], (double)bv[u].v[i], acc[r][i]);
         }
@@ -251,7 +250,7 @@ coarse_mm(Grid gr, int n, int lgW, int lg, const double* __restrict__ Ainv, cons
             Pack<T, CPT> bv;
             bv.load(B + (int64_t)j * NC + c0);
 #pragma unroll
-            for (int r = 0; r < CROWS; ++r) {
+            for (int r = 0; r < R; ++r) {
                 const double av = __builtin_nontemporal_load(a[r] + j);
 #pragma unroll
                 for (int i = 0; i < CPT; ++i) acc[r][i] = fma(av, (double)bv.v[i], acc[r][i]);
@@ -260,31 +259,31 @@ coarse_mm(Grid gr, int n, int lgW, int lg, const double* __restrict__ Ainv, cons
     }
     const int wave = t >> 6, lane = t & 63;
 #pragma unroll
-    for (int r = 0; r < CROWS; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int i = 0; i < CPT; ++i) {
             double v = acc[r][i];
             for (int m = TPJ; m < 64; m <<= 1) v += __shfl_xor(v, m, 64);
-            if (lane < TPJ) sh[(wave * CROWS + r) * 64 + c0 + i] = v;
+            if (lane < TPJ) sh[(wave * R + r) * 64 + c0 + i] = v;
         }
     __syncthreads();
-    if (t < CROWS * NC) {
+    if (t < R * NC) {
         const int r = t >> lg, c = t & (NC - 1);
         if (c < W && r0 + r < n && !stopped) {
             double v = sh[r * 64 + c];
 #pragma unroll
-            for (int w = 1; w < WAVES; ++w) v += sh[(w * CROWS + r) * 64 + c];
+            for (int w = 1; w < WAVES; ++w) v += sh[(w * R + r) * 64 + c];
             X[(int64_t)(r0 + r) * NC + c] = (T)v;
         }
     }
 }
 
-template <typename T, int CPT>
+template <typename T, int CPT, int R>
 struct CoarseMM {
     static constexpr int block = BLOCK;
-    using sig = decltype(&coarse_mm<T, CPT, HwGrid>);
+    using sig = decltype(&coarse_mm<T, CPT, R, HwGrid>);
     template <class G, class... A>
-    __device__ static void run(G g, A... a) { coarse_mm<T, CPT>(g, a...); }
+    __device__ static void run(G g, A... a) { coarse_mm<T, CPT, R>(g, a...); }
 };
 
 // ---------------------------------------------------------------- batched PCG

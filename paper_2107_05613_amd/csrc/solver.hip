@@ -670,21 +670,76 @@ inline int log2i(int v) {
     return l;
 }
 
+// X = tail_op B on the first W columns (the batched coarsest solve or folded tail).
+template <class T, int CPT>
+void bcoarse_c(const amge_hierarchy* H, int W, const T* b, T* x, const int* stop, hipStream_t s) {
+    const int R = H->tail_rpb, n = H->tail_n, lgW = log2i(W);
+    const unsigned grid = (unsigned)((n + R - 1) / R);
+    switch (R) {
+        case 1: launch<dev::CoarseMM<T, CPT, 1>>(grid, s, n, lgW, H->lgNC, H->tail_op, b, x, stop); break;
+        case 2: launch<dev::CoarseMM<T, CPT, 2>>(grid, s, n, lgW, H->lgNC, H->tail_op, b, x, stop); break;
+        default: launch<dev::CoarseMM<T, CPT, 4>>(grid, s, n, lgW, H->lgNC, H->tail_op, b, x, stop);
+    }
+}
+
+template <class T>
+void bcoarse(const amge_hierarchy* H, int W, const T* b, T* x, const int* stop, hipStream_t s) {
+    switch (std::min(H->NC, 8)) {   // columns per thread
+        case 1: bcoarse_c<T, 1>(H, W, b, x, stop, s); break;
+        case 2: bcoarse_c<T, 2>(H, W, b, x, stop, s); break;
+        case 4: bcoarse_c<T, 4>(H, W, b, x, stop, s); break;
+        default: bcoarse_c<T, 8>(H, W, b, x, stop, s);
+    }
+}
+
+// Rows per block of the batched dense tail: 4, 2 and 1 timed on the full width (a
+// row's sums do not depend on it), a smaller count kept only if clearly faster (few
+// rows leave too few blocks to fill the device).
+template <class T>
+void tune_tail(amge_hierarchy* H, hipStream_t s) {
+    if (!H->tail_n || H->NC < 2) return;
+    const size_t m = (size_t)H->tail_n * H->NC;
+    amge_hierarchy tmp;   // owns the trial buffers
+    T* B = tmp.alloc<T>(m);
+    T* X = tmp.alloc<T>(m);
+    HIPCHECK(hipMemsetAsync(B, 0, sizeof(T) * m, s));
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    HIPCHECK(hipEventCreate(&e1));
+    int best = 4;
+    float best_ms = 1e30f;
+    for (int R : {4, 2, 1}) {
+        H->tail_rpb = R;
+        bcoarse<T>(H, H->NC, B, X, H->zero_flag, s);
+        float ms = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCHECK(hipEventRecord(e0, s));
+            for (int i = 0; i < 3; ++i) bcoarse<T>(H, H->NC, B, X, H->zero_flag, s);
+            HIPCHECK(hipEventRecord(e1, s));
+            HIPCHECK(hipEventSynchronize(e1));
+            float t = 0;
+            HIPCHECK(hipEventElapsedTime(&t, e0, e1));
+            ms = std::min(ms, t);
+        }
+        HIPCHECK(hipGetLastError());
+        if (verbose())
+            fprintf(stderr, "[amge tune-tail] n %d NC %d rows/block %d: %.2f us\n", H->tail_n, H->NC, R, 1e3 * ms / 3);
+        if (R == 4 || ms < best_ms * 0.95f) {
+            best_ms = ms;
+            best = R;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    H->tail_rpb = best;
+}
+
 template <class T>
 void bvcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, int W, const int* stop,
                    hipStream_t s) {
     const int NC = H->NC;
     if (l == H->tail) {   // the coarsest solve, or the folded coarse tail
-        if (H->tail_n) {
-            const unsigned grid = (unsigned)((H->tail_n + dev::CROWS - 1) / dev::CROWS);
-            const int lgW = log2i(W);
-            switch (std::min(H->NC, 8)) {   // columns per thread
-                case 1: launch<dev::CoarseMM<T, 1>>(grid, s, H->tail_n, lgW, H->lgNC, H->tail_op, b, xout, stop); break;
-                case 2: launch<dev::CoarseMM<T, 2>>(grid, s, H->tail_n, lgW, H->lgNC, H->tail_op, b, xout, stop); break;
-                case 4: launch<dev::CoarseMM<T, 4>>(grid, s, H->tail_n, lgW, H->lgNC, H->tail_op, b, xout, stop); break;
-                default: launch<dev::CoarseMM<T, 8>>(grid, s, H->tail_n, lgW, H->lgNC, H->tail_op, b, xout, stop);
-            }
-        }
+        if (H->tail_n) bcoarse<T>(H, W, b, xout, stop, s);
         return;
     }
     DLevel& L = H->lv[l];
@@ -1162,6 +1217,10 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     H->tail_n = H->nc;
     H->tail_op = H->Ainv;
     fold_tail(H, tl, ainv, s);
+    if (batched) {
+        if (H->opts.precond_bits == 32 && H->lv.size() > 1) tune_tail<float>(H, s);
+        else tune_tail<double>(H, s);
+    }
     HIPCHECK(hipStreamSynchronize(s));
 }
 
