@@ -282,8 +282,9 @@ def stream_reference(nbytes=1 << 30, reps=10):
 
 
 def run_grouped_ab():
-    """Solo streams vs the grouped ensemble on 16 resident 16^3 hierarchies (both types,
-    8 coefficient fields), 128 requests at once, 8 columns each."""
+    """Solo streams vs grouped launches (one ensemble, and four ensembles on their own
+    streams) on 16 resident 16^3 hierarchies (both types, 8 coefficient fields), 128
+    requests at once, 8 columns each."""
     from paper_2107_05613_amd import serve
     mix = serve.build_mix(num=128, seed=0, sizes=(16,), coef_pool=8, slots=8, precond_bits=0)
     first = {}
@@ -291,8 +292,8 @@ def run_grouped_ab():
         first.setdefault(h, j)
     out = {"workload": f"{len(mix.requests)} requests at once on {len(mix.keys)} resident 16^3 hierarchies "
                        f"(H(curl)/H(div), 8 coefficient-jump fields each), 8 columns each"}
-    for name, gmax in (("solo", 0), ("grouped", 16)):
-        srv, ids = serve.make_server(mix, chunk=8, grouped_max_n=gmax)
+    for name, gmax, ens in (("solo", 0, 1), ("grouped", 16, 1), ("grouped_4_ensembles", 16, 4)):
+        srv, ids = serve.make_server(mix, chunk=8, grouped_max_n=gmax, ensembles=ens)
         serve.run(srv, ids, mix, order=list(first.values()))
         done, lat, mk = serve.run(srv, ids, mix)
         members, launches, solo_launches = srv.ensemble()

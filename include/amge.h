@@ -233,18 +233,21 @@ void amge_server_destroy(amge_server* s);
 /* Makes h resident in the server; *id numbers the hierarchies 0, 1, ...
  * Errors: AMGE_ERR_ARG (max_rhs < 2, added twice), AMGE_ERR_BUSY (budget). */
 amge_status amge_server_add(amge_server* s, amge_hierarchy* h, int32_t* id);
-/* Like amge_server_add, but h joins the server's ensemble: one PCG iteration of every
- * hierarchy added this way runs as a single captured graph in which the same level
- * operator of several hierarchies is one grouped launch (each workgroup of a grouped
- * launch works for one member, with that member's operands), so hierarchies whose
- * iterations are chains of short, latency-bound launches (small problems) share their
- * launches.  The ensemble advances all its members together, on all their columns, on
- * one stream of its own; it is recaptured at its next chunk after a member joins.  A
- * request's result is bitwise the same as on a hierarchy added with amge_server_add.
- * Errors as amge_server_add. */
-amge_status amge_server_add_grouped(amge_server* s, amge_hierarchy* h, int32_t* id);
-/* The ensemble: number of members, kernels in its captured iteration, and kernels the
- * members' iterations take when captured one by one (0 before its first chunk). */
+/* Like amge_server_add, but h joins ensemble number `ensemble` (0 <= ensemble < 16) of
+ * the server: one PCG iteration of every hierarchy of an ensemble runs as a single
+ * captured graph in which the same level operator of several hierarchies is one grouped
+ * launch (each workgroup of a grouped launch works for one member, with that member's
+ * operands), so hierarchies whose iterations are chains of short, latency-bound launches
+ * (small problems) share their launches.  An ensemble advances all its members
+ * together, on all their columns, on one stream of its own (different ensembles and
+ * solo hierarchies advance concurrently); it is recaptured at its next chunk after a
+ * member joins.  A request's result is bitwise the same as on a hierarchy added with
+ * amge_server_add.  Errors as amge_server_add; AMGE_ERR_ARG for an ensemble number out
+ * of range. */
+amge_status amge_server_add_grouped(amge_server* s, amge_hierarchy* h, int32_t ensemble, int32_t* id);
+/* The ensembles, summed: number of members, kernels in their captured iterations, and
+ * kernels the members' iterations take when captured one by one (an ensemble counts 0
+ * before its first chunk). */
 amge_status amge_server_ensemble(const amge_server* s, int32_t* members, int32_t* launches,
                                  int32_t* solo_launches);
 /* Work footprint of one request on hierarchy id, in bytes. */

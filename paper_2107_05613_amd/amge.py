@@ -79,7 +79,7 @@ def _load():
         "amge_server_create": (i32, [C.c_size_t, C.c_size_t, i32, C.POINTER(vp)]),
         "amge_server_destroy": (None, [vp]),
         "amge_server_add": (i32, [vp, vp, C.POINTER(i32)]),
-        "amge_server_add_grouped": (i32, [vp, vp, C.POINTER(i32)]),
+        "amge_server_add_grouped": (i32, [vp, vp, i32, C.POINTER(i32)]),
         "amge_server_ensemble": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]),
         "amge_server_request_bytes": (i32, [vp, i32, C.POINTER(C.c_size_t)]),
         "amge_server_submit": (i32, [vp, i32, vp, vp, f64, i32, i32, C.c_int64, vp]),
@@ -328,11 +328,14 @@ class Server:
         except Exception:
             pass
 
-    def add(self, H: "Hierarchy", grouped=False) -> int:
-        """grouped: H joins the ensemble, whose members' iterations share grouped launches."""
+    def add(self, H: "Hierarchy", grouped=False, ensemble=0) -> int:
+        """grouped: H joins ensemble number `ensemble`, whose members' iterations share
+        grouped launches."""
         i = C.c_int32()
-        add = _lib.amge_server_add_grouped if grouped else _lib.amge_server_add
-        _check(add(self._h, H.handle, C.byref(i)))
+        if grouped:
+            _check(_lib.amge_server_add_grouped(self._h, H.handle, int(ensemble), C.byref(i)))
+        else:
+            _check(_lib.amge_server_add(self._h, H.handle, C.byref(i)))
         self._rows.append(H.rows[0])
         self._hier.append(H)
         return i.value
@@ -360,7 +363,8 @@ class Server:
                 return out
 
     def ensemble(self):
-        """(members, kernels per grouped iteration, kernels of the members' own iterations)."""
+        """Summed over the ensembles: (members, kernels per grouped iteration, kernels of
+        the members' own iterations)."""
         m, k, k1 = C.c_int32(), C.c_int32(), C.c_int32()
         _check(_lib.amge_server_ensemble(self._h, C.byref(m), C.byref(k), C.byref(k1)))
         return m.value, k.value, k1.value

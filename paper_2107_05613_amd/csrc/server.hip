@@ -8,11 +8,12 @@
 // the other columns stay in flight: continuous batching at the granularity of a PCG
 // iteration.  Different hierarchies advance concurrently on their own streams.
 //
-// Hierarchies added as grouped form the server's ensemble instead: one PCG iteration of
-// every member is captured as a single graph in which the same level operator of the
-// members runs as one grouped launch (grouped.hpp), so small hierarchies, whose
-// iterations are chains of short launches, share their launches.  The ensemble runs its
-// chunks on its own stream; every member computes exactly what it computes alone.
+// Hierarchies added as grouped join one of the server's ensembles instead: one PCG
+// iteration of every member of an ensemble is captured as a single graph in which the
+// same level operator of the members runs as one grouped launch (grouped.hpp), so small
+// hierarchies, whose iterations are chains of short launches, share their launches.
+// Each ensemble runs its chunks on its own stream (ensembles advance concurrently, like
+// solo hierarchies); every member computes exactly what it computes alone.
 //
 // Admission: a hierarchy is made resident only if its device footprint fits the
 // hierarchy budget; a request is admitted when its hierarchy has a free column and the
@@ -121,8 +122,9 @@ struct Group {
     uint64_t turn = 0;             // when the group last finished a chunk (scheduling order)
 };
 
-// The grouped hierarchies: one captured graph runs an iteration of all of them (on all
-// their columns), recaptured when a member joins.
+// A set of grouped hierarchies: one captured graph runs an iteration of all of them (on
+// all their columns), recaptured when a member joins.
+constexpr int MAX_ENSEMBLES = 16;
 struct Ensemble {
     std::vector<Group*> members;
     hipStream_t stream = nullptr;
@@ -153,7 +155,7 @@ struct amge_server {
     double queued_ms = 0;             // estimated GPU time of the chunks in flight
     uint64_t clock = 0;               // scheduling turns
     std::vector<std::unique_ptr<Group>> groups;
-    Ensemble ens;
+    std::vector<std::unique_ptr<Ensemble>> ens;
     std::vector<Request> reqs;        // request table (indices stay valid)
     std::vector<int> free_reqs;       // reusable entries of the table
     std::deque<int> queue;            // submitted, not admitted, in arrival order
@@ -161,10 +163,12 @@ struct amge_server {
     std::vector<hipEvent_t> event_pool;
 
     ~amge_server() {
-        if (ens.stream) (void)hipStreamSynchronize(ens.stream);
-        if (ens.exec) (void)hipGraphExecDestroy(ens.exec);
-        if (ens.ev_chunk) (void)hipEventDestroy(ens.ev_chunk);
-        if (ens.stream) (void)hipStreamDestroy(ens.stream);
+        for (auto& e : ens) {
+            if (e->stream) (void)hipStreamSynchronize(e->stream);
+            if (e->exec) (void)hipGraphExecDestroy(e->exec);
+            if (e->ev_chunk) (void)hipEventDestroy(e->ev_chunk);
+            if (e->stream) (void)hipStreamDestroy(e->stream);
+        }
         for (auto& g : groups) {
             (void)hipStreamSynchronize(g->H->gstream);
             if (g->cs_host) (void)hipHostFree(g->cs_host);
@@ -230,16 +234,16 @@ struct amge_server {
         return true;
     }
 
-    bool reap_ensemble() {
-        if (!ens.busy) return false;
-        hipError_t e = hipEventQuery(ens.ev_chunk);
+    bool reap_ensemble(Ensemble& en) {
+        if (!en.busy) return false;
+        hipError_t e = hipEventQuery(en.ev_chunk);
         if (e == hipErrorNotReady) return false;
         HIPCHECK(e);
-        ens.busy = false;
-        queued_ms -= ens.chunk_ms;
+        en.busy = false;
+        queued_ms -= en.chunk_ms;
         if (queued_ms < 1e-9) queued_ms = 0;
-        ens.turn = ++clock;
-        for (Group* g : ens.members) collect(*g);
+        en.turn = ++clock;
+        for (Group* g : en.members) collect(*g);
         return true;
     }
 
@@ -311,25 +315,30 @@ struct amge_server {
     // new chunk of a small hierarchy waits behind the chunks of large ones.  A chunk has as
     // many iterations as fit SCHED_CHUNK_MS (at least one, at most `chunk`).
     bool launch() {
-        std::vector<Group*> cand;   // null: the ensemble
+        struct Cand {
+            Group* g;      // a solo hierarchy, or
+            Ensemble* e;   // an ensemble
+            uint64_t turn;
+        };
+        std::vector<Cand> cand;
         for (auto& gp : groups)
-            if (!gp->grouped && !gp->chunk_busy && gp->active > 0) cand.push_back(gp.get());
-        if (!ens.busy)
-            for (Group* g : ens.members)
-                if (g->active > 0) {
-                    cand.push_back(nullptr);
-                    break;
-                }
-        auto turn = [&](const Group* g) { return g ? g->turn : ens.turn; };
-        std::sort(cand.begin(), cand.end(), [&](const Group* a, const Group* b) { return turn(a) < turn(b); });
+            if (!gp->grouped && !gp->chunk_busy && gp->active > 0) cand.push_back({gp.get(), nullptr, gp->turn});
+        for (auto& ep : ens)
+            if (!ep->busy)
+                for (Group* g : ep->members)
+                    if (g->active > 0) {
+                        cand.push_back({nullptr, ep.get(), ep->turn});
+                        break;
+                    }
+        std::sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) { return a.turn < b.turn; });
         bool any = false;
-        for (Group* gp : cand) {
-            if (!gp) {
-                if (!launch_ensemble()) break;
+        for (const Cand& cd : cand) {
+            if (cd.e) {
+                if (!launch_ensemble(*cd.e)) break;
                 any = true;
                 continue;
             }
-            Group& g = *gp;
+            Group& g = *cd.g;
             amge_hierarchy* H = g.H;
             // active width: the columns up to the highest occupied one (requests take the
             // lowest free column)
@@ -355,31 +364,31 @@ struct amge_server {
         return any;
     }
 
-    // A chunk of the ensemble (all members, all columns); false if the queue is full.
-    bool launch_ensemble() {
-        if (ens.stale || !ens.exec) {
+    // A chunk of an ensemble (all members, all columns); false if the queue is full.
+    bool launch_ensemble(Ensemble& en) {
+        if (en.stale || !en.exec) {
             std::vector<amge_hierarchy*> hs;
-            for (Group* g : ens.members) hs.push_back(g->H);
-            hipGraphExecDestroy_if(ens.exec);
-            ens.exec = capture_grouped_iteration(hs, ens.stream, &ens.launches, &ens.solo_launches);
-            ens.stale = false;
+            for (Group* g : en.members) hs.push_back(g->H);
+            hipGraphExecDestroy_if(en.exec);
+            en.exec = capture_grouped_iteration(hs, en.stream, &en.launches, &en.solo_launches);
+            en.stale = false;
         }
         // members without requests return from every kernel at once
-        double it_ms = ens.launches * SCHED_LAUNCH_MS;
-        for (Group* g : ens.members)
+        double it_ms = en.launches * SCHED_LAUNCH_MS;
+        for (Group* g : en.members)
             if (g->active > 0) it_ms += g->mat_ms + g->H->NC * g->per_col_ms;
         const int k = std::max(1, std::min(chunk, (int)(SCHED_CHUNK_MS / it_ms)));
         const double est = k * it_ms;
         if (queued_ms > 0 && queued_ms + est > SCHED_QUEUE_MS) return false;
-        for (int i = 0; i < k; ++i) HIPCHECK(hipGraphLaunch(ens.exec, ens.stream));
-        for (Group* g : ens.members) {
+        for (int i = 0; i < k; ++i) HIPCHECK(hipGraphLaunch(en.exec, en.stream));
+        for (Group* g : en.members) {
             HIPCHECK(hipMemcpyAsync(g->cs_host, g->H->cs, sizeof(dev::ColState) * g->H->NC, hipMemcpyDeviceToHost,
-                                    ens.stream));
+                                    en.stream));
             g->chunk_busy = true;
         }
-        HIPCHECK(hipEventRecord(ens.ev_chunk, ens.stream));
-        ens.busy = true;
-        ens.chunk_ms = est;
+        HIPCHECK(hipEventRecord(en.ev_chunk, en.stream));
+        en.busy = true;
+        en.chunk_ms = est;
         queued_ms += est;
         return true;
     }
@@ -390,7 +399,9 @@ struct amge_server {
     }
 
     bool busy() const {
-        if (!queue.empty() || ens.busy) return true;
+        if (!queue.empty()) return true;
+        for (auto& e : ens)
+            if (e->busy) return true;
         for (auto& g : groups)
             if (g->chunk_busy || g->active || !g->extracting.empty()) return true;
         return false;
@@ -432,8 +443,10 @@ extern "C" amge_status amge_server_create(size_t hierarchy_budget, size_t inflig
 extern "C" void amge_server_destroy(amge_server* s) { delete s; }
 
 namespace {
-amge_status server_add(amge_server* s, amge_hierarchy* h, int32_t* id, bool grouped) {
+amge_status server_add(amge_server* s, amge_hierarchy* h, int32_t* id, int ensemble) {
+    const bool grouped = ensemble >= 0;
     return sguard([&]() -> amge_status {
+        if (ensemble >= MAX_ENSEMBLES) fail(AMGE_ERR_ARG, "ensemble index out of range");
         if (!s || !h || !id) fail(AMGE_ERR_ARG, "null argument");
         if (h->NC < 2) fail(AMGE_ERR_ARG, "hierarchy needs max_rhs >= 2 to serve");
         for (auto& g : s->groups)
@@ -468,12 +481,14 @@ amge_status server_add(amge_server* s, amge_hierarchy* h, int32_t* id, bool grou
         HIPCHECK(hipEventCreateWithFlags(&g->ev_chunk, hipEventDisableTiming));
         HIPCHECK(hipEventCreateWithFlags(&g->ev_extract, hipEventDisableTiming));
         if (grouped) {
-            if (!s->ens.stream) {
-                HIPCHECK(hipStreamCreateWithFlags(&s->ens.stream, hipStreamNonBlocking));
-                HIPCHECK(hipEventCreateWithFlags(&s->ens.ev_chunk, hipEventDisableTiming));
+            while ((int)s->ens.size() <= ensemble) s->ens.push_back(std::make_unique<Ensemble>());
+            Ensemble& en = *s->ens[ensemble];
+            if (!en.stream) {
+                HIPCHECK(hipStreamCreateWithFlags(&en.stream, hipStreamNonBlocking));
+                HIPCHECK(hipEventCreateWithFlags(&en.ev_chunk, hipEventDisableTiming));
             }
             g->grouped = true;
-            g->stream = s->ens.stream;
+            g->stream = en.stream;
         } else {
             g->stream = h->gstream;
             for (int W = 1; W <= h->NC; W *= 2) capture_iteration(h, W);
@@ -484,8 +499,8 @@ amge_status server_add(amge_server* s, amge_hierarchy* h, int32_t* id, bool grou
         s->resident += g->footprint;
         *id = (int32_t)s->groups.size();
         if (grouped) {
-            s->ens.members.push_back(g.get());
-            s->ens.stale = true;
+            s->ens[ensemble]->members.push_back(g.get());
+            s->ens[ensemble]->stale = true;
         }
         s->groups.push_back(std::move(g));
         return AMGE_OK;
@@ -494,20 +509,30 @@ amge_status server_add(amge_server* s, amge_hierarchy* h, int32_t* id, bool grou
 }  // namespace
 
 extern "C" amge_status amge_server_add(amge_server* s, amge_hierarchy* h, int32_t* id) {
-    return server_add(s, h, id, false);
+    return server_add(s, h, id, -1);
 }
 
-extern "C" amge_status amge_server_add_grouped(amge_server* s, amge_hierarchy* h, int32_t* id) {
-    return server_add(s, h, id, true);
+extern "C" amge_status amge_server_add_grouped(amge_server* s, amge_hierarchy* h, int32_t ensemble, int32_t* id) {
+    if (ensemble < 0) {
+        set_last_error("ensemble index must be >= 0");
+        return AMGE_ERR_ARG;
+    }
+    return server_add(s, h, id, ensemble);
 }
 
 extern "C" amge_status amge_server_ensemble(const amge_server* s, int32_t* members, int32_t* launches,
                                             int32_t* solo_launches) {
     return sguard([&]() -> amge_status {
         if (!s) fail(AMGE_ERR_ARG, "null argument");
-        if (members) *members = (int32_t)s->ens.members.size();
-        if (launches) *launches = s->ens.launches;
-        if (solo_launches) *solo_launches = s->ens.solo_launches;
+        int32_t m = 0, k = 0, k1 = 0;
+        for (auto& e : s->ens) {
+            m += (int32_t)e->members.size();
+            k += e->launches;
+            k1 += e->solo_launches;
+        }
+        if (members) *members = m;
+        if (launches) *launches = k;
+        if (solo_launches) *solo_launches = k1;
         return AMGE_OK;
     });
 }
@@ -556,7 +581,7 @@ extern "C" amge_status amge_server_progress(amge_server* s, int32_t wait, amge_c
                 moved |= s->reap_extractions(*g);
                 moved |= s->reap_chunk(*g);
             }
-            moved |= s->reap_ensemble();
+            for (auto& e : s->ens) moved |= s->reap_ensemble(*e);
             moved |= s->admit();
             moved |= s->launch();
             if (!s->done.empty() || !wait || !s->busy()) break;

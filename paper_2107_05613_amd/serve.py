@@ -59,11 +59,17 @@ def build_mix(num=256, seed=0, sizes=(16, 24, 32, 48, 64), coef_pool=2, slots=8,
     return Mix(reqs, keys, hs, hid_of, rhs, xs, tb, ts)
 
 
-def make_server(mix, hierarchy_budget=0, inflight_budget=0, chunk=8, grouped_max_n=0):
+def make_server(mix, hierarchy_budget=0, inflight_budget=0, chunk=8, grouped_max_n=0, ensembles=1):
     """Server with every hierarchy of the mix resident; those with n <= grouped_max_n
-    join the ensemble (their iterations share grouped launches)."""
+    join one of `ensembles` ensembles in turn (their iterations share grouped launches)."""
     srv = amge.Server(hierarchy_budget, inflight_budget, chunk)
-    ids = [srv.add(h, grouped=key[1] <= grouped_max_n) for h, key in zip(mix.hierarchies, mix.keys)]
+    ids, k = [], 0
+    for h, key in zip(mix.hierarchies, mix.keys):
+        if key[1] <= grouped_max_n:
+            ids.append(srv.add(h, grouped=True, ensemble=k % ensembles))
+            k += 1
+        else:
+            ids.append(srv.add(h))
     return srv, ids
 
 

@@ -64,11 +64,12 @@ def requests(res, num, seed=0):
 
 def serve(res, reqs, order, inflight_budget=0, maxit=None, watch=None, grouped=None, info=None):
     """Serves the requests of `order` (all submitted at once, in that order); returns
-    {request: (status, iters, relres, x)}.  grouped[i]: hierarchy i joins the ensemble;
-    info (a list) receives the server's ensemble figures."""
+    {request: (status, iters, relres, x)}.  grouped[i]: None for a solo hierarchy, else
+    the ensemble hierarchy i joins; info (a list) receives the server's ensemble figures."""
     from paper_2107_05613_amd import amge
     srv = amge.Server(inflight_budget=inflight_budget, chunk=2)
-    ids = [srv.add(H, grouped=bool(grouped and grouped[i])) for i, H in enumerate(res.H)]
+    ids = [srv.add(H) if not grouped or grouped[i] is None else srv.add(H, grouped=True, ensemble=grouped[i])
+           for i, H in enumerate(res.H)]
     xs = {j: torch.full((res.n1[reqs[j][0]],), 3.0, dtype=torch.float64, device="cuda") for j in order}
     for j in order:
         h, b = reqs[j]
@@ -118,18 +119,21 @@ class _Joined:
 
 def test_grouped_ensemble_bitwise():
     """a9 grouped launches: the six hierarchies (H(curl) and H(div), FP32 and FP64
-    V-cycles) served as one ensemble, and half of them grouped beside solo ones, give
-    every request bitwise the result it gets with every hierarchy served on its own; the
-    ensemble's graph has fewer kernels than its members' own graphs together."""
+    V-cycles) served as one ensemble, as two ensembles, and half of them grouped beside
+    solo ones, give every request bitwise the result it gets with every hierarchy served
+    on its own; the ensemble's graph has fewer kernels than its members' own graphs
+    together."""
+    from paper_2107_05613_amd import amge
     res = _Joined(resident(32), resident(64))
     reqs = requests(res, 24, seed=3)
     order = list(range(len(reqs)))
     solo = serve(res, reqs, order)
     info = []
-    allg = serve(res, reqs, order, grouped=[True] * len(res.H), info=info)
-    half = serve(res, reqs, order, grouped=[i % 2 == 0 for i in range(len(res.H))])
+    allg = serve(res, reqs, order, grouped=[0] * len(res.H), info=info)
+    two = serve(res, reqs, order, grouped=[i % 2 for i in range(len(res.H))])
+    half = serve(res, reqs, order, grouped=[3 if i % 2 == 0 else None for i in range(len(res.H))])
     for j in order:
-        for other in (allg, half):
+        for other in (allg, two, half):
             o = other[j]
             assert o[0] == solo[j][0] == 0, (j, o[:3], solo[j][:3])
             assert o[1] == solo[j][1] and o[2] == solo[j][2], (j, o[:3], solo[j][:3])
@@ -138,6 +142,13 @@ def test_grouped_ensemble_bitwise():
     print(f"\n[ensemble] {members} members: {launches} kernels per iteration vs {solo_launches} alone", flush=True)
     assert members == len(res.H)
     assert 0 < launches < solo_launches
+    srv = amge.Server()
+    with pytest.raises(amge.AmgeError) as ei:
+        srv.add(res.H[0], grouped=True, ensemble=16)
+    assert ei.value.code == -1
+    with pytest.raises(amge.AmgeError):
+        srv.add(res.H[0], grouped=True, ensemble=-1)
+    srv.close()
 
 
 def test_grouped_ensemble_recapture_and_split():
