@@ -36,7 +36,7 @@ struct DSell {
     float* v32 = nullptr;
     uint16_t* lead = nullptr; // split rows: leading entries per slot that read the first operand
     bool stream = false;      // FP32 matrix streams read with non-temporal loads
-    bool deep = false;        // K = 1 with long rows on a large level: 8 entries' loads in flight
+    bool deep = false;        // long rows per lane in a large matrix: 8 entries' loads in flight
     int fixedw = 0;           // incidence with fixedw entries in every row: fent (n x fixedw
     uint32_t* fent = nullptr; //   row-major words) replaces the sliced layout
 };

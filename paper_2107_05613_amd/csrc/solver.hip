@@ -46,10 +46,12 @@ DSell upload_sell(amge_hierarchy* H, const Csr& A, bool incidence, int K, hipStr
     d.K = K;
     d.nslices = h.nslices;
     d.stored = h.sptr[h.nslices];
-    // one lane per row with long rows on a large level (the fine A_k): eight entries'
-    // loads in flight per lane (measured on the 64^3 H(curl) fine level: FP32 sweep 40.8
-    // -> 38.4 us, FP64 83.5 -> 77.9 us; four stay better for short rows and small levels)
-    d.deep = !incidence && K == 1 && A.nrows >= (1 << 20) && A.nnz() >= 12 * (int64_t)A.nrows;
+    // long rows for their lanes (>= 12 entries per lane) in a large matrix (>= 2^23
+    // entries): eight entries' loads in flight per lane.  Measured on the 64^3 H(curl)
+    // hierarchy: fine A_k (one lane per row) FP32 sweep 40.8 -> 38.4 us, FP64 83.5 -> 77.9
+    // us; adding the level-1 auxiliary and restriction matrices (4 and 8 lanes per row)
+    // FP32 solve 12.53 -> 12.38 ms.  Four stay better for short rows and small levels.
+    d.deep = !incidence && K <= 8 && A.nnz() >= (1 << 23) && A.nnz() >= 12 * (int64_t)K * A.nrows;
     d.sptr = upload(H, h.sptr.data(), h.sptr.size(), s);
     d.srow = upload(H, h.srow.data(), h.srow.size(), s);
     if (incidence) {
@@ -107,9 +109,9 @@ void sell_ku(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T*
 template <class T, int K>
 void sell_k(const DSell& M, int mode, const T* x, const T* b, const T* dinv, T* y, T* yd, hipStream_t s,
             const int* stop) {
-    if constexpr (K == 1) {
+    if constexpr (K <= 8) {
         if (M.deep) {
-            sell_ku<T, 1, 8>(M, mode, x, b, dinv, y, yd, s, stop);
+            sell_ku<T, K, 8>(M, mode, x, b, dinv, y, yd, s, stop);
             return;
         }
     }
