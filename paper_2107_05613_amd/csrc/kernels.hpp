@@ -309,6 +309,37 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
     return block_sum(v, sh);
 }
 
+// N sums of NRED partials each, in the order of sum_partials (so with the same
+// results), with every load issued before the first reduction and one exchange through
+// LDS for all N (sh: N * (WAVES + 1) doubles).
+template <int N>
+__device__ __forceinline__ void sum_partials_n(const double* const (&part)[N], double* sh, double (&out)[N]) {
+    static_assert(NRED % BLOCK == 0, "partials per thread");
+    double v[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = 0;
+#pragma unroll
+    for (int i = 0; i < NRED / BLOCK; ++i)
+#pragma unroll
+        for (int q = 0; q < N; ++q) v[q] += part[q][threadIdx.x + i * BLOCK];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        v[q] = wave_sum(v[q]);
+        if (lane == 0) sh[q * WAVES + wave] = v[q];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < N) {
+        double t = 0;
+        for (int w = 0; w < WAVES; ++w) t += sh[threadIdx.x * WAVES + w];
+        sh[N * WAVES + threadIdx.x] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q) out[q] = sh[N * WAVES + q];
+    __syncthreads();
+}
+
 // q = A p (FP64 sliced ELL) and partial sums of p.q.  NRED blocks, each over a
 // contiguous range of slices; UNR as in k_sell.
 template <int K, bool C16, int UNR = 4>
@@ -354,10 +385,11 @@ k_pcg_xr(int n, const double* __restrict__ part_pq, const double* __restrict__ p
          double* __restrict__ r, float* __restrict__ r32, float* __restrict__ rd32,
          const float* __restrict__ dinv32, double* __restrict__ rd64, const double* __restrict__ dinv64,
          int* __restrict__ done, int* __restrict__ flag) {
-    __shared__ double sh[WAVES + 1];
+    __shared__ double sh[2 * (WAVES + 1)];
     const int stopped = *done;   // tested after the reductions, whose loads it overlaps
-    const double pq = sum_partials(part_pq, sh);
-    const double delta = sum_partials(part_delta, sh);
+    double sums[2];
+    sum_partials_n<2>({part_pq, part_delta}, sh, sums);
+    const double pq = sums[0], delta = sums[1];
     if (stopped) return;
     if (!(pq > 0) || !isfinite(pq)) {      // breakdown: recorded, iterate no further
         if (blockIdx.x == 0 && threadIdx.x == 0) *flag = 1;
@@ -421,14 +453,13 @@ k_pcg_p(int n, const double* __restrict__ part_new, const double* __restrict__ p
         const TZ* __restrict__ z, double* __restrict__ p, PcgStatus* __restrict__ st,
         int* __restrict__ done, const int* __restrict__ flag, const int* __restrict__ it_in,
         int* __restrict__ it_out, PcgRecord* __restrict__ ring) {
-    __shared__ double sh[WAVES + 1];
+    __shared__ double sh[4 * (WAVES + 1)];
     const int stopped = *done;   // tested after the reductions, whose loads it overlaps
     const int it = *it_in, maxit = st->maxit, stop_l2 = st->stop_l2;
     const double rtol = st->rtol;
-    const double dnew = sum_partials(part_new, sh);
-    const double rzold = sum_partials(part_new + NRED, sh);
-    const double rr = sum_partials(part_new + 2 * NRED, sh);
-    const double dold = sum_partials(part_old, sh);
+    double sums[4];
+    sum_partials_n<4>({part_new, part_new + NRED, part_new + 2 * NRED, part_old}, sh, sums);
+    const double dnew = sums[0], rzold = sums[1], rr = sums[2], dold = sums[3];
     if (stopped) return;
     const double rel = stop_l2 ? sqrt(rr) / st->bnorm : sqrt(fmax(dnew, 0.0) / st->delta0);
     const bool stop = (*flag != 0) || (rtol > 0 && rel <= rtol) || (it + 1 >= maxit) || !isfinite(dnew);
