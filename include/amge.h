@@ -191,10 +191,12 @@ const char* amge_last_error(void);
  * cost of the method pays off (section 5).
  *
  * Every hierarchy added to a server runs the batched PCG on its own stream, one column
- * per request.  Between chunks of iterations a request is loaded into a free column of
- * its hierarchy while the other columns stay in flight (continuous batching), and the
- * hierarchies advance concurrently on the device.  The arithmetic of a column does not
- * depend on the other columns, so a request's result is the same alone and in a mix.
+ * per request (or, added with amge_server_add_grouped, together with the other members
+ * of its ensemble in grouped launches).  Between chunks of iterations a request is
+ * loaded into a free column of its hierarchy while the other columns stay in flight
+ * (continuous batching), and the hierarchies advance concurrently on the device.  The
+ * arithmetic of a column does not depend on the other columns, so a request's result is
+ * the same alone and in a mix.
  *
  * Admission by device memory:
  *   hierarchy_budget  bytes; amge_server_add fails with AMGE_ERR_BUSY if the sum of the

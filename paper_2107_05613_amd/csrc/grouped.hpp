@@ -11,8 +11,9 @@
 //
 // The host side: launch<Op>(grid, stream, operands...) launches the body of Op solo, or,
 // while a LaunchRecorder is installed on the calling thread, appends the launch to it
-// instead.  The serving engine records one PCG iteration of each hierarchy of a group,
-// merges the records (group_launches) and captures the merged launches as one graph.
+// instead.  The serving engine records one PCG iteration of each hierarchy of an
+// ensemble, merges the records (group_launches) and captures the merged launches as one
+// graph.
 #pragma once
 
 #include <hip/hip_runtime.h>
