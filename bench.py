@@ -281,10 +281,13 @@ def stream_reference(nbytes=1 << 30, reps=10):
     return out
 
 
-def run_grouped_ab():
+GROUPED_CONFIGS = (("solo", 0, 1), ("grouped", 16, 1), ("grouped_4_ensembles", 16, 4))
+
+
+def run_grouped_ab(only=None):
     """Solo streams vs grouped launches (one ensemble, and four ensembles on their own
     streams) on 16 resident 16^3 hierarchies (both types, 8 coefficient fields), 128
-    requests at once, 8 columns each."""
+    requests at once, 8 columns each.  only: run that configuration alone."""
     from paper_2107_05613_amd import serve
     mix = serve.build_mix(num=128, seed=0, sizes=(16,), coef_pool=8, slots=8, precond_bits=0)
     first = {}
@@ -292,7 +295,9 @@ def run_grouped_ab():
         first.setdefault(h, j)
     out = {"workload": f"{len(mix.requests)} requests at once on {len(mix.keys)} resident 16^3 hierarchies "
                        f"(H(curl)/H(div), 8 coefficient-jump fields each), 8 columns each"}
-    for name, gmax, ens in (("solo", 0, 1), ("grouped", 16, 1), ("grouped_4_ensembles", 16, 4)):
+    for name, gmax, ens in GROUPED_CONFIGS:
+        if only and name != only:
+            continue
         srv, ids = serve.make_server(mix, chunk=8, grouped_max_n=gmax, ensembles=ens)
         serve.run(srv, ids, mix, order=list(first.values()))
         done, lat, mk = serve.run(srv, ids, mix)
@@ -320,6 +325,9 @@ def main():
                     help="requests of the serving mix run beside the main workload (0 to skip)")
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--grouped-ab-only", choices=[c[0] for c in GROUPED_CONFIGS],
+                    help="run only that configuration of the small-hierarchy serving burst and print its JSON "
+                         "(for kernel traces)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -336,6 +344,10 @@ def main():
     import torch
     from paper_2107_05613_amd import amge
     from paper_2107_05613_amd import workloads as W
+
+    if args.grouped_ab_only:
+        print(json.dumps(run_grouped_ab(only=args.grouped_ab_only)), flush=True)
+        return 0
 
     w = W.WORKLOADS[args.workload]
     a, b = W.coefficients(w)
