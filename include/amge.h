@@ -26,8 +26,9 @@
  *   - Negative return values are errors, amge_last_error() gives a message for
  *     the calling thread.  AMGE_NOT_CONVERGED is a warning: outputs are valid.
  *   - A hierarchy is read-only after set-up apart from its work buffers: calls
- *     that use one hierarchy must not overlap in time (use one hierarchy, or one
- *     context, per concurrent stream).
+ *     that use one hierarchy must not overlap in time (use one hierarchy per
+ *     concurrent stream, or the serving engine, which multiplexes requests onto the
+ *     columns of a hierarchy).
  */
 #ifndef AMGE_H
 #define AMGE_H
