@@ -125,7 +125,8 @@ struct amge_hierarchy {
     amge::dev::BatchStatus* bs = nullptr;
     int* zero_flag = nullptr;    // a device 0: the stop flag of launches outside PCG iterations
     hipStream_t gstream = nullptr;   // the hierarchy's stream for graph capture / replay
-    hipGraphExec_t gexec[7] = {};    // one captured batched PCG iteration per active width 2^i
+    hipGraphExec_t gexec[7][2] = {}; // captured batched PCG iteration per active width 2^i and parity
+    int bpar = 0;                    // parity of the next batched iteration: z block bpar is the new z
     hipGraphExec_t pexec[2] = {};    // one captured single-column PCG iteration per buffer parity
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     // single-column PCG: host ring of iteration records (pinned, written by the device)
@@ -140,8 +141,9 @@ struct amge_hierarchy {
     amge::Probe probe;
     ~amge_hierarchy() {
         if (gstream) (void)hipStreamSynchronize(gstream);
-        for (hipGraphExec_t g : gexec)
-            if (g) (void)hipGraphExecDestroy(g);
+        for (auto& gw : gexec)
+            for (hipGraphExec_t g : gw)
+                if (g) (void)hipGraphExecDestroy(g);
         for (hipGraphExec_t g : pexec)
             if (g) (void)hipGraphExecDestroy(g);
         for (hipEvent_t e : pev)
@@ -173,14 +175,15 @@ struct amge_hierarchy {
 };
 
 namespace amge {
-// One batched PCG iteration on the first W columns (W a power of two <= NC) of a
-// hierarchy, captured as a HIP graph on its own stream on first use.
-hipGraphExec_t capture_iteration(amge_hierarchy* H, int W);
+// One batched PCG iteration of parity par (z block par receives the new z) on the
+// first W columns (W a power of two <= NC) of a hierarchy, captured as a HIP graph on
+// its own stream on first use.  Iterations must alternate parities (H->bpar).
+hipGraphExec_t capture_iteration(amge_hierarchy* H, int W, int par);
 
-// One batched PCG iteration of every hierarchy of hs (all NC columns of each), with the
+// One batched PCG iteration of parity par of every hierarchy of hs (all NC columns of each), with the
 // same level operator of several hierarchies run in one grouped launch, captured as one
 // graph on stream s.  Every hierarchy computes exactly what its own captured iteration
 // computes.  launches / solo_launches: kernels in the graph / in the separate graphs.
-hipGraphExec_t capture_grouped_iteration(const std::vector<amge_hierarchy*>& hs, hipStream_t s, int* launches,
-                                         int* solo_launches);
+hipGraphExec_t capture_grouped_iteration(const std::vector<amge_hierarchy*>& hs, int par, hipStream_t s,
+                                         int* launches, int* solo_launches);
 }  // namespace amge

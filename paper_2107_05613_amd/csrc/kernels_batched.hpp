@@ -466,12 +466,13 @@ struct BpcgXr {
     __device__ static void run(G g, A... a) { bpcg_xr(g, a...); }
 };
 
-// Z = Zv after using the old Z: partials of r.z_new, r.z_old, r.r per column.  Z has the
-// preconditioner's precision (an FP32 z is exact in FP32), sums are FP64.
+// Partials of r.z_new, r.z_old, r.r per column (the new and old z are the two z blocks,
+// alternating with the iteration parity).  z has the preconditioner's precision (an
+// FP32 z is exact in FP32), sums are FP64.
 template <typename TZ, class G>
 __device__ __forceinline__ void
-bpcg_dots(G g, int n, int W, int NC, const TZ* __restrict__ Zv, TZ* __restrict__ Z, const double* __restrict__ R,
-            double* __restrict__ part, const BatchStatus* __restrict__ bs) {
+bpcg_dots(G g, int n, int W, int NC, const TZ* __restrict__ Znew, const TZ* __restrict__ Zold,
+          const double* __restrict__ R, double* __restrict__ part, const BatchStatus* __restrict__ bs) {
     __shared__ double sh[BLOCK];
     if (bs->all_done) return;
     const int rpb = BLOCK / NC;
@@ -479,9 +480,7 @@ bpcg_dots(G g, int n, int W, int NC, const TZ* __restrict__ Zv, TZ* __restrict__
     double a = 0, b = 0, d = 0;
     for (int row = g.bid() * rpb + threadIdx.x / NC; c < W && row < n; row += g.nb() * rpb) {
         const int64_t t = (int64_t)row * NC + c;
-        const TZ znv = Zv[t];
-        const double zn = (double)znv, zo = (double)Z[t], r = R[t];
-        Z[t] = znv;
+        const double zn = (double)Znew[t], zo = (double)Zold[t], r = R[t];
         a = fma(r, zn, a);
         b = fma(r, zo, b);
         d = fma(r, r, d);

@@ -128,7 +128,8 @@ constexpr int MAX_ENSEMBLES = 16;
 struct Ensemble {
     std::vector<Group*> members;
     hipStream_t stream = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec[2] = {};   // by iteration parity (which z block is new)
+    int par = 0;                   // parity of the next iteration
     bool stale = false;            // a member joined since the capture
     bool busy = false;             // a chunk is in flight
     hipEvent_t ev_chunk = nullptr;
@@ -165,7 +166,8 @@ struct amge_server {
     ~amge_server() {
         for (auto& e : ens) {
             if (e->stream) (void)hipStreamSynchronize(e->stream);
-            if (e->exec) (void)hipGraphExecDestroy(e->exec);
+            for (hipGraphExec_t x : e->exec)
+                if (x) (void)hipGraphExecDestroy(x);
             if (e->ev_chunk) (void)hipEventDestroy(e->ev_chunk);
             if (e->stream) (void)hipStreamDestroy(e->stream);
         }
@@ -351,8 +353,10 @@ struct amge_server {
             const int k = std::max(1, std::min(chunk, (int)(SCHED_CHUNK_MS / it_ms)));
             const double est = k * it_ms;
             if (queued_ms > 0 && queued_ms + est > SCHED_QUEUE_MS) break;
-            hipGraphExec_t ex = capture_iteration(H, W);
-            for (int i = 0; i < k; ++i) HIPCHECK(hipGraphLaunch(ex, H->gstream));
+            for (int i = 0; i < k; ++i) {
+                HIPCHECK(hipGraphLaunch(capture_iteration(H, W, H->bpar), H->gstream));
+                H->bpar ^= 1;
+            }
             HIPCHECK(hipMemcpyAsync(g.cs_host, H->cs, sizeof(dev::ColState) * H->NC, hipMemcpyDeviceToHost,
                                     H->gstream));
             HIPCHECK(hipEventRecord(g.ev_chunk, H->gstream));
@@ -366,11 +370,13 @@ struct amge_server {
 
     // A chunk of an ensemble (all members, all columns); false if the queue is full.
     bool launch_ensemble(Ensemble& en) {
-        if (en.stale || !en.exec) {
+        if (en.stale || !en.exec[0]) {
             std::vector<amge_hierarchy*> hs;
             for (Group* g : en.members) hs.push_back(g->H);
-            hipGraphExecDestroy_if(en.exec);
-            en.exec = capture_grouped_iteration(hs, en.stream, &en.launches, &en.solo_launches);
+            for (int p = 0; p < 2; ++p) {
+                hipGraphExecDestroy_if(en.exec[p]);
+                en.exec[p] = capture_grouped_iteration(hs, p, en.stream, &en.launches, &en.solo_launches);
+            }
             en.stale = false;
         }
         // members without requests return from every kernel at once
@@ -380,7 +386,10 @@ struct amge_server {
         const int k = std::max(1, std::min(chunk, (int)(SCHED_CHUNK_MS / it_ms)));
         const double est = k * it_ms;
         if (queued_ms > 0 && queued_ms + est > SCHED_QUEUE_MS) return false;
-        for (int i = 0; i < k; ++i) HIPCHECK(hipGraphLaunch(en.exec, en.stream));
+        for (int i = 0; i < k; ++i) {
+            HIPCHECK(hipGraphLaunch(en.exec[en.par], en.stream));
+            en.par ^= 1;
+        }
         for (Group* g : en.members) {
             HIPCHECK(hipMemcpyAsync(g->cs_host, g->H->cs, sizeof(dev::ColState) * g->H->NC, hipMemcpyDeviceToHost,
                                     en.stream));
@@ -491,7 +500,8 @@ amge_status server_add(amge_server* s, amge_hierarchy* h, int32_t* id, int ensem
             g->stream = en.stream;
         } else {
             g->stream = h->gstream;
-            for (int W = 1; W <= h->NC; W *= 2) capture_iteration(h, W);
+            for (int W = 1; W <= h->NC; W *= 2)
+                for (int p = 0; p < 2; ++p) capture_iteration(h, W, p);
         }
         dev::k_serve_reset<<<1, 64, 0, h->gstream>>>(h->NC, h->cs, h->bs);
         HIPCHECK(hipGetLastError());

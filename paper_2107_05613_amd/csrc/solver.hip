@@ -935,7 +935,9 @@ void setup_batched(amge_hierarchy* H, const std::vector<HostLevel>& hl, hipStrea
     H->bR = H->alloc<double>(nn);
     H->bP = H->alloc<double>(nn);
     H->bQ = H->alloc<double>(nn);
-    H->bZ = H->alloc<double>(nn);   // z in the preconditioner precision (FP32: first half used)
+    // the two z blocks (new and old, alternating with the iteration parity): FP64 blocks
+    // bZ and bZv, or, for an FP32 V-cycle, the two halves of bZ
+    H->bZ = H->alloc<double>(nn);
     H->bZv = H->alloc<double>(nn);
     H->bpart = H->alloc<double>((size_t)3 * NC * BPCG_BLOCKS);
     H->cs = H->alloc<dev::ColState>(NC);
@@ -1479,26 +1481,33 @@ bool bz32(const amge_hierarchy* H) { return H->opts.precond_bits == 32 && H->lv.
 // itself (JAC0), so the PCG update does not store it.
 bool bpcg_fused_bd(const amge_hierarchy* H) { return H->lv.size() > 1 && H->opts.nu_primary >= 2; }
 
-void bpcg_precond(amge_hierarchy* H, int W, const int* stop, hipStream_t s) {
+// z block of parity par in the preconditioner precision.
+float* bz_f32(const amge_hierarchy* H, int par) {
+    return reinterpret_cast<float*>(H->bZ) + (par ? (int64_t)H->lv[0].n * H->NC : 0);
+}
+double* bz_f64(const amge_hierarchy* H, int par) { return par ? H->bZv : H->bZ; }
+
+void bpcg_precond(amge_hierarchy* H, int W, int par, const int* stop, hipStream_t s) {
     DLevel& L = H->lv[0];
     const bool fused = bpcg_fused_bd(H);
-    if (bz32(H)) bvcycle_level<float>(H, 0, L.bw32.b, fused ? nullptr : L.bw32.bd, L.bw32.x, W, stop, s);
-    else bvcycle_level<double>(H, 0, H->bR, fused ? nullptr : L.bw64.bd, H->bZv, W, stop, s);
+    if (bz32(H)) bvcycle_level<float>(H, 0, L.bw32.b, fused ? nullptr : L.bw32.bd, bz_f32(H, par), W, stop, s);
+    else bvcycle_level<double>(H, 0, H->bR, fused ? nullptr : L.bw64.bd, bz_f64(H, par), W, stop, s);
 }
 
-void bpcg_dots(amge_hierarchy* H, int W, hipStream_t s) {
-    DLevel& L = H->lv[0];
-    const int n = L.n;
+void bpcg_dots(amge_hierarchy* H, int W, int par, hipStream_t s) {
+    const int n = H->lv[0].n;
     if (bz32(H))
-        launch<dev::BpcgDots<float>>(BPCG_BLOCKS, s, n, W, H->NC, L.bw32.x, (float*)H->bZ, H->bR, H->bpart, H->bs);
+        launch<dev::BpcgDots<float>>(BPCG_BLOCKS, s, n, W, H->NC, bz_f32(H, par), bz_f32(H, par ^ 1), H->bR,
+                                     H->bpart, H->bs);
     else
-        launch<dev::BpcgDots<double>>(BPCG_BLOCKS, s, n, W, H->NC, H->bZv, H->bZ, H->bR, H->bpart, H->bs);
+        launch<dev::BpcgDots<double>>(BPCG_BLOCKS, s, n, W, H->NC, bz_f64(H, par), bz_f64(H, par ^ 1), H->bR,
+                                      H->bpart, H->bs);
 }
 
 // One PCG iteration on the first W columns (the captured body): q = A p, alpha, x/r
 // update with the next preconditioner input, z = B r, dots, stopping test and beta,
 // p update.
-void bpcg_iteration(amge_hierarchy* H, int W, hipStream_t s) {
+void bpcg_iteration(amge_hierarchy* H, int W, int par, hipStream_t s) {
     DLevel& L = H->lv[0];
     const int lgW = log2i(W);
     const int64_t nn = (int64_t)L.n * W;
@@ -1511,22 +1520,22 @@ void bpcg_iteration(amge_hierarchy* H, int W, hipStream_t s) {
     launch<dev::BpcgXr>(g, s, nn, lgW, H->lgNC, H->cs, H->bQ, H->bR, f32 ? L.bw32.b : nullptr,
                         f32 && !fused ? L.bw32.bd : nullptr, f32 ? L.bw32.dinv : nullptr,
                         !f32 && ml && !fused ? L.bw64.bd : nullptr, !f32 && ml ? L.bw64.dinv : nullptr, H->bs);
-    bpcg_precond(H, W, &H->bs->all_done, s);
-    bpcg_dots(H, W, s);
+    bpcg_precond(H, W, par, &H->bs->all_done, s);
+    bpcg_dots(H, W, par, s);
     launch<dev::BpcgUpdate>(1, s, W, H->NC, H->bpart, BPCG_BLOCKS, H->cs, H->bs);
-    if (f32) launch<dev::BpcgP<float>>(g, s, nn, lgW, H->lgNC, H->cs, (const float*)H->bZ, H->bP, H->bX, H->bs);
-    else launch<dev::BpcgP<double>>(g, s, nn, lgW, H->lgNC, H->cs, H->bZ, H->bP, H->bX, H->bs);
+    if (f32) launch<dev::BpcgP<float>>(g, s, nn, lgW, H->lgNC, H->cs, bz_f32(H, par), H->bP, H->bX, H->bs);
+    else launch<dev::BpcgP<double>>(g, s, nn, lgW, H->lgNC, H->cs, bz_f64(H, par), H->bP, H->bX, H->bs);
     launch<dev::BpcgFinish>(1, s, H->bs);
 }
 
-hipGraphExec_t capture_iteration(amge_hierarchy* H, int W) {
+hipGraphExec_t capture_iteration(amge_hierarchy* H, int W, int par) {
     if (H->NC < 2 || !H->gstream) fail(AMGE_ERR_ARG, "hierarchy has no batched path (max_rhs = 1)");
     if (W < 1 || W > H->NC || (W & (W - 1))) fail(AMGE_ERR_ARG, "active width must be a power of two <= NC");
-    hipGraphExec_t& ex = H->gexec[log2i(W)];
+    hipGraphExec_t& ex = H->gexec[log2i(W)][par & 1];
     if (ex) return ex;
     hipGraph_t graph = nullptr;
     HIPCHECK(hipStreamBeginCapture(H->gstream, hipStreamCaptureModeThreadLocal));
-    bpcg_iteration(H, W, H->gstream);
+    bpcg_iteration(H, W, par & 1, H->gstream);
     hipError_t e = hipStreamEndCapture(H->gstream, &graph);
     if (e != hipSuccess || !graph) fail(AMGE_ERR_HIP, "graph capture of the batched PCG iteration failed");
     e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
@@ -1577,15 +1586,15 @@ int group_launches(const std::vector<LaunchRecorder>& mem, hipStream_t s) {
     return launches;
 }
 
-hipGraphExec_t capture_grouped_iteration(const std::vector<amge_hierarchy*>& hs, hipStream_t s, int* launches,
-                                         int* solo_launches) {
+hipGraphExec_t capture_grouped_iteration(const std::vector<amge_hierarchy*>& hs, int par, hipStream_t s,
+                                         int* launches, int* solo_launches) {
     std::vector<LaunchRecorder> rec(hs.size());
     int solo = 0;
     for (size_t i = 0; i < hs.size(); ++i) {
         amge_hierarchy* H = hs[i];
         if (H->NC < 2 || !H->gstream) fail(AMGE_ERR_ARG, "hierarchy has no batched path (max_rhs = 1)");
         RecordLaunches scope(&rec[i]);
-        bpcg_iteration(H, H->NC, s);
+        bpcg_iteration(H, H->NC, par & 1, s);
         solo += (int)rec[i].ops.size();
     }
     hipGraph_t graph = nullptr;
@@ -1609,7 +1618,7 @@ amge_status bpcg(amge_hierarchy* H, const double* b, double* x, int nrhs, double
     const int NC = H->NC;
     hipStream_t gs = H->gstream;
     const int W = active_width(H, nrhs);
-    hipGraphExec_t ex = capture_iteration(H, W);
+    hipGraphExec_t ex[2] = {capture_iteration(H, W, 0), capture_iteration(H, W, 1)};
     // order the internal stream after the caller's work
     HIPCHECK(hipEventRecord(H->ev_in, s));
     HIPCHECK(hipStreamWaitEvent(gs, H->ev_in, 0));
@@ -1620,7 +1629,10 @@ amge_status bpcg(amge_hierarchy* H, const double* b, double* x, int nrhs, double
     // every column finishes within maxit steps after its initial pass
     for (int launched = 0;;) {
         if (launched > maxit + 1) fail(AMGE_ERR_HIP, "batched PCG did not terminate");
-        for (int i = 0; i < BPCG_CHUNK; ++i) HIPCHECK(hipGraphLaunch(ex, gs));
+        for (int i = 0; i < BPCG_CHUNK; ++i) {
+            HIPCHECK(hipGraphLaunch(ex[H->bpar], gs));
+            H->bpar ^= 1;
+        }
         launched += BPCG_CHUNK;
         HIPCHECK(hipMemcpyAsync(&st, H->bs, sizeof(st), hipMemcpyDeviceToHost, gs));
         HIPCHECK(hipStreamSynchronize(gs));
