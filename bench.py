@@ -7,8 +7,17 @@ right-hand side already resident in HBM.  The same solve with an all-FP64 V-cycl
 ("plain FP64 PCG") is timed beside it, and the V-cycle's achieved bandwidth is
 reported from its algorithmic bytes.
 
+Beside it, in the same JSON line: the roofline of the dominant kernel family (fine-level
+A sweeps and residual, HIP events on their launch stream) with a measured device-copy
+bandwidth for reference, the batched solve of the 48^3 H(div) workload with 32
+right-hand sides, the serving mix (burst, closed loop, open loop) with a solo vs
+grouped-launch comparison on small hierarchies, and the oracle timed on one host core.
+
 Prints one JSON line (rank 0).  Options: --gpus N (only 1 is supported), --steps K,
---warmup W, --workload NAME, --no-cpu-baseline.
+--warmup W, --workload NAME, --no-cpu-baseline, --batched-workload NAME ("" to skip),
+--serving-requests N (0 to skip), --grouped-ab-only CONFIG (one configuration of the
+small-hierarchy serving burst alone, for kernel traces), --copy-calibration (a 1 GiB
+device copy first: the reference kernel of the HBM counter runs).
 """
 from __future__ import annotations
 
