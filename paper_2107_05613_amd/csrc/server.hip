@@ -104,7 +104,7 @@ struct Request {
 // One resident hierarchy and its columns.
 struct Group {
     amge_hierarchy* H = nullptr;
-    bool grouped = false;          // member of the ensemble
+    bool grouped = false;          // member of an ensemble
     hipStream_t stream = nullptr;  // where its inserts, chunks and copy-outs run
     size_t footprint = 0;          // device bytes of the hierarchy
     size_t col_bytes = 0;          // work bytes of one column
@@ -122,8 +122,8 @@ struct Group {
     uint64_t turn = 0;             // when the group last finished a chunk (scheduling order)
 };
 
-// A set of grouped hierarchies: one captured graph runs an iteration of all of them (on
-// all their columns), recaptured when a member joins.
+// A set of grouped hierarchies: one captured graph (per iteration parity) runs an
+// iteration of all of them (on all their columns), recaptured when a member joins.
 constexpr int MAX_ENSEMBLES = 16;
 struct Ensemble {
     std::vector<Group*> members;
