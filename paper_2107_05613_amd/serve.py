@@ -1,8 +1,9 @@
 """Serving driver: a seeded Poisson stream of solve requests over resident hierarchies.
 
-The engine itself (admission, continuous batching, per-hierarchy streams and graphs) is
-native (amge_server_* in the library); this module builds the resident hierarchies of a
-request mix, feeds requests at their arrival times and records latencies.
+The engine itself (admission, continuous batching, per-hierarchy streams and graphs,
+ensembles of hierarchies sharing grouped launches) is native (amge_server_* in the
+library); this module builds the resident hierarchies of a request mix, feeds requests
+at their arrival times and records latencies.
 """
 from __future__ import annotations
 
