@@ -82,6 +82,7 @@ struct DLevel {
     Probe* probe = nullptr;
     DSell A, Ah, P, Pt;
     DSell Aux;                // [D^T | -D^T A]: auxiliary residual D^T b - (D^T A) x
+    DSell PtA;                // [P^T | -P^T A] below the fine level: restricted residual
     DSell D, Dt;              // signed incidences
     Work<float> w32;
     Work<double> w64;

@@ -413,9 +413,14 @@ void vcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, hi
     auxiliary<T>(L, b, x, nua, s, stop);
     // restriction of the residual (and the coarse first sweep), coarse correction,
     // prolongation
-    asell<T>(L, dev::RESID, x, b, nullptr, w.r, s, stop);
-    sell<T>(L.Pt, dev::SPMV, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, s, stop,
-            next_coarsest ? nullptr : wc.bd);
+    if (L.PtA.nrows) {   // P^T b - (P^T A) x in one launch
+        sell<T>(L.PtA, dev::SPLIT, x, b, next_coarsest ? nullptr : wc.dinv, wc.b, s, stop,
+                next_coarsest ? nullptr : wc.bd);
+    } else {
+        asell<T>(L, dev::RESID, x, b, nullptr, w.r, s, stop);
+        sell<T>(L.Pt, dev::SPMV, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, s, stop,
+                next_coarsest ? nullptr : wc.bd);
+    }
     vcycle_level<T>(H, l + 1, wc.b, wc.bd, wc.x, s, stop);
     sell<T>(L.P, dev::SPMV_ADD, wc.x, nullptr, nullptr, x, s, stop);
     // post-smoothing with Mbar^T: auxiliary first, then primary
@@ -1186,6 +1191,33 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
             }
             L.Aux = upload_tuned(H, X, false, s, &lead);
             L.Aux.stream = true;
+            if (k >= 1) {
+                // [P^T | -P^T A] on [b; x] below the fine level: the restricted residual
+                // P^T (b - A x) in one (latency-bound) launch instead of a residual and a
+                // restriction.  On the fine level the residual reads the cache-resident
+                // A_k and stays separate.
+                const Csr Pt = transpose(P[k]);
+                const Csr PtA = spgemm(Pt, A[k]);
+                Csr R;
+                R.nrows = Pt.nrows;
+                R.ncols = L.n;
+                R.rowptr.assign(Pt.nrows + 1, 0);
+                std::vector<int> rlead(Pt.nrows);
+                for (int i = 0; i < Pt.nrows; ++i) {
+                    for (int q = Pt.rowptr[i]; q < Pt.rowptr[i + 1]; ++q) {
+                        R.col.push_back(Pt.col[q]);
+                        R.val.push_back(Pt.val[q]);
+                    }
+                    rlead[i] = Pt.rowptr[i + 1] - Pt.rowptr[i];
+                    for (int q = PtA.rowptr[i]; q < PtA.rowptr[i + 1]; ++q) {
+                        R.col.push_back(PtA.col[q]);
+                        R.val.push_back(-PtA.val[q]);
+                    }
+                    R.rowptr[i + 1] = (int32_t)R.col.size();
+                }
+                L.PtA = upload_tuned(H, R, false, s, &rlead);
+                L.PtA.stream = true;
+            }
             if (batched) {
                 hl[k].Ah = Ah;
                 hl[k].P = P[k];
@@ -1921,9 +1953,14 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
                 aux += incb(L.D, L.bD) + sx * (m + 2 * n);
                 tot += 2 * aux;
             }
-            // restriction residual, P^T, P add
-            tot += mat(L.A, L.bA) + 3 * sx * n;
-            tot += mat(L.Pt, L.bPt) + sx * (n + nc);
+            // restriction: residual then P^T, or (single column below the fine level)
+            // [P^T | -P^T A][b; x] with its split counts; then the P add
+            if (!batched && L.PtA.nrows) {
+                tot += mat(L.PtA, L.bPt) + 2.0 * nc + sx * (2 * n) + 2 * sx * nc;
+            } else {
+                tot += mat(L.A, L.bA) + 3 * sx * n;
+                tot += mat(L.Pt, L.bPt) + sx * (n + nc);
+            }
             tot += mat(L.P, L.bP) + sx * (nc + 2 * n);
         }
         // the dense operator read once, the right-hand side and solution blocks
