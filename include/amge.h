@@ -97,10 +97,12 @@ typedef struct amge_hierarchy amge_hierarchy;
 void amge_default_opts(amge_opts* opts);
 
 /* Builds the device hierarchy from host level matrices (section 3.2, Algorithm 4.1 inputs).
- * Host work: validation, D^T, P^T, the products D^T A and D^T A D (FP64 sparse products;
- * the auxiliary residual D^T (b - A x) is evaluated as D^T b - (D^T A) x), the l1 row
- * sums, the cancellation factor, a dense FP64 Cholesky factor of the coarsest matrix and
- * the inverse it gives (coarsest level at most 8192 rows).  The device layouts are tuned
+ * Host work: validation, D^T, P^T, the products D^T A and D^T A D, and P^T A below the
+ * fine level (FP64 sparse products; the auxiliary residual D^T (b - A x) is evaluated as
+ * D^T b - (D^T A) x, and below the fine level the restricted residual P^T (b - A x) as
+ * P^T b - (P^T A) x), the l1 row sums, the cancellation factor, a dense FP64 Cholesky
+ * factor of the coarsest matrix and the inverse it gives (coarsest level at most 8192
+ * rows), and the folded coarse tail (tail_rows).  The device layouts are tuned
  * by timing candidate launches on `stream`.  Device buffers and a private stream (for the
  * captured PCG iterations) are owned by the hierarchy.
  * Errors: AMGE_ERR_ARG, AMGE_ERR_SHAPE, AMGE_ERR_NONFINITE (NaN/Inf value),
