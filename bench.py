@@ -53,57 +53,105 @@ def measured_traffic():
     return rec["traffic_bytes_per_launch"]
 
 
-def cpu_baseline_worker(workload: str, budget_s: float):
-    """Oracle leg (separate process, one thread): hierarchy build untimed, then a bounded
-    number of FP64 PCG iterations timed; prints a JSON dict."""
+def _oracle_sample(H, ml, rhs, iters):
+    """Seconds per PCG iteration of the oracle: `iters` fixed iterations timed (they cost
+    iters + 1 V-cycles and iters A-products)."""
+    from oracle.solve import pcg
+    t0 = time.perf_counter()
+    pcg(H.A[0], rhs, ml, fixed_iters=iters)
+    return (time.perf_counter() - t0) / (iters + 1)
+
+
+def cpu_baseline_worker(workloads, budget_s: float, outdir: str):
+    """Oracle leg (separate process, one thread per process).  Per workload: the oracle
+    hierarchy is built (not timed); its FP64 PCG solve to the workload's rtol gives the
+    reference solution (saved to outdir for the GPU results' errors); a bounded number
+    of PCG iterations is timed on one core; then one forked process per host core (the
+    hierarchy shared copy-on-write) times the same iterations concurrently, for the
+    aggregate throughput.  Prints a JSON dict."""
+    import multiprocessing as mp
     import numpy as np
     from paper_2107_05613_amd import workloads as W
     from oracle.hierarchy import build_hierarchy
     from oracle.solve import Multilevel, pcg
-    w = W.WORKLOADS[workload]
-    a, b = W.coefficients(w)
-    t0 = time.perf_counter()
-    H = build_hierarchy(w.kind, w.n, w.levels, a, b, check_targets=False)
-    ml = Multilevel.from_hierarchy(H)
-    t_build = time.perf_counter() - t0
-    rhs = W.rhs(H.A[0].shape[0], w.rhs_seed)[:, 0]
-    t0 = time.perf_counter()
-    pcg(H.A[0], rhs, ml, fixed_iters=1)                  # setup V-cycle + 1 iteration
-    t1 = time.perf_counter() - t0
-    iters = max(1, min(200, int(budget_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    pcg(H.A[0], rhs, ml, fixed_iters=iters)
-    t = time.perf_counter() - t0
-    # the fixed-iteration run costs (iters + 1) V-cycles and iters A-products
-    print(json.dumps({"t_build_s": t_build, "sample_iters": iters, "sample_s": t,
-                      "s_per_iter": t / (iters + 1)}), flush=True)
+    cores = len(os.sched_getaffinity(0))
+    res = {}
+    for name in workloads:
+        w = W.WORKLOADS[name]
+        a, b = W.coefficients(w)
+        t0 = time.perf_counter()
+        H = build_hierarchy(w.kind, w.n, w.levels, a, b, check_targets=False)
+        ml = Multilevel.from_hierarchy(H)
+        t_build = time.perf_counter() - t0
+        rhs = W.rhs(H.A[0].shape[0], w.rhs_seed)[:, 0]
+        t0 = time.perf_counter()
+        x, ito, hist = pcg(H.A[0], rhs, ml, rtol=w.rtol)
+        t_solve = time.perf_counter() - t0
+        np.save(os.path.join(outdir, f"{name}.npy"), x)
+        s1 = t_solve / (2 * ito + 1) * 2          # first estimate of seconds per iteration
+        iters = max(1, min(200, int(budget_s / max(s1, 1e-4))))
+        s_iter = _oracle_sample(H, ml, rhs, iters)
+        # all cores: the same sample in one forked process per core, started together
+        it_n = max(1, iters // 2)
+        ctx = mp.get_context("fork")
+        q = ctx.Queue()
+        procs = [ctx.Process(target=lambda: q.put(_oracle_sample(H, ml, rhs, it_n))) for _ in range(cores)]
+        t0 = time.perf_counter()
+        for p in procs:
+            p.start()
+        per = [q.get() for _ in procs]
+        for p in procs:
+            p.join()
+        wall = time.perf_counter() - t0
+        res[name] = {"t_build_s": t_build, "oracle_iters": ito, "oracle_relres": hist[-1],
+                     "t_solve_s": t_solve, "sample_iters": iters, "s_per_iter": s_iter,
+                     "allcore_iters": it_n, "allcore_s_per_iter": per, "allcore_wall_s": wall}
+        print(f"[oracle] {name}: build {t_build:.1f}s, {ito} iterations in {t_solve:.1f}s, "
+              f"{1e3 * s_iter:.0f} ms/iteration on 1 core, {cores} cores {wall:.1f}s", file=sys.stderr, flush=True)
+    res["cores"] = cores
+    print(json.dumps(res), flush=True)
 
 
-def run_cpu_baseline(workload, iters_needed, budget_s=20.0):
+def run_cpu_baseline(workloads, budget_s=20.0):
+    """Runs cpu_baseline_worker in a subprocess (BLAS and OpenMP pinned to one thread per
+    process); returns (its JSON, directory of the oracle's reference solutions)."""
+    import tempfile
     env = dict(os.environ)
     for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
         env[k] = "1"
-    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", "--workload", workload,
-           "--cpu-budget", str(budget_s)]
-    r = subprocess.run(cmd, capture_output=True, text=True, env=env, timeout=1500)
+    outdir = tempfile.mkdtemp(prefix="amge_oracle_")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", "--workload", ",".join(workloads),
+           "--cpu-budget", str(budget_s), "--oracle-dir", outdir]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, env=env, timeout=1500)
     if r.returncode != 0:
-        return {"error": r.stderr[-500:]}
-    res = json.loads(r.stdout.strip().splitlines()[-1])
-    s_per_solve = res["s_per_iter"] * (iters_needed + 1)
-    model = ""
+        return {"error": f"oracle worker exited with {r.returncode}"}, outdir
+    return json.loads(r.stdout.strip().splitlines()[-1]), outdir
+
+
+def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
+                return line.split(":", 1)[1].strip()
     except OSError:
         pass
-    return {"value": 1.0 / s_per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "host_cores_available": len(os.sched_getaffinity(0)), "cpu_model": model,
-            "sample": (f"FP64 oracle (scipy CSR, 1 thread) PCG on the same hierarchy and rhs: "
-                       f"{res['sample_iters']} iterations timed ({res['sample_s']:.1f} s), scaled to "
-                       f"{iters_needed} iterations per solve (the FP64 GPU count); hierarchy build "
-                       f"{res['t_build_s']:.0f} s not timed")}
+    return ""
+
+
+def baseline_entry(res, iters_needed):
+    """cpu_baseline object for one workload: 1-core solves/s (the sample scaled to
+    iters_needed iterations per solve) and the all-core aggregate."""
+    per_solve = res["s_per_iter"] * (iters_needed + 1)
+    agg = sum(1.0 / (s * (iters_needed + 1)) for s in res["allcore_s_per_iter"])
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "allcore": {"value": agg, "unit": "solves/s", "cores": len(res["allcore_s_per_iter"]),
+                        "processes": "one forked oracle process per core, all timing the same sample at once"},
+            "cpu_model": cpu_model(),
+            "sample": (f"FP64 oracle (scipy CSR, 1 thread per process) PCG on its own hierarchy of the same "
+                       f"workload and rhs: {res['sample_iters']} iterations timed on 1 core "
+                       f"({res['sample_iters'] * res['s_per_iter']:.1f} s) and {res['allcore_iters']} per process on "
+                       f"all cores ({res['allcore_wall_s']:.1f} s), scaled to {iters_needed} iterations per solve; "
+                       f"hierarchy build {res['t_build_s']:.0f} s not timed")}
 
 
 def run_batched(args, amge, W):
@@ -198,6 +246,75 @@ def run_batched(args, amge, W):
                    "ms_per_column": vms / k},
         "setup_s": {"build": t_build, "device_setup": t_setup},
     }
+
+
+def run_small_configs(names, steps):
+    """The two small configurations, each solved with the FP32 and the FP64 V-cycle on the
+    library's own hierarchy: iterations, time per solve (host clock around complete
+    solves), and the solutions (kept for their errors against the oracle)."""
+    import torch
+    from paper_2107_05613_amd import amge
+    from paper_2107_05613_amd import workloads as W
+    out, sols = {}, {}
+    for name in names:
+        w = W.WORKLOADS[name]
+        a, b = W.coefficients(w)
+        prod = amge.build_problem(w.kind, w.n, w.levels, a, b)
+        rhs = None
+        r = {"workload": (f"H({w.kind}) on {w.n}^3x6 Kuhn tets, {w.levels} levels, coefficients {w.coef}, "
+                          f"rhs uniform[-1,1] seed {w.rhs_seed}, rtol {w.rtol:g}")}
+        for bits in (32, 64):
+            H = amge.Hierarchy(prod, precond_bits=bits)
+            if rhs is None:
+                rhs = torch.from_numpy(W.rhs(H.rows[0], w.rhs_seed)[:, 0]).cuda()
+                r["level_rows"] = H.rows
+                r["kappa"] = H.precision_info()[0]
+            x = torch.zeros_like(rhs)
+            for _ in range(2):
+                st, it, rr = H.pcg(rhs, x, rtol=w.rtol, maxit=2000)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                st, it, rr = H.pcg(rhs, x, rtol=w.rtol, maxit=2000)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            r[f"fp{bits}"] = {"iters": it[0], "relres": rr[0], "status": st, "ms_per_solve": 1e3 * dt,
+                              "solves_per_s": 1.0 / dt}
+            sols[(name, bits)] = x.cpu().numpy()
+            H.close()
+        out[name] = r
+        print(f"[bench] {name}: FP32-preconditioned {r['fp32']['iters']} iterations {r['fp32']['ms_per_solve']:.2f} "
+              f"ms, FP64 {r['fp64']['iters']} iterations {r['fp64']['ms_per_solve']:.2f} ms", file=sys.stderr,
+              flush=True)
+    return out, sols
+
+
+def cold_sweep(H, rhs, x, reps=10):
+    """Average time of the fine-level FP32 l1-Jacobi sweep launched alone (amge_level_apply
+    SWEEP, HIP events on its stream), warm (launched back to back, its matrix partly
+    served by the last-level cache) and cold (after a 2 GiB device copy that evicts the
+    256 MB last-level cache, so the matrix streams from HBM)."""
+    import torch
+    from paper_2107_05613_amd import amge
+    out = torch.empty_like(rhs)
+    src = torch.ones(1 << 29, dtype=torch.float32, device="cuda")   # 2 GiB
+    dst = torch.empty_like(src)
+    res = {}
+    for name, flush in (("warm", False), ("cold", True)):
+        H.level_apply(0, amge.OP_SWEEP, rhs, out, x2=x, precision=32)
+        torch.cuda.synchronize()
+        H.timing_enable(True)
+        for _ in range(reps):
+            if flush:
+                dst.copy_(src)
+            H.level_apply(0, amge.OP_SWEEP, rhs, out, x2=x, precision=32)
+        torch.cuda.synchronize()
+        ms, n, by = H.timing_read()
+        H.timing_enable(False)
+        res[name] = (ms / max(n, 1), by / max(n, 1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_serving(args):
@@ -333,7 +450,10 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=256,
                     help="requests of the serving mix run beside the main workload (0 to skip)")
     ap.add_argument("--cpu-baseline-worker", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--oracle-dir", default=None)
+    ap.add_argument("--small-configs", default="curl_n8_l2,div_n32_l4_jumps",
+                    help="comma-separated small configurations timed beside the main one ('' to skip)")
     ap.add_argument("--grouped-ab-only", choices=[c[0] for c in GROUPED_CONFIGS],
                     help="run only that configuration of the small-hierarchy serving burst and print its JSON "
                          "(for kernel traces)")
@@ -342,7 +462,7 @@ def main():
     args = ap.parse_args()
 
     if args.cpu_baseline_worker:
-        cpu_baseline_worker(args.workload, args.cpu_budget)
+        cpu_baseline_worker(args.workload.split(","), args.cpu_budget, args.oracle_dir)
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the solve phase is not sharded across GPUs "
@@ -405,6 +525,7 @@ def main():
     torch.cuda.synchronize()
     k_ms, k_launches, k_bytes = H32.timing_read()
     H32.timing_enable(False)
+    sweep = cold_sweep(H32, rhs, x32)
 
     # ---- plain FP64 PCG on the same hierarchy
     for _ in range(max(1, args.warmup)):
@@ -435,14 +556,25 @@ def main():
         vc[bits] = (ms, by, by / (ms * 1e-3) / 1e9)
     err = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
 
+    sol = {(w.name, 32): x32.cpu().numpy(), (w.name, 64): x64.cpu().numpy()}
+    lv0 = prod[0][0]
     del H64
     stream_ref = stream_reference()
+    small_names = [c for c in args.small_configs.split(",") if c]
+    small, small_sol = run_small_configs(small_names, args.steps) if small_names else ({}, {})
+    sol.update(small_sol)
     batched = run_batched(args, amge, W) if args.batched_workload else None
     serving = run_serving(args) if args.serving_requests > 0 else None
 
     value = args.steps / dt32
     k_avg_ms = k_ms / max(k_launches, 1)
     k_gbps = (k_bytes / max(k_launches, 1)) / (k_avg_ms * 1e-3) / 1e9 if k_launches else 0.0
+    # byte model of the scope table (32-bit column indices, one FP32 value per entry,
+    # rows + 1 row pointers, four vector streams of the sweep: x, b, d, y)
+    model_bytes = 8.0 * lv0.nnz + 4.0 * (n1 + 1) + 16.0 * n1
+
+    def gbps(by, ms):
+        return by / (ms * 1e-3) / 1e9
     out = {
         "metric": METRIC,
         "value": value,
@@ -488,15 +620,44 @@ def main():
             "avg_launch_us": 1e3 * k_avg_ms,
             "bytes_per_launch": k_bytes / max(k_launches, 1),
             "launches": k_launches,
+            "model_bytes_per_launch": model_bytes,
+            "frac_model": gbps(model_bytes, k_avg_ms) / PEAK_HBM_GBPS,
+            "sweep_alone": {
+                name: {"avg_launch_us": 1e3 * ms_, "achieved": gbps(by_, ms_), "frac": gbps(by_, ms_) / PEAK_HBM_GBPS,
+                       "frac_model": gbps(model_bytes, ms_) / PEAK_HBM_GBPS}
+                for name, (ms_, by_) in sweep.items()},
+            "cold_note": ("sweep_alone.cold: the same FP32 sweep launched after a 2 GiB device copy that evicts "
+                          "the 256 MB last-level cache (its matrix streams from HBM); warm: launched back to back"),
             "stream_reference_GBps": stream_ref,
         },
+        "configs": small,
         "setup_s": {"build": t_build, "device_setup": t_setup},
         "batched": batched,
         "serving": serving,
     }
     if not args.no_cpu_baseline:
+        import shutil
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = run_cpu_baseline(args.workload, it64, args.cpu_budget)
+        ores, odir = run_cpu_baseline([args.workload] + small_names, args.cpu_budget)
+        if "error" in ores:
+            out["cpu_baseline"] = ores
+        else:
+            out["cpu_baseline"] = baseline_entry(ores[args.workload], it64)
+            out["cpu_baseline"]["host_cores_available"] = ores["cores"]
+
+            def err_vs_oracle(name, bits):
+                xo = np.load(os.path.join(odir, f"{name}.npy"))
+                return float(np.linalg.norm(sol[(name, bits)] - xo) / np.linalg.norm(xo))
+            out["solution_rel_err_vs_oracle"] = {"fp32_precond": err_vs_oracle(args.workload, 32),
+                                                 "fp64": err_vs_oracle(args.workload, 64),
+                                                 "oracle_iters": ores[args.workload]["oracle_iters"]}
+            for name in small_names:
+                r = out["configs"][name]
+                r["oracle_iters"] = ores[name]["oracle_iters"]
+                for bits in (32, 64):
+                    r[f"fp{bits}"]["rel_err_vs_oracle"] = err_vs_oracle(name, bits)
+                r["cpu_baseline"] = baseline_entry(ores[name], ores[name]["oracle_iters"])
+        shutil.rmtree(odir, ignore_errors=True)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -25,10 +25,13 @@
  *     functions that return host scalars synchronise it before returning.
  *   - Negative return values are errors, amge_last_error() gives a message for
  *     the calling thread.  AMGE_NOT_CONVERGED is a warning: outputs are valid.
- *   - A hierarchy is read-only after set-up apart from its work buffers: calls
- *     that use one hierarchy must not overlap in time (use one hierarchy per
- *     concurrent stream, or the serving engine, which multiplexes requests onto the
- *     columns of a hierarchy).
+ *   - A hierarchy (amge_setup_hierarchy) holds the level operators of Algorithm 4.1
+ *     and is read-only after set-up.  The solve calls run on a context
+ *     (amge_ctx_create): the work buffers, PCG state, stream and captured graphs of one
+ *     caller.  Calls on one context must not overlap in time; contexts of the same
+ *     hierarchy may run concurrently on different streams or threads.
+ *   - Device memory of hierarchies and contexts comes from the caller's allocator
+ *     (amge_opts.alloc) when one is given, else from hipMalloc.
  */
 #ifndef AMGE_H
 #define AMGE_H
@@ -81,7 +84,8 @@ typedef struct {
                                V-cycle with the coarsest Cholesky solve kept in FP64;
                                0: chosen at set-up, 32 unless 2^-24 * kappa > 0.1, kappa
                                being the cancellation factor of amge_precision_info         */
-    int32_t max_rhs;        /* largest nrhs the work buffers are sized for (>= 1)           */
+    int32_t max_rhs;        /* largest nrhs of a context of this hierarchy (1 <= max_rhs <= 64);
+                               > 1 also builds the batched operators                        */
     int32_t tail_rows;      /* coarse-tail folding: while the level above the coarse tail
                                (initially the coarsest level) is not the fine level and has
                                at most tail_rows rows, the V-cycle from that level down (a
@@ -89,11 +93,24 @@ typedef struct {
                                FP64, one unit vector at a time, and applied in every V-cycle
                                (single-column and batched) as one dense FP64 product.  Same
                                operator, fewer launches.  0: off (0 <= tail_rows <= 8192). */
+    /* Caller's device allocator (both NULL: hipMalloc / hipFree).  alloc(bytes, user)
+     * returns device memory of at least `bytes` bytes, 256-byte aligned, or NULL (the
+     * call then fails with AMGE_ERR_OOM); dealloc(ptr, user) returns it.  The library
+     * calls them from the thread that calls it, during amge_setup_hierarchy (operators),
+     * amge_ctx_create (work buffers), the first amge_level_apply of a precision other
+     * than the V-cycle's, and the destroy calls (after a device-wide synchronisation, so
+     * no queued work still uses the memory).  The hierarchy's contexts use the same
+     * allocator. */
+    void* (*alloc)(size_t bytes, void* user);
+    void (*dealloc)(void* ptr, void* user);
+    void* alloc_user;
 } amge_opts;
 
 typedef struct amge_hierarchy amge_hierarchy;
+typedef struct amge_ctx amge_ctx;
 
-/* Default options: nu = 2 + 2, FP32 preconditioner, max_rhs = 1, tail_rows = 2048. */
+/* Default options: nu = 2 + 2, FP32 preconditioner, max_rhs = 1, tail_rows = 2048,
+ * hipMalloc. */
 void amge_default_opts(amge_opts* opts);
 
 /* Builds the device hierarchy from host level matrices (section 3.2, Algorithm 4.1 inputs).
@@ -103,45 +120,61 @@ void amge_default_opts(amge_opts* opts);
  * P^T b - (P^T A) x), the l1 row sums, the cancellation factor, a dense FP64 Cholesky
  * factor of the coarsest matrix and the inverse it gives (coarsest level at most 8192
  * rows), and the folded coarse tail (tail_rows).  The device layouts are tuned
- * by timing candidate launches on `stream`.  Device buffers and a private stream (for the
- * captured PCG iterations) are owned by the hierarchy.
+ * by timing candidate launches on `stream`.  The hierarchy owns the device operators
+ * (allocated through opts.alloc when given) and holds no work buffers.
  * Errors: AMGE_ERR_ARG, AMGE_ERR_SHAPE, AMGE_ERR_NONFINITE (NaN/Inf value),
  * AMGE_ERR_NOT_SPD (coarsest matrix not symmetric positive definite, or a zero row),
  * AMGE_ERR_OOM, AMGE_ERR_HIP. */
 amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nlevels, const amge_opts* opts,
                                  void* stream, amge_hierarchy** out);
 
+/* Destroys a hierarchy; its contexts must be destroyed first. */
 void amge_destroy(amge_hierarchy* h);
 
-/* Device memory held by the hierarchy (operators and work buffers), in bytes. */
-amge_status amge_footprint(const amge_hierarchy* h, size_t* bytes);
+/* Context for up to nrhs columns (1 <= nrhs <= opts.max_rhs of h): per-level work
+ * vectors of the V-cycle precision, the outer PCG vectors and partial sums (FP64), with
+ * nrhs > 1 also the n x NC batched blocks (NC = nrhs rounded up to a power of two), a
+ * stream for the captured PCG iterations, events and a pinned host ring of iteration
+ * records.  The Algorithm 4.1 inputs themselves stay in h, shared by all its contexts.
+ * Errors: AMGE_ERR_ARG (nrhs out of range), AMGE_ERR_OOM, AMGE_ERR_HIP. */
+amge_status amge_ctx_create(const amge_hierarchy* h, int32_t nrhs, amge_ctx** out);
+/* Waits for the device, then frees the context's buffers (NULL: no-op). */
+void amge_ctx_destroy(amge_ctx* c);
+
+/* Device memory of the hierarchy's operators (hier_bytes) and of one context for nrhs
+ * columns (ctx_bytes: what amge_ctx_create(h, nrhs) allocates, not counting a level
+ * work set that amge_level_apply may add).  Either output may be NULL; nrhs is checked
+ * only when ctx_bytes is requested. */
+amge_status amge_footprint(const amge_hierarchy* h, int32_t nrhs, size_t* hier_bytes, size_t* ctx_bytes);
 
 /* z = B r: one V-cycle of Algorithm 4.1 with zero initial guess, on nrhs columns.
- * r, z: device FP64, n_1 x nrhs row-major.  1 <= nrhs <= opts.max_rhs; nrhs > 1 runs
- * the batched kernels (one launch per level operator for all columns).  Asynchronous
- * on `stream`. */
-amge_status amge_vcycle(amge_hierarchy* h, const double* r, double* z, int32_t nrhs, void* stream);
+ * r, z: device FP64, n_1 x nrhs row-major.  1 <= nrhs <= the context's nrhs; nrhs > 1
+ * runs the batched kernels (one launch per level operator for all columns).
+ * Asynchronous on `stream`. */
+amge_status amge_vcycle(amge_ctx* c, const double* r, double* z, int32_t nrhs, void* stream);
 
 /* Inexact PCG (section 5.1) for A_1 x = b with x0 = 0 and one V-cycle per iteration.
  *   b, x     device FP64, n_1 x nrhs row-major; x is overwritten
- *   nrhs     1 <= nrhs <= opts.max_rhs; every column follows its own recurrences and
+ *   nrhs     1 <= nrhs <= the context's nrhs; every column follows its own recurrences and
  *            stopping test (nrhs > 1: batched kernels, a column that has stopped keeps
  *            its iterate while the others go on)
  *   rtol     stop when sqrt(r.z / r0.z0) <= rtol (stop_norm = 0, preconditioner norm) or
  *            ||r|| / ||b|| <= rtol (stop_norm = 1); rtol <= 0 runs exactly maxit iterations
  *   iters    host, nrhs entries: PCG steps per column (0 for a zero right-hand side)
  *   relres   host, nrhs entries: final relative residual in the chosen norm
- * The iterations run as replays of a HIP graph captured on the hierarchy's own stream
+ * The iterations run as replays of a HIP graph captured on the context's own stream
  * (ordered after `stream` and before later work on it by events); the call returns after
  * the solve.  Returns AMGE_NOT_CONVERGED if a column missed rtol within maxit,
  * AMGE_ERR_NONFINITE for a NaN/Inf right-hand side (nrhs > 1: in any column; the other
  * columns are still solved and written), AMGE_ERR_BREAKDOWN if p.q <= 0 or r.z <= 0
  * occurs. */
-amge_status amge_pcg_solve(amge_hierarchy* h, const double* b, double* x, int32_t nrhs, double rtol,
+amge_status amge_pcg_solve(amge_ctx* c, const double* b, double* x, int32_t nrhs, double rtol,
                            int32_t maxit, int32_t stop_norm, int32_t* iters, double* relres, void* stream);
 
 /* Single level operations, for testing each kernel of the path on its own.  Device FP64
- * in/out vectors (one column); precision 32 runs the FP32 kernel on rounded inputs.
+ * in/out vectors (one column); precision 32 runs the FP32 kernel on rounded inputs
+ * (temporary buffers; the first call in the precision other than the V-cycle's adds
+ * that precision's level work set to the context).
  *   op  AMGE_OP_A       out = A_k in                 (sparse product)
  *       AMGE_OP_AHAT    out = (D^T A D)_k in          (auxiliary matrix)
  *       AMGE_OP_D       out = D_k in                  (incidence)
@@ -150,12 +183,19 @@ amge_status amge_pcg_solve(amge_hierarchy* h, const double* b, double* x, int32_
  *       AMGE_OP_PT      out = P_k^T in                (restriction)
  *       AMGE_OP_SMOOTH  out = x + Mbar^{-1}(b - A x) with b = in, x = in2 (eq. (4.1))
  *       AMGE_OP_SMOOTHT out = x + Mbar^{-T}(b - A x) with b = in, x = in2 (reversed order)
- *       AMGE_OP_COARSE  out = A_L^{-1} in on the coarsest level (Cholesky apply) */
+ *       AMGE_OP_COARSE  out = A_L^{-1} in on the coarsest level (Cholesky apply)
+ *       AMGE_OP_SWEEP   out = x + d^{-1} (b - A x), b = in, x = in2: one l1-Jacobi sweep,
+ *                       d_i = sum_j |a_ij| (the V-cycle's sweep kernel, eq. (4.1))
+ *       AMGE_OP_RESID   out = b - A x, b = in, x = in2 (the V-cycle's residual kernel,
+ *                       Algorithm 4.1)
+ * On the fine level, SWEEP and RESID run exactly the launches the V-cycle times with
+ * amge_timing_enable. */
 enum {
     AMGE_OP_A = 0, AMGE_OP_AHAT = 1, AMGE_OP_D = 2, AMGE_OP_DT = 3, AMGE_OP_P = 4,
-    AMGE_OP_PT = 5, AMGE_OP_SMOOTH = 6, AMGE_OP_SMOOTHT = 7, AMGE_OP_COARSE = 8
+    AMGE_OP_PT = 5, AMGE_OP_SMOOTH = 6, AMGE_OP_SMOOTHT = 7, AMGE_OP_COARSE = 8,
+    AMGE_OP_SWEEP = 9, AMGE_OP_RESID = 10
 };
-amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_t op, int32_t precision,
+amge_status amge_level_apply(amge_ctx* c, int32_t level, int32_t op, int32_t precision,
                              const double* in, const double* in2, double* out, void* stream);
 
 /* Event timing of the fine-level A_1 kernels of the V-cycle (the l1-Jacobi sweeps and
@@ -165,10 +205,10 @@ amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_t op, int32
  * kernel time in ms, the number of launches, and their algorithmic bytes (values and
  * column indices, row pointers, and each vector stream once).  Intended for measurement
  * runs; reading resets the counters. */
-amge_status amge_timing_enable(amge_hierarchy* h, int32_t enable);
-amge_status amge_timing_read(amge_hierarchy* h, double* ms, int64_t* launches, double* bytes);
+amge_status amge_timing_enable(amge_ctx* c, int32_t enable);
+amge_status amge_timing_read(amge_ctx* c, double* ms, int64_t* launches, double* bytes);
 
-/* Algorithmic bytes of one V-cycle on nrhs columns (1 <= nrhs <= max_rhs) in the given
+/* Algorithmic bytes of one V-cycle on nrhs columns (1 <= nrhs <= opts.max_rhs) in the given
  * precision (32 or 64): every matrix of every level read once per use (values + column
  * indices + row pointers, incidences index-only; the batched path reads each matrix
  * once for all columns), every vector stream once per column, the l1 scalings once,
@@ -193,8 +233,8 @@ const char* amge_last_error(void);
  * The hierarchies are reused across many right-hand sides, the regime where the setup
  * cost of the method pays off (section 5).
  *
- * Every hierarchy added to a server runs the batched PCG on its own stream, one column
- * per request (or, added with amge_server_add_grouped, together with the other members
+ * Every hierarchy added to a server gets a context of the server's own (max_rhs columns)
+ * and runs the batched PCG on its stream, one column per request (or, added with amge_server_add_grouped, together with the other members
  * of its ensemble in grouped launches).  Between chunks of iterations a request is
  * loaded into a free column of its hierarchy while the other columns stay in flight
  * (continuous batching), and the hierarchies advance concurrently on the device.  The
@@ -203,8 +243,8 @@ const char* amge_last_error(void);
  *
  * Admission by device memory:
  *   hierarchy_budget  bytes; amge_server_add fails with AMGE_ERR_BUSY if the sum of the
- *                     footprints (amge_footprint) of the added hierarchies would exceed
- *                     it (0 = no limit)
+ *                     footprints of the added hierarchies and of their server contexts
+ *                     (amge_footprint with nrhs = max_rhs) would exceed it (0 = no limit)
  *   inflight_budget   bytes; a request is admitted only while the work footprint of all
  *                     admitted requests (amge_server_request_bytes each: its column of
  *                     the work blocks) stays within it (0 = no limit); requests are
@@ -217,9 +257,9 @@ const char* amge_last_error(void);
  *                     started in turn while the estimated queued GPU time stays under 8 ms)
  *
  * Single-threaded: calls on one server must not overlap.  A hierarchy added to a
- * server (it needs max_rhs >= 2: its max_rhs is the number of columns) is used only by
- * the server until amge_server_destroy, which waits for the server's work; the
- * hierarchies outlive the server and are destroyed by the caller.
+ * server needs max_rhs >= 2 (its max_rhs is the number of columns); it stays usable
+ * through other contexts.  amge_server_destroy waits for the server's work and frees
+ * its contexts; the hierarchies outlive the server and are destroyed by the caller.
  * ---------------------------------------------------------------------------------- */
 typedef struct amge_server amge_server;
 

@@ -2,13 +2,16 @@
 
 Every numerical step of the solve phase runs in the library's HIP kernels; this
 module converts Python arguments to the C ABI.  Device vectors are torch CUDA
-(HIP) tensors passed by pointer; streams are torch streams.  There is no Python
-or CPU fallback: if the library is missing, importing the binding raises.
+(HIP) tensors passed by pointer; streams are torch streams; by default the library's
+device memory comes from torch's caching allocator (amge_opts.alloc).  There is no
+Python or CPU fallback: if the library is missing, importing the binding raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 # torch is loaded before the library: torch ships its own HIP runtime, and the library's
@@ -20,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libamge.so")
 
 CURL, DIV = 0, 1
-OP_A, OP_AHAT, OP_D, OP_DT, OP_P, OP_PT, OP_SMOOTH, OP_SMOOTHT, OP_COARSE = range(9)
+OP_A, OP_AHAT, OP_D, OP_DT, OP_P, OP_PT, OP_SMOOTH, OP_SMOOTHT, OP_COARSE, OP_SWEEP, OP_RESID = range(11)
 
 STATUS = {0: "AMGE_OK", 1: "AMGE_NOT_CONVERGED", -1: "AMGE_ERR_ARG", -2: "AMGE_ERR_SHAPE",
           -3: "AMGE_ERR_NOT_SPD", -4: "AMGE_ERR_OOM", -5: "AMGE_ERR_HIP", -6: "AMGE_ERR_BREAKDOWN",
@@ -43,9 +46,29 @@ class LevelC(C.Structure):
     _fields_ = [("A", CsrC), ("D", CsrC), ("P", CsrC)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class OptsC(C.Structure):
     _fields_ = [("nu_primary", C.c_int32), ("nu_aux", C.c_int32), ("precond_bits", C.c_int32),
-                ("max_rhs", C.c_int32), ("tail_rows", C.c_int32)]
+                ("max_rhs", C.c_int32), ("tail_rows", C.c_int32), ("alloc", ALLOC_FN), ("dealloc", DEALLOC_FN),
+                ("alloc_user", C.c_void_p)]
+
+
+def _torch_alloc(nbytes, _user):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes))
+    except Exception:   # out of memory: the library reports AMGE_ERR_OOM
+        return None
+
+
+def _torch_dealloc(ptr, _user):
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+# torch's caching allocator as the library's device allocator (kept alive for the process)
+TORCH_ALLOC = (ALLOC_FN(_torch_alloc), DEALLOC_FN(_torch_dealloc))
 
 
 class CompletionC(C.Structure):
@@ -62,7 +85,9 @@ def _load():
         "amge_default_opts": (None, [C.POINTER(OptsC)]),
         "amge_setup_hierarchy": (i32, [C.POINTER(LevelC), i32, C.POINTER(OptsC), vp, C.POINTER(vp)]),
         "amge_destroy": (None, [vp]),
-        "amge_footprint": (i32, [vp, C.POINTER(C.c_size_t)]),
+        "amge_ctx_create": (i32, [vp, i32, C.POINTER(vp)]),
+        "amge_ctx_destroy": (None, [vp]),
+        "amge_footprint": (i32, [vp, i32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         "amge_vcycle": (i32, [vp, vp, vp, i32, vp]),
         "amge_pcg_solve": (i32, [vp, vp, vp, i32, f64, i32, i32, C.POINTER(i32), C.POINTER(f64), vp]),
         "amge_level_apply": (i32, [vp, i32, i32, i32, vp, vp, vp, vp]),
@@ -96,8 +121,24 @@ def _load():
 
 _lib = _load()
 
+# Objects still open at interpreter exit are closed before torch shuts down (their device
+# memory goes back through torch's allocator): servers first, then contexts, then
+# hierarchies.  Registered after torch's own exit handlers, so it runs before them.
+_LIVE = {"server": weakref.WeakSet(), "context": weakref.WeakSet(), "hierarchy": weakref.WeakSet()}
+
+
+@atexit.register
+def _close_all():
+    for kind in ("server", "context", "hierarchy"):
+        for obj in list(_LIVE[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
 # Names declared by include/amge.h (checked by the test suite against the header).
-EXPORTS = ("amge_default_opts", "amge_setup_hierarchy", "amge_destroy", "amge_footprint", "amge_vcycle",
+EXPORTS = ("amge_default_opts", "amge_setup_hierarchy", "amge_destroy", "amge_ctx_create", "amge_ctx_destroy",
+           "amge_footprint", "amge_vcycle",
            "amge_pcg_solve", "amge_level_apply", "amge_hierarchy_info", "amge_precision_info", "amge_last_error",
            "amge_timing_enable", "amge_timing_read", "amge_vcycle_bytes",
            "amge_kuhn_build", "amge_problem_nlevels", "amge_problem_levels", "amge_problem_free",
@@ -211,13 +252,18 @@ def build_problem(kind, n, nlevels, alpha_hex, beta_hex):
 
 # ----------------------------------------------------------------------------- hierarchy
 class Hierarchy:
-    """Device-resident AMGe hierarchy (amge_setup_hierarchy).
+    """Device-resident AMGe hierarchy (amge_setup_hierarchy): the read-only level
+    operators.  Solves run on contexts (Context, amge_ctx_create); the hierarchy's own
+    methods vcycle / pcg / level_apply / timing_* use a default context of max_rhs
+    columns, created on first use.
 
     precond_bits: 32, 64 or 0 (chosen from the cancellation factor); max_rhs: widest
-    block for the batched path; tail_rows: levels of at most this many rows below the
-    fine one are folded into one dense FP64 operator (0: every level runs its kernels)."""
+    block of a context (the batched path); tail_rows: levels of at most this many rows
+    below the fine one are folded into one dense FP64 operator (0: every level runs its
+    kernels); allocator: "torch" (torch's caching allocator) or None (hipMalloc)."""
 
-    def __init__(self, levels, nu_primary=2, nu_aux=2, precond_bits=32, max_rhs=1, tail_rows=2048, stream=None):
+    def __init__(self, levels, nu_primary=2, nu_aux=2, precond_bits=32, max_rhs=1, tail_rows=2048, stream=None,
+                 allocator="torch"):
         L = len(levels)
         arr = (LevelC * L)()
         self._keep = []
@@ -231,19 +277,31 @@ class Hierarchy:
                 mats.append(M)
             self._keep.extend(mats)
             arr[i].A, arr[i].D, arr[i].P = (m.to_c() for m in mats)
-        opts = OptsC(nu_primary, nu_aux, precond_bits, max_rhs, tail_rows)
+        if allocator == "torch":
+            al, de = TORCH_ALLOC
+        elif allocator is None:
+            al, de = ALLOC_FN(), DEALLOC_FN()
+        else:
+            raise ValueError("allocator must be 'torch' or None")
+        opts = OptsC(nu_primary, nu_aux, precond_bits, max_rhs, tail_rows, al, de, None)
         h = C.c_void_p()
         _check(_lib.amge_setup_hierarchy(arr, L, C.byref(opts), _stream(stream), C.byref(h)))
         self._h = h
         self._keep = None
+        self._ctx = None
         self.opts = opts
+        self.max_rhs = max_rhs
         nl = C.c_int32()
         rows = (C.c_int32 * L)()
         _check(_lib.amge_hierarchy_info(h, C.byref(nl), rows))
         self.rows = list(rows)
         self.nlevels = nl.value
+        _LIVE["hierarchy"].add(self)
 
     def close(self):
+        if getattr(self, "_ctx", None) is not None:
+            self._ctx.close()
+            self._ctx = None
         if getattr(self, "_h", None):
             _lib.amge_destroy(self._h)
             self._h = None
@@ -258,47 +316,107 @@ class Hierarchy:
     def handle(self):
         return self._h
 
+    def context(self, nrhs=1):
+        """A new context (work buffers, stream, captured graphs) for up to nrhs columns."""
+        return Context(self, nrhs)
+
+    @property
+    def ctx(self):
+        """The default context (max_rhs columns)."""
+        if self._ctx is None:
+            self._ctx = Context(self, self.max_rhs)
+        return self._ctx
+
     def precision_info(self):
         """(kappa, precond_bits in use)."""
         k, b = C.c_double(), C.c_int32()
         _check(_lib.amge_precision_info(self._h, C.byref(k), C.byref(b)))
         return k.value, b.value
 
-    def footprint(self):
-        b = C.c_size_t()
-        _check(_lib.amge_footprint(self._h, C.byref(b)))
-        return b.value
+    def footprint_parts(self, nrhs=None):
+        """(hierarchy bytes, bytes of one context of nrhs columns; default max_rhs)."""
+        hb, cb = C.c_size_t(), C.c_size_t()
+        _check(_lib.amge_footprint(self._h, int(nrhs or self.max_rhs), C.byref(hb), C.byref(cb)))
+        return hb.value, cb.value
 
-    def vcycle(self, r, z, nrhs=1, stream=None):
-        """z = B r (one V-cycle) on n_1 x nrhs row-major FP64 device blocks."""
-        n = self.rows[0] * nrhs
-        _check(_lib.amge_vcycle(self._h, _vec(r, n), _vec(z, n), nrhs, _stream(stream)))
-
-    def pcg(self, b, x, rtol=1e-8, maxit=500, stop_norm=0, nrhs=1, stream=None):
-        """Returns (status, iters[nrhs], relres[nrhs]); status 0 or 1 (not converged)."""
-        it = (C.c_int32 * nrhs)()
-        rr = (C.c_double * nrhs)()
-        n = self.rows[0] * nrhs
-        code = _check(_lib.amge_pcg_solve(self._h, _vec(b, n), _vec(x, n), nrhs, float(rtol), int(maxit),
-                                          int(stop_norm), it, rr, _stream(stream)), allow=(0, 1))
-        return code, list(it), list(rr)
+    def footprint(self, nrhs=None):
+        """Device bytes of the hierarchy and one context of nrhs columns (default max_rhs)."""
+        return sum(self.footprint_parts(nrhs))
 
     def vcycle_bytes(self, precision=32, nrhs=1):
         v = C.c_double()
         _check(_lib.amge_vcycle_bytes(self._h, precision, nrhs, C.byref(v)))
         return v.value
 
+    def vcycle(self, r, z, nrhs=1, stream=None):
+        self.ctx.vcycle(r, z, nrhs=nrhs, stream=stream)
+
+    def pcg(self, b, x, rtol=1e-8, maxit=500, stop_norm=0, nrhs=1, stream=None):
+        return self.ctx.pcg(b, x, rtol=rtol, maxit=maxit, stop_norm=stop_norm, nrhs=nrhs, stream=stream)
+
+    def level_apply(self, level, op, x, out, x2=None, precision=64, stream=None):
+        self.ctx.level_apply(level, op, x, out, x2=x2, precision=precision, stream=stream)
+
     def timing_enable(self, on=True):
-        _check(_lib.amge_timing_enable(self._h, 1 if on else 0))
+        self.ctx.timing_enable(on)
+
+    def timing_read(self):
+        return self.ctx.timing_read()
+
+
+class Context:
+    """Execution context of a hierarchy (amge_ctx_create): the solve calls run here.
+    Contexts of one hierarchy may run concurrently (different streams or threads)."""
+
+    def __init__(self, H: Hierarchy, nrhs=1):
+        c = C.c_void_p()
+        _check(_lib.amge_ctx_create(H.handle, int(nrhs), C.byref(c)))
+        self._c = c
+        self.H = H            # the hierarchy outlives its contexts
+        self.nrhs = nrhs
+        self.rows = H.rows
+        _LIVE["context"].add(self)
+
+    def close(self):
+        if getattr(self, "_c", None):
+            _lib.amge_ctx_destroy(self._c)
+            self._c = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._c
+
+    def vcycle(self, r, z, nrhs=1, stream=None):
+        """z = B r (one V-cycle) on n_1 x nrhs row-major FP64 device blocks."""
+        n = self.rows[0] * nrhs
+        _check(_lib.amge_vcycle(self._c, _vec(r, n), _vec(z, n), nrhs, _stream(stream)))
+
+    def pcg(self, b, x, rtol=1e-8, maxit=500, stop_norm=0, nrhs=1, stream=None):
+        """Returns (status, iters[nrhs], relres[nrhs]); status 0 or 1 (not converged)."""
+        it = (C.c_int32 * nrhs)()
+        rr = (C.c_double * nrhs)()
+        n = self.rows[0] * nrhs
+        code = _check(_lib.amge_pcg_solve(self._c, _vec(b, n), _vec(x, n), nrhs, float(rtol), int(maxit),
+                                          int(stop_norm), it, rr, _stream(stream)), allow=(0, 1))
+        return code, list(it), list(rr)
+
+    def timing_enable(self, on=True):
+        _check(_lib.amge_timing_enable(self._c, 1 if on else 0))
 
     def timing_read(self):
         """(ms, launches, algorithmic bytes) of the fine-level A kernels since the last read."""
         ms, n, by = C.c_double(), C.c_int64(), C.c_double()
-        _check(_lib.amge_timing_read(self._h, C.byref(ms), C.byref(n), C.byref(by)))
+        _check(_lib.amge_timing_read(self._c, C.byref(ms), C.byref(n), C.byref(by)))
         return ms.value, n.value, by.value
 
     def level_apply(self, level, op, x, out, x2=None, precision=64, stream=None):
-        _check(_lib.amge_level_apply(self._h, level, op, precision, _ptr(x), _ptr(x2), _ptr(out),
+        _check(_lib.amge_level_apply(self._c, level, op, precision, _ptr(x), _ptr(x2), _ptr(out),
                                      _stream(stream)))
 
 
@@ -316,6 +434,7 @@ class Server:
         self._hier = []
         self._cap = 256
         self._buf = (CompletionC * self._cap)()
+        _LIVE["server"].add(self)
 
     def close(self):
         if getattr(self, "_h", None):

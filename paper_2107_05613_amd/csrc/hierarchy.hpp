@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <memory>
 #include <vector>
 
 #include "state.hpp"
@@ -101,9 +102,17 @@ template <> inline Work<double>& DLevel::bw<double>() { return bw64; }
 
 }  // namespace amge
 
+// A hierarchy (amge_setup_hierarchy) holds the read-only device operators of every
+// level.  A context (amge_ctx_create) is an execution state: a copy of the hierarchy's
+// operator descriptors (pointing at the hierarchy's device memory) plus work buffers,
+// PCG state, stream, events and captured graphs of its own, so contexts of one
+// hierarchy run concurrently.  Every launch routine works on an amge_hierarchy object:
+// the hierarchy itself during set-up, a context's state afterwards.
 struct amge_hierarchy {
     std::vector<amge::DLevel> lv;
     amge_opts opts{};
+    const amge_hierarchy* parent = nullptr;   // context state: the hierarchy it runs
+    int nrhs_cap = 0;            // context state: columns its work buffers hold
     int nc = 0;                  // coarsest size
     double kappa = 1.0;          // largest cancellation factor of the auxiliary matrices
     double* Ainv = nullptr;      // coarsest inverse from the Cholesky factor
@@ -117,7 +126,7 @@ struct amge_hierarchy {
     double *part_pq = nullptr, *part_dots[2] = {nullptr, nullptr};
     amge::dev::PcgStatus* st = nullptr;
     int* flags = nullptr;        // [0] done, [1] breakdown, [2..3] iteration count by buffer parity
-    // batched PCG (NC = max_rhs rounded up to a power of two, columns beyond nrhs are zero)
+    // batched PCG (NC = columns rounded up to a power of two, columns beyond nrhs are zero)
     int NC = 1, lgNC = 0;
     double *bX = nullptr, *bR = nullptr, *bP = nullptr, *bQ = nullptr, *bZ = nullptr, *bZv = nullptr;
     double* bpart = nullptr;
@@ -125,7 +134,7 @@ struct amge_hierarchy {
     amge::dev::ColState* cs = nullptr;
     amge::dev::BatchStatus* bs = nullptr;
     int* zero_flag = nullptr;    // a device 0: the stop flag of launches outside PCG iterations
-    hipStream_t gstream = nullptr;   // the hierarchy's stream for graph capture / replay
+    hipStream_t gstream = nullptr;   // the state's stream for graph capture / replay
     hipGraphExec_t gexec[7][2] = {}; // captured batched PCG iteration per active width 2^i and parity
     int bpar = 0;                    // parity of the next batched iteration: z block bpar is the new z
     hipGraphExec_t pexec[2] = {};    // one captured single-column PCG iteration per buffer parity
@@ -137,8 +146,14 @@ struct amge_hierarchy {
     amge::dev::PcgRecord* ring_dev = nullptr; // its device address
     uint32_t epoch = 0;
     hipEvent_t pev[NPEV] = {};
+    // device memory owned by this object: from the arena if one is set (no allocation
+    // at all), else from the caller's allocator (opts.alloc) or hipMalloc.  dry: only
+    // count the bytes (sizing), hand out placeholder addresses that are never used.
     std::vector<void*> allocs;
     size_t bytes = 0;
+    bool dry = false;
+    char* arena = nullptr;
+    size_t arena_size = 0, arena_used = 0;
     amge::Probe probe;
     ~amge_hierarchy() {
         if (gstream) (void)hipStreamSynchronize(gstream);
@@ -153,27 +168,71 @@ struct amge_hierarchy {
         if (ev_in) (void)hipEventDestroy(ev_in);
         if (ev_out) (void)hipEventDestroy(ev_out);
         if (gstream) (void)hipStreamDestroy(gstream);
-        for (void* a : allocs) (void)hipFree(a);
+        if (!allocs.empty()) {
+            // the caller's allocator may hand the memory out again at once: no work queued
+            // on any stream may still use it
+            if (opts.dealloc) (void)hipDeviceSynchronize();
+            for (void* a : allocs) {
+                if (opts.dealloc) opts.dealloc(a, opts.alloc_user);
+                else (void)hipFree(a);
+            }
+        }
     }
     template <class T>
     T* alloc(size_t n) {
         if (n == 0) n = 1;
+        const size_t nb = (n * sizeof(T) + 255) & ~(size_t)255;
+        if (arena) {
+            if (arena_used + nb > arena_size) {
+                char msg[160];
+                snprintf(msg, sizeof(msg), "work buffers need more than the %zu bytes of the static scratch",
+                         arena_size);
+                amge::fail(AMGE_ERR_ARG, msg);
+            }
+            T* ptr = reinterpret_cast<T*>(arena + arena_used);
+            arena_used += nb;
+            return ptr;
+        }
+        bytes += n * sizeof(T);
+        if (dry) return reinterpret_cast<T*>((uintptr_t)256);
         void* ptr = nullptr;
-        hipError_t e = hipMalloc(&ptr, n * sizeof(T));
-        if (e != hipSuccess) {
-            size_t fr = 0, tot = 0;
-            (void)hipGetLastError();
-            (void)hipMemGetInfo(&fr, &tot);
-            char msg[160];
-            snprintf(msg, sizeof(msg), "hipMalloc of %zu bytes failed (%s; device memory free %zu of %zu bytes)",
-                     n * sizeof(T), hipGetErrorString(e), fr, tot);
-            amge::fail(AMGE_ERR_OOM, msg);
+        if (opts.alloc) {
+            ptr = opts.alloc(n * sizeof(T), opts.alloc_user);
+            if (!ptr) {
+                bytes -= n * sizeof(T);
+                char msg[160];
+                snprintf(msg, sizeof(msg), "the caller's allocator returned no memory for %zu bytes", n * sizeof(T));
+                amge::fail(AMGE_ERR_OOM, msg);
+            }
+        } else {
+            hipError_t e = hipMalloc(&ptr, n * sizeof(T));
+            if (e != hipSuccess) {
+                size_t fr = 0, tot = 0;
+                (void)hipGetLastError();
+                (void)hipMemGetInfo(&fr, &tot);
+                char msg[160];
+                snprintf(msg, sizeof(msg), "hipMalloc of %zu bytes failed (%s; device memory free %zu of %zu bytes)",
+                         n * sizeof(T), hipGetErrorString(e), fr, tot);
+                bytes -= n * sizeof(T);
+                amge::fail(AMGE_ERR_OOM, msg);
+            }
         }
         allocs.push_back(ptr);
-        bytes += n * sizeof(T);
         return (T*)ptr;
     }
 };
+
+// A context: execution state of one hierarchy (see above).
+struct amge_ctx {
+    amge_hierarchy st;
+};
+
+namespace amge {
+// Execution state for nrhs columns of hierarchy P (nrhs <= P's max_rhs): operator
+// descriptors copied from P, work buffers, PCG state, stream, events and the pinned
+// iteration ring allocated here.  dry: only sizes it (amge_footprint).
+std::unique_ptr<amge_ctx> make_ctx(const amge_hierarchy* P, int nrhs, bool dry = false);
+}  // namespace amge
 
 namespace amge {
 // One batched PCG iteration of parity par (z block par receives the new z) on the

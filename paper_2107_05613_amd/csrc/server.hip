@@ -103,7 +103,9 @@ struct Request {
 
 // One resident hierarchy and its columns.
 struct Group {
-    amge_hierarchy* H = nullptr;
+    const amge_hierarchy* hier = nullptr;   // the resident hierarchy
+    std::unique_ptr<amge_ctx> ctx;          // the server's context of it (max_rhs columns)
+    amge_hierarchy* H = nullptr;            // the context's execution state
     bool grouped = false;          // member of an ensemble
     hipStream_t stream = nullptr;  // where its inserts, chunks and copy-outs run
     size_t footprint = 0;          // device bytes of the hierarchy
@@ -452,19 +454,24 @@ extern "C" amge_status amge_server_create(size_t hierarchy_budget, size_t inflig
 extern "C" void amge_server_destroy(amge_server* s) { delete s; }
 
 namespace {
-amge_status server_add(amge_server* s, amge_hierarchy* h, int32_t* id, int ensemble) {
+amge_status server_add(amge_server* s, amge_hierarchy* hier, int32_t* id, int ensemble) {
     const bool grouped = ensemble >= 0;
     return sguard([&]() -> amge_status {
         if (ensemble >= MAX_ENSEMBLES) fail(AMGE_ERR_ARG, "ensemble index out of range");
-        if (!s || !h || !id) fail(AMGE_ERR_ARG, "null argument");
-        if (h->NC < 2) fail(AMGE_ERR_ARG, "hierarchy needs max_rhs >= 2 to serve");
+        if (!s || !hier || !id) fail(AMGE_ERR_ARG, "null argument");
+        if (hier->parent) fail(AMGE_ERR_ARG, "not a hierarchy");
+        if (hier->opts.max_rhs < 2) fail(AMGE_ERR_ARG, "hierarchy needs max_rhs >= 2 to serve");
         for (auto& g : s->groups)
-            if (g->H == h) fail(AMGE_ERR_ARG, "hierarchy already added");
-        if (s->hierarchy_budget && s->resident + h->bytes > s->hierarchy_budget)
+            if (g->hier == hier) fail(AMGE_ERR_ARG, "hierarchy already added");
+        const size_t need = hier->bytes + make_ctx(hier, hier->opts.max_rhs, true)->st.bytes;
+        if (s->hierarchy_budget && s->resident + need > s->hierarchy_budget)
             fail(AMGE_ERR_BUSY, "hierarchy does not fit the device memory budget");
         auto g = std::make_unique<Group>();
+        g->hier = hier;
+        g->ctx = make_ctx(hier, hier->opts.max_rhs);
+        amge_hierarchy* h = &g->ctx->st;
         g->H = h;
-        g->footprint = h->bytes;
+        g->footprint = hier->bytes + h->bytes;
         // one column of the work blocks: six FP64 PCG blocks and the V-cycle's level blocks
         size_t cb = 6 * sizeof(double) * (size_t)h->lv[0].n;
         const size_t vs = (h->opts.precond_bits == 32 && h->lv.size() > 1) ? sizeof(float) : sizeof(double);
@@ -476,7 +483,7 @@ amge_status server_add(amge_server* s, amge_hierarchy* h, int32_t* id, int ensem
             // product with A_1 and about twelve FP64 vector streams of the PCG updates
             const int bits = h->opts.precond_bits == 32 && h->lv.size() > 1 ? 32 : 64;
             double b1 = 0, b2 = 0;
-            if (amge_vcycle_bytes(h, bits, 1, &b1) != AMGE_OK || amge_vcycle_bytes(h, bits, 2, &b2) != AMGE_OK)
+            if (amge_vcycle_bytes(hier, bits, 1, &b1) != AMGE_OK || amge_vcycle_bytes(hier, bits, 2, &b2) != AMGE_OK)
                 fail(AMGE_ERR_ARG, "cost model");
             const double n1 = h->lv[0].n;
             const double col = (b2 - b1) + 12 * 8 * n1;

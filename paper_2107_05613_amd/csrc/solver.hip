@@ -197,7 +197,7 @@ static bool verbose() {
 static std::mutex g_tune_mu;
 static std::map<TuneKey, int> g_tune;
 
-int tune_lanes(const Csr& A, bool incidence, hipStream_t s) {
+int tune_lanes(const Csr& A, bool incidence, const amge_opts& opts, hipStream_t s) {
     TuneKey key{A.nrows, A.ncols, A.nnz(), incidence};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -215,6 +215,7 @@ int tune_lanes(const Csr& A, bool incidence, hipStream_t s) {
     int best = cands[0];
     if (cands.size() > 1) {
         amge_hierarchy tmp;   // owns the trial buffers
+        tmp.opts = opts;
         float* x = tmp.alloc<float>(A.ncols);
         float* y = tmp.alloc<float>(A.nrows);
         int* zero = tmp.alloc<int>(1);
@@ -226,6 +227,7 @@ int tune_lanes(const Csr& A, bool incidence, hipStream_t s) {
         float best_ms = 1e30f;
         for (int K : cands) {
             amge_hierarchy t2;
+            t2.opts = opts;
             DSell M = upload_sell(&t2, A, incidence, K, s);
             auto run = [&]() {
                 if (incidence) sell_inc<float>(M, 0, x, y, s, zero);
@@ -261,7 +263,7 @@ int tune_lanes(const Csr& A, bool incidence, hipStream_t s) {
 
 DSell upload_tuned(amge_hierarchy* H, const Csr& A, bool incidence, hipStream_t s,
                    const std::vector<int>* lead = nullptr) {
-    return upload_sell(H, A, incidence, tune_lanes(A, incidence, s), s, lead);
+    return upload_sell(H, A, incidence, tune_lanes(A, incidence, H->opts, s), s, lead);
 }
 
 // A signed incidence (entries +-1): rows of one common length W <= 4 (the fine-level
@@ -707,6 +709,7 @@ void tune_tail(amge_hierarchy* H, hipStream_t s) {
     if (!H->tail_n || H->NC < 2) return;
     const size_t m = (size_t)H->tail_n * H->NC;
     amge_hierarchy tmp;   // owns the trial buffers
+    tmp.opts = H->opts;
     T* B = tmp.alloc<T>(m);
     T* X = tmp.alloc<T>(m);
     HIPCHECK(hipMemsetAsync(B, 0, sizeof(T) * m, s));
@@ -840,23 +843,29 @@ void build_coarse(amge_hierarchy* H, const Csr& A, hipStream_t s, std::vector<do
     ainv.swap(Ainv);
 }
 
+// l1 scalings of a level (read-only, in the hierarchy): dinv = 1 / d, dhinv = 1 / dhat.
 template <class T>
-void alloc_work(amge_hierarchy* H, DLevel& L, Work<T>& w, const std::vector<double>& dinv,
-                const std::vector<double>& dhinv, hipStream_t s) {
-    size_t nr = (size_t)L.n, mr = (size_t)L.m;
-    w.b = H->alloc<T>(nr);
-    w.x = H->alloc<T>(nr);
-    w.xt = H->alloc<T>(nr);
-    w.r = H->alloc<T>(nr);
-    w.g = H->alloc<T>(mr);
-    w.y = H->alloc<T>(mr);
-    w.yt = H->alloc<T>(mr);
-    w.bd = H->alloc<T>(nr);
-    w.gd = H->alloc<T>(mr);
+void upload_scalings(amge_hierarchy* H, Work<T>& w, const std::vector<double>& dinv,
+                     const std::vector<double>& dhinv, hipStream_t s) {
     std::vector<T> a(dinv.begin(), dinv.end()), c(dhinv.begin(), dhinv.end());
     w.dinv = upload(H, a.data(), a.size(), s);
     w.dhinv = upload(H, c.data(), c.size(), s);
     HIPCHECK(hipStreamSynchronize(s));
+}
+
+// Single-column work vectors of one level (context state); the scalings stay shared.
+template <class T>
+void alloc_work(amge_hierarchy* C, DLevel& L, Work<T>& w) {
+    size_t nr = (size_t)L.n, mr = (size_t)L.m;
+    w.b = C->alloc<T>(nr);
+    w.x = C->alloc<T>(nr);
+    w.xt = C->alloc<T>(nr);
+    w.r = C->alloc<T>(nr);
+    w.g = C->alloc<T>(mr);
+    w.y = C->alloc<T>(mr);
+    w.yt = C->alloc<T>(mr);
+    w.bd = C->alloc<T>(nr);
+    w.gd = C->alloc<T>(mr);
 }
 
 // Batched work block of one level (n x NC, m x NC) in the preconditioner precision;
@@ -896,6 +905,7 @@ void tune_batched(amge_hierarchy* H, hipStream_t s) {
             }
     if (!mx) return;
     amge_hierarchy tmp;   // owns the trial buffers
+    tmp.opts = H->opts;
     T* X = tmp.alloc<T>(mx);
     T* Y = tmp.alloc<T>(my);
     HIPCHECK(hipMemsetAsync(X, 0, sizeof(T) * mx, s));
@@ -932,21 +942,7 @@ void setup_batched(amge_hierarchy* H, const std::vector<HostLevel>& hl, hipStrea
             L.bAux = upload_sell_b(H, h.Aux, false, f32, !f32, s, &h.aux_lead);
             L.bD = upload_sell_b(H, h.D, true, false, false, s);
         }
-        if (f32 && nl > 1) alloc_bwork<float>(H, L, L.w32, L.bw32);
-        else alloc_bwork<double>(H, L, L.w64, L.bw64);
     }
-    const size_t nn = (size_t)H->lv[0].n * NC;
-    H->bX = H->alloc<double>(nn);
-    H->bR = H->alloc<double>(nn);
-    H->bP = H->alloc<double>(nn);
-    H->bQ = H->alloc<double>(nn);
-    // the two z blocks (new and old, alternating with the iteration parity): FP64 blocks
-    // bZ and bZv, or, for an FP32 V-cycle, the two halves of bZ
-    H->bZ = H->alloc<double>(nn);
-    H->bZv = H->alloc<double>(nn);
-    H->bpart = H->alloc<double>((size_t)3 * NC * BPCG_BLOCKS);
-    H->cs = H->alloc<dev::ColState>(NC);
-    H->bs = H->alloc<dev::BatchStatus>(1);
     if (f32 && nl > 1) tune_batched<float>(H, s);
     else tune_batched<double>(H, s);
 }
@@ -1113,14 +1109,6 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     H->lv.resize(nl);
     H->zero_flag = H->alloc<int>(1);
     HIPCHECK(hipMemsetAsync(H->zero_flag, 0, sizeof(int), s));
-    HIPCHECK(hipStreamCreateWithFlags(&H->gstream, hipStreamNonBlocking));
-    HIPCHECK(hipEventCreateWithFlags(&H->ev_in, hipEventDisableTiming));
-    HIPCHECK(hipEventCreateWithFlags(&H->ev_out, hipEventDisableTiming));
-    for (hipEvent_t& e : H->pev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    HIPCHECK(hipHostMalloc((void**)&H->ring, sizeof(dev::PcgRecord) * dev::PCG_RING,
-                           hipHostMallocMapped | hipHostMallocCoherent));
-    memset((void*)H->ring, 0, sizeof(dev::PcgRecord) * dev::PCG_RING);
-    HIPCHECK(hipHostGetDevicePointer((void**)&H->ring_dev, H->ring, 0));
     const bool batched = H->opts.max_rhs > 1;
     std::vector<HostLevel> hl(batched ? nl : 0);
     std::vector<TailLevel> tl(nl);   // host copies of the levels that may be folded
@@ -1131,9 +1119,6 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         if (batched) hl[k].A = A[k];
         if (k == nl - 1) {
             build_coarse(H, A[k], s, ainv);
-            std::vector<double> none;
-            alloc_work<float>(H, L, L.w32, none, none, s);
-            alloc_work<double>(H, L, L.w64, none, none, s);
             continue;
         }
         L.m = D[k].ncols;
@@ -1227,25 +1212,13 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
                 hl[k].D = D[k];
             }
         }
-        alloc_work<float>(H, L, L.w32, dinv, dhinv, s);
-        alloc_work<double>(H, L, L.w64, dinv, dhinv, s);
+        upload_scalings<float>(H, L.w32, dinv, dhinv, s);
+        upload_scalings<double>(H, L.w64, dinv, dhinv, s);
     }
     if (nl == 1) {
         // the fine matrix itself is needed by the outer PCG even on one level
         H->lv[0].A = upload_tuned(H, A[0], false, s);
     }
-    size_t n1 = (size_t)H->lv[0].n;
-    H->r = H->alloc<double>(n1);
-    H->p = H->alloc<double>(n1);
-    H->q = H->alloc<double>(n1);
-    H->z[0] = H->alloc<double>(n1);
-    H->z[1] = H->alloc<double>(n1);
-    H->x = H->alloc<double>(n1);
-    H->part_pq = H->alloc<double>(dev::NRED);
-    H->part_dots[0] = H->alloc<double>(3 * dev::NRED);
-    H->part_dots[1] = H->alloc<double>(3 * dev::NRED);
-    H->st = H->alloc<dev::PcgStatus>(1);
-    H->flags = H->alloc<int>(4);
     if (H->opts.precond_bits == 0)
         H->opts.precond_bits = std::ldexp(H->kappa, -24) <= AUTO_FP32_LIMIT ? 32 : 64;
     if (batched) setup_batched(H, hl, s);
@@ -1258,6 +1231,94 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         else tune_tail<double>(H, s);
     }
     HIPCHECK(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------ contexts
+// Execution state S of hierarchy P for nrhs columns: P's operator descriptors and
+// scalings (P's device memory; P holds no work buffers, so every work pointer copied
+// here is null), then the single-column level work in the V-cycle precision from S's
+// own allocator (an arena, the caller's allocator or hipMalloc).
+void init_state(amge_hierarchy* S, const amge_hierarchy* P, int nrhs) {
+    S->opts = P->opts;
+    S->parent = P;
+    S->nrhs_cap = nrhs;
+    S->lv = P->lv;
+    for (DLevel& L : S->lv) L.probe = nullptr;
+    S->nc = P->nc;
+    S->kappa = P->kappa;
+    S->Ainv = P->Ainv;
+    S->tail = P->tail;
+    S->tail_n = P->tail_n;
+    S->tail_op = P->tail_op;
+    S->tail_rpb = P->tail_rpb;
+    S->zero_flag = P->zero_flag;
+    const bool f32 = S->opts.precond_bits == 32 && S->lv.size() > 1;
+    for (DLevel& L : S->lv) {
+        if (f32) alloc_work<float>(S, L, L.w32);
+        else alloc_work<double>(S, L, L.w64);
+    }
+}
+
+std::unique_ptr<amge_ctx> make_ctx(const amge_hierarchy* P, int nrhs, bool dry) {
+    if (!P || P->parent) fail(AMGE_ERR_ARG, "not a hierarchy");
+    if (nrhs < 1 || nrhs > P->opts.max_rhs) fail(AMGE_ERR_ARG, "a context needs 1 <= nrhs <= max_rhs of its hierarchy");
+    auto C = std::make_unique<amge_ctx>();
+    amge_hierarchy* S = &C->st;
+    S->dry = dry;
+    init_state(S, P, nrhs);
+    const bool f32 = S->opts.precond_bits == 32 && S->lv.size() > 1;
+    // outer PCG (FP64, level-1 length) and its partial sums
+    const size_t n1 = (size_t)S->lv[0].n;
+    S->r = S->alloc<double>(n1);
+    S->p = S->alloc<double>(n1);
+    S->q = S->alloc<double>(n1);
+    S->z[0] = S->alloc<double>(n1);
+    S->z[1] = S->alloc<double>(n1);
+    S->x = S->alloc<double>(n1);
+    S->part_pq = S->alloc<double>(dev::NRED);
+    S->part_dots[0] = S->alloc<double>(3 * dev::NRED);
+    S->part_dots[1] = S->alloc<double>(3 * dev::NRED);
+    S->st = S->alloc<dev::PcgStatus>(1);
+    S->flags = S->alloc<int>(4);
+    if (nrhs > 1) {
+        int NC = 2, lg = 1;
+        while (NC < nrhs) {
+            NC *= 2;
+            ++lg;
+        }
+        S->NC = NC;
+        S->lgNC = lg;
+        for (DLevel& L : S->lv) {
+            if (f32) alloc_bwork<float>(S, L, L.w32, L.bw32);
+            else alloc_bwork<double>(S, L, L.w64, L.bw64);
+        }
+        const size_t nn = n1 * NC;
+        S->bX = S->alloc<double>(nn);
+        S->bR = S->alloc<double>(nn);
+        S->bP = S->alloc<double>(nn);
+        S->bQ = S->alloc<double>(nn);
+        // the two z blocks (new and old, alternating with the iteration parity): FP64
+        // blocks bZ and bZv, or, for an FP32 V-cycle, the two halves of bZ
+        S->bZ = S->alloc<double>(nn);
+        S->bZv = S->alloc<double>(nn);
+        S->bpart = S->alloc<double>((size_t)3 * NC * BPCG_BLOCKS);
+        S->cs = S->alloc<dev::ColState>(NC);
+        S->bs = S->alloc<dev::BatchStatus>(1);
+    } else {
+        S->NC = 1;
+        S->lgNC = 0;
+    }
+    if (!dry) {
+        HIPCHECK(hipStreamCreateWithFlags(&S->gstream, hipStreamNonBlocking));
+        HIPCHECK(hipEventCreateWithFlags(&S->ev_in, hipEventDisableTiming));
+        HIPCHECK(hipEventCreateWithFlags(&S->ev_out, hipEventDisableTiming));
+        for (hipEvent_t& e : S->pev) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIPCHECK(hipHostMalloc((void**)&S->ring, sizeof(dev::PcgRecord) * dev::PCG_RING,
+                               hipHostMallocMapped | hipHostMallocCoherent));
+        memset((void*)S->ring, 0, sizeof(dev::PcgRecord) * dev::PCG_RING);
+        HIPCHECK(hipHostGetDevicePointer((void**)&S->ring_dev, S->ring, 0));
+    }
+    return C;
 }
 
 // ------------------------------------------------------------------ PCG
@@ -1718,6 +1779,9 @@ extern "C" void amge_default_opts(amge_opts* o) {
     o->precond_bits = 32;
     o->max_rhs = 1;
     o->tail_rows = 2048;
+    o->alloc = nullptr;
+    o->dealloc = nullptr;
+    o->alloc_user = nullptr;
 }
 
 extern "C" amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nlevels, const amge_opts* opts,
@@ -1732,6 +1796,8 @@ extern "C" amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nl
             H->opts.tail_rows < 0 || H->opts.tail_rows > 8192 ||
             (H->opts.precond_bits != 0 && H->opts.precond_bits != 32 && H->opts.precond_bits != 64))
             fail(AMGE_ERR_ARG, "invalid options");
+        if ((H->opts.alloc == nullptr) != (H->opts.dealloc == nullptr))
+            fail(AMGE_ERR_ARG, "give both alloc and dealloc, or neither");
         setup(H.get(), levels, nlevels, (hipStream_t)stream);
         *out = H.release();
         return AMGE_OK;
@@ -1740,13 +1806,25 @@ extern "C" amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nl
 
 extern "C" void amge_destroy(amge_hierarchy* h) { delete h; }
 
-extern "C" amge_status amge_footprint(const amge_hierarchy* h, size_t* bytes) {
-    if (!h || !bytes) {
-        set_last_error("null argument");
-        return AMGE_ERR_ARG;
-    }
-    *bytes = h->bytes;
-    return AMGE_OK;
+extern "C" amge_status amge_ctx_create(const amge_hierarchy* h, int32_t nrhs, amge_ctx** out) {
+    return guard([&]() -> amge_status {
+        if (!h || !out) fail(AMGE_ERR_ARG, "null argument");
+        *out = nullptr;
+        *out = make_ctx(h, nrhs).release();
+        return AMGE_OK;
+    });
+}
+
+extern "C" void amge_ctx_destroy(amge_ctx* c) { delete c; }
+
+extern "C" amge_status amge_footprint(const amge_hierarchy* h, int32_t nrhs, size_t* hier_bytes,
+                                      size_t* ctx_bytes) {
+    return guard([&]() -> amge_status {
+        if (!h || h->parent) fail(AMGE_ERR_ARG, "not a hierarchy");
+        if (hier_bytes) *hier_bytes = h->bytes;
+        if (ctx_bytes) *ctx_bytes = make_ctx(h, nrhs, true)->st.bytes;
+        return AMGE_OK;
+    });
 }
 
 extern "C" amge_status amge_precision_info(const amge_hierarchy* h, double* kappa, int32_t* precond_bits) {
@@ -1770,10 +1848,11 @@ extern "C" amge_status amge_hierarchy_info(const amge_hierarchy* h, int32_t* nle
     return AMGE_OK;
 }
 
-extern "C" amge_status amge_vcycle(amge_hierarchy* h, const double* r, double* z, int32_t nrhs, void* stream) {
+extern "C" amge_status amge_vcycle(amge_ctx* c, const double* r, double* z, int32_t nrhs, void* stream) {
     return guard([&]() -> amge_status {
-        if (!h || !r || !z) fail(AMGE_ERR_ARG, "null argument");
-        if (nrhs < 1 || nrhs > h->opts.max_rhs) fail(AMGE_ERR_ARG, "amge_vcycle: need 1 <= nrhs <= max_rhs");
+        if (!c || !r || !z) fail(AMGE_ERR_ARG, "null argument");
+        amge_hierarchy* h = &c->st;
+        if (nrhs < 1 || nrhs > h->nrhs_cap) fail(AMGE_ERR_ARG, "amge_vcycle: need 1 <= nrhs <= the context's nrhs");
         hipStream_t s = (hipStream_t)stream;
         if (nrhs > 1) {
             if (h->opts.precond_bits == 32 && h->lv.size() > 1) bprecondition<float>(h, r, z, nrhs, s);
@@ -1788,12 +1867,14 @@ extern "C" amge_status amge_vcycle(amge_hierarchy* h, const double* r, double* z
     });
 }
 
-extern "C" amge_status amge_pcg_solve(amge_hierarchy* h, const double* b, double* x, int32_t nrhs, double rtol,
+extern "C" amge_status amge_pcg_solve(amge_ctx* c, const double* b, double* x, int32_t nrhs, double rtol,
                                       int32_t maxit, int32_t stop_norm, int32_t* iters, double* relres,
                                       void* stream) {
     return guard([&]() -> amge_status {
-        if (!h || !b || !x || !iters || !relres) fail(AMGE_ERR_ARG, "null argument");
-        if (nrhs < 1 || nrhs > h->opts.max_rhs) fail(AMGE_ERR_ARG, "amge_pcg_solve: need 1 <= nrhs <= max_rhs");
+        if (!c || !b || !x || !iters || !relres) fail(AMGE_ERR_ARG, "null argument");
+        amge_hierarchy* h = &c->st;
+        if (nrhs < 1 || nrhs > h->nrhs_cap)
+            fail(AMGE_ERR_ARG, "amge_pcg_solve: need 1 <= nrhs <= the context's nrhs");
         if (maxit < 1) fail(AMGE_ERR_ARG, "maxit must be >= 1");
         if (nrhs > 1) return bpcg(h, b, x, nrhs, rtol, maxit, stop_norm, iters, relres, (hipStream_t)stream);
         int it = 0;
@@ -1805,10 +1886,11 @@ extern "C" amge_status amge_pcg_solve(amge_hierarchy* h, const double* b, double
     });
 }
 
-extern "C" amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_t op, int32_t precision,
+extern "C" amge_status amge_level_apply(amge_ctx* c, int32_t level, int32_t op, int32_t precision,
                                         const double* in, const double* in2, double* out, void* stream) {
     return guard([&]() -> amge_status {
-        if (!h || !in || !out) fail(AMGE_ERR_ARG, "null argument");
+        if (!c || !in || !out) fail(AMGE_ERR_ARG, "null argument");
+        amge_hierarchy* h = &c->st;
         const int nl = (int)h->lv.size();
         if (level < 0 || level >= nl) fail(AMGE_ERR_ARG, "level out of range");
         if (precision != 32 && precision != 64) fail(AMGE_ERR_ARG, "precision must be 32 or 64");
@@ -1822,7 +1904,8 @@ extern "C" amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_
             return AMGE_OK;
         }
         if (last) fail(AMGE_ERR_ARG, "operator not stored on the coarsest level");
-        if ((op == AMGE_OP_SMOOTH || op == AMGE_OP_SMOOTHT) && !in2) fail(AMGE_ERR_ARG, "smoother needs x");
+        if ((op == AMGE_OP_SMOOTH || op == AMGE_OP_SMOOTHT || op == AMGE_OP_SWEEP || op == AMGE_OP_RESID) && !in2)
+            fail(AMGE_ERR_ARG, "this operation needs x (in2)");
         // in / out lengths
         int nin = L.n, nout = L.n;
         switch (op) {
@@ -1832,12 +1915,14 @@ extern "C" amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_
             case AMGE_OP_DT: nout = L.m; break;
             case AMGE_OP_P: nin = h->lv[level + 1].n; break;
             case AMGE_OP_PT: nout = h->lv[level + 1].n; break;
-            case AMGE_OP_SMOOTH: case AMGE_OP_SMOOTHT: break;
+            case AMGE_OP_SMOOTH: case AMGE_OP_SMOOTHT: case AMGE_OP_SWEEP: case AMGE_OP_RESID: break;
             default: fail(AMGE_ERR_ARG, "unknown op");
         }
         const int* z0 = h->zero_flag;
         auto run = [&](auto tag, const auto* vin, const auto* vin2, auto* vout) {
             using T = decltype(tag);
+            // the level work of this precision, if the context does not hold it yet
+            if (!L.w<T>().x) alloc_work<T>(h, L, L.w<T>());
             switch (op) {
                 case AMGE_OP_A: sell<T>(L.A, dev::SPMV, vin, nullptr, nullptr, vout, s, z0); break;
                 case AMGE_OP_AHAT: sell<T>(L.Ah, dev::SPMV, vin, nullptr, nullptr, vout, s, z0); break;
@@ -1845,6 +1930,9 @@ extern "C" amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_
                 case AMGE_OP_DT: sell_inc<T>(L.Dt, 0, vin, vout, s, z0); break;
                 case AMGE_OP_P: sell<T>(L.P, dev::SPMV, vin, nullptr, nullptr, vout, s, z0); break;
                 case AMGE_OP_PT: sell<T>(L.Pt, dev::SPMV, vin, nullptr, nullptr, vout, s, z0); break;
+                // the V-cycle's own A_k launches (timed by amge_timing_* on the fine level)
+                case AMGE_OP_SWEEP: asell<T>(L, dev::JAC, vin2, vin, L.w<T>().dinv, vout, s, z0); break;
+                case AMGE_OP_RESID: asell<T>(L, dev::RESID, vin2, vin, nullptr, vout, s, z0); break;
                 default: {
                     Work<T>& w = L.w<T>();
                     // x lives in w.x (copied in), result copied out
@@ -1867,27 +1955,26 @@ extern "C" amge_status amge_level_apply(amge_hierarchy* h, int32_t level, int32_
         } else {
             // FP32 kernels on rounded copies held in temporary buffers
             size_t nmax = (size_t)std::max(std::max(nin, nout), L.n);
-            float *fin = nullptr, *fin2 = nullptr, *fout = nullptr;
-            HIPCHECK(hipMalloc(&fin, nmax * sizeof(float)));
-            HIPCHECK(hipMalloc(&fin2, nmax * sizeof(float)));
-            HIPCHECK(hipMalloc(&fout, nmax * sizeof(float)));
+            amge_hierarchy tmp;   // owns the temporaries (the context's allocator)
+            tmp.opts = h->opts;
+            float* fin = tmp.alloc<float>(nmax);
+            float* fin2 = tmp.alloc<float>(nmax);
+            float* fout = tmp.alloc<float>(nmax);
             convert<double, float>(nin, in, fin, s);
             if (in2) convert<double, float>(L.n, in2, fin2, s);
             run(float{}, (const float*)fin, (const float*)fin2, fout);
             convert<float, double>(nout, fout, out, s);
             HIPCHECK(hipStreamSynchronize(s));
-            (void)hipFree(fin);
-            (void)hipFree(fin2);
-            (void)hipFree(fout);
         }
         HIPCHECK(hipGetLastError());
         return AMGE_OK;
     });
 }
 
-extern "C" amge_status amge_timing_enable(amge_hierarchy* h, int32_t enable) {
+extern "C" amge_status amge_timing_enable(amge_ctx* c, int32_t enable) {
     return guard([&]() -> amge_status {
-        if (!h) fail(AMGE_ERR_ARG, "null argument");
+        if (!c) fail(AMGE_ERR_ARG, "null argument");
+        amge_hierarchy* h = &c->st;
         h->probe.on = enable != 0;
         h->probe.used = 0;
         h->probe.bytes = 0;
@@ -1896,9 +1983,10 @@ extern "C" amge_status amge_timing_enable(amge_hierarchy* h, int32_t enable) {
     });
 }
 
-extern "C" amge_status amge_timing_read(amge_hierarchy* h, double* ms, int64_t* launches, double* bytes) {
+extern "C" amge_status amge_timing_read(amge_ctx* c, double* ms, int64_t* launches, double* bytes) {
     return guard([&]() -> amge_status {
-        if (!h || !ms || !launches || !bytes) fail(AMGE_ERR_ARG, "null argument");
+        if (!c || !ms || !launches || !bytes) fail(AMGE_ERR_ARG, "null argument");
+        amge_hierarchy* h = &c->st;
         double tot = 0;
         for (size_t i = 0; i < h->probe.used; ++i) {
             HIPCHECK(hipEventSynchronize(h->probe.ev[2 * i + 1]));
@@ -1920,6 +2008,7 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
         if (!h || !bytes) fail(AMGE_ERR_ARG, "null argument");
         if (precision != 32 && precision != 64) fail(AMGE_ERR_ARG, "precision must be 32 or 64");
         if (nrhs < 1 || nrhs > h->opts.max_rhs) fail(AMGE_ERR_ARG, "need 1 <= nrhs <= max_rhs");
+        if (h->parent) fail(AMGE_ERR_ARG, "not a hierarchy");
         const bool batched = nrhs > 1;
         const double sv = precision == 32 ? 4.0 : 8.0;   // value size
         const double sx = sv * nrhs;                       // one row of a vector block

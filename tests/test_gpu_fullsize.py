@@ -1,24 +1,32 @@
-"""Full-size checks in the launch configuration of the benchmark (the 64^3 H(curl)
-5-level problem, one right-hand side, FP32 V-cycle; the 48^3 H(div) 5-level problem with
-a 32-column block), through the C ABI.
+"""Full-size parity in the launch configuration of the benchmark, through the C ABI:
+the 64^3 H(curl) 5-level problem (one right-hand side; FP32 and FP64 V-cycles) and the
+48^3 H(div) 5-level problem with a 32-column block.
 
-At these sizes the oracle hierarchy is not rebuilt; instead
-* the fine operator A_1 (the kernel family that dominates the solve) is compared with
-  the oracle's fine matrix on every row, to the per-entry bounds of the small cases;
-* the solves are checked by properties that hold at any size: the true FP64 residual
-  ||b - A_1 x|| / ||b|| with the oracle's A_1, agreement of the FP32-preconditioned and
-  FP64 solutions, symmetry and positivity of the V-cycle operator B (Algorithm 4.1 with
-  the reversed post-smoother is symmetric), and batched columns against single-column
-  solves.
+Same inputs: the GPU hierarchies are set up from the oracle's own level matrices (built
+by oracle.hierarchy at full size), so only the solve phase differs.  Both workloads have
+unit coefficients, where the oracle's reformulation spread (tests/reformulation.py) is
+~1e-13, so the FP64 bar is the plain 1e-10:
+* the fine-level kernels the benchmark times (A_1 product, l1-Jacobi sweep and residual;
+  A_1 has 30.3 M entries, so the eight-deep unrolled instances run) per entry against
+  the oracle's A_1, FP64 1e-13 and FP32 1e-5 relative to |A||x| + |b|;
+* one V-cycle (FP64 <= 1e-10 relative; FP32 energy-norm error printed, <= 1e-3);
+* PCG: iteration counts at rtol 1e-8 within +-1, and the iterate after the oracle's count
+  within 1e-10 (FP64 preconditioner); FP32 preconditioner within +3 iterations and 1e-6
+  of the oracle solution (printed);
+* the batched block: sampled columns (first, middle, last) of the 32-column FP64 solve
+  against the oracle's single-column PCG, the FP32 block the same way to 1e-6;
+* properties that need no oracle: symmetry and positivity of B.
 """
 import numpy as np
 import pytest
 
 from paper_2107_05613_amd import workloads as W
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
 torch = pytest.importorskip("torch")
+
+SAMPLED = (0, 16, 31)
 
 
 def dev(x):
@@ -30,81 +38,121 @@ def host(t):
     return t.cpu().numpy()
 
 
-def oracle_fine_matrix(w):
-    from oracle.fem import FineMesh, fine_problem
-    a, b = W.coefficients(w)
-    A, _, _, _ = fine_problem(FineMesh(w.n), w.kind, a, b)
-    return A
+class Full:
+    def __init__(self, name, max_rhs=1):
+        import time
+        from oracle.hierarchy import build_hierarchy
+        from oracle.solve import Multilevel
+        from paper_2107_05613_amd import amge
+        w = W.WORKLOADS[name]
+        print(f"\n[fullsize] {w.name}: building the oracle hierarchy", flush=True)
+        t0 = time.perf_counter()
+        a, b = W.coefficients(w)
+        H = build_hierarchy(w.kind, w.n, w.levels, a, b, check_targets=False)
+        self.ml = Multilevel.from_hierarchy(H)
+        L = len(H.A)
+        levels = [(H.A[k], H.D[k], H.P[k] if k < L - 1 else None) for k in range(L)]
+        print(f"[fullsize] oracle hierarchy {[A.shape[0] for A in H.A]} in {time.perf_counter() - t0:.0f} s; "
+              f"GPU set-up from its matrices", flush=True)
+        self.gpu = {bits: amge.Hierarchy(levels, precond_bits=bits, max_rhs=max_rhs) for bits in (32, 64)}
+        self.w, self.H, self.A = w, H, H.A[0]
+        self._sol = {}
+
+    def oracle_pcg(self, b, key, **kw):
+        """Oracle PCG on b (cached by key): (x, iterations)."""
+        from oracle.solve import pcg
+        if key not in self._sol:
+            x, it, _ = pcg(self.A, b, self.ml, **kw)
+            self._sol[key] = (x, it)
+        return self._sol[key]
 
 
 @pytest.fixture(scope="module")
 def curl64():
-    from paper_2107_05613_amd import amge
-    w = W.WORKLOADS["curl_n64_l5"]
-    print(f"\n[fullsize] {w.name}", flush=True)
-    a, b = W.coefficients(w)
-    prod = amge.build_problem(w.kind, w.n, w.levels, a, b)
-    A = oracle_fine_matrix(w)
-    H = {bits: amge.Hierarchy(prod, precond_bits=bits) for bits in (32, 64)}
-    return w, A, H
+    return Full("curl_n64_l5")
 
 
 @pytest.fixture(scope="module")
 def div48():
-    from paper_2107_05613_amd import amge
-    w = W.WORKLOADS["div_n48_l5_rhs32"]
-    print(f"\n[fullsize] {w.name}", flush=True)
-    a, b = W.coefficients(w)
-    prod = amge.build_problem(w.kind, w.n, w.levels, a, b)
-    A = oracle_fine_matrix(w)
-    H = {bits: amge.Hierarchy(prod, precond_bits=bits, max_rhs=w.nrhs) for bits in (32, 64)}
-    return w, A, H
+    return Full("div_n48_l5_rhs32", max_rhs=32)
 
 
-def test_fullsize_fine_operator(curl64):
-    """a1 at full size: A_1 x on every row against the oracle's fine matrix."""
+def test_fullsize_fine_kernels(curl64):
+    """a1 + a2 at full size: the A_1 product, the l1-Jacobi sweep and the residual (the
+    launches the benchmark times) on every row against the oracle's A_1."""
     from paper_2107_05613_amd import amge
-    w, A, H = curl64
-    x = np.random.default_rng(3).uniform(-1, 1, A.shape[0])
-    ref = A @ x
-    scale = abs(A) @ np.abs(x)
+    f = curl64
+    A, ml = f.A, f.ml
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1, 1, A.shape[0])
+    b = rng.uniform(-1, 1, A.shape[0])
+    Ax = A @ x
+    dinv = 1.0 / ml.levels[0].d
+    refs = {amge.OP_A: Ax, amge.OP_SWEEP: x + dinv * (b - Ax), amge.OP_RESID: b - Ax}
+    absAx = abs(A) @ np.abs(x)
+    scales = {amge.OP_A: absAx, amge.OP_SWEEP: np.abs(x) + dinv * (np.abs(b) + absAx),
+              amge.OP_RESID: np.abs(b) + absAx}
     out = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
-    for bits, tol in ((64, 1e-13), (32, 1e-5)):
-        H[32].level_apply(0, amge.OP_A, dev(x), out, precision=bits)
-        e = float(np.max(np.abs(host(out) - ref) / scale))
-        print(f"A_1 ({A.shape[0]} rows, {A.nnz} nnz) FP{bits}: max error / (|A||x|) = {e:.1e}")
-        assert e <= tol
+    for op, ref in refs.items():
+        for bits, tol in ((64, 1e-13), (32, 1e-5)):
+            if op == amge.OP_A:
+                f.gpu[32].level_apply(0, op, dev(x), out, precision=bits)
+            else:
+                f.gpu[32].level_apply(0, op, dev(b), out, x2=dev(x), precision=bits)
+            e = float(np.max(np.abs(host(out) - ref) / scales[op]))
+            print(f"A_1 ({A.shape[0]} rows, {A.nnz} nnz) op {op} FP{bits}: max error / scale = {e:.1e}")
+            assert e <= tol, (op, bits)
+
+
+def test_fullsize_vcycle(curl64):
+    """Algorithm 4.1 at full size against the oracle's V-cycle."""
+    f = curl64
+    b = W.rhs(f.A.shape[0], f.w.rhs_seed)[:, 0]
+    ref = f.ml.vcycle(b)
+    z = torch.empty(f.A.shape[0], dtype=torch.float64, device="cuda")
+    f.gpu[64].vcycle(dev(b), z)
+    e64 = float(np.max(np.abs(host(z) - ref)) / np.max(np.abs(ref)))
+    f.gpu[32].vcycle(dev(b), z)
+    d = host(z) - ref
+    en = float(np.sqrt(d @ (f.A @ d)) / np.sqrt(ref @ (f.A @ ref)))
+    print(f"V-cycle vs oracle: FP64 {e64:.1e} (max-norm relative), FP32 {en:.1e} (energy norm)")
+    assert e64 <= 1e-10
+    assert en <= 1e-3
 
 
 def test_fullsize_pcg(curl64):
-    """a7 at full size: FP32-preconditioned and FP64 PCG both reach rtol 1e-8 in the
-    preconditioner norm, with small true residuals, and agree with each other."""
-    w, A, H = curl64
-    b = W.rhs(A.shape[0], w.rhs_seed)[:, 0]
-    xs = {}
-    for bits in (32, 64):
-        x = torch.zeros(A.shape[0], dtype=torch.float64, device="cuda")
-        status, it, rr = H[bits].pcg(dev(b), x, rtol=w.rtol, maxit=500)
-        xs[bits] = host(x)
-        res = np.linalg.norm(b - A @ xs[bits]) / np.linalg.norm(b)
-        print(f"FP{bits} preconditioner: {it[0]} iterations, B-norm relres {rr[0]:.1e}, "
-              f"true l2 residual {res:.1e}")
-        assert status == 0 and rr[0] <= w.rtol
-        assert res <= 1e-6
-    d = np.linalg.norm(xs[32] - xs[64]) / np.linalg.norm(xs[64])
-    print(f"FP32-precond vs FP64 solution: {d:.1e}")
-    assert d <= 1e-6
+    """a7 at full size: FP64 PCG takes the oracle's iteration count (+-1) and, after that
+    count, matches its iterate to 1e-10; the FP32-preconditioned solve (the benchmark
+    step) converges within +3 iterations and 1e-6 of the oracle's solution."""
+    f = curl64
+    b = W.rhs(f.A.shape[0], f.w.rhs_seed)[:, 0]
+    xo, ito = f.oracle_pcg(b, "rhs0", rtol=f.w.rtol)
+    x = torch.zeros(f.A.shape[0], dtype=torch.float64, device="cuda")
+    status, it, rr = f.gpu[64].pcg(dev(b), x, rtol=f.w.rtol, maxit=500)
+    assert status == 0 and abs(it[0] - ito) <= 1, (it, ito)
+    f.gpu[64].pcg(dev(b), x, rtol=0.0, maxit=ito)
+    e64 = float(np.linalg.norm(host(x) - xo) / np.linalg.norm(xo))
+    status, it32, rr32 = f.gpu[32].pcg(dev(b), x, rtol=f.w.rtol, maxit=500)
+    x32 = host(x)
+    e32 = float(np.linalg.norm(x32 - xo) / np.linalg.norm(xo))
+    res = float(np.linalg.norm(b - f.A @ x32) / np.linalg.norm(b))
+    print(f"oracle {ito} iterations; FP64 {it[0]} iterations, fixed-count error {e64:.1e}; "
+          f"FP32-preconditioned {it32[0]} iterations, error vs oracle {e32:.1e}, true l2 residual {res:.1e}")
+    assert e64 <= 1e-10
+    assert status == 0 and rr32[0] <= f.w.rtol and it32[0] <= ito + 3
+    assert e32 <= 1e-6
 
 
 def test_fullsize_vcycle_symmetric(curl64):
     """Algorithm 4.1 at full size (FP64): r2 . B r1 = r1 . B r2 and r . B r > 0."""
-    w, A, H = curl64
+    f = curl64
+    n = f.A.shape[0]
     rng = np.random.default_rng(5)
-    r1, r2 = rng.uniform(-1, 1, A.shape[0]), rng.uniform(-1, 1, A.shape[0])
-    z1 = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
+    r1, r2 = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    z1 = torch.empty(n, dtype=torch.float64, device="cuda")
     z2 = torch.empty_like(z1)
-    H[64].vcycle(dev(r1), z1)
-    H[64].vcycle(dev(r2), z2)
+    f.gpu[64].vcycle(dev(r1), z1)
+    f.gpu[64].vcycle(dev(r2), z2)
     b1, b2 = host(z1), host(z2)
     s12, s21 = r2 @ b1, r1 @ b2
     scale = np.sqrt((r1 @ b1) * (r2 @ b2))
@@ -114,39 +162,48 @@ def test_fullsize_vcycle_symmetric(curl64):
 
 
 def test_fullsize_batched_pcg(div48):
-    """a8 at full size: 32 columns in one batched FP32-preconditioned solve; every column
-    converges with a small true residual, and sampled columns match single-column solves."""
-    w, A, H = div48
-    n = A.shape[0]
-    B = W.rhs(n, w.rhs_seed, w.nrhs)
-    X = torch.zeros(n * w.nrhs, dtype=torch.float64, device="cuda")
-    status, its, rrs = H[32].pcg(dev(B), X, rtol=w.rtol, maxit=500, nrhs=w.nrhs)
-    Xs = host(X).reshape(n, w.nrhs)
-    R = B - A @ Xs
-    res = np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0)
-    print(f"batched {w.nrhs} columns: iterations {min(its)}..{max(its)}, worst B-norm relres "
-          f"{max(rrs):.1e}, worst true residual {res.max():.1e}")
-    assert status == 0 and max(rrs) <= w.rtol
-    assert res.max() <= 1e-6
-    x1 = torch.zeros(n, dtype=torch.float64, device="cuda")
-    for j in (0, w.nrhs - 1):
-        st, it1, _ = H[32].pcg(dev(B[:, j]), x1, rtol=w.rtol, maxit=500)
-        x1h = host(x1)
-        d = np.linalg.norm(Xs[:, j] - x1h) / np.linalg.norm(x1h)
-        print(f"column {j}: batched {its[j]} iterations, single {it1[0]}, solution difference {d:.1e}")
-        assert st == 0 and abs(its[j] - it1[0]) <= 2
-        assert d <= 1e-6
+    """a8 at full size: the 32-column block in one batched call.  FP64: sampled columns
+    take the oracle's count (+-1) at rtol 1e-8 and match its iterate after that count to
+    1e-10.  FP32 (the benchmark's block solve): every column converges, sampled columns
+    within +3 iterations and 1e-6 of the oracle's solution."""
+    f = div48
+    n, k = f.A.shape[0], f.w.nrhs
+    B = W.rhs(n, f.w.rhs_seed, k)
+    X = torch.zeros(n * k, dtype=torch.float64, device="cuda")
+    ref = {j: f.oracle_pcg(np.ascontiguousarray(B[:, j]), j, rtol=f.w.rtol) for j in SAMPLED}
+    status, its, rrs = f.gpu[64].pcg(dev(B), X, rtol=f.w.rtol, maxit=500, nrhs=k)
+    assert status == 0 and max(rrs) <= f.w.rtol
+    for j in SAMPLED:
+        assert abs(its[j] - ref[j][1]) <= 1, (j, its[j], ref[j][1])
+    kfix = max(r[1] for r in ref.values())
+    f.gpu[64].pcg(dev(B), X, rtol=0.0, maxit=kfix, nrhs=k)
+    Xs = host(X).reshape(n, k)
+    e64 = {}
+    for j in SAMPLED:
+        xo = ref[j][0] if ref[j][1] == kfix else f.oracle_pcg(np.ascontiguousarray(B[:, j]), ("fixed", j),
+                                                                 fixed_iters=kfix)[0]
+        e64[j] = float(np.linalg.norm(Xs[:, j] - xo) / np.linalg.norm(xo))
+    status, its32, rrs32 = f.gpu[32].pcg(dev(B), X, rtol=f.w.rtol, maxit=500, nrhs=k)
+    Xs = host(X).reshape(n, k)
+    e32 = {j: float(np.linalg.norm(Xs[:, j] - ref[j][0]) / np.linalg.norm(ref[j][0])) for j in SAMPLED}
+    print(f"oracle iterations {[ref[j][1] for j in SAMPLED]}; FP64 block {min(its)}..{max(its)}, fixed-count "
+          f"errors {[f'{e:.1e}' for e in e64.values()]}; FP32 block {min(its32)}..{max(its32)}, errors vs oracle "
+          f"{[f'{e:.1e}' for e in e32.values()]}")
+    assert max(e64.values()) <= 1e-10
+    assert status == 0 and max(rrs32) <= f.w.rtol
+    assert all(its32[j] <= ref[j][1] + 3 for j in SAMPLED)
+    assert max(e32.values()) <= 1e-6
 
 
 def test_fullsize_batched_vcycle_symmetric(div48):
     """Batched Algorithm 4.1 at full size (FP64): R^T (B R) is symmetric with a positive
     diagonal."""
-    w, A, H = div48
-    n = A.shape[0]
+    f = div48
+    n = f.A.shape[0]
     k = 8
     R = np.random.default_rng(9).uniform(-1, 1, (n, k))
     Z = torch.empty(n * k, dtype=torch.float64, device="cuda")
-    H[64].vcycle(dev(R), Z, nrhs=k)
+    f.gpu[64].vcycle(dev(R), Z, nrhs=k)
     S = R.T @ host(Z).reshape(n, k)
     d = np.sqrt(np.abs(np.diag(S)))
     defect = np.max(np.abs(S - S.T) / np.outer(d, d))

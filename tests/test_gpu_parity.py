@@ -1,8 +1,9 @@
 """GPU parity of the HIP solve path against the FP64 oracle, through the C ABI.
 
-The GPU side runs on hierarchies made by the library's own builder; the oracle
-side on hierarchies made by the oracle; the two builders agree to rounding
-(tests/test_library_cpu.py), so the whole path is compared end to end.
+Same inputs: the GPU hierarchies are set up (amge_setup_hierarchy) from the oracle's
+own level matrices A_k, D_k, P_k, so the two sides differ only in how the solve phase
+evaluates them.  The library's own builder is checked against the oracle's matrices
+separately (tests/test_library_cpu.py) and end to end here (test_builder_end_to_end).
 
 Tolerances
 ----------
@@ -11,22 +12,23 @@ Tolerances
   auxiliary matrix D^T A D the bound uses |D|^T |A| |D|: the curl-curl (resp.
   div-div) part of A cancels exactly in D^T A D, so both sides carry rounding of the
   size of the cancelled terms (up to 1e3 larger with the coefficient jumps).
-* Smoother, V-cycle and PCG iterates, FP64: max(1e-10, u * kappa) relative, u = 2^-53
-  and kappa = max_i (|D|^T |A| |D| 1)_i / (|D^T A D| 1)_i over the levels: entries of the
-  auxiliary matrix are only fixed to u * kappa by the rounding of A itself, so two
-  independently assembled hierarchies cannot agree more closely than that.  kappa is
-  ~1e4 for unit coefficients (the 1e-10 bar applies) and ~5e7 for the 1e6 coefficient
-  contrast of the jump workloads.
-* PCG, FP64: after the same number of iterations, relative solution error
-  <= 1e-10; iteration counts at rtol 1e-8 within +-1.
-* PCG with the FP32 preconditioner: converges to rtol 1e-8; its distance to the
-  FP64 oracle solution is reported and bounded by 1e-6 relative.
+* Smoother, V-cycle and PCG iterates, FP64: relative error <= max(1e-10, 3 s), where s
+  is the distance between the oracle and a second FP64 evaluation of the same
+  arithmetic (tests/reformulation.py: explicit coarsest inverse, split auxiliary and
+  restricted residuals), measured per case on the CPU.  s is below 1e-11 on every case
+  but the 1e6-contrast H(div) jump workload (n = 32), where the definition itself only
+  fixes the FP64 iterate to ~3e-10 (PCG after 77 iterations) and ~2e-9 (one smoother
+  application).  PCG iterates are compared after the same number of iterations (rtol
+  <= 0 runs exactly maxit); iteration counts at rtol 1e-8 within +-1.
+* PCG with the FP32 preconditioner: converges to rtol 1e-8 within +3 iterations of the
+  oracle; its distance to the FP64 oracle solution is printed and bounded by 1e-6.
 """
 import numpy as np
 import pytest
 import scipy.linalg as sla
 
 from paper_2107_05613_amd import workloads as W
+from reformulation import fp64_bar, spreads
 
 pytestmark = pytest.mark.gpu
 
@@ -51,21 +53,28 @@ def relerr(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
+def oracle_levels(H):
+    """The oracle hierarchy's level matrices in the layout amge.Hierarchy takes."""
+    L = len(H.A)
+    return [(H.A[k], H.D[k], H.P[k] if k < L - 1 else None) for k in range(L)]
+
+
 class Case:
-    def __init__(self, kind, n, L, coef, precond_bits=64):
+    def __init__(self, kind, n, L, coef):
         from oracle.hierarchy import build_hierarchy
-        from oracle.solve import Multilevel
+        from oracle.solve import Multilevel, pcg
         amge = _amge()
-        print(f"\n[case] {kind} n={n} levels={L} coef={coef} bits={precond_bits}", flush=True)
+        print(f"\n[case] {kind} n={n} levels={L} coef={coef}", flush=True)
         w = W.Workload("t", kind, n, L, coef)
         self.alpha, self.beta = W.coefficients(w)
         self.kind, self.n, self.L = kind, n, L
-        self.prod = amge.build_problem(kind, n, L, self.alpha, self.beta)
         self.H = build_hierarchy(kind, n, L, self.alpha, self.beta, check_targets=False)
+        self.levels = oracle_levels(self.H)
         self.ml = Multilevel.from_hierarchy(self.H)
-        self.gpu = {bits: amge.Hierarchy(self.prod, precond_bits=bits) for bits in (64, 32)}
+        self.gpu = {bits: amge.Hierarchy(self.levels, precond_bits=bits) for bits in (64, 32)}
         self.n1 = self.H.A[0].shape[0]
         self.b = W.rhs(self.n1, 0)[:, 0]
+        self.xo, self.ito, _ = pcg(self.H.A[0], self.b, self.ml, rtol=1e-8)
         kap = 1.0
         for k in range(L - 1):
             A, D = self.H.A[k], self.H.D[k]
@@ -73,8 +82,19 @@ class Case:
             den = abs((D.T @ A @ D).tocsr()) @ np.ones(D.shape[1])
             kap = max(kap, float(np.max(num / den)))
         self.kappa = kap
-        self.tol64 = max(1e-10, 2.0 ** -53 * kap)
-        print(f"[case] cancellation factor {kap:.1e}, FP64 parity tolerance {self.tol64:.1e}", flush=True)
+        self.spread = spreads(self.H, self.b, self.ito)
+        self.bar = {k: fp64_bar(v) for k, v in self.spread.items()}
+        print(f"[case] cancellation factor {kap:.1e}; oracle PCG {self.ito} iterations; reformulation spread "
+              + ", ".join(f"{k} {v:.1e}" for k, v in self.spread.items()), flush=True)
+
+    _prod = None
+
+    @property
+    def prod(self):
+        """The same workload from the library's own builder."""
+        if self._prod is None:
+            self._prod = _amge().build_problem(self.kind, self.n, self.L, self.alpha, self.beta)
+        return self._prod
 
 
 _CASES = {}
@@ -134,7 +154,7 @@ def test_hybrid_smoother(spec):
             c.gpu[64].level_apply(k, op, dev(b), out, x2=dev(x0), precision=32)
             e32 = relerr(host(out), ref)
             print(f"level {k} op {op}: smoother error fp64 {e64:.1e} fp32 {e32:.1e}")
-            assert e64 <= c.tol64, (k, op)
+            assert e64 <= c.bar["smooth"], (k, op)
             assert e32 <= 1e-4, (k, op)
 
 
@@ -149,7 +169,6 @@ def test_coarse_cholesky(spec):
     out = torch.empty_like(dev(b))
     c.gpu[64].level_apply(c.L - 1, amge.OP_COARSE, dev(b), out)
     xs = host(out)
-    # the two coarsest matrices (Galerkin products of two builders) agree to ~1e-14
     assert relerr(xs, ref) <= 1e-10
     assert np.linalg.norm(Ac @ xs - b) <= 1e-12 * np.linalg.norm(Ac, 2) * np.linalg.norm(xs)
 
@@ -162,8 +181,8 @@ def test_vcycle(spec):
     z = torch.empty_like(dev(c.b))
     c.gpu[64].vcycle(dev(c.b), z)
     e64 = relerr(host(z), ref)
-    print(f"FP64 V-cycle relative error vs FP64 oracle: {e64:.2e}")
-    assert e64 <= c.tol64
+    print(f"FP64 V-cycle relative error vs FP64 oracle: {e64:.2e} (bar {c.bar['vcycle']:.1e})")
+    assert e64 <= c.bar["vcycle"]
     c.gpu[32].vcycle(dev(c.b), z)
     z32 = host(z)
     e32 = relerr(z32, ref)
@@ -191,7 +210,7 @@ def test_folded_tail(spec):
     A = c.H.A[0]
     z = torch.empty_like(dev(c.b))
     for bits in (64, 32):
-        H0 = amge.Hierarchy(c.prod, precond_bits=bits, tail_rows=0)
+        H0 = amge.Hierarchy(c.levels, precond_bits=bits, tail_rows=0)
         H0.vcycle(dev(c.b), z)
         z0 = host(z)
         c.gpu[bits].vcycle(dev(c.b), z)
@@ -201,8 +220,8 @@ def test_folded_tail(spec):
         e0, ef = relerr(z0, ref), relerr(zf, z0)
         print(f"{spec} FP{bits}: unfolded vs oracle {e0:.2e} (energy {en:.2e}); folded vs unfolded {ef:.2e}")
         if bits == 64:
-            assert e0 <= c.tol64
-            assert ef <= c.tol64
+            assert e0 <= c.bar["vcycle"]
+            assert ef <= c.bar["vcycle"]
         else:
             assert en <= (1e-3 if c.kappa < 1e6 else 5e-2)
         x0, xf = torch.zeros_like(dev(c.b)), torch.zeros_like(dev(c.b))
@@ -211,16 +230,15 @@ def test_folded_tail(spec):
         assert abs(it0[0] - itf[0]) <= 1, (it0, itf)
         H0.close()
     with pytest.raises(amge.AmgeError):
-        amge.Hierarchy(c.prod, tail_rows=-1)
+        amge.Hierarchy(c.levels, tail_rows=-1)
 
 
 @pytest.mark.parametrize("spec", [("curl", 8, 2, "unit"), ("div", 8, 3, "blocks"), ("div", 32, 4, "blocks")])
 def test_pcg_fp64_parity(spec):
     """a7: inexact PCG in FP64; same iterates as the oracle after the same count, and
     the same iteration count (+-1) at rtol 1e-8."""
-    from oracle.solve import pcg
     c = case(*spec)
-    xo, ito, hist = pcg(c.H.A[0], c.b, c.ml, rtol=1e-8)
+    xo, ito = c.xo, c.ito
     x = torch.zeros_like(dev(c.b))
     status, it, rr = c.gpu[64].pcg(dev(c.b), x, rtol=1e-8, maxit=500)
     assert status == 0 and abs(it[0] - ito) <= 1, (it, ito)
@@ -228,16 +246,35 @@ def test_pcg_fp64_parity(spec):
     status, it2, _ = c.gpu[64].pcg(dev(c.b), x, rtol=0.0, maxit=ito)
     assert it2[0] == ito
     err = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
-    print(f"{spec}: oracle iters {ito}, gpu iters {it[0]}, fixed-count solution error {err:.2e}")
-    assert err <= c.tol64
+    print(f"{spec}: oracle iters {ito}, gpu iters {it[0]}, fixed-count solution error {err:.2e} "
+          f"(bar {c.bar['pcg']:.1e})")
+    assert err <= c.bar["pcg"]
+
+
+@pytest.mark.parametrize("spec", SMALL + [("div", 32, 4, "blocks")])
+def test_builder_end_to_end(spec):
+    """The library's own builder (amge_kuhn_build) feeding the solve phase: fixed-count
+    FP64 PCG on its hierarchy against the oracle on the oracle's hierarchy.  The two
+    builders' matrices agree to rounding, a perturbation of the size the reformulation
+    spread already measures."""
+    c = case(*spec)
+    amge = _amge()
+    H = amge.Hierarchy(c.prod, precond_bits=64)
+    x = torch.zeros_like(dev(c.b))
+    status, it, _ = H.pcg(dev(c.b), x, rtol=1e-8, maxit=500)
+    assert status == 0 and abs(it[0] - c.ito) <= 1, (it, c.ito)
+    H.pcg(dev(c.b), x, rtol=0.0, maxit=c.ito)
+    err = np.linalg.norm(host(x) - c.xo) / np.linalg.norm(c.xo)
+    print(f"{spec}: builder hierarchy, fixed-count solution error vs oracle {err:.2e} (bar {c.bar['pcg']:.1e})")
+    assert err <= c.bar["pcg"]
+    H.close()
 
 
 @pytest.mark.parametrize("spec", [("curl", 8, 3, "blocks"), ("div", 32, 4, "blocks")])
 def test_pcg_fp32_preconditioner(spec):
     """FP32 V-cycle inside FP64 PCG reaches rtol 1e-8; error vs the FP64 oracle stated."""
-    from oracle.solve import pcg
     c = case(*spec)
-    xo, ito, _ = pcg(c.H.A[0], c.b, c.ml, rtol=1e-8)
+    xo, ito = c.xo, c.ito
     x = torch.zeros_like(dev(c.b))
     status, it, rr = c.gpu[32].pcg(dev(c.b), x, rtol=1e-8, maxit=500)
     xs = host(x)
@@ -277,10 +314,9 @@ def test_error_paths():
         c.gpu[64].vcycle(dev(np.tile(c.b, 2)), torch.zeros(2 * c.n1, dtype=torch.float64, device="cuda"), nrhs=2)
     assert e.value.code == -1
     # an indefinite coarsest matrix is rejected at set-up
-    A, D, P = c.prod[-1]
-    Aneg = amge.HostCsr(A.shape[0], A.shape[1], A.rowptr, A.col, -A.val)
+    A, D, P = c.levels[-1]
     with pytest.raises(amge.AmgeError) as e:
-        amge.Hierarchy(c.prod[:-1] + [(Aneg, D, None)])
+        amge.Hierarchy(c.levels[:-1] + [(-A, D, None)])
     assert e.value.code == -3
 
 
@@ -301,7 +337,7 @@ def test_cancellation_factor_and_auto_precision(spec):
     hierarchy, and precond_bits = 0 picks FP32 exactly when 2^-24 kappa <= 0.1."""
     amge = _amge()
     c = case(*spec)
-    H = amge.Hierarchy(c.prod, precond_bits=0)
+    H = amge.Hierarchy(c.levels, precond_bits=0)
     kap, bits = H.precision_info()
     print(f"{spec}: kappa library {kap:.6e}, oracle {c.kappa:.6e}, auto precision FP{bits}")
     assert abs(kap - c.kappa) <= 1e-9 * c.kappa
@@ -349,27 +385,28 @@ def test_other_sweep_counts(nus, tail):
     nup, nua = nus
     c = case("curl", 8, 3, "blocks")
     ml = Multilevel.from_hierarchy(c.H, nu_primary=nup, nu_aux=nua)
-    H = amge.Hierarchy(c.prod, precond_bits=64, nu_primary=nup, nu_aux=nua, max_rhs=2, tail_rows=tail)
+    H = amge.Hierarchy(c.levels, precond_bits=64, nu_primary=nup, nu_aux=nua, max_rhs=2, tail_rows=tail)
+    bar = fp64_bar(max(spreads(c.H, c.b, 8, nu_primary=nup, nu_aux=nua).values()))
     ref = ml.vcycle(c.b)
     z = torch.empty_like(dev(c.b))
     H.vcycle(dev(c.b), z)
-    assert relerr(host(z), ref) <= c.tol64
+    assert relerr(host(z), ref) <= bar
     B = np.stack([c.b, W.rhs(c.n1, 5)[:, 0]], 1)
     Z = torch.empty(2 * c.n1, dtype=torch.float64, device="cuda")
     H.vcycle(dev(B), Z, nrhs=2)
     Zs = host(Z).reshape(c.n1, 2)
-    assert relerr(Zs[:, 0], ref) <= c.tol64
-    assert relerr(Zs[:, 1], ml.vcycle(B[:, 1])) <= c.tol64
+    assert relerr(Zs[:, 0], ref) <= bar
+    assert relerr(Zs[:, 1], ml.vcycle(B[:, 1])) <= bar
     k = 8
     xo, _, _ = pcg(c.H.A[0], c.b, ml, fixed_iters=k)
     x = torch.zeros_like(dev(c.b))
     status, it, _ = H.pcg(dev(c.b), x, rtol=0.0, maxit=k)
     assert it[0] == k
-    assert np.linalg.norm(host(x) - xo) <= c.tol64 * np.linalg.norm(xo)
+    assert np.linalg.norm(host(x) - xo) <= bar * np.linalg.norm(xo)
     X = torch.zeros(2 * c.n1, dtype=torch.float64, device="cuda")
     status, its, _ = H.pcg(dev(B), X, rtol=0.0, maxit=k, nrhs=2)
     assert its == [k, k]
-    assert np.linalg.norm(host(X).reshape(c.n1, 2)[:, 0] - xo) <= c.tol64 * np.linalg.norm(xo)
+    assert np.linalg.norm(host(X).reshape(c.n1, 2)[:, 0] - xo) <= bar * np.linalg.norm(xo)
     H.close()
 
 
@@ -378,7 +415,7 @@ def test_one_level_hierarchy():
     one step, single-column and batched."""
     amge = _amge()
     c = case("curl", 8, 2, "unit")
-    A, D, P = c.prod[0]
+    A, D, P = c.levels[0]
     H = amge.Hierarchy([(A, D, None)], precond_bits=32, max_rhs=3)
     import scipy.linalg as sl
     xd = sl.solve(c.H.A[0].toarray(), c.b, assume_a="pos")

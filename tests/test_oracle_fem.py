@@ -10,7 +10,7 @@ import itertools
 import numpy as np
 import pytest
 
-from oracle.fem import FineMesh, assemble, fine_problem, TET_EDGES, TET_FACES
+from oracle.fem import FineMesh, assemble, fine_problem, TET_EDGES, TET_FACES, TRI_EDGES
 from paper_2107_05613_amd.workloads import entity_counts
 
 
@@ -149,6 +149,33 @@ def test_element_masses_by_quadrature():
         rt = np.stack(rt, 1)
         Q = np.einsum("qad,qbd->ab", rt, rt) * vol / 4
         assert np.allclose(Q, Mrt[t], rtol=1e-12, atol=1e-14)
+
+
+def test_face_trace_mass_by_quadrature_and_constant_fields():
+    """The tangential-trace mass of a face (the mass the ND extension minimises on
+    coarse faces, section 3.3.3) against two independent facts.
+    (a) An edge-midpoint quadrature (exact for degree 2) of the 2-D Whitney edge
+        functions l_i grad_F l_j - l_j grad_F l_i, the surface gradients taken from the
+        cross-product formula grad_F l_i = n x (x_{i+2} - x_{i+1}) / (2 |F|).
+    (b) Every constant field c: with u_e = c . (x_b - x_a) on the face's edges,
+        u^T M u = |F| |c - (c . n) n|^2, the L2 norm of its tangential part."""
+    m = FineMesh(2)
+    M = m.nd_face_trace_mass()
+    rng = np.random.default_rng(0)
+    mids = np.array([[0.5, 0.5, 0.0], [0.5, 0.0, 0.5], [0.0, 0.5, 0.5]])
+    for f in range(len(m.faces)):
+        xs = m.X[m.faces[f]].astype(float) * m.h
+        nv = np.cross(xs[1] - xs[0], xs[2] - xs[0])
+        area = np.linalg.norm(nv) / 2
+        nu = nv / np.linalg.norm(nv)
+        g = np.stack([np.cross(nu, xs[(i + 2) % 3] - xs[(i + 1) % 3]) / (2 * area) for i in range(3)])
+        w = np.stack([mids[:, i, None] * g[j] - mids[:, j, None] * g[i] for i, j in TRI_EDGES], 1)  # (q, e, 3)
+        Q = np.einsum("qad,qbd->ab", w, w) * area / 3
+        assert np.allclose(Q, M[f], rtol=1e-12, atol=1e-15), f
+        for c in rng.uniform(-1, 1, (3, 3)):
+            u = np.array([c @ (xs[j] - xs[i]) for i, j in TRI_EDGES])
+            ct = c - (c @ nu) * nu
+            assert abs(u @ M[f] @ u - area * (ct @ ct)) <= 1e-12 * area * (c @ c), f
 
 
 def test_nd_basis_unit_circulation():

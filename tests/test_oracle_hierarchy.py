@@ -230,6 +230,30 @@ def test_targets_do_not_survive():
     assert H.A[1].shape[0] == 3 * 2 * 9
 
 
+def test_planted_surviving_targets_are_caught():
+    """The target check (sections 3.3.1-3.3.3) fires on targets that do survive: the
+    interpolant of the linear field (x, 0, 0) varies along the fine edges of an x-directed
+    coarse edge, so it survives the PV removal there; the gradient of the hat function of
+    a coarse face's centre vertex vanishes on every coarse edge but is a D-free face bubble
+    (grad phi is curl-free, zero on the face boundary), so it survives the bubble
+    projection.  Order-0 targets pass (test_targets_do_not_survive)."""
+    from oracle.fem import FineMesh
+    mesh = FineMesh(4)
+    lev = hm.fine_level(mesh)
+    cg = hm._Coarsening(lev, mesh.h)
+    X = lev.X.astype(float) * mesh.h
+    xa, xb = X[mesh.edges[:, 0]], X[mesh.edges[:, 1]]
+    lin = ((xb - xa)[:, 0] * (xa + xb)[:, 0] / 2)[:, None]      # integral of x dx along each edge
+    with pytest.raises(NotImplementedError, match="PV removal"):
+        hm._check_targets(cg, 1, lin)
+    centre = 1 + 5 * 1                                          # vertex (1, 1, 0) of the 4^3 mesh
+    bubble = np.asarray(mesh.grad()[:, centre].todense())
+    with pytest.raises(NotImplementedError, match="bubble projection"):
+        hm._check_targets(cg, 1, bubble)
+    const = hm.order0_targets(lev)[1]
+    hm._check_targets(cg, 1, const)
+
+
 def test_coefficients_do_not_change_prolongators():
     """With unweighted L2 masses in the extensions the prolongators do not depend
     on alpha, beta (only the Galerkin operators do)."""
