@@ -153,6 +153,20 @@ amge_status amge_footprint(const amge_hierarchy* h, int32_t nrhs, size_t* hier_b
  * Asynchronous on `stream`. */
 amge_status amge_vcycle(amge_ctx* c, const double* r, double* z, int32_t nrhs, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): z = B r on one column, exactly the
+ * computation of amge_vcycle with nrhs = 1, with the level work vectors taken from a
+ * static device scratch array of AMGE_STATIC_SCRATCH_BYTES per GPU (held from the
+ * first call on a device until the process ends) instead of a context.  The call
+ * allocates nothing.  r, z: device FP64, n_1 entries, caller-owned.  Asynchronous on
+ * `stream`.  All calls on one GPU share its scratch, whose contents the next call
+ * overwrites: calls that overlap in time on one GPU (other streams or threads) race.
+ * Errors: AMGE_ERR_ARG if the hierarchy's single-column work vectors (sum over the
+ * levels of 5 n_k + 4 m_k values of the V-cycle precision, each vector rounded up to
+ * 256 bytes) exceed the scratch; AMGE_ERR_HIP. */
+#define AMGE_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+amge_status amge_vcycle_static(const amge_hierarchy* h, const double* r, double* z, void* stream);
+
 /* Inexact PCG (section 5.1) for A_1 x = b with x0 = 0 and one V-cycle per iteration.
  *   b, x     device FP64, n_1 x nrhs row-major; x is overwritten
  *   nrhs     1 <= nrhs <= the context's nrhs; every column follows its own recurrences and

@@ -89,6 +89,7 @@ def _load():
         "amge_ctx_destroy": (None, [vp]),
         "amge_footprint": (i32, [vp, i32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         "amge_vcycle": (i32, [vp, vp, vp, i32, vp]),
+        "amge_vcycle_static": (i32, [vp, vp, vp, vp]),
         "amge_pcg_solve": (i32, [vp, vp, vp, i32, f64, i32, i32, C.POINTER(i32), C.POINTER(f64), vp]),
         "amge_level_apply": (i32, [vp, i32, i32, i32, vp, vp, vp, vp]),
         "amge_hierarchy_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
@@ -138,7 +139,7 @@ def _close_all():
 
 # Names declared by include/amge.h (checked by the test suite against the header).
 EXPORTS = ("amge_default_opts", "amge_setup_hierarchy", "amge_destroy", "amge_ctx_create", "amge_ctx_destroy",
-           "amge_footprint", "amge_vcycle",
+           "amge_footprint", "amge_vcycle", "amge_vcycle_static",
            "amge_pcg_solve", "amge_level_apply", "amge_hierarchy_info", "amge_precision_info", "amge_last_error",
            "amge_timing_enable", "amge_timing_read", "amge_vcycle_bytes",
            "amge_kuhn_build", "amge_problem_nlevels", "amge_problem_levels", "amge_problem_free",
@@ -350,6 +351,12 @@ class Hierarchy:
 
     def vcycle(self, r, z, nrhs=1, stream=None):
         self.ctx.vcycle(r, z, nrhs=nrhs, stream=stream)
+
+    def vcycle_static(self, r, z, stream=None):
+        """z = B r on one column with the library's static scratch (amge_vcycle_static):
+        no context, no device allocation."""
+        n = self.rows[0]
+        _check(_lib.amge_vcycle_static(self._h, _vec(r, n), _vec(z, n), _stream(stream)))
 
     def pcg(self, b, x, rtol=1e-8, maxit=500, stop_norm=0, nrhs=1, stream=None):
         return self.ctx.pcg(b, x, rtol=rtol, maxit=maxit, stop_norm=stop_norm, nrhs=nrhs, stream=stream)

@@ -1867,6 +1867,51 @@ extern "C" amge_status amge_vcycle(amge_ctx* c, const double* r, double* z, int3
     });
 }
 
+// ------------------------------------------------------------------ no-allocation V-cycle
+// amge_vcycle_static: the single-column V-cycle with its level work vectors carved out
+// of `scratch`, a file-scope device array (one per GPU, held until the process ends),
+// instead of a context's buffers.  Host code never passes `scratch` itself to a kernel
+// (in host code the name is a stand-in, not a device address): its device address is
+// looked up once per device with hipGetSymbolAddress and only that address is used.
+constexpr size_t STATIC_SCRATCH_BYTES = AMGE_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch_ptr;   // device -> address of its scratch
+
+// Address of the current device's scratch, looked up on the first call on that device.
+char* scratch_address() {
+    int d = 0;
+    HIPCHECK(hipGetDevice(&d));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(d);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        fail(AMGE_ERR_HIP, std::string("hipGetSymbolAddress of the static scratch failed: ") + hipGetErrorString(e));
+    g_scratch_ptr[d] = (char*)ptr;
+    return (char*)ptr;
+}
+}  // namespace
+
+extern "C" amge_status amge_vcycle_static(const amge_hierarchy* h, const double* r, double* z, void* stream) {
+    return guard([&]() -> amge_status {
+        if (!h || !r || !z) fail(AMGE_ERR_ARG, "null argument");
+        if (h->parent) fail(AMGE_ERR_ARG, "not a hierarchy");
+        amge_hierarchy S;   // execution state whose work vectors live in the scratch
+        S.arena = scratch_address();
+        S.arena_size = STATIC_SCRATCH_BYTES;
+        init_state(&S, h, 1);   // fails before any launch if the work does not fit
+        hipStream_t s = (hipStream_t)stream;
+        if (S.lv.size() == 1) coarse_solve<double>(&S, r, z, s, S.zero_flag);
+        else precondition(&S, r, z, s);
+        HIPCHECK(hipGetLastError());
+        return AMGE_OK;
+    });
+}
+
 extern "C" amge_status amge_pcg_solve(amge_ctx* c, const double* b, double* x, int32_t nrhs, double rtol,
                                       int32_t maxit, int32_t stop_norm, int32_t* iters, double* relres,
                                       void* stream) {
