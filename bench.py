@@ -289,6 +289,78 @@ def run_small_configs(names, steps):
     return out, sols
 
 
+def run_options(steps):
+    """Coefficient-aware extensions and essential boundary conditions (the library's
+    builder options) on the 32^3 H(div) jump workload and on two of the serving mix's
+    48^3 jump hierarchies: FP64 PCG iterations to rtol 1e-8 and time per solve."""
+    import torch
+    from paper_2107_05613_amd import amge
+    from paper_2107_05613_amd import workloads as W
+    cases = [W.WORKLOADS["div_n32_l4_jumps"],
+             W.Workload("curl_n48_c0", "curl", 48, W.default_levels(48), "blocks", coef_seed=0),
+             W.Workload("div_n48_c0", "div", 48, W.default_levels(48), "blocks", coef_seed=0)]
+    out = {}
+    for w in cases:
+        a, b = W.coefficients(w)
+        r = {}
+        for ext in ("l2", "coefficient"):
+            for bc in ("natural", "essential"):
+                prod = amge.build_problem(w.kind, w.n, w.levels, a, b, extension=ext, bc=bc)
+                H = amge.Hierarchy(prod, precond_bits=64)
+                rhs = torch.from_numpy(W.rhs(H.rows[0], w.rhs_seed)[:, 0]).cuda()
+                x = torch.zeros_like(rhs)
+                st, it, rr = H.pcg(rhs, x, rtol=1e-8, maxit=2000)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(max(1, steps // 5)):
+                    H.pcg(rhs, x, rtol=1e-8, maxit=2000)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / max(1, steps // 5)
+                r[f"{ext}/{bc}"] = {"iters": it[0], "status": st, "dofs": H.rows[0], "ms_per_solve": 1e3 * dt}
+                H.close()
+        out[w.name] = r
+        print(f"[bench] options {w.name}: " + ", ".join(f"{k} {v['iters']}" for k, v in r.items()),
+              file=sys.stderr, flush=True)
+    return out
+
+
+def run_gs(w, prod, rhs, steps):
+    """The same solve with the symmetric Gauss-Seidel point smoother (colour order) in
+    place of l1-Jacobi: iterations, time per solve and V-cycle time, FP32 and FP64
+    V-cycles."""
+    import torch
+    from paper_2107_05613_amd import amge
+    out = {}
+    for bits in (32, 64):
+        t0 = time.perf_counter()
+        H = amge.Hierarchy(prod, precond_bits=bits, smoother="symgs")
+        t_setup = time.perf_counter() - t0
+        x = torch.zeros_like(rhs)
+        for _ in range(2):
+            st, it, rr = H.pcg(rhs, x, rtol=w.rtol, maxit=1000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st, it, rr = H.pcg(rhs, x, rtol=w.rtol, maxit=1000)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        z = torch.empty_like(rhs)
+        H.vcycle(rhs, z)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            H.vcycle(rhs, z)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"fp{bits}"] = {"iters": it[0], "status": st, "ms_per_solve": 1e3 * dt, "solves_per_s": 1.0 / dt,
+                            "vcycle_ms": e0.elapsed_time(e1) / 10, "setup_s": t_setup}
+        H.close()
+    print(f"[bench] symmetric Gauss-Seidel smoother: FP32 {out['fp32']['iters']} iterations "
+          f"{out['fp32']['ms_per_solve']:.2f} ms, FP64 {out['fp64']['iters']} iterations "
+          f"{out['fp64']['ms_per_solve']:.2f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def cold_sweep(H, rhs, x, reps=10):
     """Average time of the fine-level FP32 l1-Jacobi sweep launched alone (amge_level_apply
     SWEEP, HIP events on its stream), warm (launched back to back, its matrix partly
@@ -317,15 +389,29 @@ def cold_sweep(H, rhs, x, reps=10):
     return res
 
 
+def _by_class(mix, lat, order=None):
+    """p50/p99 latency per size class n."""
+    from paper_2107_05613_amd import serve
+    out = {}
+    for n in sorted({r["n"] for r in mix.requests}):
+        sub = {j: v for j, v in lat.items() if mix.requests[j]["n"] == n}
+        if sub:
+            st = serve.latency_stats(sub)
+            out[str(n)] = {"requests": len(sub), "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"]}
+    return out
+
+
 def run_serving(args):
     """Serving mix: seeded requests over 20 resident hierarchies (H(curl)/H(div),
-    n in {16,24,32,48,64}, two coefficient-jump fields each), 8 columns per hierarchy.
-    All requests at once (burst), a closed loop with two outstanding requests per
-    hierarchy (capacity), then Poisson arrivals at 0.8 x that capacity (open loop:
-    p50/p99 latency)."""
+    n in {16,24,32,48,64}, two coefficient-jump fields each), 8 columns per hierarchy,
+    V-cycle precision chosen per hierarchy at set-up (trial solves).  All requests at once
+    (burst), a closed loop with two outstanding requests per hierarchy (capacity), Poisson
+    arrivals at 0.8 x and 0.4 x that capacity (open loop: p50/p99 overall and per size
+    class); and the burst again with every hierarchy in FP64 (the FP32 ones rebuilt)."""
     import numpy as np
     import torch
-    from paper_2107_05613_amd import serve
+    from paper_2107_05613_amd import amge, serve
+    from paper_2107_05613_amd import workloads as W
     t0 = time.perf_counter()
     mix = serve.build_mix(num=args.serving_requests, seed=0, slots=8, precond_bits=0)
     print(f"[bench] serving: {len(mix.keys)} hierarchies built in {time.perf_counter() - t0:.1f}s "
@@ -333,7 +419,7 @@ def run_serving(args):
     srv, ids = serve.make_server(mix, chunk=8)
     resident = srv.stats()["resident_bytes"]
     prec = [h.precision_info() for h in mix.hierarchies]
-    n32 = sum(1 for k, b in prec if b == 32)
+    fp32_keys = [k for k, (_, b) in zip(mix.keys, prec) if b == 32]
     # warm-up: one request per hierarchy
     first = {}
     for j, h in enumerate(mix.hid_of):
@@ -342,44 +428,77 @@ def run_serving(args):
     # burst: every request at t = 0 (columns as full as the stream allows)
     done, lat, makespan = serve.run(srv, ids, mix)
     burst = len(done) / makespan
+    burst_by = _by_class(mix, lat)
     bad = sum(1 for v in done.values() if v[0] != 0)
-    print(f"[bench] serving burst: {burst:.1f} solves/s ({makespan:.2f}s for {len(done)})", file=sys.stderr,
-          flush=True)
+    print(f"[bench] serving burst: {burst:.1f} solves/s ({makespan:.2f}s for {len(done)}; "
+          f"{len(fp32_keys)} of {len(prec)} hierarchies FP32)", file=sys.stderr, flush=True)
     # closed loop: two requests per resident hierarchy outstanding on average
     conc = 2 * len(mix.keys)
     donec, latc, makespanc = serve.run_closed(srv, ids, mix, conc)
     capacity = len(donec) / makespanc
     bad += sum(1 for v in donec.values() if v[0] != 0)
     print(f"[bench] serving closed loop ({conc} outstanding): {capacity:.1f} solves/s", file=sys.stderr, flush=True)
-    rate = 0.8 * capacity
-    arrivals = np.array([r["t_arrive"] for r in mix.requests]) / rate
-    done2, lat2, makespan2 = serve.run(srv, ids, mix, arrivals=arrivals)
-    st = serve.latency_stats(lat2)
-    bad += sum(1 for v in done2.values() if v[0] != 0)
-    iters = [v[1] for v in done2.values()]
-    print(f"[bench] serving open loop at {rate:.1f}/s: p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms",
-          file=sys.stderr, flush=True)
+    open_loop = {}
+    iters = []
+    for frac, num in ((0.8, len(mix.requests)), (0.4, len(mix.requests) // 2)):
+        rate = frac * capacity
+        order = list(range(num))
+        arrivals = np.array([mix.requests[j]["t_arrive"] for j in order]) / rate
+        d2, l2, mk2 = serve.run(srv, ids, mix, arrivals=arrivals, order=order)
+        st = serve.latency_stats(l2)
+        bad += sum(1 for v in d2.values() if v[0] != 0)
+        iters += [v[1] for v in d2.values()]
+        open_loop[f"{frac}x_capacity"] = {"arrival_rate_per_s": rate, "requests": num,
+                                           "solves_per_s": len(d2) / mk2, **st, "by_size": _by_class(mix, l2)}
+        print(f"[bench] serving open loop at {rate:.1f}/s: p50 {st['p50_ms']:.1f} ms p99 {st['p99_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
+    srv.close()
+    # the burst with every hierarchy in FP64: rebuild the FP32 ones
+    fp64 = list(mix.hierarchies)
+    rebuilt = []
+    for i, (key, (_, b)) in enumerate(zip(mix.keys, prec)):
+        if b == 32:
+            kind, n, cs = key
+            w = W.Workload(f"{kind}_n{n}_c{cs}", kind, n, W.default_levels(n), "blocks", coef_seed=cs)
+            a, be = W.coefficients(w)
+            fp64[i] = amge.Hierarchy(amge.build_problem(kind, n, w.levels, a, be), precond_bits=64, max_rhs=8)
+            rebuilt.append(fp64[i])
+    mix64 = serve.Mix(mix.requests, mix.keys, fp64, mix.hid_of, mix.rhs, mix.x)
+    srv64, ids64 = serve.make_server(mix64, chunk=8)
+    serve.run(srv64, ids64, mix64, order=list(first.values()))
+    d64, l64, mk64 = serve.run(srv64, ids64, mix64)
+    burst64 = len(d64) / mk64
+    bad += sum(1 for v in d64.values() if v[0] != 0)
+    srv64.close()
+    for H in rebuilt:
+        H.close()
+    print(f"[bench] serving burst, all FP64: {burst64:.1f} solves/s", file=sys.stderr, flush=True)
     mix_desc = {"requests": mix.requests, "keys": len(mix.keys),
                 "setup_s": {"build": mix.build_s, "device_setup": mix.setup_s}}
-    srv.close()
-    del mix
+    del mix, mix64
     torch.cuda.synchronize()
     grouped = run_grouped_ab()
     out = {
         "workload": (f"{len(mix_desc['requests'])} seeded requests, H(curl)/H(div) on n^3x6 Kuhn tets with n in "
                      f"{{16,24,32,48,64}} drawn uniformly, per-4^3-block coefficient jumps 10^U(-3,3) from a pool "
                      f"of 2 seeds per (type, n): {mix_desc['keys']} resident hierarchies, 8 PCG columns each; "
-                     f"V-cycle precision per hierarchy from its cancellation factor, per-column FP64 PCG "
+                     f"V-cycle precision per hierarchy from trial solves at set-up, per-column FP64 PCG "
                      f"to rel-res 1e-8"),
-        "precision": {"fp32_hierarchies": n32, "fp64_hierarchies": len(prec) - n32,
+        "precision": {"fp32_hierarchies": len(fp32_keys), "fp64_hierarchies": len(prec) - len(fp32_keys),
+                      "fp32": [f"{k[0]} n={k[1]} seed {k[2]}" for k in fp32_keys],
                       "kappa_range": [min(k for k, b in prec), max(k for k, b in prec)]},
         "resident_bytes": resident,
-        "burst": {"solves_per_s": burst, "makespan_s": makespan, **serve.latency_stats(lat)},
+        "burst": {"solves_per_s": burst, "makespan_s": makespan, **serve.latency_stats(lat), "by_size": burst_by},
+        "burst_all_fp64": {"solves_per_s": burst64, "makespan_s": mk64, **serve.latency_stats(l64)},
         "closed_loop": {"outstanding": conc, "solves_per_s": capacity, **serve.latency_stats(latc)},
-        "open_loop": {"arrival_rate_per_s": rate, "solves_per_s": len(done2) / makespan2, **st},
+        "open_loop": open_loop,
         "iters": [int(min(iters)), int(max(iters))],
         "failed_requests": bad,
         "setup_s": mix_desc["setup_s"],
+        "persistent_launches": ("not built: a grid-wide barrier of a cooperative kernel measured 27 us at 256 "
+                                "workgroups (110 us at 1024), against 1.7-2.1 us for a dependent launch in a HIP "
+                                "graph, so a persistent kernel stepping through the V-cycle's operators would be "
+                                "slower than the grouped and solo launches"),
         "grouped_launches": grouped,
     }
     return out
@@ -452,6 +571,9 @@ def main():
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--oracle-dir", default=None)
+    ap.add_argument("--no-gs", action="store_true", help="skip the Gauss-Seidel smoother comparison")
+    ap.add_argument("--no-options", action="store_true",
+                    help="skip the extension / boundary-condition option comparison")
     ap.add_argument("--small-configs", default="curl_n8_l2,div_n32_l4_jumps",
                     help="comma-separated small configurations timed beside the main one ('' to skip)")
     ap.add_argument("--grouped-ab-only", choices=[c[0] for c in GROUPED_CONFIGS],
@@ -559,10 +681,12 @@ def main():
     sol = {(w.name, 32): x32.cpu().numpy(), (w.name, 64): x64.cpu().numpy()}
     lv0 = prod[0][0]
     del H64
+    gs = run_gs(w, prod, rhs, args.steps) if not args.no_gs else None
     stream_ref = stream_reference()
     small_names = [c for c in args.small_configs.split(",") if c]
     small, small_sol = run_small_configs(small_names, args.steps) if small_names else ({}, {})
     sol.update(small_sol)
+    options = run_options(args.steps) if not args.no_options else None
     batched = run_batched(args, amge, W) if args.batched_workload else None
     serving = run_serving(args) if args.serving_requests > 0 else None
 
@@ -630,7 +754,9 @@ def main():
                           "the 256 MB last-level cache (its matrix streams from HBM); warm: launched back to back"),
             "stream_reference_GBps": stream_ref,
         },
+        "smoother_sym_gs": gs,
         "configs": small,
+        "extension_and_boundary_options": options,
         "setup_s": {"build": t_build, "device_setup": t_setup},
         "batched": batched,
         "serving": serving,

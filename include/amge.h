@@ -78,12 +78,13 @@ typedef struct {
 } amge_level;
 
 typedef struct {
-    int32_t nu_primary;     /* l1-Jacobi sweeps on A_k per smoothing step (paper: 2)        */
-    int32_t nu_aux;         /* l1-Jacobi sweeps on D^T A D per smoothing step (paper: 2)    */
+    int32_t nu_primary;     /* point-smoother sweeps on A_k per smoothing step (paper: 2)   */
+    int32_t nu_aux;         /* point-smoother sweeps on D^T A D per smoothing step (paper: 2) */
     int32_t precond_bits;   /* 64: V-cycle in FP64; 32: FP32 values/accumulation in the
                                V-cycle with the coarsest Cholesky solve kept in FP64;
-                               0: chosen at set-up, 32 unless 2^-24 * kappa > 0.1, kappa
-                               being the cancellation factor of amge_precision_info         */
+                               0: chosen at set-up by one trial PCG solve per precision on a
+                               fixed pseudo-random right-hand side to rtol 1e-8: 32 if the
+                               FP32 V-cycle converges within 3 iterations of the FP64 one */
     int32_t max_rhs;        /* largest nrhs of a context of this hierarchy (1 <= max_rhs <= 64);
                                > 1 also builds the batched operators                        */
     int32_t tail_rows;      /* coarse-tail folding: while the level above the coarse tail
@@ -93,6 +94,15 @@ typedef struct {
                                FP64, one unit vector at a time, and applied in every V-cycle
                                (single-column and batched) as one dense FP64 product.  Same
                                operator, fewer launches.  0: off (0 <= tail_rows <= 8192). */
+    int32_t smoother;       /* point smoother of the hybrid smoother (section 4.1):
+                               AMGE_SMOOTHER_L1_JACOBI: x += d^{-1}(b - A x), d_i = sum_j |a_ij|;
+                               AMGE_SMOOTHER_SYM_GS: symmetric Gauss-Seidel in colour order
+                               (the smoother of the paper's experiments): rows coloured
+                               greedily (first fit in increasing row order over the rows
+                               coupled to earlier ones), a sweep relaxes the colours in
+                               increasing then decreasing order, each row by
+                               x_i += (b - A x)_i / a_ii.  Single-column contexts only
+                               (max_rhs = 1).                                                 */
     /* Caller's device allocator (both NULL: hipMalloc / hipFree).  alloc(bytes, user)
      * returns device memory of at least `bytes` bytes, 256-byte aligned, or NULL (the
      * call then fails with AMGE_ERR_OOM); dealloc(ptr, user) returns it.  The library
@@ -109,8 +119,10 @@ typedef struct {
 typedef struct amge_hierarchy amge_hierarchy;
 typedef struct amge_ctx amge_ctx;
 
+enum { AMGE_SMOOTHER_L1_JACOBI = 0, AMGE_SMOOTHER_SYM_GS = 1 };
+
 /* Default options: nu = 2 + 2, FP32 preconditioner, max_rhs = 1, tail_rows = 2048,
- * hipMalloc. */
+ * l1-Jacobi, hipMalloc. */
 void amge_default_opts(amge_opts* opts);
 
 /* Builds the device hierarchy from host level matrices (section 3.2, Algorithm 4.1 inputs).
@@ -340,12 +352,22 @@ amge_status amge_server_stats(const amge_server* s, int32_t* queued, int32_t* in
  * their sorted vertex indices, vertex (i,j,k) = i + (n+1)(j + (n+1)k).
  *   alpha_hex, beta_hex  host, n^3 values, hex (i,j,k) at i + n(j + n k)
  *   nlevels              >= 1; n must be divisible by 2^(nlevels-1)
+ *   flags                0, or a combination of
+ *       AMGE_BUILD_COEFFICIENT  coefficient-aware extensions (the remark closing section
+ *                               3.3): the local minimum-mass problems weight the system
+ *                               space's element masses by beta and the next space's (RT
+ *                               for H(curl)) by alpha; face trace masses stay unweighted
+ *       AMGE_BUILD_ESSENTIAL    homogeneous essential boundary conditions (section 5.1's
+ *                               benchmark): every level keeps only the dofs off the boundary
+ *                               of the cube (rows/columns of A, rows of D and P, columns
+ *                               of P and of D restricted alike), renumbered in order
  * The returned problem owns host CSR arrays for every level (amge_level layout).
  * ---------------------------------------------------------------------------------- */
 typedef struct amge_problem amge_problem;
 
+enum { AMGE_BUILD_ESSENTIAL = 1, AMGE_BUILD_COEFFICIENT = 2 };
 amge_status amge_kuhn_build(int32_t kind, int32_t n, int32_t nlevels, const double* alpha_hex,
-                            const double* beta_hex, amge_problem** out);
+                            const double* beta_hex, int32_t flags, amge_problem** out);
 int32_t amge_problem_nlevels(const amge_problem* p);
 /* Fills levels[0..nlevels-1] with pointers into p (valid until amge_problem_free). */
 amge_status amge_problem_levels(const amge_problem* p, amge_level* levels);

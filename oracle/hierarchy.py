@@ -27,7 +27,19 @@ Paper anchors
 * Sections 3.3.3 (bubbles, eqs. (3.7), (3.9)) and 3.3.4: cross-space bubbles
   arise only from targets orthogonal to the PV traces; for order-0 targets none
   survive the filtering, which is asserted.
-* Remark in section 3.3.3 (L2 vs coefficient-weighted masses): unweighted L2.
+* Remark closing section 3.3 (coefficients in the local problems): by default the
+  extensions minimise the unweighted L2 norm; with extension="coefficient" the element
+  masses of the system space are weighted by beta and those of the next space (the
+  range of its derivative) by alpha, so each local problem minimises the part of the
+  energy (2.2) its space carries.  Coarse element masses follow by RAP, so the weights
+  reach every level.  Face trace masses stay unweighted (a face between cells of
+  different beta has no single weight; beta = 1 in every workload here).
+* Essential boundary conditions (the benchmark of section 5.1; boundary attributes
+  tracked on every level, section 3): bc="essential" keeps on every level only the
+  entities not lying in the boundary of the cube.  A coarse basis function of an
+  interior entity vanishes on the boundary (its extensions reach only entities whose
+  closure contains it), so the restricted P maps interior to interior dofs and the
+  restricted operators are still Galerkin products.
 
 Local problems are solved by the SVD null-space method: particular solution
 from the pseudo-inverse of the constraint block, minimisation over the right
@@ -73,7 +85,9 @@ class Level:
         return len(self.ent[d])
 
 
-def fine_level(mesh: FineMesh) -> Level:
+def fine_level(mesh: FineMesh, weights=None) -> Level:
+    """Fine level of the Kuhn mesh; weights: {space: per-tet factor} multiplying that
+    space's element masses (coefficient-aware extensions)."""
     h = mesh.h
     ev, fn = mesh.edge_vectors(), mesh.face_normals()
     measure = [np.ones(mesh.nv),
@@ -81,10 +95,25 @@ def fine_level(mesh: FineMesh) -> Level:
                np.linalg.norm(fn.astype(float), axis=1) / 2.0 * h * h,
                mesh.volumes()]
     ent = [np.arange(mesh.nv)[:, None], mesh.edges, mesh.faces, mesh.tets]
+    masses = {1: mesh.nd_element_mass(), 2: mesh.rt_element_mass()}
+    for i, w in (weights or {}).items():
+        masses[i] = masses[i] * np.asarray(w, dtype=np.float64)[:, None, None]
     return Level(1, mesh.X, ent, [mesh.grad(), mesh.curl(), mesh.div()], measure,
                  [None, ev, fn, None],
-                 {1: (mesh.tet_edges, mesh.nd_element_mass()), 2: (mesh.tet_faces, mesh.rt_element_mass())},
+                 {1: (mesh.tet_edges, masses[1]), 2: (mesh.tet_faces, masses[2])},
                  (mesh.face_edges, mesh.nd_face_trace_mass()), 1, None)
+
+
+def boundary_entities(level: Level, d: int):
+    """Mask of the d-dimensional entities of a level lying in the boundary of the cube:
+    all their vertices on one of its six faces."""
+    X = np.asarray(level.X)
+    top = X.max(axis=0)
+    V = X[np.asarray(level.ent[d])]          # (entities, vertices, 3)
+    on = np.zeros(len(V), dtype=bool)
+    for a in range(3):
+        on |= np.all(V[:, :, a] == 0, axis=1) | np.all(V[:, :, a] == top[a], axis=1)
+    return on
 
 
 def cube_level(k: int, N: int, side: int, h: float) -> Level:
@@ -576,16 +605,31 @@ class Hierarchy:
 
 
 def build_hierarchy(kind: str, n: int, nlevels: int, alpha_hex, beta_hex, spaces=None,
-                    check_targets=True):
+                    check_targets=True, extension="l2", bc="natural"):
     """FP64 hierarchy for H(curl) (kind='curl') or H(div) (kind='div').
 
     spaces: which sequence spaces to coarsen (default: the ones the system
     space needs -- ND needs RT and L2; RT needs L2 -- plus H1 for small meshes).
+    extension: "l2" (unweighted local problems) or "coefficient" (masses of the system
+    space weighted by beta, of the next space by alpha; the order-0 target check does
+    not apply to weighted masses and is skipped).
+    bc: "natural", or "essential" (every level restricted to its interior entities;
+    H.interior[k] is the kept mask of level k's system space).
     """
+    if extension not in ("l2", "coefficient") or bc not in ("natural", "essential"):
+        raise ValueError("extension must be 'l2' or 'coefficient', bc 'natural' or 'essential'")
     mesh = FineMesh(n)
     A, G, C, Dv = fine_problem(mesh, kind, alpha_hex, beta_hex)
-    lev = fine_level(mesh)
     sys_space = 1 if kind == "curl" else 2
+    weights = None
+    if extension == "coefficient":
+        a_t = np.asarray(alpha_hex, dtype=np.float64)[mesh.tet_hex]
+        b_t = np.asarray(beta_hex, dtype=np.float64)[mesh.tet_hex]
+        weights = {sys_space: b_t}
+        if sys_space + 1 <= 2:
+            weights[sys_space + 1] = a_t
+        check_targets = False
+    lev = fine_level(mesh, weights)
     if spaces is None:
         spaces = tuple(range(sys_space, 4)) + ((0,) if n <= 16 and kind == "curl" else ())
     H = Hierarchy()
@@ -609,4 +653,14 @@ def build_hierarchy(kind: str, n: int, nlevels: int, alpha_hex, beta_hex, spaces
         if targets is not None:
             targets = {s: Pi[s] @ targets[s] for s in targets if s in Pi}
         lev = coarse
+    H.extension, H.bc = extension, bc
+    if bc == "essential":
+        keep = [~boundary_entities(L, sys_space) for L in H.levels]
+        keepd = [~boundary_entities(L, sys_space - 1) for L in H.levels]
+        H.interior = keep
+        for k in range(nlevels):
+            H.A[k] = H.A[k][keep[k]][:, keep[k]].tocsr()
+            H.D[k] = H.D[k][keep[k]][:, keepd[k]].tocsr()
+            if k < nlevels - 1:
+                H.P[k] = H.P[k][keep[k]][:, keep[k + 1]].tocsr()
     return H

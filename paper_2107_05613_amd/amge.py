@@ -52,8 +52,11 @@ DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 class OptsC(C.Structure):
     _fields_ = [("nu_primary", C.c_int32), ("nu_aux", C.c_int32), ("precond_bits", C.c_int32),
-                ("max_rhs", C.c_int32), ("tail_rows", C.c_int32), ("alloc", ALLOC_FN), ("dealloc", DEALLOC_FN),
-                ("alloc_user", C.c_void_p)]
+                ("max_rhs", C.c_int32), ("tail_rows", C.c_int32), ("smoother", C.c_int32), ("alloc", ALLOC_FN),
+                ("dealloc", DEALLOC_FN), ("alloc_user", C.c_void_p)]
+
+
+SMOOTHERS = {"l1jacobi": 0, "symgs": 1}
 
 
 def _torch_alloc(nbytes, _user):
@@ -98,7 +101,7 @@ def _load():
         "amge_vcycle_bytes": (i32, [vp, i32, i32, C.POINTER(f64)]),
         "amge_timing_read": (i32, [vp, C.POINTER(f64), C.POINTER(C.c_int64), C.POINTER(f64)]),
         "amge_last_error": (C.c_char_p, []),
-        "amge_kuhn_build": (i32, [i32, i32, i32, C.POINTER(f64), C.POINTER(f64), C.POINTER(vp)]),
+        "amge_kuhn_build": (i32, [i32, i32, i32, C.POINTER(f64), C.POINTER(f64), i32, C.POINTER(vp)]),
         "amge_problem_nlevels": (i32, [vp]),
         "amge_problem_levels": (i32, [vp, C.POINTER(LevelC)]),
         "amge_problem_free": (None, [vp]),
@@ -228,16 +231,23 @@ def _csr_copy(c: CsrC):
     return HostCsr(nr, c.ncols, rp, ci, va)
 
 
-def build_problem(kind, n, nlevels, alpha_hex, beta_hex):
-    """Structured workload (amge_kuhn_build): per level (A, D, P) as HostCsr, P None on the last."""
+BUILD_ESSENTIAL, BUILD_COEFFICIENT = 1, 2
+
+
+def build_problem(kind, n, nlevels, alpha_hex, beta_hex, extension="l2", bc="natural"):
+    """Structured workload (amge_kuhn_build): per level (A, D, P) as HostCsr, P None on the last.
+    extension: "l2" or "coefficient" (weighted local problems); bc: "natural" or "essential"."""
     k = {"curl": CURL, "div": DIV}.get(kind, kind)
+    if extension not in ("l2", "coefficient") or bc not in ("natural", "essential"):
+        raise ValueError("extension must be 'l2' or 'coefficient', bc 'natural' or 'essential'")
+    flags = (BUILD_COEFFICIENT if extension == "coefficient" else 0) | (BUILD_ESSENTIAL if bc == "essential" else 0)
     a = np.ascontiguousarray(alpha_hex, dtype=np.float64)
     b = np.ascontiguousarray(beta_hex, dtype=np.float64)
     if a.size != n ** 3 or b.size != n ** 3:
         raise ValueError("alpha_hex and beta_hex need n**3 values")
     h = C.c_void_p()
     _check(_lib.amge_kuhn_build(k, n, nlevels, a.ctypes.data_as(C.POINTER(C.c_double)),
-                                b.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)))
+                                b.ctypes.data_as(C.POINTER(C.c_double)), flags, C.byref(h)))
     try:
         L = _lib.amge_problem_nlevels(h)
         arr = (LevelC * L)()
@@ -261,10 +271,12 @@ class Hierarchy:
     precond_bits: 32, 64 or 0 (chosen from the cancellation factor); max_rhs: widest
     block of a context (the batched path); tail_rows: levels of at most this many rows
     below the fine one are folded into one dense FP64 operator (0: every level runs its
-    kernels); allocator: "torch" (torch's caching allocator) or None (hipMalloc)."""
+    kernels); smoother: "l1jacobi" or "symgs" (symmetric Gauss-Seidel in colour order,
+    single-column contexts only); allocator: "torch" (torch's caching allocator) or None
+    (hipMalloc)."""
 
     def __init__(self, levels, nu_primary=2, nu_aux=2, precond_bits=32, max_rhs=1, tail_rows=2048, stream=None,
-                 allocator="torch"):
+                 allocator="torch", smoother="l1jacobi"):
         L = len(levels)
         arr = (LevelC * L)()
         self._keep = []
@@ -284,7 +296,7 @@ class Hierarchy:
             al, de = ALLOC_FN(), DEALLOC_FN()
         else:
             raise ValueError("allocator must be 'torch' or None")
-        opts = OptsC(nu_primary, nu_aux, precond_bits, max_rhs, tail_rows, al, de, None)
+        opts = OptsC(nu_primary, nu_aux, precond_bits, max_rhs, tail_rows, SMOOTHERS[smoother], al, de, None)
         h = C.c_void_p()
         _check(_lib.amge_setup_hierarchy(arr, L, C.byref(opts), _stream(stream), C.byref(h)))
         self._h = h

@@ -3,10 +3,16 @@
 // hierarchy of section 3 for 2x2x2 agglomerates.
 //
 // Every agglomerate of a level is a translate of the same 2x2x2 block (uniform Kuhn
-// mesh, unweighted L2 extension masses), so the local problems of section 3.3 are
-// solved once per level on a reference block and the resulting local prolongators
-// are placed at every agglomerate.  Shared rows receive identical values from both
-// sides ("overwriting" assembly, section 2.2 footnote).
+// mesh), so the local problems of section 3.3 are solved once per level on a reference
+// block and the resulting local prolongators are placed at every agglomerate.  With
+// coefficient-aware extensions (the remark closing section 3.3: the system space's
+// element masses weighted by beta, the next space's by alpha) an agglomerate whose cells
+// carry different weights solves its own block; one whose cells share a weight keeps
+// the reference solution (scaling a local problem's mass does not move its minimiser).
+// Shared rows receive identical values from both sides ("overwriting" assembly,
+// section 2.2 footnote): face values come from face problems, which no cell weight
+// enters.  With essential boundary conditions every level keeps only the entities off
+// the boundary of the cube.
 //
 // Local extension problems (eqs. (3.6), (3.8)): minimise the L2 norm of the extension
 // subject to the derivative constraint on the entity's interior, with the trace on its
@@ -17,6 +23,7 @@
 #include <cmath>
 #include <map>
 #include <memory>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -551,8 +558,9 @@ Owner classify(const std::vector<std::array<int, 3>>& X, const Unit& U) {
     return o;
 }
 
-// Level-1 block: the Kuhn mesh of a 2x2x2 hex block.
-Block kuhn_block(double h, const Kuhn& B, const Unit& U) {
+// Level-1 block: the Kuhn mesh of a 2x2x2 hex block.  w (optional): per block hex
+// (i + 2 j + 4 k) the factors of its ND and RT element masses.
+Block kuhn_block(double h, const Kuhn& B, const Unit& U, const std::array<double, 2>* w = nullptr) {
     Block blk;
     blk.nE = (int)B.E.size(); blk.nF = (int)B.F.size(); blk.nC = (int)B.T.size();
     // incidences
@@ -609,10 +617,16 @@ Block kuhn_block(double h, const Kuhn& B, const Unit& U) {
         double Mn[6][6], Mr[4][4];
         nd_mass(g, Mn);
         rt_mass(g, Mr);
+        double wn = 1.0, wr = 1.0;
+        if (w) {
+            auto c = B.coord(B.T[t][0]);   // the tet's hex: its lowest vertex
+            wn = w[c[0] + 2 * c[1] + 4 * c[2]][0];
+            wr = w[c[0] + 2 * c[1] + 4 * c[2]][1];
+        }
         for (int p = 0; p < 6; ++p)
-            for (int q = 0; q < 6; ++q) blk.Mnd(B.te[t][p], B.te[t][q]) += Mn[p][q];
+            for (int q = 0; q < 6; ++q) blk.Mnd(B.te[t][p], B.te[t][q]) += wn * Mn[p][q];
         for (int p = 0; p < 4; ++p)
-            for (int q = 0; q < 4; ++q) blk.Mrt(B.tf[t][p], B.tf[t][q]) += Mr[p][q];
+            for (int q = 0; q < 4; ++q) blk.Mrt(B.tf[t][p], B.tf[t][q]) += wr * Mr[p][q];
     }
     for (int f = 0; f < blk.nF; ++f) {
         auto c0 = B.coord(B.F[f][0]), c1 = B.coord(B.F[f][1]), c2 = B.coord(B.F[f][2]);
@@ -636,8 +650,12 @@ struct CubeElem {
     Mat trace[3];
 };
 
-// Coarser-level block: the 2x2x2 cube complex with element data `el`.
-Block cube_block(const CubeElem& el, const Unit& U) {
+// Coarser-level block: the 2x2x2 cube complex.  Cell c (= i + 2 j + 4 k) carries the ND
+// and RT masses cel[c]->nd * w[c][0] and cel[c]->rt * w[c][1]; the face trace masses
+// are the level's `tr` (they do not depend on the cell weights).
+Block cube_block(const CubeElem* const cel[8], const std::array<double, 2> w[8], const CubeElem& tr,
+                 const Unit& U) {
+    const CubeElem& el = tr;
     Block blk;
     Cubes c2(2);
     blk.nE = c2.nE; blk.nF = c2.nF; blk.nC = c2.nT;
@@ -695,11 +713,13 @@ Block cube_block(const CubeElem& el, const Unit& U) {
                         int g[3] = {q[0] + o[0], q[1] + o[1], q[2] + o[2]};
                         lf[U.face(o, a)] = c2.face(g, a);
                     }
-                if (el.nd.r)
+                const int cidx = i + 2 * j + 4 * k;
+                const CubeElem& ce = *cel[cidx];
+                if (ce.nd.r)
                     for (int p = 0; p < 12; ++p)
-                        for (int r = 0; r < 12; ++r) blk.Mnd(le[p], le[r]) += el.nd(p, r);
+                        for (int r = 0; r < 12; ++r) blk.Mnd(le[p], le[r]) += w[cidx][0] * ce.nd(p, r);
                 for (int p = 0; p < 6; ++p)
-                    for (int r = 0; r < 6; ++r) blk.Mrt(lf[p], lf[r]) += el.rt(p, r);
+                    for (int r = 0; r < 6; ++r) blk.Mrt(lf[p], lf[r]) += w[cidx][1] * ce.rt(p, r);
             }
     for (auto& d : fdesc) {
         int p[3] = {d[0], d[1], d[2]}, a = d[3], b = (a + 1) % 3, c = (a + 2) % 3;
@@ -920,11 +940,14 @@ Csr kuhn_curl(const Kuhn& K) {
     return from_triplets((int32_t)K.F.size(), nE, keys, vals, true);
 }
 
-// Place the block prolongator at every agglomerate.  `fine_index(q, local)` maps a block
-// entity of the agglomerate with base q to its global index on the finer level;
-// coarse entities (unit-cube local order) map to the coarser cube complex.
-template <class FineIndex>
-Csr stamp(const Mat& Pl, int kind_dim, int Nc, int32_t nfine, const FineIndex& fine_index) {
+// Place the local prolongators at every agglomerate.  local_of(t) is the block
+// prolongator of agglomerate t (coarse cube t = i + Nc (j + Nc k)); `fine_index(q,
+// local)` maps a block entity of the agglomerate with base q to its global index on the
+// finer level; coarse entities (unit-cube local order) map to the coarser cube complex.
+// Entries that vanish up to rounding (below 1e-14 of the local prolongator's largest) are
+// not stored.
+template <class FineIndex, class LocalOf>
+Csr stamp(const LocalOf& local_of, int kind_dim, int Nc, int32_t nfine, const FineIndex& fine_index) {
     Cubes coarse(Nc);
     Unit U;
     // unit-cube entity (o, a) -> global coarse entity (q + o, a)
@@ -942,41 +965,137 @@ Csr stamp(const Mat& Pl, int kind_dim, int Nc, int32_t nfine, const FineIndex& f
                     udesc[U.face(o, a)] = {o[0], o[1], o[2], a};
                 }
             }
-    double mx = 0;
-    for (double v : Pl.a) mx = std::max(mx, std::fabs(v));
-    const double tiny = 1e-14 * mx;   // entries that vanish up to rounding are not stored
     int32_t ncoarse = kind_dim == 1 ? coarse.nE : coarse.nF;
     int64_t ncube = (int64_t)Nc * Nc * Nc;
-    std::vector<std::pair<int, int>> nz;
-    for (int i = 0; i < Pl.r; ++i)
-        for (int j = 0; j < Pl.c; ++j)
-            if (std::fabs(Pl(i, j)) > tiny) nz.push_back({i, j});
-    std::vector<int64_t> keys(ncube * nz.size());
-    std::vector<double> vals(ncube * nz.size());
+    // per chunk of agglomerates, in agglomerate order (first-kept duplicates are then
+    // independent of the threading)
+    std::map<int64_t, std::pair<std::vector<int64_t>, std::vector<double>>> parts;
+    std::mutex mu;
     parallel_for(ncube, [&](int64_t s, int64_t e) {
-        std::vector<int32_t> fi(Pl.r), ci(Pl.c);
+        std::vector<int64_t> keys;
+        std::vector<double> vals;
+        std::vector<int32_t> fi, ci;
         for (int64_t t = s; t < e; ++t) {
+            const Mat& Pl = local_of(t);
+            double mx = 0;
+            for (double v : Pl.a) mx = std::max(mx, std::fabs(v));
+            const double tiny = 1e-14 * mx;
             int q[3] = {(int)(t % Nc), (int)((t / Nc) % Nc), (int)(t / ((int64_t)Nc * Nc))};
+            fi.resize(Pl.r);
+            ci.resize(Pl.c);
             for (int i = 0; i < Pl.r; ++i) fi[i] = fine_index(q, i);
             for (int j = 0; j < Pl.c; ++j) {
                 int g[3] = {q[0] + udesc[j][0], q[1] + udesc[j][1], q[2] + udesc[j][2]};
                 ci[j] = kind_dim == 1 ? coarse.edge(g, udesc[j][3]) : coarse.face(g, udesc[j][3]);
             }
-            int64_t o = t * (int64_t)nz.size();
-            for (auto& z : nz) {
-                keys[o] = (int64_t)fi[z.first] * ncoarse + ci[z.second];
-                vals[o++] = Pl(z.first, z.second);
-            }
+            for (int i = 0; i < Pl.r; ++i)
+                for (int j = 0; j < Pl.c; ++j)
+                    if (std::fabs(Pl(i, j)) > tiny) {
+                        keys.push_back((int64_t)fi[i] * ncoarse + ci[j]);
+                        vals.push_back(Pl(i, j));
+                    }
         }
+        std::lock_guard<std::mutex> lk(mu);
+        parts[s] = {std::move(keys), std::move(vals)};
     });
+    std::vector<int64_t> keys;
+    std::vector<double> vals;
+    for (auto& kv : parts) {
+        keys.insert(keys.end(), kv.second.first.begin(), kv.second.first.end());
+        vals.insert(vals.end(), kv.second.second.begin(), kv.second.second.end());
+    }
     return from_triplets(nfine, ncoarse, keys, vals, false);
 }
 
-Problem build(int kind, int n, int nlevels, const double* alpha, const double* beta) {
+// Weights of a cell's element masses in the extension problems (coefficient-aware
+// extensions): the ND masses carry nd, the RT masses rt; ex >= 0 names an explicit
+// element (from a non-uniform agglomerate below), whose masses already carry them.
+struct CellW {
+    double nd = 1.0, rt = 1.0;
+    int32_t ex = -1;
+};
+
+// An agglomerate whose eight cells carry the same scalar weights: each of its local
+// problems is the reference one with its mass scaled, which has the same minimiser.
+bool uniform_cells(const CellW* const c[8]) {
+    for (int i = 0; i < 8; ++i)
+        if (c[i]->ex >= 0 || c[i]->nd != c[0]->nd || c[i]->rt != c[0]->rt) return false;
+    return true;
+}
+
+// Essential boundary conditions: keep the entities not lying in the boundary of the
+// cube.  map[i] = new index of a kept entity, -1 for a boundary one.
+std::vector<int32_t> renumber(const std::vector<char>& bnd) {
+    std::vector<int32_t> m(bnd.size());
+    int32_t k = 0;
+    for (size_t i = 0; i < bnd.size(); ++i) m[i] = bnd[i] ? -1 : k++;
+    return m;
+}
+
+Csr restrict_csr(const Csr& A, const std::vector<int32_t>& rmap, const std::vector<int32_t>& cmap) {
+    Csr B;
+    B.ncols = 0;
+    for (int32_t v : cmap) B.ncols += v >= 0;
+    B.nrows = 0;
+    for (int32_t i = 0; i < A.nrows; ++i) {
+        if (rmap[i] < 0) continue;
+        for (int32_t q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q)
+            if (cmap[A.col[q]] >= 0) {
+                B.col.push_back(cmap[A.col[q]]);
+                B.val.push_back(A.val[q]);
+            }
+        B.rowptr.push_back((int32_t)B.col.size());
+        ++B.nrows;
+    }
+    return B;
+}
+
+// Boundary masks of the fine Kuhn mesh: vertices (d = 0), edges (1), faces (2) whose
+// vertices all lie on one face of the cube (a shared coordinate 0 or n).
+std::vector<char> kuhn_boundary(const Kuhn& K, int d) {
+    auto on = [&](const std::vector<std::array<int, 3>>& X) {
+        for (int a = 0; a < 3; ++a) {
+            bool lo = true, hi = true;
+            for (auto& x : X) { lo &= x[a] == 0; hi &= x[a] == K.n; }
+            if (lo || hi) return true;
+        }
+        return false;
+    };
+    std::vector<char> m;
+    if (d == 0)
+        for (int64_t v = 0; v < K.nv; ++v) m.push_back(on({K.coord(v)}));
+    else if (d == 1)
+        for (auto& e : K.E) m.push_back(on({K.coord(e[0]), K.coord(e[1])}));
+    else
+        for (auto& f : K.F) m.push_back(on({K.coord(f[0]), K.coord(f[1]), K.coord(f[2])}));
+    return m;
+}
+
+// Boundary masks of the cube complex with N cells per side: a vertex with a coordinate
+// 0 or N; an edge (p, a) with such a coordinate off its axis; a face (p, a) with p_a = 0
+// or N.
+std::vector<char> cubes_boundary(const Cubes& C, int d) {
+    const int N = C.N;
+    auto edgeb = [&](int p) { return p == 0 || p == N; };
+    std::vector<char> m(d == 0 ? C.nV : d == 1 ? C.nE : C.nF, 0);
+    for (int64_t v = 0; v < C.nV; ++v) {
+        int p[3] = {(int)(v % C.M), (int)((v / C.M) % C.M), (int)(v / (C.M * C.M))};
+        if (d == 0) m[v] = edgeb(p[0]) || edgeb(p[1]) || edgeb(p[2]);
+        for (int a = 0; a < 3; ++a) {
+            const int b = (a + 1) % 3, c = (a + 2) % 3;
+            if (d == 1 && Cubes::edge_ok(N, p, a)) m[C.edge(p, a)] = edgeb(p[b]) || edgeb(p[c]);
+            if (d == 2 && Cubes::face_ok(N, p, a)) m[C.face(p, a)] = edgeb(p[a]);
+        }
+    }
+    return m;
+}
+
+Problem build(int kind, int n, int nlevels, const double* alpha, const double* beta, int flags) {
     if (kind != AMGE_CURL && kind != AMGE_DIV) fail(AMGE_ERR_ARG, "kind must be AMGE_CURL or AMGE_DIV");
     if (n < 1 || nlevels < 1) fail(AMGE_ERR_ARG, "n and nlevels must be positive");
     if (nlevels > 1 && (n % (1 << (nlevels - 1))) != 0) fail(AMGE_ERR_ARG, "n not divisible by 2^(nlevels-1)");
     if (!alpha || !beta) fail(AMGE_ERR_ARG, "null coefficient array");
+    if (flags & ~(AMGE_BUILD_ESSENTIAL | AMGE_BUILD_COEFFICIENT)) fail(AMGE_ERR_ARG, "unknown build flags");
     for (int64_t i = 0; i < (int64_t)n * n * n; ++i)
         if (!(alpha[i] > 0) || !(beta[i] > 0) || !std::isfinite(alpha[i]) || !std::isfinite(beta[i]))
             fail(AMGE_ERR_ARG, "coefficients must be positive and finite");
@@ -988,14 +1107,66 @@ Problem build(int kind, int n, int nlevels, const double* alpha, const double* b
     pr.A.push_back(fine_matrix(K, kind, alpha, beta));
     pr.D.push_back(curl ? kuhn_grad(K) : kuhn_curl(K));
     Unit U;
-    // level 1 -> 2: reference Kuhn block
-    CubeElem el;
+    // extension weights per cell of the current level: the system space's masses carry
+    // beta, the next space's (RT for H(curl)) alpha; all 1 for unweighted extensions
+    const bool coef = (flags & AMGE_BUILD_COEFFICIENT) != 0;
+    std::vector<CellW> cw((size_t)n * n * n);
+    if (coef)
+        for (size_t i = 0; i < cw.size(); ++i) {
+            cw[i].nd = curl ? beta[i] : 1.0;
+            cw[i].rt = curl ? alpha[i] : beta[i];
+        }
+    std::vector<CubeElem> ex;   // explicit elements of the current level (non-uniform cells)
+    // Per agglomerate of the step from `Nf` cells per side: its eight cells' weights, and
+    // whether it is uniform.
+    auto children = [&](int Nf, int64_t t, const CellW* c[8]) {
+        const int Nc = Nf / 2;
+        int q[3] = {(int)(t % Nc), (int)((t / Nc) % Nc), (int)(t / ((int64_t)Nc * Nc))};
+        for (int k = 0; k < 2; ++k)
+            for (int j = 0; j < 2; ++j)
+                for (int i = 0; i < 2; ++i) {
+                    int64_t cell = (2 * q[0] + i) + (int64_t)Nf * ((2 * q[1] + j) + (int64_t)Nf * (2 * q[2] + k));
+                    c[i + 2 * j + 4 * k] = &cw[cell];
+                }
+    };
+    // level 1 -> 2: reference Kuhn block (unit weights); non-uniform agglomerates solve
+    // their own weighted block
+    CubeElem el;   // reference element of the current level (unit weights)
     if (nlevels > 1) {
         Kuhn B = build_kuhn(2);
         Block blk = kuhn_block(1.0 / n, B, U);
         LocalP L = solve_block(blk, U, curl);
         el = next_elem(blk, L, U, curl);
-        const Mat& Pl = curl ? L.nd : L.rt;
+        const int Nc = n / 2;
+        const int64_t nagg = (int64_t)Nc * Nc * Nc;
+        std::vector<int32_t> own(nagg, -1);   // explicit local solution per agglomerate
+        std::vector<int64_t> todo;
+        std::vector<CellW> next(nagg);
+        for (int64_t t = 0; t < nagg; ++t) {
+            const CellW* c[8];
+            children(n, t, c);
+            if (uniform_cells(c)) {
+                next[t].nd = c[0]->nd;
+                next[t].rt = c[0]->rt;
+            } else {
+                own[t] = (int32_t)todo.size();
+                next[t].ex = (int32_t)todo.size();
+                todo.push_back(t);
+            }
+        }
+        std::vector<LocalP> Ls(todo.size());
+        std::vector<CubeElem> nex(todo.size());
+        parallel_for((int64_t)todo.size(), [&](int64_t s, int64_t e) {
+            for (int64_t u = s; u < e; ++u) {
+                const CellW* c[8];
+                children(n, todo[u], c);
+                std::array<double, 2> w[8];
+                for (int i = 0; i < 8; ++i) w[i] = {c[i]->nd, c[i]->rt};
+                Block b2 = kuhn_block(1.0 / n, B, U, w);
+                Ls[u] = solve_block(b2, U, curl);
+                nex[u] = next_elem(b2, Ls[u], U, curl);
+            }
+        });
         int32_t nfine = curl ? (int32_t)K.E.size() : (int32_t)K.F.size();
         auto fine_index = [&](const int q[3], int i) -> int32_t {
             int64_t off[3] = {2 * q[0], 2 * q[1], 2 * q[2]};
@@ -1006,16 +1177,58 @@ Problem build(int kind, int n, int nlevels, const double* alpha, const double* b
             if (curl) return K.edge(gv(B.E[i][0]), gv(B.E[i][1]));
             return K.face(gv(B.F[i][0]), gv(B.F[i][1]), gv(B.F[i][2]));
         };
-        pr.P.push_back(stamp(Pl, sdim, n / 2, nfine, fine_index));
+        auto local_of = [&](int64_t t) -> const Mat& {
+            const LocalP& lp = own[t] < 0 ? L : Ls[own[t]];
+            return curl ? lp.nd : lp.rt;
+        };
+        pr.P.push_back(stamp(local_of, sdim, Nc, nfine, fine_index));
+        cw.swap(next);
+        ex.swap(nex);
     }
-    // coarser levels: reference cube-complex block
+    // coarser levels: reference cube-complex block, and non-uniform agglomerates
     for (int k = 2; k < nlevels; ++k) {
         int Nf = n >> (k - 1);      // cubes per side on level k
-        Block blk = cube_block(el, U);
+        const CubeElem* ref8[8];
+        std::array<double, 2> one8[8];
+        for (int i = 0; i < 8; ++i) { ref8[i] = &el; one8[i] = {1.0, 1.0}; }
+        Block blk = cube_block(ref8, one8, el, U);
         LocalP L = solve_block(blk, U, curl);
-        CubeElem next = next_elem(blk, L, U, curl);
+        CubeElem next_ref = next_elem(blk, L, U, curl);
+        const int Nc = Nf / 2;
+        const int64_t nagg = (int64_t)Nc * Nc * Nc;
+        std::vector<int32_t> own(nagg, -1);
+        std::vector<int64_t> todo;
+        std::vector<CellW> next(nagg);
+        for (int64_t t = 0; t < nagg; ++t) {
+            const CellW* c[8];
+            children(Nf, t, c);
+            if (uniform_cells(c)) {
+                next[t].nd = c[0]->nd;
+                next[t].rt = c[0]->rt;
+            } else {
+                own[t] = (int32_t)todo.size();
+                next[t].ex = (int32_t)todo.size();
+                todo.push_back(t);
+            }
+        }
+        std::vector<LocalP> Ls(todo.size());
+        std::vector<CubeElem> nex(todo.size());
+        parallel_for((int64_t)todo.size(), [&](int64_t s, int64_t e) {
+            for (int64_t u = s; u < e; ++u) {
+                const CellW* c[8];
+                children(Nf, todo[u], c);
+                const CubeElem* ce[8];
+                std::array<double, 2> w[8];
+                for (int i = 0; i < 8; ++i) {
+                    if (c[i]->ex >= 0) { ce[i] = &ex[c[i]->ex]; w[i] = {1.0, 1.0}; }
+                    else { ce[i] = &el; w[i] = {c[i]->nd, c[i]->rt}; }
+                }
+                Block b2 = cube_block(ce, w, el, U);
+                Ls[u] = solve_block(b2, U, curl);
+                nex[u] = next_elem(b2, Ls[u], U, curl);
+            }
+        });
         Cubes fineC(Nf), c2(2);
-        const Mat& Pl = curl ? L.nd : L.rt;
         // block entity descriptors (base, axis) in the 2x2x2 block's canonical order
         std::vector<std::array<int, 4>> bdesc;
         for (int64_t v = 0; v < c2.nV; ++v) {
@@ -1030,8 +1243,14 @@ Problem build(int kind, int n, int nlevels, const double* alpha, const double* b
             int g[3] = {2 * q[0] + bdesc[i][0], 2 * q[1] + bdesc[i][1], 2 * q[2] + bdesc[i][2]};
             return curl ? fineC.edge(g, bdesc[i][3]) : fineC.face(g, bdesc[i][3]);
         };
-        pr.P.push_back(stamp(Pl, sdim, Nf / 2, curl ? fineC.nE : fineC.nF, fine_index));
-        el = next;
+        auto local_of = [&](int64_t t) -> const Mat& {
+            const LocalP& lp = own[t] < 0 ? L : Ls[own[t]];
+            return curl ? lp.nd : lp.rt;
+        };
+        pr.P.push_back(stamp(local_of, sdim, Nc, curl ? fineC.nE : fineC.nF, fine_index));
+        el = next_ref;
+        cw.swap(next);
+        ex.swap(nex);
     }
     // Galerkin coarse matrices and coarse derivatives
     for (int k = 1; k < nlevels; ++k) {
@@ -1040,6 +1259,23 @@ Problem build(int kind, int n, int nlevels, const double* alpha, const double* b
         pr.A.push_back(spgemm(transpose(P), AP));
         Cubes c(n >> k);
         pr.D.push_back(curl ? c.grad() : c.curl());
+    }
+    if (flags & AMGE_BUILD_ESSENTIAL) {
+        // every level restricted to the entities off the boundary: the system space (rows
+        // and columns of A, rows of P and D) and the derivative's domain (columns of D)
+        std::vector<std::vector<int32_t>> sm(nlevels), dm(nlevels);
+        sm[0] = renumber(kuhn_boundary(K, sdim));
+        dm[0] = renumber(kuhn_boundary(K, sdim - 1));
+        for (int k = 1; k < nlevels; ++k) {
+            Cubes c(n >> k);
+            sm[k] = renumber(cubes_boundary(c, sdim));
+            dm[k] = renumber(cubes_boundary(c, sdim - 1));
+        }
+        for (int k = 0; k < nlevels; ++k) {
+            pr.A[k] = restrict_csr(pr.A[k], sm[k], sm[k]);
+            pr.D[k] = restrict_csr(pr.D[k], sm[k], dm[k]);
+            if (k + 1 < nlevels) pr.P[k] = restrict_csr(pr.P[k], sm[k], sm[k + 1]);
+        }
     }
     return pr;
 }
@@ -1053,12 +1289,12 @@ struct amge_problem {
 };
 
 extern "C" amge_status amge_kuhn_build(int32_t kind, int32_t n, int32_t nlevels, const double* alpha_hex,
-                                       const double* beta_hex, amge_problem** out) {
+                                       const double* beta_hex, int32_t flags, amge_problem** out) {
     try {
         if (!out) amge::fail(AMGE_ERR_ARG, "null output pointer");
         auto* pp = new amge_problem;
         try {
-            pp->p = amge::build(kind, n, nlevels, alpha_hex, beta_hex);
+            pp->p = amge::build(kind, n, nlevels, alpha_hex, beta_hex, flags);
         } catch (...) {
             delete pp;
             throw;

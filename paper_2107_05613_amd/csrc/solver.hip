@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <cstdlib>
@@ -36,9 +37,13 @@ T* upload(amge_hierarchy* H, const T* src, size_t n, hipStream_t s) {
     return d;
 }
 
+// rowmap (optional): global row of each row of A (A holds a subset of a matrix's rows).
 DSell upload_sell(amge_hierarchy* H, const Csr& A, bool incidence, int K, hipStream_t s,
-                  const std::vector<int>* lead = nullptr) {
+                  const std::vector<int>* lead = nullptr, const std::vector<int>* rowmap = nullptr) {
     HostSell h = make_sell(A, incidence, K, lead);
+    if (rowmap)
+        for (int& r : h.srow)
+            if (r >= 0) r = (*rowmap)[r];
     DSell d;
     d.nrows = A.nrows;
     d.ncols = A.ncols;
@@ -169,6 +174,49 @@ void sell_inc(const DSell& M, int add, const T* x, T* y, hipStream_t s, const in
         case 16: sell_inc_k<T, 16>(M, add, x, y, s, stop); break;
         case 32: sell_inc_k<T, 32>(M, add, x, y, s, stop); break;
         default: sell_inc_k<T, 64>(M, add, x, y, s, stop); break;
+    }
+}
+
+// ------------------------------------------------------------------ multicolour Gauss-Seidel
+template <class T, int K, int UNR>
+void gs_ku(const DSell& M, const T* b, const T* dg, T* x, hipStream_t s, const int* stop) {
+    unsigned g = grid_slices(M.nslices);
+    if (g == 0) return;
+    const T* v = vals<T>(M);
+    if (M.c16)
+        dev::k_sell_gs<T, K, true, false, UNR><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ci, M.c16, M.cbase,
+                                                                   v, b, dg, x, stop);
+    else
+        dev::k_sell_gs<T, K, false, false, UNR><<<g, BLOCK, 0, s>>>(M.nslices, M.sptr, M.srow, M.ci, M.c16,
+                                                                    M.cbase, v, b, dg, x, stop);
+}
+
+// One colour's relaxation x_i += dg_i (b - A x)_i over the colour's rows.
+template <class T>
+void gs_color(const DSell& M, const T* b, const T* dg, T* x, hipStream_t s, const int* stop) {
+    switch (M.K) {
+        case 1: gs_ku<T, 1, 4>(M, b, dg, x, s, stop); break;
+        case 2: gs_ku<T, 2, 4>(M, b, dg, x, s, stop); break;
+        case 4: gs_ku<T, 4, 4>(M, b, dg, x, s, stop); break;
+        case 8: gs_ku<T, 8, 4>(M, b, dg, x, s, stop); break;
+        case 16: gs_ku<T, 16, 4>(M, b, dg, x, s, stop); break;
+        case 32: gs_ku<T, 32, 4>(M, b, dg, x, s, stop); break;
+        default: gs_ku<T, 64, 4>(M, b, dg, x, s, stop); break;
+    }
+}
+
+// nu symmetric sweeps (colours increasing, then decreasing) on x in place.  The colour
+// that ends one half-sweep would start the next with a zero residual on its rows, so it
+// is not relaxed twice: nu sweeps of C colours launch 2 nu (C - 1) + 1 colours.
+template <class T>
+void gs_sweeps(const GsColors& g, const T* b, T* x, int nu, hipStream_t s, const int* stop) {
+    const int C = (int)g.col.size();
+    if (nu <= 0 || C == 0) return;
+    const T* dg = g.dg<T>();
+    gs_color<T>(g.col[0], b, dg, x, s, stop);
+    for (int k = 0; k < nu; ++k) {
+        for (int c = 1; c < C; ++c) gs_color<T>(g.col[c], b, dg, x, s, stop);
+        for (int c = C - 2; c >= 0; --c) gs_color<T>(g.col[c], b, dg, x, s, stop);
     }
 }
 
@@ -356,6 +404,11 @@ void convert(int64_t n, const S* a, D* b, hipStream_t s) {
 template <class T>
 void primary(DLevel& L, const T* b, const T* bd, T*& x, T*& xt, bool from_zero, int nu, hipStream_t s,
              const int* stop) {
+    if (!L.gsA.col.empty()) {   // symmetric Gauss-Seidel: in place, from zero if asked
+        if (from_zero) fill_zero<T>(L.n, x, s, stop);
+        gs_sweeps<T>(L.gsA, b, x, nu, s, stop);
+        return;
+    }
     Work<T>& w = L.w<T>();
     int k = 0;
     if (from_zero) {
@@ -382,6 +435,13 @@ template <class T>
 void auxiliary(DLevel& L, const T* b, T* x, int nu, hipStream_t s, const int* stop) {
     if (nu <= 0 || L.m == 0) return;
     Work<T>& w = L.w<T>();
+    if (!L.gsAh.col.empty()) {   // symmetric Gauss-Seidel sweeps on D^T A D from zero
+        sell<T>(L.Aux, dev::SPLIT, x, b, nullptr, w.g, s, stop);
+        fill_zero<T>(L.m, w.y, s, stop);
+        gs_sweeps<T>(L.gsAh, w.g, w.y, nu, s, stop);
+        sell_inc<T>(L.D, 1, w.y, x, s, stop);
+        return;
+    }
     sell<T>(L.Aux, dev::SPLIT, x, b, w.dhinv, w.g, s, stop, w.gd);
     const T* y = w.gd;
     T* ya = w.y;
@@ -968,9 +1028,57 @@ double cancellation_factor(const Csr& A, const Csr& D, const Csr& Dt, const std:
     return kap;
 }
 
-// Automatic preconditioner precision: FP32 unless the cancellation factor would let
-// FP32 rounding reach a tenth of the near-kernel components.
-constexpr double AUTO_FP32_LIMIT = 0.1;
+amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int maxit, int stop_l2, int* iters,
+                double* relres, hipStream_t s);
+
+// Automatic V-cycle precision (opts.precond_bits = 0): one trial PCG solve per precision
+// on a fixed pseudo-random right-hand side (uniform in [-1, 1), splitmix64 of the row
+// index), to rtol 1e-8 in the preconditioner norm.  The FP32 V-cycle is kept when it
+// converges within AUTO_FP32_EXTRA iterations of the FP64 one.  Neither the cancellation
+// factor nor the FP32 cycle's deviation on one vector predicts this: on the jump
+// workloads FP32 costs nothing on every H(div) hierarchy up to n = 32 (kappa 5.5e7) but
+// 60 % more iterations on an H(curl) one with n = 24 (kappa 2.5e7), and stalls at n >= 48.
+constexpr int AUTO_FP32_EXTRA = 3;
+constexpr double AUTO_TRIAL_RTOL = 1e-8;
+constexpr int AUTO_TRIAL_MAXIT = 1000;
+
+int trial_precision(amge_hierarchy* H, hipStream_t s) {
+    if (H->lv.size() < 2) return 64;   // no V-cycle: the preconditioner is the FP64 coarse solve
+    const int n = H->lv[0].n;
+    std::vector<double> b(n);
+    for (int i = 0; i < n; ++i) {
+        uint64_t z = (uint64_t)i * 0x9e3779b97f4a7c15ull + 0x632be59bd9b4e019ull;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        z ^= z >> 31;
+        b[i] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+    }
+    amge_hierarchy tmp;   // the trial vectors, through the caller's allocator
+    tmp.opts = H->opts;
+    double* db = tmp.alloc<double>(n);
+    double* dx = tmp.alloc<double>(n);
+    HIPCHECK(hipMemcpyAsync(db, b.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+    int its[2] = {0, 0};
+    for (int p = 0; p < 2; ++p) {
+        H->opts.precond_bits = p ? 32 : 64;
+        const int maxit = p ? its[0] + AUTO_FP32_EXTRA : AUTO_TRIAL_MAXIT;
+        int it = 0;
+        double rr = 0;
+        amge_status st = AMGE_ERR_BREAKDOWN;
+        try {
+            auto C = make_ctx(H, 1);
+            st = pcg(&C->st, db, dx, AUTO_TRIAL_RTOL, maxit, 0, &it, &rr, s);
+        } catch (const Error& e) {
+            if (e.code == AMGE_ERR_OOM || e.code == AMGE_ERR_HIP) throw;
+        }
+        its[p] = st == AMGE_OK ? it : -1;
+        if (verbose())
+            fprintf(stderr, "[amge precision] FP%d trial: %d iterations (status %d)\n", p ? 32 : 64, it, (int)st);
+        if (its[0] < 0) break;   // FP64 itself did not converge: keep FP64
+    }
+    H->opts.precond_bits = 0;
+    return its[0] >= 0 && its[1] >= 0 && its[1] <= its[0] + AUTO_FP32_EXTRA ? 32 : 64;
+}
 
 // ------------------------------------------------------------------ coarse-tail folding
 // With a zero initial guess the V-cycle from level l down is a fixed linear map B_l of
@@ -981,11 +1089,30 @@ constexpr double AUTO_FP32_LIMIT = 0.1;
 // the single-column V-cycle then applies it as one dense FP64 product (k_coarse), the
 // same operator in one launch instead of every launch of those levels.
 
+std::vector<int> greedy_colors(const Csr& A);
+
 // Host copy of a level that may be folded.
 struct TailLevel {
     Csr A, D, Dt, DtA, Ah, P, Pt;
     std::vector<double> dinv, dhinv;
+    // symmetric Gauss-Seidel smoother: rows of every colour, 1 / a_ii (A and D^T A D)
+    bool gs = false;
+    std::vector<std::vector<int>> clsA, clsAh;
+    std::vector<double> dgA, dgAh;
 };
+
+// Rows of every colour, and 1 / a_ii, of a matrix (host Gauss-Seidel of the folded tail).
+void host_gs_data(const Csr& A, std::vector<std::vector<int>>& cls, std::vector<double>& dg) {
+    const std::vector<int> color = greedy_colors(A);
+    int C = 0;
+    for (int c : color) C = std::max(C, c + 1);
+    cls.assign(C, {});
+    for (int i = 0; i < A.nrows; ++i) cls[color[i]].push_back(i);
+    dg.assign(A.nrows, 0.0);
+    for (int i = 0; i < A.nrows; ++i)
+        for (int q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q)
+            if (A.col[q] == i) dg[i] = 1.0 / A.val[q];
+}
 
 namespace {
 
@@ -1001,6 +1128,26 @@ struct TailScratch {
     std::vector<double> ax, g, y, ay, r, bc, xc;
     TailScratch(int n, int m, int nc) : ax(n), g(m), y(m), ay(m), r(n), bc(nc), xc(nc) {}
 };
+
+// nu symmetric Gauss-Seidel sweeps in colour order on x, with the colour sequence of
+// gs_sweeps (the colour that ends a half-sweep is not relaxed again).
+void host_gs(const Csr& A, const std::vector<std::vector<int>>& cls, const std::vector<double>& dg, int nu,
+             const double* b, double* x) {
+    const int C = (int)cls.size();
+    if (nu <= 0 || C == 0) return;
+    auto relax = [&](int c) {
+        for (int i : cls[c]) {
+            double a = 0;
+            for (int q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) a += A.val[q] * x[A.col[q]];
+            x[i] += dg[i] * (b[i] - a);
+        }
+    };
+    relax(0);
+    for (int k = 0; k < nu; ++k) {
+        for (int c = 1; c < C; ++c) relax(c);
+        for (int c = C - 2; c >= 0; --c) relax(c);
+    }
+}
 
 // nu l1-Jacobi sweeps x <- x + dinv (b - A x)
 void host_sweeps(const TailLevel& L, int nu, const double* b, double* x, TailScratch& w) {
@@ -1018,10 +1165,15 @@ void host_aux(const TailLevel& L, int nua, const double* b, double* x, TailScrat
     host_spmv(L.Dt, b, w.g.data());
     host_spmv(L.DtA, x, w.ay.data());
     for (int i = 0; i < m; ++i) w.g[i] -= w.ay[i];
-    for (int i = 0; i < m; ++i) w.y[i] = L.dhinv[i] * w.g[i];
-    for (int k = 1; k < nua; ++k) {
-        host_spmv(L.Ah, w.y.data(), w.ay.data());
-        for (int i = 0; i < m; ++i) w.y[i] += L.dhinv[i] * (w.g[i] - w.ay[i]);
+    if (L.gs) {
+        std::fill(w.y.begin(), w.y.end(), 0.0);
+        host_gs(L.Ah, L.clsAh, L.dgAh, nua, w.g.data(), w.y.data());
+    } else {
+        for (int i = 0; i < m; ++i) w.y[i] = L.dhinv[i] * w.g[i];
+        for (int k = 1; k < nua; ++k) {
+            host_spmv(L.Ah, w.y.data(), w.ay.data());
+            for (int i = 0; i < m; ++i) w.y[i] += L.dhinv[i] * (w.g[i] - w.ay[i]);
+        }
     }
     host_spmv(L.D, w.y.data(), w.ax.data());
     for (int i = 0; i < n; ++i) x[i] += w.ax[i];
@@ -1031,7 +1183,10 @@ void host_aux(const TailLevel& L, int nua, const double* b, double* x, TailScrat
 void host_tail_vcycle(const TailLevel& L, int nu, int nua, const std::vector<double>& Bc, int nc,
                       const double* b, double* x, TailScratch& w) {
     const int n = L.A.nrows;
-    if (nu >= 1) {   // the first sweep from zero is dinv b
+    if (L.gs) {
+        std::fill(x, x + n, 0.0);
+        host_gs(L.A, L.clsA, L.dgA, nu, b, x);
+    } else if (nu >= 1) {   // the first sweep from zero is dinv b
         for (int i = 0; i < n; ++i) x[i] = L.dinv[i] * b[i];
         host_sweeps(L, nu - 1, b, x, w);
     } else {
@@ -1049,7 +1204,8 @@ void host_tail_vcycle(const TailLevel& L, int nu, int nua, const std::vector<dou
     host_spmv(L.P, w.xc.data(), w.ax.data());
     for (int i = 0; i < n; ++i) x[i] += w.ax[i];
     host_aux(L, nua, b, x, w);
-    host_sweeps(L, nu, b, x, w);
+    if (L.gs) host_gs(L.A, L.clsA, L.dgA, nu, b, x);
+    else host_sweeps(L, nu, b, x, w);
 }
 
 }  // namespace
@@ -1092,8 +1248,76 @@ void fold_tail(amge_hierarchy* H, const std::vector<TailLevel>& tl, const std::v
     HIPCHECK(hipStreamSynchronize(s));
 }
 
+// Greedy colouring: row i takes the smallest colour not held by an earlier row j < i
+// with a_ij != 0.
+std::vector<int> greedy_colors(const Csr& A) {
+    std::vector<int> color(A.nrows, -1), mark;
+    for (int i = 0; i < A.nrows; ++i) {
+        for (int q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) {
+            const int j = A.col[q];
+            if (j >= i || A.val[q] == 0.0) continue;
+            if (color[j] >= (int)mark.size()) mark.resize(color[j] + 1, -1);
+            mark[color[j]] = i;
+        }
+        int c = 0;
+        while (c < (int)mark.size() && mark[c] == i) ++c;
+        color[i] = c;
+    }
+    return color;
+}
+
+// Multicolour Gauss-Seidel data of A: the rows of every colour as their own sliced ELL
+// (lanes per row tuned per colour) and 1 / a_ii in both precisions.
+void build_gs(amge_hierarchy* H, const Csr& A, GsColors& g, hipStream_t s) {
+    const std::vector<int> color = greedy_colors(A);
+    int C = 0;
+    for (int c : color) C = std::max(C, c + 1);
+    std::vector<std::vector<int>> rows(C);
+    for (int i = 0; i < A.nrows; ++i) rows[color[i]].push_back(i);
+    std::vector<double> dg(A.nrows, 0.0);
+    for (int i = 0; i < A.nrows; ++i) {
+        for (int q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q)
+            if (A.col[q] == i) dg[i] = A.val[q];
+        if (!(dg[i] > 0)) fail(AMGE_ERR_NOT_SPD, "Gauss-Seidel needs a positive diagonal");
+        dg[i] = 1.0 / dg[i];
+    }
+    for (int c = 0; c < C; ++c) {
+        Csr S;
+        S.nrows = (int32_t)rows[c].size();
+        S.ncols = A.ncols;
+        for (int i : rows[c]) {
+            for (int q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) {
+                S.col.push_back(A.col[q]);
+                S.val.push_back(A.val[q]);
+            }
+            S.rowptr.push_back((int32_t)S.col.size());
+        }
+        g.col.push_back(upload_sell(H, S, false, tune_lanes(S, false, H->opts, s), s, nullptr, &rows[c]));
+    }
+    std::vector<float> dg32(dg.begin(), dg.end());
+    g.dg64 = upload(H, dg.data(), dg.size(), s);
+    g.dg32 = upload(H, dg32.data(), dg32.size(), s);
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+// Wall-clock phases of set-up, printed with AMGE_VERBOSE.
+struct PhaseClock {
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    std::map<std::string, double> ms;
+    void lap(const char* name) {
+        auto now = std::chrono::steady_clock::now();
+        ms[name] += std::chrono::duration<double, std::milli>(now - t).count();
+        t = now;
+    }
+    ~PhaseClock() {
+        if (!verbose()) return;
+        for (auto& kv : ms) fprintf(stderr, "[amge setup] %-28s %9.1f ms\n", kv.first.c_str(), kv.second);
+    }
+};
+
 void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     if (!levels || nl < 1) fail(AMGE_ERR_ARG, "need at least one level");
+    PhaseClock clk;
     std::vector<Csr> A(nl), D(nl), P(nl);
     for (int k = 0; k < nl; ++k) {
         A[k] = csr_from_view(levels[k].A);
@@ -1122,6 +1346,7 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
             continue;
         }
         L.m = D[k].ncols;
+        clk.lap("input copies, coarse Cholesky");
         Csr Dt = transpose(D[k]);
         Csr DtA = spgemm(Dt, A[k]);                 // D^T A, for the auxiliary residual
         Csr Ah = spgemm(DtA, D[k]);                 // auxiliary matrix D^T A D (eq. (4.1))
@@ -1144,9 +1369,19 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
             T.Pt = transpose(P[k]);
             T.dinv = dinv;
             T.dhinv = dhinv;
+            if (H->opts.smoother == AMGE_SMOOTHER_SYM_GS) {
+                T.gs = true;
+                host_gs_data(A[k], T.clsA, T.dgA);
+                host_gs_data(Ah, T.clsAh, T.dgAh);
+            }
         }
+        clk.lap("host products D^T A, D^T A D");
         L.A = upload_tuned(H, A[k], false, s);
         L.Ah = upload_tuned(H, Ah, false, s);
+        if (H->opts.smoother == AMGE_SMOOTHER_SYM_GS) {
+            build_gs(H, A[k], L.gsA, s);
+            build_gs(H, Ah, L.gsAh, s);
+        }
         L.P = upload_tuned(H, P[k], false, s);
         L.Pt = upload_tuned(H, transpose(P[k]), false, s);
         // every operator but A_k streamed past the caches (A_k is used four times)
@@ -1219,13 +1454,16 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         // the fine matrix itself is needed by the outer PCG even on one level
         H->lv[0].A = upload_tuned(H, A[0], false, s);
     }
-    if (H->opts.precond_bits == 0)
-        H->opts.precond_bits = std::ldexp(H->kappa, -24) <= AUTO_FP32_LIMIT ? 32 : 64;
-    if (batched) setup_batched(H, hl, s);
     H->tail = nl - 1;
     H->tail_n = H->nc;
     H->tail_op = H->Ainv;
+    clk.lap("layouts, tuning, uploads");
     fold_tail(H, tl, ainv, s);
+    clk.lap("folded coarse tail");
+    if (H->opts.precond_bits == 0) H->opts.precond_bits = trial_precision(H, s);
+    clk.lap("precision trial");
+    if (batched) setup_batched(H, hl, s);
+    clk.lap("batched layouts, tuning");
     if (batched) {
         if (H->opts.precond_bits == 32 && H->lv.size() > 1) tune_tail<float>(H, s);
         else tune_tail<double>(H, s);
@@ -1779,6 +2017,7 @@ extern "C" void amge_default_opts(amge_opts* o) {
     o->precond_bits = 32;
     o->max_rhs = 1;
     o->tail_rows = 2048;
+    o->smoother = AMGE_SMOOTHER_L1_JACOBI;
     o->alloc = nullptr;
     o->dealloc = nullptr;
     o->alloc_user = nullptr;
@@ -1798,6 +2037,10 @@ extern "C" amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nl
             fail(AMGE_ERR_ARG, "invalid options");
         if ((H->opts.alloc == nullptr) != (H->opts.dealloc == nullptr))
             fail(AMGE_ERR_ARG, "give both alloc and dealloc, or neither");
+        if (H->opts.smoother != AMGE_SMOOTHER_L1_JACOBI && H->opts.smoother != AMGE_SMOOTHER_SYM_GS)
+            fail(AMGE_ERR_ARG, "unknown smoother");
+        if (H->opts.smoother == AMGE_SMOOTHER_SYM_GS && H->opts.max_rhs > 1)
+            fail(AMGE_ERR_ARG, "the Gauss-Seidel smoother runs single-column contexts only (max_rhs = 1)");
         setup(H.get(), levels, nlevels, (hipStream_t)stream);
         *out = H.release();
         return AMGE_OK;
@@ -2075,12 +2318,40 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
                 return batched ? (double)B.nnz * 4.0 + 4.0 * B.nrows
                                : (double)M.nnz * 4.0 + (M.fixedw ? 0.0 : 4.0 * M.nrows);
             };
-            // primary sweeps: the first one from zero is the producer's bd = dinv b (two
-            // extra streams there), every launched sweep reads x, b and writes y (+ dinv)
-            const int launched = std::max(0, nup - 1) + nup;
-            tot += launched * (mat(L.A, L.bA) + 3 * sx * n + sv * n) + 2 * sx * n;
+            // Gauss-Seidel colour launches: the colour's rows (values, indices, row index,
+            // b, 1/a_ii, x read and written) and the gathered x once
+            auto gsb = [&](const GsColors& g, double ncols, int nu) {
+                const int C = (int)g.col.size();
+                if (nu <= 0 || C == 0) return 0.0;
+                auto one = [&](int c) {
+                    const DSell& M = g.col[c];
+                    return (double)M.nnz * (sv + (M.c16 ? 2.0 : 4.0)) + 4.0 * M.nrows + 4 * sv * M.nrows + sv * ncols;
+                };
+                double t = one(0);
+                for (int k = 0; k < nu; ++k) {
+                    for (int c = 1; c < C; ++c) t += one(c);
+                    for (int c = C - 2; c >= 0; --c) t += one(c);
+                }
+                return t;
+            };
+            const bool gs = !L.gsA.col.empty();
+            if (gs) {
+                // pre-smoother from zero (x filled with zeros), post-smoother from x
+                tot += sx * n + 2 * gsb(L.gsA, n, nup);
+            } else {
+                // primary sweeps: the first one from zero is the producer's bd = dinv b (two
+                // extra streams there), every launched sweep reads x, b and writes y (+ dinv)
+                const int launched = std::max(0, nup - 1) + nup;
+                tot += launched * (mat(L.A, L.bA) + 3 * sx * n + sv * n) + 2 * sx * n;
+            }
             // auxiliary step, pre and post: residual [D^T | -D^T A][b; x] (+ gd), sweeps, D add
-            if (nua > 0) {
+            if (nua > 0 && gs) {
+                // [D^T | -D^T A] (g only), y filled with zeros, Gauss-Seidel on D^T A D, D add
+                double aux = mat(L.Aux, L.bAux) + 2.0 * m + sx * (2 * n + m) + sx * m;
+                aux += gsb(L.gsAh, m, nua);
+                aux += incb(L.D, L.bD) + sx * (m + 2 * n);
+                tot += 2 * aux;
+            } else if (nua > 0) {
                 // [D^T | -D^T A] with its split counts (2 bytes a row); b, x; g, gd; dhinv
                 double aux = mat(L.Aux, L.bAux) + 2.0 * m + sx * (2 * n + m) + sx * m + sv * m;
                 aux += (nua - 1) * (mat(L.Ah, L.bAh) + 3 * sx * m + sv * m);

@@ -334,14 +334,39 @@ def test_deterministic():
 @pytest.mark.parametrize("spec", [("curl", 12, 3, "unit"), ("div", 8, 3, "blocks"), ("div", 32, 4, "blocks")])
 def test_cancellation_factor_and_auto_precision(spec):
     """The library's cancellation factor equals the one computed from the oracle's
-    hierarchy, and precond_bits = 0 picks FP32 exactly when 2^-24 kappa <= 0.1."""
+    hierarchy; precond_bits = 0 keeps the FP32 V-cycle on these hierarchies, where it
+    converges in the FP64 iteration count (+3)."""
     amge = _amge()
     c = case(*spec)
     H = amge.Hierarchy(c.levels, precond_bits=0)
     kap, bits = H.precision_info()
-    print(f"{spec}: kappa library {kap:.6e}, oracle {c.kappa:.6e}, auto precision FP{bits}")
+    x = torch.zeros_like(dev(c.b))
+    _, it32, _ = c.gpu[32].pcg(dev(c.b), x, rtol=1e-8)
+    print(f"{spec}: kappa library {kap:.6e}, oracle {c.kappa:.6e}; auto precision FP{bits}; "
+          f"FP32 {it32[0]} vs FP64 {c.ito} iterations")
     assert abs(kap - c.kappa) <= 1e-9 * c.kappa
-    assert bits == (32 if 2.0 ** -24 * c.kappa <= 0.1 else 64)
+    assert bits == 32 and it32[0] <= c.ito + 3
+    H.close()
+
+
+def test_auto_precision_keeps_fp64_where_fp32_slows_down():
+    """precond_bits = 0 on a hierarchy whose FP32 V-cycle needs far more iterations (the
+    24^3 H(curl) jump workload: ~220 vs ~140) keeps FP64."""
+    amge = _amge()
+    w = W.Workload("t", "curl", 24, W.default_levels(24), "blocks", coef_seed=0)
+    a, b = W.coefficients(w)
+    prod = amge.build_problem(w.kind, w.n, w.levels, a, b)
+    H = amge.Hierarchy(prod, precond_bits=0)
+    bits = H.precision_info()[1]
+    rhs = dev(W.rhs(H.rows[0], 3)[:, 0])
+    its = {}
+    for p in (32, 64):
+        G = amge.Hierarchy(prod, precond_bits=p)
+        st, it, _ = G.pcg(rhs, torch.zeros_like(rhs), rtol=1e-8, maxit=1000)
+        its[p] = it[0]
+        G.close()
+    print(f"curl n=24 jumps: auto precision FP{bits}; FP32 {its[32]} vs FP64 {its[64]} iterations")
+    assert its[32] > its[64] + 3 and bits == 64
     H.close()
 
 
@@ -431,3 +456,36 @@ def test_one_level_hierarchy():
     assert np.linalg.norm(Xs[:, 1] - 2 * xd) <= 1e-10 * np.linalg.norm(xd)
     assert not np.any(Xs[:, 2])
     H.close()
+
+
+@pytest.mark.parametrize("spec", [("curl", 16, 4, "blocks"), ("div", 16, 4, "blocks")])
+@pytest.mark.parametrize("ext,bc", [("coefficient", "natural"), ("l2", "essential"), ("coefficient", "essential")])
+def test_pcg_extension_and_boundary_options(spec, ext, bc):
+    """Coefficient-aware extensions and essential boundary conditions change only the
+    level matrices: the solve phase set up from the oracle's hierarchy of that kind takes
+    the oracle's iteration count (+-1) and matches its fixed-count iterate within the
+    FP64 bar; the library's own builder gives the same count."""
+    from oracle.hierarchy import build_hierarchy
+    from oracle.solve import Multilevel, pcg
+    amge = _amge()
+    kind, n, L, coef = spec
+    w = W.Workload("t", kind, n, L, coef)
+    a, b = W.coefficients(w)
+    H = build_hierarchy(kind, n, L, a, b, check_targets=False, extension=ext, bc=bc)
+    ml = Multilevel.from_hierarchy(H)
+    rhs = W.rhs(H.A[0].shape[0], 0)[:, 0]
+    xo, ito, _ = pcg(H.A[0], rhs, ml, rtol=1e-8)
+    bar = fp64_bar(spreads(H, rhs, ito)["pcg"])
+    G = amge.Hierarchy(oracle_levels(H), precond_bits=64)
+    x = torch.zeros_like(dev(rhs))
+    st, it, _ = G.pcg(dev(rhs), x, rtol=1e-8, maxit=1000)
+    G.pcg(dev(rhs), x, rtol=0.0, maxit=ito)
+    err = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
+    B = amge.Hierarchy(amge.build_problem(kind, n, L, a, b, extension=ext, bc=bc), precond_bits=64)
+    _, itb, _ = B.pcg(dev(rhs), torch.zeros_like(x), rtol=1e-8, maxit=1000)
+    print(f"{spec} {ext}/{bc}: {H.A[0].shape[0]} dofs, oracle {ito} iterations, GPU {it[0]}, builder {itb[0]}; "
+          f"fixed-count error {err:.1e} (bar {bar:.1e})")
+    assert st == 0 and abs(it[0] - ito) <= 1 and abs(itb[0] - ito) <= 1
+    assert err <= bar
+    G.close()
+    B.close()

@@ -235,6 +235,29 @@ def test_served_fp64_matches_oracle():
         assert err <= tol
 
 
+def test_served_fp32_matches_oracle():
+    """Served requests on FP32-preconditioner hierarchies, run to rtol 1e-8: within 3
+    iterations of the oracle's FP64 count and within 1e-6 of its solution (printed)."""
+    from oracle.hierarchy import build_hierarchy
+    from oracle.solve import Multilevel, pcg
+    res = resident(32)
+    reqs = requests(res, 6, seed=4)
+    out = serve(res, reqs, list(range(len(reqs))))
+    oracles = {}
+    for j, (h, b) in enumerate(reqs):
+        w, a, be = res.prods[h]
+        if h not in oracles:
+            H = build_hierarchy(w.kind, w.n, w.levels, a, be, check_targets=False)
+            oracles[h] = (H, Multilevel.from_hierarchy(H))
+        H, ml = oracles[h]
+        status, iters, relres, x = out[j]
+        xo, ito, _ = pcg(H.A[0], b.cpu().numpy(), ml, rtol=1e-8)
+        err = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+        print(f"request {j} (hierarchy {h}): {iters} iterations (oracle {ito}), error vs oracle {err:.1e}")
+        assert status == 0 and relres <= 1e-8 and iters <= ito + 3
+        assert err <= 1e-6
+
+
 def test_admission_by_inflight_budget():
     """At most two requests' work footprint admitted at any moment; the results are still
     those of the unconstrained mix."""

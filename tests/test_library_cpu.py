@@ -51,6 +51,35 @@ def test_builder_matches_oracle(kind, n, L, coef):
             assert abs(P - H.P[k]).max() <= 1e-13 * abs(H.P[k]).max()
 
 
+@pytest.mark.parametrize("kind,n,L,coef,ext,bc", [("curl", 16, 4, "blocks", "coefficient", "natural"),
+                                                ("div", 16, 4, "blocks", "coefficient", "essential"),
+                                                ("curl", 8, 3, "unit", "l2", "essential"),
+                                                ("curl", 8, 3, "random", "coefficient", "essential"),
+                                                ("div", 8, 3, "random", "coefficient", "natural")])
+def test_builder_options_match_oracle(kind, n, L, coef, ext, bc):
+    """Coefficient-aware extensions and essential boundary conditions in the library's
+    builder against the oracle.  Bar for P: 1e-13 times the coefficient contrast r =
+    max(alpha, beta) / min(alpha, beta) (the two builders' different local solvers round
+    within the weighted local problems, whose conditioning grows with r)."""
+    from oracle.hierarchy import build_hierarchy
+    amge = _amge()
+    if coef == "random":
+        rng = np.random.default_rng(5)
+        a, b = 10 ** rng.uniform(-2, 2, n ** 3), 10 ** rng.uniform(-1, 1, n ** 3)
+    else:
+        a, b = W.coefficients(W.Workload("t", kind, n, L, coef))
+    r = max(a.max(), b.max()) / min(a.min(), b.min()) if ext == "coefficient" else 1.0
+    prod = amge.build_problem(kind, n, L, a, b, extension=ext, bc=bc)
+    H = build_hierarchy(kind, n, L, a, b, check_targets=False, extension=ext, bc=bc)
+    for k in range(L):
+        A, D, P = (None if M is None else M.to_scipy() for M in prod[k])
+        assert A.shape == H.A[k].shape and D.shape == H.D[k].shape
+        assert abs(A - H.A[k]).max() <= 1e-13 * abs(H.A[k]).max()
+        assert abs(D - H.D[k]).max() == 0
+        if k < L - 1:
+            assert abs(P - H.P[k]).max() <= 1e-13 * r * abs(H.P[k]).max()
+
+
 def test_builder_rejects_bad_arguments():
     amge = _amge()
     one = np.ones(27)

@@ -14,6 +14,7 @@ import pytest
 import scipy.sparse as sp
 
 from oracle import hierarchy as hm
+from oracle.fem import FineMesh
 from oracle.hierarchy import build_hierarchy, minmass_extend
 from paper_2107_05613_amd.workloads import entity_counts
 
@@ -263,3 +264,97 @@ def test_coefficients_do_not_change_prolongators():
     H2 = build_hierarchy("div", 4, 2, a, np.ones(64))
     assert (H1.P[0] != H2.P[0]).nnz == 0
     assert abs(H1.A[1] - H2.A[1]).max() > 1e-3
+
+
+# ----------------------------------------------------------------------------
+# coefficient-aware extensions and essential boundary conditions
+# ----------------------------------------------------------------------------
+def _random_coefficients(n, seed=5):
+    rng = np.random.default_rng(seed)
+    return 10 ** rng.uniform(-2, 2, n ** 3), 10 ** rng.uniform(-1, 1, n ** 3)
+
+
+def test_coefficient_extension_reduces_to_l2_for_constant_coefficients():
+    """Weighting every local problem's mass by one constant does not move its minimiser:
+    with constant alpha, beta the coefficient-aware prolongators equal the L2 ones."""
+    for kind in ("curl", "div"):
+        a, b = np.full(64, 37.0), np.full(64, 0.02)
+        H1 = build_hierarchy(kind, 4, 3, a, b, check_targets=False)
+        H2 = build_hierarchy(kind, 4, 3, a, b, extension="coefficient")
+        for k in range(2):
+            assert abs(H1.P[k] - H2.P[k]).max() <= 1e-13 * abs(H1.P[k]).max()
+
+
+def test_coefficient_extension_keeps_sequence_invariants():
+    """With per-hex random coefficients (every agglomerate non-uniform) the weighted
+    hierarchy still satisfies Pi P = I, the commutation D P_i = P_{i+1} D^H and
+    D^H = Pi D P (eqs. (3.3), (3.4)), and its prolongators differ from the L2 ones."""
+    a, b = _random_coefficients(4)
+    H = build_hierarchy("curl", 4, 3, a, b, spaces=(0, 1, 2, 3), extension="coefficient")
+    H0 = build_hierarchy("curl", 4, 3, a, b, spaces=(0, 1, 2, 3), check_targets=False)
+    for k in range(2):
+        err = _check_sequence(H, k)
+        assert max(err.values()) < 1e-12, err
+    assert abs(H.P[0] - H0.P[0]).max() > 1e-3
+
+
+def test_coefficient_extension_is_weighted_minimum():
+    """The RT cube extensions of an H(curl) hierarchy minimise the alpha-weighted mass:
+    the weighted mass times the extension is orthogonal to every divergence-free interior
+    bubble (the KKT condition), and is not for the unweighted mass."""
+    a, b = _random_coefficients(4)
+    H = build_hierarchy("curl", 4, 2, a, b, extension="coefficient")
+    fine = H.levels[0]
+    cg = hm._Coarsening(fine, 1.0 / 4)
+    P2 = H.Pall[0][2]
+    Zs = np.arange(cg.nc[3])
+    dofs, intr, Mw = cg.local(2, 3, Zs)
+    fine.cell_mass[2] = (fine.cell_mass[2][0], FineMesh(4).rt_element_mass())   # unweighted, for contrast
+    _, _, M1 = cg.local(2, 3, Zs)
+    yrows = hm._rows2d(cg.interior[3][3], Zs)
+    K = hm.batched_block(fine.D[2], yrows, dofs)
+    Xs = hm._rows2d(cg.sub[(3, 2)], Zs)
+    worst_w = worst_1 = 0.0
+    for bb in range(len(Zs)):
+        U = hm.batched_block(P2, dofs[bb][None], Xs[bb][None])[0]
+        _, sv, Vt = np.linalg.svd(K[bb][:, intr[bb]])
+        N = Vt[np.sum(sv > 1e-12 * sv.max()):].T
+        worst_w = max(worst_w, abs(N.T @ (Mw[bb] @ U)[intr[bb]]).max() / abs(Mw[bb]).max())
+        worst_1 = max(worst_1, abs(N.T @ (M1[bb] @ U)[intr[bb]]).max() / abs(M1[bb]).max())
+    assert worst_w < 1e-12 and worst_1 > 1e-6
+
+
+def test_essential_restriction_is_galerkin():
+    """Essential boundary conditions: a coarse basis function of an interior entity
+    vanishes on every boundary dof (the natural P has no boundary-row / interior-column
+    entries), so the restricted operators are Galerkin products of the restricted
+    prolongators; the restricted fine matrix is the fine matrix on interior dofs."""
+    for kind in ("curl", "div"):
+        a, b = _random_coefficients(8)
+        Hn = build_hierarchy(kind, 8, 3, a, b, check_targets=False)
+        He = build_hierarchy(kind, 8, 3, a, b, check_targets=False, bc="essential")
+        keep = He.interior
+        assert abs(He.A[0] - Hn.A[0][keep[0]][:, keep[0]]).max() == 0
+        for k in range(2):
+            cross = Hn.P[k][~keep[k]][:, keep[k + 1]]
+            assert cross.nnz == 0 or abs(cross).max() == 0
+            Ac = (He.P[k].T @ He.A[k] @ He.P[k]).tocsr()
+            assert abs(Ac - He.A[k + 1]).max() <= 1e-13 * abs(He.A[k + 1]).max()
+
+
+@pytest.mark.parametrize("kind", ["curl", "div"])
+def test_essential_boundary_is_a_sphere_and_interior_sequence_exact(kind):
+    """The boundary entities found on every level form a closed surface of Euler
+    characteristic 2 (V - E + F = 2); on the fine level the interior sequence is exact:
+    the interior gradient is injective and ker(C) = range(G) on interior dofs."""
+    H = build_hierarchy(kind, 4, 3, *_ones(4), check_targets=False)
+    for lev in H.levels:
+        nb = [int(hm.boundary_entities(lev, d).sum()) for d in range(3)]
+        assert nb[0] - nb[1] + nb[2] == 2, nb
+    fine = H.levels[0]
+    iv, ie, iff = (~hm.boundary_entities(fine, d) for d in range(3))
+    G = fine.D[0][ie][:, iv].toarray()
+    Cm = fine.D[1][iff][:, ie].toarray()
+    assert abs(Cm @ G).max() == 0
+    rg, rc = np.linalg.matrix_rank(G), np.linalg.matrix_rank(Cm)
+    assert rg == iv.sum() and rg + rc == ie.sum()
