@@ -78,9 +78,21 @@ struct DSellB {
     int V = 1;                 // columns per lane, tuned
 };
 
+// Multicolour Gauss-Seidel data of one matrix: the rows of each colour as a sliced ELL
+// of their own (srow: global rows), and 1 / a_ii.
+struct GsColors {
+    std::vector<DSell> col;
+    double* dg64 = nullptr;
+    float* dg32 = nullptr;
+    template <class T> const T* dg() const;
+};
+template <> inline const double* GsColors::dg<double>() const { return dg64; }
+template <> inline const float* GsColors::dg<float>() const { return dg32; }
+
 struct DLevel {
     int n = 0, m = 0;
     Probe* probe = nullptr;
+    GsColors gsA, gsAh;       // symmetric Gauss-Seidel smoother (opts.smoother)
     DSell A, Ah, P, Pt;
     DSell Aux;                // [D^T | -D^T A]: auxiliary residual D^T b - (D^T A) x
     DSell PtA;                // [P^T | -P^T A] below the fine level: restricted residual

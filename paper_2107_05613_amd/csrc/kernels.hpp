@@ -147,6 +147,43 @@ k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, 
     else y[row] = xr + dr * (br - acc);
 }
 
+// One colour of a multicolour Gauss-Seidel sweep, in place: for the rows of the colour
+// (the sliced ELL holds only them; srow maps slots to global rows)
+//   x_i += dg_i (b_i - (A x)_i),  dg_i = 1 / a_ii.
+// No row of a colour is coupled to another row of the same colour, so every x_j a lane
+// gathers belongs to another colour and is not written by this launch: x is read and
+// written through one unrestricted pointer, without a race.
+template <typename T, int K, bool C16, bool NT, int UNR = 4>
+__global__ void __launch_bounds__(BLOCK)
+k_sell_gs(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const int* __restrict__ ci,
+          const uint16_t* __restrict__ c16, const int* __restrict__ cbase, const T* __restrict__ av,
+          const T* __restrict__ b, const T* __restrict__ dg, T* x, const int* __restrict__ stop) {
+    const int slice = xcd_block(blockIdx.x, gridDim.x) * WAVES + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int sl = min(slice, nslices - 1);
+    const int stopped = *stop;
+    const int base = sptr[sl];
+    const int end = sptr[sl + 1];
+    const int row = srow[sl * (64 / K) + lane / K];
+    const int cb = C16 ? cbase[sl] : 0;
+    if (stopped | (slice >= nslices) | (end < base) | (row < -1) | (cb < 0)) return;
+    const int width = (end - base) >> 6;
+    const int e0 = base + lane;
+    const T* v = av + e0;
+    const bool owner = row >= 0 && !(lane & (K - 1));
+    const int rw = owner ? row : 0;
+    const T br = b[rw], dr = dg[rw];
+    T acc = 0;
+#pragma unroll UNR
+    for (int k = 0; k < width; ++k) {
+        const int j = col_at<C16, NT>(ci, c16, cb, e0 + k * 64);
+        acc = fma(stream_load<T, NT || sizeof(T) == 8>(v + k * 64), x[j], acc);
+    }
+    acc = row_sum<K>(acc);
+    if (!owner) return;
+    x[row] = x[row] + dr * (br - acc);
+}
+
 // Signed incidence, index-only (same layout): y = D x (ADD = 0) or y += D x (ADD = 1).
 template <typename T, int K, int ADD>
 __global__ void __launch_bounds__(BLOCK)

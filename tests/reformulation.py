@@ -23,7 +23,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
-from oracle.solve import Multilevel, pcg
+from oracle.solve import Multilevel, gs_sweep, pcg
 
 SPREAD_FACTOR = 3.0
 
@@ -46,7 +46,10 @@ class Reformulated(Multilevel):
         g = lv.D.T @ b - lv.DtA @ x
         y = np.zeros_like(g)
         for _ in range(lv.nu_aux):
-            y = y + (g - lv.Ahat @ y) / lv.dhat
+            if lv.smoother == "symgs":
+                y = gs_sweep(lv.Ahat, lv.diaghat, lv.classes_hat, g, y, lv.blocks_hat)
+            else:
+                y = y + (g - lv.Ahat @ y) / lv.dhat
         return x + lv.D @ y
 
     def vcycle(self, b, l=0, x0=None):
@@ -66,12 +69,12 @@ def relmax(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
 
 
-def spreads(H, b, iters, nu_primary=2, nu_aux=2):
+def spreads(H, b, iters, nu_primary=2, nu_aux=2, smoother="l1jacobi"):
     """Distances between the oracle and its reformulation on right-hand side b: one
     smoother application per level (max-norm relative), one V-cycle (max-norm
     relative) and PCG after `iters` iterations (2-norm relative)."""
-    ml = Multilevel.from_hierarchy(H, nu_primary=nu_primary, nu_aux=nu_aux)
-    rf = Reformulated(H.A, H.D, H.P, nu_primary=nu_primary, nu_aux=nu_aux)
+    ml = Multilevel.from_hierarchy(H, nu_primary=nu_primary, nu_aux=nu_aux, smoother=smoother)
+    rf = Reformulated(H.A, H.D, H.P, nu_primary=nu_primary, nu_aux=nu_aux, smoother=smoother)
     rng = np.random.default_rng(8)
     smooth = 0.0
     for k in range(len(H.A) - 1):

@@ -130,3 +130,60 @@ def test_pcg_stops_on_preconditioner_norm(div4):
     # fixed-iteration mode runs exactly that many products
     x2, it2, _ = pcg(A, b, ml, fixed_iters=it)
     assert it2 == it and np.allclose(x2, x, rtol=0, atol=1e-14 * abs(x).max())
+
+
+# ----------------------------------------------------------------------------
+# symmetric Gauss-Seidel in colour order
+# ----------------------------------------------------------------------------
+def test_greedy_coloring_is_proper_and_first_fit(curl4):
+    """No two coupled rows share a colour, and every row's colour is the smallest one
+    its earlier neighbours leave free (checked by brute force over the dense pattern)."""
+    from oracle.solve import greedy_coloring
+    for A in (curl4.A[0], curl4.A[1]):
+        color = greedy_coloring(A)
+        Ad = A.toarray()
+        for i in range(A.shape[0]):
+            nb = np.nonzero(Ad[i])[0]
+            nb = nb[nb != i]
+            assert np.all(color[nb] != color[i])
+            earlier = set(color[nb[nb < i]].tolist())
+            assert color[i] == min(set(range(len(earlier) + 1)) - earlier)
+
+
+def test_gs_sweep_is_textbook_symmetric_gauss_seidel(div4):
+    """One colour-order sweep equals textbook symmetric Gauss-Seidel on the matrix with
+    its rows and columns permuted into colour order: a forward triangular solve with
+    (D + L) then a backward one with (D + U), L / U the strict triangles in that order."""
+    from oracle.solve import greedy_coloring, gs_sweep
+    A = div4.A[0].tocsr()
+    color = greedy_coloring(A)
+    order = np.argsort(color, kind="stable")
+    classes = [np.nonzero(color == c)[0] for c in range(color.max() + 1)]
+    rng = np.random.default_rng(3)
+    b, x = rng.uniform(-1, 1, A.shape[0]), rng.uniform(-1, 1, A.shape[0])
+    got = gs_sweep(A, A.diagonal(), classes, b, x)
+    Ap = A[order][:, order].toarray()
+    bp, xp = b[order], x[order]
+    lower, upper = np.tril(Ap), np.triu(Ap)
+    xp = xp + sla.solve_triangular(lower, bp - Ap @ xp, lower=True)
+    xp = xp + sla.solve_triangular(upper, bp - Ap @ xp, lower=False)
+    ref = np.empty_like(xp)
+    ref[order] = xp
+    assert abs(got - ref).max() <= 1e-12 * abs(ref).max()
+
+
+@pytest.mark.parametrize("which", ["curl4", "div4"])
+def test_gs_vcycle_symmetric_and_positive(which, request):
+    """With symmetric Gauss-Seidel point smoothers the V-cycle is again symmetric and
+    lambda(BA) lies in (0, 1], and PCG needs fewer iterations than with l1-Jacobi."""
+    H = request.getfixturevalue(which)
+    ml = Multilevel.from_hierarchy(H, smoother="symgs")
+    n = H.A[0].shape[0]
+    B = _explicit(ml.vcycle, n)
+    assert abs(B - B.T).max() <= 1e-11 * abs(B).max()
+    ev = sla.eigh(H.A[0].toarray(), np.linalg.inv(B), eigvals_only=True)
+    assert ev.min() > 0 and ev.max() <= 1 + 1e-10
+    b = W.rhs(n, 0)[:, 0]
+    _, it_gs, _ = pcg(H.A[0], b, ml, rtol=1e-8)
+    _, it_j, _ = pcg(H.A[0], b, Multilevel.from_hierarchy(H), rtol=1e-8)
+    assert it_gs < it_j
