@@ -16,14 +16,16 @@
 //
 // Local extension problems (eqs. (3.6), (3.8)): minimise the L2 norm of the extension
 // subject to the derivative constraint on the entity's interior, with the trace on its
-// boundary fixed.  Solved by the range-space method: drop linearly dependent
-// constraint rows (Gaussian elimination with partial pivoting), Cholesky of the interior
-// mass, Schur complement on the multipliers.
+// boundary fixed.  Solved by the null-space method with a pivoted Householder QR of the
+// constraint (particular solution on its range, mass minimised over its null space).
 #include <array>
 #include <cmath>
 #include <map>
 #include <memory>
 #include <mutex>
+#include <chrono>
+#include <cstdlib>
+#include <string>
 
 #include "common.hpp"
 
@@ -98,39 +100,75 @@ void chol_solve(const Mat& L, Mat& B) {
     }
 }
 
-// Indices of a maximal set of linearly independent rows of K (partial pivoting on rows).
-std::vector<int> independent_rows(const Mat& K, double tol) {
-    Mat W = K;
-    std::vector<int> rows;
-    std::vector<char> used(K.r, 0);
-    double scale = 0;
-    for (double v : K.a) scale = std::max(scale, std::fabs(v));
-    for (int j = 0; j < K.c && (int)rows.size() < K.r; ++j) {
-        int piv = -1;
-        double best = tol * scale;
-        for (int i = 0; i < K.r; ++i)
-            if (!used[i] && std::fabs(W(i, j)) > best) { best = std::fabs(W(i, j)); piv = i; }
-        if (piv < 0) continue;
-        used[piv] = 1;
-        rows.push_back(piv);
-        for (int i = 0; i < K.r; ++i) {
-            if (used[i] || W(i, j) == 0) continue;
-            double f = W(i, j) / W(piv, j);
-            for (int l = j; l < K.c; ++l) W(i, l) -= f * W(piv, l);
+// Householder QR with column pivoting of an r x c matrix A (in place): A P = Q R.
+// On return A holds R in its upper triangle, Qf the r x r orthogonal factor, piv the
+// column order, and the rank is the number of diagonal entries of R above
+// tol * |R(0, 0)|.
+int qr_pivoted(Mat& A, Mat& Qf, std::vector<int>& piv, double tol) {
+    const int r = A.r, c = A.c, kmax = std::min(r, c);
+    piv.resize(c);
+    for (int j = 0; j < c; ++j) piv[j] = j;
+    Qf = Mat(r, r);
+    for (int i = 0; i < r; ++i) Qf(i, i) = 1.0;
+    std::vector<double> v(r);
+    double r00 = 0;
+    int rank = 0;
+    for (int k = 0; k < kmax; ++k) {
+        // the remaining column of largest norm
+        int best = -1;
+        double bn = -1;
+        for (int j = k; j < c; ++j) {
+            double s = 0;
+            for (int i = k; i < r; ++i) s += A(i, j) * A(i, j);
+            if (s > bn) { bn = s; best = j; }
         }
+        bn = std::sqrt(bn);
+        if (k == 0) r00 = bn;
+        if (!(bn > tol * r00) || bn == 0) break;
+        if (best != k) {
+            for (int i = 0; i < r; ++i) std::swap(A(i, k), A(i, best));
+            std::swap(piv[k], piv[best]);
+        }
+        // reflector H = I - 2 v v^T / (v^T v) mapping A(k:, k) to -sign(a_kk) |.| e_k
+        const double alpha = A(k, k) >= 0 ? -bn : bn;
+        double vv = 0;
+        for (int i = k; i < r; ++i) {
+            v[i] = A(i, k) - (i == k ? alpha : 0.0);
+            vv += v[i] * v[i];
+        }
+        if (vv > 0) {
+            for (int j = k; j < c; ++j) {
+                double d = 0;
+                for (int i = k; i < r; ++i) d += v[i] * A(i, j);
+                d = 2 * d / vv;
+                for (int i = k; i < r; ++i) A(i, j) -= d * v[i];
+            }
+            for (int j = 0; j < r; ++j) {   // Qf <- Qf H (Qf accumulates the reflectors)
+                double d = 0;
+                for (int i = k; i < r; ++i) d += Qf(j, i) * v[i];
+                d = 2 * d / vv;
+                for (int i = k; i < r; ++i) Qf(j, i) -= d * v[i];
+            }
+        }
+        ++rank;
     }
-    std::sort(rows.begin(), rows.end());
-    return rows;
+    return rank;
 }
 
-// Minimum-mass extension on one entity.
+// Minimum-mass extension on one entity (eqs. (3.6), (3.8) read as the optimality
+// conditions of: minimise the mass of the extension subject to the derivative
+// constraint on the entity's interior, its trace on the boundary fixed).
 //   M     mass on the entity's closure dofs (nd x nd), or empty if the constraint alone
 //         determines the interior values
 //   K     constraint rows over the closure dofs (m x nd)
 //   intr  interior mask (nd)
 //   S     right-hand sides of the constraint (m x nrhs)
 //   UB    boundary values (nB x nrhs), in closure order of the non-interior dofs
-// Returns U_I (nI x nrhs).
+// Returns U_I (nI x nrhs).  Null-space method: with K_I^T P = Q R (pivoted QR), the
+// constraint K_I u = g reads R^T (Q^T u) = P^T g; its first `rank` rows fix the range
+// part y1 of y = Q^T u (triangular solve), and the null-space part y2 minimises the
+// mass: (Q2^T M_II Q2) y2 = -Q2^T (M_II Q1 y1 + M_IB u_B).  The constraint then holds to
+// rounding whatever the conditioning of the mass (coefficient-weighted masses).
 Mat extend(const Mat& M, const Mat& K, const std::vector<char>& intr, const Mat& S, const Mat& UB) {
     int nd = K.c, m = K.r, nrhs = S.c;
     std::vector<int> I, B;
@@ -145,70 +183,53 @@ Mat extend(const Mat& M, const Mat& K, const std::vector<char>& intr, const Mat&
             G(i, t) = s;
         }
     }
-    std::vector<int> R = independent_rows(KI, 1e-12);
-    int r = (int)R.size();
-    Mat KR(r, nI), GR(r, nrhs);
-    for (int i = 0; i < r; ++i) {
-        for (int a = 0; a < nI; ++a) KR(i, a) = KI(R[i], a);
-        for (int t = 0; t < nrhs; ++t) GR(i, t) = G(R[i], t);
-    }
-    Mat U(nI, nrhs);
-    if (r == nI) {
-        // square nonsingular: solve KR U = GR by Gaussian elimination with pivoting
-        Mat Aug = KR, X = GR;
-        std::vector<int> perm(nI);
-        for (int i = 0; i < nI; ++i) perm[i] = i;
-        for (int j = 0; j < nI; ++j) {
-            int piv = j;
-            for (int i = j + 1; i < nI; ++i)
-                if (std::fabs(Aug(i, j)) > std::fabs(Aug(piv, j))) piv = i;
-            if (piv != j) {
-                for (int l = 0; l < nI; ++l) std::swap(Aug(j, l), Aug(piv, l));
-                for (int t = 0; t < nrhs; ++t) std::swap(X(j, t), X(piv, t));
-            }
-            for (int i = j + 1; i < nI; ++i) {
-                double f = Aug(i, j) / Aug(j, j);
-                if (f == 0) continue;
-                for (int l = j; l < nI; ++l) Aug(i, l) -= f * Aug(j, l);
-                for (int t = 0; t < nrhs; ++t) X(i, t) -= f * X(j, t);
-            }
+    Mat R(nI, m), Qf;
+    for (int i = 0; i < m; ++i)
+        for (int a = 0; a < nI; ++a) R(a, i) = KI(i, a);
+    std::vector<int> piv;
+    const int rk = qr_pivoted(R, Qf, piv, 1e-12);
+    // y1: R11^T y1 = (P^T g)(0 : rk), forward substitution
+    Mat Y1(rk, nrhs);
+    for (int t = 0; t < nrhs; ++t)
+        for (int i = 0; i < rk; ++i) {
+            double s = G(piv[i], t);
+            for (int l = 0; l < i; ++l) s -= R(l, i) * Y1(l, t);
+            Y1(i, t) = s / R(i, i);
         }
-        for (int t = 0; t < nrhs; ++t)
-            for (int i = nI - 1; i >= 0; --i) {
-                double s = X(i, t);
-                for (int l = i + 1; l < nI; ++l) s -= Aug(i, l) * U(l, t);
-                U(i, t) = s / Aug(i, i);
-            }
-    } else {
+    Mat U(nI, nrhs);   // particular solution Q1 y1
+    for (int a = 0; a < nI; ++a)
+        for (int t = 0; t < nrhs; ++t) {
+            double s = 0;
+            for (int i = 0; i < rk; ++i) s += Qf(a, i) * Y1(i, t);
+            U(a, t) = s;
+        }
+    const int nz = nI - rk;
+    if (nz > 0) {
         if (M.r == 0) fail(AMGE_ERR_ARG, "extension not determined by its constraint");
-        // KKT: M_II u + K_R^T lam = -M_IB u_B,  K_R u = g_R
-        Mat L(nI, nI), F(nI, nrhs);
+        // Q2 = Qf(:, rk:), reduced mass Q2^T M_II Q2 and right-hand side
+        Mat MII(nI, nI), F(nI, nrhs);
         for (int a = 0; a < nI; ++a) {
-            for (int b = 0; b < nI; ++b) L(a, b) = M(I[a], I[b]);
+            for (int b = 0; b < nI; ++b) MII(a, b) = M(I[a], I[b]);
             for (int t = 0; t < nrhs; ++t) {
                 double s = 0;
-                for (size_t b = 0; b < B.size(); ++b) s -= M(I[a], B[b]) * UB((int)b, t);
-                F(a, t) = s;
+                for (size_t b = 0; b < B.size(); ++b) s += M(I[a], B[b]) * UB((int)b, t);
+                for (int b = 0; b < nI; ++b) s += M(I[a], I[b]) * U(b, t);
+                F(a, t) = s;   // M_II u_p + M_IB u_B
             }
         }
-        if (!cholesky(L)) fail(AMGE_ERR_NOT_SPD, "local mass not positive definite");
-        Mat Y(nI, r);                       // M_II^{-1} K_R^T
+        Mat Q2(nI, nz);
         for (int a = 0; a < nI; ++a)
-            for (int i = 0; i < r; ++i) Y(a, i) = KR(i, a);
-        chol_solve(L, Y);
-        Mat Sch = matmul(KR, Y);            // K_R M^{-1} K_R^T
-        Mat MF = F;
-        chol_solve(L, MF);                  // M^{-1} f
-        Mat rhs = matmul(KR, MF);           // K_R M^{-1} f - g_R
-        for (int i = 0; i < r; ++i)
-            for (int t = 0; t < nrhs; ++t) rhs(i, t) -= GR(i, t);
-        if (!cholesky(Sch)) fail(AMGE_ERR_NOT_SPD, "extension Schur complement not positive definite");
-        chol_solve(Sch, rhs);               // lam
-        Mat YL = matmul(Y, rhs);
+            for (int j = 0; j < nz; ++j) Q2(a, j) = Qf(a, rk + j);
+        Mat Red = tmatmul(Q2, matmul(MII, Q2));
+        Mat W2 = tmatmul(Q2, F);
+        for (double& v : W2.a) v = -v;
+        if (!cholesky(Red)) fail(AMGE_ERR_NOT_SPD, "local mass not positive definite on the null space");
+        chol_solve(Red, W2);
+        Mat Z = matmul(Q2, W2);
         for (int a = 0; a < nI; ++a)
-            for (int t = 0; t < nrhs; ++t) U(a, t) = MF(a, t) - YL(a, t);
+            for (int t = 0; t < nrhs; ++t) U(a, t) += Z(a, t);
     }
-    // consistency: every constraint row (including dropped ones) must hold
+    // consistency: every constraint row (the dependent ones too) must hold
     double res = 0, gn = 0;
     for (int i = 0; i < m; ++i)
         for (int t = 0; t < nrhs; ++t) {
@@ -1090,7 +1111,24 @@ std::vector<char> cubes_boundary(const Cubes& C, int d) {
     return m;
 }
 
+// Wall-clock phases of the build, printed with AMGE_VERBOSE.
+struct BuildClock {
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    std::map<std::string, double> ms;
+    void lap(const char* name) {
+        auto now = std::chrono::steady_clock::now();
+        ms[name] += std::chrono::duration<double, std::milli>(now - t).count();
+        t = now;
+    }
+    ~BuildClock() {
+        const char* e = getenv("AMGE_VERBOSE");
+        if (!e || !*e || *e == '0') return;
+        for (auto& kv : ms) fprintf(stderr, "[amge build] %-28s %9.1f ms\n", kv.first.c_str(), kv.second);
+    }
+};
+
 Problem build(int kind, int n, int nlevels, const double* alpha, const double* beta, int flags) {
+    BuildClock clk;
     if (kind != AMGE_CURL && kind != AMGE_DIV) fail(AMGE_ERR_ARG, "kind must be AMGE_CURL or AMGE_DIV");
     if (n < 1 || nlevels < 1) fail(AMGE_ERR_ARG, "n and nlevels must be positive");
     if (nlevels > 1 && (n % (1 << (nlevels - 1))) != 0) fail(AMGE_ERR_ARG, "n not divisible by 2^(nlevels-1)");
@@ -1104,8 +1142,10 @@ Problem build(int kind, int n, int nlevels, const double* alpha, const double* b
     Problem pr;
     pr.kind = kind; pr.n = n; pr.nlevels = nlevels;
     Kuhn K = build_kuhn(n);
+    clk.lap("Kuhn mesh");
     pr.A.push_back(fine_matrix(K, kind, alpha, beta));
     pr.D.push_back(curl ? kuhn_grad(K) : kuhn_curl(K));
+    clk.lap("fine matrix, derivative");
     Unit U;
     // extension weights per cell of the current level: the system space's masses carry
     // beta, the next space's (RT for H(curl)) alpha; all 1 for unweighted extensions
@@ -1181,7 +1221,9 @@ Problem build(int kind, int n, int nlevels, const double* alpha, const double* b
             const LocalP& lp = own[t] < 0 ? L : Ls[own[t]];
             return curl ? lp.nd : lp.rt;
         };
+        clk.lap("local problems");
         pr.P.push_back(stamp(local_of, sdim, Nc, nfine, fine_index));
+        clk.lap("prolongator assembly");
         cw.swap(next);
         ex.swap(nex);
     }
@@ -1247,7 +1289,9 @@ Problem build(int kind, int n, int nlevels, const double* alpha, const double* b
             const LocalP& lp = own[t] < 0 ? L : Ls[own[t]];
             return curl ? lp.nd : lp.rt;
         };
+        clk.lap("local problems");
         pr.P.push_back(stamp(local_of, sdim, Nc, curl ? fineC.nE : fineC.nF, fine_index));
+        clk.lap("prolongator assembly");
         el = next_ref;
         cw.swap(next);
         ex.swap(nex);
@@ -1260,6 +1304,7 @@ Problem build(int kind, int n, int nlevels, const double* alpha, const double* b
         Cubes c(n >> k);
         pr.D.push_back(curl ? c.grad() : c.curl());
     }
+    clk.lap("Galerkin products");
     if (flags & AMGE_BUILD_ESSENTIAL) {
         // every level restricted to the entities off the boundary: the system space (rows
         // and columns of A, rows of P and D) and the derivative's domain (columns of D)

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <exception>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -1223,18 +1224,25 @@ void fold_tail(amge_hierarchy* H, const std::vector<TailLevel>& tl, const std::v
         std::vector<double> Bl((size_t)n * n);
         const int nthr = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
         std::vector<std::thread> pool;
+        std::vector<std::exception_ptr> err(nthr);   // carried to this thread, rethrown after the join
         for (int id = 0; id < nthr; ++id)
             pool.emplace_back([&, id]() {
-                TailScratch w(n, m, nb);
-                std::vector<double> e(n, 0.0), x(n);
-                for (int i = id; i < n; i += nthr) {   // column i = B_l e_i
-                    e[i] = 1.0;
-                    host_tail_vcycle(L, nu, nua, B, nb, e.data(), x.data(), w);
-                    e[i] = 0.0;
-                    for (int j = 0; j < n; ++j) Bl[(size_t)j * n + i] = x[j];
+                try {
+                    TailScratch w(n, m, nb);
+                    std::vector<double> e(n, 0.0), x(n);
+                    for (int i = id; i < n; i += nthr) {   // column i = B_l e_i
+                        e[i] = 1.0;
+                        host_tail_vcycle(L, nu, nua, B, nb, e.data(), x.data(), w);
+                        e[i] = 0.0;
+                        for (int j = 0; j < n; ++j) Bl[(size_t)j * n + i] = x[j];
+                    }
+                } catch (...) {
+                    err[id] = std::current_exception();
                 }
             });
         for (std::thread& th : pool) th.join();
+        for (auto& e : err)
+            if (e) std::rethrow_exception(e);
         B.swap(Bl);
         nb = n;
         t -= 1;
@@ -1346,7 +1354,7 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
             continue;
         }
         L.m = D[k].ncols;
-        clk.lap("input copies, coarse Cholesky");
+        clk.lap("other per-level work");
         Csr Dt = transpose(D[k]);
         Csr DtA = spgemm(Dt, A[k]);                 // D^T A, for the auxiliary residual
         Csr Ah = spgemm(DtA, D[k]);                 // auxiliary matrix D^T A D (eq. (4.1))
@@ -1378,12 +1386,14 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         clk.lap("host products D^T A, D^T A D");
         L.A = upload_tuned(H, A[k], false, s);
         L.Ah = upload_tuned(H, Ah, false, s);
+        clk.lap("layouts+tuning A, D^T A D");
         if (H->opts.smoother == AMGE_SMOOTHER_SYM_GS) {
             build_gs(H, A[k], L.gsA, s);
             build_gs(H, Ah, L.gsAh, s);
         }
         L.P = upload_tuned(H, P[k], false, s);
         L.Pt = upload_tuned(H, transpose(P[k]), false, s);
+        clk.lap("layouts+tuning P, P^T");
         // every operator but A_k streamed past the caches (A_k is used four times)
         L.Ah.stream = L.P.stream = L.Pt.stream = true;
         L.D = upload_incidence(H, D[k], s);
@@ -1409,8 +1419,10 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
                 }
                 X.rowptr[i + 1] = (int32_t)X.col.size();
             }
+            clk.lap("other per-level work");
             L.Aux = upload_tuned(H, X, false, s, &lead);
             L.Aux.stream = true;
+            clk.lap("layouts+tuning aux residual");
             if (k >= 1) {
                 // [P^T | -P^T A] on [b; x] below the fine level: the restricted residual
                 // P^T (b - A x) in one (latency-bound) launch instead of a residual and a
@@ -1435,8 +1447,10 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
                     }
                     R.rowptr[i + 1] = (int32_t)R.col.size();
                 }
+                clk.lap("host products P^T A");
                 L.PtA = upload_tuned(H, R, false, s, &rlead);
                 L.PtA.stream = true;
+                clk.lap("layouts+tuning restriction");
             }
             if (batched) {
                 hl[k].Ah = Ah;
@@ -1457,7 +1471,7 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     H->tail = nl - 1;
     H->tail_n = H->nc;
     H->tail_op = H->Ainv;
-    clk.lap("layouts, tuning, uploads");
+    clk.lap("other per-level work");
     fold_tail(H, tl, ainv, s);
     clk.lap("folded coarse tail");
     if (H->opts.precond_bits == 0) H->opts.precond_bits = trial_precision(H, s);

@@ -1,4 +1,5 @@
 // Host sparse kernels used at set-up: transpose, sparse product, triplet assembly.
+#include <exception>
 #include <atomic>
 #include <cmath>
 #include <numeric>
@@ -24,14 +25,25 @@ void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& body) 
         body(0, n);
         return;
     }
+    // an exception in a worker is carried to the caller (an escaping one would end the
+    // process); the first one, in chunk order, is rethrown after every worker has joined
     std::vector<std::thread> th;
+    std::vector<std::exception_ptr> err(nt);
     int64_t chunk = (n + nt - 1) / nt;
     for (int t = 0; t < nt; ++t) {
         int64_t s = t * chunk, e = std::min(n, s + chunk);
         if (s >= e) break;
-        th.emplace_back([&body, s, e] { body(s, e); });
+        th.emplace_back([&body, &err, t, s, e] {
+            try {
+                body(s, e);
+            } catch (...) {
+                err[t] = std::current_exception();
+            }
+        });
     }
     for (auto& t : th) t.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
 }
 
 Csr csr_from_view(const amge_csr& v) {
