@@ -361,11 +361,17 @@ amge_status amge_server_stats(const amge_server* s, int32_t* queued, int32_t* in
  *                               benchmark): every level keeps only the dofs off the boundary
  *                               of the cube (rows/columns of A, rows of D and P, columns
  *                               of P and of D restricted alike), renumbered in order
+ *       AMGE_BUILD_DEVICE       set-up work on the current GPU (section 5.2.1: the local
+ *                               extensions are embarrassingly parallel): the weighted local
+ *                               problems of the first agglomeration step, one workgroup per
+ *                               agglomerate whose hexes carry different weights (with
+ *                               AMGE_BUILD_COEFFICIENT; unweighted agglomerates share the
+ *                               reference solution on either path)
  * The returned problem owns host CSR arrays for every level (amge_level layout).
  * ---------------------------------------------------------------------------------- */
 typedef struct amge_problem amge_problem;
 
-enum { AMGE_BUILD_ESSENTIAL = 1, AMGE_BUILD_COEFFICIENT = 2 };
+enum { AMGE_BUILD_ESSENTIAL = 1, AMGE_BUILD_COEFFICIENT = 2, AMGE_BUILD_DEVICE = 4 };
 amge_status amge_kuhn_build(int32_t kind, int32_t n, int32_t nlevels, const double* alpha_hex,
                             const double* beta_hex, int32_t flags, amge_problem** out);
 int32_t amge_problem_nlevels(const amge_problem* p);

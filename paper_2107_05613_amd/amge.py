@@ -231,16 +231,18 @@ def _csr_copy(c: CsrC):
     return HostCsr(nr, c.ncols, rp, ci, va)
 
 
-BUILD_ESSENTIAL, BUILD_COEFFICIENT = 1, 2
+BUILD_ESSENTIAL, BUILD_COEFFICIENT, BUILD_DEVICE = 1, 2, 4
 
 
-def build_problem(kind, n, nlevels, alpha_hex, beta_hex, extension="l2", bc="natural"):
+def build_problem(kind, n, nlevels, alpha_hex, beta_hex, extension="l2", bc="natural", device=False):
     """Structured workload (amge_kuhn_build): per level (A, D, P) as HostCsr, P None on the last.
-    extension: "l2" or "coefficient" (weighted local problems); bc: "natural" or "essential"."""
+    extension: "l2" or "coefficient" (weighted local problems); bc: "natural" or "essential";
+    device: the set-up work of AMGE_BUILD_DEVICE on the current GPU."""
     k = {"curl": CURL, "div": DIV}.get(kind, kind)
     if extension not in ("l2", "coefficient") or bc not in ("natural", "essential"):
         raise ValueError("extension must be 'l2' or 'coefficient', bc 'natural' or 'essential'")
-    flags = (BUILD_COEFFICIENT if extension == "coefficient" else 0) | (BUILD_ESSENTIAL if bc == "essential" else 0)
+    flags = ((BUILD_COEFFICIENT if extension == "coefficient" else 0) | (BUILD_ESSENTIAL if bc == "essential" else 0)
+             | (BUILD_DEVICE if device else 0))
     a = np.ascontiguousarray(alpha_hex, dtype=np.float64)
     b = np.ascontiguousarray(beta_hex, dtype=np.float64)
     if a.size != n ** 3 or b.size != n ** 3:

@@ -28,6 +28,7 @@
 #include <string>
 
 #include "common.hpp"
+#include "setup_device.hpp"
 
 namespace amge {
 namespace {
@@ -155,6 +156,78 @@ int qr_pivoted(Mat& A, Mat& Qf, std::vector<int>& piv, double tol) {
     return rank;
 }
 
+// Null space of a constraint block K_I (m x nI): pivoted Householder QR K_I^T P = Q R.
+// The constraint K_I u = g reads R^T (Q^T u) = P^T g: its first `rk` rows fix the part
+// y1 of y = Q^T u on the range (a triangular solve), the rest of y spans the null space
+// Q2 = Q(:, rk:).
+struct NullSpace {
+    int nI = 0, m = 0, rk = 0;
+    Mat R, Qf;
+    std::vector<int> piv;
+    explicit NullSpace(const Mat& KI) : nI(KI.c), m(KI.r), R(KI.c, KI.r) {
+        for (int i = 0; i < m; ++i)
+            for (int a = 0; a < nI; ++a) R(a, i) = KI(i, a);
+        rk = qr_pivoted(R, Qf, piv, 1e-12);
+    }
+    // Q1 y1 with R11^T y1 = (P^T G)(0:rk): the particular solution of minimal norm for
+    // the right-hand sides G (m x t)
+    Mat particular(const Mat& G) const {
+        Mat Y1(rk, G.c);
+        for (int t = 0; t < G.c; ++t)
+            for (int i = 0; i < rk; ++i) {
+                double s = G(piv[i], t);
+                for (int l = 0; l < i; ++l) s -= R(l, i) * Y1(l, t);
+                Y1(i, t) = s / R(i, i);
+            }
+        Mat U(nI, G.c);
+        for (int a = 0; a < nI; ++a)
+            for (int t = 0; t < G.c; ++t) {
+                double s = 0;
+                for (int i = 0; i < rk; ++i) s += Qf(a, i) * Y1(i, t);
+                U(a, t) = s;
+            }
+        return U;
+    }
+    Mat Q2() const {
+        Mat Z(nI, nI - rk);
+        for (int a = 0; a < nI; ++a)
+            for (int j = 0; j < nI - rk; ++j) Z(a, j) = Qf(a, rk + j);
+        return Z;
+    }
+};
+
+// Interior / boundary split of a local problem: K_I, and G = S - K_B u_B.
+void split_constraint(const Mat& K, const std::vector<char>& intr, const Mat& S, const Mat& UB, std::vector<int>& I,
+                      std::vector<int>& B, Mat& KI, Mat& G) {
+    const int nd = K.c, m = K.r, nrhs = S.c;
+    I.clear();
+    B.clear();
+    for (int j = 0; j < nd; ++j) (intr[j] ? I : B).push_back(j);
+    KI = Mat(m, (int)I.size());
+    G = Mat(m, nrhs);
+    for (int i = 0; i < m; ++i) {
+        for (size_t a = 0; a < I.size(); ++a) KI(i, (int)a) = K(i, I[a]);
+        for (int t = 0; t < nrhs; ++t) {
+            double v = S(i, t);
+            for (size_t b = 0; b < B.size(); ++b) v -= K(i, B[b]) * UB((int)b, t);
+            G(i, t) = v;
+        }
+    }
+}
+
+// Every constraint row (the dependent ones too) must hold for the extension U.
+void check_consistent(const Mat& KI, const Mat& G, const Mat& U) {
+    double res = 0, gn = 0;
+    for (int i = 0; i < KI.r; ++i)
+        for (int t = 0; t < G.c; ++t) {
+            double v = -G(i, t);
+            for (int a = 0; a < KI.c; ++a) v += KI(i, a) * U(a, t);
+            res = std::max(res, std::fabs(v));
+            gn = std::max(gn, std::fabs(G(i, t)));
+        }
+    if (res > 1e-10 * std::max(1.0, gn)) fail(AMGE_ERR_ARG, "inconsistent extension constraint");
+}
+
 // Minimum-mass extension on one entity (eqs. (3.6), (3.8) read as the optimality
 // conditions of: minimise the mass of the extension subject to the derivative
 // constraint on the entity's interior, its trace on the boundary fixed).
@@ -164,62 +237,31 @@ int qr_pivoted(Mat& A, Mat& Qf, std::vector<int>& piv, double tol) {
 //   intr  interior mask (nd)
 //   S     right-hand sides of the constraint (m x nrhs)
 //   UB    boundary values (nB x nrhs), in closure order of the non-interior dofs
-// Returns U_I (nI x nrhs).  Null-space method: with K_I^T P = Q R (pivoted QR), the
-// constraint K_I u = g reads R^T (Q^T u) = P^T g; its first `rank` rows fix the range
-// part y1 of y = Q^T u (triangular solve), and the null-space part y2 minimises the
-// mass: (Q2^T M_II Q2) y2 = -Q2^T (M_II Q1 y1 + M_IB u_B).  The constraint then holds to
-// rounding whatever the conditioning of the mass (coefficient-weighted masses).
+// Returns U_I (nI x nrhs).  Null-space method: the particular solution on the range of
+// K_I^T, then the mass minimised over its null space Q2: (Q2^T M_II Q2) y2 =
+// -Q2^T (M_II u_p + M_IB u_B).  The constraint then holds to rounding whatever the
+// conditioning of the mass (coefficient-weighted masses).
 Mat extend(const Mat& M, const Mat& K, const std::vector<char>& intr, const Mat& S, const Mat& UB) {
-    int nd = K.c, m = K.r, nrhs = S.c;
     std::vector<int> I, B;
-    for (int j = 0; j < nd; ++j) (intr[j] ? I : B).push_back(j);
-    int nI = (int)I.size();
-    Mat KI(m, nI), G(m, nrhs);
-    for (int i = 0; i < m; ++i) {
-        for (int a = 0; a < nI; ++a) KI(i, a) = K(i, I[a]);
-        for (int t = 0; t < nrhs; ++t) {
-            double s = S(i, t);
-            for (size_t b = 0; b < B.size(); ++b) s -= K(i, B[b]) * UB((int)b, t);
-            G(i, t) = s;
-        }
-    }
-    Mat R(nI, m), Qf;
-    for (int i = 0; i < m; ++i)
-        for (int a = 0; a < nI; ++a) R(a, i) = KI(i, a);
-    std::vector<int> piv;
-    const int rk = qr_pivoted(R, Qf, piv, 1e-12);
-    // y1: R11^T y1 = (P^T g)(0 : rk), forward substitution
-    Mat Y1(rk, nrhs);
-    for (int t = 0; t < nrhs; ++t)
-        for (int i = 0; i < rk; ++i) {
-            double s = G(piv[i], t);
-            for (int l = 0; l < i; ++l) s -= R(l, i) * Y1(l, t);
-            Y1(i, t) = s / R(i, i);
-        }
-    Mat U(nI, nrhs);   // particular solution Q1 y1
-    for (int a = 0; a < nI; ++a)
-        for (int t = 0; t < nrhs; ++t) {
-            double s = 0;
-            for (int i = 0; i < rk; ++i) s += Qf(a, i) * Y1(i, t);
-            U(a, t) = s;
-        }
-    const int nz = nI - rk;
+    Mat KI, G;
+    split_constraint(K, intr, S, UB, I, B, KI, G);
+    const int nI = (int)I.size(), nrhs = S.c;
+    NullSpace ns(KI);
+    Mat U = ns.particular(G);
+    const int nz = nI - ns.rk;
     if (nz > 0) {
         if (M.r == 0) fail(AMGE_ERR_ARG, "extension not determined by its constraint");
-        // Q2 = Qf(:, rk:), reduced mass Q2^T M_II Q2 and right-hand side
         Mat MII(nI, nI), F(nI, nrhs);
         for (int a = 0; a < nI; ++a) {
             for (int b = 0; b < nI; ++b) MII(a, b) = M(I[a], I[b]);
             for (int t = 0; t < nrhs; ++t) {
-                double s = 0;
-                for (size_t b = 0; b < B.size(); ++b) s += M(I[a], B[b]) * UB((int)b, t);
-                for (int b = 0; b < nI; ++b) s += M(I[a], I[b]) * U(b, t);
-                F(a, t) = s;   // M_II u_p + M_IB u_B
+                double v = 0;
+                for (size_t b = 0; b < B.size(); ++b) v += M(I[a], B[b]) * UB((int)b, t);
+                for (int b = 0; b < nI; ++b) v += M(I[a], I[b]) * U(b, t);
+                F(a, t) = v;   // M_II u_p + M_IB u_B
             }
         }
-        Mat Q2(nI, nz);
-        for (int a = 0; a < nI; ++a)
-            for (int j = 0; j < nz; ++j) Q2(a, j) = Qf(a, rk + j);
+        Mat Q2 = ns.Q2();
         Mat Red = tmatmul(Q2, matmul(MII, Q2));
         Mat W2 = tmatmul(Q2, F);
         for (double& v : W2.a) v = -v;
@@ -229,16 +271,7 @@ Mat extend(const Mat& M, const Mat& K, const std::vector<char>& intr, const Mat&
         for (int a = 0; a < nI; ++a)
             for (int t = 0; t < nrhs; ++t) U(a, t) += Z(a, t);
     }
-    // consistency: every constraint row (the dependent ones too) must hold
-    double res = 0, gn = 0;
-    for (int i = 0; i < m; ++i)
-        for (int t = 0; t < nrhs; ++t) {
-            double s = -G(i, t);
-            for (int a = 0; a < nI; ++a) s += KI(i, a) * U(a, t);
-            res = std::max(res, std::fabs(s));
-            gn = std::max(gn, std::fabs(G(i, t)));
-        }
-    if (res > 1e-10 * std::max(1.0, gn)) fail(AMGE_ERR_ARG, "inconsistent extension constraint");
+    check_consistent(KI, G, U);
     return U;
 }
 
@@ -893,6 +926,204 @@ CubeElem next_elem(const Block& blk, const LocalP& L, const Unit& U, bool need_n
     return el;
 }
 
+// ------------------------------------------------------------------ batched weighted local problems
+// The weighted local problems of the first agglomeration step.  Every agglomerate of the
+// step has the reference block's topology, constraints, PV traces and face extensions
+// (no cell weight enters those); its RT and ND masses are sums over its eight hexes
+// ("slots") of the slot's unit mass times the hex weight, M(w) = sum_s w_s M_s.  So the
+// null space of each constraint, the particular solution (RT) and every slot's reduced
+// matrices are formed once, and an agglomerate's problem reduces to weighted sums of
+// small matrices and one Cholesky solve:
+//   RT:  u = u_p + Q2 y,  (sum_s w_s H_s) y = -(sum_s w_s h_s),
+//        H_s = Q2^T M_s,II Q2,  h_s = Q2^T (M_s,II u_p + M_s,IB u_B);
+//        next-level RT element  L^T M(w) L = sum_s w_s C_s + h(w)^T y  (the Schur form:
+//        C_s = L_p^T M_s L_p with L_p the particular local prolongator).
+//   ND (H(curl)): the constraint's right-hand side is the coarse curl of the RT
+//        solution, G = u_I C^H - G0, so u_p = Wn G varies; the ND mass M(w) is formed
+//        explicitly (26 x 26) and minimised over its null space Q2n.
+// This is what the device path (setup_device.hip) computes per agglomerate.
+struct KuhnPlan {
+    bool nd = false;
+    std::vector<int> fI, eI;     // interior block faces / edges (constraint order)
+    int nI = 0, nz = 0;          // RT interior faces, null-space dimension
+    Mat up, Q2;                  // nI x 6, nI x nz
+    Mat H[8], h[8], C[8];        // per slot: nz x nz, nz x 6, 6 x 6
+    int nIn = 0, nzn = 0;        // ND interior edges, null-space dimension
+    Mat CH, G0, Wn, Q2n;         // 6 x 12, nI x 12, nIn x nI, nIn x nzn
+    Mat Mn[8], Fn[8], Cn[8];     // per slot: nIn x nIn, nIn x 12, 12 x 12
+    LocalP ref;                  // unit-weight solution: the rows every agglomerate shares
+    CubeElem ref_el;             // unit-weight next element (its trace masses are shared)
+};
+
+KuhnPlan kuhn_plan(double h, const Kuhn& B, const Unit& U, bool need_nd) {
+    KuhnPlan P;
+    P.nd = need_nd;
+    Block blk = kuhn_block(h, B, U);
+    P.ref = solve_block(blk, U, need_nd);
+    P.ref_el = next_elem(blk, P.ref, U, need_nd);
+    const Cubes& cc = U.cc;
+    Csr CHs = cc.curl(), DH = cc.div();
+    // RT: constraint div u = D^H[T,F] PV_T on every cell, interior = faces inside the cube
+    std::vector<char> fin(blk.nF);
+    for (int f = 0; f < blk.nF; ++f) fin[f] = blk.fo[f].dim == 3;
+    Mat K(blk.nC, blk.nF), S(blk.nC, 6);
+    for (int t = 0; t < blk.nC; ++t)
+        for (int k = blk.Dv.rowptr[t]; k < blk.Dv.rowptr[t + 1]; ++k) K(t, blk.Dv.col[k]) = blk.Dv.val[k];
+    for (int F = 0; F < 6; ++F) {
+        double dh = 0;
+        for (int k = DH.rowptr[0]; k < DH.rowptr[1]; ++k) if (DH.col[k] == F) dh = DH.val[k];
+        for (int t = 0; t < blk.nC; ++t) S(t, F) = dh * blk.co[t].ratio;
+    }
+    std::vector<int> fB;
+    for (int f = 0; f < blk.nF; ++f) (fin[f] ? P.fI : fB).push_back(f);
+    Mat UB((int)fB.size(), 6);
+    for (size_t b = 0; b < fB.size(); ++b)
+        for (int F = 0; F < 6; ++F) UB((int)b, F) = P.ref.rt(fB[b], F);
+    Mat KI, G;
+    std::vector<int> Iv, Bv;
+    split_constraint(K, fin, S, UB, Iv, Bv, KI, G);
+    NullSpace ns(KI);
+    P.nI = ns.nI;
+    P.nz = ns.nI - ns.rk;
+    P.up = ns.particular(G);
+    P.Q2 = ns.Q2();
+    // per slot (hex s of the block): unit RT and ND masses
+    Block bs[8];
+    for (int sl = 0; sl < 8; ++sl) {
+        std::array<double, 2> w[8];
+        for (int i = 0; i < 8; ++i) w[i] = {i == sl ? 1.0 : 0.0, i == sl ? 1.0 : 0.0};
+        bs[sl] = kuhn_block(h, B, U, w);
+    }
+    // boundary / interior parts of the particular local prolongator (RT)
+    Mat Lp = P.ref.rt;
+    for (int a = 0; a < P.nI; ++a)
+        for (int F = 0; F < 6; ++F) Lp(P.fI[a], F) = P.up(a, F);
+    for (int sl = 0; sl < 8; ++sl) {
+        const Mat& M = bs[sl].Mrt;
+        Mat MII(P.nI, P.nI), Fs(P.nI, 6);
+        for (int a = 0; a < P.nI; ++a) {
+            for (int b = 0; b < P.nI; ++b) MII(a, b) = M(P.fI[a], P.fI[b]);
+            for (int F = 0; F < 6; ++F) {
+                double v = 0;
+                for (size_t b = 0; b < fB.size(); ++b) v += M(P.fI[a], fB[b]) * UB((int)b, F);
+                for (int b = 0; b < P.nI; ++b) v += MII(a, b) * P.up(b, F);
+                Fs(a, F) = v;   // M_II u_p + M_IB u_B
+            }
+        }
+        P.H[sl] = tmatmul(P.Q2, matmul(MII, P.Q2));
+        P.h[sl] = tmatmul(P.Q2, Fs);
+        P.C[sl] = tmatmul(Lp, matmul(M, Lp));
+    }
+    if (!need_nd) return P;
+    // ND: constraint curl u = sum_F C^H[F,E] (RT basis of F) on the faces inside the cube,
+    // interior = edges inside the cube; the boundary edges carry the shared PV and face
+    // extension values
+    P.CH = Mat(6, 12);
+    for (int F = 0; F < 6; ++F)
+        for (int k = CHs.rowptr[F]; k < CHs.rowptr[F + 1]; ++k) P.CH(F, CHs.col[k]) = CHs.val[k];
+    std::vector<char> ein(blk.nE);
+    for (int e = 0; e < blk.nE; ++e) ein[e] = blk.eo[e].dim == 3;
+    Mat Kn(P.nI, blk.nE);
+    for (int r = 0; r < P.nI; ++r)
+        for (int k = blk.C.rowptr[P.fI[r]]; k < blk.C.rowptr[P.fI[r] + 1]; ++k) Kn(r, blk.C.col[k]) = blk.C.val[k];
+    std::vector<int> eB;
+    for (int e = 0; e < blk.nE; ++e) (ein[e] ? P.eI : eB).push_back(e);
+    Mat UBn((int)eB.size(), 12);
+    for (size_t b = 0; b < eB.size(); ++b)
+        for (int E = 0; E < 12; ++E) UBn((int)b, E) = P.ref.nd(eB[b], E);
+    Mat KnI, G0neg;
+    Mat zeroS(P.nI, 12);
+    split_constraint(Kn, ein, zeroS, UBn, Iv, Bv, KnI, G0neg);   // G0neg = -K_B u_B
+    P.G0 = G0neg;
+    for (double& v : P.G0.a) v = -v;                             // G0 = K_B u_B
+    NullSpace nsn(KnI);
+    P.nIn = nsn.nI;
+    P.nzn = nsn.nI - nsn.rk;
+    Mat Id(P.nI, P.nI);
+    for (int i = 0; i < P.nI; ++i) Id(i, i) = 1.0;
+    P.Wn = nsn.particular(Id);                                   // u_p = Wn G
+    P.Q2n = nsn.Q2();
+    for (int sl = 0; sl < 8; ++sl) {
+        const Mat& M = bs[sl].Mnd;
+        P.Mn[sl] = Mat(P.nIn, P.nIn);
+        P.Fn[sl] = Mat(P.nIn, 12);
+        P.Cn[sl] = Mat(12, 12);
+        for (int a = 0; a < P.nIn; ++a) {
+            for (int b = 0; b < P.nIn; ++b) P.Mn[sl](a, b) = M(P.eI[a], P.eI[b]);
+            for (int E = 0; E < 12; ++E) {
+                double v = 0;
+                for (size_t b = 0; b < eB.size(); ++b) v += M(P.eI[a], eB[b]) * UBn((int)b, E);
+                P.Fn[sl](a, E) = v;   // M_IB u_B
+            }
+        }
+        for (int E = 0; E < 12; ++E)
+            for (int E2 = 0; E2 < 12; ++E2) {
+                double v = 0;
+                for (size_t a = 0; a < eB.size(); ++a)
+                    for (size_t b = 0; b < eB.size(); ++b) v += UBn((int)a, E) * M(eB[a], eB[b]) * UBn((int)b, E2);
+                P.Cn[sl](E, E2) = v;   // u_B^T M_BB u_B
+            }
+    }
+    return P;
+}
+
+// The weighted local problems of one agglomerate (hex weights wnd / wrt per slot): its
+// local prolongator (the shared rows from the reference, the interior ones solved) and
+// next-level element.
+void kuhn_solve_one(const KuhnPlan& P, const double* wnd, const double* wrt, LocalP& L, CubeElem& el) {
+    L = P.ref;
+    el = P.ref_el;
+    Mat Hw(P.nz, P.nz), hw(P.nz, 6), Cw(6, 6);
+    for (int sl = 0; sl < 8; ++sl) {
+        for (size_t i = 0; i < Hw.a.size(); ++i) Hw.a[i] += wrt[sl] * P.H[sl].a[i];
+        for (size_t i = 0; i < hw.a.size(); ++i) hw.a[i] += wrt[sl] * P.h[sl].a[i];
+        for (size_t i = 0; i < Cw.a.size(); ++i) Cw.a[i] += wrt[sl] * P.C[sl].a[i];
+    }
+    Mat y = hw;
+    for (double& v : y.a) v = -v;
+    if (P.nz > 0) {
+        if (!cholesky(Hw)) fail(AMGE_ERR_NOT_SPD, "local mass not positive definite on the null space");
+        chol_solve(Hw, y);
+    }
+    Mat u = P.up;
+    if (P.nz > 0) {
+        Mat Z = matmul(P.Q2, y);
+        for (size_t i = 0; i < u.a.size(); ++i) u.a[i] += Z.a[i];
+    }
+    for (int a = 0; a < P.nI; ++a)
+        for (int F = 0; F < 6; ++F) L.rt(P.fI[a], F) = u(a, F);
+    Mat hy = tmatmul(hw, y);
+    for (size_t i = 0; i < Cw.a.size(); ++i) el.rt.a[i] = Cw.a[i] + hy.a[i];
+    if (!P.nd) return;
+    // ND: G = u C^H - G0, u_p = Wn G, mass M(w) minimised over the null space
+    Mat G = matmul(u, P.CH);
+    for (size_t i = 0; i < G.a.size(); ++i) G.a[i] -= P.G0.a[i];
+    Mat un = matmul(P.Wn, G);
+    Mat Mw(P.nIn, P.nIn), Fw(P.nIn, 12), Cnw(12, 12);
+    for (int sl = 0; sl < 8; ++sl) {
+        for (size_t i = 0; i < Mw.a.size(); ++i) Mw.a[i] += wnd[sl] * P.Mn[sl].a[i];
+        for (size_t i = 0; i < Fw.a.size(); ++i) Fw.a[i] += wnd[sl] * P.Fn[sl].a[i];
+        for (size_t i = 0; i < Cnw.a.size(); ++i) Cnw.a[i] += wnd[sl] * P.Cn[sl].a[i];
+    }
+    if (P.nzn > 0) {
+        Mat R = matmul(Mw, un);
+        for (size_t i = 0; i < R.a.size(); ++i) R.a[i] += Fw.a[i];
+        Mat yn = tmatmul(P.Q2n, R);
+        for (double& v : yn.a) v = -v;
+        Mat Hn = tmatmul(P.Q2n, matmul(Mw, P.Q2n));
+        if (!cholesky(Hn)) fail(AMGE_ERR_NOT_SPD, "local mass not positive definite on the null space");
+        chol_solve(Hn, yn);
+        Mat Z = matmul(P.Q2n, yn);
+        for (size_t i = 0; i < un.a.size(); ++i) un.a[i] += Z.a[i];
+    }
+    for (int a = 0; a < P.nIn; ++a)
+        for (int E = 0; E < 12; ++E) L.nd(P.eI[a], E) = un(a, E);
+    // el.nd = u^T M_II u + u^T F + F^T u + u_B^T M_BB u_B with M = M(w)
+    Mat uMu = tmatmul(un, matmul(Mw, un)), uF = tmatmul(un, Fw);
+    for (int E = 0; E < 12; ++E)
+        for (int E2 = 0; E2 < 12; ++E2) el.nd(E, E2) = uMu(E, E2) + uF(E, E2) + uF(E2, E) + Cnw(E, E2);
+}
+
 // ------------------------------------------------------------------ global assembly
 struct Problem {
     int kind, n, nlevels;
@@ -1133,7 +1364,8 @@ Problem build(int kind, int n, int nlevels, const double* alpha, const double* b
     if (n < 1 || nlevels < 1) fail(AMGE_ERR_ARG, "n and nlevels must be positive");
     if (nlevels > 1 && (n % (1 << (nlevels - 1))) != 0) fail(AMGE_ERR_ARG, "n not divisible by 2^(nlevels-1)");
     if (!alpha || !beta) fail(AMGE_ERR_ARG, "null coefficient array");
-    if (flags & ~(AMGE_BUILD_ESSENTIAL | AMGE_BUILD_COEFFICIENT)) fail(AMGE_ERR_ARG, "unknown build flags");
+    if (flags & ~(AMGE_BUILD_ESSENTIAL | AMGE_BUILD_COEFFICIENT | AMGE_BUILD_DEVICE))
+        fail(AMGE_ERR_ARG, "unknown build flags");
     for (int64_t i = 0; i < (int64_t)n * n * n; ++i)
         if (!(alpha[i] > 0) || !(beta[i] > 0) || !std::isfinite(alpha[i]) || !std::isfinite(beta[i]))
             fail(AMGE_ERR_ARG, "coefficients must be positive and finite");
@@ -1196,17 +1428,63 @@ Problem build(int kind, int n, int nlevels, const double* alpha, const double* b
         }
         std::vector<LocalP> Ls(todo.size());
         std::vector<CubeElem> nex(todo.size());
-        parallel_for((int64_t)todo.size(), [&](int64_t s, int64_t e) {
-            for (int64_t u = s; u < e; ++u) {
-                const CellW* c[8];
-                children(n, todo[u], c);
-                std::array<double, 2> w[8];
-                for (int i = 0; i < 8; ++i) w[i] = {c[i]->nd, c[i]->rt};
-                Block b2 = kuhn_block(1.0 / n, B, U, w);
-                Ls[u] = solve_block(b2, U, curl);
-                nex[u] = next_elem(b2, Ls[u], U, curl);
+        if (!todo.empty()) {
+            // the shared plan of the step, then every non-uniform agglomerate's weighted
+            // problems from its hex weights: on the host, or (AMGE_BUILD_DEVICE) one
+            // workgroup per agglomerate on the GPU
+            const KuhnPlan plan = kuhn_plan(1.0 / n, B, U, curl);
+            const int64_t na = (int64_t)todo.size();
+            if (flags & AMGE_BUILD_DEVICE) {
+                std::vector<double> w((size_t)na * 16);
+                for (int64_t u = 0; u < na; ++u) {
+                    const CellW* c[8];
+                    children(n, todo[u], c);
+                    for (int i = 0; i < 8; ++i) {
+                        w[u * 16 + i] = c[i]->nd;
+                        w[u * 16 + 8 + i] = c[i]->rt;
+                    }
+                }
+                auto cat = [](const Mat* m, int k) {
+                    std::vector<double> v;
+                    for (int i = 0; i < k; ++i) v.insert(v.end(), m[i].a.begin(), m[i].a.end());
+                    return v;
+                };
+                const std::vector<double> H = cat(plan.H, 8), h = cat(plan.h, 8), C = cat(plan.C, 8);
+                const std::vector<double> Mn = curl ? cat(plan.Mn, 8) : std::vector<double>(),
+                                          Fn = curl ? cat(plan.Fn, 8) : std::vector<double>(),
+                                          Cn = curl ? cat(plan.Cn, 8) : std::vector<double>();
+                KuhnPlanView v{curl ? 1 : 0, plan.nI, plan.nz, plan.nIn, plan.nzn, H.data(), h.data(), C.data(),
+                               plan.up.a.data(), plan.Q2.a.data(), plan.CH.a.data(), plan.G0.a.data(),
+                               plan.Wn.a.data(), plan.Q2n.a.data(), Mn.data(), Fn.data(), Cn.data()};
+                std::vector<double> Uo((size_t)na * plan.nI * 6), er((size_t)na * 36);
+                std::vector<double> Uno(curl ? (size_t)na * plan.nIn * 12 : 1), en(curl ? (size_t)na * 144 : 1);
+                kuhn_local_device(v, w.data(), na, Uo.data(), er.data(), Uno.data(), en.data());
+                parallel_for(na, [&](int64_t s, int64_t e) {
+                    for (int64_t u = s; u < e; ++u) {
+                        Ls[u] = plan.ref;
+                        nex[u] = plan.ref_el;
+                        for (int a = 0; a < plan.nI; ++a)
+                            for (int F = 0; F < 6; ++F) Ls[u].rt(plan.fI[a], F) = Uo[((size_t)u * plan.nI + a) * 6 + F];
+                        std::copy(er.begin() + u * 36, er.begin() + (u + 1) * 36, nex[u].rt.a.begin());
+                        if (!curl) continue;
+                        for (int a = 0; a < plan.nIn; ++a)
+                            for (int E = 0; E < 12; ++E)
+                                Ls[u].nd(plan.eI[a], E) = Uno[((size_t)u * plan.nIn + a) * 12 + E];
+                        std::copy(en.begin() + u * 144, en.begin() + (u + 1) * 144, nex[u].nd.a.begin());
+                    }
+                });
+            } else {
+                parallel_for(na, [&](int64_t s, int64_t e) {
+                    for (int64_t u = s; u < e; ++u) {
+                        const CellW* c[8];
+                        children(n, todo[u], c);
+                        double wnd[8], wrt[8];
+                        for (int i = 0; i < 8; ++i) { wnd[i] = c[i]->nd; wrt[i] = c[i]->rt; }
+                        kuhn_solve_one(plan, wnd, wrt, Ls[u], nex[u]);
+                    }
+                });
             }
-        });
+        }
         int32_t nfine = curl ? (int32_t)K.E.size() : (int32_t)K.F.size();
         auto fine_index = [&](const int q[3], int i) -> int32_t {
             int64_t off[3] = {2 * q[0], 2 * q[1], 2 * q[2]};
