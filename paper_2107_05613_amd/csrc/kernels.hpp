@@ -546,5 +546,74 @@ __global__ void k_pcg_init(const double* __restrict__ part, PcgStatus* __restric
     }
 }
 
+// ---- set-up: entry arrays of the sliced ELL from a device copy of the CSR matrix.
+// One wave per slice; the row part of the layout (slot -> row map srow, slice offsets
+// sptr) comes from the host.  Lane l of a slice serves entries t = l % K (mod K) of the
+// row in slot l / K, so for every chunk c of 64 consecutive slots the wave writes
+// slots sptr + 64 c .. sptr + 64 c + 63 at once.
+
+// Column range of every slice: cbase = smallest column (0 for an empty slice); *wide
+// set if some slice spans more than 65536 consecutive columns.
+__global__ void __launch_bounds__(BLOCK)
+k_slice_range(int ns, int K, const int* __restrict__ srow, const int* __restrict__ rowptr,
+              const int* __restrict__ col, int* __restrict__ cbase, int* __restrict__ wide) {
+    const int w = blockIdx.x * WAVES + threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (w >= ns) return;
+    const int R = 64 / K;
+    const int r = srow[(int64_t)w * R + lane / K];
+    int lo = 0x7fffffff, hi = -1;
+    if (r >= 0)
+        for (int t = rowptr[r] + lane % K; t < rowptr[r + 1]; t += K) {
+            lo = min(lo, col[t]);
+            hi = max(hi, col[t]);
+        }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, __shfl_xor(lo, off, 64));
+        hi = max(hi, __shfl_xor(hi, off, 64));
+    }
+    if (lane == 0) {
+        cbase[w] = hi < 0 ? 0 : lo;
+        if (hi >= 0 && hi - lo > 65535) atomicOr(wide, 1);
+    }
+}
+
+// Entry arrays: value matrices write the columns (ci, or c16 offsets from cbase) and the
+// values (v64 and/or v32, rounded to nearest); incidence matrices write column | sign
+// << 31 to ent and set *bad on an entry other than +-1.  Padding: column 0, value 0,
+// incidence word 0xffffffff.
+template <bool INC>
+__global__ void __launch_bounds__(BLOCK)
+k_sell_fill(int ns, int K, const int* __restrict__ sptr, const int* __restrict__ srow, const int* __restrict__ rowptr,
+            const int* __restrict__ col, const double* __restrict__ val, const int* __restrict__ cbase,
+            int* __restrict__ ci, uint16_t* __restrict__ c16, double* __restrict__ v64, float* __restrict__ v32,
+            uint32_t* __restrict__ ent, int* __restrict__ bad) {
+    const int w = blockIdx.x * WAVES + threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (w >= ns) return;
+    const int R = 64 / K, j = lane % K;
+    const int r = srow[(int64_t)w * R + lane / K];
+    const int b0 = r >= 0 ? rowptr[r] : 0;
+    const int len = r >= 0 ? rowptr[r + 1] - b0 : 0;
+    const int64_t base = sptr[w];
+    const int width = (sptr[w + 1] - sptr[w]) / 64;
+    const int cb = c16 ? cbase[w] : 0;
+    for (int c = 0; c < width; ++c) {
+        const int t = c * K + j;
+        const int64_t idx = base + (int64_t)c * 64 + lane;
+        const bool in = t < len;
+        const int cc = in ? col[b0 + t] : 0;
+        const double v = in ? val[b0 + t] : 0.0;
+        if (INC) {
+            if (in && v != 1.0 && v != -1.0) *bad = 1;
+            ent[idx] = in ? ((uint32_t)cc | (v < 0 ? 0x80000000u : 0u)) : 0xffffffffu;
+        } else {
+            if (c16) c16[idx] = (uint16_t)(in ? cc - cb : 0);
+            else ci[idx] = cc;
+            if (v64) v64[idx] = v;
+            if (v32) v32[idx] = (float)v;
+        }
+    }
+}
+
 }  // namespace dev
 }  // namespace amge

@@ -10,40 +10,51 @@ namespace amge {
 
 // 16-bit column offsets on (default); AMGE_INDEX32=1 keeps 32-bit indices everywhere.
 bool compact_indices() {
-    static int v = -1;
-    if (v < 0) {
-        const char* e = getenv("AMGE_INDEX32");
-        v = (e && *e && *e != '0') ? 0 : 1;
-    }
-    return v == 1;
+    const char* e = getenv("AMGE_INDEX32");   // read per set-up call
+    return !(e && *e && *e != '0');
 }
 
-HostSell make_sell(const Csr& A, bool incidence, int K, const std::vector<int>* lead) {
+bool device_layouts() {
+    const char* e = getenv("AMGE_HOST_LAYOUT");   // read per set-up call
+    return !(e && *e && *e != '0');
+}
+
+HostSell sell_rows(const Csr& A, int K, const std::vector<int>* lead) {
+    if (K < 1 || K > 64 || 64 % K) fail(AMGE_ERR_ARG, "lanes per row must divide 64");
     const int R = 64 / K;
     HostSell h;
     h.K = K;
     h.nslices = (A.nrows + R - 1) / R;
     h.srow.assign((size_t)h.nslices * R, -1);
     const int win = 8 * R;
-    std::vector<int> order;
     auto len = [&](int r) { return A.rowptr[r + 1] - A.rowptr[r]; };
-    for (int w0 = 0; w0 < A.nrows; w0 += win) {
-        int w1 = std::min(A.nrows, w0 + win);
-        order.resize(w1 - w0);
-        std::iota(order.begin(), order.end(), w0);
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return len(a) > len(b); });
-        for (int i = 0; i < w1 - w0; ++i) h.srow[w0 + i] = order[i];
-    }
+    // rows sorted by decreasing length (stable) inside windows of 8 slices
+    const int64_t nwin = (A.nrows + win - 1) / win;
+    parallel_for(nwin, [&](int64_t a, int64_t b) {
+        std::vector<int> order;
+        for (int64_t wi = a; wi < b; ++wi) {
+            const int w0 = (int)(wi * win), w1 = std::min(A.nrows, w0 + win);
+            order.resize(w1 - w0);
+            std::iota(order.begin(), order.end(), w0);
+            std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return len(x) > len(y); });
+            for (int i = 0; i < w1 - w0; ++i) h.srow[w0 + i] = order[i];
+        }
+    });
+    std::vector<int64_t> width(h.nslices);
+    parallel_for(h.nslices, [&](int64_t a, int64_t b) {
+        for (int64_t sl = a; sl < b; ++sl) {
+            int mx = 0;
+            for (int l = 0; l < R; ++l) {
+                const int r = h.srow[(size_t)sl * R + l];
+                if (r >= 0) mx = std::max(mx, len(r));
+            }
+            width[sl] = (mx + K - 1) / K;
+        }
+    });
     h.sptr.assign(h.nslices + 1, 0);
     for (int sl = 0; sl < h.nslices; ++sl) {
-        int mx = 0;
-        for (int l = 0; l < R; ++l) {
-            int r = h.srow[(size_t)sl * R + l];
-            if (r >= 0) mx = std::max(mx, len(r));
-        }
-        int64_t width = (mx + K - 1) / K;
-        if ((int64_t)h.sptr[sl] + width * 64 > INT32_MAX) fail(AMGE_ERR_SHAPE, "matrix too large for int32 offsets");
-        h.sptr[sl + 1] = h.sptr[sl] + (int)(width * 64);
+        if ((int64_t)h.sptr[sl] + width[sl] * 64 > INT32_MAX) fail(AMGE_ERR_SHAPE, "matrix too large for int32 offsets");
+        h.sptr[sl + 1] = h.sptr[sl] + (int)(width[sl] * 64);
     }
     if (lead) {
         if ((int)lead->size() != A.nrows) fail(AMGE_ERR_SHAPE, "split counts: one per row needed");
@@ -56,6 +67,13 @@ HostSell make_sell(const Csr& A, bool incidence, int K, const std::vector<int>* 
             h.lead[i] = (uint16_t)c;
         }
     }
+    return h;
+}
+
+HostSell make_sell(const Csr& A, bool incidence, int K, const std::vector<int>* lead) {
+    HostSell h = sell_rows(A, K, lead);
+    const int R = 64 / K;
+    auto len = [&](int r) { return A.rowptr[r + 1] - A.rowptr[r]; };
     const size_t stored = h.sptr[h.nslices];
     if (incidence) h.ent.assign(stored, 0xffffffffu);
     else {

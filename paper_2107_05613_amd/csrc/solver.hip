@@ -38,10 +38,94 @@ T* upload(amge_hierarchy* H, const T* src, size_t n, hipStream_t s) {
     return d;
 }
 
+// A host CSR matrix copied to the device once, for the layout kernels of set-up (every
+// candidate layout of the tuner and the final one are filled from it); the copy lives
+// in its own allocation owner (the caller's allocator, if any) and goes with it.
+struct Staged {
+    amge_hierarchy mem;
+    const Csr* A = nullptr;
+    int32_t *rowptr = nullptr, *col = nullptr;
+    double* val = nullptr;
+    int* flag = nullptr;
+};
+
+std::unique_ptr<Staged> stage(const amge_opts& opts, const Csr& A, hipStream_t s) {
+    auto st = std::make_unique<Staged>();
+    st->mem.opts = opts;
+    st->A = &A;
+    st->rowptr = upload(&st->mem, A.rowptr.data(), A.rowptr.size(), s);
+    st->col = upload(&st->mem, A.col.data(), A.col.size(), s);
+    st->val = upload(&st->mem, A.val.data(), A.val.size(), s);
+    st->flag = st->mem.alloc<int>(1);
+    return st;
+}
+
+// Entry arrays of layout h (its row part) on the device from the staged matrix; srow
+// is the layout's own slot -> row map (rows of st->A).  Value matrices: c16 + cbase when
+// every slice spans < 65536 columns (and compact indices are on), else ci; v64 / v32 as
+// requested.  Incidence matrices: ent.
+struct DevEntries {
+    int *ci = nullptr, *cbase = nullptr;
+    uint16_t* c16 = nullptr;
+    uint32_t* ent = nullptr;
+    double* v64 = nullptr;
+    float* v32 = nullptr;
+};
+
+DevEntries fill_entries(amge_hierarchy* H, const Staged& st, const HostSell& h, const int* d_sptr, bool incidence,
+                        bool f32, bool f64, hipStream_t s) {
+    DevEntries e;
+    const size_t stored = h.sptr[h.nslices];
+    const int ns = h.nslices;
+    amge_hierarchy tmp;
+    tmp.opts = H->opts;
+    const int* srow = upload(&tmp, h.srow.data(), h.srow.size(), s);
+    const unsigned grid = (unsigned)((ns + dev::WAVES - 1) / dev::WAVES);
+    int flag = 0;
+    HIPCHECK(hipMemsetAsync(st.flag, 0, sizeof(int), s));
+    if (incidence) {
+        e.ent = H->alloc<uint32_t>(stored);
+        if (grid)
+            dev::k_sell_fill<true><<<grid, dev::BLOCK, 0, s>>>(ns, h.K, d_sptr, srow, st.rowptr, st.col, st.val,
+                                                                nullptr, nullptr, nullptr, nullptr, nullptr, e.ent,
+                                                                st.flag);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipMemcpyAsync(&flag, st.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        if (flag) fail(AMGE_ERR_ARG, "derivative matrix entries must be +-1");
+        return e;
+    }
+    int* cb = tmp.alloc<int>(ns);
+    if (grid)
+        dev::k_slice_range<<<grid, dev::BLOCK, 0, s>>>(ns, h.K, srow, st.rowptr, st.col, cb, st.flag);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(&flag, st.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (!flag && compact_indices()) {
+        e.cbase = H->alloc<int>(ns);
+        HIPCHECK(hipMemcpyAsync(e.cbase, cb, sizeof(int) * std::max(ns, 1), hipMemcpyDeviceToDevice, s));
+        e.c16 = H->alloc<uint16_t>(stored);
+    } else {
+        e.ci = H->alloc<int>(stored);
+    }
+    if (f64) e.v64 = H->alloc<double>(stored);
+    if (f32) e.v32 = H->alloc<float>(stored);
+    if (grid)
+        dev::k_sell_fill<false><<<grid, dev::BLOCK, 0, s>>>(ns, h.K, d_sptr, srow, st.rowptr, st.col, st.val, e.cbase,
+                                                             e.ci, e.c16, e.v64, e.v32, nullptr, st.flag);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(s));   // tmp's buffers are freed on return
+    return e;
+}
+
 // rowmap (optional): global row of each row of A (A holds a subset of a matrix's rows).
+// st (optional): A staged on the device; staged here when absent.
 DSell upload_sell(amge_hierarchy* H, const Csr& A, bool incidence, int K, hipStream_t s,
-                  const std::vector<int>* lead = nullptr, const std::vector<int>* rowmap = nullptr) {
-    HostSell h = make_sell(A, incidence, K, lead);
+                  const std::vector<int>* lead = nullptr, const std::vector<int>* rowmap = nullptr,
+                  const Staged* st = nullptr) {
+    const bool on_dev = device_layouts();
+    HostSell h = on_dev ? sell_rows(A, K, lead) : make_sell(A, incidence, K, lead);
+    const std::vector<int> local_srow = rowmap && on_dev ? h.srow : std::vector<int>();
     if (rowmap)
         for (int& r : h.srow)
             if (r >= 0) r = (*rowmap)[r];
@@ -60,6 +144,27 @@ DSell upload_sell(amge_hierarchy* H, const Csr& A, bool incidence, int K, hipStr
     d.deep = !incidence && K <= 8 && A.nnz() >= (1 << 23) && A.nnz() >= 12 * (int64_t)K * A.nrows;
     d.sptr = upload(H, h.sptr.data(), h.sptr.size(), s);
     d.srow = upload(H, h.srow.data(), h.srow.size(), s);
+    if (!incidence && lead) d.lead = upload(H, h.lead.data(), h.lead.size(), s);
+    if (on_dev) {
+        std::unique_ptr<Staged> own;
+        if (!st) {
+            own = stage(H->opts, A, s);
+            st = own.get();
+        }
+        HostSell rows;   // the fill kernels read rows of A: the unmapped slot map
+        rows.K = K;
+        rows.nslices = h.nslices;
+        rows.sptr = std::move(h.sptr);
+        rows.srow = rowmap ? local_srow : std::move(h.srow);
+        const DevEntries e = fill_entries(H, *st, rows, d.sptr, incidence, true, true, s);
+        d.ent = e.ent;
+        d.ci = e.ci;
+        d.c16 = e.c16;
+        d.cbase = e.cbase;
+        d.v64 = e.v64;
+        d.v32 = e.v32;
+        return d;
+    }
     if (incidence) {
         d.ent = upload(H, h.ent.data(), h.ent.size(), s);
     } else {
@@ -72,7 +177,6 @@ DSell upload_sell(amge_hierarchy* H, const Csr& A, bool incidence, int K, hipStr
         d.v64 = upload(H, h.val.data(), h.val.size(), s);
         std::vector<float> v32(h.val.begin(), h.val.end());   // round to nearest
         d.v32 = upload(H, v32.data(), v32.size(), s);
-        if (lead) d.lead = upload(H, h.lead.data(), h.lead.size(), s);
     }
     HIPCHECK(hipStreamSynchronize(s));
     return d;
@@ -246,7 +350,7 @@ static bool verbose() {
 static std::mutex g_tune_mu;
 static std::map<TuneKey, int> g_tune;
 
-int tune_lanes(const Csr& A, bool incidence, const amge_opts& opts, hipStream_t s) {
+int tune_lanes(const Csr& A, bool incidence, const amge_opts& opts, hipStream_t s, const Staged* st = nullptr) {
     TuneKey key{A.nrows, A.ncols, A.nnz(), incidence};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -263,6 +367,11 @@ int tune_lanes(const Csr& A, bool incidence, const amge_opts& opts, hipStream_t 
         if (K >= 1 && K <= 32 && avg >= 2.0 * K) cands.push_back(K);
     int best = cands[0];
     if (cands.size() > 1) {
+        std::unique_ptr<Staged> own;
+        if (!st && device_layouts()) {
+            own = stage(opts, A, s);
+            st = own.get();
+        }
         amge_hierarchy tmp;   // owns the trial buffers
         tmp.opts = opts;
         float* x = tmp.alloc<float>(A.ncols);
@@ -277,7 +386,7 @@ int tune_lanes(const Csr& A, bool incidence, const amge_opts& opts, hipStream_t 
         for (int K : cands) {
             amge_hierarchy t2;
             t2.opts = opts;
-            DSell M = upload_sell(&t2, A, incidence, K, s);
+            DSell M = upload_sell(&t2, A, incidence, K, s, nullptr, nullptr, st);
             auto run = [&]() {
                 if (incidence) sell_inc<float>(M, 0, x, y, s, zero);
                 else sell<float>(M, dev::SPMV, x, nullptr, nullptr, y, s, zero);
@@ -312,7 +421,9 @@ int tune_lanes(const Csr& A, bool incidence, const amge_opts& opts, hipStream_t 
 
 DSell upload_tuned(amge_hierarchy* H, const Csr& A, bool incidence, hipStream_t s,
                    const std::vector<int>* lead = nullptr) {
-    return upload_sell(H, A, incidence, tune_lanes(A, incidence, H->opts, s), s, lead);
+    std::unique_ptr<Staged> st;
+    if (device_layouts()) st = stage(H->opts, A, s);
+    return upload_sell(H, A, incidence, tune_lanes(A, incidence, H->opts, s, st.get()), s, lead, nullptr, st.get());
 }
 
 // A signed incidence (entries +-1): rows of one common length W <= 4 (the fine-level
@@ -519,7 +630,8 @@ template <> const double* bvals<double>(const DSellB& M) { return M.v64; }
 
 DSellB upload_sell_b(amge_hierarchy* H, const Csr& A, bool incidence, bool f32, bool f64, hipStream_t s,
                      const std::vector<int>* lead = nullptr) {
-    HostSell h = make_sell(A, incidence, 1, lead);
+    const bool on_dev = device_layouts();
+    HostSell h = on_dev ? sell_rows(A, 1, lead) : make_sell(A, incidence, 1, lead);
     DSellB M;
     M.nrows = A.nrows;
     M.ncols = A.ncols;
@@ -527,6 +639,18 @@ DSellB upload_sell_b(amge_hierarchy* H, const Csr& A, bool incidence, bool f32, 
     M.nslices = h.nslices;
     M.sptr = upload(H, h.sptr.data(), h.sptr.size(), s);
     M.srow = upload(H, h.srow.data(), h.srow.size(), s);
+    if (!incidence && lead) M.lead = upload(H, h.lead.data(), h.lead.size(), s);
+    if (on_dev) {
+        const std::unique_ptr<Staged> st = stage(H->opts, A, s);
+        const DevEntries e = fill_entries(H, *st, h, M.sptr, incidence, f32, f64, s);
+        M.ent = e.ent;
+        M.ci = e.ci;
+        M.c16 = e.c16;
+        M.cbase = e.cbase;
+        M.v64 = e.v64;
+        M.v32 = e.v32;
+        return M;
+    }
     if (incidence) {
         M.ent = upload(H, h.ent.data(), h.ent.size(), s);
     } else {
@@ -541,7 +665,6 @@ DSellB upload_sell_b(amge_hierarchy* H, const Csr& A, bool incidence, bool f32, 
             std::vector<float> v(h.val.begin(), h.val.end());
             M.v32 = upload(H, v.data(), v.size(), s);
         }
-        if (lead) M.lead = upload(H, h.lead.data(), h.lead.size(), s);
     }
     HIPCHECK(hipStreamSynchronize(s));
     return M;

@@ -1,0 +1,116 @@
+"""Set-up builds the sliced-ELL entry arrays on the device (k_slice_range, k_sell_fill)
+from a staged copy of each CSR matrix; AMGE_HOST_LAYOUT=1 builds the same layout on the
+host.  The layout is integer and byte work, so the bar is bit equality: every level
+operator, smoother, V-cycle and PCG result of a hierarchy set up either way must be
+identical bit for bit (same kernels, same arrays).  Covered: 16-bit column offsets and
+32-bit indices (AMGE_INDEX32=1), split-row operators, incidence matrices, the colour
+blocks of the Gauss-Seidel smoother and the batched layouts."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2107_05613_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _hier(levels, host, **kw):
+    from paper_2107_05613_amd import amge
+    old = os.environ.get("AMGE_HOST_LAYOUT")
+    os.environ["AMGE_HOST_LAYOUT"] = "1" if host else "0"
+    try:
+        return amge.Hierarchy(levels, **kw)
+    finally:
+        if old is None:
+            del os.environ["AMGE_HOST_LAYOUT"]
+        else:
+            os.environ["AMGE_HOST_LAYOUT"] = old
+
+
+def _levels(kind, n, L, coef):
+    from paper_2107_05613_amd import amge
+    a, b = W.coefficients(W.Workload("t", kind, n, L, coef))
+    return amge.build_problem(kind, n, L, a, b)
+
+
+def _same(a, b):
+    return torch.equal(a, b)
+
+
+SPECS = [("curl", 12, 3, "unit", "l1jacobi", False), ("div", 16, 4, "blocks", "symgs", False),
+         ("curl", 16, 3, "blocks", "l1jacobi", True)]
+
+
+@pytest.mark.parametrize("kind,n,L,coef,smoother,index32", SPECS)
+def test_level_operators_bitwise(kind, n, L, coef, smoother, index32, monkeypatch):
+    from paper_2107_05613_amd import amge
+    if index32:
+        monkeypatch.setenv("AMGE_INDEX32", "1")
+    lv = _levels(kind, n, L, coef)
+    kw = dict(precond_bits=64, tail_rows=0, smoother=smoother)
+    Hh, Hd = _hier(lv, True, **kw), _hier(lv, False, **kw)
+    rng = np.random.default_rng(3)
+    dev = lambda v: torch.from_numpy(v).cuda()
+    ops = 0
+    for k in range(L - 1):
+        nk, mk, nc = lv[k][0].shape[0], lv[k][1].shape[1], lv[k][2].shape[1]
+        x = {s: dev(rng.uniform(-1, 1, s)) for s in {nk, mk, nc}}
+        for op, nin, nout, two in ((amge.OP_A, nk, nk, False), (amge.OP_AHAT, mk, mk, False),
+                                   (amge.OP_D, mk, nk, False), (amge.OP_DT, nk, mk, False),
+                                   (amge.OP_P, nc, nk, False), (amge.OP_PT, nk, nc, False),
+                                   (amge.OP_SWEEP, nk, nk, True), (amge.OP_RESID, nk, nk, True),
+                                   (amge.OP_SMOOTH, nk, nk, True), (amge.OP_SMOOTHT, nk, nk, True)):
+            x2 = dev(rng.uniform(-1, 1, nk)) if two else None
+            for prec in (64, 32):
+                oh = torch.empty(nout, dtype=torch.float64, device="cuda")
+                od = torch.empty_like(oh)
+                Hh.level_apply(k, op, x[nin], oh, x2=x2, precision=prec)
+                Hd.level_apply(k, op, x[nin], od, x2=x2, precision=prec)
+                assert _same(oh, od), (k, op, prec)
+                ops += 1
+    print(f"{kind} n={n} {smoother}{' int32' if index32 else ''}: {ops} operator results identical")
+
+
+@pytest.mark.parametrize("kind,n,L,coef,smoother,nrhs", [("curl", 12, 3, "unit", "l1jacobi", 1),
+                                                         ("div", 16, 4, "blocks", "symgs", 1),
+                                                         ("div", 12, 3, "blocks", "l1jacobi", 8)])
+def test_solves_bitwise(kind, n, L, coef, smoother, nrhs):
+    lv = _levels(kind, n, L, coef)
+    kw = dict(precond_bits=32, smoother=smoother, max_rhs=nrhs)
+    Hh, Hd = _hier(lv, True, **kw), _hier(lv, False, **kw)
+    n1 = lv[0][0].shape[0]
+    b = torch.from_numpy(np.random.default_rng(4).uniform(-1, 1, n1 * nrhs)).cuda()
+    zh, zd = torch.empty_like(b), torch.empty_like(b)
+    Hh.vcycle(b, zh, nrhs=nrhs)
+    Hd.vcycle(b, zd, nrhs=nrhs)
+    assert _same(zh, zd)
+    xh, xd = torch.zeros_like(b), torch.zeros_like(b)
+    rh = Hh.pcg(b, xh, rtol=1e-8, nrhs=nrhs)
+    rd = Hd.pcg(b, xd, rtol=1e-8, nrhs=nrhs)
+    assert rh == rd and _same(xh, xd)
+    print(f"{kind} n={n} {smoother} nrhs={nrhs}: V-cycle and PCG ({rh[1]} iterations) identical")
+
+
+def test_fine_level_full_size_bitwise():
+    """The 64^3 H(curl) hierarchy: the fine-level kernels the solve times (deep-unrolled
+    sliced ELL of A_1) from device-built and host-built layouts."""
+    from paper_2107_05613_amd import amge
+    w = W.WORKLOADS["curl_n64_l5"]
+    a, b = W.coefficients(w)
+    lv = amge.build_problem(w.kind, w.n, w.levels, a, b)
+    kw = dict(precond_bits=32)
+    Hh, Hd = _hier(lv, True, **kw), _hier(lv, False, **kw)
+    n1 = lv[0][0].shape[0]
+    rng = np.random.default_rng(5)
+    x, x2 = (torch.from_numpy(rng.uniform(-1, 1, n1)).cuda() for _ in range(2))
+    for op in (amge.OP_A, amge.OP_SWEEP, amge.OP_RESID, amge.OP_SMOOTH):
+        for prec in (64, 32):
+            oh, od = torch.empty_like(x), torch.empty_like(x)
+            Hh.level_apply(0, op, x, oh, x2=x2, precision=prec)
+            Hd.level_apply(0, op, x, od, x2=x2, precision=prec)
+            assert _same(oh, od), (op, prec)
+    xh, xd = torch.zeros_like(x), torch.zeros_like(x)
+    assert Hh.pcg(x, xh) == Hd.pcg(x, xd) and _same(xh, xd)
