@@ -381,13 +381,51 @@ void tri_trace_mass(V3 x0, V3 x1, V3 x2, double M[3][3]) {
 }
 
 // ------------------------------------------------------------------ Kuhn mesh
+// Every edge of the Kuhn triangulation runs from a vertex v to v + d for a nonempty
+// 0/1 step d (an axis, a face diagonal or the cube diagonal, always towards increasing
+// coordinates), and every triangle is (u, u + s, u + s + t) with s, t nonempty and
+// disjoint: the in-plane triangles (|s| = |t| = 1) of the squares and the six interior
+// triangles of the cube at u.  An entity exists iff its steps stay inside the grid.
+// Entities are numbered in the order of their sorted vertex tuples, so with steps as
+// bit masks (x = 1, y = 2, z = 4: the vertex offset grows with the mask) the index is
+// the count of entities at lower vertices plus the step's rank among those existing at
+// the vertex, in closed form.
+namespace kuhn_steps {
+// the 12 triangle types (s, s | t) in increasing order
+constexpr int NTRI = 12;
+constexpr int TRI[NTRI][2] = {{1, 3}, {1, 5}, {1, 7}, {2, 3}, {2, 6}, {2, 7}, {3, 7}, {4, 5}, {4, 6}, {4, 7}, {5, 7}, {6, 7}};
+struct Tables {
+    int ecnt[8], erank[8][8], fcnt[8], frank[8][8][8];
+    Tables() {
+        for (int f = 0; f < 8; ++f) {
+            int c = 0;
+            for (int d = 0; d < 8; ++d) {
+                erank[f][d] = -1;
+                if (d && (d & ~f) == 0) erank[f][d] = c++;
+            }
+            ecnt[f] = c;
+            c = 0;
+            for (int a = 0; a < 8; ++a)
+                for (int b = 0; b < 8; ++b) frank[f][a][b] = -1;
+            for (auto& tr : TRI)
+                if ((tr[1] & ~f) == 0) frank[f][tr[0]][tr[1]] = c++;
+            fcnt[f] = c;
+        }
+    }
+};
+const Tables& tables() {
+    static const Tables t;
+    return t;
+}
+}  // namespace kuhn_steps
+
 struct Kuhn {
     int n = 0;
     int64_t nv = 0;
     std::vector<std::array<int32_t, 2>> E;
     std::vector<std::array<int32_t, 3>> F;
     std::vector<std::array<int32_t, 4>> T;
-    std::vector<int64_t> ekey, fkey;
+    std::vector<int64_t> eoff, foff;   // first edge / face with tail vertex v (nv + 1 entries)
     std::vector<std::array<int32_t, 6>> te;
     std::vector<std::array<int32_t, 4>> tf;
     std::vector<std::array<int32_t, 3>> fe;
@@ -396,57 +434,101 @@ struct Kuhn {
         return {(int)(v % m), (int)((v / m) % m), (int)(v / ((int64_t)m * m))};
     }
     int64_t vid(int i, int j, int k) const { int64_t m = n + 1; return i + m * (j + m * k); }
+    // axes along which a step from v stays inside the grid
+    int room(int64_t v) const {
+        auto c = coord(v);
+        return (c[0] < n ? 1 : 0) | (c[1] < n ? 2 : 0) | (c[2] < n ? 4 : 0);
+    }
+    int64_t step(int d) const {
+        int64_t m = n + 1;
+        return (d & 1) + ((d >> 1) & 1) * m + ((d >> 2) & 1) * m * m;
+    }
+    // 0/1 step mask from a to b, -1 if b - a is not such a step
+    int mask(int64_t a, int64_t b) const {
+        if (a < 0 || b < 0 || a >= nv || b >= nv) return -1;
+        auto ca = coord(a), cb = coord(b);
+        int d = 0;
+        for (int x = 0; x < 3; ++x) {
+            const int q = cb[x] - ca[x];
+            if (q != 0 && q != 1) return -1;
+            d |= q << x;
+        }
+        return d;
+    }
     int32_t edge(int64_t a, int64_t b) const {
-        int64_t k = a * nv + b;
-        auto it = std::lower_bound(ekey.begin(), ekey.end(), k);
-        if (it == ekey.end() || *it != k) fail(AMGE_ERR_ARG, "edge not in mesh");
-        return (int32_t)(it - ekey.begin());
+        const int d = mask(a, b);
+        const int r = d > 0 ? kuhn_steps::tables().erank[room(a)][d] : -1;
+        if (r < 0) fail(AMGE_ERR_ARG, "edge not in mesh");
+        return (int32_t)(eoff[a] + r);
     }
     int32_t face(int64_t a, int64_t b, int64_t c) const {
-        int64_t k = (a * nv + b) * nv + c;
-        auto it = std::lower_bound(fkey.begin(), fkey.end(), k);
-        if (it == fkey.end() || *it != k) fail(AMGE_ERR_ARG, "face not in mesh");
-        return (int32_t)(it - fkey.begin());
+        const int s = mask(a, b), st = mask(a, c);
+        const int r = s > 0 && st > 0 ? kuhn_steps::tables().frank[room(a)][s][st] : -1;
+        if (r < 0) fail(AMGE_ERR_ARG, "face not in mesh");
+        return (int32_t)(foff[a] + r);
     }
 };
 
 Kuhn build_kuhn(int n) {
+    using namespace kuhn_steps;
+    const Tables& tb = tables();
     Kuhn K;
     K.n = n;
-    int64_t m = n + 1;
+    const int64_t m = n + 1;
     K.nv = m * m * m;
-    if ((double)K.nv * K.nv * K.nv > 9.0e18) fail(AMGE_ERR_ARG, "mesh too large");
-    const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
-    int64_t step[3] = {1, m, m * m};
-    K.T.reserve((size_t)n * n * n * 6);
-    for (int k = 0; k < n; ++k)
-        for (int j = 0; j < n; ++j)
-            for (int i = 0; i < n; ++i) {
-                int64_t base = K.vid(i, j, k);
-                for (auto& p : perms) {
-                    int64_t v1 = base + step[p[0]], v2 = v1 + step[p[1]], v3 = v2 + step[p[2]];
-                    K.T.push_back({(int32_t)base, (int32_t)v1, (int32_t)v2, (int32_t)v3});
-                }
-            }
-    std::sort(K.T.begin(), K.T.end());
-    for (auto& t : K.T) {
-        for (auto& e : TE) K.ekey.push_back((int64_t)t[e[0]] * K.nv + t[e[1]]);
-        for (auto& f : TF) K.fkey.push_back(((int64_t)t[f[0]] * K.nv + t[f[1]]) * K.nv + t[f[2]]);
+    if ((double)n * n * n * 6 > 2.0e9) fail(AMGE_ERR_ARG, "mesh too large");
+    K.eoff.assign(K.nv + 1, 0);
+    K.foff.assign(K.nv + 1, 0);
+    for (int64_t v = 0; v < K.nv; ++v) {
+        const int f = K.room(v);
+        K.eoff[v + 1] = K.eoff[v] + tb.ecnt[f];
+        K.foff[v + 1] = K.foff[v] + tb.fcnt[f];
     }
-    std::sort(K.ekey.begin(), K.ekey.end());
-    K.ekey.erase(std::unique(K.ekey.begin(), K.ekey.end()), K.ekey.end());
-    std::sort(K.fkey.begin(), K.fkey.end());
-    K.fkey.erase(std::unique(K.fkey.begin(), K.fkey.end()), K.fkey.end());
-    for (int64_t k : K.ekey) K.E.push_back({(int32_t)(k / K.nv), (int32_t)(k % K.nv)});
-    for (int64_t k : K.fkey)
-        K.F.push_back({(int32_t)(k / (K.nv * K.nv)), (int32_t)((k / K.nv) % K.nv), (int32_t)(k % K.nv)});
+    if (K.eoff[K.nv] > INT32_MAX || K.foff[K.nv] > INT32_MAX) fail(AMGE_ERR_ARG, "mesh too large");
+    K.E.resize(K.eoff[K.nv]);
+    K.F.resize(K.foff[K.nv]);
+    parallel_for(K.nv, [&](int64_t s, int64_t e) {
+        for (int64_t v = s; v < e; ++v) {
+            const int f = K.room(v);
+            for (int d = 1; d < 8; ++d)
+                if (tb.erank[f][d] >= 0) K.E[K.eoff[v] + tb.erank[f][d]] = {(int32_t)v, (int32_t)(v + K.step(d))};
+            for (auto& tr : TRI)
+                if (tb.frank[f][tr[0]][tr[1]] >= 0)
+                    K.F[K.foff[v] + tb.frank[f][tr[0]][tr[1]]] = {(int32_t)v, (int32_t)(v + K.step(tr[0])),
+                                                                  (int32_t)(v + K.step(tr[1]))};
+        }
+    });
+    // six tetrahedra per cube along the paths base -> base + (1,1,1) adding one axis at a
+    // time, in the axis orders below; cubes in increasing base vertex, so the tetrahedra
+    // come out in increasing order of their vertex tuples
+    const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    const int64_t ncube = (int64_t)n * n * n;
+    K.T.resize(ncube * 6);
     K.te.resize(K.T.size());
     K.tf.resize(K.T.size());
-    parallel_for((int64_t)K.T.size(), [&](int64_t s, int64_t e) {
-        for (int64_t t = s; t < e; ++t) {
-            auto& v = K.T[t];
-            for (int p = 0; p < 6; ++p) K.te[t][p] = K.edge(v[TE[p][0]], v[TE[p][1]]);
-            for (int p = 0; p < 4; ++p) K.tf[t][p] = K.face(v[TF[p][0]], v[TF[p][1]], v[TF[p][2]]);
+    parallel_for(ncube, [&](int64_t s, int64_t e) {
+        for (int64_t q = s; q < e; ++q) {
+            const int i = (int)(q % n), j = (int)((q / n) % n), k = (int)(q / ((int64_t)n * n));
+            const int64_t base = K.vid(i, j, k);
+            for (int p = 0; p < 6; ++p) {
+                const int cm[4] = {0, 1 << perms[p][0], (1 << perms[p][0]) | (1 << perms[p][1]), 7};
+                int64_t v[4];
+                int rm[4];
+                for (int a = 0; a < 4; ++a) {
+                    v[a] = base + K.step(cm[a]);
+                    rm[a] = K.room(v[a]);
+                }
+                const int64_t t = q * 6 + p;
+                K.T[t] = {(int32_t)v[0], (int32_t)v[1], (int32_t)v[2], (int32_t)v[3]};
+                for (int a = 0; a < 6; ++a) {
+                    const int x = TE[a][0], y = TE[a][1];
+                    K.te[t][a] = (int32_t)(K.eoff[v[x]] + tb.erank[rm[x]][cm[y] ^ cm[x]]);
+                }
+                for (int a = 0; a < 4; ++a) {
+                    const int x = TF[a][0], y = TF[a][1], z = TF[a][2];
+                    K.tf[t][a] = (int32_t)(K.foff[v[x]] + tb.frank[rm[x]][cm[y] ^ cm[x]][cm[z] ^ cm[x]]);
+                }
+            }
         }
     });
     K.fe.resize(K.F.size());
@@ -1132,41 +1214,58 @@ struct Problem {
 
 // Fine system matrix, eq. (2.2).
 Csr fine_matrix(const Kuhn& K, int kind, const double* alpha, const double* beta) {
+    // the tetrahedra are translates of the six of the cube at the origin (tetrahedron t
+    // is cube t / 6's copy of type t % 6, with the same local vertex order and face
+    // orientations), so their unit-coefficient element matrices are computed once
     const int n = K.n;
     const double h = 1.0 / n;
-    int64_t nt = (int64_t)K.T.size();
-    int per = kind == AMGE_CURL ? 36 : 16;
-    int32_t ndof = kind == AMGE_CURL ? (int32_t)K.E.size() : (int32_t)K.F.size();
-    std::vector<int64_t> keys(nt * per);
-    std::vector<double> vals(nt * per);
-    parallel_for(nt, [&](int64_t s, int64_t e) {
-        for (int64_t t = s; t < e; ++t) {
-            Tet g = kuhn_tet(K, t, h);
-            auto c0 = K.coord(K.T[t][0]);          // lower hex corner
-            int64_t hx = c0[0] + (int64_t)n * (c0[1] + (int64_t)n * c0[2]);
-            double al = alpha[hx], be = beta[hx];
-            int64_t o = t * per;
+    const int64_t nt = (int64_t)K.T.size();
+    const int per = kind == AMGE_CURL ? 36 : 16;
+    const int32_t ndof = kind == AMGE_CURL ? (int32_t)K.E.size() : (int32_t)K.F.size();
+    double Ka[6][36], Mb[6][36];   // per type: the alpha and beta parts, row-major
+    {
+        Kuhn C = build_kuhn(1);
+        for (int p = 0; p < 6; ++p) {
+            Tet g = kuhn_tet(C, p, h);
             if (kind == AMGE_CURL) {
                 double M[6][6], Kc[6][6];
                 nd_mass(g, M);
                 curlcurl(g, Kc);
-                for (int p = 0; p < 6; ++p)
-                    for (int q = 0; q < 6; ++q) {
-                        keys[o] = (int64_t)K.te[t][p] * ndof + K.te[t][q];
-                        vals[o++] = al * Kc[p][q] + be * M[p][q];
+                for (int a = 0; a < 6; ++a)
+                    for (int b = 0; b < 6; ++b) {
+                        Ka[p][a * 6 + b] = Kc[a][b];
+                        Mb[p][a * 6 + b] = M[a][b];
                     }
             } else {
                 double M[4][4];
                 rt_mass(g, M);
-                for (int p = 0; p < 4; ++p)
-                    for (int q = 0; q < 4; ++q) {
-                        keys[o] = (int64_t)K.tf[t][p] * ndof + K.tf[t][q];
-                        vals[o++] = al * g.s[p] * g.s[q] / g.vol + be * M[p][q];
+                for (int a = 0; a < 4; ++a)
+                    for (int b = 0; b < 4; ++b) {
+                        Ka[p][a * 4 + b] = g.s[a] * g.s[b] / g.vol;
+                        Mb[p][a * 4 + b] = M[a][b];
                     }
             }
         }
+    }
+    // written in full (and first touched) by the parallel loop
+    std::unique_ptr<int64_t[]> keys(new int64_t[nt * per + 1]);
+    std::unique_ptr<double[]> vals(new double[nt * per + 1]);
+    parallel_for(nt, [&](int64_t s, int64_t e) {
+        for (int64_t t = s; t < e; ++t) {
+            const int p = (int)(t % 6);
+            const int64_t hx = t / 6;   // cube index i + n (j + n k), as the coefficients
+            const double al = alpha[hx], be = beta[hx];
+            int64_t o = t * per;
+            const int w = kind == AMGE_CURL ? 6 : 4;
+            const int32_t* dof = kind == AMGE_CURL ? K.te[t].data() : K.tf[t].data();
+            for (int a = 0; a < w; ++a)
+                for (int b = 0; b < w; ++b) {
+                    keys[o] = (int64_t)dof[a] * ndof + dof[b];
+                    vals[o++] = al * Ka[p][a * w + b] + be * Mb[p][a * w + b];
+                }
+        }
     });
-    return from_triplets(ndof, ndof, keys, vals, true);
+    return from_triplets(ndof, ndof, keys.get(), vals.get(), nt * per, true);
 }
 
 Csr kuhn_grad(const Kuhn& K) {

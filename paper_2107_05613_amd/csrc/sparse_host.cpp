@@ -1,7 +1,9 @@
 // Host sparse kernels used at set-up: transpose, sparse product, triplet assembly.
 #include <exception>
 #include <atomic>
+#include <climits>
 #include <cmath>
+#include <memory>
 #include <numeric>
 
 #include "common.hpp"
@@ -18,9 +20,32 @@ extern "C" const char* amge_last_error(void) { return amge::g_last_error.c_str()
 
 namespace amge {
 
+int host_threads() { return (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency())); }
+
+void parallel_tasks(int ntasks, const std::function<void(int)>& fn) {
+    if (ntasks <= 0) return;
+    if (ntasks == 1) {
+        fn(0);
+        return;
+    }
+    std::vector<std::thread> th;
+    std::vector<std::exception_ptr> err(ntasks);
+    for (int t = 0; t < ntasks; ++t)
+        th.emplace_back([&fn, &err, t] {
+            try {
+                fn(t);
+            } catch (...) {
+                err[t] = std::current_exception();
+            }
+        });
+    for (auto& t : th) t.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
+}
+
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& body) {
     if (n <= 0) return;
-    int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    int nt = host_threads();
     if (n < 4096 || nt == 1) {
         body(0, n);
         return;
@@ -140,28 +165,72 @@ Csr spgemm(const Csr& A, const Csr& B) {
     return C;
 }
 
-Csr from_triplets(int32_t nr, int32_t nc, std::vector<int64_t>& keys, std::vector<double>& vals,
+Csr from_triplets(int32_t nr, int32_t nc, const int64_t* keys, const double* vals, int64_t m,
                   bool sum_duplicates) {
-    // bucket by row (counting sort), then sort each row by column and merge duplicates:
-    // summed (assembly) or first-kept (overwrite assembly: shared entries agree)
-    const int64_t m = (int64_t)keys.size();
-    std::vector<int64_t> start(nr + 1, 0);
-    for (int64_t t = 0; t < m; ++t) start[keys[t] / nc + 1]++;
-    for (int32_t i = 0; i < nr; ++i) start[i + 1] += start[i];
-    std::vector<int32_t> bc(m);
-    std::vector<double> bv(m);
-    {
-        std::vector<int64_t> pos(start.begin(), start.end() - 1);
-        for (int64_t t = 0; t < m; ++t) {
-            int64_t r = keys[t] / nc;
-            int64_t p = pos[r]++;
-            bc[p] = (int32_t)(keys[t] % nc);
-            bv[p] = vals[t];
+    // Stable bucketing by row (a counting sort in parallel: each thread counts the rows of
+    // its contiguous chunk of triplets, over the row range the chunk touches; a row's
+    // entries from chunk t follow those of chunks < t), then each row sorted by column
+    // (stable) and its duplicates merged in triplet order: summed (assembly) or the first
+    // kept (overwrite assembly: shared entries agree).
+    if (nc <= 0 && m > 0) fail(AMGE_ERR_SHAPE, "triplets for a matrix without columns");
+    const int nt = m >= (1 << 16) ? host_threads() : 1;
+    std::vector<int64_t> cut(nt + 1);
+    for (int t = 0; t <= nt; ++t) cut[t] = m * t / nt;
+    std::vector<int64_t> rlo(nt, 0), rhi(nt, -1);
+    std::vector<std::vector<int64_t>> cnt(nt);
+    parallel_tasks(nt, [&](int t) {
+        int64_t lo = INT64_MAX, hi = -1;
+        for (int64_t q = cut[t]; q < cut[t + 1]; ++q) {
+            const int64_t r = keys[q] / nc;
+            if (r < 0 || r >= nr || keys[q] % nc < 0) fail(AMGE_ERR_SHAPE, "triplet outside the matrix");
+            lo = std::min(lo, r);
+            hi = std::max(hi, r);
         }
-    }
+        if (hi < 0) return;
+        rlo[t] = lo;
+        rhi[t] = hi;
+        cnt[t].assign(hi - lo + 1, 0);
+        for (int64_t q = cut[t]; q < cut[t + 1]; ++q) cnt[t][keys[q] / nc - lo]++;
+    });
+    std::vector<int64_t> start(nr + 1, 0);
+    parallel_for(nr, [&](int64_t s, int64_t e) {
+        for (int64_t r = s; r < e; ++r) {
+            int64_t c = 0;
+            for (int t = 0; t < nt; ++t)
+                if (r >= rlo[t] && r <= rhi[t]) c += cnt[t][r - rlo[t]];
+            start[r + 1] = c;
+        }
+    });
+    for (int32_t i = 0; i < nr; ++i) start[i + 1] += start[i];
+    // counts -> first position of each chunk's entries in each row
+    parallel_for(nr, [&](int64_t s, int64_t e) {
+        for (int64_t r = s; r < e; ++r) {
+            int64_t run = start[r];
+            for (int t = 0; t < nt; ++t)
+                if (r >= rlo[t] && r <= rhi[t]) {
+                    const int64_t c = cnt[t][r - rlo[t]];
+                    cnt[t][r - rlo[t]] = run;
+                    run += c;
+                }
+        }
+    });
+    // every slot is written by the scatter: no initialisation
+    std::unique_ptr<int32_t[]> bc(new int32_t[std::max<int64_t>(m, 1)]);
+    std::unique_ptr<double[]> bv(new double[std::max<int64_t>(m, 1)]);
+    parallel_tasks(nt, [&](int t) {
+        for (int64_t q = cut[t]; q < cut[t + 1]; ++q) {
+            const int64_t r = keys[q] / nc;
+            const int64_t p = cnt[t][r - rlo[t]]++;
+            bc[p] = (int32_t)(keys[q] % nc);
+            bv[p] = vals[q];
+        }
+    });
+    cnt.clear();
     std::vector<int32_t> rowcnt(nr, 0);
     parallel_for(nr, [&](int64_t s, int64_t e) {
         std::vector<std::pair<int32_t, int64_t>> tmp;
+        std::vector<double> v2;
+        std::vector<int32_t> c2;
         for (int64_t i = s; i < e; ++i) {
             tmp.clear();
             for (int64_t p = start[i]; p < start[i + 1]; ++p) tmp.emplace_back(bc[p], p);
@@ -169,8 +238,8 @@ Csr from_triplets(int32_t nr, int32_t nc, std::vector<int64_t>& keys, std::vecto
                              [](const std::pair<int32_t, int64_t>& a, const std::pair<int32_t, int64_t>& b) {
                                  return a.first < b.first;
                              });
-            std::vector<double> v2;
-            std::vector<int32_t> c2;
+            v2.clear();
+            c2.clear();
             for (auto& q : tmp) {
                 if (!c2.empty() && c2.back() == q.first) {
                     if (sum_duplicates) v2.back() += bv[q.second];
