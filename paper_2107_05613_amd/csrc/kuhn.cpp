@@ -29,6 +29,7 @@
 
 #include "common.hpp"
 #include "setup_device.hpp"
+#include "spgemm_device.hpp"
 
 namespace amge {
 namespace {
@@ -1676,8 +1677,12 @@ Problem build(int kind, int n, int nlevels, const double* alpha, const double* b
     // Galerkin coarse matrices and coarse derivatives
     for (int k = 1; k < nlevels; ++k) {
         const Csr& P = pr.P[k - 1];
-        Csr AP = spgemm(pr.A[k - 1], P);
-        pr.A.push_back(spgemm(transpose(P), AP));
+        if (flags & AMGE_BUILD_DEVICE) {
+            pr.A.push_back(triple_on_device(transpose(P), pr.A[k - 1], P, nullptr));
+        } else {
+            Csr AP = spgemm(pr.A[k - 1], P);
+            pr.A.push_back(spgemm(transpose(P), AP));
+        }
         Cubes c(n >> k);
         pr.D.push_back(curl ? c.grad() : c.curl());
     }

@@ -24,6 +24,7 @@
 #include "kernels.hpp"
 #include "kernels_batched.hpp"
 #include "sell_layout.hpp"
+#include "spgemm_device.hpp"
 
 
 namespace amge {
@@ -1479,8 +1480,8 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         L.m = D[k].ncols;
         clk.lap("other per-level work");
         Csr Dt = transpose(D[k]);
-        Csr DtA = spgemm(Dt, A[k]);                 // D^T A, for the auxiliary residual
-        Csr Ah = spgemm(DtA, D[k]);                 // auxiliary matrix D^T A D (eq. (4.1))
+        // D^T A (for the auxiliary residual) and the auxiliary matrix D^T A D (eq. (4.1))
+        auto [DtA, Ah] = chain_on_device(Dt, A[k], D[k], s, &H->opts);
         std::vector<double> d = l1_row_sums(A[k]), dh = l1_row_sums(Ah);
         H->kappa = std::max(H->kappa, cancellation_factor(A[k], D[k], Dt, dh));
         std::vector<double> dinv(d.size()), dhinv(dh.size());
@@ -1552,7 +1553,7 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
                 // restriction.  On the fine level the residual reads the cache-resident
                 // A_k and stays separate.
                 const Csr Pt = transpose(P[k]);
-                const Csr PtA = spgemm(Pt, A[k]);
+                const Csr PtA = spgemm_on_device(Pt, A[k], s, &H->opts);
                 Csr R;
                 R.nrows = Pt.nrows;
                 R.ncols = L.n;

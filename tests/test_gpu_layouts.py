@@ -1,10 +1,16 @@
-"""Set-up builds the sliced-ELL entry arrays on the device (k_slice_range, k_sell_fill)
-from a staged copy of each CSR matrix; AMGE_HOST_LAYOUT=1 builds the same layout on the
-host.  The layout is integer and byte work, so the bar is bit equality: every level
-operator, smoother, V-cycle and PCG result of a hierarchy set up either way must be
-identical bit for bit (same kernels, same arrays).  Covered: 16-bit column offsets and
-32-bit indices (AMGE_INDEX32=1), split-row operators, incidence matrices, the colour
-blocks of the Gauss-Seidel smoother and the batched layouts."""
+"""Set-up work on the device against the same work on the host, bit for bit.
+
+* Sliced-ELL entry arrays (k_slice_range, k_sell_fill) filled from a staged copy of each
+  CSR matrix; AMGE_HOST_LAYOUT=1 builds the same layout on the host.  Layouts are
+  integer and byte work.
+* The set-up products D^T A, D^T A D and P^T A (spgemm_device.hip); AMGE_HOST_PRODUCTS=1
+  forms them on the host.  The device products sum in the host product's order with
+  separately rounded operations, so they are equal bit for bit.
+
+Every level operator, smoother, V-cycle and PCG result of a hierarchy set up either way
+must be identical bit for bit (same kernels, same arrays).  Covered: 16-bit column
+offsets and 32-bit indices (AMGE_INDEX32=1), split-row operators, incidence matrices,
+the colour blocks of the Gauss-Seidel smoother and the batched layouts."""
 import os
 
 import numpy as np
@@ -17,17 +23,23 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
+SWITCHES = ("AMGE_HOST_LAYOUT", "AMGE_HOST_PRODUCTS")
+
+
 def _hier(levels, host, **kw):
+    """Hierarchy set up with every set-up step on the host (host=True) or the device."""
     from paper_2107_05613_amd import amge
-    old = os.environ.get("AMGE_HOST_LAYOUT")
-    os.environ["AMGE_HOST_LAYOUT"] = "1" if host else "0"
+    old = {k: os.environ.get(k) for k in SWITCHES}
+    for k in SWITCHES:
+        os.environ[k] = "1" if host else "0"
     try:
         return amge.Hierarchy(levels, **kw)
     finally:
-        if old is None:
-            del os.environ["AMGE_HOST_LAYOUT"]
-        else:
-            os.environ["AMGE_HOST_LAYOUT"] = old
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
 
 
 def _levels(kind, n, L, coef):
@@ -114,3 +126,22 @@ def test_fine_level_full_size_bitwise():
             assert _same(oh, od), (op, prec)
     xh, xd = torch.zeros_like(x), torch.zeros_like(x)
     assert Hh.pcg(x, xh) == Hd.pcg(x, xd) and _same(xh, xd)
+
+
+@pytest.mark.parametrize("kind,n,L,coef", [("curl", 16, 4, "blocks"), ("div", 16, 4, "unit")])
+def test_builder_galerkin_products_bitwise(kind, n, L, coef):
+    """Galerkin coarse matrices P^T (A P) formed on the device (AMGE_BUILD_DEVICE) equal the
+    host builder's bit for bit (unweighted extensions: the local problems are shared, so
+    only the products differ in where they run)."""
+    from paper_2107_05613_amd import amge
+    a, b = W.coefficients(W.Workload("t", kind, n, L, coef))
+    dev = amge.build_problem(kind, n, L, a, b, device=True)
+    hst = amge.build_problem(kind, n, L, a, b)
+    for k in range(L):
+        for i in range(3):
+            if hst[k][i] is None:
+                continue
+            Md, Mh = dev[k][i], hst[k][i]
+            assert Md.shape == Mh.shape
+            assert np.array_equal(Md.rowptr, Mh.rowptr) and np.array_equal(Md.col, Mh.col), (k, i)
+            assert np.array_equal(Md.val.view(np.uint64), Mh.val.view(np.uint64)), (k, i)
