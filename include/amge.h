@@ -46,6 +46,7 @@ extern "C" {
 typedef enum {
     AMGE_OK = 0,
     AMGE_NOT_CONVERGED = 1,
+    AMGE_CANCELLED = 2,       /* serving: the request was cancelled (amge_server_cancel)  */
     AMGE_ERR_ARG = -1,        /* invalid argument (null pointer, bad size, bad option)   */
     AMGE_ERR_SHAPE = -2,      /* matrix dimensions do not chain, indices out of range    */
     AMGE_ERR_NOT_SPD = -3,    /* coarsest matrix not symmetric positive definite         */
@@ -292,7 +293,8 @@ typedef struct amge_server amge_server;
 typedef struct {
     int64_t tag;         /* the caller's request id                                        */
     int32_t hierarchy;   /* id from amge_server_add                                         */
-    int32_t status;      /* AMGE_OK, AMGE_NOT_CONVERGED, AMGE_ERR_BREAKDOWN, AMGE_ERR_NONFINITE */
+    int32_t status;      /* AMGE_OK, AMGE_NOT_CONVERGED, AMGE_CANCELLED, AMGE_ERR_BREAKDOWN,
+                            AMGE_ERR_NONFINITE                                               */
     int32_t iters;       /* PCG steps                                                       */
     int32_t pad;
     double relres;       /* final relative residual in the chosen norm                      */
@@ -337,6 +339,15 @@ amge_status amge_server_submit(amge_server* s, int32_t id, const double* b, doub
  * written to out (*nout of them); x of a returned request is final. */
 amge_status amge_server_progress(amge_server* s, int32_t wait, amge_completion* out, int32_t cap,
                                  int32_t* nout);
+/* Cancels every request with this tag that has not finished: a queued one is removed,
+ * an in-flight one leaves its column when the chunk of iterations it is in ends (at
+ * once if none is running), and the column goes back to the pool.  Each cancelled
+ * request is still returned by amge_server_progress, once, with status AMGE_CANCELLED
+ * (iters / relres: its state at the last chunk boundary); its x is not written after the
+ * call and b is no longer read once that completion is returned.  A request whose
+ * solution is already being copied out is not cancelled (its completion is the real
+ * one).  *count (may be NULL): the number of requests cancelled.  Errors: AMGE_ERR_ARG. */
+amge_status amge_server_cancel(amge_server* s, int64_t tag, int32_t* count);
 /* Queued and in-flight request counts, in-flight work bytes and resident hierarchy bytes
  * (any pointer may be NULL). */
 amge_status amge_server_stats(const amge_server* s, int32_t* queued, int32_t* inflight,

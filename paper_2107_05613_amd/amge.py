@@ -23,9 +23,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libamge.so")
 
 CURL, DIV = 0, 1
+OK, NOT_CONVERGED, CANCELLED = 0, 1, 2   # request statuses that are not errors
 OP_A, OP_AHAT, OP_D, OP_DT, OP_P, OP_PT, OP_SMOOTH, OP_SMOOTHT, OP_COARSE, OP_SWEEP, OP_RESID = range(11)
 
-STATUS = {0: "AMGE_OK", 1: "AMGE_NOT_CONVERGED", -1: "AMGE_ERR_ARG", -2: "AMGE_ERR_SHAPE",
+STATUS = {0: "AMGE_OK", 1: "AMGE_NOT_CONVERGED", 2: "AMGE_CANCELLED", -1: "AMGE_ERR_ARG", -2: "AMGE_ERR_SHAPE",
           -3: "AMGE_ERR_NOT_SPD", -4: "AMGE_ERR_OOM", -5: "AMGE_ERR_HIP", -6: "AMGE_ERR_BREAKDOWN",
           -7: "AMGE_ERR_NONFINITE", -8: "AMGE_ERR_BUSY"}
 
@@ -115,6 +116,7 @@ def _load():
         "amge_server_progress": (i32, [vp, i32, C.POINTER(CompletionC), i32, C.POINTER(i32)]),
         "amge_server_stats": (i32, [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_size_t),
                                     C.POINTER(C.c_size_t)]),
+        "amge_server_cancel": (i32, [vp, C.c_int64, C.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -148,7 +150,7 @@ EXPORTS = ("amge_default_opts", "amge_setup_hierarchy", "amge_destroy", "amge_ct
            "amge_kuhn_build", "amge_problem_nlevels", "amge_problem_levels", "amge_problem_free",
            "amge_server_create", "amge_server_destroy", "amge_server_add", "amge_server_add_grouped",
            "amge_server_ensemble", "amge_server_request_bytes", "amge_server_submit", "amge_server_progress",
-           "amge_server_stats")
+           "amge_server_stats", "amge_server_cancel")
 
 
 def lib():
@@ -508,6 +510,13 @@ class Server:
         m, k, k1 = C.c_int32(), C.c_int32(), C.c_int32()
         _check(_lib.amge_server_ensemble(self._h, C.byref(m), C.byref(k), C.byref(k1)))
         return m.value, k.value, k1.value
+
+    def cancel(self, tag) -> int:
+        """Cancels the unfinished requests with this tag (amge_server_cancel); returns how
+        many.  Each still completes, once, with status CANCELLED."""
+        n = C.c_int32()
+        _check(_lib.amge_server_cancel(self._h, int(tag), C.byref(n)))
+        return n.value
 
     def stats(self):
         q, f = C.c_int32(), C.c_int32()

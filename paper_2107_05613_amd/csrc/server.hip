@@ -67,6 +67,15 @@ k_serve_extract(int64_t n, int lg, int c, const double* __restrict__ X, double* 
         x[i] = X[(i << lg) + c];
 }
 
+// Column c idle (a cancelled request leaves it).
+__global__ void k_serve_cancel(int c, ColState* __restrict__ cs) {
+    if (threadIdx.x == 0) {
+        ColState s = {};
+        s.done = 1;
+        cs[c] = s;
+    }
+}
+
 // Every column idle.
 __global__ void k_serve_reset(int NC, ColState* __restrict__ cs, BatchStatus* __restrict__ bs) {
     const int c = threadIdx.x;
@@ -98,6 +107,7 @@ struct Request {
     double rtol = 0;
     int maxit = 0, stop_l2 = 0;
     hipEvent_t ready = nullptr;   // recorded on the caller's stream at submission
+    bool cancel = false;          // cancelled while its chunk was in flight
     amge_completion done{};
 };
 
@@ -251,7 +261,59 @@ struct amge_server {
         return true;
     }
 
-    // After a chunk: report finished columns, copy them out and free them.
+    // Frees column c of an idle group and reports its request as cancelled (x is not
+    // written); the column is marked idle on the device before anything later on the
+    // group's stream.
+    void drop_column(Group& g, int c) {
+        const int i = g.slot[c];
+        dev::k_serve_cancel<<<1, 64, 0, g.stream>>>(c, g.H->cs);
+        HIPCHECK(hipGetLastError());
+        Request& r = reqs[i];
+        amge_completion d{};
+        d.tag = r.tag;
+        d.hierarchy = r.hid;
+        d.status = AMGE_CANCELLED;
+        d.iters = g.cs_host[c].iters;
+        d.relres = g.cs_host[c].relres;
+        done.push_back(d);
+        release(i);
+        g.slot[c] = -1;
+        g.active -= 1;
+        inflight -= g.col_bytes;
+    }
+
+    // Cancels every queued or in-flight request with this tag (see amge_server_cancel).
+    int cancel(int64_t tag) {
+        int n = 0;
+        for (auto it = queue.begin(); it != queue.end();) {
+            if (reqs[*it].tag != tag) {
+                ++it;
+                continue;
+            }
+            amge_completion d{};
+            d.tag = tag;
+            d.hierarchy = reqs[*it].hid;
+            d.status = AMGE_CANCELLED;
+            done.push_back(d);
+            release(*it);
+            it = queue.erase(it);
+            ++n;
+        }
+        for (auto& gp : groups) {
+            Group& g = *gp;
+            for (int c = 0; c < (int)g.slot.size(); ++c) {
+                const int i = g.slot[c];
+                if (i < 0 || reqs[i].tag != tag || reqs[i].cancel) continue;
+                if (g.chunk_busy) reqs[i].cancel = true;   // dropped when the chunk ends
+                else drop_column(g, c);
+                ++n;
+            }
+        }
+        return n;
+    }
+
+    // After a chunk: report finished columns, copy them out and free them; drop the
+    // columns of requests cancelled meanwhile.
     void collect(Group& g) {
         g.chunk_busy = false;
         amge_hierarchy* H = g.H;
@@ -260,6 +322,10 @@ struct amge_server {
         for (int c = 0; c < H->NC; ++c) {
             const int i = g.slot[c];
             if (i < 0) continue;
+            if (reqs[i].cancel) {
+                drop_column(g, c);
+                continue;
+            }
             const dev::ColState& s = g.cs_host[c];
             if (!s.done) continue;
             Request& r = reqs[i];
@@ -610,6 +676,15 @@ extern "C" amge_status amge_server_progress(amge_server* s, int32_t wait, amge_c
             s->done.pop_front();
         }
         *nout = k;
+        return AMGE_OK;
+    });
+}
+
+extern "C" amge_status amge_server_cancel(amge_server* s, int64_t tag, int32_t* count) {
+    return sguard([&]() -> amge_status {
+        if (!s) fail(AMGE_ERR_ARG, "null argument");
+        const int n = s->cancel(tag);
+        if (count) *count = n;
         return AMGE_OK;
     });
 }

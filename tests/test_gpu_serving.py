@@ -13,6 +13,8 @@ Bars
 * Grouped launches: hierarchies added as the server's ensemble (one captured graph of
   grouped launches for an iteration of all of them) give bitwise the results of the
   same hierarchies served one by one.
+* Cancellation: cancelled requests complete once, as cancelled, x untouched; the
+  others are bitwise unaffected.
 * Admission: the in-flight budget caps the admitted requests' work footprint at every
   moment; hierarchies beyond the resident budget and requests beyond the in-flight
   budget are refused with AMGE_ERR_BUSY.
@@ -316,3 +318,48 @@ def test_budget_refusals_and_failed_requests():
     assert got[3][0] == 1 and got[3][1] == 2
     for j in (0, 2, 4):
         assert got[j][0] == 0 and np.array_equal(got[j][3], ref[j][3])
+
+
+@pytest.mark.parametrize("grouped", [False, True])
+def test_cancellation(grouped):
+    """amge_server_cancel: a queued request and one whose chunk is running each complete
+    once with status CANCELLED and their x untouched; every other request gives bitwise
+    the result it gives when nothing is cancelled; an unknown tag cancels nothing; the
+    server holds no request or in-flight bytes afterwards."""
+    from paper_2107_05613_amd import amge
+    res = resident(32)
+    reqs = requests(res, 12, seed=3)
+    order = list(range(12))
+    grp = [0, 0, 0] if grouped else None
+    ref = serve(res, reqs, order, grouped=grp)
+    srv = amge.Server(chunk=2)
+    ids = [srv.add(H) if not grouped else srv.add(H, grouped=True, ensemble=0) for H in res.H]
+    xs = {j: torch.full((res.n1[reqs[j][0]],), float("nan"), dtype=torch.float64, device="cuda") for j in order}
+    for j in order:
+        srv.submit(ids[reqs[j][0]], reqs[j][1], xs[j], tag=j, rtol=1e-8, maxit=500)
+    assert srv.cancel(5) == 1          # still queued
+    assert srv.cancel(999) == 0
+    out = {}
+
+    def take(done):
+        for tag, hid, status, iters, relres in done:
+            assert tag not in out, f"request {tag} completed twice"
+            out[tag] = (status, iters, relres)
+
+    take(srv.progress(wait=False))     # admits the first requests and starts their chunks
+    assert srv.cancel(0) == 1          # admitted first, its chunk in flight
+    while len(out) < len(order):
+        take(srv.progress(wait=True))
+    st = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    assert st["queued"] == 0 and st["inflight"] == 0 and st["inflight_bytes"] == 0
+    for j in order:
+        x = xs[j].cpu().numpy()
+        if j in (0, 5):
+            assert out[j][0] == amge.CANCELLED, (j, out[j])
+            assert np.isnan(x).all(), j
+            continue
+        assert out[j] == ref[j][:3], (j, out[j], ref[j][:3])
+        assert np.array_equal(x, ref[j][3]), j
+    print(f"grouped={grouped}: 2 of 12 requests cancelled, the other 10 bitwise as uncancelled")
