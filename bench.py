@@ -413,7 +413,8 @@ def run_serving(args):
     from paper_2107_05613_amd import amge, serve
     from paper_2107_05613_amd import workloads as W
     t0 = time.perf_counter()
-    mix = serve.build_mix(num=args.serving_requests, seed=0, slots=8, precond_bits=0)
+    mix = serve.build_mix(num=args.serving_requests, seed=0, slots=8, precond_bits=0,
+                          extension=args.serving_extension)
     print(f"[bench] serving: {len(mix.keys)} hierarchies built in {time.perf_counter() - t0:.1f}s "
           f"(build {mix.build_s:.1f}s, device setup {mix.setup_s:.1f}s)", file=sys.stderr, flush=True)
     srv, ids = serve.make_server(mix, chunk=8)
@@ -461,7 +462,8 @@ def run_serving(args):
             kind, n, cs = key
             w = W.Workload(f"{kind}_n{n}_c{cs}", kind, n, W.default_levels(n), "blocks", coef_seed=cs)
             a, be = W.coefficients(w)
-            fp64[i] = amge.Hierarchy(amge.build_problem(kind, n, w.levels, a, be), precond_bits=64, max_rhs=8)
+            fp64[i] = amge.Hierarchy(amge.build_problem(kind, n, w.levels, a, be, extension=args.serving_extension,
+                                                        device=True), precond_bits=64, max_rhs=8)
             rebuilt.append(fp64[i])
     mix64 = serve.Mix(mix.requests, mix.keys, fp64, mix.hid_of, mix.rhs, mix.x)
     srv64, ids64 = serve.make_server(mix64, chunk=8)
@@ -483,7 +485,7 @@ def run_serving(args):
                      f"{{16,24,32,48,64}} drawn uniformly, per-4^3-block coefficient jumps 10^U(-3,3) from a pool "
                      f"of 2 seeds per (type, n): {mix_desc['keys']} resident hierarchies, 8 PCG columns each; "
                      f"V-cycle precision per hierarchy from trial solves at set-up, per-column FP64 PCG "
-                     f"to rel-res 1e-8"),
+                     f"to rel-res 1e-8; local extensions: {args.serving_extension}"),
         "precision": {"fp32_hierarchies": len(fp32_keys), "fp64_hierarchies": len(prec) - len(fp32_keys),
                       "fp32": [f"{k[0]} n={k[1]} seed {k[2]}" for k in fp32_keys],
                       "kappa_range": [min(k for k, b in prec), max(k for k, b in prec)]},
@@ -568,6 +570,8 @@ def main():
                     help="multi-right-hand-side workload timed beside the main one ('' to skip)")
     ap.add_argument("--serving-requests", type=int, default=256,
                     help="requests of the serving mix run beside the main workload (0 to skip)")
+    ap.add_argument("--serving-extension", choices=("l2", "coefficient"), default="l2",
+                    help="extension of the serving hierarchies' local problems (remark closing section 3.3)")
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--oracle-dir", default=None)
@@ -608,13 +612,22 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    torch.zeros(1, device="cuda")
+    torch.cuda.synchronize()
+    # set-up: the level matrices built with the GPU steps of the builder (Galerkin products
+    # on the device), the host-only build timed beside it; then the device hierarchies
     t0 = time.perf_counter()
-    prod = amge.build_problem(w.kind, w.n, w.levels, a, b)
+    prod = amge.build_problem(w.kind, w.n, w.levels, a, b, device=True)
     t_build = time.perf_counter() - t0
-    torch.cuda.init()
+    t0 = time.perf_counter()
+    amge.build_problem(w.kind, w.n, w.levels, a, b)
+    t_build_host = time.perf_counter() - t0
     t0 = time.perf_counter()
     H32 = amge.Hierarchy(prod, precond_bits=32)
+    torch.cuda.synchronize()
+    t_setup32 = time.perf_counter() - t0
     H64 = amge.Hierarchy(prod, precond_bits=64)
+    torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     n1 = H32.rows[0]
     rhs = torch.from_numpy(W.rhs(n1, w.rhs_seed)[:, 0]).cuda()
@@ -757,7 +770,11 @@ def main():
         "smoother_sym_gs": gs,
         "configs": small,
         "extension_and_boundary_options": options,
-        "setup_s": {"build": t_build, "device_setup": t_setup},
+        "setup_s": {"build": t_build, "build_host_only": t_build_host, "device_setup": t_setup,
+                    "device_setup_fp32_hierarchy": t_setup32,
+                    "note": ("build: level matrices with the builder's GPU steps (AMGE_BUILD_DEVICE); "
+                             "device_setup: the FP32- and FP64-V-cycle hierarchies (layouts filled on the "
+                             "device, set-up products on the device, tuning)")},
         "batched": batched,
         "serving": serving,
     }

@@ -80,16 +80,20 @@ Csr csr_from_view(const amge_csr& v) {
     A.ncols = v.ncols;
     A.rowptr.assign(v.rowptr, v.rowptr + v.nrows + 1);
     if (A.rowptr[0] != 0 || A.rowptr[v.nrows] != v.nnz) fail(AMGE_ERR_SHAPE, "CSR rowptr does not span nnz");
+    for (int32_t i = 0; i < v.nrows; ++i)
+        if (A.rowptr[i + 1] < A.rowptr[i]) fail(AMGE_ERR_SHAPE, "CSR rowptr not monotone");
     A.col.assign(v.col, v.col + v.nnz);
     A.val.assign(v.val, v.val + v.nnz);
-    for (int32_t i = 0; i < v.nrows; ++i) {
-        if (A.rowptr[i + 1] < A.rowptr[i]) fail(AMGE_ERR_SHAPE, "CSR rowptr not monotone");
-        for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
-            if (A.col[k] < 0 || A.col[k] >= v.ncols) fail(AMGE_ERR_SHAPE, "CSR column index out of range");
-            if (k > A.rowptr[i] && A.col[k] <= A.col[k - 1]) fail(AMGE_ERR_SHAPE, "CSR columns not sorted/unique");
-            if (!std::isfinite(A.val[k])) fail(AMGE_ERR_NONFINITE, "non-finite CSR value");
-        }
-    }
+    // rows checked in parallel; the first failing chunk's error is reported
+    parallel_for(v.nrows, [&](int64_t s, int64_t e) {
+        for (int64_t i = s; i < e; ++i)
+            for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+                if (A.col[k] < 0 || A.col[k] >= v.ncols) fail(AMGE_ERR_SHAPE, "CSR column index out of range");
+                if (k > A.rowptr[i] && A.col[k] <= A.col[k - 1])
+                    fail(AMGE_ERR_SHAPE, "CSR columns not sorted/unique");
+                if (!std::isfinite(A.val[k])) fail(AMGE_ERR_NONFINITE, "non-finite CSR value");
+            }
+    });
     return A;
 }
 
@@ -293,8 +297,10 @@ void drop_small(Csr& A, double rel) {
 
 std::vector<double> l1_row_sums(const Csr& A) {
     std::vector<double> d(A.nrows, 0.0);
-    for (int32_t i = 0; i < A.nrows; ++i)
-        for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) d[i] += std::fabs(A.val[k]);
+    parallel_for(A.nrows, [&](int64_t s, int64_t e) {
+        for (int64_t i = s; i < e; ++i)
+            for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) d[i] += std::fabs(A.val[k]);
+    });
     return d;
 }
 

@@ -30,7 +30,7 @@ class Mix:
 
 
 def build_mix(num=256, seed=0, sizes=(16, 24, 32, 48, 64), coef_pool=2, slots=8, precond_bits=0,
-              nu_primary=2, nu_aux=2, tail_rows=2048):
+              nu_primary=2, nu_aux=2, tail_rows=2048, extension="l2"):
     """Hierarchies for every (kind, n, coefficient seed) of the stream (coefficients as the
     jump workload: per 4^3-hex block 10^U(-3,3)), and one right-hand side per request
     (seed = request id).  precond_bits 0 lets every hierarchy pick its V-cycle precision
@@ -43,7 +43,7 @@ def build_mix(num=256, seed=0, sizes=(16, 24, 32, 48, 64), coef_pool=2, slots=8,
         w = W.Workload(f"{kind}_n{n}_c{cs}", kind, n, W.default_levels(n), "blocks", coef_seed=cs)
         a, b = W.coefficients(w)
         t0 = time.perf_counter()
-        prod = amge.build_problem(kind, n, w.levels, a, b)
+        prod = amge.build_problem(kind, n, w.levels, a, b, extension=extension, device=True)
         t1 = time.perf_counter()
         hs.append(amge.Hierarchy(prod, precond_bits=precond_bits, max_rhs=slots, nu_primary=nu_primary,
                                  nu_aux=nu_aux, tail_rows=tail_rows(n) if callable(tail_rows) else tail_rows))
