@@ -83,9 +83,10 @@ typedef struct {
     int32_t nu_aux;         /* point-smoother sweeps on D^T A D per smoothing step (paper: 2) */
     int32_t precond_bits;   /* 64: V-cycle in FP64; 32: FP32 values/accumulation in the
                                V-cycle with the coarsest Cholesky solve kept in FP64;
-                               0: chosen at set-up by one trial PCG solve per precision on a
-                               fixed pseudo-random right-hand side to rtol 1e-8: 32 if the
-                               FP32 V-cycle converges within 3 iterations of the FP64 one */
+                               0: chosen at set-up by trial PCG solves on a fixed
+                               pseudo-random right-hand side to rtol 1e-8: FP32 (with the
+                               first resid_bits that works, 32 then 64) if it converges
+                               within 3 iterations of the FP64 V-cycle, else FP64            */
     int32_t max_rhs;        /* largest nrhs of a context of this hierarchy (1 <= max_rhs <= 64);
                                > 1 also builds the batched operators                        */
     int32_t tail_rows;      /* coarse-tail folding: while the level above the coarse tail
@@ -104,6 +105,15 @@ typedef struct {
                                increasing then decreasing order, each row by
                                x_i += (b - A x)_i / a_ii.  Single-column contexts only
                                (max_rhs = 1).                                                 */
+    int32_t resid_bits;     /* FP32 V-cycles: precision of the fine-level residual b - A x that
+                               is restricted to level 2 (Algorithm 4.1).  32: FP32 values and
+                               sums; 64: the FP64 values of A_1 summed in FP64, the result
+                               rounded to FP32 once (one FP64-value pass over A_1 per V-cycle
+                               instead of an FP32 one).  On high-contrast coefficients the
+                               FP32 residual loses the small mass part of A x near the range
+                               of D (see amge_precision_info); the FP64 one keeps the FP32
+                               V-cycle converging like the FP64 one.  0: 32, or chosen by the
+                               trial when precond_bits = 0.  Ignored for FP64 V-cycles.      */
     /* Caller's device allocator (both NULL: hipMalloc / hipFree).  alloc(bytes, user)
      * returns device memory of at least `bytes` bytes, 256-byte aligned, or NULL (the
      * call then fails with AMGE_ERR_OOM); dealloc(ptr, user) returns it.  The library
@@ -245,9 +255,11 @@ amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precision, int32_
 /* Cancellation factor kappa = max over levels and rows e of (|D|^T |A| |D| 1)_e /
  * (|D^T A D| 1)_e (D^T A D keeps only the mass part of A, so products of A with vectors
  * near the range of D cancel up to this factor; their rounding error is ~ u * kappa
- * relative), and the preconditioner precision in use (32 or 64).  Either pointer may be
- * NULL. */
-amge_status amge_precision_info(const amge_hierarchy* h, double* kappa, int32_t* precond_bits);
+ * relative), the preconditioner precision in use (32 or 64) and, for an FP32 V-cycle,
+ * the precision of its fine-level residual (32 or 64; 64 for an FP64 V-cycle).  Any
+ * pointer may be NULL. */
+amge_status amge_precision_info(const amge_hierarchy* h, double* kappa, int32_t* precond_bits,
+                                int32_t* resid_bits);
 
 /* Host sizes of a hierarchy: nlevels, and rows of A_k for k = 0..nlevels-1 (rows[] may be NULL). */
 amge_status amge_hierarchy_info(const amge_hierarchy* h, int32_t* nlevels, int32_t* rows);

@@ -53,8 +53,8 @@ DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 class OptsC(C.Structure):
     _fields_ = [("nu_primary", C.c_int32), ("nu_aux", C.c_int32), ("precond_bits", C.c_int32),
-                ("max_rhs", C.c_int32), ("tail_rows", C.c_int32), ("smoother", C.c_int32), ("alloc", ALLOC_FN),
-                ("dealloc", DEALLOC_FN), ("alloc_user", C.c_void_p)]
+                ("max_rhs", C.c_int32), ("tail_rows", C.c_int32), ("smoother", C.c_int32),
+                ("resid_bits", C.c_int32), ("alloc", ALLOC_FN), ("dealloc", DEALLOC_FN), ("alloc_user", C.c_void_p)]
 
 
 SMOOTHERS = {"l1jacobi": 0, "symgs": 1}
@@ -97,7 +97,7 @@ def _load():
         "amge_pcg_solve": (i32, [vp, vp, vp, i32, f64, i32, i32, C.POINTER(i32), C.POINTER(f64), vp]),
         "amge_level_apply": (i32, [vp, i32, i32, i32, vp, vp, vp, vp]),
         "amge_hierarchy_info": (i32, [vp, C.POINTER(i32), C.POINTER(i32)]),
-        "amge_precision_info": (i32, [vp, C.POINTER(f64), C.POINTER(i32)]),
+        "amge_precision_info": (i32, [vp, C.POINTER(f64), C.POINTER(i32), C.POINTER(i32)]),
         "amge_timing_enable": (i32, [vp, i32]),
         "amge_vcycle_bytes": (i32, [vp, i32, i32, C.POINTER(f64)]),
         "amge_timing_read": (i32, [vp, C.POINTER(f64), C.POINTER(C.c_int64), C.POINTER(f64)]),
@@ -272,15 +272,16 @@ class Hierarchy:
     methods vcycle / pcg / level_apply / timing_* use a default context of max_rhs
     columns, created on first use.
 
-    precond_bits: 32, 64 or 0 (chosen from the cancellation factor); max_rhs: widest
-    block of a context (the batched path); tail_rows: levels of at most this many rows
-    below the fine one are folded into one dense FP64 operator (0: every level runs its
-    kernels); smoother: "l1jacobi" or "symgs" (symmetric Gauss-Seidel in colour order,
-    single-column contexts only); allocator: "torch" (torch's caching allocator) or None
-    (hipMalloc)."""
+    precond_bits: 32, 64 or 0 (chosen by trial solves at set-up); max_rhs: widest block
+    of a context (the batched path); tail_rows: levels of at most this many rows below the
+    fine one are folded into one dense FP64 operator (0: every level runs its kernels);
+    smoother: "l1jacobi" or "symgs" (symmetric Gauss-Seidel in colour order, single-column
+    contexts only); resid_bits: precision of an FP32 V-cycle's fine-level residual (32,
+    64, or 0: 32 unless the trial picks 64); allocator: "torch" (torch's caching
+    allocator) or None (hipMalloc)."""
 
     def __init__(self, levels, nu_primary=2, nu_aux=2, precond_bits=32, max_rhs=1, tail_rows=2048, stream=None,
-                 allocator="torch", smoother="l1jacobi"):
+                 allocator="torch", smoother="l1jacobi", resid_bits=0):
         L = len(levels)
         arr = (LevelC * L)()
         self._keep = []
@@ -300,7 +301,8 @@ class Hierarchy:
             al, de = ALLOC_FN(), DEALLOC_FN()
         else:
             raise ValueError("allocator must be 'torch' or None")
-        opts = OptsC(nu_primary, nu_aux, precond_bits, max_rhs, tail_rows, SMOOTHERS[smoother], al, de, None)
+        opts = OptsC(nu_primary, nu_aux, precond_bits, max_rhs, tail_rows, SMOOTHERS[smoother], resid_bits, al, de,
+                     None)
         h = C.c_void_p()
         _check(_lib.amge_setup_hierarchy(arr, L, C.byref(opts), _stream(stream), C.byref(h)))
         self._h = h
@@ -347,8 +349,14 @@ class Hierarchy:
     def precision_info(self):
         """(kappa, precond_bits in use)."""
         k, b = C.c_double(), C.c_int32()
-        _check(_lib.amge_precision_info(self._h, C.byref(k), C.byref(b)))
+        _check(_lib.amge_precision_info(self._h, C.byref(k), C.byref(b), None))
         return k.value, b.value
+
+    def resid_bits(self):
+        """Precision of an FP32 V-cycle's fine-level residual (32 or 64; 64 for FP64 V-cycles)."""
+        r = C.c_int32()
+        _check(_lib.amge_precision_info(self._h, None, None, C.byref(r)))
+        return r.value
 
     def footprint_parts(self, nrhs=None):
         """(hierarchy bytes, bytes of one context of nrhs columns; default max_rhs)."""

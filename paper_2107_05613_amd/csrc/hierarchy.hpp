@@ -92,6 +92,10 @@ template <> inline const float* GsColors::dg<float>() const { return dg32; }
 struct DLevel {
     int n = 0, m = 0;
     Probe* probe = nullptr;
+    // FP32 V-cycle: the residual b - A x ahead of the restriction is formed with the FP64
+    // values of A, summed in FP64 and rounded to FP32 once (opts.resid_bits = 64; fine
+    // level only)
+    bool resid64 = false;
     GsColors gsA, gsAh;       // symmetric Gauss-Seidel smoother (opts.smoother)
     DSell A, Ah, P, Pt;
     DSell Aux;                // [D^T | -D^T A]: auxiliary residual D^T b - (D^T A) x

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "state.hpp"
 
 namespace amge {
@@ -83,13 +85,16 @@ __device__ __forceinline__ T stream_load(const T* __restrict__ p) {
 // other than A_k, so that A_k, used four times per V-cycle, stays in the last-level
 // cache between its uses: the fine-level FP32 sweep of the 64^3 H(curl) workload takes
 // 45 instead of 50 us).  UNR: entries per lane whose loads are issued together (8 for
-// the long rows of a large fine level, 4 otherwise).
-template <typename T, int K, int MODE, bool C16, bool NT, int UNR = 4>
+// the long rows of a large fine level, 4 otherwise).  TV: the matrix value type, T by
+// default; FP64 values with FP32 vectors (the fine-level residual of an FP32 V-cycle on
+// high-contrast problems) sum in FP64 and round the result to T once.
+template <typename T, int K, int MODE, bool C16, bool NT, int UNR = 4, typename TV = T>
 __global__ void __launch_bounds__(BLOCK)
 k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, const int* __restrict__ ci,
-       const uint16_t* __restrict__ c16, const int* __restrict__ cbase, const T* __restrict__ av,
+       const uint16_t* __restrict__ c16, const int* __restrict__ cbase, const TV* __restrict__ av,
        const T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv, T* __restrict__ y,
        T* __restrict__ yd, const uint16_t* __restrict__ lead, const int* __restrict__ stop) {
+    using TA = typename std::conditional<(sizeof(TV) > sizeof(T)), TV, T>::type;   // accumulation
     // SPMV / SPLIT with yd != null also write yd = dinv * y: the first l1-Jacobi sweep
     // from zero on the next operator, produced where its right-hand side is produced.
     // Every launch of the PCG iteration returns without writing when *stop is set
@@ -111,7 +116,7 @@ k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, 
     if (stopped | (slice >= nslices) | (end < base) | (row < -1) | (cb < 0)) return;
     const int width = (end - base) >> 6;
     const int e0 = base + lane;
-    const T* v = av + e0;
+    const TV* v = av + e0;
     // the row's own operands of the update are requested before the product, so their
     // latency overlaps it
     const bool owner = row >= 0 && !(lane & (K - 1));
@@ -128,23 +133,23 @@ k_sell(int nslices, const int* __restrict__ sptr, const int* __restrict__ srow, 
     } else if (yd) {
         dr = dinv[rw];
     }
-    T acc = 0;
+    TA acc = 0;
 #pragma unroll UNR
     for (int k = 0; k < width; ++k) {
         const int j = col_at<C16, NT>(ci, c16, cb, e0 + k * 64);
         T xv;
         if (MODE == SPLIT) xv = (k * K + (lane & (K - 1)) < nlead ? b : x)[j];   // entry k*K + lane%K
         else xv = x[j];
-        acc = fma(stream_load<T, NT || sizeof(T) == 8>(v + k * 64), xv, acc);
+        acc = fma((TA)stream_load<TV, NT || sizeof(TV) == 8>(v + k * 64), (TA)xv, acc);
     }
     acc = row_sum<K>(acc);
     if (!owner) return;
     if (MODE == SPMV || MODE == SPLIT) {
-        y[row] = acc;
-        if (yd) yd[row] = dr * acc;
-    } else if (MODE == SPMV_ADD) y[row] = xr + acc;
-    else if (MODE == RESID) y[row] = br - acc;
-    else y[row] = xr + dr * (br - acc);
+        y[row] = (T)acc;
+        if (yd) yd[row] = dr * (T)acc;
+    } else if (MODE == SPMV_ADD) y[row] = xr + (T)acc;
+    else if (MODE == RESID) y[row] = (T)((TA)br - acc);
+    else y[row] = xr + dr * (T)((TA)br - acc);
 }
 
 // One colour of a multicolour Gauss-Seidel sweep, in place: for the rows of the colour

@@ -9,6 +9,8 @@
 // wave are consecutive.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -64,13 +66,16 @@ struct Pack {
 // covers 64 / L consecutive slots of one slice and a slice takes L waves; the matrix
 // entries of those slots are consecutive (coalesced), each broadcast to the L lanes of
 // its row.  Every column sums its row's entries in CSR order whatever W, L and V are.
-// Modes as in Mode (kernels.hpp); YD (SPMV, SPLIT) also receives dinv * y.
-template <typename T, int V, int MODE, bool C16, class G>
+// Modes as in Mode (kernels.hpp); YD (SPMV, SPLIT) also receives dinv * y.  TV: the
+// matrix value type (T by default; FP64 values with FP32 blocks sum in FP64 and round
+// each result once, as in k_sell).
+template <typename T, int V, int MODE, bool C16, class G, typename TV = T>
 __device__ __forceinline__ void
 sell_mm(G g, int nslices, int L, int NC, const int* __restrict__ sptr, const int* __restrict__ srow,
           const int* __restrict__ ci, const uint16_t* __restrict__ c16, const int* __restrict__ cbase,
-          const T* __restrict__ av, const T* __restrict__ X, const T* __restrict__ B, const T* __restrict__ dinv,
+          const TV* __restrict__ av, const T* __restrict__ X, const T* __restrict__ B, const T* __restrict__ dinv,
           T* __restrict__ Y, T* __restrict__ YD, const uint16_t* __restrict__ lead, const int* __restrict__ stop) {
+    using TA = typename std::conditional<(sizeof(TV) > sizeof(T)), TV, T>::type;   // accumulation
     const int gw = xcd_block(g.bid(), g.nb()) * WAVES + ((int)threadIdx.x >> 6);
     const int slice = gw / L;
     const int lane = threadIdx.x & 63;
@@ -87,14 +92,14 @@ sell_mm(G g, int nslices, int L, int NC, const int* __restrict__ sptr, const int
     const int nlead = MODE == SPLIT ? lead[sl * 64 + rr] : 0;
     if (stopped | (slice >= nslices) | (end < base) | (row < -1) | (cb < 0)) return;   // last three never hold
     const int width = (end - base) >> 6;
-    Pack<T, V> acc;
+    Pack<TA, V> acc;
 #pragma unroll
     for (int i = 0; i < V; ++i) acc.v[i] = 0;
 #pragma unroll 4
     for (int k = 0; k < width; ++k) {
         const int e = base + k * 64 + rr;
         const int j = C16 ? cb + (int)c16[e] : ci[e];
-        const T a = av[e];
+        const TA a = av[e];
         Pack<T, V> xv;
         if (MODE == SPLIT) {
             xv.load((k < nlead ? B : X) + (int64_t)j * NC + col);
@@ -107,29 +112,31 @@ sell_mm(G g, int nslices, int L, int NC, const int* __restrict__ sptr, const int
             xv.load(X + (int64_t)j * NC + col);
         }
 #pragma unroll
-        for (int i = 0; i < V; ++i) acc.v[i] = fma(a, xv.v[i], acc.v[i]);
+        for (int i = 0; i < V; ++i) acc.v[i] = fma(a, (TA)xv.v[i], acc.v[i]);
     }
     if (row < 0) return;
     const int64_t o = (int64_t)row * NC + col;
     Pack<T, V> out;
     if (MODE == SPMV || MODE == SPLIT) {
-        acc.store(Y + o);
+#pragma unroll
+        for (int i = 0; i < V; ++i) out.v[i] = (T)acc.v[i];
+        out.store(Y + o);
         if (YD) {
             const T d = dinv[row];
 #pragma unroll
-            for (int i = 0; i < V; ++i) out.v[i] = d * acc.v[i];
+            for (int i = 0; i < V; ++i) out.v[i] = d * (T)acc.v[i];
             out.store(YD + o);
         }
     } else if (MODE == SPMV_ADD) {
         out.load(Y + o);
 #pragma unroll
-        for (int i = 0; i < V; ++i) out.v[i] += acc.v[i];
+        for (int i = 0; i < V; ++i) out.v[i] += (T)acc.v[i];
         out.store(Y + o);
     } else if (MODE == RESID) {
         Pack<T, V> bv;
         bv.load(B + o);
 #pragma unroll
-        for (int i = 0; i < V; ++i) out.v[i] = bv.v[i] - acc.v[i];
+        for (int i = 0; i < V; ++i) out.v[i] = (T)((TA)bv.v[i] - acc.v[i]);
         out.store(Y + o);
     } else if (MODE == JAC0) {
         Pack<T, V> bv;
@@ -137,7 +144,7 @@ sell_mm(G g, int nslices, int L, int NC, const int* __restrict__ sptr, const int
         const T d = dinv[row];
         // x0 = dinv b rounded on its own (not contracted into the update), as if stored
 #pragma unroll
-        for (int i = 0; i < V; ++i) out.v[i] = mul_rn(d, bv.v[i]) + d * (bv.v[i] - acc.v[i]);
+        for (int i = 0; i < V; ++i) out.v[i] = mul_rn(d, bv.v[i]) + d * (bv.v[i] - (T)acc.v[i]);
         out.store(Y + o);
     } else {   // JAC
         Pack<T, V> bv, xv;
@@ -145,18 +152,18 @@ sell_mm(G g, int nslices, int L, int NC, const int* __restrict__ sptr, const int
         xv.load(X + o);
         const T d = dinv[row];
 #pragma unroll
-        for (int i = 0; i < V; ++i) out.v[i] = xv.v[i] + d * (bv.v[i] - acc.v[i]);
+        for (int i = 0; i < V; ++i) out.v[i] = xv.v[i] + d * (bv.v[i] - (T)acc.v[i]);
         out.store(Y + o);
     }
 }
 
 // Launch tags of the batched bodies: block size, the solo signature, the body.
-template <typename T, int V, int MODE, bool C16>
+template <typename T, int V, int MODE, bool C16, typename TV = T>
 struct SellMM {
     static constexpr int block = BLOCK;
-    using sig = decltype(&sell_mm<T, V, MODE, C16, HwGrid>);
+    using sig = decltype(&sell_mm<T, V, MODE, C16, HwGrid, TV>);
     template <class G, class... A>
-    __device__ static void run(G g, A... a) { sell_mm<T, V, MODE, C16>(g, a...); }
+    __device__ static void run(G g, A... a) { sell_mm<T, V, MODE, C16, G, TV>(g, a...); }
 };
 
 // Y += D X for a signed incidence in the same layout (index-only entries, bit 31 =

@@ -18,6 +18,7 @@
 #include <numeric>
 #include <thread>
 #include <tuple>
+#include <type_traits>
 
 #include "common.hpp"
 #include "hierarchy.hpp"
@@ -455,11 +456,62 @@ DSell upload_incidence(amge_hierarchy* H, const Csr& D, hipStream_t s) {
 // Launch of an A_k kernel; on a probed level the launch is bracketed by events and its
 // algorithmic bytes are counted: values + column indices, one row index per row, and
 // the vector streams of the mode (x gathered once, b, dinv, y).
+// y = b - A x with FP32 vectors and the FP64 values of A, summed in FP64 (the
+// fine-level residual of an FP32 V-cycle with opts.resid_bits = 64).
+template <int K, int UNR>
+void sell_resid64_ku(const DSell& M, const float* x, const float* b, float* y, hipStream_t s, const int* stop) {
+    const unsigned g = grid_slices(M.nslices);
+    if (g == 0) return;
+    if (M.c16)
+        dev::k_sell<float, K, dev::RESID, true, true, UNR, double><<<g, BLOCK, 0, s>>>(
+            M.nslices, M.sptr, M.srow, M.ci, M.c16, M.cbase, M.v64, x, b, nullptr, y, nullptr, M.lead, stop);
+    else
+        dev::k_sell<float, K, dev::RESID, false, true, UNR, double><<<g, BLOCK, 0, s>>>(
+            M.nslices, M.sptr, M.srow, M.ci, M.c16, M.cbase, M.v64, x, b, nullptr, y, nullptr, M.lead, stop);
+}
+
+template <int K>
+void sell_resid64_k(const DSell& M, const float* x, const float* b, float* y, hipStream_t s, const int* stop) {
+    if constexpr (K <= 8) {
+        if (M.deep) {
+            sell_resid64_ku<K, 8>(M, x, b, y, s, stop);
+            return;
+        }
+    }
+    sell_resid64_ku<K, 4>(M, x, b, y, s, stop);
+}
+
+void sell_resid64(const DSell& M, const float* x, const float* b, float* y, hipStream_t s, const int* stop) {
+    if (!M.v64) fail(AMGE_ERR_ARG, "FP64 residual on a matrix without FP64 values");
+    switch (M.K) {
+        case 1: sell_resid64_k<1>(M, x, b, y, s, stop); break;
+        case 2: sell_resid64_k<2>(M, x, b, y, s, stop); break;
+        case 4: sell_resid64_k<4>(M, x, b, y, s, stop); break;
+        case 8: sell_resid64_k<8>(M, x, b, y, s, stop); break;
+        case 16: sell_resid64_k<16>(M, x, b, y, s, stop); break;
+        case 32: sell_resid64_k<32>(M, x, b, y, s, stop); break;
+        default: sell_resid64_k<64>(M, x, b, y, s, stop); break;
+    }
+}
+
+// A launch on A_k (probed on the fine level when timing is on); the residual of an FP32
+// level with resid64 takes the FP64 values.
+template <class T>
+void asell_launch(DLevel& L, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s, const int* stop) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (L.resid64 && mode == dev::RESID) {
+            sell_resid64(L.A, x, b, y, s, stop);
+            return;
+        }
+    }
+    sell<T>(L.A, mode, x, b, dinv, y, s, stop);
+}
+
 template <class T>
 void asell(DLevel& L, int mode, const T* x, const T* b, const T* dinv, T* y, hipStream_t s, const int* stop) {
     Probe* pr = L.probe;
     if (!pr || !pr->on) {
-        sell<T>(L.A, mode, x, b, dinv, y, s, stop);
+        asell_launch<T>(L, mode, x, b, dinv, y, s, stop);
         return;
     }
     if (pr->ev.size() < 2 * (pr->used + 1)) {
@@ -470,11 +522,12 @@ void asell(DLevel& L, int mode, const T* x, const T* b, const T* dinv, T* y, hip
         pr->ev.push_back(c);
     }
     HIPCHECK(hipEventRecord(pr->ev[2 * pr->used], s));
-    sell<T>(L.A, mode, x, b, dinv, y, s, stop);
+    asell_launch<T>(L, mode, x, b, dinv, y, s, stop);
     HIPCHECK(hipEventRecord(pr->ev[2 * pr->used + 1], s));
     pr->used++;
     const double nv = mode == dev::JAC ? 4 : 3;   // JAC: x, b, dinv, y; others: three streams
-    pr->bytes += (double)L.A.nnz * (sizeof(T) + (L.A.c16 ? 2 : 4)) + 4.0 * L.n + nv * sizeof(T) * L.n;
+    const double vs = (std::is_same<T, float>::value && L.resid64 && mode == dev::RESID) ? 8 : sizeof(T);
+    pr->bytes += (double)L.A.nnz * (vs + (L.A.c16 ? 2 : 4)) + 4.0 * L.n + nv * sizeof(T) * L.n;
 }
 
 template <class T>
@@ -704,6 +757,38 @@ void bmm_m(const DSellB& M, int mode, int W, int NC, const T* X, const T* B, con
 
 // Columns per lane actually used: the tuned V, at most the active width W.
 inline int lane_cols(int V, int W) { return std::min(V, W); }
+
+// Y = B - A X on FP32 blocks with the FP64 values of A, summed in FP64 (the fine-level
+// residual of an FP32 batched V-cycle with opts.resid_bits = 64).
+template <int V>
+void bmm_resid64_v(const DSellB& M, int W, int NC, const float* X, const float* B, float* Y, const int* stop,
+                   hipStream_t s) {
+    const int L = W / V;
+    const unsigned grid = (unsigned)(((int64_t)M.nslices * L + WAVES - 1) / WAVES);
+    if (!grid) return;
+    if (M.c16)
+        launch<dev::SellMM<float, V, dev::RESID, true, double>>(grid, s, M.nslices, L, NC, M.sptr, M.srow, M.ci,
+                                                                M.c16, M.cbase, (const double*)M.v64, X, B,
+                                                                (const float*)nullptr, Y, (float*)nullptr, M.lead,
+                                                                stop);
+    else
+        launch<dev::SellMM<float, V, dev::RESID, false, double>>(grid, s, M.nslices, L, NC, M.sptr, M.srow, M.ci,
+                                                                 M.c16, M.cbase, (const double*)M.v64, X, B,
+                                                                 (const float*)nullptr, Y, (float*)nullptr, M.lead,
+                                                                 stop);
+}
+
+void bmm_resid64(const DSellB& M, int W, int NC, const float* X, const float* B, float* Y, const int* stop,
+                 hipStream_t s) {
+    if (!M.v64) fail(AMGE_ERR_ARG, "FP64 residual on a matrix without FP64 values");
+    switch (lane_cols(M.V, W)) {
+        case 1: bmm_resid64_v<1>(M, W, NC, X, B, Y, stop, s); break;
+        case 2: bmm_resid64_v<2>(M, W, NC, X, B, Y, stop, s); break;
+        case 4: bmm_resid64_v<4>(M, W, NC, X, B, Y, stop, s); break;
+        case 8: bmm_resid64_v<8>(M, W, NC, X, B, Y, stop, s); break;
+        default: bmm_resid64_v<16>(M, W, NC, X, B, Y, stop, s); break;
+    }
+}
 
 // Block product on the first W (active) of the NC stored columns.
 template <class T>
@@ -947,7 +1032,12 @@ void bvcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, i
     const bool next_coarsest = l + 1 == H->tail;   // needs no first sweep of its own
     bprimary<T>(H, L, b, bd, x, xt, true, nup, W, stop, s);
     bauxiliary<T>(H, L, b, x, nua, W, stop, s);
-    bmm<T>(L.bA, dev::RESID, W, NC, x, b, nullptr, w.r, stop, s);
+    if constexpr (std::is_same<T, float>::value) {
+        if (L.resid64) bmm_resid64(L.bA, W, NC, x, b, w.r, stop, s);
+        else bmm<T>(L.bA, dev::RESID, W, NC, x, b, nullptr, w.r, stop, s);
+    } else {
+        bmm<T>(L.bA, dev::RESID, W, NC, x, b, nullptr, w.r, stop, s);
+    }
     bmm<T>(L.bPt, dev::SPMV, W, NC, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, stop, s,
               next_coarsest ? nullptr : wc.bd);
     bvcycle_level<T>(H, l + 1, wc.b, wc.bd, wc.x, W, stop, s);
@@ -1156,19 +1246,22 @@ double cancellation_factor(const Csr& A, const Csr& D, const Csr& Dt, const std:
 amge_status pcg(amge_hierarchy* H, const double* b, double* x, double rtol, int maxit, int stop_l2, int* iters,
                 double* relres, hipStream_t s);
 
-// Automatic V-cycle precision (opts.precond_bits = 0): one trial PCG solve per precision
-// on a fixed pseudo-random right-hand side (uniform in [-1, 1), splitmix64 of the row
-// index), to rtol 1e-8 in the preconditioner norm.  The FP32 V-cycle is kept when it
-// converges within AUTO_FP32_EXTRA iterations of the FP64 one.  Neither the cancellation
-// factor nor the FP32 cycle's deviation on one vector predicts this: on the jump
-// workloads FP32 costs nothing on every H(div) hierarchy up to n = 32 (kappa 5.5e7) but
-// 60 % more iterations on an H(curl) one with n = 24 (kappa 2.5e7), and stalls at n >= 48.
+// Automatic V-cycle precision (opts.precond_bits = 0): trial PCG solves on a fixed
+// pseudo-random right-hand side (uniform in [-1, 1), splitmix64 of the row index), to
+// rtol 1e-8 in the preconditioner norm.  An FP32 V-cycle is kept when it converges within
+// AUTO_FP32_EXTRA iterations of the FP64 one: first with the FP32 fine-level residual,
+// then with the FP64 one.  Neither the cancellation factor nor the FP32 cycle's deviation
+// on one vector predicts this: on the jump workloads the all-FP32 cycle costs nothing on
+// every H(div) hierarchy up to n = 32 (kappa 5.5e7) but 60 % more iterations on an
+// H(curl) one with n = 24 (kappa 2.5e7), and stalls at n >= 48; with the fine-level
+// residual in FP64 it takes the FP64 iteration count on those too.
 constexpr int AUTO_FP32_EXTRA = 3;
 constexpr double AUTO_TRIAL_RTOL = 1e-8;
 constexpr int AUTO_TRIAL_MAXIT = 1000;
 
-int trial_precision(amge_hierarchy* H, hipStream_t s) {
-    if (H->lv.size() < 2) return 64;   // no V-cycle: the preconditioner is the FP64 coarse solve
+// Returns {precond_bits, resid_bits}.
+std::pair<int, int> trial_precision(amge_hierarchy* H, hipStream_t s) {
+    if (H->lv.size() < 2) return {64, 64};   // no V-cycle: the preconditioner is the FP64 coarse solve
     const int n = H->lv[0].n;
     std::vector<double> b(n);
     for (int i = 0; i < n; ++i) {
@@ -1183,10 +1276,14 @@ int trial_precision(amge_hierarchy* H, hipStream_t s) {
     double* db = tmp.alloc<double>(n);
     double* dx = tmp.alloc<double>(n);
     HIPCHECK(hipMemcpyAsync(db, b.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
-    int its[2] = {0, 0};
-    for (int p = 0; p < 2; ++p) {
-        H->opts.precond_bits = p ? 32 : 64;
-        const int maxit = p ? its[0] + AUTO_FP32_EXTRA : AUTO_TRIAL_MAXIT;
+    // candidates in order: FP64; FP32 with the FP32 fine-level residual; FP32 with the
+    // FP64 one.  The first FP32 candidate within AUTO_FP32_EXTRA iterations of FP64 wins.
+    const int bits[3] = {64, 32, 32}, resid[3] = {64, 32, 64};
+    int it64 = -1;
+    for (int p = 0; p < 3; ++p) {
+        H->opts.precond_bits = bits[p];
+        H->lv[0].resid64 = resid[p] == 64 && bits[p] == 32;
+        const int maxit = p ? it64 + AUTO_FP32_EXTRA : AUTO_TRIAL_MAXIT;
         int it = 0;
         double rr = 0;
         amge_status st = AMGE_ERR_BREAKDOWN;
@@ -1196,13 +1293,20 @@ int trial_precision(amge_hierarchy* H, hipStream_t s) {
         } catch (const Error& e) {
             if (e.code == AMGE_ERR_OOM || e.code == AMGE_ERR_HIP) throw;
         }
-        its[p] = st == AMGE_OK ? it : -1;
+        const int its = st == AMGE_OK ? it : -1;
         if (verbose())
-            fprintf(stderr, "[amge precision] FP%d trial: %d iterations (status %d)\n", p ? 32 : 64, it, (int)st);
-        if (its[0] < 0) break;   // FP64 itself did not converge: keep FP64
+            fprintf(stderr, "[amge precision] FP%d trial (fine residual FP%d): %d iterations (status %d)\n", bits[p],
+                    resid[p], it, (int)st);
+        H->lv[0].resid64 = false;
+        H->opts.precond_bits = 0;
+        if (p == 0) {
+            if (its < 0) return {64, 64};   // FP64 itself did not converge: keep FP64
+            it64 = its;
+        } else if (its >= 0 && its <= it64 + AUTO_FP32_EXTRA) {
+            return {32, resid[p]};
+        }
     }
-    H->opts.precond_bits = 0;
-    return its[0] >= 0 && its[1] >= 0 && its[1] <= its[0] + AUTO_FP32_EXTRA ? 32 : 64;
+    return {64, 64};
 }
 
 // ------------------------------------------------------------------ coarse-tail folding
@@ -1598,7 +1702,13 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
     clk.lap("other per-level work");
     fold_tail(H, tl, ainv, s);
     clk.lap("folded coarse tail");
-    if (H->opts.precond_bits == 0) H->opts.precond_bits = trial_precision(H, s);
+    if (H->opts.precond_bits == 0) {
+        const std::pair<int, int> pr = trial_precision(H, s);
+        H->opts.precond_bits = pr.first;
+        H->opts.resid_bits = pr.second;
+    }
+    if (H->opts.resid_bits == 0) H->opts.resid_bits = 32;
+    H->lv[0].resid64 = H->opts.precond_bits == 32 && H->opts.resid_bits == 64 && H->lv.size() > 1;
     clk.lap("precision trial");
     if (batched) setup_batched(H, hl, s);
     clk.lap("batched layouts, tuning");
@@ -2156,6 +2266,7 @@ extern "C" void amge_default_opts(amge_opts* o) {
     o->max_rhs = 1;
     o->tail_rows = 2048;
     o->smoother = AMGE_SMOOTHER_L1_JACOBI;
+    o->resid_bits = 0;
     o->alloc = nullptr;
     o->dealloc = nullptr;
     o->alloc_user = nullptr;
@@ -2171,7 +2282,8 @@ extern "C" amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nl
         else amge_default_opts(&H->opts);
         if (H->opts.nu_primary < 0 || H->opts.nu_aux < 0 || H->opts.max_rhs < 1 || H->opts.max_rhs > 64 ||
             H->opts.tail_rows < 0 || H->opts.tail_rows > 8192 ||
-            (H->opts.precond_bits != 0 && H->opts.precond_bits != 32 && H->opts.precond_bits != 64))
+            (H->opts.precond_bits != 0 && H->opts.precond_bits != 32 && H->opts.precond_bits != 64) ||
+            (H->opts.resid_bits != 0 && H->opts.resid_bits != 32 && H->opts.resid_bits != 64))
             fail(AMGE_ERR_ARG, "invalid options");
         if ((H->opts.alloc == nullptr) != (H->opts.dealloc == nullptr))
             fail(AMGE_ERR_ARG, "give both alloc and dealloc, or neither");
@@ -2208,13 +2320,15 @@ extern "C" amge_status amge_footprint(const amge_hierarchy* h, int32_t nrhs, siz
     });
 }
 
-extern "C" amge_status amge_precision_info(const amge_hierarchy* h, double* kappa, int32_t* precond_bits) {
+extern "C" amge_status amge_precision_info(const amge_hierarchy* h, double* kappa, int32_t* precond_bits,
+                                           int32_t* resid_bits) {
     if (!h) {
         set_last_error("null argument");
         return AMGE_ERR_ARG;
     }
     if (kappa) *kappa = h->kappa;
     if (precond_bits) *precond_bits = h->opts.precond_bits;
+    if (resid_bits) *resid_bits = (h->opts.precond_bits == 32 && !h->lv.empty() && !h->lv[0].resid64) ? 32 : 64;
     return AMGE_OK;
 }
 
@@ -2501,7 +2615,10 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
             if (!batched && L.PtA.nrows) {
                 tot += mat(L.PtA, L.bPt) + 2.0 * nc + sx * (2 * n) + 2 * sx * nc;
             } else {
-                tot += mat(L.A, L.bA) + 3 * sx * n;
+                // an FP32 cycle's fine-level residual with resid64 reads the FP64 values
+                const double extra = (precision == 32 && L.resid64)
+                                         ? (double)(batched ? L.bA.nnz : L.A.nnz) * (8.0 - sv) : 0.0;
+                tot += mat(L.A, L.bA) + extra + 3 * sx * n;
                 tot += mat(L.Pt, L.bPt) + sx * (n + nc);
             }
             tot += mat(L.P, L.bP) + sx * (nc + 2 * n);

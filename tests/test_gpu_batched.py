@@ -270,3 +270,38 @@ def test_batched_widest_block(nrhs):
     # FP32 preconditioner converges in every column
     status, its, rrs = c.gpu[32].pcg(dev(B), X, rtol=1e-8, nrhs=nrhs)
     assert status == 0 and max(rrs) <= 1e-8
+
+
+def test_batched_fp64_fine_residual():
+    """The batched FP32 V-cycle with the fine-level residual in FP64 (resid_bits = 64) on
+    the 24^3 H(curl) jump workload: every column converges within 3 iterations of the
+    same column's FP64 batched solve, and each column's solution is within 1e-6 of the
+    single-column FP32 + FP64-residual solve (both FP32 preconditioners, FP64 PCG)."""
+    from paper_2107_05613_amd import amge
+    w = W.Workload("t", "curl", 24, W.default_levels(24), "blocks", coef_seed=0)
+    a, b = W.coefficients(w)
+    prod = amge.build_problem(w.kind, w.n, w.levels, a, b)
+    k = 4
+    H64 = amge.Hierarchy(prod, precond_bits=64, max_rhs=k)
+    Hm = amge.Hierarchy(prod, precond_bits=32, resid_bits=64, max_rhs=k)
+    n = Hm.rows[0]
+    B = W.rhs(n, 21, k)
+    X = torch.zeros(n * k, dtype=torch.float64, device="cuda")
+    st, it64, _ = H64.pcg(dev(B), X, rtol=1e-8, maxit=1000, nrhs=k)
+    X.zero_()
+    st, itm, rrm = Hm.pcg(dev(B), X, rtol=1e-8, maxit=1000, nrhs=k)
+    Xm = host(X).reshape(n, k)
+    H1 = amge.Hierarchy(prod, precond_bits=32, resid_bits=64)
+    errs = []
+    for j in range(k):
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        H1.pcg(dev(np.ascontiguousarray(B[:, j])), x, rtol=1e-8, maxit=1000)
+        xj = host(x)
+        errs.append(float(np.linalg.norm(Xm[:, j] - xj) / np.linalg.norm(xj)))
+    print(f"batched curl n=24 jumps: FP64 {it64}, FP32 + FP64 fine residual {itm}; vs single column "
+          f"{[f'{e:.1e}' for e in errs]}")
+    assert st == 0 and max(rrm) <= 1e-8
+    assert all(itm[j] <= it64[j] + 3 for j in range(k))
+    assert max(errs) <= 1e-6
+    for H in (H64, Hm, H1):
+        H.close()

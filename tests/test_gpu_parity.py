@@ -349,24 +349,75 @@ def test_cancellation_factor_and_auto_precision(spec):
     H.close()
 
 
-def test_auto_precision_keeps_fp64_where_fp32_slows_down():
-    """precond_bits = 0 on a hierarchy whose FP32 V-cycle needs far more iterations (the
-    24^3 H(curl) jump workload: ~220 vs ~140) keeps FP64."""
+def _curl24_jumps():
     amge = _amge()
     w = W.Workload("t", "curl", 24, W.default_levels(24), "blocks", coef_seed=0)
     a, b = W.coefficients(w)
-    prod = amge.build_problem(w.kind, w.n, w.levels, a, b)
+    return w, a, b, amge.build_problem(w.kind, w.n, w.levels, a, b)
+
+
+def test_fine_residual_fp64_values():
+    """resid_bits = 64: the fine-level residual of an FP32 V-cycle takes the FP64 values
+    of A_1 and sums in FP64: on FP32 inputs x, b it returns fl32(b - A x) of the exact
+    FP64 product up to the FP64 summation (1 FP32 ulp of the result plus 1e-13 |A||x|),
+    also where A x cancels (x with a large gradient part on the 24^3 H(curl) jump
+    workload); the FP32 kernel is off by far more there."""
+    amge = _amge()
+    w, _, _, prod = _curl24_jumps()
+    A = prod[0][0].to_scipy()
+    D = prod[0][1].to_scipy()
+    rng = np.random.default_rng(11)
+    x = (1e3 * (D @ rng.uniform(-1, 1, D.shape[1])) + rng.uniform(-1, 1, A.shape[0])).astype(np.float32)
+    b = rng.uniform(-1, 1, A.shape[0]).astype(np.float32)
+    x64, b64 = x.astype(np.float64), b.astype(np.float64)
+    ref = b64 - A @ x64
+    scale = np.abs(b64) + abs(A) @ np.abs(x64)
+    ulp = np.spacing(np.abs(ref.astype(np.float32))).astype(np.float64)
+    out = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
+    err = {}
+    for rb in (64, 32):
+        H = amge.Hierarchy(prod, precond_bits=32, resid_bits=rb)
+        assert H.resid_bits() == rb
+        H.level_apply(0, amge.OP_RESID, dev(b64), out, x2=dev(x64), precision=32)
+        d = np.abs(host(out) - ref)
+        err[rb] = (float(np.max(d / (ulp + 1e-13 * scale))), float(np.median(np.abs(ref) / scale)))
+        H.close()
+    print(f"fine residual vs fl32(exact): FP64 values {err[64][0]:.2f} (ulp + 1e-13 |A||x|), FP32 values "
+          f"{err[32][0]:.1e}; median |r| / (|b| + |A||x|) = {err[64][1]:.1e}")
+    assert err[64][0] <= 1.0
+    assert err[32][0] > 100.0
+
+
+def test_auto_precision_fp64_fine_residual():
+    """The 24^3 H(curl) jump workload: the all-FP32 V-cycle needs far more PCG iterations
+    than the FP64 one (~200 vs ~137); with the fine-level residual in FP64 (resid_bits =
+    64) the FP32 V-cycle takes the FP64 count (+3), so precond_bits = 0 keeps FP32 with
+    resid_bits 64.  Its solution is within 1e-6 of the oracle's (same level matrices)."""
+    from oracle.solve import Multilevel, pcg
+    amge = _amge()
+    w, a, b, prod = _curl24_jumps()
     H = amge.Hierarchy(prod, precond_bits=0)
-    bits = H.precision_info()[1]
-    rhs = dev(W.rhs(H.rows[0], 3)[:, 0])
-    its = {}
-    for p in (32, 64):
-        G = amge.Hierarchy(prod, precond_bits=p)
-        st, it, _ = G.pcg(rhs, torch.zeros_like(rhs), rtol=1e-8, maxit=1000)
-        its[p] = it[0]
+    bits, rbits = H.precision_info()[1], H.resid_bits()
+    rhs = W.rhs(H.rows[0], 3)[:, 0]
+    its, xs = {}, {}
+    for p, rb in ((64, 0), (32, 32), (32, 64)):
+        G = amge.Hierarchy(prod, precond_bits=p, resid_bits=rb)
+        x = torch.zeros_like(dev(rhs))
+        st, it, _ = G.pcg(dev(rhs), x, rtol=1e-8, maxit=1000)
+        its[(p, rb)], xs[(p, rb)] = it[0], host(x)
         G.close()
-    print(f"curl n=24 jumps: auto precision FP{bits}; FP32 {its[32]} vs FP64 {its[64]} iterations")
-    assert its[32] > its[64] + 3 and bits == 64
+    L = len(prod)
+    Ao = [prod[k][0].to_scipy() for k in range(L)]
+    Do = [prod[k][1].to_scipy() for k in range(L)]
+    Po = [prod[k][2].to_scipy() if k < L - 1 else None for k in range(L)]
+    xo, ito, _ = pcg(Ao[0], rhs, Multilevel(Ao, Do, Po), rtol=1e-8)
+    e = float(np.linalg.norm(xs[(32, 64)] - xo) / np.linalg.norm(xo))
+    print(f"curl n=24 jumps: auto FP{bits} with FP{rbits} fine residual; iterations FP64 {its[(64, 0)]}, "
+          f"FP32 {its[(32, 32)]}, FP32 + FP64 fine residual {its[(32, 64)]}, oracle {ito}; error vs oracle {e:.1e}")
+    assert its[(32, 32)] > its[(64, 0)] + 3
+    assert its[(32, 64)] <= its[(64, 0)] + 3 and abs(its[(64, 0)] - ito) <= 1
+    assert bits == 32 and rbits == 64
+    assert e <= 1e-6
     H.close()
 
 
