@@ -570,8 +570,9 @@ def main():
                     help="multi-right-hand-side workload timed beside the main one ('' to skip)")
     ap.add_argument("--serving-requests", type=int, default=256,
                     help="requests of the serving mix run beside the main workload (0 to skip)")
-    ap.add_argument("--serving-extension", choices=("l2", "coefficient"), default="l2",
-                    help="extension of the serving hierarchies' local problems (remark closing section 3.3)")
+    ap.add_argument("--serving-extension", choices=("l2", "coefficient"), default="coefficient",
+                    help="extension of the serving hierarchies' local problems (remark closing section 3.3): "
+                         "coefficient-weighted (default) or unweighted L2")
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--oracle-dir", default=None)

@@ -34,7 +34,7 @@ SLOTS = 4
 
 
 class Resident:
-    def __init__(self, precond_bits):
+    def __init__(self, precond_bits, resid_bits=0):
         from paper_2107_05613_amd import amge
         self.prods, self.H, self.n1 = [], [], []
         for kind, n, L, coef, cs in SPECS:
@@ -42,17 +42,17 @@ class Resident:
             a, b = W.coefficients(w)
             prod = amge.build_problem(kind, n, L, a, b)
             self.prods.append((w, a, b))
-            self.H.append(amge.Hierarchy(prod, precond_bits=precond_bits, max_rhs=SLOTS))
+            self.H.append(amge.Hierarchy(prod, precond_bits=precond_bits, max_rhs=SLOTS, resid_bits=resid_bits))
             self.n1.append(self.H[-1].rows[0])
 
 
 _RES = {}
 
 
-def resident(bits):
-    if bits not in _RES:
-        _RES[bits] = Resident(bits)
-    return _RES[bits]
+def resident(bits, resid_bits=0):
+    if (bits, resid_bits) not in _RES:
+        _RES[(bits, resid_bits)] = Resident(bits, resid_bits)
+    return _RES[(bits, resid_bits)]
 
 
 def requests(res, num, seed=0):
@@ -237,12 +237,16 @@ def test_served_fp64_matches_oracle():
         assert err <= tol
 
 
-def test_served_fp32_matches_oracle():
-    """Served requests on FP32-preconditioner hierarchies, run to rtol 1e-8: within 3
-    iterations of the oracle's FP64 count and within 1e-6 of its solution (printed)."""
+@pytest.mark.parametrize("resid_bits", [32, 64])
+def test_served_fp32_matches_oracle(resid_bits):
+    """Served requests on FP32-preconditioner hierarchies (fine-level residual in FP32, or
+    in FP64 as the precision trial picks for high-contrast hierarchies), run to rtol 1e-8:
+    within 3 iterations of the oracle's FP64 count and within 1e-6 of its solution
+    (printed)."""
     from oracle.hierarchy import build_hierarchy
     from oracle.solve import Multilevel, pcg
-    res = resident(32)
+    res = resident(32, resid_bits)
+    assert all(H.resid_bits() == resid_bits for H in res.H)
     reqs = requests(res, 6, seed=4)
     out = serve(res, reqs, list(range(len(reqs))))
     oracles = {}
