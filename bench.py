@@ -421,6 +421,7 @@ def run_serving(args):
     resident = srv.stats()["resident_bytes"]
     prec = [h.precision_info() for h in mix.hierarchies]
     fp32_keys = [k for k, (_, b) in zip(mix.keys, prec) if b == 32]
+    resid64_keys = [k for k, (_, b), h in zip(mix.keys, prec, mix.hierarchies) if b == 32 and h.resid_bits() == 64]
     # warm-up: one request per hierarchy
     first = {}
     for j, h in enumerate(mix.hid_of):
@@ -488,6 +489,7 @@ def run_serving(args):
                      f"to rel-res 1e-8; local extensions: {args.serving_extension}"),
         "precision": {"fp32_hierarchies": len(fp32_keys), "fp64_hierarchies": len(prec) - len(fp32_keys),
                       "fp32": [f"{k[0]} n={k[1]} seed {k[2]}" for k in fp32_keys],
+                      "fp32_with_fp64_fine_residual": [f"{k[0]} n={k[1]} seed {k[2]}" for k in resid64_keys],
                       "kappa_range": [min(k for k, b in prec), max(k for k, b in prec)]},
         "resident_bytes": resident,
         "burst": {"solves_per_s": burst, "makespan_s": makespan, **serve.latency_stats(lat), "by_size": burst_by},
