@@ -145,3 +145,46 @@ def test_builder_galerkin_products_bitwise(kind, n, L, coef):
             assert Md.shape == Mh.shape
             assert np.array_equal(Md.rowptr, Mh.rowptr) and np.array_equal(Md.col, Mh.col), (k, i)
             assert np.array_equal(Md.val.view(np.uint64), Mh.val.view(np.uint64)), (k, i)
+
+
+def test_permuted_fine_level_uses_32bit_indices():
+    """A random renumbering of the fine-level dofs (A -> Q^T A Q, D -> Q^T D, P -> Q^T P)
+    spreads every slice's columns over the whole range (238,688 dofs), so the fine-level
+    layouts need 32-bit column indices (k_slice_range flags them, k_sell_fill writes
+    them).  The device-filled layouts equal the host-built ones bit for bit, and the
+    renumbered problem is the same problem: FP64 PCG takes the same iteration count (+-1)
+    and its solution, renumbered back, is within 1e-10 of the original one's."""
+    import scipy.sparse as sp
+    from paper_2107_05613_amd import amge
+    lv = _levels("curl", 32, 3, "unit")   # unit coefficients: FP64 reorderings agree to ~1e-13
+    n1 = lv[0][0].shape[0]
+    perm = np.random.default_rng(17).permutation(n1)
+    Q = sp.csr_matrix((np.ones(n1), (perm, np.arange(n1))), shape=(n1, n1))   # Q e_i = e_perm[i]
+    A, D, P = (m.to_scipy() for m in lv[0])
+    plv = [((Q.T @ A @ Q).tocsr(), (Q.T @ D).tocsr(), (Q.T @ P).tocsr())] + \
+          [tuple(None if m is None else m.to_scipy() for m in lk) for lk in lv[1:]]
+    kw = dict(precond_bits=64)
+    Hh, Hd = _hier(plv, True, **kw), _hier(plv, False, **kw)
+    b = W.rhs(n1, 2)[:, 0]
+    bp = Q.T @ b
+    rng = np.random.default_rng(1)
+    x = torch.from_numpy(rng.uniform(-1, 1, n1)).cuda()
+    for op in (amge.OP_A, amge.OP_SWEEP, amge.OP_RESID):
+        oh, od = torch.empty_like(x), torch.empty_like(x)
+        x2 = torch.from_numpy(rng.uniform(-1, 1, n1)).cuda()
+        Hh.level_apply(0, op, x, oh, x2=x2, precision=64)
+        Hd.level_apply(0, op, x, od, x2=x2, precision=64)
+        assert _same(oh, od), op
+    H0 = amge.Hierarchy(lv, **kw)
+    x0 = torch.zeros(n1, dtype=torch.float64, device="cuda")
+    xp = torch.zeros_like(x0)
+    _, it0, _ = H0.pcg(torch.from_numpy(b).cuda(), x0, rtol=1e-8)
+    _, itp, _ = Hd.pcg(torch.from_numpy(bp).cuda(), xp, rtol=1e-8)
+    H0.pcg(torch.from_numpy(b).cuda(), x0, rtol=0.0, maxit=it0[0])
+    Hd.pcg(torch.from_numpy(bp).cuda(), xp, rtol=0.0, maxit=it0[0])
+    xs = Q @ xp.cpu().numpy()
+    e = float(np.linalg.norm(xs - x0.cpu().numpy()) / np.linalg.norm(x0.cpu().numpy()))
+    print(f"renumbered fine level: iterations {itp[0]} vs {it0[0]}, solution difference {e:.1e}")
+    assert abs(itp[0] - it0[0]) <= 1 and e <= 1e-10
+    for h in (Hh, Hd, H0):
+        h.close()
