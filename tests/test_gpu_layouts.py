@@ -188,3 +188,41 @@ def test_permuted_fine_level_uses_32bit_indices():
     assert abs(itp[0] - it0[0]) <= 1 and e <= 1e-10
     for h in (Hh, Hd, H0):
         h.close()
+
+
+def test_set_up_product_with_a_row_beyond_the_device_tables():
+    """A set-up product with a row of more distinct columns than the largest device hash
+    table (4096): D^T A and D^T A D of a 'star' derivative whose first column touches all
+    6000 rows.  That product runs on the host instead; the hierarchy equals the one set up
+    with every product on the host, bit for bit (auxiliary operator and V-cycle)."""
+    import scipy.sparse as sp
+    from paper_2107_05613_amd import amge
+    n = 6000
+    rng = np.random.default_rng(4)
+    off = sp.random(n, n, density=4.0 / n, random_state=5, format="csr")
+    off = (off + off.T) * 0.1
+    A = (off + sp.diags(np.asarray(abs(off).sum(axis=1)).ravel() + 1.0)).tocsr()
+    # D: column 0 touches every row (the star), plus a second entry per row
+    rows = np.concatenate([np.arange(n), np.arange(n)])
+    cols = np.concatenate([np.zeros(n, dtype=int), 1 + (np.arange(n) % 1999)])
+    vals = np.concatenate([np.ones(n), -np.ones(n)])
+    D = sp.csr_matrix((vals, (rows, cols)), shape=(n, 2000))
+    P = sp.csr_matrix((np.ones(n), (np.arange(n), np.arange(n) // 60)), shape=(n, 100))
+    Ac = (P.T @ A @ P).tocsr()
+    Dc = sp.identity(100, format="csr")
+    levels = [(A, D, P), (Ac, Dc, None)]
+    Hh, Hd = _hier(levels, True, precond_bits=64), _hier(levels, False, precond_bits=64)
+    y = torch.from_numpy(rng.uniform(-1, 1, 2000)).cuda()
+    oh, od = torch.empty_like(y), torch.empty_like(y)
+    Hh.level_apply(0, amge.OP_AHAT, y, oh, precision=64)
+    Hd.level_apply(0, amge.OP_AHAT, y, od, precision=64)
+    ref = (D.T @ A @ D) @ y.cpu().numpy()
+    assert _same(oh, od)
+    assert np.max(np.abs(od.cpu().numpy() - ref)) <= 1e-12 * np.max(np.abs(ref))
+    b = torch.from_numpy(rng.uniform(-1, 1, n)).cuda()
+    zh, zd = torch.empty_like(b), torch.empty_like(b)
+    Hh.vcycle(b, zh)
+    Hd.vcycle(b, zd)
+    assert _same(zh, zd)
+    Hh.close()
+    Hd.close()
