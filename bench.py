@@ -413,7 +413,7 @@ def run_serving(args):
     from paper_2107_05613_amd import amge, serve
     from paper_2107_05613_amd import workloads as W
     t0 = time.perf_counter()
-    mix = serve.build_mix(num=args.serving_requests, seed=0, slots=8, precond_bits=0,
+    mix = serve.build_mix(num=args.serving_requests, seed=0, slots=args.serving_slots, precond_bits=0,
                           extension=args.serving_extension)
     print(f"[bench] serving: {len(mix.keys)} hierarchies built in {time.perf_counter() - t0:.1f}s "
           f"(build {mix.build_s:.1f}s, device setup {mix.setup_s:.1f}s)", file=sys.stderr, flush=True)
@@ -464,7 +464,7 @@ def run_serving(args):
             w = W.Workload(f"{kind}_n{n}_c{cs}", kind, n, W.default_levels(n), "blocks", coef_seed=cs)
             a, be = W.coefficients(w)
             fp64[i] = amge.Hierarchy(amge.build_problem(kind, n, w.levels, a, be, extension=args.serving_extension,
-                                                        device=True), precond_bits=64, max_rhs=8)
+                                                        device=True), precond_bits=64, max_rhs=args.serving_slots)
             rebuilt.append(fp64[i])
     mix64 = serve.Mix(mix.requests, mix.keys, fp64, mix.hid_of, mix.rhs, mix.x)
     srv64, ids64 = serve.make_server(mix64, chunk=8)
@@ -484,7 +484,8 @@ def run_serving(args):
     out = {
         "workload": (f"{len(mix_desc['requests'])} seeded requests, H(curl)/H(div) on n^3x6 Kuhn tets with n in "
                      f"{{16,24,32,48,64}} drawn uniformly, per-4^3-block coefficient jumps 10^U(-3,3) from a pool "
-                     f"of 2 seeds per (type, n): {mix_desc['keys']} resident hierarchies, 8 PCG columns each; "
+                     f"of 2 seeds per (type, n): {mix_desc['keys']} resident hierarchies, {args.serving_slots} PCG "
+                     f"columns each; "
                      f"V-cycle precision per hierarchy from trial solves at set-up, per-column FP64 PCG "
                      f"to rel-res 1e-8; local extensions: {args.serving_extension}"),
         "precision": {"fp32_hierarchies": len(fp32_keys), "fp64_hierarchies": len(prec) - len(fp32_keys),
@@ -575,6 +576,7 @@ def main():
     ap.add_argument("--serving-extension", choices=("l2", "coefficient"), default="coefficient",
                     help="extension of the serving hierarchies' local problems (remark closing section 3.3): "
                          "coefficient-weighted (default) or unweighted L2")
+    ap.add_argument("--serving-slots", type=int, default=8, help="PCG columns per serving hierarchy")
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--oracle-dir", default=None)
