@@ -224,7 +224,8 @@ amge_status amge_pcg_solve(amge_ctx* c, const double* b, double* x, int32_t nrhs
  *       AMGE_OP_SWEEP   out = x + d^{-1} (b - A x), b = in, x = in2: one l1-Jacobi sweep,
  *                       d_i = sum_j |a_ij| (the V-cycle's sweep kernel, eq. (4.1))
  *       AMGE_OP_RESID   out = b - A x, b = in, x = in2 (the V-cycle's residual kernel,
- *                       Algorithm 4.1)
+ *                       Algorithm 4.1; on the fine level at precision 32 with resid_bits =
+ *                       64 in use, the FP64-value kernel with FP64 sums)
  * On the fine level, SWEEP and RESID run exactly the launches the V-cycle times with
  * amge_timing_enable. */
 enum {
