@@ -1,4 +1,4 @@
-"""Oracle, solve phase: l1-Jacobi hybrid smoother, V-cycle, inexact PCG (FP64).
+"""Oracle, solve phase: hybrid smoother (l1-Jacobi, Gauss-Seidel), V-cycle, inexact PCG (FP64).
 
 Test infrastructure only (see the package docstring).
 
@@ -9,7 +9,7 @@ Paper anchors
   with the correction mapped back through D.  The transpose smoother runs the
   two steps in reverse order with the transposed point smoothers.
 * Section 4.1 (smoother choice) and section 5.1: two sweeps for the primary and
-  for the auxiliary smoothing.  Two point smoothers:
+  for the auxiliary smoothing.  Three point smoothers:
   - l1-Jacobi (default), d_i = sum_j |a_ij| (the l1 scaling of the cited smoother
     paper with point blocks); its sweeps are symmetric so M^{-T} = M^{-1};
   - symmetric Gauss-Seidel in colour order (smoother="symgs"), the smoother the
@@ -21,6 +21,20 @@ Paper anchors
     l1 term of the cited smoother, which covers couplings to rows relaxed in parallel
     in other blocks, is empty when the colours are the blocks.  One symmetric sweep
     is symmetric, so again M^{-T} = M^{-1}.
+  - l1-scaled symmetric block Gauss-Seidel (smoother="l1blockgs"), the smoother of
+    the cited smoother paper with row blocks in place of processors: row i belongs
+    to block i // gs_block (contiguous ranges of gs_block rows); inside a block the
+    rows are coloured greedily over the couplings within the block (first fit in
+    increasing row order) and relaxed colour by colour, forward through the colours
+    and then backward through all of them again, each row i by
+        x_i += (b_i - sum_{j in block} a_ij x_j - sum_{j not in block} a_ij x0_j) / d_i,
+        d_i = a_ii + sum_{j not in block} |a_ij|,
+    where x holds the current values and x0 the values at the start of the sweep
+    (couplings across blocks are relaxed Jacobi-fashion, their weight moved to the
+    diagonal: the l1 scaling).  Blocks of one row give a closed form built from
+    l1-Jacobi steps, one block holding every row gives the Gauss-Seidel above, and
+    the sweep is symmetric, x += Mb^{-1} (D + 2 D_l1) Mf^{-1} (b - A x) with Mf / Mb
+    the block lower / upper factors (pinned by tests).
   The auxiliary sweeps start from zero.
 * Algorithm 4.1: V-cycle, pre-relax, restrict with P^T, recurse or coarse solve,
   prolong, post-relax with the transposed smoother.
@@ -72,8 +86,66 @@ def gs_sweep(A, diag, classes, b, x, blocks=None):
     return x
 
 
+def block_coloring(A, blk):
+    """Colour of every row over the couplings inside its own block (blk[i] is row i's
+    block): the smallest non-negative integer not held by an earlier row of the same
+    block coupled to it (a_ij != 0, j < i)."""
+    A = A.tocsr()
+    n = A.shape[0]
+    color = np.full(n, -1, dtype=np.int64)
+    for i in range(n):
+        used = set()
+        lo, hi = A.indptr[i], A.indptr[i + 1]
+        for j, v in zip(A.indices[lo:hi], A.data[lo:hi]):
+            if j < i and v != 0 and blk[j] == blk[i]:
+                used.add(int(color[j]))
+        c = 0
+        while c in used:
+            c += 1
+        color[i] = c
+    return color
+
+
+class BlockGS:
+    """Data of the l1-scaled symmetric block Gauss-Seidel sweep on A for a row partition
+    blk: the couplings inside and across blocks, d_i = a_ii + sum_{j not in block}
+    |a_ij|, and the rows of every colour (colours taken over couplings inside blocks)."""
+
+    def __init__(self, A, blk):
+        A = A.tocsr()
+        self.A = A
+        blk = np.asarray(blk)
+        coo = A.tocoo()
+        inside = blk[coo.row] == blk[coo.col]
+        n = A.shape[0]
+        self.A_in = sp.csr_matrix((coo.data[inside], (coo.row[inside], coo.col[inside])), shape=(n, n))
+        self.A_off = sp.csr_matrix((coo.data[~inside], (coo.row[~inside], coo.col[~inside])), shape=(n, n))
+        self.d = A.diagonal() + l1_diag(self.A_off)
+        color = block_coloring(A, blk)
+        C = int(color.max()) + 1 if n else 0
+        self.classes = [np.nonzero(color == c)[0] for c in range(C)]
+        self.rows_in = [self.A_in[rows] for rows in self.classes]
+
+    def sweep(self, b, x):
+        """One symmetric sweep: colours 0..C-1, then C-1..0; couplings across blocks
+        read the values x0 at the start of the sweep."""
+        x0 = x
+        off = self.A_off @ x0
+        x = x0.copy()
+        order = list(range(len(self.classes)))
+        for c in order + order[::-1]:
+            rows = self.classes[c]
+            x[rows] += (b[rows] - off[rows] - self.rows_in[c] @ x) / self.d[rows]
+        return x
+
+
+def contiguous_blocks(n, block):
+    """Block index of every row for contiguous ranges of `block` rows."""
+    return np.arange(n) // int(block)
+
+
 class SolveLevel:
-    def __init__(self, A, D, P=None, nu_primary=2, nu_aux=2, smoother="l1jacobi"):
+    def __init__(self, A, D, P=None, nu_primary=2, nu_aux=2, smoother="l1jacobi", gs_block=64):
         self.A = A.tocsr()
         self.D = D.tocsr()
         self.Ahat = (self.D.T @ self.A @ self.D).tocsr()
@@ -88,6 +160,9 @@ class SolveLevel:
             self.classes_hat = self._classes(greedy_coloring(self.Ahat))
             self.blocks = [self.A[rows] for rows in self.classes]
             self.blocks_hat = [self.Ahat[rows] for rows in self.classes_hat]
+        elif smoother == "l1blockgs":
+            self.bgs = BlockGS(self.A, contiguous_blocks(self.A.shape[0], gs_block))
+            self.bgs_hat = BlockGS(self.Ahat, contiguous_blocks(self.Ahat.shape[0], gs_block))
         elif smoother != "l1jacobi":
             raise ValueError(smoother)
 
@@ -99,10 +174,10 @@ class SolveLevel:
 class Multilevel:
     """Algorithm 4.1 over a list of levels; the last one is solved by Cholesky."""
 
-    def __init__(self, As, Ds, Ps, nu_primary=2, nu_aux=2, smoother="l1jacobi"):
+    def __init__(self, As, Ds, Ps, nu_primary=2, nu_aux=2, smoother="l1jacobi", gs_block=64):
         L = len(As)
         self.levels = [SolveLevel(As[k], Ds[k], Ps[k] if k < L - 1 else None, nu_primary, nu_aux,
-                                  smoother if k < L - 1 else "l1jacobi")
+                                  smoother if k < L - 1 else "l1jacobi", gs_block)
                        for k in range(L)]
         self.chol = sla.cho_factor(As[-1].toarray(), lower=True)
 
@@ -116,6 +191,8 @@ class Multilevel:
         for _ in range(lv.nu_primary):
             if lv.smoother == "symgs":
                 x = gs_sweep(lv.A, lv.diag, lv.classes, b, x, lv.blocks)
+            elif lv.smoother == "l1blockgs":
+                x = lv.bgs.sweep(b, x)
             else:
                 x = x + (b - lv.A @ x) / lv.d
         return x
@@ -127,6 +204,8 @@ class Multilevel:
         for _ in range(lv.nu_aux):
             if lv.smoother == "symgs":
                 y = gs_sweep(lv.Ahat, lv.diaghat, lv.classes_hat, g, y, lv.blocks_hat)
+            elif lv.smoother == "l1blockgs":
+                y = lv.bgs_hat.sweep(g, y)
             else:
                 y = y + (g - lv.Ahat @ y) / lv.dhat
         return x + lv.D @ y
