@@ -3,7 +3,9 @@
 One step = one complete PCG solve (FP32 V-cycle preconditioner inside FP64 inexact
 PCG, stopped at relative residual 1e-8 in the preconditioner norm) of the H(curl)
 system on the 64^3 x 6 Kuhn mesh with the 5-level hierarchy, starting from the
-right-hand side already resident in HBM.  The same solve with an all-FP64 V-cycle
+right-hand side already resident in HBM.  The hybrid smoother's point smoother is the
+l1-scaled symmetric block Gauss-Seidel of the paper's experiments (64-row blocks; the
+other point smoothers are timed beside it, --smoother picks the headline's).  The same solve with an all-FP64 V-cycle
 ("plain FP64 PCG") is timed beside it, and the V-cycle's achieved bandwidth is
 reported from its algorithmic bytes.
 
@@ -15,7 +17,7 @@ grouped-launch comparison on small hierarchies, and the oracle timed on one host
 
 Prints one JSON line (rank 0).  Options: --gpus N (only 1 is supported), --steps K,
 --warmup W, --workload NAME, --no-cpu-baseline, --batched-workload NAME ("" to skip),
---serving-requests N (0 to skip), --grouped-ab-only CONFIG (one configuration of the
+--serving-requests N (0 to skip), --smoother NAME, --grouped-ab-only CONFIG (one configuration of the
 small-hierarchy serving burst alone, for kernel traces), --copy-calibration (a 1 GiB
 device copy first: the reference kernel of the HBM counter runs).
 """
@@ -33,6 +35,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solves/s + V-cycle HBM GB/s, FP32-precond vs FP64 PCG at rel-res 1e-8"
 PEAK_HBM_GBPS = 8000.0
+SMOOTHER_NAMES = {"l1blockgs": "l1-scaled symmetric block Gauss-Seidel (64-row blocks)",
+                  "l1jacobi": "l1-Jacobi", "symgs": "symmetric Gauss-Seidel in colour order"}
+ROOFLINE_KERNELS = {
+    "l1blockgs": ("fine-level A_1 kernels on the block layout (block Gauss-Seidel sweeps, the first from zero "
+                  "reading the in-block entries only, and the residual; FP32 values, 16-bit codes)"),
+    "l1jacobi": "fine-level A_1 sliced-ELL kernels (l1-Jacobi sweeps + residual, FP32, 16-bit column offsets)",
+    "symgs": "fine-level A_1 sliced-ELL residual (the colour sweeps are separate launches)"}
 
 
 def measured_traffic():
@@ -62,7 +71,7 @@ def _oracle_sample(H, ml, rhs, iters):
     return (time.perf_counter() - t0) / (iters + 1)
 
 
-def cpu_baseline_worker(workloads, budget_s: float, outdir: str):
+def cpu_baseline_worker(workloads, budget_s: float, outdir: str, smoother: str = "l1jacobi"):
     """Oracle leg (separate process, one thread per process).  Per workload: the oracle
     hierarchy is built (not timed); its FP64 PCG solve to the workload's rtol gives the
     reference solution (saved to outdir for the GPU results' errors); a bounded number
@@ -81,7 +90,7 @@ def cpu_baseline_worker(workloads, budget_s: float, outdir: str):
         a, b = W.coefficients(w)
         t0 = time.perf_counter()
         H = build_hierarchy(w.kind, w.n, w.levels, a, b, check_targets=False)
-        ml = Multilevel.from_hierarchy(H)
+        ml = Multilevel.from_hierarchy(H, smoother=smoother)
         t_build = time.perf_counter() - t0
         rhs = W.rhs(H.A[0].shape[0], w.rhs_seed)[:, 0]
         t0 = time.perf_counter()
@@ -112,7 +121,7 @@ def cpu_baseline_worker(workloads, budget_s: float, outdir: str):
     print(json.dumps(res), flush=True)
 
 
-def run_cpu_baseline(workloads, budget_s=20.0):
+def run_cpu_baseline(workloads, budget_s=20.0, smoother="l1jacobi"):
     """Runs cpu_baseline_worker in a subprocess (BLAS and OpenMP pinned to one thread per
     process); returns (its JSON, directory of the oracle's reference solutions)."""
     import tempfile
@@ -121,7 +130,7 @@ def run_cpu_baseline(workloads, budget_s=20.0):
         env[k] = "1"
     outdir = tempfile.mkdtemp(prefix="amge_oracle_")
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", "--workload", ",".join(workloads),
-           "--cpu-budget", str(budget_s), "--oracle-dir", outdir]
+           "--cpu-budget", str(budget_s), "--oracle-dir", outdir, "--smoother", smoother]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, env=env, timeout=1500)
     if r.returncode != 0:
         return {"error": f"oracle worker exited with {r.returncode}"}, outdir
@@ -151,7 +160,7 @@ def baseline_entry(res, iters_needed):
                        f"workload and rhs: {res['sample_iters']} iterations timed on 1 core "
                        f"({res['sample_iters'] * res['s_per_iter']:.1f} s) and {res['allcore_iters']} per process on "
                        f"all cores ({res['allcore_wall_s']:.1f} s), scaled to {iters_needed} iterations per solve; "
-                       f"hierarchy build {res['t_build_s']:.0f} s not timed")}
+                       f"hierarchy build {res['t_build_s']:.0f} s not timed (with the smoother's set-up)")}
 
 
 def run_batched(args, amge, W):
@@ -248,7 +257,7 @@ def run_batched(args, amge, W):
     }
 
 
-def run_small_configs(names, steps):
+def run_small_configs(names, steps, smoother):
     """The two small configurations, each solved with the FP32 and the FP64 V-cycle on the
     library's own hierarchy: iterations, time per solve (host clock around complete
     solves), and the solutions (kept for their errors against the oracle)."""
@@ -262,9 +271,9 @@ def run_small_configs(names, steps):
         prod = amge.build_problem(w.kind, w.n, w.levels, a, b)
         rhs = None
         r = {"workload": (f"H({w.kind}) on {w.n}^3x6 Kuhn tets, {w.levels} levels, coefficients {w.coef}, "
-                          f"rhs uniform[-1,1] seed {w.rhs_seed}, rtol {w.rtol:g}")}
+                          f"rhs uniform[-1,1] seed {w.rhs_seed}, rtol {w.rtol:g}, smoother {smoother}")}
         for bits in (32, 64):
-            H = amge.Hierarchy(prod, precond_bits=bits)
+            H = amge.Hierarchy(prod, precond_bits=bits, smoother=smoother)
             if rhs is None:
                 rhs = torch.from_numpy(W.rhs(H.rows[0], w.rhs_seed)[:, 0]).cuda()
                 r["level_rows"] = H.rows
@@ -324,16 +333,15 @@ def run_options(steps):
     return out
 
 
-def run_gs(w, prod, rhs, steps):
-    """The same solve with the symmetric Gauss-Seidel point smoother (colour order) in
-    place of l1-Jacobi: iterations, time per solve and V-cycle time, FP32 and FP64
-    V-cycles."""
+def run_smoother(w, prod, rhs, steps, smoother):
+    """The same solve with another point smoother in the hybrid smoother: iterations, time
+    per solve and V-cycle time, FP32 and FP64 V-cycles."""
     import torch
     from paper_2107_05613_amd import amge
     out = {}
     for bits in (32, 64):
         t0 = time.perf_counter()
-        H = amge.Hierarchy(prod, precond_bits=bits, smoother="symgs")
+        H = amge.Hierarchy(prod, precond_bits=bits, smoother=smoother)
         t_setup = time.perf_counter() - t0
         x = torch.zeros_like(rhs)
         for _ in range(2):
@@ -355,15 +363,16 @@ def run_gs(w, prod, rhs, steps):
         out[f"fp{bits}"] = {"iters": it[0], "status": st, "ms_per_solve": 1e3 * dt, "solves_per_s": 1.0 / dt,
                             "vcycle_ms": e0.elapsed_time(e1) / 10, "setup_s": t_setup}
         H.close()
-    print(f"[bench] symmetric Gauss-Seidel smoother: FP32 {out['fp32']['iters']} iterations "
+    print(f"[bench] smoother {smoother}: FP32 {out['fp32']['iters']} iterations "
           f"{out['fp32']['ms_per_solve']:.2f} ms, FP64 {out['fp64']['iters']} iterations "
           f"{out['fp64']['ms_per_solve']:.2f} ms", file=sys.stderr, flush=True)
     return out
 
 
 def cold_sweep(H, rhs, x, reps=10):
-    """Average time of the fine-level FP32 l1-Jacobi sweep launched alone (amge_level_apply
-    SWEEP, HIP events on its stream), warm (launched back to back, its matrix partly
+    """Average time of the fine-level FP32 sweep of the point smoother launched alone
+    (amge_level_apply SWEEP: a block Gauss-Seidel sweep from x, or an l1-Jacobi sweep; HIP
+    events on its stream), warm (launched back to back, its matrix partly
     served by the last-level cache) and cold (after a 2 GiB device copy that evicts the
     256 MB last-level cache, so the matrix streams from HBM)."""
     import torch
@@ -580,7 +589,10 @@ def main():
     ap.add_argument("--cpu-baseline-worker", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--oracle-dir", default=None)
-    ap.add_argument("--no-gs", action="store_true", help="skip the Gauss-Seidel smoother comparison")
+    ap.add_argument("--smoother", choices=("l1blockgs", "l1jacobi", "symgs"), default="l1blockgs",
+                    help="point smoother of the headline solve (section 4.1): l1-scaled symmetric block "
+                         "Gauss-Seidel (default), l1-Jacobi, or symmetric Gauss-Seidel in colour order")
+    ap.add_argument("--no-gs", action="store_true", help="skip the solves with the other point smoothers")
     ap.add_argument("--no-options", action="store_true",
                     help="skip the extension / boundary-condition option comparison")
     ap.add_argument("--small-configs", default="curl_n8_l2,div_n32_l4_jumps",
@@ -593,7 +605,7 @@ def main():
     args = ap.parse_args()
 
     if args.cpu_baseline_worker:
-        cpu_baseline_worker(args.workload.split(","), args.cpu_budget, args.oracle_dir)
+        cpu_baseline_worker(args.workload.split(","), args.cpu_budget, args.oracle_dir, args.smoother)
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: the solve phase is not sharded across GPUs "
@@ -628,10 +640,10 @@ def main():
     amge.build_problem(w.kind, w.n, w.levels, a, b)
     t_build_host = time.perf_counter() - t0
     t0 = time.perf_counter()
-    H32 = amge.Hierarchy(prod, precond_bits=32)
+    H32 = amge.Hierarchy(prod, precond_bits=32, smoother=args.smoother)
     torch.cuda.synchronize()
     t_setup32 = time.perf_counter() - t0
-    H64 = amge.Hierarchy(prod, precond_bits=64)
+    H64 = amge.Hierarchy(prod, precond_bits=64, smoother=args.smoother)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     n1 = H32.rows[0]
@@ -699,10 +711,11 @@ def main():
     sol = {(w.name, 32): x32.cpu().numpy(), (w.name, 64): x64.cpu().numpy()}
     lv0 = prod[0][0]
     del H64
-    gs = run_gs(w, prod, rhs, args.steps) if not args.no_gs else None
+    others = {sm: run_smoother(w, prod, rhs, args.steps, sm)
+              for sm in ("l1jacobi", "symgs", "l1blockgs") if sm != args.smoother} if not args.no_gs else None
     stream_ref = stream_reference()
     small_names = [c for c in args.small_configs.split(",") if c]
-    small, small_sol = run_small_configs(small_names, args.steps) if small_names else ({}, {})
+    small, small_sol = run_small_configs(small_names, args.steps, args.smoother) if small_names else ({}, {})
     sol.update(small_sol)
     options = run_options(args.steps) if not args.no_options else None
     batched = run_batched(args, amge, W) if args.batched_workload else None
@@ -733,7 +746,8 @@ def main():
         "config": {
             "workload": (f"{w.name}: H({w.kind}) lowest-order "
                          f"{'Nedelec' if w.kind == 'curl' else 'Raviart-Thomas'} on {w.n}^3x6 Kuhn tets, "
-                         f"{w.levels}-level AMGe (2x2x2 agglomerates), l1-Jacobi hybrid smoother 2+2, "
+                         f"{w.levels}-level AMGe (2x2x2 agglomerates), hybrid smoother 2+2 sweeps with "
+                         f"{SMOOTHER_NAMES[args.smoother]}, "
                          f"FP32 V-cycle in FP64 inexact PCG to rel-res {w.rtol:g} (preconditioner norm)"),
             "fine_dofs": n1,
             "level_rows": H32.rows,
@@ -753,7 +767,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "fine-level A_1 sliced-ELL kernels (l1-Jacobi sweeps + residual, FP32, 16-bit column offsets)",
+            "kernel": ROOFLINE_KERNELS[args.smoother],
             "achieved": k_gbps,
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",
@@ -772,7 +786,8 @@ def main():
                           "the 256 MB last-level cache (its matrix streams from HBM); warm: launched back to back"),
             "stream_reference_GBps": stream_ref,
         },
-        "smoother_sym_gs": gs,
+        "smoother": args.smoother,
+        "other_smoothers": others,
         "configs": small,
         "extension_and_boundary_options": options,
         "setup_s": {"build": t_build, "build_host_only": t_build_host, "device_setup": t_setup,
@@ -786,7 +801,7 @@ def main():
     if not args.no_cpu_baseline:
         import shutil
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        ores, odir = run_cpu_baseline([args.workload] + small_names, args.cpu_budget)
+        ores, odir = run_cpu_baseline([args.workload] + small_names, args.cpu_budget, args.smoother)
         if "error" in ores:
             out["cpu_baseline"] = ores
         else:

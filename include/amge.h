@@ -98,13 +98,22 @@ typedef struct {
                                operator, fewer launches.  0: off (0 <= tail_rows <= 8192). */
     int32_t smoother;       /* point smoother of the hybrid smoother (section 4.1):
                                AMGE_SMOOTHER_L1_JACOBI: x += d^{-1}(b - A x), d_i = sum_j |a_ij|;
-                               AMGE_SMOOTHER_SYM_GS: symmetric Gauss-Seidel in colour order
-                               (the smoother of the paper's experiments): rows coloured
-                               greedily (first fit in increasing row order over the rows
-                               coupled to earlier ones), a sweep relaxes the colours in
-                               increasing then decreasing order, each row by
-                               x_i += (b - A x)_i / a_ii.  Single-column contexts only
-                               (max_rhs = 1).                                                 */
+                               AMGE_SMOOTHER_SYM_GS: symmetric Gauss-Seidel in colour order:
+                               rows coloured greedily (first fit in increasing row order over
+                               the rows coupled to earlier ones), a sweep relaxes the colours
+                               in increasing then decreasing order, each row by
+                               x_i += (b - A x)_i / a_ii;
+                               AMGE_SMOOTHER_BLOCK_GS: l1-scaled symmetric block Gauss-Seidel
+                               (the smoother of the paper's experiments, section 4.1 last
+                               paragraph and section 5.1, with blocks of 64 consecutive rows
+                               in place of processors): inside a block, rows coloured greedily
+                               over the couplings within the block and relaxed colour by
+                               colour, forward then backward through all colours, each row by
+                               x_i += (b_i - sum_j a_ij x_j) / d_i, d_i = a_ii + sum of |a_ij|
+                               over columns outside the block, where x_j outside the block
+                               keeps its value from the start of the sweep.
+                               The Gauss-Seidel smoothers need a positive diagonal and run
+                               single-column contexts only (max_rhs = 1).                     */
     int32_t resid_bits;     /* FP32 V-cycles: precision of the fine-level residual b - A x that
                                is restricted to level 2 (Algorithm 4.1).  32: FP32 values and
                                sums; 64: the FP64 values of A_1 summed in FP64, the result
@@ -130,7 +139,7 @@ typedef struct {
 typedef struct amge_hierarchy amge_hierarchy;
 typedef struct amge_ctx amge_ctx;
 
-enum { AMGE_SMOOTHER_L1_JACOBI = 0, AMGE_SMOOTHER_SYM_GS = 1 };
+enum { AMGE_SMOOTHER_L1_JACOBI = 0, AMGE_SMOOTHER_SYM_GS = 1, AMGE_SMOOTHER_BLOCK_GS = 2 };
 
 /* Default options: nu = 2 + 2, FP32 preconditioner, max_rhs = 1, tail_rows = 2048,
  * l1-Jacobi, hipMalloc. */
@@ -221,11 +230,14 @@ amge_status amge_pcg_solve(amge_ctx* c, const double* b, double* x, int32_t nrhs
  *       AMGE_OP_SMOOTH  out = x + Mbar^{-1}(b - A x) with b = in, x = in2 (eq. (4.1))
  *       AMGE_OP_SMOOTHT out = x + Mbar^{-T}(b - A x) with b = in, x = in2 (reversed order)
  *       AMGE_OP_COARSE  out = A_L^{-1} in on the coarsest level (Cholesky apply)
- *       AMGE_OP_SWEEP   out = x + d^{-1} (b - A x), b = in, x = in2: one l1-Jacobi sweep,
- *                       d_i = sum_j |a_ij| (the V-cycle's sweep kernel, eq. (4.1))
+ *       AMGE_OP_SWEEP   one sweep of the V-cycle's point smoother on A_k from x, b = in,
+ *                       x = in2 (its sweep kernel): with the block Gauss-Seidel smoother
+ *                       one symmetric block sweep, otherwise the l1-Jacobi sweep
+ *                       out = x + d^{-1} (b - A x), d_i = sum_j |a_ij| (eq. (4.1))
  *       AMGE_OP_RESID   out = b - A x, b = in, x = in2 (the V-cycle's residual kernel,
- *                       Algorithm 4.1; on the fine level at precision 32 with resid_bits =
- *                       64 in use, the FP64-value kernel with FP64 sums)
+ *                       Algorithm 4.1: with the block Gauss-Seidel smoother the kernel on
+ *                       the smoother's layout of A; on the fine level at precision 32 with
+ *                       resid_bits = 64 in use, FP64 values with FP64 sums)
  * On the fine level, SWEEP and RESID run exactly the launches the V-cycle times with
  * amge_timing_enable. */
 enum {
@@ -236,8 +248,8 @@ enum {
 amge_status amge_level_apply(amge_ctx* c, int32_t level, int32_t op, int32_t precision,
                              const double* in, const double* in2, double* out, void* stream);
 
-/* Event timing of the fine-level A_1 kernels of the V-cycle (the l1-Jacobi sweeps and
- * residuals on level 1, the dominant kernel family of the path).  While enabled, every
+/* Event timing of the fine-level A_1 kernels of the V-cycle (the point smoother's sweeps
+ * on A_1 and the residuals on level 1, the dominant kernel family of the path).  While enabled, every
  * such launch is bracketed by HIP events on its own stream.  amge_timing_read waits for
  * the recorded events and returns, since enabling or the previous read: the summed
  * kernel time in ms, the number of launches, and their algorithmic bytes (values and

@@ -57,7 +57,7 @@ class OptsC(C.Structure):
                 ("resid_bits", C.c_int32), ("alloc", ALLOC_FN), ("dealloc", DEALLOC_FN), ("alloc_user", C.c_void_p)]
 
 
-SMOOTHERS = {"l1jacobi": 0, "symgs": 1}
+SMOOTHERS = {"l1jacobi": 0, "symgs": 1, "l1blockgs": 2}
 
 
 def _torch_alloc(nbytes, _user):
@@ -275,8 +275,9 @@ class Hierarchy:
     precond_bits: 32, 64 or 0 (chosen by trial solves at set-up); max_rhs: widest block
     of a context (the batched path); tail_rows: levels of at most this many rows below the
     fine one are folded into one dense FP64 operator (0: every level runs its kernels);
-    smoother: "l1jacobi" or "symgs" (symmetric Gauss-Seidel in colour order, single-column
-    contexts only); resid_bits: precision of an FP32 V-cycle's fine-level residual (32,
+    smoother: "l1jacobi", "symgs" (symmetric Gauss-Seidel in colour order) or "l1blockgs"
+    (l1-scaled symmetric block Gauss-Seidel, 64-row blocks); the Gauss-Seidel smoothers run
+    single-column contexts only; resid_bits: precision of an FP32 V-cycle's fine-level residual (32,
     64, or 0: 32 unless the trial picks 64); allocator: "torch" (torch's caching
     allocator) or None (hipMalloc)."""
 

@@ -89,6 +89,27 @@ struct GsColors {
 template <> inline const double* GsColors::dg<double>() const { return dg64; }
 template <> inline const float* GsColors::dg<float>() const { return dg32; }
 
+// l1-scaled symmetric block Gauss-Seidel data of one matrix (kernels_bgs.hpp): blocks of
+// 64 consecutive rows, one wave per block, an ELL per block (entry t of the block's row q
+// at blk.base + t * 64 + q); a row's entries inside its block first (code: the column's
+// position in the block), then the others (code: column, or a 16-bit offset from
+// blk.cbase when every block's outside columns span < 65536).
+struct DBgs {
+    int n = 0, nblk = 0;
+    int nin = 0;              // register bound of inside entries per row (8 ... 64)
+    int64_t nnz = 0;          // entries of A
+    int64_t nnz_in = 0;       // entries inside blocks (read by sweeps from zero)
+    dev::BgsBlock* blk = nullptr;
+    uint16_t* meta = nullptr; // per row: inside entries | colour << 8
+    int* ci = nullptr;
+    uint16_t* c16 = nullptr;
+    double* v64 = nullptr;
+    float* v32 = nullptr;
+    double *dinv64 = nullptr, *mid64 = nullptr;   // 1 / (a_ii + l1 outside), a_ii + 2 l1 outside
+    float *dinv32 = nullptr, *mid32 = nullptr;
+    bool on() const { return nblk > 0; }
+};
+
 struct DLevel {
     int n = 0, m = 0;
     Probe* probe = nullptr;
@@ -97,6 +118,7 @@ struct DLevel {
     // level only)
     bool resid64 = false;
     GsColors gsA, gsAh;       // symmetric Gauss-Seidel smoother (opts.smoother)
+    DBgs bgA, bgAh;           // l1-scaled symmetric block Gauss-Seidel smoother
     DSell A, Ah, P, Pt;
     DSell Aux;                // [D^T | -D^T A]: auxiliary residual D^T b - (D^T A) x
     DSell PtA;                // [P^T | -P^T A] below the fine level: restricted residual

@@ -17,15 +17,11 @@
 
 #include <type_traits>
 
+#include "kernels_base.hpp"
 #include "state.hpp"
 
 namespace amge {
 namespace dev {
-
-constexpr int BLOCK = 256;
-constexpr int WAVES = BLOCK / 64;   // slices per block
-constexpr int NRED = 1024;          // blocks (and partial sums) of the streaming reductions
-constexpr int NXCD = 8;
 
 enum Mode : int {
     SPMV = 0,      // y = A x
@@ -35,20 +31,6 @@ enum Mode : int {
     JAC0 = 4,      // batched only: JAC from x = dinv * b, formed where x is read
     SPLIT = 5,     // y = A [b; x]: the first lead entries of a row read b, the others x
 };
-
-// Blocks are dispatched round-robin over the XCDs; give XCD k a contiguous range.
-__device__ __forceinline__ int xcd_block(int b, int G) {
-    const int xcd = b % NXCD, idx = b / NXCD;
-    const int per = G / NXCD, rem = G % NXCD;
-    return xcd * per + min(xcd, rem) + idx;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 // Sliced ELL with K lanes per row (K | 64): a slice holds R = 64/K rows; entry t of
 // the slice's row rr is stored at base + (t / K) * 64 + rr * K + t % K, so every load

@@ -20,6 +20,7 @@
 #include <tuple>
 #include <type_traits>
 
+#include "block_gs.hpp"
 #include "common.hpp"
 #include "hierarchy.hpp"
 #include "kernels.hpp"
@@ -567,9 +568,86 @@ void convert(int64_t n, const S* a, D* b, hipStream_t s) {
 // first sweep is x = dinv b, which the producer of b has already written to bd, so the
 // first launched sweep starts from bd.  x and xt are swapped by the ping-pong; the
 // caller tracks where the result is.
+// One block Gauss-Seidel sweep on A_k or D^T A D (probed on the fine level like asell).
+template <class T>
+void bgs(DLevel& L, const DBgs& g, bool zero, const T* x, const T* b, T* y, hipStream_t s, const int* stop) {
+    Probe* pr = &g == &L.bgA ? L.probe : nullptr;
+    if (!pr || !pr->on) {
+        bgs_launch<T>(g, zero, x, b, y, s, stop);
+        return;
+    }
+    if (pr->ev.size() < 2 * (pr->used + 1)) {
+        hipEvent_t a, c;
+        HIPCHECK(hipEventCreate(&a));
+        HIPCHECK(hipEventCreate(&c));
+        pr->ev.push_back(a);
+        pr->ev.push_back(c);
+    }
+    HIPCHECK(hipEventRecord(pr->ev[2 * pr->used], s));
+    bgs_launch<T>(g, zero, x, b, y, s, stop);
+    HIPCHECK(hipEventRecord(pr->ev[2 * pr->used + 1], s));
+    pr->used++;
+    pr->bytes += bgs_bytes(g, zero, (int)sizeof(T));
+}
+
+// r = b - A x ahead of the restriction.  With the block Gauss-Seidel smoother it reads
+// the smoother's copy of A_k (one copy of A_k stays cache-resident through the V-cycle);
+// probed on the fine level like the sweeps.
+template <class T>
+void aresid(DLevel& L, const T* x, const T* b, T* r, hipStream_t s, const int* stop) {
+    if (!L.bgA.on()) {
+        asell<T>(L, dev::RESID, x, b, nullptr, r, s, stop);
+        return;
+    }
+    const bool v64 = std::is_same<T, float>::value && L.resid64;
+    Probe* pr = L.probe;
+    if (!pr || !pr->on) {
+        bgs_resid_launch<T>(L.bgA, v64, x, b, r, s, stop);
+        return;
+    }
+    if (pr->ev.size() < 2 * (pr->used + 1)) {
+        hipEvent_t a, c;
+        HIPCHECK(hipEventCreate(&a));
+        HIPCHECK(hipEventCreate(&c));
+        pr->ev.push_back(a);
+        pr->ev.push_back(c);
+    }
+    HIPCHECK(hipEventRecord(pr->ev[2 * pr->used], s));
+    bgs_resid_launch<T>(L.bgA, v64, x, b, r, s, stop);
+    HIPCHECK(hipEventRecord(pr->ev[2 * pr->used + 1], s));
+    pr->used++;
+    pr->bytes += bgs_resid_bytes(L.bgA, v64 ? 8 : (int)sizeof(T), (int)sizeof(T));
+}
+
+// nu block Gauss-Seidel sweeps through the ping-pong pair x / xt (the result ends in x).
+template <class T>
+void bgs_sweeps(DLevel& L, const DBgs& g, const T* b, T*& x, T*& xt, bool from_zero, int nu, hipStream_t s,
+                const int* stop) {
+    int k = 0;
+    if (from_zero) {
+        if (nu <= 0) {
+            fill_zero<T>(g.n, x, s, stop);
+            return;
+        }
+        // start in the other buffer: a V-cycle level then makes 2 nu - 1 swaps in all
+        // and ends in the buffer it started with (no copy)
+        std::swap(x, xt);
+        bgs<T>(L, g, true, nullptr, b, x, s, stop);
+        k = 1;
+    }
+    for (; k < nu; ++k) {
+        bgs<T>(L, g, false, x, b, xt, s, stop);
+        std::swap(x, xt);
+    }
+}
+
 template <class T>
 void primary(DLevel& L, const T* b, const T* bd, T*& x, T*& xt, bool from_zero, int nu, hipStream_t s,
              const int* stop) {
+    if (L.bgA.on()) {   // l1-scaled symmetric block Gauss-Seidel
+        bgs_sweeps<T>(L, L.bgA, b, x, xt, from_zero, nu, s, stop);
+        return;
+    }
     if (!L.gsA.col.empty()) {   // symmetric Gauss-Seidel: in place, from zero if asked
         if (from_zero) fill_zero<T>(L.n, x, s, stop);
         gs_sweeps<T>(L.gsA, b, x, nu, s, stop);
@@ -601,6 +679,14 @@ template <class T>
 void auxiliary(DLevel& L, const T* b, T* x, int nu, hipStream_t s, const int* stop) {
     if (nu <= 0 || L.m == 0) return;
     Work<T>& w = L.w<T>();
+    if (L.bgAh.on()) {   // block Gauss-Seidel sweeps on D^T A D from zero
+        sell<T>(L.Aux, dev::SPLIT, x, b, nullptr, w.g, s, stop);
+        T* y = w.y;
+        T* yt = w.yt;
+        bgs_sweeps<T>(L, L.bgAh, w.g, y, yt, true, nu, s, stop);
+        sell_inc<T>(L.D, 1, y, x, s, stop);
+        return;
+    }
     if (!L.gsAh.col.empty()) {   // symmetric Gauss-Seidel sweeps on D^T A D from zero
         sell<T>(L.Aux, dev::SPLIT, x, b, nullptr, w.g, s, stop);
         fill_zero<T>(L.m, w.y, s, stop);
@@ -635,7 +721,9 @@ void vcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, hi
     T* x = xout;
     T* xt = w.xt;
     const int nup = H->opts.nu_primary, nua = H->opts.nu_aux;
-    const bool next_coarsest = l + 1 == H->tail;   // needs no first sweep of its own
+    // the coarse level's first l1-Jacobi sweep from zero, written with its right-hand
+    // side (not needed by the coarsest level or the Gauss-Seidel smoothers)
+    const bool next_coarsest = l + 1 == H->tail || C.bgA.on() || !C.gsA.col.empty();
     // pre-smoothing with Mbar (eq. (4.1)): primary, then auxiliary
     primary<T>(L, b, bd, x, xt, true, nup, s, stop);
     auxiliary<T>(L, b, x, nua, s, stop);
@@ -645,7 +733,7 @@ void vcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, hi
         sell<T>(L.PtA, dev::SPLIT, x, b, next_coarsest ? nullptr : wc.dinv, wc.b, s, stop,
                 next_coarsest ? nullptr : wc.bd);
     } else {
-        asell<T>(L, dev::RESID, x, b, nullptr, w.r, s, stop);
+        aresid<T>(L, x, b, w.r, s, stop);
         sell<T>(L.Pt, dev::SPMV, w.r, nullptr, next_coarsest ? nullptr : wc.dinv, wc.b, s, stop,
                 next_coarsest ? nullptr : wc.bd);
     }
@@ -1328,6 +1416,9 @@ struct TailLevel {
     bool gs = false;
     std::vector<std::vector<int>> clsA, clsAh;
     std::vector<double> dgA, dgAh;
+    // l1-scaled symmetric block Gauss-Seidel smoother (A and D^T A D)
+    bool bgs = false;
+    BgsHost bgA, bgAh;
 };
 
 // Rows of every colour, and 1 / a_ii, of a matrix (host Gauss-Seidel of the folded tail).
@@ -1397,6 +1488,9 @@ void host_aux(const TailLevel& L, int nua, const double* b, double* x, TailScrat
     if (L.gs) {
         std::fill(w.y.begin(), w.y.end(), 0.0);
         host_gs(L.Ah, L.clsAh, L.dgAh, nua, w.g.data(), w.y.data());
+    } else if (L.bgs) {
+        std::fill(w.y.begin(), w.y.end(), 0.0);
+        for (int k = 0; k < nua; ++k) host_bgs_sweep(L.bgAh, w.g.data(), w.y.data(), w.ay);
     } else {
         for (int i = 0; i < m; ++i) w.y[i] = L.dhinv[i] * w.g[i];
         for (int k = 1; k < nua; ++k) {
@@ -1415,6 +1509,9 @@ void host_tail_vcycle(const TailLevel& L, int nu, int nua, const std::vector<dou
     if (L.gs) {
         std::fill(x, x + n, 0.0);
         host_gs(L.A, L.clsA, L.dgA, nu, b, x);
+    } else if (L.bgs) {
+        std::fill(x, x + n, 0.0);
+        for (int k = 0; k < nu; ++k) host_bgs_sweep(L.bgA, b, x, w.r);
     } else if (nu >= 1) {   // the first sweep from zero is dinv b
         for (int i = 0; i < n; ++i) x[i] = L.dinv[i] * b[i];
         host_sweeps(L, nu - 1, b, x, w);
@@ -1434,6 +1531,8 @@ void host_tail_vcycle(const TailLevel& L, int nu, int nua, const std::vector<dou
     for (int i = 0; i < n; ++i) x[i] += w.ax[i];
     host_aux(L, nua, b, x, w);
     if (L.gs) host_gs(L.A, L.clsA, L.dgA, nu, b, x);
+    else if (L.bgs)
+        for (int k = 0; k < nu; ++k) host_bgs_sweep(L.bgA, b, x, w.r);
     else host_sweeps(L, nu, b, x, w);
 }
 
@@ -1609,6 +1708,10 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
                 T.gs = true;
                 host_gs_data(A[k], T.clsA, T.dgA);
                 host_gs_data(Ah, T.clsAh, T.dgAh);
+            } else if (H->opts.smoother == AMGE_SMOOTHER_BLOCK_GS) {
+                T.bgs = true;
+                T.bgA = bgs_layout(A[k]);
+                T.bgAh = bgs_layout(Ah);
             }
         }
         clk.lap("host products D^T A, D^T A D");
@@ -1618,6 +1721,10 @@ void setup(amge_hierarchy* H, const amge_level* levels, int nl, hipStream_t s) {
         if (H->opts.smoother == AMGE_SMOOTHER_SYM_GS) {
             build_gs(H, A[k], L.gsA, s);
             build_gs(H, Ah, L.gsAh, s);
+        } else if (H->opts.smoother == AMGE_SMOOTHER_BLOCK_GS) {
+            build_bgs(H, A[k], L.bgA, s);
+            build_bgs(H, Ah, L.bgAh, s);
+            clk.lap("block Gauss-Seidel layouts");
         }
         L.P = upload_tuned(H, P[k], false, s);
         L.Pt = upload_tuned(H, transpose(P[k]), false, s);
@@ -2287,10 +2394,11 @@ extern "C" amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nl
             fail(AMGE_ERR_ARG, "invalid options");
         if ((H->opts.alloc == nullptr) != (H->opts.dealloc == nullptr))
             fail(AMGE_ERR_ARG, "give both alloc and dealloc, or neither");
-        if (H->opts.smoother != AMGE_SMOOTHER_L1_JACOBI && H->opts.smoother != AMGE_SMOOTHER_SYM_GS)
+        if (H->opts.smoother != AMGE_SMOOTHER_L1_JACOBI && H->opts.smoother != AMGE_SMOOTHER_SYM_GS &&
+            H->opts.smoother != AMGE_SMOOTHER_BLOCK_GS)
             fail(AMGE_ERR_ARG, "unknown smoother");
-        if (H->opts.smoother == AMGE_SMOOTHER_SYM_GS && H->opts.max_rhs > 1)
-            fail(AMGE_ERR_ARG, "the Gauss-Seidel smoother runs single-column contexts only (max_rhs = 1)");
+        if (H->opts.smoother != AMGE_SMOOTHER_L1_JACOBI && H->opts.max_rhs > 1)
+            fail(AMGE_ERR_ARG, "the Gauss-Seidel smoothers run single-column contexts only (max_rhs = 1)");
         setup(H.get(), levels, nlevels, (hipStream_t)stream);
         *out = H.release();
         return AMGE_OK;
@@ -2471,8 +2579,11 @@ extern "C" amge_status amge_level_apply(amge_ctx* c, int32_t level, int32_t op, 
                 case AMGE_OP_P: sell<T>(L.P, dev::SPMV, vin, nullptr, nullptr, vout, s, z0); break;
                 case AMGE_OP_PT: sell<T>(L.Pt, dev::SPMV, vin, nullptr, nullptr, vout, s, z0); break;
                 // the V-cycle's own A_k launches (timed by amge_timing_* on the fine level)
-                case AMGE_OP_SWEEP: asell<T>(L, dev::JAC, vin2, vin, L.w<T>().dinv, vout, s, z0); break;
-                case AMGE_OP_RESID: asell<T>(L, dev::RESID, vin2, vin, nullptr, vout, s, z0); break;
+                case AMGE_OP_SWEEP:
+                    if (L.bgA.on()) bgs<T>(L, L.bgA, false, vin2, vin, vout, s, z0);
+                    else asell<T>(L, dev::JAC, vin2, vin, L.w<T>().dinv, vout, s, z0);
+                    break;
+                case AMGE_OP_RESID: aresid<T>(L, vin2, vin, vout, s, z0); break;
                 default: {
                     Work<T>& w = L.w<T>();
                     // x lives in w.x (copied in), result copied out
@@ -2587,7 +2698,16 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
                 return t;
             };
             const bool gs = !L.gsA.col.empty();
-            if (gs) {
+            const bool bg = L.bgA.on();
+            // block Gauss-Seidel: nu sweeps, the first of a smoothing from zero a pre-smoothing
+            auto bgb = [&](const DBgs& g, int nu, bool zero) {
+                if (nu <= 0) return zero ? sx * g.n : 0.0;
+                return (zero ? bgs_bytes(g, true, (int)sv) : bgs_bytes(g, false, (int)sv)) +
+                       (nu - 1) * bgs_bytes(g, false, (int)sv);
+            };
+            if (bg) {
+                tot += bgb(L.bgA, nup, true) + bgb(L.bgA, nup, false);
+            } else if (gs) {
                 // pre-smoother from zero (x filled with zeros), post-smoother from x
                 tot += sx * n + 2 * gsb(L.gsA, n, nup);
             } else {
@@ -2597,7 +2717,13 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
                 tot += launched * (mat(L.A, L.bA) + 3 * sx * n + sv * n) + 2 * sx * n;
             }
             // auxiliary step, pre and post: residual [D^T | -D^T A][b; x] (+ gd), sweeps, D add
-            if (nua > 0 && gs) {
+            if (nua > 0 && bg) {
+                // [D^T | -D^T A] (g only), block sweeps on D^T A D from zero, D add
+                double aux = mat(L.Aux, L.bAux) + 2.0 * m + sx * (2 * n + m);
+                aux += bgb(L.bgAh, nua, true);
+                aux += incb(L.D, L.bD) + sx * (m + 2 * n);
+                tot += 2 * aux;
+            } else if (nua > 0 && gs) {
                 // [D^T | -D^T A] (g only), y filled with zeros, Gauss-Seidel on D^T A D, D add
                 double aux = mat(L.Aux, L.bAux) + 2.0 * m + sx * (2 * n + m) + sx * m;
                 aux += gsb(L.gsAh, m, nua);
@@ -2618,7 +2744,10 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
                 // an FP32 cycle's fine-level residual with resid64 reads the FP64 values
                 const double extra = (precision == 32 && L.resid64)
                                          ? (double)(batched ? L.bA.nnz : L.A.nnz) * (8.0 - sv) : 0.0;
-                tot += mat(L.A, L.bA) + extra + 3 * sx * n;
+                if (bg && !batched)
+                    tot += bgs_resid_bytes(L.bgA, (precision == 32 && L.resid64) ? 8 : (int)sv, (int)sv);
+                else
+                    tot += mat(L.A, L.bA) + extra + 3 * sx * n;
                 tot += mat(L.Pt, L.bPt) + sx * (n + nc);
             }
             tot += mat(L.P, L.bP) + sx * (nc + 2 * n);

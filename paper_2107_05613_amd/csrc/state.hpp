@@ -43,5 +43,12 @@ struct BatchStatus {
     int all_done_next;   // all_done after the current iteration (made current by its last kernel)
 };
 
+// One 64-row block of the l1-scaled symmetric block Gauss-Seidel layout: entry base,
+// width (entries per row, padded), inside width (most inside entries of a row) |
+// colours << 8, base column of the outside 16-bit offsets.
+struct alignas(16) BgsBlock {
+    int base, width, info, cbase;
+};
+
 }  // namespace dev
 }  // namespace amge

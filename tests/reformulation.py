@@ -48,6 +48,8 @@ class Reformulated(Multilevel):
         for _ in range(lv.nu_aux):
             if lv.smoother == "symgs":
                 y = gs_sweep(lv.Ahat, lv.diaghat, lv.classes_hat, g, y, lv.blocks_hat)
+            elif lv.smoother == "l1blockgs":
+                y = lv.bgs_hat.sweep(g, y)
             else:
                 y = y + (g - lv.Ahat @ y) / lv.dhat
         return x + lv.D @ y

@@ -16,8 +16,8 @@ unit coefficients, where the oracle's reformulation spread (tests/reformulation.
 * the batched block: sampled columns (first, middle, last) of the 32-column FP64 solve
   against the oracle's single-column PCG, the FP32 block the same way to 1e-6;
 * properties that need no oracle: symmetry and positivity of B;
-* the symmetric Gauss-Seidel smoother at full size: one smoother application and PCG
-  against the oracle's colour-order smoother.
+* the symmetric Gauss-Seidel smoothers at full size (colour order; l1-scaled block): one
+  smoother application and PCG against the oracle's sweeps.
 """
 import numpy as np
 import pytest
@@ -203,6 +203,54 @@ def test_fullsize_symgs(curl64):
     e32 = float(np.linalg.norm(host(x) - xo) / np.linalg.norm(xo))
     print(f"Gauss-Seidel smoother vs oracle: FP64 {err[64]:.1e}, FP32 {err[32]:.1e}; PCG oracle {ito}, FP64 "
           f"{it[0]} (fixed-count error {e64:.1e}), FP32 {it32[0]} (error {e32:.1e})")
+    assert err[64] <= 1e-10 and err[32] <= 1e-4
+    assert e64 <= 1e-10
+    assert status32 == 0 and rr32[0] <= f.w.rtol and it32[0] <= ito + 3 and e32 <= 1e-6
+    for h in gpu.values():
+        h.close()
+
+
+def test_fullsize_blockgs(curl64):
+    """The l1-scaled symmetric block Gauss-Seidel smoother at full size (the launches the
+    benchmark times with that smoother: 64-row blocks over 1,872,064 rows) on
+    hierarchies set up from the oracle's matrices.  One hybrid smoother application on
+    the fine level against the oracle's block sweep (FP64 within 1e-10, FP32 within 1e-4,
+    max-norm relative), and PCG: FP64 iteration count +-1 and the iterate after the
+    oracle's count within 1e-10; FP32 within +3 iterations and 1e-6 of the oracle's
+    solution."""
+    import time
+    from oracle.solve import Multilevel, pcg
+    from paper_2107_05613_amd import amge
+    f = curl64
+    H = f.H
+    L = len(H.A)
+    t0 = time.perf_counter()
+    ml = Multilevel(H.A, H.D, H.P, smoother="l1blockgs", gs_block=64)
+    print(f"oracle block Gauss-Seidel set-up (colourings) {time.perf_counter() - t0:.0f} s", flush=True)
+    levels = [(H.A[k], H.D[k], H.P[k] if k < L - 1 else None) for k in range(L)]
+    gpu = {bits: amge.Hierarchy(levels, precond_bits=bits, smoother="l1blockgs") for bits in (32, 64)}
+    n = f.A.shape[0]
+    rng = np.random.default_rng(6)
+    b, x0 = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    ref = ml.smooth(ml.levels[0], b, x0)
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    err = {}
+    for bits in (64, 32):
+        gpu[bits].level_apply(0, amge.OP_SMOOTH, dev(b), out, x2=dev(x0), precision=bits)
+        err[bits] = float(np.max(np.abs(host(out) - ref)) / np.max(np.abs(ref)))
+    rhs = W.rhs(n, f.w.rhs_seed)[:, 0]
+    t0 = time.perf_counter()
+    xo, ito, _ = pcg(f.A, rhs, ml, rtol=f.w.rtol)
+    print(f"oracle block Gauss-Seidel PCG {ito} iterations in {time.perf_counter() - t0:.0f} s", flush=True)
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    status, it, _ = gpu[64].pcg(dev(rhs), x, rtol=f.w.rtol, maxit=500)
+    assert status == 0 and abs(it[0] - ito) <= 1, (it, ito)
+    gpu[64].pcg(dev(rhs), x, rtol=0.0, maxit=ito)
+    e64 = float(np.linalg.norm(host(x) - xo) / np.linalg.norm(xo))
+    status32, it32, rr32 = gpu[32].pcg(dev(rhs), x, rtol=f.w.rtol, maxit=500)
+    e32 = float(np.linalg.norm(host(x) - xo) / np.linalg.norm(xo))
+    print(f"block Gauss-Seidel smoother vs oracle: FP64 {err[64]:.1e}, FP32 {err[32]:.1e}; PCG oracle {ito}, "
+          f"FP64 {it[0]} (fixed-count error {e64:.1e}), FP32 {it32[0]} (error {e32:.1e})")
     assert err[64] <= 1e-10 and err[32] <= 1e-4
     assert e64 <= 1e-10
     assert status32 == 0 and rr32[0] <= f.w.rtol and it32[0] <= ito + 3 and e32 <= 1e-6
