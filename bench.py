@@ -44,20 +44,34 @@ ROOFLINE_KERNELS = {
     "symgs": "fine-level A_1 sliced-ELL residual (the colour sweeps are separate launches)"}
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel family from the committed rocprofv3
-    counter runs (profiles/hbm_traffic.json), or None if the kernel source or the
-    matrix layout builder changed since the counters were taken."""
+TRAFFIC_SOURCES = {
+    "l1blockgs": ("paper_2107_05613_amd/csrc/kernels_base.hpp", "paper_2107_05613_amd/csrc/kernels_bgs.hpp",
+                  "paper_2107_05613_amd/csrc/block_gs.hpp", "paper_2107_05613_amd/csrc/block_gs.hip"),
+    "l1jacobi": ("paper_2107_05613_amd/csrc/kernels_base.hpp", "paper_2107_05613_amd/csrc/kernels.hpp",
+                 "paper_2107_05613_amd/csrc/sell_layout.hpp", "paper_2107_05613_amd/csrc/sell_layout.cpp"),
+}
+
+
+def traffic_hash(smoother):
+    """Hash of the sources of the dominant kernel family and its matrix layout."""
     import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES.get(smoother, ()):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(smoother):
+    """HBM bytes per launch of the dominant kernel family from the committed rocprofv3
+    counter runs (profiles/hbm_traffic.json), or None if they were taken with another
+    smoother or the kernel source or its matrix layout changed since."""
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "hbm_traffic.json")))
     except (OSError, ValueError):
         return None
-    h = hashlib.sha256()
-    for f in ("paper_2107_05613_amd/csrc/kernels.hpp", "paper_2107_05613_amd/csrc/sell_layout.hpp",
-              "paper_2107_05613_amd/csrc/sell_layout.cpp"):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if h.hexdigest()[:16] != rec.get("source_hash"):
+    if rec.get("smoother") != smoother or smoother not in TRAFFIC_SOURCES:
+        return None
+    if traffic_hash(smoother) != rec.get("source_hash"):
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -772,7 +786,7 @@ def main():
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",
             "frac": k_gbps / PEAK_HBM_GBPS,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(args.smoother),
             "avg_launch_us": 1e3 * k_avg_ms,
             "bytes_per_launch": k_bytes / max(k_launches, 1),
             "launches": k_launches,

@@ -21,7 +21,8 @@
 // the inside entries) are loaded together, then gathered together; the rest follow in
 // uniform loops, and the colour passes read LDS without per-lane branches.  The inside
 // couplings stay in registers, u and w in LDS; the passes synchronise the wave only.  A
-// sweep from x0 = 0 reads the first NIN entries of every row only.
+// sweep from x0 = 0 reads the first wi entries of every row only (wi: the block's most
+// inside entries of a row).
 //
 // Bytes: a full sweep reads every stored entry once (value + 2- or 4-byte code) plus b,
 // x, the row data and writes y, like an l1-Jacobi sweep.
@@ -90,19 +91,22 @@ k_bgs(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint16_t* __re
     int id[NIN];
 #pragma unroll
     for (int t = 0; t < NIN; ++t) {
-        a[t] = av[e0 + t * 64];
-        id[t] = bgs_code<C16>(ci, c16, e0 + t * 64);
+        a[t] = T(0);
+        id[t] = lane;
+        // a sweep from zero needs the block's inside width only (a uniform bound: its
+        // loads are still issued together, no gathers wait on them)
+        if (!ZERO || t < (B.info & 0xff)) {
+            a[t] = av[e0 + t * 64];
+            id[t] = bgs_code<C16>(ci, c16, e0 + t * 64);
+        }
     }
     T acc = 0;
     if (!ZERO) {
-        T xv[NIN];
 #pragma unroll
         for (int t = 0; t < NIN; ++t) {
             const int j = t < W ? bgs_col<C16>(t, nin, id[t], row0, cb) : row0;
-            xv[t] = x[j];
+            acc = fma(t < W ? a[t] : T(0), x[j], acc);
         }
-#pragma unroll
-        for (int t = 0; t < NIN; ++t) acc = fma(t < W ? a[t] : T(0), xv[t], acc);
     }
 #pragma unroll
     for (int t = 0; t < NIN; ++t) {   // keep the inside couplings: value 0 / own position elsewhere
