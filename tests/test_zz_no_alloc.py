@@ -2,7 +2,8 @@
 
 It computes what amge_vcycle computes on one column, with the level work vectors in the
 library's static device scratch instead of a context's buffers; the kernels and their
-order are the same, so the bar is bitwise equality with amge_vcycle.  Checked on two
+order are the same, so the bar is bitwise equality with amge_vcycle (with the l1-Jacobi
+and with the block Gauss-Seidel point smoother).  Checked on two
 calls in a row, the second on a smaller hierarchy (the scratch keeps the first call's
 contents), then again on the first; a hierarchy whose work vectors exceed the scratch
 is refused with AMGE_ERR_ARG before anything runs; torch's allocator sees no
@@ -18,17 +19,18 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def build(kind, n, L, coef, bits):
+def build(kind, n, L, coef, bits, smoother="l1jacobi"):
     from paper_2107_05613_amd import amge
     w = W.Workload("t", kind, n, L, coef)
     a, b = W.coefficients(w)
-    print(f"\n[no-alloc] {kind} n={n} levels={L} FP{bits}", flush=True)
-    return amge.Hierarchy(amge.build_problem(kind, n, L, a, b), precond_bits=bits)
+    print(f"\n[no-alloc] {kind} n={n} levels={L} FP{bits} smoother {smoother}", flush=True)
+    return amge.Hierarchy(amge.build_problem(kind, n, L, a, b), precond_bits=bits, smoother=smoother)
 
 
-def test_static_vcycle_matches_vcycle():
-    big = build("curl", 12, 3, "unit", 32)
-    small = build("div", 8, 3, "blocks", 64)
+@pytest.mark.parametrize("smoother", ["l1jacobi", "l1blockgs"])
+def test_static_vcycle_matches_vcycle(smoother):
+    big = build("curl", 12, 3, "unit", 32, smoother)
+    small = build("div", 8, 3, "blocks", 64, smoother)
     ref = {}
     rhs = {}
     for name, H in (("big", big), ("small", small)):
