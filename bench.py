@@ -177,6 +177,12 @@ def baseline_entry(res, iters_needed):
                        f"hierarchy build {res['t_build_s']:.0f} s not timed (with the smoother's set-up)")}
 
 
+def batched_smoother(args):
+    """Point smoother of the batched and serving legs: the headline's, except the
+    colour-order Gauss-Seidel (single-column only), which falls back to l1-Jacobi."""
+    return args.smoother if args.smoother != "symgs" else "l1jacobi"
+
+
 def run_batched(args, amge, W):
     """Block solve of the multi-right-hand-side workload: all columns in one batched
     FP32-preconditioned PCG call, against the same columns solved one at a time on the
@@ -187,8 +193,9 @@ def run_batched(args, amge, W):
     t0 = time.perf_counter()
     prod = amge.build_problem(w.kind, w.n, w.levels, a, b)
     t_build = time.perf_counter() - t0
+    sm = batched_smoother(args)
     t0 = time.perf_counter()
-    H = amge.Hierarchy(prod, precond_bits=32, max_rhs=w.nrhs)
+    H = amge.Hierarchy(prod, precond_bits=32, max_rhs=w.nrhs, smoother=sm)
     t_setup = time.perf_counter() - t0
     n1, k = H.rows[0], w.nrhs
     B = torch.from_numpy(W.rhs(n1, w.rhs_seed, k)).cuda().reshape(-1)
@@ -238,7 +245,7 @@ def run_batched(args, amge, W):
     by = H.vcycle_bytes(32, nrhs=k)
     H.close()
     # the same block with the all-FP64 V-cycle (plain FP64 PCG)
-    H64 = amge.Hierarchy(prod, precond_bits=64, max_rhs=w.nrhs)
+    H64 = amge.Hierarchy(prod, precond_bits=64, max_rhs=w.nrhs, smoother=sm)
     X.zero_()
     st, its64, _ = H64.pcg(B, X, rtol=w.rtol, maxit=1000, nrhs=k)
     torch.cuda.synchronize()
@@ -254,7 +261,7 @@ def run_batched(args, amge, W):
     return {
         "workload": (f"{w.name}: H({w.kind}) on {w.n}^3x6 Kuhn tets, {w.levels}-level AMGe, {k} right-hand "
                      f"sides (uniform[-1,1] seed {w.rhs_seed}) in one call, FP32 V-cycle in per-column FP64 "
-                     f"PCG to rel-res {w.rtol:g}"),
+                     f"PCG to rel-res {w.rtol:g}, smoother {SMOOTHER_NAMES[sm]}"),
         "fine_dofs": n1,
         "solves_per_s": k / dt_b,
         "ms_per_block": 1e3 * dt_b,
@@ -437,7 +444,7 @@ def run_serving(args):
     from paper_2107_05613_amd import workloads as W
     t0 = time.perf_counter()
     mix = serve.build_mix(num=args.serving_requests, seed=0, slots=args.serving_slots, precond_bits=0,
-                          extension=args.serving_extension)
+                          extension=args.serving_extension, smoother=batched_smoother(args))
     print(f"[bench] serving: {len(mix.keys)} hierarchies built in {time.perf_counter() - t0:.1f}s "
           f"(build {mix.build_s:.1f}s, device setup {mix.setup_s:.1f}s)", file=sys.stderr, flush=True)
     srv, ids = serve.make_server(mix, chunk=8)
@@ -487,7 +494,8 @@ def run_serving(args):
             w = W.Workload(f"{kind}_n{n}_c{cs}", kind, n, W.default_levels(n), "blocks", coef_seed=cs)
             a, be = W.coefficients(w)
             fp64[i] = amge.Hierarchy(amge.build_problem(kind, n, w.levels, a, be, extension=args.serving_extension,
-                                                        device=True), precond_bits=64, max_rhs=args.serving_slots)
+                                                        device=True), precond_bits=64, max_rhs=args.serving_slots,
+                                     smoother=batched_smoother(args))
             rebuilt.append(fp64[i])
     mix64 = serve.Mix(mix.requests, mix.keys, fp64, mix.hid_of, mix.rhs, mix.x)
     srv64, ids64 = serve.make_server(mix64, chunk=8)
@@ -510,7 +518,8 @@ def run_serving(args):
                      f"of 2 seeds per (type, n): {mix_desc['keys']} resident hierarchies, {args.serving_slots} PCG "
                      f"columns each; "
                      f"V-cycle precision per hierarchy from trial solves at set-up, per-column FP64 PCG "
-                     f"to rel-res 1e-8; local extensions: {args.serving_extension}"),
+                     f"to rel-res 1e-8; local extensions: {args.serving_extension}; smoother "
+                     f"{SMOOTHER_NAMES[batched_smoother(args)]}"),
         "precision": {"fp32_hierarchies": len(fp32_keys), "fp64_hierarchies": len(prec) - len(fp32_keys),
                       "fp32": [f"{k[0]} n={k[1]} seed {k[2]}" for k in fp32_keys],
                       "fp32_with_fp64_fine_residual": [f"{k[0]} n={k[1]} seed {k[2]}" for k in resid64_keys],

@@ -276,8 +276,8 @@ class Hierarchy:
     of a context (the batched path); tail_rows: levels of at most this many rows below the
     fine one are folded into one dense FP64 operator (0: every level runs its kernels);
     smoother: "l1jacobi", "symgs" (symmetric Gauss-Seidel in colour order) or "l1blockgs"
-    (l1-scaled symmetric block Gauss-Seidel, 64-row blocks); the Gauss-Seidel smoothers run
-    single-column contexts only; resid_bits: precision of an FP32 V-cycle's fine-level residual (32,
+    (l1-scaled symmetric block Gauss-Seidel, 64-row blocks); "symgs" runs single-column
+    contexts only; resid_bits: precision of an FP32 V-cycle's fine-level residual (32,
     64, or 0: 32 unless the trial picks 64); allocator: "torch" (torch's caching
     allocator) or None (hipMalloc)."""
 

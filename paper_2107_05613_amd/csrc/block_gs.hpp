@@ -39,9 +39,20 @@ void bgs_launch(const DBgs& g, bool zero, const T* x, const T* b, T* y, hipStrea
 template <class T>
 void bgs_resid_launch(const DBgs& g, bool v64, const T* x, const T* b, T* y, hipStream_t s, const int* stop);
 
-// Algorithmic bytes of one sweep, and of one residual (vbytes: value size).
-double bgs_bytes(const DBgs& g, bool zero, int vbytes);
-double bgs_resid_bytes(const DBgs& g, int vbytes, int xbytes);
+// Batched sweep and residual on the first W (a power of two) of the NC columns of
+// row-major n x NC blocks; launched solo, or recorded while a launch recorder is
+// installed (grouped launches of the serving engine).
+template <class T>
+void bgs_mm_launch(const DBgs& g, bool zero, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
+                   hipStream_t s);
+template <class T>
+void bgs_resid_mm_launch(const DBgs& g, bool v64, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
+                         hipStream_t s);
+
+// Algorithmic bytes of one sweep, and of one residual (vbytes: value size; cols: columns
+// of the vector blocks, the matrix read once for all of them).
+double bgs_bytes(const DBgs& g, bool zero, int vbytes, int cols = 1);
+double bgs_resid_bytes(const DBgs& g, int vbytes, int xbytes, int cols = 1);
 
 // One host sweep in FP64 on x in place (tmp: scratch of n values).
 void host_bgs_sweep(const BgsHost& g, const double* b, double* x, std::vector<double>& tmp);

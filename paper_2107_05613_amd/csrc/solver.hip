@@ -994,6 +994,22 @@ void bprimary(amge_hierarchy* H, DLevel& L, const T* b, const T* bd, T*& x, T*& 
     Work<T>& w = L.bw<T>();
     const int NC = H->NC;
     int k = 0;
+    if (L.bgA.on()) {   // block Gauss-Seidel sweeps, arranged as in bgs_sweeps (no final copy)
+        if (from_zero) {
+            if (nu <= 0) {
+                bfill<T>((int64_t)L.n * NC, x, stop, s);
+                return;
+            }
+            std::swap(x, xt);
+            bgs_mm_launch<T>(L.bgA, true, W, NC, nullptr, b, x, stop, s);
+            k = 1;
+        }
+        for (; k < nu; ++k) {
+            bgs_mm_launch<T>(L.bgA, false, W, NC, x, b, xt, stop, s);
+            std::swap(x, xt);
+        }
+        return;
+    }
     if (from_zero) {
         if (nu >= 2) {
             // bd = dinv b from the producer of b, or (bd null) formed by the sweep itself
@@ -1019,6 +1035,20 @@ void bauxiliary(amge_hierarchy* H, DLevel& L, const T* b, T* x, int nu, int W, c
     if (nu <= 0 || L.m == 0) return;
     Work<T>& w = L.bw<T>();
     const int NC = H->NC;
+    if (L.bgAh.on()) {   // block Gauss-Seidel sweeps on D^T A D from zero
+        bmm<T>(L.bAux, dev::SPLIT, W, NC, x, b, nullptr, w.g, stop, s);
+        T* y = w.y;
+        T* yt = w.yt;
+        bgs_mm_launch<T>(L.bgAh, true, W, NC, nullptr, w.g, yt, stop, s);
+        y = yt;
+        yt = w.y;
+        for (int k = 1; k < nu; ++k) {
+            bgs_mm_launch<T>(L.bgAh, false, W, NC, y, w.g, yt, stop, s);
+            std::swap(y, yt);
+        }
+        inc_mm_add<T>(L.bD, W, NC, y, x, stop, s);
+        return;
+    }
     bmm<T>(L.bAux, dev::SPLIT, W, NC, x, b, w.dhinv, w.g, stop, s, w.gd);
     const T* y = w.gd;
     T* ya = w.y;
@@ -1117,10 +1147,14 @@ void bvcycle_level(amge_hierarchy* H, int l, const T* b, const T* bd, T* xout, i
     T* x = xout;
     T* xt = w.xt;
     const int nup = H->opts.nu_primary, nua = H->opts.nu_aux;
-    const bool next_coarsest = l + 1 == H->tail;   // needs no first sweep of its own
+    // the coarse level's first l1-Jacobi sweep from zero, written with its right-hand side
+    // (not needed by the coarsest level or the block Gauss-Seidel smoother)
+    const bool next_coarsest = l + 1 == H->tail || C.bgA.on();
     bprimary<T>(H, L, b, bd, x, xt, true, nup, W, stop, s);
     bauxiliary<T>(H, L, b, x, nua, W, stop, s);
-    if constexpr (std::is_same<T, float>::value) {
+    if (L.bgA.on()) {
+        bgs_resid_mm_launch<T>(L.bgA, std::is_same<T, float>::value && L.resid64, W, NC, x, b, w.r, stop, s);
+    } else if constexpr (std::is_same<T, float>::value) {
         if (L.resid64) bmm_resid64(L.bA, W, NC, x, b, w.r, stop, s);
         else bmm<T>(L.bA, dev::RESID, W, NC, x, b, nullptr, w.r, stop, s);
     } else {
@@ -2397,8 +2431,8 @@ extern "C" amge_status amge_setup_hierarchy(const amge_level* levels, int32_t nl
         if (H->opts.smoother != AMGE_SMOOTHER_L1_JACOBI && H->opts.smoother != AMGE_SMOOTHER_SYM_GS &&
             H->opts.smoother != AMGE_SMOOTHER_BLOCK_GS)
             fail(AMGE_ERR_ARG, "unknown smoother");
-        if (H->opts.smoother != AMGE_SMOOTHER_L1_JACOBI && H->opts.max_rhs > 1)
-            fail(AMGE_ERR_ARG, "the Gauss-Seidel smoothers run single-column contexts only (max_rhs = 1)");
+        if (H->opts.smoother == AMGE_SMOOTHER_SYM_GS && H->opts.max_rhs > 1)
+            fail(AMGE_ERR_ARG, "the colour-order Gauss-Seidel smoother runs single-column contexts only (max_rhs = 1)");
         setup(H.get(), levels, nlevels, (hipStream_t)stream);
         *out = H.release();
         return AMGE_OK;
@@ -2702,8 +2736,7 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
             // block Gauss-Seidel: nu sweeps, the first of a smoothing from zero a pre-smoothing
             auto bgb = [&](const DBgs& g, int nu, bool zero) {
                 if (nu <= 0) return zero ? sx * g.n : 0.0;
-                return (zero ? bgs_bytes(g, true, (int)sv) : bgs_bytes(g, false, (int)sv)) +
-                       (nu - 1) * bgs_bytes(g, false, (int)sv);
+                return bgs_bytes(g, zero, (int)sv, nrhs) + (nu - 1) * bgs_bytes(g, false, (int)sv, nrhs);
             };
             if (bg) {
                 tot += bgb(L.bgA, nup, true) + bgb(L.bgA, nup, false);
@@ -2744,8 +2777,8 @@ extern "C" amge_status amge_vcycle_bytes(const amge_hierarchy* h, int32_t precis
                 // an FP32 cycle's fine-level residual with resid64 reads the FP64 values
                 const double extra = (precision == 32 && L.resid64)
                                          ? (double)(batched ? L.bA.nnz : L.A.nnz) * (8.0 - sv) : 0.0;
-                if (bg && !batched)
-                    tot += bgs_resid_bytes(L.bgA, (precision == 32 && L.resid64) ? 8 : (int)sv, (int)sv);
+                if (bg)
+                    tot += bgs_resid_bytes(L.bgA, (precision == 32 && L.resid64) ? 8 : (int)sv, (int)sv, nrhs);
                 else
                     tot += mat(L.A, L.bA) + extra + 3 * sx * n;
                 tot += mat(L.Pt, L.bPt) + sx * (n + nc);

@@ -30,11 +30,11 @@ class Mix:
 
 
 def build_mix(num=256, seed=0, sizes=(16, 24, 32, 48, 64), coef_pool=2, slots=8, precond_bits=0,
-              nu_primary=2, nu_aux=2, tail_rows=2048, extension="l2"):
+              nu_primary=2, nu_aux=2, tail_rows=2048, extension="l2", smoother="l1jacobi"):
     """Hierarchies for every (kind, n, coefficient seed) of the stream (coefficients as the
     jump workload: per 4^3-hex block 10^U(-3,3)), and one right-hand side per request
     (seed = request id).  precond_bits 0 lets every hierarchy pick its V-cycle precision
-    from its cancellation factor."""
+    by trial solves at set-up; smoother: the point smoother ("l1jacobi" or "l1blockgs")."""
     import torch
     reqs = W.serving_requests(num, seed, sizes, coef_pool, rate=1.0)
     keys = sorted({(r["kind"], r["n"], r["coef_seed"]) for r in reqs})
@@ -46,7 +46,8 @@ def build_mix(num=256, seed=0, sizes=(16, 24, 32, 48, 64), coef_pool=2, slots=8,
         prod = amge.build_problem(kind, n, w.levels, a, b, extension=extension, device=True)
         t1 = time.perf_counter()
         hs.append(amge.Hierarchy(prod, precond_bits=precond_bits, max_rhs=slots, nu_primary=nu_primary,
-                                 nu_aux=nu_aux, tail_rows=tail_rows(n) if callable(tail_rows) else tail_rows))
+                                 nu_aux=nu_aux, tail_rows=tail_rows(n) if callable(tail_rows) else tail_rows,
+                                 smoother=smoother))
         tb += t1 - t0
         ts += time.perf_counter() - t1
     index = {k: i for i, k in enumerate(keys)}

@@ -34,25 +34,27 @@ SLOTS = 4
 
 
 class Resident:
-    def __init__(self, precond_bits, resid_bits=0):
+    def __init__(self, precond_bits, resid_bits=0, smoother="l1jacobi"):
         from paper_2107_05613_amd import amge
+        self.smoother = smoother
         self.prods, self.H, self.n1 = [], [], []
         for kind, n, L, coef, cs in SPECS:
             w = W.Workload("t", kind, n, L, coef, coef_seed=cs)
             a, b = W.coefficients(w)
             prod = amge.build_problem(kind, n, L, a, b)
             self.prods.append((w, a, b))
-            self.H.append(amge.Hierarchy(prod, precond_bits=precond_bits, max_rhs=SLOTS, resid_bits=resid_bits))
+            self.H.append(amge.Hierarchy(prod, precond_bits=precond_bits, max_rhs=SLOTS, resid_bits=resid_bits,
+                                         smoother=smoother))
             self.n1.append(self.H[-1].rows[0])
 
 
 _RES = {}
 
 
-def resident(bits, resid_bits=0):
-    if (bits, resid_bits) not in _RES:
-        _RES[(bits, resid_bits)] = Resident(bits, resid_bits)
-    return _RES[(bits, resid_bits)]
+def resident(bits, resid_bits=0, smoother="l1jacobi"):
+    if (bits, resid_bits, smoother) not in _RES:
+        _RES[(bits, resid_bits, smoother)] = Resident(bits, resid_bits, smoother)
+    return _RES[(bits, resid_bits, smoother)]
 
 
 def requests(res, num, seed=0):
@@ -262,6 +264,60 @@ def test_served_fp32_matches_oracle(resid_bits):
         print(f"request {j} (hierarchy {h}): {iters} iterations (oracle {ito}), error vs oracle {err:.1e}")
         assert status == 0 and relres <= 1e-8 and iters <= ito + 3
         assert err <= 1e-6
+
+
+class _OracleResident:
+    """The SPECS hierarchies set up from the oracle's own level matrices (the block
+    smoother's colours depend on which couplings are nonzero, so both sides take the
+    same matrices), with the oracle's block Gauss-Seidel V-cycle beside them."""
+
+    def __init__(self, precond_bits, smoother):
+        from oracle.hierarchy import build_hierarchy
+        from oracle.solve import Multilevel
+        from paper_2107_05613_amd import amge
+        self.H, self.n1, self.oracle = [], [], []
+        for kind, n, L, coef, cs in SPECS:
+            a, b = W.coefficients(W.Workload("t", kind, n, L, coef, coef_seed=cs))
+            Ho = build_hierarchy(kind, n, L, a, b, check_targets=False)
+            levels = [(Ho.A[k], Ho.D[k], Ho.P[k] if k < L - 1 else None) for k in range(L)]
+            self.H.append(amge.Hierarchy(levels, precond_bits=precond_bits, max_rhs=SLOTS, smoother=smoother))
+            self.n1.append(self.H[-1].rows[0])
+            self.oracle.append((Ho, Multilevel.from_hierarchy(Ho, smoother=smoother, gs_block=64)))
+
+
+def test_served_block_gs():
+    """Served requests on hierarchies with the l1-scaled symmetric block Gauss-Seidel
+    smoother (set up from the oracle's level matrices): FP64 preconditioner at a fixed
+    iteration count against the oracle's block Gauss-Seidel PCG iterate (max(1e-10, 3 s));
+    FP32 preconditioner to rtol 1e-8 within 3 iterations of the oracle's count and 1e-6
+    of its solution; and the same requests with the hierarchies as one ensemble (grouped
+    launches of the batched block sweeps) bitwise as served one by one."""
+    from oracle.solve import pcg
+    r64, r32 = _OracleResident(64, "l1blockgs"), _OracleResident(32, "l1blockgs")
+    reqs = requests(r64, 6, seed=5)
+    k = 7
+    out64 = serve(r64, reqs, list(range(len(reqs))), maxit={j: k for j in range(len(reqs))})
+    out32 = serve(r32, reqs, list(range(len(reqs))))
+    grouped = serve(r32, reqs, list(range(len(reqs))), grouped=[0] * len(r32.H))
+    for j, (h, b) in enumerate(reqs):
+        H, ml = r64.oracle[h]
+        bb = b.cpu().numpy()
+        tol = fp64_bar(spreads(H, bb, k, smoother="l1blockgs")["pcg"])
+        xk, _, _ = pcg(H.A[0], bb, ml, fixed_iters=k)
+        xo, ito, _ = pcg(H.A[0], bb, ml, rtol=1e-8)
+        s64, it64, _, x64 = out64[j]
+        s32, it32, rr32, x32 = out32[j]
+        e64 = np.linalg.norm(x64 - xk) / np.linalg.norm(xk)
+        e32 = np.linalg.norm(x32 - xo) / np.linalg.norm(xo)
+        print(f"request {j} (hierarchy {h}): FP64 {k} iterations, error {e64:.1e} (tol {tol:.1e}); FP32 {it32} "
+              f"iterations (oracle {ito}), error {e32:.1e}")
+        assert s64 == 1 and it64 == k and e64 <= tol
+        assert s32 == 0 and rr32 <= 1e-8 and it32 <= ito + 3 and e32 <= 1e-6
+        g = grouped[j]
+        assert g[:3] == out32[j][:3] and np.array_equal(g[3], x32), j
+    for r in (r64, r32):
+        for H in r.H:
+            H.close()
 
 
 def test_admission_by_inflight_budget():
