@@ -91,7 +91,7 @@ BgsHost bgs_layout(const Csr& A) {
         g.nnz_in += inside[bk];
     }
     if (g.ninmax > BGS_ROWS) fail(AMGE_ERR_SHAPE, "duplicate entries in a block Gauss-Seidel matrix");
-    static const int bounds[] = {8, 12, 16, 24, 32, 48, 64};
+    static const int bounds[] = {8, 12, 16, 32, 64};
     for (int bnd : bounds)
         if (g.ninmax <= bnd) {
             g.nin = bnd;
@@ -183,9 +183,7 @@ void go_nin(const DBgs& g, const T* x, const T* b, T* y, hipStream_t s, const in
         case 8: go<T, C16, ZERO, 8>(g, x, b, y, s, stop); break;
         case 12: go<T, C16, ZERO, 12>(g, x, b, y, s, stop); break;
         case 16: go<T, C16, ZERO, 16>(g, x, b, y, s, stop); break;
-        case 24: go<T, C16, ZERO, 24>(g, x, b, y, s, stop); break;
         case 32: go<T, C16, ZERO, 32>(g, x, b, y, s, stop); break;
-        case 48: go<T, C16, ZERO, 48>(g, x, b, y, s, stop); break;
         default: go<T, C16, ZERO, 64>(g, x, b, y, s, stop); break;
     }
 }
@@ -235,108 +233,6 @@ template void bgs_resid_launch<float>(const DBgs&, bool, const float*, const flo
                                       const int*);
 template void bgs_resid_launch<double>(const DBgs&, bool, const double*, const double*, double*, hipStream_t,
                                        const int*);
-
-namespace {
-
-// Columns per wave of the batched sweeps: 16-byte rows of the vector blocks where the
-// active width allows.
-template <class T>
-int bgs_cols(int W) {
-    const int v = 16 / (int)sizeof(T);
-    return std::min(W, v);
-}
-
-template <class T, int V, bool C16, bool ZERO, int NIN>
-void go_mm(const DBgs& g, int W, int NC, const T* X, const T* B, T* Y, const int* stop, hipStream_t s) {
-    const int L = W / V;
-    const int64_t waves = (int64_t)g.nblk * L;
-    launch<dev::BgsMM<T, V, C16, ZERO, NIN>>((unsigned)((waves + dev::WAVES - 1) / dev::WAVES), s, g.nblk, g.n, L,
-                                             NC, (const dev::BgsBlock*)g.blk, (const uint16_t*)g.meta,
-                                             (const int*)g.ci, (const uint16_t*)g.c16, vals<T>(g), dinvs<T>(g),
-                                             mids<T>(g), X, B, Y, stop);
-}
-
-template <class T, int V, bool C16, bool ZERO>
-void go_mm_nin(const DBgs& g, int W, int NC, const T* X, const T* B, T* Y, const int* stop, hipStream_t s) {
-    switch (g.nin) {
-        case 8: go_mm<T, V, C16, ZERO, 8>(g, W, NC, X, B, Y, stop, s); break;
-        case 12: go_mm<T, V, C16, ZERO, 12>(g, W, NC, X, B, Y, stop, s); break;
-        case 16: go_mm<T, V, C16, ZERO, 16>(g, W, NC, X, B, Y, stop, s); break;
-        case 24: go_mm<T, V, C16, ZERO, 24>(g, W, NC, X, B, Y, stop, s); break;
-        case 32: go_mm<T, V, C16, ZERO, 32>(g, W, NC, X, B, Y, stop, s); break;
-        case 48: go_mm<T, V, C16, ZERO, 48>(g, W, NC, X, B, Y, stop, s); break;
-        default: go_mm<T, V, C16, ZERO, 64>(g, W, NC, X, B, Y, stop, s); break;
-    }
-}
-
-template <class T, int V>
-void go_mm_v(const DBgs& g, bool zero, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
-             hipStream_t s) {
-    const bool c16 = g.c16 != nullptr;
-    if (zero) {
-        if (c16) go_mm_nin<T, V, true, true>(g, W, NC, X, B, Y, stop, s);
-        else go_mm_nin<T, V, false, true>(g, W, NC, X, B, Y, stop, s);
-    } else {
-        if (c16) go_mm_nin<T, V, true, false>(g, W, NC, X, B, Y, stop, s);
-        else go_mm_nin<T, V, false, false>(g, W, NC, X, B, Y, stop, s);
-    }
-}
-
-template <class T, int V, class TV>
-void go_resid_mm(const DBgs& g, const TV* av, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
-                 hipStream_t s) {
-    const int L = W / V;
-    const int64_t waves = (int64_t)g.nblk * L;
-    const unsigned grid = (unsigned)((waves + dev::WAVES - 1) / dev::WAVES);
-    if (g.c16)
-        launch<dev::BgsResidMM<T, V, true, TV>>(grid, s, g.nblk, g.n, L, NC, (const dev::BgsBlock*)g.blk,
-                                                (const uint16_t*)g.meta, (const int*)g.ci, (const uint16_t*)g.c16, av,
-                                                X, B, Y, stop);
-    else
-        launch<dev::BgsResidMM<T, V, false, TV>>(grid, s, g.nblk, g.n, L, NC, (const dev::BgsBlock*)g.blk,
-                                                 (const uint16_t*)g.meta, (const int*)g.ci, (const uint16_t*)g.c16,
-                                                 av, X, B, Y, stop);
-}
-
-template <class T, class TV>
-void go_resid_mm_v(const DBgs& g, const TV* av, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
-                   hipStream_t s) {
-    switch (bgs_cols<T>(W)) {
-        case 1: go_resid_mm<T, 1, TV>(g, av, W, NC, X, B, Y, stop, s); break;
-        case 2: go_resid_mm<T, 2, TV>(g, av, W, NC, X, B, Y, stop, s); break;
-        default: go_resid_mm<T, (16 / sizeof(T) >= 4 ? 4 : 2), TV>(g, av, W, NC, X, B, Y, stop, s); break;
-    }
-}
-
-}  // namespace
-
-template <class T>
-void bgs_mm_launch(const DBgs& g, bool zero, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
-                   hipStream_t s) {
-    if (g.nblk == 0) return;
-    switch (bgs_cols<T>(W)) {
-        case 1: go_mm_v<T, 1>(g, zero, W, NC, X, B, Y, stop, s); break;
-        case 2: go_mm_v<T, 2>(g, zero, W, NC, X, B, Y, stop, s); break;
-        default: go_mm_v<T, (16 / sizeof(T) >= 4 ? 4 : 2)>(g, zero, W, NC, X, B, Y, stop, s); break;
-    }
-}
-
-template <class T>
-void bgs_resid_mm_launch(const DBgs& g, bool v64, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
-                         hipStream_t s) {
-    if (g.nblk == 0) return;
-    if (v64 && !std::is_same<T, double>::value) go_resid_mm_v<T, double>(g, g.v64, W, NC, X, B, Y, stop, s);
-    else go_resid_mm_v<T, T>(g, vals<T>(g), W, NC, X, B, Y, stop, s);
-}
-
-template void bgs_mm_launch<float>(const DBgs&, bool, int, int, const float*, const float*, float*, const int*,
-                                   hipStream_t);
-template void bgs_mm_launch<double>(const DBgs&, bool, int, int, const double*, const double*, double*, const int*,
-                                    hipStream_t);
-template void bgs_resid_mm_launch<float>(const DBgs&, bool, int, int, const float*, const float*, float*,
-                                         const int*, hipStream_t);
-template void bgs_resid_mm_launch<double>(const DBgs&, bool, int, int, const double*, const double*, double*,
-                                          const int*, hipStream_t);
 
 double bgs_bytes(const DBgs& g, bool zero, int vbytes, int cols) {
     const double cb = g.c16 ? 2 : 4;

@@ -1,0 +1,120 @@
+// l1-scaled symmetric block Gauss-Seidel smoother on the batched path (n x NC blocks):
+// launches of the sweep and residual bodies of kernels_bgs.hpp, solo or recorded for
+// grouped launches.  Included by one translation unit per vector type BGS_T, so that the
+// kernel instances of the two types compile in parallel.
+#ifndef BGS_T
+#error "define BGS_T (float or double) before including this file"
+#endif
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
+
+#include "block_gs.hpp"
+#include "kernels_bgs.hpp"
+
+namespace amge {
+
+namespace {
+
+template <class T> const T* vals(const DBgs& g);
+template <> const double* vals<double>(const DBgs& g) { return g.v64; }
+template <> const float* vals<float>(const DBgs& g) { return g.v32; }
+template <class T> const T* dinvs(const DBgs& g);
+template <> const double* dinvs<double>(const DBgs& g) { return g.dinv64; }
+template <> const float* dinvs<float>(const DBgs& g) { return g.dinv32; }
+template <class T> const T* mids(const DBgs& g);
+template <> const double* mids<double>(const DBgs& g) { return g.mid64; }
+template <> const float* mids<float>(const DBgs& g) { return g.mid32; }
+
+}  // namespace
+
+namespace {
+
+// Columns per wave of the batched sweeps: 32-byte rows of the vector blocks (fewer waves
+// per block re-read its entries), or one column per wave when fewer columns are active.
+template <class T>
+int bgs_cols(int W) {
+    const int v = 32 / (int)sizeof(T);
+    return W >= v ? v : 1;
+}
+
+template <class T, int V, bool C16, bool ZERO, int NIN>
+void go_mm(const DBgs& g, int W, int NC, const T* X, const T* B, T* Y, const int* stop, hipStream_t s) {
+    const int L = W / V;
+    const int64_t waves = (int64_t)g.nblk * L;
+    launch<dev::BgsMM<T, V, C16, ZERO, NIN>>((unsigned)((waves + dev::WAVES - 1) / dev::WAVES), s, g.nblk, g.n, L,
+                                             NC, (const dev::BgsBlock*)g.blk, (const uint16_t*)g.meta,
+                                             (const int*)g.ci, (const uint16_t*)g.c16, vals<T>(g), dinvs<T>(g),
+                                             mids<T>(g), X, B, Y, stop);
+}
+
+template <class T, int V, bool C16, bool ZERO>
+void go_mm_nin(const DBgs& g, int W, int NC, const T* X, const T* B, T* Y, const int* stop, hipStream_t s) {
+    // register bounds of the batched bodies: 8, 16, 32 or 64 (fewer instances)
+    if (g.nin <= 8) go_mm<T, V, C16, ZERO, 8>(g, W, NC, X, B, Y, stop, s);
+    else if (g.nin <= 16) go_mm<T, V, C16, ZERO, 16>(g, W, NC, X, B, Y, stop, s);
+    else if (g.nin <= 32) go_mm<T, V, C16, ZERO, 32>(g, W, NC, X, B, Y, stop, s);
+    else go_mm<T, V, C16, ZERO, 64>(g, W, NC, X, B, Y, stop, s);
+}
+
+template <class T, int V>
+void go_mm_v(const DBgs& g, bool zero, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
+             hipStream_t s) {
+    const bool c16 = g.c16 != nullptr;
+    if (zero) {
+        if (c16) go_mm_nin<T, V, true, true>(g, W, NC, X, B, Y, stop, s);
+        else go_mm_nin<T, V, false, true>(g, W, NC, X, B, Y, stop, s);
+    } else {
+        if (c16) go_mm_nin<T, V, true, false>(g, W, NC, X, B, Y, stop, s);
+        else go_mm_nin<T, V, false, false>(g, W, NC, X, B, Y, stop, s);
+    }
+}
+
+template <class T, int V, class TV>
+void go_resid_mm(const DBgs& g, const TV* av, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
+                 hipStream_t s) {
+    const int L = W / V;
+    const int64_t waves = (int64_t)g.nblk * L;
+    const unsigned grid = (unsigned)((waves + dev::WAVES - 1) / dev::WAVES);
+    if (g.c16)
+        launch<dev::BgsResidMM<T, V, true, TV>>(grid, s, g.nblk, g.n, L, NC, (const dev::BgsBlock*)g.blk,
+                                                (const uint16_t*)g.meta, (const int*)g.ci, (const uint16_t*)g.c16, av,
+                                                X, B, Y, stop);
+    else
+        launch<dev::BgsResidMM<T, V, false, TV>>(grid, s, g.nblk, g.n, L, NC, (const dev::BgsBlock*)g.blk,
+                                                 (const uint16_t*)g.meta, (const int*)g.ci, (const uint16_t*)g.c16,
+                                                 av, X, B, Y, stop);
+}
+
+template <class T, class TV>
+void go_resid_mm_v(const DBgs& g, const TV* av, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
+                   hipStream_t s) {
+    if (bgs_cols<T>(W) == 1) go_resid_mm<T, 1, TV>(g, av, W, NC, X, B, Y, stop, s);
+    else go_resid_mm<T, 32 / sizeof(T), TV>(g, av, W, NC, X, B, Y, stop, s);
+}
+
+}  // namespace
+
+template <class T>
+void bgs_mm_launch(const DBgs& g, bool zero, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
+                   hipStream_t s) {
+    if (g.nblk == 0) return;
+    if (bgs_cols<T>(W) == 1) go_mm_v<T, 1>(g, zero, W, NC, X, B, Y, stop, s);
+    else go_mm_v<T, 32 / sizeof(T)>(g, zero, W, NC, X, B, Y, stop, s);
+}
+
+template <class T>
+void bgs_resid_mm_launch(const DBgs& g, bool v64, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
+                         hipStream_t s) {
+    if (g.nblk == 0) return;
+    if (v64 && !std::is_same<T, double>::value) go_resid_mm_v<T, double>(g, g.v64, W, NC, X, B, Y, stop, s);
+    else go_resid_mm_v<T, T>(g, vals<T>(g), W, NC, X, B, Y, stop, s);
+}
+
+template void bgs_mm_launch<BGS_T>(const DBgs&, bool, int, int, const BGS_T*, const BGS_T*, BGS_T*, const int*,
+                                   hipStream_t);
+template void bgs_resid_mm_launch<BGS_T>(const DBgs&, bool, int, int, const BGS_T*, const BGS_T*, BGS_T*,
+                                         const int*, hipStream_t);
+
+}  // namespace amge

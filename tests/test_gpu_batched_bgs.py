@@ -121,9 +121,10 @@ def test_batched_bgs_pcg(spec, nrhs):
 
 
 def test_batched_bgs_column_independent_of_block():
-    """Column 2 of a 3-column V-cycle (active width 4, four columns per wave) equals the
-    same right-hand side as column 0 of a 2-column V-cycle (width 2, two columns per wave)
-    next to other data, bit for bit, in both precisions."""
+    """Column 2 of a 3-column V-cycle (active width 4) equals the same right-hand side as
+    column 0 of a 2-column V-cycle (width 2) next to other data, and column 2 of a
+    4-column block equals it in a block whose other columns differ, bit for bit, in both
+    precisions."""
     c = case("curl", 16, 4, "blocks", 4)
     B = W.rhs(c.n1, 17, 3)
     B2 = np.ascontiguousarray(np.stack([B[:, 2], W.rhs(c.n1, 18)[:, 0]], 1))
