@@ -31,18 +31,19 @@ BgsHost bgs_layout(const Csr& A) {
     g.nnz = A.nnz();
     g.nblk = (n + BGS_ROWS - 1) / BGS_ROWS;
     g.blk.resize(g.nblk);
-    g.meta.assign(n, 0);
+    g.meta.assign((size_t)g.nblk * BGS_ROWS, 0xffu << 24);
     g.dinv.assign(n, 0.0);
     g.mid.assign(n, 0.0);
-    std::vector<int> width(g.nblk, 0), wi(g.nblk, 0), cmin(g.nblk, 0), cmax(g.nblk, 0);
-    std::vector<int64_t> inside(g.nblk, 0);
+    std::vector<int> wi(g.nblk, 0), cmin(g.nblk, 0), cmax(g.nblk, 0);
+    std::vector<int64_t> inside(g.nblk, 0), stored(g.nblk, 0);
     std::vector<std::string> err(g.nblk);
-    // colours, inside counts, l1 sums and block shapes, block by block
+    // colours, inside counts, l1 sums, lane order (rows by length, longest first) and block
+    // shapes, block by block
     parallel_for(g.nblk, [&](int64_t b0, int64_t b1) {
-        std::vector<int> colour(BGS_ROWS);
+        int colour[BGS_ROWS], nin[BGS_ROWS], len[BGS_ROWS], lane_row[BGS_ROWS];
         for (int64_t bk = b0; bk < b1; ++bk) {
-            const int r0 = (int)bk * BGS_ROWS, r1 = std::min(n, r0 + BGS_ROWS);
-            int w = 0, mi = 0, ncol = 0;
+            const int r0 = (int)bk * BGS_ROWS, r1 = std::min(n, r0 + BGS_ROWS), nr = r1 - r0;
+            int mi = 0, ncol = 0;
             int lo = std::numeric_limits<int>::max(), hi = -1;
             for (int i = r0; i < r1; ++i) {
                 uint64_t used = 0;
@@ -63,22 +64,34 @@ BgsHost bgs_layout(const Csr& A) {
                 }
                 const int c = __builtin_ctzll(~used);
                 colour[i - r0] = c;
-                g.meta[i] = (uint16_t)(k | c << 8);
+                nin[i - r0] = k;
+                len[i - r0] = A.rowptr[i + 1] - A.rowptr[i];
                 const double d = aii + l1;
                 if (!(aii > 0) || !(d > 0)) {
                     err[bk] = "block Gauss-Seidel needs a positive diagonal";
                     break;
                 }
+                if (len[i - r0] > 255) {
+                    err[bk] = "block Gauss-Seidel rows hold at most 255 entries";
+                    break;
+                }
                 g.dinv[i] = 1.0 / d;
                 g.mid[i] = aii + 2.0 * l1;
                 mi = std::max(mi, k);
-                w = std::max(w, A.rowptr[i + 1] - A.rowptr[i]);
                 ncol = std::max(ncol, c + 1);
                 inside[bk] += k;
+                stored[bk] += len[i - r0];
             }
-            width[bk] = w;
+            if (!err[bk].empty()) continue;
+            for (int q = 0; q < nr; ++q) lane_row[q] = q;
+            std::stable_sort(lane_row, lane_row + nr, [&](int u, int v) { return len[u] > len[v]; });
+            for (int q = 0; q < nr; ++q) {
+                const int p = lane_row[q];
+                g.meta[(size_t)bk * BGS_ROWS + q] =
+                    (uint32_t)nin[p] | (uint32_t)colour[p] << 8 | (uint32_t)len[p] << 16 | (uint32_t)p << 24;
+            }
             wi[bk] = mi;
-            g.blk[bk].width = w;
+            g.blk[bk].width = nr ? len[lane_row[0]] : 0;
             g.blk[bk].info = mi | ncol << 8;
             cmin[bk] = hi >= 0 ? lo : 0;
             cmax[bk] = hi >= 0 ? hi : 0;
@@ -103,27 +116,35 @@ BgsHost bgs_layout(const Csr& A) {
     for (int bk = 0; bk < g.nblk; ++bk) {
         g.blk[bk].base = (int)base;
         g.blk[bk].cbase = g.c16 ? cmin[bk] : 0;
-        base += (int64_t)BGS_ROWS * width[bk];
-        if (base > std::numeric_limits<int>::max()) fail(AMGE_ERR_SHAPE, "block Gauss-Seidel layout too large");
+        base += stored[bk];
+        if (base > std::numeric_limits<int>::max() - 64 * 65) fail(AMGE_ERR_SHAPE, "block Gauss-Seidel layout too large");
     }
-    // the sweeps read the first g.nin entries of every row of a block unconditionally:
-    // pad past the end so that the last block's reads stay inside the arrays
-    g.code.assign(base + (int64_t)BGS_ROWS * g.nin, 0);
-    g.val.assign(base + (int64_t)BGS_ROWS * g.nin, 0.0);
+    // the kernels issue loads for every lane of every slab up to their register bound
+    // (results of lanes past a slab's rows are masked): pad past the end so that the last
+    // block's loads stay inside the arrays
+    g.code.assign(base + (int64_t)BGS_ROWS * (g.nin + 1), 0);
+    g.val.assign(base + (int64_t)BGS_ROWS * (g.nin + 1), 0.0);
     parallel_for(g.nblk, [&](int64_t b0, int64_t b1) {
         for (int64_t bk = b0; bk < b1; ++bk) {
             const int r0 = (int)bk * BGS_ROWS, r1 = std::min(n, r0 + BGS_ROWS);
-            const int64_t e0 = g.blk[bk].base;
             const int cb = g.blk[bk].cbase;
-            for (int i = r0; i < r1; ++i) {
-                const int lane = i - r0;
-                int tin = 0, tout = g.meta[i] & 0xff;
-                for (int q = A.rowptr[i]; q < A.rowptr[i + 1]; ++q) {
-                    const int j = A.col[q];
+            const uint32_t* mt = &g.meta[(size_t)bk * BGS_ROWS];
+            int cnt[256] = {0};   // rows longer than t, for every slab t
+            for (int q = 0; q < r1 - r0; ++q)
+                for (int t = 0; t < (int)((mt[q] >> 16) & 0xff); ++t) ++cnt[t];
+            int64_t off[257];
+            off[0] = g.blk[bk].base;
+            for (int t = 0; t < g.blk[bk].width; ++t) off[t + 1] = off[t] + cnt[t];
+            for (int q = 0; q < r1 - r0; ++q) {
+                const int i = r0 + (int)(mt[q] >> 24);
+                int tin = 0, tout = mt[q] & 0xff;
+                for (int p = A.rowptr[i]; p < A.rowptr[i + 1]; ++p) {
+                    const int j = A.col[p];
                     const bool in = j >= r0 && j < r1;
-                    const int64_t e = e0 + (int64_t)(in ? tin++ : tout++) * BGS_ROWS + lane;
+                    const int t = in ? tin++ : tout++;
+                    const int64_t e = off[t] + q;
                     g.code[e] = in ? j - r0 : j - cb;
-                    g.val[e] = A.val[q];
+                    g.val[e] = A.val[p];
                 }
             }
         }
@@ -237,29 +258,42 @@ template void bgs_resid_launch<double>(const DBgs&, bool, const double*, const d
 double bgs_bytes(const DBgs& g, bool zero, int vbytes, int cols) {
     const double cb = g.c16 ? 2 : 4;
     const double ent = (double)(zero ? g.nnz_in : g.nnz) * (vbytes + cb);
-    // per row: meta (2 bytes), the two scalings, and per column b, y (and x for a full
-    // sweep); per block its record
-    return ent + (double)g.n * (2 + 2 * vbytes + (zero ? 2 : 3) * (double)cols * vbytes) + 16.0 * g.nblk;
+    // per row: its 4-byte lane word, the two scalings, and per column b, y (and x for a
+    // full sweep); per block its record
+    return ent + (double)g.n * (4 + 2 * vbytes + (zero ? 2 : 3) * (double)cols * vbytes) + 16.0 * g.nblk;
 }
 
 double bgs_resid_bytes(const DBgs& g, int vbytes, int xbytes, int cols) {
     const double cb = g.c16 ? 2 : 4;
-    // entries; per row: meta, and per column x, b, y; per block its record
-    return (double)g.nnz * (vbytes + cb) + (double)g.n * (2 + 3 * (double)cols * xbytes) + 16.0 * g.nblk;
+    // entries; per row: its lane word, and per column x, b, y; per block its record
+    return (double)g.nnz * (vbytes + cb) + (double)g.n * (4 + 3 * (double)cols * xbytes) + 16.0 * g.nblk;
 }
 
 void host_bgs_sweep(const BgsHost& g, const double* b, double* x, std::vector<double>& tmp) {
     std::vector<double>& r = tmp;
     r.assign(g.n, 0.0);
+    // entry t of lane q: slab offsets of the block's jagged diagonals
+    auto offsets = [&](int bk, int64_t* off) {
+        const dev::BgsBlock& B = g.blk[bk];
+        int cnt[256] = {0};
+        for (int q = 0; q < BGS_ROWS; ++q)
+            for (int t = 0; t < (int)((g.meta[(size_t)bk * BGS_ROWS + q] >> 16) & 0xff); ++t) ++cnt[t];
+        off[0] = B.base;
+        for (int t = 0; t < B.width; ++t) off[t + 1] = off[t] + cnt[t];
+    };
+    int64_t off[257];
     // r = b - A x with the values at the start of the sweep, every row before any changes
     for (int bk = 0; bk < g.nblk; ++bk) {
         const dev::BgsBlock& B = g.blk[bk];
-        const int r0 = bk * BGS_ROWS, r1 = std::min(g.n, r0 + BGS_ROWS);
-        for (int i = r0; i < r1; ++i) {
-            const int lane = i - r0, nin = g.meta[i] & 0xff;
+        const int r0 = bk * BGS_ROWS;
+        offsets(bk, off);
+        for (int q = 0; q < BGS_ROWS; ++q) {
+            const uint32_t mt = g.meta[(size_t)bk * BGS_ROWS + q];
+            if ((mt >> 24) == 0xff) continue;
+            const int i = r0 + (int)(mt >> 24), nin = mt & 0xff, len = (mt >> 16) & 0xff;
             double acc = 0;
-            for (int t = 0; t < B.width; ++t) {
-                const int64_t e = B.base + (int64_t)t * BGS_ROWS + lane;
+            for (int t = 0; t < len; ++t) {
+                const int64_t e = off[t] + q;
                 const int j = t < nin ? r0 + g.code[e] : (g.c16 ? B.cbase + g.code[e] : g.code[e]);
                 acc += g.val[e] * x[j];
             }
@@ -269,26 +303,34 @@ void host_bgs_sweep(const BgsHost& g, const double* b, double* x, std::vector<do
     double u[BGS_ROWS], w[BGS_ROWS];
     for (int bk = 0; bk < g.nblk; ++bk) {
         const dev::BgsBlock& B = g.blk[bk];
-        const int r0 = bk * BGS_ROWS, r1 = std::min(g.n, r0 + BGS_ROWS);
+        const int r0 = bk * BGS_ROWS;
         const int ncol = B.info >> 8;
-        std::fill(u, u + BGS_ROWS, 0.0);
+        offsets(bk, off);
+        std::fill(u, u + BGS_ROWS, 0.0);   // by position in the block
         std::fill(w, w + BGS_ROWS, 0.0);
-        auto inside = [&](int i, const double* z) {
-            const int lane = i - r0, nin = g.meta[i] & 0xff;
+        auto inside = [&](int q, int nin, const double* z) {
             double s = 0;
             for (int t = 0; t < nin; ++t) {
-                const int64_t e = B.base + (int64_t)t * BGS_ROWS + lane;
+                const int64_t e = off[t] + q;
                 s += g.val[e] * z[g.code[e]];
             }
             return s;
         };
         for (int c = 0; c < ncol; ++c)
-            for (int i = r0; i < r1; ++i)
-                if ((g.meta[i] >> 8) == c) u[i - r0] = (r[i] - inside(i, u)) * g.dinv[i];
+            for (int q = 0; q < BGS_ROWS; ++q) {
+                const uint32_t mt = g.meta[(size_t)bk * BGS_ROWS + q];
+                if ((mt >> 24) == 0xff || (int)((mt >> 8) & 0xff) != c) continue;
+                const int p = mt >> 24, i = r0 + p;
+                u[p] = (r[i] - inside(q, mt & 0xff, u)) * g.dinv[i];
+            }
         for (int c = ncol - 1; c >= 0; --c)
-            for (int i = r0; i < r1; ++i)
-                if ((g.meta[i] >> 8) == c) w[i - r0] = (g.mid[i] * u[i - r0] - inside(i, w)) * g.dinv[i];
-        for (int i = r0; i < r1; ++i) x[i] += w[i - r0];
+            for (int q = 0; q < BGS_ROWS; ++q) {
+                const uint32_t mt = g.meta[(size_t)bk * BGS_ROWS + q];
+                if ((mt >> 24) == 0xff || (int)((mt >> 8) & 0xff) != c) continue;
+                const int p = mt >> 24, i = r0 + p;
+                w[p] = (g.mid[i] * u[p] - inside(q, mt & 0xff, w)) * g.dinv[i];
+            }
+        for (int p = 0; p < BGS_ROWS && r0 + p < g.n; ++p) x[r0 + p] += w[p];
     }
 }
 

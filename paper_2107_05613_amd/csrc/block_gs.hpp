@@ -16,8 +16,9 @@ struct BgsHost {
     bool c16 = false;
     int64_t nnz = 0, nnz_in = 0;
     std::vector<dev::BgsBlock> blk;
-    std::vector<uint16_t> meta;     // per row: inside entries | colour << 8 (colours over
-                                    // the couplings inside the row's block)
+    std::vector<uint32_t> meta;     // per lane (block-major): inside entries | colour << 8 |
+                                    // length << 16 | position of its row << 24 (0xff: none);
+                                    // colours over the couplings inside the row's block
     std::vector<int32_t> code;      // inside: position in the block; outside: column
                                     // (C16: offset from the block's base column)
     std::vector<double> val, dinv, mid;

@@ -44,7 +44,7 @@ void go_mm(const DBgs& g, int W, int NC, const T* X, const T* B, T* Y, const int
     const int L = W / V;
     const int64_t waves = (int64_t)g.nblk * L;
     launch<dev::BgsMM<T, V, C16, ZERO, NIN>>((unsigned)((waves + dev::WAVES - 1) / dev::WAVES), s, g.nblk, g.n, L,
-                                             NC, (const dev::BgsBlock*)g.blk, (const uint16_t*)g.meta,
+                                             NC, (const dev::BgsBlock*)g.blk, (const uint32_t*)g.meta,
                                              (const int*)g.ci, (const uint16_t*)g.c16, vals<T>(g), dinvs<T>(g),
                                              mids<T>(g), X, B, Y, stop);
 }
@@ -79,11 +79,11 @@ void go_resid_mm(const DBgs& g, const TV* av, int W, int NC, const T* X, const T
     const unsigned grid = (unsigned)((waves + dev::WAVES - 1) / dev::WAVES);
     if (g.c16)
         launch<dev::BgsResidMM<T, V, true, TV>>(grid, s, g.nblk, g.n, L, NC, (const dev::BgsBlock*)g.blk,
-                                                (const uint16_t*)g.meta, (const int*)g.ci, (const uint16_t*)g.c16, av,
+                                                (const uint32_t*)g.meta, (const int*)g.ci, (const uint16_t*)g.c16, av,
                                                 X, B, Y, stop);
     else
         launch<dev::BgsResidMM<T, V, false, TV>>(grid, s, g.nblk, g.n, L, NC, (const dev::BgsBlock*)g.blk,
-                                                 (const uint16_t*)g.meta, (const int*)g.ci, (const uint16_t*)g.c16,
+                                                 (const uint32_t*)g.meta, (const int*)g.ci, (const uint16_t*)g.c16,
                                                  av, X, B, Y, stop);
 }
 

@@ -90,17 +90,18 @@ template <> inline const double* GsColors::dg<double>() const { return dg64; }
 template <> inline const float* GsColors::dg<float>() const { return dg32; }
 
 // l1-scaled symmetric block Gauss-Seidel data of one matrix (kernels_bgs.hpp): blocks of
-// 64 consecutive rows, one wave per block, an ELL per block (entry t of the block's row q
-// at blk.base + t * 64 + q); a row's entries inside its block first (code: the column's
-// position in the block), then the others (code: column, or a 16-bit offset from
-// blk.cbase when every block's outside columns span < 65536).
+// 64 consecutive rows, one wave per block, the block's rows on the lanes sorted by
+// length and its entries as jagged diagonals (slab t: entry t of the rows longer than t,
+// contiguous); a row's entries inside its block first (code: the column's position in
+// the block), then the others (code: column, or a 16-bit offset from blk.cbase when
+// every block's outside columns span < 65536).
 struct DBgs {
     int n = 0, nblk = 0;
     int nin = 0;              // register bound of inside entries per row (8 ... 64)
     int64_t nnz = 0;          // entries of A
     int64_t nnz_in = 0;       // entries inside blocks (read by sweeps from zero)
     dev::BgsBlock* blk = nullptr;
-    uint16_t* meta = nullptr; // per row: inside entries | colour << 8
+    uint32_t* meta = nullptr; // per lane: inside entries | colour << 8 | length << 16 | position << 24
     int* ci = nullptr;
     uint16_t* c16 = nullptr;
     double* v64 = nullptr;

@@ -14,18 +14,24 @@
 // / later colours); this is the forward-then-backward row relaxation with the outside
 // couplings frozen.
 //
-// Layout per block: an ELL of width w (entry t of lane q at base + t * 64 + q), each
-// row's entries inside the block first (code: position in the block), then the others
-// (code: column, or a 16-bit offset from the block's base column); padding: value 0 and
-// code 0.  The first NIN entries of a row (NIN >= every block's inside width, so they hold
-// the inside entries) are loaded together, then gathered together; the rest follow in
-// uniform loops, and the colour passes read LDS without per-lane branches.  The inside
-// couplings stay in registers, u and w in LDS; the passes synchronise the wave only.  A
-// sweep from x0 = 0 reads the first wi entries of every row only (wi: the block's most
-// inside entries of a row).
+// Layout per block (jagged diagonals): the lanes hold the block's rows sorted by length,
+// longest first, and slab t holds entry t of the rows longer than t, contiguously, so
+// the block stores exactly its entries (no padding): entry t of lane q sits at
+// base + (entries of slabs 0..t-1) + q, the slab sizes taken from a ballot of the
+// lanes' lengths.  A row's entries inside the block come first (code: the column's
+// position in the block), then the others (code: column, or a 16-bit offset from the
+// block's base column).  Per lane a 32-bit word: inside entries | colour << 8 |
+// length << 16 | position of its row in the block << 24 (0xff: no row); u and w live in
+// LDS by position in the block.  Loads are issued for every lane and slab
+// (clamped addresses, results masked), so a row's loads are in flight together: the
+// first NIN slabs (NIN >= every block's inside width, so they hold the inside entries)
+// are loaded together, then gathered together; the rest follow in a uniform loop; the
+// colour passes read LDS without per-lane branches.  The inside couplings stay in
+// registers, u and w in LDS; the passes synchronise the wave only.  A sweep from x0 = 0
+// reads the block's first wi slabs only (wi: its most inside entries of a row).
 //
-// Bytes: a full sweep reads every stored entry once (value + 2- or 4-byte code) plus b,
-// x, the row data and writes y, like an l1-Jacobi sweep.
+// Bytes: a full sweep reads every entry once (value + 2- or 4-byte code) plus b, x, the
+// row data and writes y, like an l1-Jacobi sweep.
 #pragma once
 
 #include <type_traits>
@@ -45,7 +51,8 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Column of entry t of a row with nin inside entries.
+// Column of entry t of a row with nin inside entries (code: the column's position in the
+// block, else the column or its offset from the block's base column).
 template <bool C16>
 __device__ __forceinline__ int bgs_col(int t, int nin, int code, int row0, int cb) {
     return t < nin ? row0 + code : (C16 ? cb + code : code);
@@ -56,10 +63,41 @@ __device__ __forceinline__ int bgs_code(const int* __restrict__ ci, const uint16
     return C16 ? (int)c16[e] : ci[e];
 }
 
+// Lanes whose rows are longer than t: a prefix of the wave (rows sorted by length).
+__device__ __forceinline__ int bgs_slab(int len, int t) {
+    return __popcll(__ballot(len > t));
+}
+
+// Entries t0 .. t0 + CH - 1 of this lane's row (or a masked stand-in past its length):
+// offsets from the slab counts first, then the CH loads together.
+template <int CH, typename TV, bool C16>
+__device__ __forceinline__ void bgs_chunk(int& e, int len, int t0, const TV* __restrict__ av,
+                                          const int* __restrict__ ci, const uint16_t* __restrict__ c16,
+                                          TV (&v)[CH], int (&code)[CH]) {
+    int ee[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        ee[k] = e;
+        e += bgs_slab(len, t0 + k);
+    }
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        v[k] = av[ee[k]];
+        code[k] = bgs_code<C16>(ci, c16, ee[k]);
+    }
+}
+
+// Slabs per chunk of the streaming loops: 16 for kernels with few inside entries (long
+// rows of coarse levels), 8 otherwise.
+template <int NIN>
+constexpr int bgs_ch() {
+    return NIN <= 8 ? 16 : 8;
+}
+
 // y = x + w (ZERO: x = 0, y = w) for every block; NIN >= every block's inside width.
 template <typename T, bool C16, bool ZERO, int NIN>
 __global__ void __launch_bounds__(BLOCK)
-k_bgs(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint16_t* __restrict__ meta,
+k_bgs(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint32_t* __restrict__ meta,
       const int* __restrict__ ci, const uint16_t* __restrict__ c16, const T* __restrict__ av,
       const T* __restrict__ dinv, const T* __restrict__ mid, const T* __restrict__ x,
       const T* __restrict__ b, T* __restrict__ y, const int* __restrict__ stop) {
@@ -71,61 +109,60 @@ k_bgs(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint16_t* __re
     const BgsBlock B = blocks[bl];
     if (stopped | (blk >= nblk)) return;   // whole waves only
     const int row0 = bl * 64;
-    const int i = row0 + lane;
-    const bool live = i < n;
-    const int ir = live ? i : row0;
-    const int mt = meta[ir];
-    const int nin = live ? (mt & 0xff) : 0;
-    const int colour = live ? (mt >> 8) : -1;
+    const uint32_t mt = meta[row0 + lane];
+    const int pos = mt >> 24;                 // this lane's row in the block (0xff: none)
+    const bool live = pos != 0xff;
+    const int nin = mt & 0xff, colour = live ? (int)((mt >> 8) & 0xff) : -1;
+    const int len = (mt >> 16) & 0xff;
+    const int ir = row0 + (live ? pos : 0);
     const T br = b[ir], di = dinv[ir], mi = mid[ir];
     const T xr = ZERO ? T(0) : x[ir];
     su[wv][lane] = T(0);
     sw[wv][lane] = T(0);
-    const int ncol = B.info >> 8;
-    const int e0 = B.base + lane;
-    const int cb = B.cbase;
-    // the first NIN entries of every row (they hold every inside entry): all loads first,
-    // then all gathers, so a row's loads are in flight together; the arrays are padded
-    // past their end, and entries at t >= width are masked
-    const int W = B.width;
+    const int W = B.width, cb = B.cbase;
+    const int wi = B.info & 0xff, ncol = B.info >> 8;
+    int e = B.base + lane;    // entry t of this lane: slab base + lane
     T a[NIN];
     int id[NIN];
 #pragma unroll
     for (int t = 0; t < NIN; ++t) {
         a[t] = T(0);
-        id[t] = lane;
-        // a sweep from zero needs the block's inside width only (a uniform bound: its
-        // loads are still issued together, no gathers wait on them)
-        if (!ZERO || t < (B.info & 0xff)) {
-            a[t] = av[e0 + t * 64];
-            id[t] = bgs_code<C16>(ci, c16, e0 + t * 64);
+        id[t] = 0;
+        if (!ZERO || t < wi) {   // a sweep from zero reads the inside slabs only
+            a[t] = av[e];
+            id[t] = bgs_code<C16>(ci, c16, e);
+            e += bgs_slab(len, t);
         }
     }
     T acc = 0;
     if (!ZERO) {
 #pragma unroll
         for (int t = 0; t < NIN; ++t) {
-            const int j = t < W ? bgs_col<C16>(t, nin, id[t], row0, cb) : row0;
-            acc = fma(t < W ? a[t] : T(0), x[j], acc);
+            const bool on = t < len;
+            const int j = on ? bgs_col<C16>(t, nin, id[t], row0, cb) : row0;
+            acc = fma(on ? a[t] : T(0), x[j], acc);
+        }
+        constexpr int CH = bgs_ch<NIN>();
+        for (int t0 = NIN; t0 < W; t0 += CH) {   // outside entries, CH slabs at a time
+            T v[CH];
+            int code[CH];
+            bgs_chunk<CH, T, C16>(e, len, t0, av, ci, c16, v, code);
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const bool on = t0 + k < len;
+                acc = fma(on ? v[k] : T(0), x[on ? (C16 ? cb + code[k] : code[k]) : row0], acc);
+            }
         }
     }
 #pragma unroll
     for (int t = 0; t < NIN; ++t) {   // keep the inside couplings: value 0 / own position elsewhere
         const bool in = t < nin;
         a[t] = in ? a[t] : T(0);
-        id[t] = in ? id[t] : lane;
-    }
-    if (!ZERO) {
-#pragma unroll 8
-        for (int t = NIN; t < W; ++t) {   // outside entries (or padding) in every row
-            const int e = e0 + t * 64;
-            const int code = bgs_code<C16>(ci, c16, e);
-            acc = fma(av[e], x[C16 ? cb + code : code], acc);
-        }
+        id[t] = in ? id[t] : (live ? pos : 0);
     }
     const T r0 = br - acc;
     wave_sync();
-    // forward: (D_l1 + L) u = r0, colours in increasing order
+    // forward: (D_l1 + L) u = r0, colours in increasing order (u by position in the block)
     T uq = 0;
     for (int c = 0; c < ncol; ++c) {
         if (colour == c) {
@@ -133,7 +170,7 @@ k_bgs(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint16_t* __re
 #pragma unroll
             for (int t = 0; t < NIN; ++t) s = fma(a[t], su[wv][id[t]], s);
             uq = (r0 - s) * di;
-            su[wv][lane] = uq;
+            su[wv][pos] = uq;
         }
         wave_sync();
     }
@@ -146,11 +183,11 @@ k_bgs(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint16_t* __re
 #pragma unroll
             for (int t = 0; t < NIN; ++t) s = fma(a[t], sw[wv][id[t]], s);
             wq = (v - s) * di;
-            sw[wv][lane] = wq;
+            sw[wv][pos] = wq;
         }
         wave_sync();
     }
-    if (live) y[i] = ZERO ? wq : xr + wq;
+    if (live) y[ir] = ZERO ? wq : xr + wq;
 }
 
 // y = b - A x on the same layout (the residual ahead of the restriction, so that the
@@ -158,7 +195,7 @@ k_bgs(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint16_t* __re
 // FP64 and round once.
 template <typename T, bool C16, typename TV>
 __global__ void __launch_bounds__(BLOCK)
-k_bgs_resid(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint16_t* __restrict__ meta,
+k_bgs_resid(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint32_t* __restrict__ meta,
             const int* __restrict__ ci, const uint16_t* __restrict__ c16, const TV* __restrict__ av,
             const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, const int* __restrict__ stop) {
     using TA = typename std::conditional<(sizeof(TV) > sizeof(T)), TV, T>::type;
@@ -169,21 +206,26 @@ k_bgs_resid(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint16_t
     const BgsBlock B = blocks[bl];
     if (stopped | (blk >= nblk)) return;
     const int row0 = bl * 64;
-    const int i = row0 + lane;
-    const bool live = i < n;
-    const int ir = live ? i : row0;
-    const int nin = live ? (meta[ir] & 0xff) : 0;
+    const uint32_t mt = meta[row0 + lane];
+    const int pos = mt >> 24;
+    const bool live = pos != 0xff;
+    const int nin = mt & 0xff, len = (mt >> 16) & 0xff;
+    const int ir = row0 + (live ? pos : 0);
     const T br = b[ir];
-    const int e0 = B.base + lane;
     const int cb = B.cbase;
+    int e = B.base + lane;
     TA acc = 0;
-#pragma unroll 8
-    for (int t = 0; t < B.width; ++t) {
-        const int e = e0 + t * 64;
-        const int code = bgs_code<C16>(ci, c16, e);
-        acc = fma((TA)av[e], (TA)x[bgs_col<C16>(t, nin, code, row0, cb)], acc);
+    for (int t0 = 0; t0 < B.width; t0 += 8) {   // eight slabs at a time
+        TV v[8];
+        int code[8];
+        bgs_chunk<8, TV, C16>(e, len, t0, av, ci, c16, v, code);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const bool on = t0 + k < len;
+            acc = fma(on ? (TA)v[k] : TA(0), (TA)x[on ? bgs_col<C16>(t0 + k, nin, code[k], row0, cb) : row0], acc);
+        }
     }
-    if (live) y[i] = (T)((TA)br - acc);
+    if (live) y[ir] = (T)((TA)br - acc);
 }
 
 // ---------------------------------------------------------------------------------
@@ -241,7 +283,7 @@ __device__ __forceinline__ void store_row(const Row<T, V>& r, T* p) {
 
 template <typename T, int V, bool C16, bool ZERO, int NIN, class G>
 __device__ __forceinline__ void
-bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks, const uint16_t* __restrict__ meta,
+bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks, const uint32_t* __restrict__ meta,
        const int* __restrict__ ci, const uint16_t* __restrict__ c16, const T* __restrict__ av,
        const T* __restrict__ dinv, const T* __restrict__ mid, const T* __restrict__ X, const T* __restrict__ Bv,
        T* __restrict__ Y, const int* __restrict__ stop) {
@@ -256,12 +298,12 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
     const BgsBlock B = blocks[bl];
     if (stopped | (blk >= nblk)) return;   // whole waves only
     const int row0 = bl * 64;
-    const int i = row0 + lane;
-    const bool live = i < n;
-    const int ir = live ? i : row0;
-    const int mt = meta[ir];
-    const int nin = live ? (mt & 0xff) : 0;
-    const int colour = live ? (mt >> 8) : -1;
+    const uint32_t mt = meta[row0 + lane];
+    const int pos = mt >> 24;
+    const bool live = pos != 0xff;
+    const int nin = mt & 0xff, colour = live ? (int)((mt >> 8) & 0xff) : -1;
+    const int len = (mt >> 16) & 0xff;
+    const int ir = row0 + (live ? pos : 0);
     const T di = dinv[ir], mi = mid[ir];
     R br, xr;
     bgsmm::load_row(br, Bv + (int64_t)ir * NC + col);
@@ -274,16 +316,18 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
         sw[wv][lane].v[c] = T(0);
     }
     const int W = B.width, cb = B.cbase;
-    const int e0 = B.base + lane;
+    const int wi = B.info & 0xff;
+    int e = B.base + lane;
     T a[NIN];
     int id[NIN];
 #pragma unroll
     for (int t = 0; t < NIN; ++t) {
         a[t] = T(0);
-        id[t] = lane;
-        if (!ZERO || t < (B.info & 0xff)) {
-            a[t] = av[e0 + t * 64];
-            id[t] = bgs_code<C16>(ci, c16, e0 + t * 64);
+        id[t] = 0;
+        if (!ZERO || t < wi) {
+            a[t] = av[e];
+            id[t] = bgs_code<C16>(ci, c16, e);
+            e += bgs_slab(len, t);
         }
     }
     R acc;
@@ -292,29 +336,34 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
     if (!ZERO) {
 #pragma unroll
         for (int t = 0; t < NIN; ++t) {
-            const int j = t < W ? bgs_col<C16>(t, nin, id[t], row0, cb) : row0;
-            const T v = t < W ? a[t] : T(0);
+            const bool on = t < len;
+            const int j = on ? bgs_col<C16>(t, nin, id[t], row0, cb) : row0;
+            const T v = on ? a[t] : T(0);
             R xj;
             bgsmm::load_row(xj, X + (int64_t)j * NC + col);
 #pragma unroll
             for (int c = 0; c < V; ++c) acc.v[c] = fma(v, xj.v[c], acc.v[c]);
         }
-#pragma unroll 4
-        for (int t = NIN; t < W; ++t) {   // outside entries (or padding) in every row
-            const int e = e0 + t * 64;
-            const int code = bgs_code<C16>(ci, c16, e);
-            const T v = av[e];
-            R xj;
-            bgsmm::load_row(xj, X + (int64_t)(C16 ? cb + code : code) * NC + col);
+        constexpr int CH = bgs_ch<NIN>();
+        for (int t0 = NIN; t0 < W; t0 += CH) {   // outside entries, CH slabs at a time
+            T v[CH];
+            int code[CH];
+            bgs_chunk<CH, T, C16>(e, len, t0, av, ci, c16, v, code);
 #pragma unroll
-            for (int c = 0; c < V; ++c) acc.v[c] = fma(v, xj.v[c], acc.v[c]);
+            for (int k = 0; k < CH; ++k) {
+                const bool on = t0 + k < len;
+                R xj;
+                bgsmm::load_row(xj, X + (int64_t)(on ? (C16 ? cb + code[k] : code[k]) : row0) * NC + col);
+#pragma unroll
+                for (int c = 0; c < V; ++c) acc.v[c] = fma(on ? v[k] : T(0), xj.v[c], acc.v[c]);
+            }
         }
     }
 #pragma unroll
     for (int t = 0; t < NIN; ++t) {   // keep the inside couplings: value 0 / own position elsewhere
         const bool in = t < nin;
         a[t] = in ? a[t] : T(0);
-        id[t] = in ? id[t] : lane;
+        id[t] = in ? id[t] : (live ? pos : 0);
     }
     R r0;
 #pragma unroll
@@ -336,7 +385,7 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
             }
 #pragma unroll
             for (int c = 0; c < V; ++c) uq.v[c] = (r0.v[c] - s.v[c]) * di;
-            su[wv][lane] = uq;
+            su[wv][pos] = uq;
         }
         wave_sync();
     }
@@ -353,7 +402,7 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
             }
 #pragma unroll
             for (int c = 0; c < V; ++c) wq.v[c] = (mi * uq.v[c] - s.v[c]) * di;
-            sw[wv][lane] = wq;
+            sw[wv][pos] = wq;
         }
         wave_sync();
     }
@@ -361,7 +410,7 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
     R out;
 #pragma unroll
     for (int c = 0; c < V; ++c) out.v[c] = ZERO ? wq.v[c] : xr.v[c] + wq.v[c];
-    bgsmm::store_row(out, Y + (int64_t)i * NC + col);
+    bgsmm::store_row(out, Y + (int64_t)ir * NC + col);
 }
 
 template <typename T, int V, bool C16, bool ZERO, int NIN>
@@ -377,7 +426,7 @@ struct BgsMM {
 template <typename T, int V, bool C16, typename TV, class G>
 __device__ __forceinline__ void
 bgs_resid_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
-             const uint16_t* __restrict__ meta, const int* __restrict__ ci, const uint16_t* __restrict__ c16,
+             const uint32_t* __restrict__ meta, const int* __restrict__ ci, const uint16_t* __restrict__ c16,
              const TV* __restrict__ av, const T* __restrict__ X, const T* __restrict__ Bv, T* __restrict__ Y,
              const int* __restrict__ stop) {
     using TA = typename std::conditional<(sizeof(TV) > sizeof(T)), TV, T>::type;
@@ -390,31 +439,35 @@ bgs_resid_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ b
     const BgsBlock B = blocks[bl];
     if (stopped | (blk >= nblk)) return;
     const int row0 = bl * 64;
-    const int i = row0 + lane;
-    const bool live = i < n;
-    const int ir = live ? i : row0;
-    const int nin = live ? (meta[ir] & 0xff) : 0;
-    const int e0 = B.base + lane;
+    const uint32_t mt = meta[row0 + lane];
+    const int pos = mt >> 24;
+    const bool live = pos != 0xff;
+    const int nin = mt & 0xff, len = (mt >> 16) & 0xff;
+    const int ir = row0 + (live ? pos : 0);
     const int cb = B.cbase;
+    int e = B.base + lane;
     TA acc[V];
 #pragma unroll
     for (int c = 0; c < V; ++c) acc[c] = 0;
-#pragma unroll 4
-    for (int t = 0; t < B.width; ++t) {
-        const int e = e0 + t * 64;
-        const int code = bgs_code<C16>(ci, c16, e);
-        const TA v = av[e];
-        bgsmm::Row<T, V> xj;
-        bgsmm::load_row(xj, X + (int64_t)bgs_col<C16>(t, nin, code, row0, cb) * NC + col);
+    for (int t0 = 0; t0 < B.width; t0 += 8) {   // eight slabs at a time
+        TV v[8];
+        int code[8];
+        bgs_chunk<8, TV, C16>(e, len, t0, av, ci, c16, v, code);
 #pragma unroll
-        for (int c = 0; c < V; ++c) acc[c] = fma(v, (TA)xj.v[c], acc[c]);
+        for (int k = 0; k < 8; ++k) {
+            const bool on = t0 + k < len;
+            bgsmm::Row<T, V> xj;
+            bgsmm::load_row(xj, X + (int64_t)(on ? bgs_col<C16>(t0 + k, nin, code[k], row0, cb) : row0) * NC + col);
+#pragma unroll
+            for (int c = 0; c < V; ++c) acc[c] = fma(on ? (TA)v[k] : TA(0), (TA)xj.v[c], acc[c]);
+        }
     }
     if (!live) return;
     bgsmm::Row<T, V> br, out;
-    bgsmm::load_row(br, Bv + (int64_t)i * NC + col);
+    bgsmm::load_row(br, Bv + (int64_t)ir * NC + col);
 #pragma unroll
     for (int c = 0; c < V; ++c) out.v[c] = (T)((TA)br.v[c] - acc[c]);
-    bgsmm::store_row(out, Y + (int64_t)i * NC + col);
+    bgsmm::store_row(out, Y + (int64_t)ir * NC + col);
 }
 
 template <typename T, int V, bool C16, typename TV>
