@@ -92,7 +92,7 @@ BgsHost bgs_layout(const Csr& A) {
             }
             wi[bk] = mi;
             g.blk[bk].width = nr ? len[lane_row[0]] : 0;
-            g.blk[bk].info = mi | ncol << 8;
+            g.blk[bk].info = mi | ncol << 8 | (nr ? len[lane_row[nr - 1]] : 0) << 16 | nr << 24;
             cmin[bk] = hi >= 0 ? lo : 0;
             cmax[bk] = hi >= 0 ? hi : 0;
         }
@@ -304,7 +304,7 @@ void host_bgs_sweep(const BgsHost& g, const double* b, double* x, std::vector<do
     for (int bk = 0; bk < g.nblk; ++bk) {
         const dev::BgsBlock& B = g.blk[bk];
         const int r0 = bk * BGS_ROWS;
-        const int ncol = B.info >> 8;
+        const int ncol = (B.info >> 8) & 0xff;
         offsets(bk, off);
         std::fill(u, u + BGS_ROWS, 0.0);   // by position in the block
         std::fill(w, w + BGS_ROWS, 0.0);

@@ -17,8 +17,9 @@
 // Layout per block (jagged diagonals): the lanes hold the block's rows sorted by length,
 // longest first, and slab t holds entry t of the rows longer than t, contiguously, so
 // the block stores exactly its entries (no padding): entry t of lane q sits at
-// base + (entries of slabs 0..t-1) + q, the slab sizes taken from a ballot of the
-// lanes' lengths.  A row's entries inside the block come first (code: the column's
+// base + (entries of slabs 0..t-1) + q.  Slabs below the block's shortest row hold every
+// row (sizes from the block record, so these loads need no per-lane word); past it the
+// slab sizes come from a ballot of the lanes' lengths.  A row's entries inside the block come first (code: the column's
 // position in the block), then the others (code: column, or a 16-bit offset from the
 // block's base column).  Per lane a 32-bit word: inside entries | colour << 8 |
 // length << 16 | position of its row in the block << 24 (0xff: no row); u and w live in
@@ -68,18 +69,39 @@ __device__ __forceinline__ int bgs_slab(int len, int t) {
     return __popcll(__ballot(len > t));
 }
 
+// Shape of a block from its record: shortest row length and rows (the slabs below the
+// shortest length are full).
+struct BgsShape {
+    int minlen, nlive;
+    __device__ explicit BgsShape(int info) : minlen((info >> 16) & 0xff), nlive(info >> 24) {}
+};
+
+// Offsets of slabs t0 .. t0 + CH - 1 for this lane, e advanced past them.  Full slabs
+// (the uniform branch) take their sizes from the block record, so their loads do not
+// wait for the lane's length.
+template <int CH>
+__device__ __forceinline__ void bgs_offsets(int& e, int len, int t0, BgsShape sh, int (&ee)[CH]) {
+    if (t0 + CH <= sh.minlen) {
+#pragma unroll
+        for (int k = 0; k < CH; ++k) ee[k] = e + k * sh.nlive;
+        e += CH * sh.nlive;
+    } else {
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            ee[k] = e;
+            e += bgs_slab(len, t0 + k);
+        }
+    }
+}
+
 // Entries t0 .. t0 + CH - 1 of this lane's row (or a masked stand-in past its length):
-// offsets from the slab counts first, then the CH loads together.
+// offsets first, then the CH loads together.
 template <int CH, typename TV, bool C16>
-__device__ __forceinline__ void bgs_chunk(int& e, int len, int t0, const TV* __restrict__ av,
+__device__ __forceinline__ void bgs_chunk(int& e, int len, int t0, BgsShape sh, const TV* __restrict__ av,
                                           const int* __restrict__ ci, const uint16_t* __restrict__ c16,
                                           TV (&v)[CH], int (&code)[CH]) {
     int ee[CH];
-#pragma unroll
-    for (int k = 0; k < CH; ++k) {
-        ee[k] = e;
-        e += bgs_slab(len, t0 + k);
-    }
+    bgs_offsets<CH>(e, len, t0, sh, ee);
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
         v[k] = av[ee[k]];
@@ -120,18 +142,22 @@ k_bgs(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint32_t* __re
     su[wv][lane] = T(0);
     sw[wv][lane] = T(0);
     const int W = B.width, cb = B.cbase;
-    const int wi = B.info & 0xff, ncol = B.info >> 8;
+    const int wi = B.info & 0xff, ncol = (B.info >> 8) & 0xff;
+    const BgsShape sh(B.info);
     int e = B.base + lane;    // entry t of this lane: slab base + lane
     T a[NIN];
     int id[NIN];
+    {
+        int ee[NIN];
+        bgs_offsets<NIN>(e, len, 0, sh, ee);
 #pragma unroll
-    for (int t = 0; t < NIN; ++t) {
-        a[t] = T(0);
-        id[t] = 0;
-        if (!ZERO || t < wi) {   // a sweep from zero reads the inside slabs only
-            a[t] = av[e];
-            id[t] = bgs_code<C16>(ci, c16, e);
-            e += bgs_slab(len, t);
+        for (int t = 0; t < NIN; ++t) {
+            a[t] = T(0);
+            id[t] = 0;
+            if (!ZERO || t < wi) {   // a sweep from zero reads the inside slabs only
+                a[t] = av[ee[t]];
+                id[t] = bgs_code<C16>(ci, c16, ee[t]);
+            }
         }
     }
     T acc = 0;
@@ -146,7 +172,7 @@ k_bgs(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint32_t* __re
         for (int t0 = NIN; t0 < W; t0 += CH) {   // outside entries, CH slabs at a time
             T v[CH];
             int code[CH];
-            bgs_chunk<CH, T, C16>(e, len, t0, av, ci, c16, v, code);
+            bgs_chunk<CH, T, C16>(e, len, t0, sh, av, ci, c16, v, code);
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
                 const bool on = t0 + k < len;
@@ -213,12 +239,13 @@ k_bgs_resid(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint32_t
     const int ir = row0 + (live ? pos : 0);
     const T br = b[ir];
     const int cb = B.cbase;
+    const BgsShape sh(B.info);
     int e = B.base + lane;
     TA acc = 0;
     for (int t0 = 0; t0 < B.width; t0 += 8) {   // eight slabs at a time
         TV v[8];
         int code[8];
-        bgs_chunk<8, TV, C16>(e, len, t0, av, ci, c16, v, code);
+        bgs_chunk<8, TV, C16>(e, len, t0, sh, av, ci, c16, v, code);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const bool on = t0 + k < len;
@@ -316,18 +343,22 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
         sw[wv][lane].v[c] = T(0);
     }
     const int W = B.width, cb = B.cbase;
-    const int wi = B.info & 0xff;
+    const int wi = B.info & 0xff, ncol = (B.info >> 8) & 0xff;
+    const BgsShape sh(B.info);
     int e = B.base + lane;
     T a[NIN];
     int id[NIN];
+    {
+        int ee[NIN];
+        bgs_offsets<NIN>(e, len, 0, sh, ee);
 #pragma unroll
-    for (int t = 0; t < NIN; ++t) {
-        a[t] = T(0);
-        id[t] = 0;
-        if (!ZERO || t < wi) {
-            a[t] = av[e];
-            id[t] = bgs_code<C16>(ci, c16, e);
-            e += bgs_slab(len, t);
+        for (int t = 0; t < NIN; ++t) {
+            a[t] = T(0);
+            id[t] = 0;
+            if (!ZERO || t < wi) {
+                a[t] = av[ee[t]];
+                id[t] = bgs_code<C16>(ci, c16, ee[t]);
+            }
         }
     }
     R acc;
@@ -348,7 +379,7 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
         for (int t0 = NIN; t0 < W; t0 += CH) {   // outside entries, CH slabs at a time
             T v[CH];
             int code[CH];
-            bgs_chunk<CH, T, C16>(e, len, t0, av, ci, c16, v, code);
+            bgs_chunk<CH, T, C16>(e, len, t0, sh, av, ci, c16, v, code);
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
                 const bool on = t0 + k < len;
@@ -372,7 +403,7 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
     R uq, wq;
 #pragma unroll
     for (int c = 0; c < V; ++c) uq.v[c] = wq.v[c] = T(0);
-    for (int k = 0; k < (B.info >> 8); ++k) {
+    for (int k = 0; k < ncol; ++k) {
         if (colour == k) {
             R s;
 #pragma unroll
@@ -389,7 +420,7 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
         }
         wave_sync();
     }
-    for (int k = (B.info >> 8) - 1; k >= 0; --k) {
+    for (int k = ncol - 1; k >= 0; --k) {
         if (colour == k) {
             R s;
 #pragma unroll
@@ -445,6 +476,7 @@ bgs_resid_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ b
     const int nin = mt & 0xff, len = (mt >> 16) & 0xff;
     const int ir = row0 + (live ? pos : 0);
     const int cb = B.cbase;
+    const BgsShape sh(B.info);
     int e = B.base + lane;
     TA acc[V];
 #pragma unroll
@@ -452,7 +484,7 @@ bgs_resid_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ b
     for (int t0 = 0; t0 < B.width; t0 += 8) {   // eight slabs at a time
         TV v[8];
         int code[8];
-        bgs_chunk<8, TV, C16>(e, len, t0, av, ci, c16, v, code);
+        bgs_chunk<8, TV, C16>(e, len, t0, sh, av, ci, c16, v, code);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const bool on = t0 + k < len;

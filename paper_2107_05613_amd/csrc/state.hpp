@@ -44,8 +44,9 @@ struct BatchStatus {
 };
 
 // One 64-row block of the l1-scaled symmetric block Gauss-Seidel layout: entry base,
-// width (entries per row, padded), inside width (most inside entries of a row) |
-// colours << 8, base column of the outside 16-bit offsets.
+// width (entries of its longest row), info = inside width (most inside entries of a
+// row) | colours << 8 | shortest row length << 16 | rows << 24, base column of the
+// outside 16-bit offsets.
 struct alignas(16) BgsBlock {
     int base, width, info, cbase;
 };
