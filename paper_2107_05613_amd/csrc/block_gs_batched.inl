@@ -31,67 +31,72 @@ template <> const float* mids<float>(const DBgs& g) { return g.mid32; }
 
 namespace {
 
-// Columns per wave of the batched sweeps: 32-byte rows of the vector blocks (fewer waves
+// Columns per lane of the batched sweeps: 32-byte rows of the vector blocks (fewer waves
 // per block re-read its entries), or one column per wave when fewer columns are active.
+// From four such groups on, the four waves of a workgroup share a block (P = 4): a row's
+// four groups sit in four neighbouring lanes, so each vector access of a wave touches 16
+// cache lines instead of 64.
 template <class T>
 int bgs_cols(int W) {
     const int v = 32 / (int)sizeof(T);
     return W >= v ? v : 1;
 }
 
-template <class T, int V, bool C16, bool ZERO, int NIN>
+template <class T, int V, int P, bool C16, bool ZERO, int NIN>
 void go_mm(const DBgs& g, int W, int NC, const T* X, const T* B, T* Y, const int* stop, hipStream_t s) {
-    const int L = W / V;
-    const int64_t waves = (int64_t)g.nblk * L;
-    launch<dev::BgsMM<T, V, C16, ZERO, NIN>>((unsigned)((waves + dev::WAVES - 1) / dev::WAVES), s, g.nblk, g.n, L,
-                                             NC, (const dev::BgsBlock*)g.blk, (const uint32_t*)g.meta,
-                                             (const int*)g.ci, (const uint16_t*)g.c16, vals<T>(g), dinvs<T>(g),
-                                             mids<T>(g), X, B, Y, stop);
+    const int L = W / (P * V);   // groups of P x V columns
+    const int64_t waves = (int64_t)g.nblk * L * P;
+    launch<dev::BgsMM<T, V, P, C16, ZERO, NIN>>((unsigned)((waves + dev::WAVES - 1) / dev::WAVES), s, g.nblk, g.n,
+                                                L, NC, (const dev::BgsBlock*)g.blk, (const uint32_t*)g.meta,
+                                                (const int*)g.ci, (const uint16_t*)g.c16, vals<T>(g), dinvs<T>(g),
+                                                mids<T>(g), X, B, Y, stop);
 }
 
-template <class T, int V, bool C16, bool ZERO>
+template <class T, int V, int P, bool C16, bool ZERO>
 void go_mm_nin(const DBgs& g, int W, int NC, const T* X, const T* B, T* Y, const int* stop, hipStream_t s) {
     // register bounds of the batched bodies: 8, 16, 32 or 64 (fewer instances)
-    if (g.nin <= 8) go_mm<T, V, C16, ZERO, 8>(g, W, NC, X, B, Y, stop, s);
-    else if (g.nin <= 16) go_mm<T, V, C16, ZERO, 16>(g, W, NC, X, B, Y, stop, s);
-    else if (g.nin <= 32) go_mm<T, V, C16, ZERO, 32>(g, W, NC, X, B, Y, stop, s);
-    else go_mm<T, V, C16, ZERO, 64>(g, W, NC, X, B, Y, stop, s);
+    if (g.nin <= 8) go_mm<T, V, P, C16, ZERO, 8>(g, W, NC, X, B, Y, stop, s);
+    else if (g.nin <= 16) go_mm<T, V, P, C16, ZERO, 16>(g, W, NC, X, B, Y, stop, s);
+    else if (g.nin <= 32) go_mm<T, V, P, C16, ZERO, 32>(g, W, NC, X, B, Y, stop, s);
+    else go_mm<T, V, P, C16, ZERO, 64>(g, W, NC, X, B, Y, stop, s);
 }
 
-template <class T, int V>
+template <class T, int V, int P>
 void go_mm_v(const DBgs& g, bool zero, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
              hipStream_t s) {
     const bool c16 = g.c16 != nullptr;
     if (zero) {
-        if (c16) go_mm_nin<T, V, true, true>(g, W, NC, X, B, Y, stop, s);
-        else go_mm_nin<T, V, false, true>(g, W, NC, X, B, Y, stop, s);
+        if (c16) go_mm_nin<T, V, P, true, true>(g, W, NC, X, B, Y, stop, s);
+        else go_mm_nin<T, V, P, false, true>(g, W, NC, X, B, Y, stop, s);
     } else {
-        if (c16) go_mm_nin<T, V, true, false>(g, W, NC, X, B, Y, stop, s);
-        else go_mm_nin<T, V, false, false>(g, W, NC, X, B, Y, stop, s);
+        if (c16) go_mm_nin<T, V, P, true, false>(g, W, NC, X, B, Y, stop, s);
+        else go_mm_nin<T, V, P, false, false>(g, W, NC, X, B, Y, stop, s);
     }
 }
 
-template <class T, int V, class TV>
+template <class T, int V, int P, class TV>
 void go_resid_mm(const DBgs& g, const TV* av, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
                  hipStream_t s) {
-    const int L = W / V;
-    const int64_t waves = (int64_t)g.nblk * L;
+    const int L = W / (P * V);   // groups of P x V columns
+    const int64_t waves = (int64_t)g.nblk * L * P;
     const unsigned grid = (unsigned)((waves + dev::WAVES - 1) / dev::WAVES);
     if (g.c16)
-        launch<dev::BgsResidMM<T, V, true, TV>>(grid, s, g.nblk, g.n, L, NC, (const dev::BgsBlock*)g.blk,
-                                                (const uint32_t*)g.meta, (const int*)g.ci, (const uint16_t*)g.c16, av,
-                                                X, B, Y, stop);
+        launch<dev::BgsResidMM<T, V, P, true, TV>>(grid, s, g.nblk, g.n, L, NC, (const dev::BgsBlock*)g.blk,
+                                                   (const uint32_t*)g.meta, (const int*)g.ci, (const uint16_t*)g.c16,
+                                                   av, X, B, Y, stop);
     else
-        launch<dev::BgsResidMM<T, V, false, TV>>(grid, s, g.nblk, g.n, L, NC, (const dev::BgsBlock*)g.blk,
-                                                 (const uint32_t*)g.meta, (const int*)g.ci, (const uint16_t*)g.c16,
-                                                 av, X, B, Y, stop);
+        launch<dev::BgsResidMM<T, V, P, false, TV>>(grid, s, g.nblk, g.n, L, NC, (const dev::BgsBlock*)g.blk,
+                                                    (const uint32_t*)g.meta, (const int*)g.ci, (const uint16_t*)g.c16,
+                                                    av, X, B, Y, stop);
 }
 
 template <class T, class TV>
 void go_resid_mm_v(const DBgs& g, const TV* av, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
                    hipStream_t s) {
-    if (bgs_cols<T>(W) == 1) go_resid_mm<T, 1, TV>(g, av, W, NC, X, B, Y, stop, s);
-    else go_resid_mm<T, 32 / sizeof(T), TV>(g, av, W, NC, X, B, Y, stop, s);
+    constexpr int V = 32 / sizeof(T);
+    if (bgs_cols<T>(W) == 1) go_resid_mm<T, 1, 1, TV>(g, av, W, NC, X, B, Y, stop, s);
+    else if (W >= 4 * V) go_resid_mm<T, V, 4, TV>(g, av, W, NC, X, B, Y, stop, s);
+    else go_resid_mm<T, V, 1, TV>(g, av, W, NC, X, B, Y, stop, s);
 }
 
 }  // namespace
@@ -100,8 +105,10 @@ template <class T>
 void bgs_mm_launch(const DBgs& g, bool zero, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
                    hipStream_t s) {
     if (g.nblk == 0) return;
-    if (bgs_cols<T>(W) == 1) go_mm_v<T, 1>(g, zero, W, NC, X, B, Y, stop, s);
-    else go_mm_v<T, 32 / sizeof(T)>(g, zero, W, NC, X, B, Y, stop, s);
+    constexpr int V = 32 / sizeof(T);
+    if (bgs_cols<T>(W) == 1) go_mm_v<T, 1, 1>(g, zero, W, NC, X, B, Y, stop, s);
+    else if (W >= 4 * V) go_mm_v<T, V, 4>(g, zero, W, NC, X, B, Y, stop, s);
+    else go_mm_v<T, V, 1>(g, zero, W, NC, X, B, Y, stop, s);
 }
 
 template <class T>

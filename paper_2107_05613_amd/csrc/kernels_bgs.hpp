@@ -308,29 +308,38 @@ __device__ __forceinline__ void store_row(const Row<T, V>& r, T* p) {
 
 }  // namespace bgsmm
 
-template <typename T, int V, bool C16, bool ZERO, int NIN, class G>
+template <typename T, int V, int P, bool C16, bool ZERO, int NIN, class G>
 __device__ __forceinline__ void
 bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks, const uint32_t* __restrict__ meta,
        const int* __restrict__ ci, const uint16_t* __restrict__ c16, const T* __restrict__ av,
        const T* __restrict__ dinv, const T* __restrict__ mid, const T* __restrict__ X, const T* __restrict__ Bv,
        T* __restrict__ Y, const int* __restrict__ stop) {
+    static_assert(P == 1 || P == 4, "one or four waves per block");
+    static_assert(P == 1 || P == WAVES, "four waves per block fill the workgroup");
     using R = bgsmm::Row<T, V>;
-    __shared__ R su[WAVES][64], sw[WAVES][64];
+    // u and w by position in the block: P = 1, wave wv's block at wv * 64 + position;
+    // P = 4, the workgroup's block, position * 4 + the lane's column group
+    __shared__ R su[WAVES * 64], sw[WAVES * 64];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int gw = xcd_block(g.bid(), g.nb()) * WAVES + wv;
-    const int blk = gw / L;
-    const int col = (gw % L) * V;
+    const int task = gw / P, sub = gw % P;   // P waves per (block, group of P x V columns)
+    const int blk = task / L;
+    const int q = lane % P;
+    const int col = (task % L) * (P * V) + q * V;
     const int bl = min(blk, nblk - 1);
     const int stopped = *stop;
     const BgsBlock B = blocks[bl];
-    if (stopped | (blk >= nblk)) return;   // whole waves only
+    if (stopped | (blk >= nblk)) return;   // whole waves (P = 4: the whole workgroup)
     const int row0 = bl * 64;
-    const uint32_t mt = meta[row0 + lane];
+    const int slot = sub * (64 / P) + lane / P;   // this lane's row slot in the block
+    const uint32_t ws = meta[row0 + lane];         // slot `lane`: the slab sizes
+    const uint32_t mt = P == 1 ? ws : (uint32_t)__shfl((int)ws, slot);
     const int pos = mt >> 24;
     const bool live = pos != 0xff;
     const int nin = mt & 0xff, colour = live ? (int)((mt >> 8) & 0xff) : -1;
     const int len = (mt >> 16) & 0xff;
     const int ir = row0 + (live ? pos : 0);
+    const int lb = P == 1 ? wv * 64 : q;   // LDS index of position p: lb + p * P
     const T di = dinv[ir], mi = mid[ir];
     R br, xr;
     bgsmm::load_row(br, Bv + (int64_t)ir * NC + col);
@@ -339,18 +348,18 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
     if (!ZERO) bgsmm::load_row(xr, X + (int64_t)ir * NC + col);
 #pragma unroll
     for (int c = 0; c < V; ++c) {
-        su[wv][lane].v[c] = T(0);
-        sw[wv][lane].v[c] = T(0);
+        su[lb + slot * P].v[c] = T(0);
+        sw[lb + slot * P].v[c] = T(0);
     }
     const int W = B.width, cb = B.cbase;
     const int wi = B.info & 0xff, ncol = (B.info >> 8) & 0xff;
     const BgsShape sh(B.info);
-    int e = B.base + lane;
+    int e = B.base + slot;
     T a[NIN];
     int id[NIN];
     {
         int ee[NIN];
-        bgs_offsets<NIN>(e, len, 0, sh, ee);
+        bgs_offsets<NIN>(e, (ws >> 16) & 0xff, 0, sh, ee);
 #pragma unroll
         for (int t = 0; t < NIN; ++t) {
             a[t] = T(0);
@@ -379,7 +388,7 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
         for (int t0 = NIN; t0 < W; t0 += CH) {   // outside entries, CH slabs at a time
             T v[CH];
             int code[CH];
-            bgs_chunk<CH, T, C16>(e, len, t0, sh, av, ci, c16, v, code);
+            bgs_chunk<CH, T, C16>(e, (ws >> 16) & 0xff, t0, sh, av, ci, c16, v, code);
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
                 const bool on = t0 + k < len;
@@ -399,7 +408,12 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
     R r0;
 #pragma unroll
     for (int c = 0; c < V; ++c) r0.v[c] = br.v[c] - acc.v[c];
-    wave_sync();
+    // P = 1 orders the wave's own LDS accesses; P = 4 the workgroup's (one block)
+    auto sync = [] {
+        if (P == 1) wave_sync();
+        else __syncthreads();
+    };
+    sync();
     R uq, wq;
 #pragma unroll
     for (int c = 0; c < V; ++c) uq.v[c] = wq.v[c] = T(0);
@@ -410,15 +424,15 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
             for (int c = 0; c < V; ++c) s.v[c] = T(0);
 #pragma unroll
             for (int t = 0; t < NIN; ++t) {
-                const R z = su[wv][id[t]];
+                const R z = su[lb + id[t] * P];
 #pragma unroll
                 for (int c = 0; c < V; ++c) s.v[c] = fma(a[t], z.v[c], s.v[c]);
             }
 #pragma unroll
             for (int c = 0; c < V; ++c) uq.v[c] = (r0.v[c] - s.v[c]) * di;
-            su[wv][pos] = uq;
+            su[lb + pos * P] = uq;
         }
-        wave_sync();
+        sync();
     }
     for (int k = ncol - 1; k >= 0; --k) {
         if (colour == k) {
@@ -427,15 +441,15 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
             for (int c = 0; c < V; ++c) s.v[c] = T(0);
 #pragma unroll
             for (int t = 0; t < NIN; ++t) {
-                const R z = sw[wv][id[t]];
+                const R z = sw[lb + id[t] * P];
 #pragma unroll
                 for (int c = 0; c < V; ++c) s.v[c] = fma(a[t], z.v[c], s.v[c]);
             }
 #pragma unroll
             for (int c = 0; c < V; ++c) wq.v[c] = (mi * uq.v[c] - s.v[c]) * di;
-            sw[wv][pos] = wq;
+            sw[lb + pos * P] = wq;
         }
-        wave_sync();
+        sync();
     }
     if (!live) return;
     R out;
@@ -444,47 +458,54 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
     bgsmm::store_row(out, Y + (int64_t)ir * NC + col);
 }
 
-template <typename T, int V, bool C16, bool ZERO, int NIN>
+template <typename T, int V, int P, bool C16, bool ZERO, int NIN>
 struct BgsMM {
     static constexpr int block = BLOCK;
-    using sig = decltype(&bgs_mm<T, V, C16, ZERO, NIN, HwGrid>);
+    using sig = decltype(&bgs_mm<T, V, P, C16, ZERO, NIN, HwGrid>);
     template <class G, class... A>
-    __device__ static void run(G g, A... a) { bgs_mm<T, V, C16, ZERO, NIN, G>(g, a...); }
+    __device__ static void run(G g, A... a) { bgs_mm<T, V, P, C16, ZERO, NIN, G>(g, a...); }
 };
 
-// Y = B - A X on the block layout for V columns per wave (TV: value type, FP64 values
-// with FP32 blocks sum in FP64 and round once).
-template <typename T, int V, bool C16, typename TV, class G>
+// Y = B - A X on the block layout for P x V columns per group of P waves (TV: value
+// type, FP64 values with FP32 blocks sum in FP64 and round once).  P = 1: a wave holds
+// the block's 64 rows, one per lane, and V columns.  P = 4: four waves share a block,
+// each 16 rows, and the four lanes of a row hold V consecutive columns each, so that a
+// row's P x V columns (128 bytes) are one cache line for the four lanes' vector accesses.
+template <typename T, int V, int P, bool C16, typename TV, class G>
 __device__ __forceinline__ void
 bgs_resid_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
              const uint32_t* __restrict__ meta, const int* __restrict__ ci, const uint16_t* __restrict__ c16,
              const TV* __restrict__ av, const T* __restrict__ X, const T* __restrict__ Bv, T* __restrict__ Y,
              const int* __restrict__ stop) {
+    static_assert(P == 1 || P == 4, "one or four waves per block");
     using TA = typename std::conditional<(sizeof(TV) > sizeof(T)), TV, T>::type;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int gw = xcd_block(g.bid(), g.nb()) * WAVES + wv;
-    const int blk = gw / L;
-    const int col = (gw % L) * V;
+    const int task = gw / P, sub = gw % P;   // P waves per (block, group of P x V columns)
+    const int blk = task / L;
+    const int col = (task % L) * (P * V) + (lane % P) * V;
     const int bl = min(blk, nblk - 1);
     const int stopped = *stop;
     const BgsBlock B = blocks[bl];
     if (stopped | (blk >= nblk)) return;
     const int row0 = bl * 64;
-    const uint32_t mt = meta[row0 + lane];
+    const int slot = sub * (64 / P) + lane / P;   // this lane's row slot in the block
+    const uint32_t ws = meta[row0 + lane];         // slot `lane`: the slab sizes
+    const uint32_t mt = P == 1 ? ws : (uint32_t)__shfl((int)ws, slot);
     const int pos = mt >> 24;
     const bool live = pos != 0xff;
     const int nin = mt & 0xff, len = (mt >> 16) & 0xff;
     const int ir = row0 + (live ? pos : 0);
     const int cb = B.cbase;
     const BgsShape sh(B.info);
-    int e = B.base + lane;
+    int e = B.base + slot;
     TA acc[V];
 #pragma unroll
     for (int c = 0; c < V; ++c) acc[c] = 0;
     for (int t0 = 0; t0 < B.width; t0 += 8) {   // eight slabs at a time
         TV v[8];
         int code[8];
-        bgs_chunk<8, TV, C16>(e, len, t0, sh, av, ci, c16, v, code);
+        bgs_chunk<8, TV, C16>(e, (ws >> 16) & 0xff, t0, sh, av, ci, c16, v, code);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const bool on = t0 + k < len;
@@ -502,12 +523,12 @@ bgs_resid_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ b
     bgsmm::store_row(out, Y + (int64_t)ir * NC + col);
 }
 
-template <typename T, int V, bool C16, typename TV>
+template <typename T, int V, int P, bool C16, typename TV>
 struct BgsResidMM {
     static constexpr int block = BLOCK;
-    using sig = decltype(&bgs_resid_mm<T, V, C16, TV, HwGrid>);
+    using sig = decltype(&bgs_resid_mm<T, V, P, C16, TV, HwGrid>);
     template <class G, class... A>
-    __device__ static void run(G g, A... a) { bgs_resid_mm<T, V, C16, TV, G>(g, a...); }
+    __device__ static void run(G g, A... a) { bgs_resid_mm<T, V, P, C16, TV, G>(g, a...); }
 };
 
 }  // namespace dev

@@ -134,3 +134,18 @@ def test_batched_bgs_column_independent_of_block():
         Z2 = torch.zeros(c.n1 * 2, dtype=torch.float64, device="cuda")
         c.gpu[bits].vcycle(dev(B2), Z2, nrhs=2)
         assert np.array_equal(host(Z).reshape(c.n1, 3)[:, 2], host(Z2).reshape(c.n1, 2)[:, 0]), bits
+
+
+def test_batched_bgs_wide_block_matches_narrow():
+    """Column 21 of a 32-column V-cycle (four waves per block share its rows, four lanes
+    per row) equals the same right-hand side as column 0 of a 2-column V-cycle (one
+    column per wave), bit for bit, in both precisions."""
+    c = case("div", 12, 3, "unit", 32)
+    B = W.rhs(c.n1, 19, 32)
+    B2 = np.ascontiguousarray(np.stack([B[:, 21], W.rhs(c.n1, 20)[:, 0]], 1))
+    for bits in (64, 32):
+        Z = torch.zeros(c.n1 * 32, dtype=torch.float64, device="cuda")
+        c.gpu[bits].vcycle(dev(B), Z, nrhs=32)
+        Z2 = torch.zeros(c.n1 * 2, dtype=torch.float64, device="cuda")
+        c.gpu[bits].vcycle(dev(B2), Z2, nrhs=2)
+        assert np.array_equal(host(Z).reshape(c.n1, 32)[:, 21], host(Z2).reshape(c.n1, 2)[:, 0]), bits
