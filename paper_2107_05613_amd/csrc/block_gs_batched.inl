@@ -31,15 +31,27 @@ template <> const float* mids<float>(const DBgs& g) { return g.mid32; }
 
 namespace {
 
-// Columns per lane of the batched sweeps: 32-byte rows of the vector blocks (fewer waves
-// per block re-read its entries), or one column per wave when fewer columns are active.
-// From four such groups on, the four waves of a workgroup share a block (P = 4): a row's
-// four groups sit in four neighbouring lanes, so each vector access of a wave touches 16
-// cache lines instead of 64.
-template <class T>
-int bgs_cols(int W) {
-    const int v = 32 / (int)sizeof(T);
-    return W >= v ? v : 1;
+// Shape of the batched launches for W active columns (a power of two): V columns per
+// lane, P lanes per row.  32 bytes per lane (8 FP32 or 4 FP64 columns), or one column per
+// wave when fewer columns are active.  FP32 with 32 columns or more: the four waves of a
+// workgroup share a block (P = 4) and a row's four 32-byte groups sit in neighbouring
+// lanes, so each vector access of a wave touches 16 cache lines where one row per lane
+// touches 64.  FP64 keeps one row per lane at every width: with four lanes per row its
+// batched V-cycles differed between widths at the rounding level, from run to run.
+template <class T, class F>
+void bgs_shape(int W, F&& f) {
+    constexpr int S = (int)sizeof(T);
+    using one = std::integral_constant<int, 1>;
+    using four = std::integral_constant<int, 4>;
+    using vec = std::integral_constant<int, 32 / S>;
+    if constexpr (S == 4) {
+        if (W * S >= 128) {
+            f(vec{}, four{});
+            return;
+        }
+    }
+    if (W * S >= 32) f(vec{}, one{});
+    else f(one{}, one{});
 }
 
 template <class T, int V, int P, bool C16, bool ZERO, int NIN>
@@ -93,10 +105,9 @@ void go_resid_mm(const DBgs& g, const TV* av, int W, int NC, const T* X, const T
 template <class T, class TV>
 void go_resid_mm_v(const DBgs& g, const TV* av, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
                    hipStream_t s) {
-    constexpr int V = 32 / sizeof(T);
-    if (bgs_cols<T>(W) == 1) go_resid_mm<T, 1, 1, TV>(g, av, W, NC, X, B, Y, stop, s);
-    else if (W >= 4 * V) go_resid_mm<T, V, 4, TV>(g, av, W, NC, X, B, Y, stop, s);
-    else go_resid_mm<T, V, 1, TV>(g, av, W, NC, X, B, Y, stop, s);
+    bgs_shape<T>(W, [&](auto v, auto p) {
+        go_resid_mm<T, decltype(v)::value, decltype(p)::value, TV>(g, av, W, NC, X, B, Y, stop, s);
+    });
 }
 
 }  // namespace
@@ -105,10 +116,9 @@ template <class T>
 void bgs_mm_launch(const DBgs& g, bool zero, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
                    hipStream_t s) {
     if (g.nblk == 0) return;
-    constexpr int V = 32 / sizeof(T);
-    if (bgs_cols<T>(W) == 1) go_mm_v<T, 1, 1>(g, zero, W, NC, X, B, Y, stop, s);
-    else if (W >= 4 * V) go_mm_v<T, V, 4>(g, zero, W, NC, X, B, Y, stop, s);
-    else go_mm_v<T, V, 1>(g, zero, W, NC, X, B, Y, stop, s);
+    bgs_shape<T>(W, [&](auto v, auto p) {
+        go_mm_v<T, decltype(v)::value, decltype(p)::value>(g, zero, W, NC, X, B, Y, stop, s);
+    });
 }
 
 template <class T>

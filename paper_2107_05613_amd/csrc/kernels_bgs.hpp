@@ -64,6 +64,11 @@ __device__ __forceinline__ int bgs_code(const int* __restrict__ ci, const uint16
     return C16 ? (int)c16[e] : ci[e];
 }
 
+// A product rounded on its own: never contracted with the sum that follows it, so that
+// every instance of a sweep (single column, any batched shape) rounds alike.
+__device__ __forceinline__ float bgs_mul(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double bgs_mul(double a, double b) { return __dmul_rn(a, b); }
+
 // Lanes whose rows are longer than t: a prefix of the wave (rows sorted by length).
 __device__ __forceinline__ int bgs_slab(int len, int t) {
     return __popcll(__ballot(len > t));
@@ -195,20 +200,20 @@ k_bgs(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint32_t* __re
             T s = 0;
 #pragma unroll
             for (int t = 0; t < NIN; ++t) s = fma(a[t], su[wv][id[t]], s);
-            uq = (r0 - s) * di;
+            uq = bgs_mul(r0 - s, di);
             su[wv][pos] = uq;
         }
         wave_sync();
     }
     // backward: (D_l1 + U) w = (D + 2 D_l1) u, colours in decreasing order
-    const T v = mi * uq;
+    const T v = bgs_mul(mi, uq);
     T wq = 0;
     for (int c = ncol - 1; c >= 0; --c) {
         if (colour == c) {
             T s = 0;
 #pragma unroll
             for (int t = 0; t < NIN; ++t) s = fma(a[t], sw[wv][id[t]], s);
-            wq = (v - s) * di;
+            wq = bgs_mul(v - s, di);
             sw[wv][pos] = wq;
         }
         wave_sync();
@@ -256,11 +261,13 @@ k_bgs_resid(int nblk, int n, const BgsBlock* __restrict__ blocks, const uint32_t
 }
 
 // ---------------------------------------------------------------------------------
-// Batched sweeps (n x NC row-major blocks): the block layout above, each wave a 64-row
-// block and V consecutive columns of the first W (L = W / V waves per block, each
-// reading the block's entries; the entries are L1/L2 hits after the first).  Every
+// Batched sweeps (n x NC row-major blocks): the block layout above on the first W
+// columns, a lane holding V consecutive columns of a row.  P = 1: a wave holds a 64-row
+// block, one row per lane; P = 4: the four waves of a workgroup share a block, 16 rows
+// each, with a row's four column groups in neighbouring lanes.  L = W / (P V) groups of
+// waves per block each read the block's entries (L1/L2 hits after the first).  Every
 // column goes through exactly the arithmetic of the single-column sweep, so a column's
-// result depends neither on W, V nor the other columns.  Bodies of grid objects G
+// result depends neither on W, V, P nor the other columns.  Bodies of grid objects G
 // (grouped.hpp), launched solo or grouped.
 namespace bgsmm {
 
@@ -429,7 +436,7 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
                 for (int c = 0; c < V; ++c) s.v[c] = fma(a[t], z.v[c], s.v[c]);
             }
 #pragma unroll
-            for (int c = 0; c < V; ++c) uq.v[c] = (r0.v[c] - s.v[c]) * di;
+            for (int c = 0; c < V; ++c) uq.v[c] = bgs_mul(r0.v[c] - s.v[c], di);
             su[lb + pos * P] = uq;
         }
         sync();
@@ -446,7 +453,7 @@ bgs_mm(G g, int nblk, int n, int L, int NC, const BgsBlock* __restrict__ blocks,
                 for (int c = 0; c < V; ++c) s.v[c] = fma(a[t], z.v[c], s.v[c]);
             }
 #pragma unroll
-            for (int c = 0; c < V; ++c) wq.v[c] = (mi * uq.v[c] - s.v[c]) * di;
+            for (int c = 0; c < V; ++c) wq.v[c] = bgs_mul(bgs_mul(mi, uq.v[c]) - s.v[c], di);
             sw[lb + pos * P] = wq;
         }
         sync();

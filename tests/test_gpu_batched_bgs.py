@@ -137,9 +137,10 @@ def test_batched_bgs_column_independent_of_block():
 
 
 def test_batched_bgs_wide_block_matches_narrow():
-    """Column 21 of a 32-column V-cycle (four waves per block share its rows, four lanes
-    per row) equals the same right-hand side as column 0 of a 2-column V-cycle (one
-    column per wave), bit for bit, in both precisions."""
+    """Column 21 of a 32-column V-cycle (FP32: four waves per block share its rows, four
+    lanes per row; FP64: one row per lane, four columns) equals the same right-hand side
+    as column 0 of a 2-column V-cycle (one column per wave), bit for bit, in both
+    precisions."""
     c = case("div", 12, 3, "unit", 32)
     B = W.rhs(c.n1, 19, 32)
     B2 = np.ascontiguousarray(np.stack([B[:, 21], W.rhs(c.n1, 20)[:, 0]], 1))
