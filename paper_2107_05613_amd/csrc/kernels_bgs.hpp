@@ -19,17 +19,19 @@
 // the block stores exactly its entries (no padding): entry t of lane q sits at
 // base + (entries of slabs 0..t-1) + q.  Slabs below the block's shortest row hold every
 // row (sizes from the block record, so these loads need no per-lane word); past it the
-// slab sizes come from a ballot of the lanes' lengths.  A row's entries inside the block come first (code: the column's
-// position in the block), then the others (code: column, or a 16-bit offset from the
-// block's base column).  Per lane a 32-bit word: inside entries | colour << 8 |
-// length << 16 | position of its row in the block << 24 (0xff: no row); u and w live in
-// LDS by position in the block.  Loads are issued for every lane and slab
-// (clamped addresses, results masked), so a row's loads are in flight together: the
-// first NIN slabs (NIN >= every block's inside width, so they hold the inside entries)
-// are loaded together, then gathered together; the rest follow in a uniform loop; the
-// colour passes read LDS without per-lane branches.  The inside couplings stay in
-// registers, u and w in LDS; the passes synchronise the wave only.  A sweep from x0 = 0
-// reads the block's first wi slabs only (wi: its most inside entries of a row).
+// slab sizes come from a ballot of the lanes' lengths.  A row's entries inside the block
+// come first (code: the column's position in the block), then the others (code: column,
+// or a 16-bit offset from the block's base column).  Per lane a 32-bit word: inside
+// entries | colour << 8 | length << 16 | position of its row in the block << 24 (0xff:
+// no row); u and w live in LDS by position in the block.  Every lane loads every slab of
+// a loop, its entries past its row's length included (they lie inside the arrays, which
+// end with spare slots; the values are masked), so a row's loads are in flight together:
+// the first NIN slabs (NIN >= every block's inside width, so they hold the inside
+// entries) are loaded together, then gathered together; the rest follow in a uniform
+// loop; the colour passes read LDS without per-lane branches.  The inside couplings stay
+// in registers, u and w in LDS; the single-column sweep synchronises the wave only.  A
+// sweep from x0 = 0 reads the block's first wi slabs only (wi: its most inside entries
+// of a row).
 //
 // Bytes: a full sweep reads every entry once (value + 2- or 4-byte code) plus b, x, the
 // row data and writes y, like an l1-Jacobi sweep.
