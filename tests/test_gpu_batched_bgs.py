@@ -150,3 +150,18 @@ def test_batched_bgs_wide_block_matches_narrow():
         Z2 = torch.zeros(c.n1 * 2, dtype=torch.float64, device="cuda")
         c.gpu[bits].vcycle(dev(B2), Z2, nrhs=2)
         assert np.array_equal(host(Z).reshape(c.n1, 32)[:, 21], host(Z2).reshape(c.n1, 2)[:, 0]), bits
+
+
+def test_batched_bgs_two_column_groups_match_narrow():
+    """Column 45 of a 64-column V-cycle (FP32: two groups of 32 columns per block, each
+    over four waves) equals the same right-hand side as column 0 of a 2-column V-cycle,
+    bit for bit, in both precisions."""
+    c = case("div", 12, 3, "unit", 64)
+    B = W.rhs(c.n1, 23, 64)
+    B2 = np.ascontiguousarray(np.stack([B[:, 45], W.rhs(c.n1, 24)[:, 0]], 1))
+    for bits in (64, 32):
+        Z = torch.zeros(c.n1 * 64, dtype=torch.float64, device="cuda")
+        c.gpu[bits].vcycle(dev(B), Z, nrhs=64)
+        Z2 = torch.zeros(c.n1 * 2, dtype=torch.float64, device="cuda")
+        c.gpu[bits].vcycle(dev(B2), Z2, nrhs=2)
+        assert np.array_equal(host(Z).reshape(c.n1, 64)[:, 45], host(Z2).reshape(c.n1, 2)[:, 0]), bits
