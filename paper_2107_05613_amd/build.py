@@ -15,7 +15,9 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libamge.so")
 
-SOURCES = ["solver.hip", "server.hip", "setup_device.hip", "spgemm_device.hip", "block_gs.hip", "block_gs_batched_f32.hip", "block_gs_batched_f64.hip", "sell_layout.cpp", "kuhn.cpp", "sparse_host.cpp"]
+SOURCES = ["solver.hip", "server.hip", "setup_device.hip", "spgemm_device.hip", "block_gs.hip", "block_gs_batched.hip",
+           "block_gs_batched_f32_v8p4.hip", "block_gs_batched_f32_v8p1.hip", "block_gs_batched_f32_v1p1.hip",
+           "block_gs_batched_f64_v4p1.hip", "block_gs_batched_f64_v1p1.hip", "sell_layout.cpp", "kuhn.cpp", "sparse_host.cpp"]
 ARCH = os.environ.get("AMGE_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]

@@ -1,16 +1,31 @@
 // l1-scaled symmetric block Gauss-Seidel smoother on the batched path (n x NC blocks):
 // launches of the sweep and residual bodies of kernels_bgs.hpp, solo or recorded for
-// grouped launches.  Included by one translation unit per vector type BGS_T, so that the
-// kernel instances of the two types compile in parallel.
-#ifndef BGS_T
-#error "define BGS_T (float or double) before including this file"
-#endif
+// grouped launches.  Included by one translation unit per launch shape (BGS_SHAPE_T,
+// BGS_SHAPE_V, BGS_SHAPE_P defined: the kernel instances of that shape), so that the
+// shapes compile in parallel, and once without them (the launchers, which pick a shape
+// from the active width).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <type_traits>
 
 #include "block_gs.hpp"
+
+namespace amge {
+
+// The kernel launches of one shape (V columns per lane, P lanes per row): the sweep
+// (zero: from x = 0) and the residual (v64: FP64 values with FP32 blocks).
+template <class T, int V, int P>
+void bgs_mm_shape(const DBgs& g, bool zero, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
+                  hipStream_t s);
+template <class T, int V, int P>
+void bgs_resid_mm_shape(const DBgs& g, bool v64, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
+                        hipStream_t s);
+
+#ifdef BGS_SHAPE_T
+
+}  // namespace amge
+
 #include "kernels_bgs.hpp"
 
 namespace amge {
@@ -30,29 +45,6 @@ template <> const float* mids<float>(const DBgs& g) { return g.mid32; }
 }  // namespace
 
 namespace {
-
-// Shape of the batched launches for W active columns (a power of two): V columns per
-// lane, P lanes per row.  32 bytes per lane (8 FP32 or 4 FP64 columns), or one column per
-// wave when fewer columns are active.  FP32 with 32 columns or more: the four waves of a
-// workgroup share a block (P = 4) and a row's four 32-byte groups sit in neighbouring
-// lanes, so each vector access of a wave touches 16 cache lines where one row per lane
-// touches 64.  FP64 keeps one row per lane at every width: with four lanes per row its
-// batched V-cycles differed between widths at the rounding level, from run to run.
-template <class T, class F>
-void bgs_shape(int W, F&& f) {
-    constexpr int S = (int)sizeof(T);
-    using one = std::integral_constant<int, 1>;
-    using four = std::integral_constant<int, 4>;
-    using vec = std::integral_constant<int, 32 / S>;
-    if constexpr (S == 4) {
-        if (W * S >= 128) {
-            f(vec{}, four{});
-            return;
-        }
-    }
-    if (W * S >= 32) f(vec{}, one{});
-    else f(one{}, one{});
-}
 
 template <class T, int V, int P, bool C16, bool ZERO, int NIN>
 void go_mm(const DBgs& g, int W, int NC, const T* X, const T* B, T* Y, const int* stop, hipStream_t s) {
@@ -102,12 +94,54 @@ void go_resid_mm(const DBgs& g, const TV* av, int W, int NC, const T* X, const T
                                                     av, X, B, Y, stop);
 }
 
-template <class T, class TV>
-void go_resid_mm_v(const DBgs& g, const TV* av, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
-                   hipStream_t s) {
-    bgs_shape<T>(W, [&](auto v, auto p) {
-        go_resid_mm<T, decltype(v)::value, decltype(p)::value, TV>(g, av, W, NC, X, B, Y, stop, s);
-    });
+}  // namespace
+
+template <class T, int V, int P>
+void bgs_mm_shape(const DBgs& g, bool zero, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
+                  hipStream_t s) {
+    go_mm_v<T, V, P>(g, zero, W, NC, X, B, Y, stop, s);
+}
+
+template <class T, int V, int P>
+void bgs_resid_mm_shape(const DBgs& g, bool v64, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
+                        hipStream_t s) {
+    if constexpr (std::is_same<T, double>::value) go_resid_mm<T, V, P, T>(g, vals<T>(g), W, NC, X, B, Y, stop, s);
+    else if (v64) go_resid_mm<T, V, P, double>(g, g.v64, W, NC, X, B, Y, stop, s);
+    else go_resid_mm<T, V, P, T>(g, vals<T>(g), W, NC, X, B, Y, stop, s);
+}
+
+template void bgs_mm_shape<BGS_SHAPE_T, BGS_SHAPE_V, BGS_SHAPE_P>(const DBgs&, bool, int, int, const BGS_SHAPE_T*,
+                                                                 const BGS_SHAPE_T*, BGS_SHAPE_T*, const int*,
+                                                                 hipStream_t);
+template void bgs_resid_mm_shape<BGS_SHAPE_T, BGS_SHAPE_V, BGS_SHAPE_P>(const DBgs&, bool, int, int,
+                                                                       const BGS_SHAPE_T*, const BGS_SHAPE_T*,
+                                                                       BGS_SHAPE_T*, const int*, hipStream_t);
+
+#else
+
+namespace {
+
+// Shape of the batched launches for W active columns (a power of two): V columns per
+// lane, P lanes per row.  32 bytes per lane (8 FP32 or 4 FP64 columns), or one column per
+// wave when fewer columns are active.  FP32 with 32 columns or more: the four waves of a
+// workgroup share a block (P = 4) and a row's four 32-byte groups sit in neighbouring
+// lanes, so each vector access of a wave touches 16 cache lines where one row per lane
+// touches 64.  FP64 keeps one row per lane at every width: with four lanes per row its
+// batched V-cycles differed between widths at the rounding level, from run to run.
+template <class T, class F>
+void bgs_shape(int W, F&& f) {
+    constexpr int S = (int)sizeof(T);
+    using one = std::integral_constant<int, 1>;
+    using four = std::integral_constant<int, 4>;
+    using vec = std::integral_constant<int, 32 / S>;
+    if constexpr (S == 4) {
+        if (W * S >= 128) {
+            f(vec{}, four{});
+            return;
+        }
+    }
+    if (W * S >= 32) f(vec{}, one{});
+    else f(one{}, one{});
 }
 
 }  // namespace
@@ -117,7 +151,7 @@ void bgs_mm_launch(const DBgs& g, bool zero, int W, int NC, const T* X, const T*
                    hipStream_t s) {
     if (g.nblk == 0) return;
     bgs_shape<T>(W, [&](auto v, auto p) {
-        go_mm_v<T, decltype(v)::value, decltype(p)::value>(g, zero, W, NC, X, B, Y, stop, s);
+        bgs_mm_shape<T, decltype(v)::value, decltype(p)::value>(g, zero, W, NC, X, B, Y, stop, s);
     });
 }
 
@@ -125,13 +159,20 @@ template <class T>
 void bgs_resid_mm_launch(const DBgs& g, bool v64, int W, int NC, const T* X, const T* B, T* Y, const int* stop,
                          hipStream_t s) {
     if (g.nblk == 0) return;
-    if (v64 && !std::is_same<T, double>::value) go_resid_mm_v<T, double>(g, g.v64, W, NC, X, B, Y, stop, s);
-    else go_resid_mm_v<T, T>(g, vals<T>(g), W, NC, X, B, Y, stop, s);
+    bgs_shape<T>(W, [&](auto v, auto p) {
+        bgs_resid_mm_shape<T, decltype(v)::value, decltype(p)::value>(g, v64, W, NC, X, B, Y, stop, s);
+    });
 }
 
-template void bgs_mm_launch<BGS_T>(const DBgs&, bool, int, int, const BGS_T*, const BGS_T*, BGS_T*, const int*,
+template void bgs_mm_launch<float>(const DBgs&, bool, int, int, const float*, const float*, float*, const int*,
                                    hipStream_t);
-template void bgs_resid_mm_launch<BGS_T>(const DBgs&, bool, int, int, const BGS_T*, const BGS_T*, BGS_T*,
-                                         const int*, hipStream_t);
+template void bgs_mm_launch<double>(const DBgs&, bool, int, int, const double*, const double*, double*, const int*,
+                                    hipStream_t);
+template void bgs_resid_mm_launch<float>(const DBgs&, bool, int, int, const float*, const float*, float*, const int*,
+                                         hipStream_t);
+template void bgs_resid_mm_launch<double>(const DBgs&, bool, int, int, const double*, const double*, double*,
+                                          const int*, hipStream_t);
+
+#endif
 
 }  // namespace amge
