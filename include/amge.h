@@ -112,10 +112,12 @@ typedef struct {
                                x_i += (b_i - sum_j a_ij x_j) / d_i, d_i = a_ii + sum of |a_ij|
                                over columns outside the block, where x_j outside the block
                                keeps its value from the start of the sweep.
-                               The Gauss-Seidel smoothers need a positive diagonal; the
-                               colour-order one runs single-column contexts only (max_rhs =
-                               1), the block one also the batched path (every column through
-                               the arithmetic of the single-column sweep).                   */
+                               The Gauss-Seidel smoothers need a positive diagonal
+                               (AMGE_ERR_NOT_SPD otherwise), the block one rows of at most
+                               255 entries (AMGE_ERR_SHAPE otherwise); the colour-order one
+                               runs single-column contexts only (max_rhs = 1), the block one
+                               also the batched path (every column through the arithmetic of
+                               the single-column sweep).                                      */
     int32_t resid_bits;     /* FP32 V-cycles: precision of the fine-level residual b - A x that
                                is restricted to level 2 (Algorithm 4.1).  32: FP32 values and
                                sums; 64: the FP64 values of A_1 summed in FP64, the result

@@ -37,6 +37,7 @@ BgsHost bgs_layout(const Csr& A) {
     std::vector<int> wi(g.nblk, 0), cmin(g.nblk, 0), cmax(g.nblk, 0);
     std::vector<int64_t> inside(g.nblk, 0), stored(g.nblk, 0);
     std::vector<std::string> err(g.nblk);
+    std::vector<amge_status> code(g.nblk, AMGE_OK);
     // colours, inside counts, l1 sums, lane order (rows by length, longest first) and block
     // shapes, block by block
     parallel_for(g.nblk, [&](int64_t b0, int64_t b1) {
@@ -69,10 +70,12 @@ BgsHost bgs_layout(const Csr& A) {
                 const double d = aii + l1;
                 if (!(aii > 0) || !(d > 0)) {
                     err[bk] = "block Gauss-Seidel needs a positive diagonal";
+                    code[bk] = AMGE_ERR_NOT_SPD;
                     break;
                 }
                 if (len[i - r0] > 255) {
                     err[bk] = "block Gauss-Seidel rows hold at most 255 entries";
+                    code[bk] = AMGE_ERR_SHAPE;
                     break;
                 }
                 g.dinv[i] = 1.0 / d;
@@ -97,8 +100,8 @@ BgsHost bgs_layout(const Csr& A) {
             cmax[bk] = hi >= 0 ? hi : 0;
         }
     });
-    for (const std::string& e : err)
-        if (!e.empty()) fail(AMGE_ERR_NOT_SPD, e);
+    for (int bk = 0; bk < g.nblk; ++bk)
+        if (!err[bk].empty()) fail(code[bk], err[bk]);
     for (int bk = 0; bk < g.nblk; ++bk) {
         g.ninmax = std::max(g.ninmax, wi[bk]);
         g.nnz_in += inside[bk];

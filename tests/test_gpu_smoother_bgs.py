@@ -168,3 +168,23 @@ def test_bgs_single_sweep_and_residual(spec):
             er = float(np.max(np.abs(host(out) - rres) / scale))
             print(f"level {k} (n={n}) fp{bits}: block sweep {es:.1e}, residual {er:.1e}")
             assert es <= (1e-12 if bits == 64 else 1e-4) and er <= tol, (k, bits)
+
+
+def test_bgs_row_length_limit():
+    """A row of more than 255 entries is refused at set-up with AMGE_ERR_SHAPE (the block
+    layout stores a row's length in 8 bits); the matrix stays SPD (the extra couplings are
+    weak and symmetric, diagonals raised to keep dominance)."""
+    import scipy.sparse as sp
+    from paper_2107_05613_amd import amge
+    c = case("curl", 8, 3, "blocks")
+    A = c.levels[0][0].tocsr()
+    n = A.shape[0]
+    cols = np.arange(1, 301) * (n // 301)
+    E = sp.coo_matrix((np.full(cols.size, 1e-3), (np.zeros(cols.size, dtype=int), cols)), shape=(n, n))
+    E = (E + E.T).tocsr()
+    Aw = (A + E + sp.diags(np.asarray(abs(E).sum(axis=1)).ravel())).tocsr()
+    assert np.diff(Aw.indptr).max() > 255
+    bad = [(Aw,) + tuple(c.levels[0][1:])] + list(c.levels[1:])
+    with pytest.raises(amge.AmgeError) as e:
+        amge.Hierarchy(bad, smoother="l1blockgs")
+    assert e.value.code == -2
