@@ -188,3 +188,65 @@ def test_bgs_row_length_limit():
     with pytest.raises(amge.AmgeError) as e:
         amge.Hierarchy(bad, smoother="l1blockgs")
     assert e.value.code == -2
+
+
+def _dense_block_levels(n=337, nc=12, m=90, seed=5):
+    """A two-level hierarchy whose fine matrix has dense 64-row diagonal blocks (rows with
+    up to 64 entries inside their block: the largest register bound of the block sweep),
+    a few couplings across blocks, and a positive, dominant diagonal (SPD); D an
+    incidence with two +-1 entries per row that touches every column; P piecewise
+    constant; the coarse matrix P^T A P."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    rows, cols, vals = [], [], []
+    for b0 in range(0, n, 64):
+        b1 = min(n, b0 + 64)
+        for i in range(b0, b1):
+            for j in range(b0, i):
+                if rng.random() < 0.8:
+                    rows.append(i), cols.append(j), vals.append(rng.uniform(-1, 1))
+    for _ in range(3 * n):
+        i, j = rng.integers(0, n, 2)
+        if i // 64 != j // 64 and i > j:
+            rows.append(i), cols.append(j), vals.append(rng.uniform(-1, 1))
+    L = sp.coo_matrix((vals, (rows, cols)), shape=(n, n)).tocsr()
+    L.sum_duplicates()
+    S = L + L.T
+    A = (S + sp.diags(np.asarray(abs(S).sum(axis=1)).ravel() + 1.0)).tocsr()
+    e0 = np.arange(n) % m
+    e1 = (e0 + 1 + np.arange(n) % (m - 1)) % m
+    D = sp.csr_matrix((np.r_[np.ones(n), -np.ones(n)], (np.r_[np.arange(n), np.arange(n)], np.r_[e0, e1])),
+                      shape=(n, m))
+    P = sp.csr_matrix((np.ones(n), (np.arange(n), np.arange(n) * nc // n)), shape=(n, nc))
+    Ac = (P.T @ A @ P).tocsr()
+    ec = np.arange(nc)
+    Dc = sp.csr_matrix((np.r_[np.ones(nc), -np.ones(nc)], (np.r_[ec, ec], np.r_[ec, (ec + 1) % nc])), shape=(nc, nc))
+    return [(A, D, P), (Ac, Dc, None)]
+
+
+def test_bgs_dense_blocks_largest_bound():
+    """One block sweep and the residual on a fine matrix with dense 64-row blocks (inside
+    widths above 32: the NIN = 64 instances) against the oracle's block sweep and b - A x,
+    FP64 and FP32, as in test_bgs_single_sweep_and_residual."""
+    from oracle.solve import BlockGS, contiguous_blocks
+    from paper_2107_05613_amd import amge
+    levels = _dense_block_levels()
+    A = levels[0][0]
+    n = A.shape[0]
+    inside = [sum(1 for j in A.indices[A.indptr[i]:A.indptr[i + 1]] if j // 64 == i // 64) for i in range(n)]
+    assert max(inside) > 32
+    H = amge.Hierarchy(levels, precond_bits=64, smoother="l1blockgs", tail_rows=0)
+    rng = np.random.default_rng(13)
+    b, x0 = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    ref = BlockGS(A, contiguous_blocks(n, 64)).sweep(b, x0)
+    rres = b - A @ x0
+    scale = abs(A) @ abs(x0) + abs(b)
+    out = torch.empty_like(dev(b))
+    for bits, tol in ((64, 1e-13), (32, 1e-5)):
+        H.level_apply(0, amge.OP_SWEEP, dev(b), out, x2=dev(x0), precision=bits)
+        es = relerr(host(out), ref)
+        H.level_apply(0, amge.OP_RESID, dev(b), out, x2=dev(x0), precision=bits)
+        er = float(np.max(np.abs(host(out) - rres) / scale))
+        print(f"dense blocks (n={n}, widest inside row {max(inside)}) fp{bits}: block sweep {es:.1e}, residual {er:.1e}")
+        assert es <= (1e-12 if bits == 64 else 1e-4) and er <= tol, bits
+    H.close()
