@@ -165,3 +165,36 @@ def test_batched_bgs_two_column_groups_match_narrow():
         Z2 = torch.zeros(c.n1 * 2, dtype=torch.float64, device="cuda")
         c.gpu[bits].vcycle(dev(B2), Z2, nrhs=2)
         assert np.array_equal(host(Z).reshape(c.n1, 64)[:, 45], host(Z2).reshape(c.n1, 2)[:, 0]), bits
+
+
+def test_batched_bgs_dense_blocks_largest_bound():
+    """A 32-column batched V-cycle on a two-level hierarchy whose fine matrix has dense
+    64-row blocks (inside widths above 32: the NIN = 64 batched bodies, FP32 over four
+    waves per block, FP64 one row per lane) against the oracle's block Gauss-Seidel
+    V-cycle on the same level matrices: FP64 within 1e-10 (a diagonally dominant
+    problem), FP32 energy-norm error within 1e-3."""
+    from oracle.solve import Multilevel
+    from paper_2107_05613_amd import amge
+    from test_gpu_smoother_bgs import _dense_block_levels
+    levels = _dense_block_levels()
+    A = levels[0][0]
+    n = A.shape[0]
+    ml = Multilevel([lv[0] for lv in levels], [lv[1] for lv in levels], [lv[2] for lv in levels],
+                    smoother="l1blockgs", gs_block=64)
+    B = W.rhs(n, 29, 32)
+    refs = [ml.vcycle(B[:, j]) for j in range(32)]
+    for bits in (64, 32):
+        H = amge.Hierarchy(levels, precond_bits=bits, max_rhs=32, smoother="l1blockgs", tail_rows=0)
+        Z = torch.zeros(n * 32, dtype=torch.float64, device="cuda")
+        H.vcycle(dev(B), Z, nrhs=32)
+        z = host(Z).reshape(n, 32)
+        if bits == 64:
+            err = max(relerr(z[:, j], refs[j]) for j in range(32))
+            print(f"dense blocks batched FP64: worst column error {err:.1e}")
+            assert err <= 1e-10
+        else:
+            err = max(float(np.sqrt((z[:, j] - refs[j]) @ (A @ (z[:, j] - refs[j])) / (refs[j] @ (A @ refs[j]))))
+                      for j in range(32))
+            print(f"dense blocks batched FP32: worst energy-norm error {err:.1e}")
+            assert err <= 1e-3
+        H.close()
