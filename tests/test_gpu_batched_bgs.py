@@ -198,3 +198,34 @@ def test_batched_bgs_dense_blocks_largest_bound():
             print(f"dense blocks batched FP32: worst energy-norm error {err:.1e}")
             assert err <= 1e-3
         H.close()
+
+
+def test_batched_bgs_wide_column_span():
+    """An 8-column batched V-cycle with 32-bit outside columns in the block layout (a
+    block's outside columns span more than 65,536) against the oracle's block
+    Gauss-Seidel V-cycle: FP64 within 1e-10, FP32 energy-norm error within 1e-3."""
+    from oracle.solve import Multilevel
+    from paper_2107_05613_amd import amge
+    from test_gpu_smoother_bgs import _wide_span_levels
+    levels = _wide_span_levels()
+    A = levels[0][0]
+    n = A.shape[0]
+    ml = Multilevel([lv[0] for lv in levels], [lv[1] for lv in levels], [lv[2] for lv in levels],
+                    smoother="l1blockgs", gs_block=64)
+    B = W.rhs(n, 31, 8)
+    refs = [ml.vcycle(B[:, j]) for j in range(8)]
+    for bits in (64, 32):
+        H = amge.Hierarchy(levels, precond_bits=bits, max_rhs=8, smoother="l1blockgs", tail_rows=0)
+        Z = torch.zeros(n * 8, dtype=torch.float64, device="cuda")
+        H.vcycle(dev(B), Z, nrhs=8)
+        z = host(Z).reshape(n, 8)
+        if bits == 64:
+            err = max(relerr(z[:, j], refs[j]) for j in range(8))
+            print(f"wide column span batched FP64: worst column error {err:.1e}")
+            assert err <= 1e-10
+        else:
+            err = max(float(np.sqrt((z[:, j] - refs[j]) @ (A @ (z[:, j] - refs[j])) / (refs[j] @ (A @ refs[j]))))
+                      for j in range(8))
+            print(f"wide column span batched FP32: worst energy-norm error {err:.1e}")
+            assert err <= 1e-3
+        H.close()

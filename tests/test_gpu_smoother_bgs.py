@@ -250,3 +250,61 @@ def test_bgs_dense_blocks_largest_bound():
         print(f"dense blocks (n={n}, widest inside row {max(inside)}) fp{bits}: block sweep {es:.1e}, residual {er:.1e}")
         assert es <= (1e-12 if bits == 64 else 1e-4) and er <= tol, bits
     H.close()
+
+
+def _wide_span_levels(n=70000, nc=40, m=3000, seed=7):
+    """A two-level hierarchy whose fine matrix couples rows 65,600 apart (a block's
+    outside columns then span more than 65,536, so the block layout stores 32-bit
+    outside columns): a tridiagonal band, symmetric long-range couplings, a dominant
+    diagonal; D, P and the coarse matrix as in _dense_block_levels."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    i = np.arange(n - 1)
+    far = rng.integers(0, n - 65600, 200)
+    rows = np.r_[i + 1, far + 65600]
+    cols = np.r_[i, far]
+    L = sp.coo_matrix((rng.uniform(-1, 1, rows.size), (rows, cols)), shape=(n, n)).tocsr()
+    L.sum_duplicates()
+    S = L + L.T
+    A = (S + sp.diags(np.asarray(abs(S).sum(axis=1)).ravel() + 1.0)).tocsr()
+    e0 = np.arange(n) % m
+    e1 = (e0 + 1 + np.arange(n) % (m - 1)) % m
+    D = sp.csr_matrix((np.r_[np.ones(n), -np.ones(n)], (np.r_[np.arange(n), np.arange(n)], np.r_[e0, e1])),
+                      shape=(n, m))
+    P = sp.csr_matrix((np.ones(n), (np.arange(n), np.arange(n) * nc // n)), shape=(n, nc))
+    Ac = (P.T @ A @ P).tocsr()
+    ec = np.arange(nc)
+    Dc = sp.csr_matrix((np.r_[np.ones(nc), -np.ones(nc)], (np.r_[ec, ec], np.r_[ec, (ec + 1) % nc])), shape=(nc, nc))
+    return [(A, D, P), (Ac, Dc, None)]
+
+
+def test_bgs_wide_column_span():
+    """One block sweep and the residual with 32-bit outside columns (a block's outside
+    columns span more than 65,536) against the oracle's block sweep and b - A x, FP64
+    and FP32, as in test_bgs_single_sweep_and_residual."""
+    from oracle.solve import BlockGS, contiguous_blocks
+    from paper_2107_05613_amd import amge
+    levels = _wide_span_levels()
+    A = levels[0][0]
+    n = A.shape[0]
+    span = 0
+    for b0 in range(0, n, 64):
+        cols = [j for r in range(b0, min(n, b0 + 64)) for j in A.indices[A.indptr[r]:A.indptr[r + 1]]
+                if j // 64 != r // 64]
+        span = max(span, max(cols) - min(cols))
+    assert span >= 65536
+    H = amge.Hierarchy(levels, precond_bits=64, smoother="l1blockgs", tail_rows=0)
+    rng = np.random.default_rng(17)
+    b, x0 = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    ref = BlockGS(A, contiguous_blocks(n, 64)).sweep(b, x0)
+    rres = b - A @ x0
+    scale = abs(A) @ abs(x0) + abs(b)
+    out = torch.empty_like(dev(b))
+    for bits, tol in ((64, 1e-13), (32, 1e-5)):
+        H.level_apply(0, amge.OP_SWEEP, dev(b), out, x2=dev(x0), precision=bits)
+        es = relerr(host(out), ref)
+        H.level_apply(0, amge.OP_RESID, dev(b), out, x2=dev(x0), precision=bits)
+        er = float(np.max(np.abs(host(out) - rres) / scale))
+        print(f"wide column span (n={n}) fp{bits}: block sweep {es:.1e}, residual {er:.1e}")
+        assert es <= (1e-12 if bits == 64 else 1e-4) and er <= tol, bits
+    H.close()
