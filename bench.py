@@ -319,10 +319,11 @@ def run_small_configs(names, steps, smoother):
     return out, sols
 
 
-def run_options(steps):
+def run_options(steps, smoother):
     """Coefficient-aware extensions and essential boundary conditions (the library's
     builder options) on the 32^3 H(div) jump workload and on two of the serving mix's
-    48^3 jump hierarchies: FP64 PCG iterations to rtol 1e-8 and time per solve."""
+    48^3 jump hierarchies: FP64 PCG iterations to rtol 1e-8 and time per solve, with the
+    headline's point smoother."""
     import torch
     from paper_2107_05613_amd import amge
     from paper_2107_05613_amd import workloads as W
@@ -336,7 +337,7 @@ def run_options(steps):
         for ext in ("l2", "coefficient"):
             for bc in ("natural", "essential"):
                 prod = amge.build_problem(w.kind, w.n, w.levels, a, b, extension=ext, bc=bc)
-                H = amge.Hierarchy(prod, precond_bits=64)
+                H = amge.Hierarchy(prod, precond_bits=64, smoother=smoother)
                 rhs = torch.from_numpy(W.rhs(H.rows[0], w.rhs_seed)[:, 0]).cuda()
                 x = torch.zeros_like(rhs)
                 st, it, rr = H.pcg(rhs, x, rtol=1e-8, maxit=2000)
@@ -349,6 +350,7 @@ def run_options(steps):
                 r[f"{ext}/{bc}"] = {"iters": it[0], "status": st, "dofs": H.rows[0], "ms_per_solve": 1e3 * dt}
                 H.close()
         out[w.name] = r
+        out["smoother"] = smoother
         print(f"[bench] options {w.name}: " + ", ".join(f"{k} {v['iters']}" for k, v in r.items()),
               file=sys.stderr, flush=True)
     return out
@@ -740,7 +742,7 @@ def main():
     small_names = [c for c in args.small_configs.split(",") if c]
     small, small_sol = run_small_configs(small_names, args.steps, args.smoother) if small_names else ({}, {})
     sol.update(small_sol)
-    options = run_options(args.steps) if not args.no_options else None
+    options = run_options(args.steps, args.smoother) if not args.no_options else None
     batched = run_batched(args, amge, W) if args.batched_workload else None
     serving = run_serving(args) if args.serving_requests > 0 else None
 

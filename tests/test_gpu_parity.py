@@ -511,11 +511,13 @@ def test_one_level_hierarchy():
 
 @pytest.mark.parametrize("spec", [("curl", 16, 4, "blocks"), ("div", 16, 4, "blocks")])
 @pytest.mark.parametrize("ext,bc", [("coefficient", "natural"), ("l2", "essential"), ("coefficient", "essential")])
-def test_pcg_extension_and_boundary_options(spec, ext, bc):
+@pytest.mark.parametrize("smoother", ["l1jacobi", "l1blockgs"])
+def test_pcg_extension_and_boundary_options(spec, ext, bc, smoother):
     """Coefficient-aware extensions and essential boundary conditions change only the
     level matrices: the solve phase set up from the oracle's hierarchy of that kind takes
     the oracle's iteration count (+-1) and matches its fixed-count iterate within the
-    FP64 bar; the library's own builder gives the same count."""
+    FP64 bar, with either point smoother; the library's own builder gives the same count
+    (+-1)."""
     from oracle.hierarchy import build_hierarchy
     from oracle.solve import Multilevel, pcg
     amge = _amge()
@@ -523,18 +525,20 @@ def test_pcg_extension_and_boundary_options(spec, ext, bc):
     w = W.Workload("t", kind, n, L, coef)
     a, b = W.coefficients(w)
     H = build_hierarchy(kind, n, L, a, b, check_targets=False, extension=ext, bc=bc)
-    ml = Multilevel.from_hierarchy(H)
+    ml = Multilevel.from_hierarchy(H, smoother=smoother)
     rhs = W.rhs(H.A[0].shape[0], 0)[:, 0]
     xo, ito, _ = pcg(H.A[0], rhs, ml, rtol=1e-8)
-    bar = fp64_bar(spreads(H, rhs, ito)["pcg"])
-    G = amge.Hierarchy(oracle_levels(H), precond_bits=64)
+    bar = fp64_bar(spreads(H, rhs, ito, smoother=smoother)["pcg"])
+    G = amge.Hierarchy(oracle_levels(H), precond_bits=64, smoother=smoother)
     x = torch.zeros_like(dev(rhs))
     st, it, _ = G.pcg(dev(rhs), x, rtol=1e-8, maxit=1000)
     G.pcg(dev(rhs), x, rtol=0.0, maxit=ito)
     err = np.linalg.norm(host(x) - xo) / np.linalg.norm(xo)
-    B = amge.Hierarchy(amge.build_problem(kind, n, L, a, b, extension=ext, bc=bc), precond_bits=64)
+    B = amge.Hierarchy(amge.build_problem(kind, n, L, a, b, extension=ext, bc=bc), precond_bits=64,
+                       smoother=smoother)
     _, itb, _ = B.pcg(dev(rhs), torch.zeros_like(x), rtol=1e-8, maxit=1000)
-    print(f"{spec} {ext}/{bc}: {H.A[0].shape[0]} dofs, oracle {ito} iterations, GPU {it[0]}, builder {itb[0]}; "
+    print(f"{spec} {ext}/{bc} {smoother}: {H.A[0].shape[0]} dofs, oracle {ito} iterations, GPU {it[0]}, "
+          f"builder {itb[0]}; "
           f"fixed-count error {err:.1e} (bar {bar:.1e})")
     assert st == 0 and abs(it[0] - ito) <= 1 and abs(itb[0] - ito) <= 1
     assert err <= bar
